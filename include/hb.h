@@ -1,0 +1,204 @@
+/*
+ * hb.h -- C ABI of the MI355X rule-based blocking library (libhb.so).
+ *
+ * The library computes, for a relation D and a set Delta of matching
+ * dependencies (MDs), the set Ca(D) of tuple pairs (t_i, t_j) for which some
+ * MD in Delta is a witness: every predicate of its precondition holds
+ * (Section 2, "Rule-based blocking"; the problem statement of Section 2,
+ * "Our scope: blocking": relation plus rules in, candidate pairs out).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an hb_status; nothing throws across the ABI.
+ *     On failure hb_last_error(ctx) describes the cause and the context
+ *     stays usable.
+ *   - Inputs are copied (or, for device inputs, read) during the call; the
+ *     caller may free or reuse them when the call returns.
+ *   - Device memory comes from the allocator given to hb_create (or
+ *     hipMallocAsync on the context stream when none is given) and is
+ *     released by hb_release_relation / hb_destroy.
+ *   - All device work runs on the stream given to hb_create (or a stream the
+ *     context creates).  Calls that return host-visible results synchronise
+ *     that stream before returning.
+ *   - A context is not thread-safe: serialise calls on one context.
+ *   - Rows are 0-based positions in the arrays given to hb_load_relation.
+ */
+#ifndef HB_H
+#define HB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hb_ctx hb_ctx;
+
+typedef enum {
+    HB_OK = 0,
+    HB_ERR_INVALID_ARG = 1,  /* NULL pointer, bad size, bad enum, bad offsets */
+    HB_ERR_TYPE = 2,         /* predicate applied to an attribute of the wrong type */
+    HB_ERR_UNBLOCKABLE = 3,  /* a rule has no equality on a categorical/int64 attribute */
+    HB_ERR_LIMIT = 4,        /* a documented size limit is exceeded */
+    HB_ERR_OOM = 5,          /* the allocator returned NULL */
+    HB_ERR_CAPACITY = 6,     /* output buffer too small; *n_pairs holds the size needed */
+    HB_ERR_HIP = 7,          /* a HIP runtime call failed */
+    HB_ERR_STALE_ID = 8,     /* relation / rule-set id unknown or released */
+    HB_ERR_STATE = 9         /* call out of order (e.g. hb_match before hb_partition) */
+} hb_status;
+
+/* Limits (HB_ERR_LIMIT beyond them). */
+#define HB_MAX_RULES 64          /* rules per rule set */
+#define HB_MAX_RULE_PREDS 10     /* predicates per rule (the paper's default bound) */
+#define HB_MAX_DISTINCT_PREDS 64 /* distinct predicates per rule set */
+#define HB_MAX_KEYS 4            /* distinct blocking-key attributes per rule set */
+#define HB_MAX_ED_LEN 512        /* longest string of an attribute used by an edit-distance predicate */
+#define HB_MAX_GRAM_LEN 4096     /* longest string of an attribute used by a Jaccard predicate */
+#define HB_MAX_ED_K 255
+#define HB_MAX_Q 4
+
+/* Device allocator: return `bytes` bytes of device memory on the context's
+ * device (NULL on failure); `user` is passed through. */
+typedef void* (*hb_alloc_fn)(size_t bytes, void* user);
+typedef void (*hb_free_fn)(void* ptr, void* user);
+
+/* Create a context on HIP device `device`.  `alloc`/`free_fn` may both be
+ * NULL (then hipMallocAsync/hipFreeAsync on the stream are used).  `stream`
+ * is a hipStream_t (NULL: the context creates a non-blocking stream of
+ * default priority).  The caller keeps ownership of a given stream. */
+hb_status hb_create(hb_ctx** out, int device, hb_alloc_fn alloc, hb_free_fn free_fn,
+                    void* user, void* stream);
+void hb_destroy(hb_ctx* ctx);
+const char* hb_last_error(const hb_ctx* ctx);
+const char* hb_version(void);
+
+/* ------------------------------------------------------------ relations
+ * A relation D of schema R = (A_1..A_n) (Section 2, "Relations"), stored
+ * column-wise.  Table 1's missing values ("-") are expressed with the
+ * validity bitmap: a missing value fails every predicate (Example 3; the
+ * Section 4 remark on (t1, t5)).
+ */
+typedef enum { HB_COL_STRING = 0, HB_COL_CATEGORICAL = 1, HB_COL_INT64 = 2 } hb_coltype;
+
+typedef struct {
+    int32_t type;            /* hb_coltype */
+    const uint64_t* offsets; /* STRING: n_rows + 1 non-decreasing byte offsets, offsets[0] = 0 */
+    const uint8_t* bytes;    /* STRING: offsets[n_rows] bytes (may be NULL when that is 0) */
+    const int64_t* values;   /* CATEGORICAL (dictionary codes) / INT64: n_rows values */
+    const uint8_t* valid;    /* optional LSB-first validity bitmap, ceil(n_rows / 8) bytes;
+                                NULL = every value present */
+} hb_column;
+
+/* Load a relation.  `on_device` = 0: the column arrays are host memory and
+ * are copied to the device; 1: they are device memory of this context's
+ * device and are copied device-to-device.  1 <= n_rows < 2^31,
+ * 1 <= n_cols <= 256.  String offsets are validated (HB_ERR_INVALID_ARG). */
+hb_status hb_load_relation(hb_ctx* ctx, uint32_t n_rows, uint32_t n_cols, const hb_column* cols,
+                           int on_device, uint32_t* rel_id);
+/* Release a relation and every rule set compiled against it. */
+hb_status hb_release_relation(hb_ctx* ctx, uint32_t rel_id);
+
+/* ------------------------------------------------------------ rules
+ * Predicates of the form t.A = s.A and t.A ~ s.A (Section 2, "Predicates"),
+ * with these similarity measures:
+ *   HB_EQ          byte-exact equality (STRING) or value equality
+ *                  (CATEGORICAL, INT64);
+ *   HB_ED_LE       Levenshtein distance over bytes <= k        (STRING);
+ *   HB_JACCARD_GE  |G_q(a) & G_q(b)| * den >= num * |G_q(a) | G_q(b)|, G_q the
+ *                  set of distinct length-q byte windows, {s} for a non-empty
+ *                  string shorter than q, empty for the empty string, and
+ *                  J(empty, empty) = 1                          (STRING);
+ *   HB_ABSDIFF_LE  |a - b| <= d, exact over int64                (INT64).
+ * A rule (an MD X -> t.eid = s.eid, Section 2, "Rules") is a conjunction;
+ * a rule set is their disjunction.  Every rule must contain an HB_EQ on a
+ * CATEGORICAL or INT64 attribute: its first one (in the given order) is the
+ * rule's blocking key (the partition key of Section 5.3).
+ */
+typedef enum { HB_EQ = 0, HB_ED_LE = 1, HB_JACCARD_GE = 2, HB_ABSDIFF_LE = 3 } hb_op;
+
+typedef struct {
+    int32_t op;     /* hb_op */
+    uint32_t attr;  /* column index */
+    int64_t k;      /* HB_ED_LE: 0..HB_MAX_ED_K */
+    uint32_t q;     /* HB_JACCARD_GE: 1..HB_MAX_Q */
+    uint32_t num;   /* HB_JACCARD_GE: threshold num/den, 0 <= num <= den */
+    uint32_t den;   /* HB_JACCARD_GE: den > 0 */
+    int64_t d;      /* HB_ABSDIFF_LE: d >= 0 */
+} hb_pred;
+
+typedef struct {
+    uint32_t n_preds;
+    const hb_pred* preds;
+} hb_rule;
+
+/* Validate and compile a rule set against a relation: dedups predicates,
+ * builds the q-gram indexes its Jaccard predicates need and the
+ * per-predicate selectivity estimates of the heuristic plan (Section 4.2). */
+hb_status hb_compile_rules(hb_ctx* ctx, uint32_t rel_id, uint32_t n_rules, const hb_rule* rules,
+                           uint32_t* ruleset_id);
+
+/* Partition the relation on the rule set's blocking keys (Section 2,
+ * "Data partitioning"; Section 5.3 partitioning by the root edges' keys):
+ * groups rows by exact key value.  *n_candidate_pairs receives the exact
+ * number of distinct pairs i < j sharing a value of at least one key. */
+hb_status hb_partition(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id,
+                       uint64_t* n_candidate_pairs);
+
+/* Evaluation order (output-neutral, Section 4):
+ *   HB_PLAN_GIVEN      rules and predicates in the given order;
+ *   HB_PLAN_HEURISTIC  the execution plan of Section 4.2 (cost-effectiveness
+ *                      order, execution tree, edge scores, DFS order). */
+typedef enum { HB_PLAN_GIVEN = 0, HB_PLAN_HEURISTIC = 1 } hb_plan;
+
+/* Evaluate the rule set on every candidate pair and return Ca(D): packed
+ * uint64 (i << 32) | j with i < j, sorted ascending, each pair once.
+ * `out_pairs` holds `capacity` entries in host memory (out_on_device = 0)
+ * or device memory (1).  If capacity is too small the call returns
+ * HB_ERR_CAPACITY with *n_pairs = the size needed; the result stays cached
+ * so a retry with a larger buffer only copies.  Requires hb_partition. */
+hb_status hb_match(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan,
+                   uint64_t* out_pairs, int out_on_device, uint64_t capacity, uint64_t* n_pairs);
+
+/* ------------------------------------------------------------ introspection */
+
+/* Per distinct predicate of a rule set (in first-appearance order): its
+ * selectivity estimate sp in [0, 1] and normalised cost in (0, 1].
+ * *n receives the number of distinct predicates; up to `cap` are written. */
+hb_status hb_ruleset_estimates(hb_ctx* ctx, uint32_t ruleset_id, double* sp, double* cost,
+                               uint32_t cap, uint32_t* n);
+
+/* LSH bucket counts (1024 buckets) behind sp of distinct predicate `pred`. */
+hb_status hb_ruleset_buckets(hb_ctx* ctx, uint32_t ruleset_id, uint32_t pred, uint64_t* counts,
+                             uint64_t* n_valid);
+
+/* Pure host: the sequential execution path of Section 4.2 / 5.1 for given
+ * estimates.  Predicates are ids 0..n_preds-1; rule r lists rule_len[r] ids
+ * starting at rule_preds[sum of earlier lengths].  Writes the rule order to
+ * out_rules[n_rules] and, per rule in that order, its distinct predicates
+ * in evaluation order to out_preds (at most the total input length);
+ * *out_len receives the number written to out_preds. */
+hb_status hb_epg_path(uint32_t n_preds, const double* sp, const double* cost, uint32_t n_rules,
+                      const uint32_t* rule_len, const uint32_t* rule_preds, uint32_t* out_rules,
+                      uint32_t* out_preds, uint32_t* out_len);
+
+/* Kernel timing: when enabled, HIP events bracket each kernel launch of the
+ * named step on the context stream.  Names: "match", "partition_sort",
+ * "gram_build", "lsh", "output_sort". */
+hb_status hb_profile_enable(hb_ctx* ctx, int on);
+hb_status hb_profile_query(hb_ctx* ctx, const char* name, double* total_ms, uint64_t* launches);
+hb_status hb_profile_reset(hb_ctx* ctx);
+
+/* Counters of the last hb_match: candidate pairs, pairs matched, launches
+ * and tiles of the match kernel. */
+typedef struct {
+    uint64_t candidate_pairs;
+    uint64_t matched_pairs;
+    uint64_t tiles;
+    uint64_t launches;
+} hb_match_stats;
+hb_status hb_last_match_stats(hb_ctx* ctx, hb_match_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HB_H */

@@ -1,0 +1,322 @@
+"""Python binding of libhb, the MI355X rule-based blocking library.
+
+Argument marshalling only: every step on the data runs in libhb's HIP
+kernels.  PyTorch supplies device memory (an allocator callback backed by
+its caching allocator) and the stream.  The functions carry the names of
+the C entry points declared in include/hb.h.
+
+The in-tree shared library must exist (built by `build.py`); importing
+this package without it raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhb.so")
+
+HB_OK = 0
+HB_ERR_INVALID_ARG = 1
+HB_ERR_TYPE = 2
+HB_ERR_UNBLOCKABLE = 3
+HB_ERR_LIMIT = 4
+HB_ERR_OOM = 5
+HB_ERR_CAPACITY = 6
+HB_ERR_HIP = 7
+HB_ERR_STALE_ID = 8
+HB_ERR_STATE = 9
+
+HB_PLAN_GIVEN = 0
+HB_PLAN_HEURISTIC = 1
+
+_COLTYPE = {"string": 0, "categorical": 1, "int64": 2}
+_OP = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3}
+_PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC}
+
+EXPORTED = [
+    "hb_create", "hb_destroy", "hb_last_error", "hb_version", "hb_load_relation", "hb_release_relation",
+    "hb_compile_rules", "hb_partition", "hb_match", "hb_ruleset_estimates", "hb_ruleset_buckets",
+    "hb_epg_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
+]
+
+
+class HbColumn(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("offsets", ctypes.c_void_p), ("bytes", ctypes.c_void_p),
+                ("values", ctypes.c_void_p), ("valid", ctypes.c_void_p)]
+
+
+class HbPred(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("attr", ctypes.c_uint32), ("k", ctypes.c_int64),
+                ("q", ctypes.c_uint32), ("num", ctypes.c_uint32), ("den", ctypes.c_uint32),
+                ("d", ctypes.c_int64)]
+
+
+class HbRule(ctypes.Structure):
+    _fields_ = [("n_preds", ctypes.c_uint32), ("preds", ctypes.POINTER(HbPred))]
+
+
+class HbMatchStats(ctypes.Structure):
+    _fields_ = [("candidate_pairs", ctypes.c_uint64), ("matched_pairs", ctypes.c_uint64),
+                ("tiles", ctypes.c_uint64), ("launches", ctypes.c_uint64)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _load_lib():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libhb.so is not built ({LIB_PATH}); run paper_2410_04349_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, U32, U64, I32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+    sig = {
+        "hb_create": (I32, [ctypes.POINTER(P), ctypes.c_int, ALLOC_FN, FREE_FN, P, P]),
+        "hb_destroy": (None, [P]),
+        "hb_last_error": (ctypes.c_char_p, [P]),
+        "hb_version": (ctypes.c_char_p, []),
+        "hb_load_relation": (I32, [P, U32, U32, ctypes.POINTER(HbColumn), ctypes.c_int, ctypes.POINTER(U32)]),
+        "hb_release_relation": (I32, [P, U32]),
+        "hb_compile_rules": (I32, [P, U32, U32, ctypes.POINTER(HbRule), ctypes.POINTER(U32)]),
+        "hb_partition": (I32, [P, U32, U32, ctypes.POINTER(U64)]),
+        "hb_match": (I32, [P, U32, U32, I32, P, ctypes.c_int, U64, ctypes.POINTER(U64)]),
+        "hb_ruleset_estimates": (I32, [P, U32, P, P, U32, ctypes.POINTER(U32)]),
+        "hb_ruleset_buckets": (I32, [P, U32, U32, P, ctypes.POINTER(U64)]),
+        "hb_epg_path": (I32, [U32, P, P, U32, P, P, P, P, ctypes.POINTER(U32)]),
+        "hb_profile_enable": (I32, [P, ctypes.c_int]),
+        "hb_profile_query": (I32, [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64)]),
+        "hb_profile_reset": (I32, [P]),
+        "hb_last_match_stats": (I32, [P, ctypes.POINTER(HbMatchStats)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load_lib()
+
+
+class HbError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"hb status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+def _ptr(a) -> Optional[int]:
+    """Address of a numpy array or a torch tensor (None passes through)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+class Context:
+    """An hb_ctx on one device; device memory comes from torch's caching
+    allocator (allocator='torch') or hipMallocAsync (allocator='hip')."""
+
+    def __init__(self, device: int = 0, allocator: str = "torch", stream=None):
+        self.device = device
+        self._held = {}
+        self._alloc_cb = ALLOC_FN(0)
+        self._free_cb = FREE_FN(0)
+        if allocator == "torch":
+            import torch
+
+            def _alloc(nbytes, user):
+                try:
+                    t = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{device}")
+                except RuntimeError:
+                    return None
+                p = t.data_ptr()
+                self._held[p] = t
+                return p
+
+            def _free(p, user):
+                self._held.pop(p, None)
+
+            self._alloc_cb = ALLOC_FN(_alloc)
+            self._free_cb = FREE_FN(_free)
+        if stream is None and allocator == "torch":
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = _lib.hb_create(ctypes.byref(h), device, self._alloc_cb, self._free_cb, None,
+                            ctypes.c_void_p(stream) if stream else None)
+        if st != HB_OK:
+            raise HbError(st, "hb_create failed")
+        self.h = h
+
+    def check(self, st: int):
+        if st != HB_OK:
+            raise HbError(st, _lib.hb_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.hb_destroy(self.h)
+            self.h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hb_create(device: int = 0, allocator: str = "torch", stream=None) -> Context:
+    return Context(device, allocator, stream)
+
+
+def hb_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def hb_version() -> str:
+    return _lib.hb_version().decode()
+
+
+def hb_last_error(ctx: Context) -> str:
+    return _lib.hb_last_error(ctx.h).decode()
+
+
+def hb_load_relation(ctx: Context, columns: Sequence, n_rows: int, on_device: bool = False) -> int:
+    """columns: objects with .type ('string'|'categorical'|'int64') and
+    .offsets/.data (strings), .values (others), .valid (optional bitmap);
+    numpy arrays for host input, torch device tensors for device input."""
+    arr = (HbColumn * len(columns))()
+    for k, c in enumerate(columns):
+        data = getattr(c, "data", None)
+        if data is not None and len(data) == 0:
+            data = None
+        arr[k] = HbColumn(_COLTYPE[c.type], _ptr(c.offsets), _ptr(data), _ptr(c.values), _ptr(c.valid))
+    rid = ctypes.c_uint32()
+    ctx.check(_lib.hb_load_relation(ctx.h, n_rows, len(columns), arr, int(on_device), ctypes.byref(rid)))
+    return rid.value
+
+
+def hb_release_relation(ctx: Context, rel_id: int) -> None:
+    ctx.check(_lib.hb_release_relation(ctx.h, rel_id))
+
+
+def _c_rules(rules):
+    keep = []
+    crules = (HbRule * len(rules))()
+    for r, rule in enumerate(rules):
+        preds = (HbPred * max(1, len(rule)))()
+        for x, p in enumerate(rule):
+            preds[x] = HbPred(_OP[p.op], p.attr, p.k, p.q, p.num, p.den, p.d)
+        keep.append(preds)
+        crules[r] = HbRule(len(rule), ctypes.cast(preds, ctypes.POINTER(HbPred)))
+    return crules, keep
+
+
+def hb_compile_rules(ctx: Context, rel_id: int, rules) -> int:
+    """rules: list of rules, each a list of predicates with fields
+    op ('eq'|'ed'|'jaccard'|'absdiff'), attr, k, q, num, den, d."""
+    crules, keep = _c_rules(rules)
+    rs = ctypes.c_uint32()
+    ctx.check(_lib.hb_compile_rules(ctx.h, rel_id, len(rules), crules, ctypes.byref(rs)))
+    return rs.value
+
+
+def hb_partition(ctx: Context, rel_id: int, ruleset_id: int) -> int:
+    n = ctypes.c_uint64()
+    ctx.check(_lib.hb_partition(ctx.h, rel_id, ruleset_id, ctypes.byref(n)))
+    return n.value
+
+
+def hb_match(ctx: Context, rel_id: int, ruleset_id: int, plan="heuristic", out=None, capacity: int = None):
+    """Ca(D) as sorted packed uint64 (i << 32) | j.  With out=None a host
+    numpy array is returned (sized by the capacity protocol); with a torch
+    device tensor `out` (uint64/int64) the pairs are written there and the
+    count is returned."""
+    pl = _PLAN[plan] if isinstance(plan, str) else int(plan)
+    n = ctypes.c_uint64()
+    if out is not None:
+        cap = out.numel() if capacity is None else capacity
+        ctx.check(_lib.hb_match(ctx.h, rel_id, ruleset_id, pl, ctypes.c_void_p(out.data_ptr()), 1, cap,
+                                ctypes.byref(n)))
+        return n.value
+    st = _lib.hb_match(ctx.h, rel_id, ruleset_id, pl, None, 0, 0, ctypes.byref(n))
+    if st == HB_OK:
+        return np.zeros(0, dtype=np.uint64)
+    if st != HB_ERR_CAPACITY:
+        ctx.check(st)
+    buf = np.zeros(max(1, n.value), dtype=np.uint64)
+    ctx.check(_lib.hb_match(ctx.h, rel_id, ruleset_id, pl, ctypes.c_void_p(buf.ctypes.data), 0, len(buf),
+                            ctypes.byref(n)))
+    return buf[: n.value]
+
+
+def hb_ruleset_estimates(ctx: Context, ruleset_id: int) -> Tuple[np.ndarray, np.ndarray]:
+    n = ctypes.c_uint32()
+    ctx.check(_lib.hb_ruleset_estimates(ctx.h, ruleset_id, None, None, 0, ctypes.byref(n)))
+    sp = np.zeros(n.value, dtype=np.float64)
+    cost = np.zeros(n.value, dtype=np.float64)
+    ctx.check(_lib.hb_ruleset_estimates(ctx.h, ruleset_id, ctypes.c_void_p(sp.ctypes.data),
+                                        ctypes.c_void_p(cost.ctypes.data), n.value, ctypes.byref(n)))
+    return sp, cost
+
+
+def hb_ruleset_buckets(ctx: Context, ruleset_id: int, pred: int) -> Tuple[np.ndarray, int]:
+    counts = np.zeros(1024, dtype=np.uint64)
+    n = ctypes.c_uint64()
+    ctx.check(_lib.hb_ruleset_buckets(ctx.h, ruleset_id, pred, ctypes.c_void_p(counts.ctypes.data),
+                                      ctypes.byref(n)))
+    return counts, n.value
+
+
+def hb_epg_path(sp: Sequence[float], cost: Sequence[float], rules: Sequence[Sequence[int]]):
+    """Pure host: [(rule, [pred ids])] in sequential-path order."""
+    sp = np.ascontiguousarray(sp, dtype=np.float64)
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    lens = np.array([len(r) for r in rules], dtype=np.uint32)
+    flat = np.array([p for r in rules for p in r], dtype=np.uint32)
+    if flat.size == 0:
+        flat = np.zeros(1, dtype=np.uint32)
+    out_rules = np.zeros(max(1, len(rules)), dtype=np.uint32)
+    out_preds = np.zeros(max(1, int(lens.sum())), dtype=np.uint32)
+    n = ctypes.c_uint32()
+    st = _lib.hb_epg_path(len(sp), ctypes.c_void_p(sp.ctypes.data), ctypes.c_void_p(cost.ctypes.data),
+                          len(rules), ctypes.c_void_p(lens.ctypes.data), ctypes.c_void_p(flat.ctypes.data),
+                          ctypes.c_void_p(out_rules.ctypes.data), ctypes.c_void_p(out_preds.ctypes.data),
+                          ctypes.byref(n))
+    if st != HB_OK:
+        raise HbError(st, "hb_epg_path failed")
+    res = []
+    o = 0
+    for r in out_rules[: len(rules)]:
+        k = len(set(rules[int(r)]))
+        res.append((int(r), [int(x) for x in out_preds[o:o + k]]))
+        o += k
+    return res
+
+
+def hb_profile_enable(ctx: Context, on: bool = True) -> None:
+    ctx.check(_lib.hb_profile_enable(ctx.h, int(on)))
+
+
+def hb_profile_query(ctx: Context, name: str) -> Tuple[float, int]:
+    ms = ctypes.c_double()
+    n = ctypes.c_uint64()
+    ctx.check(_lib.hb_profile_query(ctx.h, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def hb_profile_reset(ctx: Context) -> None:
+    ctx.check(_lib.hb_profile_reset(ctx.h))
+
+
+def hb_last_match_stats(ctx: Context) -> dict:
+    s = HbMatchStats()
+    ctx.check(_lib.hb_last_match_stats(ctx.h, ctypes.byref(s)))
+    return {"candidate_pairs": s.candidate_pairs, "matched_pairs": s.matched_pairs, "tiles": s.tiles,
+            "launches": s.launches}

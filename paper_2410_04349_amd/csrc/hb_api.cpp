@@ -1,0 +1,1122 @@
+// C-ABI entry points of libhb: context, relation load, rule compilation,
+// key partitioning and pair matching.  Host orchestration only; every step
+// on the data runs in this library's HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hb.h"
+#include "hb_internal.h"
+#include "hb_plan.h"
+
+namespace hb {
+
+struct Failure {
+    hb_status st;
+    std::string msg;
+};
+
+[[noreturn]] static void fail(hb_status st, const std::string& msg) { throw Failure{st, msg}; }
+
+#define HB_HIP(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) fail(HB_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Ctx;
+
+// Device buffer owned through the context's allocator.
+class DevBuf {
+public:
+    DevBuf() = default;
+    DevBuf(Ctx* c, size_t bytes) { alloc(c, bytes); }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { swap(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        release();
+        swap(o);
+        return *this;
+    }
+    void alloc(Ctx* c, size_t bytes);
+    void release();
+    template <typename T>
+    T* as() const { return static_cast<T*>(p_); }
+    void* get() const { return p_; }
+    size_t size() const { return n_; }
+
+private:
+    void swap(DevBuf& o) {
+        std::swap(c_, o.c_);
+        std::swap(p_, o.p_);
+        std::swap(n_, o.n_);
+    }
+    Ctx* c_ = nullptr;
+    void* p_ = nullptr;
+    size_t n_ = 0;
+};
+
+struct Column {
+    int32_t type = 0;
+    uint32_t max_len = 0;
+    double mean_len = 0.0;
+    DevBuf off, bytes, values, valid;
+};
+
+struct GramIndex {
+    uint32_t attr = 0, q = 0, max_cnt = 0;
+    DevBuf off, cnt, codes, flags;
+    GramDev dev() const {
+        GramDev g{};
+        g.off = off.as<uint64_t>();
+        g.cnt = cnt.as<uint32_t>();
+        g.codes = codes.as<uint32_t>();
+        g.flags = flags.as<uint8_t>();
+        g.q = q;
+        g.max_cnt = max_cnt;
+        g.attr = attr;
+        return g;
+    }
+};
+
+struct Partition {
+    uint32_t attr = 0, n_valid = 0, n_blocks = 0;
+    uint64_t n_tiles = 0, pairs = 0;
+    DevBuf perm, blk_start, blk_size, tile_prefix;
+};
+
+struct Relation {
+    uint32_t id = 0, n_rows = 0, n_cols = 0;
+    std::vector<Column> cols;
+    std::vector<ColDev> h_cols;
+    DevBuf d_cols;
+    std::map<std::pair<uint32_t, uint32_t>, GramIndex> grams;
+    std::map<uint32_t, Partition> parts;
+    std::map<std::vector<uint32_t>, uint64_t> composite;
+};
+
+struct RuleSet {
+    uint32_t id = 0, rel_id = 0;
+    std::vector<hb_pred> distinct;
+    std::vector<std::vector<uint32_t>> rules;  // distinct predicate ids per rule, input order
+    std::vector<uint32_t> keys;                // blocking-key attributes, first-appearance order
+    std::vector<double> sp, cost;
+    std::vector<std::vector<uint64_t>> buckets;
+    std::vector<uint64_t> bucket_n;
+    bool partitioned = false;
+    uint64_t candidates = 0;
+    bool has_result = false;
+    int result_plan = -1;
+    DevBuf result;
+    uint64_t n_result = 0;
+};
+
+struct ProfEntry {
+    double ms = 0.0;
+    uint64_t launches = 0;
+};
+
+struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hb_alloc_fn alloc_fn = nullptr;
+    hb_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    std::string err;
+    uint32_t next_id = 1;
+    std::map<uint32_t, std::unique_ptr<Relation>> rels;
+    std::map<uint32_t, std::unique_ptr<RuleSet>> rulesets;
+    bool profiling = false;
+    std::map<std::string, ProfEntry> prof;
+    std::vector<Pending> pending;
+    hb_match_stats last{};
+    uint32_t lds_limit = 0;
+
+    void* raw_alloc(size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        void* p = nullptr;
+        if (alloc_fn) {
+            p = alloc_fn(bytes, user);
+        } else {
+            if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
+        }
+        if (!p) fail(HB_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        return p;
+    }
+    void raw_free(void* p) {
+        if (!p) return;
+        if (free_fn) free_fn(p, user);
+        else (void)hipFreeAsync(p, stream);
+    }
+
+    template <typename F>
+    void timed(const char* name, F&& launch) {
+        if (!profiling) {
+            HB_HIP(launch());
+            return;
+        }
+        Pending pd;
+        pd.name = name;
+        HB_HIP(hipEventCreate(&pd.a));
+        HB_HIP(hipEventCreate(&pd.b));
+        HB_HIP(hipEventRecord(pd.a, stream));
+        HB_HIP(launch());
+        HB_HIP(hipEventRecord(pd.b, stream));
+        pending.push_back(pd);
+    }
+    void drain_profile() {
+        for (auto& pd : pending) {
+            (void)hipEventSynchronize(pd.b);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, pd.a, pd.b);
+            auto& e = prof[pd.name];
+            e.ms += ms;
+            e.launches += 1;
+            (void)hipEventDestroy(pd.a);
+            (void)hipEventDestroy(pd.b);
+        }
+        pending.clear();
+    }
+    void sync() { HB_HIP(hipStreamSynchronize(stream)); }
+};
+
+void DevBuf::alloc(Ctx* c, size_t bytes) {
+    release();
+    c_ = c;
+    p_ = c->raw_alloc(bytes);
+    n_ = bytes;
+}
+
+void DevBuf::release() {
+    if (p_ && c_) c_->raw_free(p_);
+    p_ = nullptr;
+    n_ = 0;
+    c_ = nullptr;
+}
+
+template <typename T>
+static T read1(Ctx* c, const T* dptr) {
+    T v{};
+    HB_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    return v;
+}
+
+static void zero(Ctx* c, void* p, size_t bytes) { HB_HIP(hipMemsetAsync(p, 0, bytes, c->stream)); }
+
+static Relation& get_rel(Ctx* c, uint32_t id) {
+    auto it = c->rels.find(id);
+    if (it == c->rels.end()) fail(HB_ERR_STALE_ID, "unknown relation id " + std::to_string(id));
+    return *it->second;
+}
+
+static RuleSet& get_rs(Ctx* c, uint32_t id, uint32_t rel_id) {
+    auto it = c->rulesets.find(id);
+    if (it == c->rulesets.end()) fail(HB_ERR_STALE_ID, "unknown rule set id " + std::to_string(id));
+    if (it->second->rel_id != rel_id) fail(HB_ERR_STALE_ID, "rule set was compiled for another relation");
+    return *it->second;
+}
+
+static int bit_width(uint64_t v) {
+    int b = 0;
+    while (v) { ++b; v >>= 1; }
+    return b;
+}
+
+static std::vector<int> shifts_for_bits(int bits, int base) {
+    std::vector<int> s;
+    for (int x = 0; x < bits; x += 8) s.push_back(base + x);
+    return s;
+}
+
+// ------------------------------------------------------------ load
+
+static void load_relation(Ctx* c, uint32_t n_rows, uint32_t n_cols, const hb_column* cols, int on_device,
+                          uint32_t* rel_id) {
+    if (!cols || !rel_id) fail(HB_ERR_INVALID_ARG, "NULL argument");
+    if (n_rows == 0 || n_rows >= 0x80000000u) fail(HB_ERR_INVALID_ARG, "n_rows must be in [1, 2^31)");
+    if (n_cols == 0 || n_cols > 256) fail(HB_ERR_INVALID_ARG, "n_cols must be in [1, 256]");
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    auto rel = std::make_unique<Relation>();
+    rel->n_rows = n_rows;
+    rel->n_cols = n_cols;
+    rel->cols.resize(n_cols);
+    const size_t vbytes = (n_rows + 7) / 8;
+    DevBuf stats(c, 32);
+    for (uint32_t a = 0; a < n_cols; ++a) {
+        const hb_column& in = cols[a];
+        Column& col = rel->cols[a];
+        col.type = in.type;
+        if (in.type == HB_COL_STRING) {
+            if (!in.offsets) fail(HB_ERR_INVALID_ARG, "string column " + std::to_string(a) + " has no offsets");
+            uint64_t total;
+            if (on_device) {
+                total = read1(c, in.offsets + n_rows);
+            } else {
+                if (in.offsets[0] != 0) fail(HB_ERR_INVALID_ARG, "string offsets must start at 0");
+                for (uint32_t r = 0; r < n_rows; ++r)
+                    if (in.offsets[r + 1] < in.offsets[r])
+                        fail(HB_ERR_INVALID_ARG, "string offsets of column " + std::to_string(a) + " decrease");
+                total = in.offsets[n_rows];
+            }
+            if (total > 0 && !in.bytes) fail(HB_ERR_INVALID_ARG, "string column " + std::to_string(a) + " has no bytes");
+            col.off.alloc(c, sizeof(uint64_t) * ((size_t)n_rows + 1));
+            HB_HIP(hipMemcpyAsync(col.off.get(), in.offsets, sizeof(uint64_t) * ((size_t)n_rows + 1), kind, c->stream));
+            col.bytes.alloc(c, total + 16);
+            if (total) HB_HIP(hipMemcpyAsync(col.bytes.get(), in.bytes, total, kind, c->stream));
+            zero(c, stats.get(), 32);
+            uint32_t* d_max = stats.as<uint32_t>();
+            unsigned long long* d_total = (unsigned long long*)(stats.as<uint8_t>() + 8);
+            uint32_t* d_bad = (uint32_t*)(stats.as<uint8_t>() + 16);
+            HB_HIP(launch_string_stats(col.off.as<uint64_t>(), n_rows, d_max, d_total, d_bad, c->stream));
+            uint32_t h[6];
+            HB_HIP(hipMemcpyAsync(h, stats.get(), 24, hipMemcpyDeviceToHost, c->stream));
+            c->sync();
+            if (h[4]) fail(HB_ERR_INVALID_ARG, "string offsets of column " + std::to_string(a) + " are invalid");
+            col.max_len = h[0];
+            uint64_t tot;
+            std::memcpy(&tot, &h[2], 8);
+            col.mean_len = (double)tot / (double)n_rows;
+        } else if (in.type == HB_COL_CATEGORICAL || in.type == HB_COL_INT64) {
+            if (!in.values) fail(HB_ERR_INVALID_ARG, "column " + std::to_string(a) + " has no values");
+            col.values.alloc(c, sizeof(int64_t) * n_rows);
+            HB_HIP(hipMemcpyAsync(col.values.get(), in.values, sizeof(int64_t) * n_rows, kind, c->stream));
+        } else {
+            fail(HB_ERR_INVALID_ARG, "column " + std::to_string(a) + " has an unknown type");
+        }
+        if (in.valid) {
+            col.valid.alloc(c, vbytes);
+            HB_HIP(hipMemcpyAsync(col.valid.get(), in.valid, vbytes, kind, c->stream));
+        }
+    }
+    rel->h_cols.resize(n_cols);
+    for (uint32_t a = 0; a < n_cols; ++a) {
+        const Column& col = rel->cols[a];
+        ColDev d{};
+        d.type = col.type;
+        d.max_len = col.max_len;
+        d.off = col.off.as<uint64_t>();
+        d.bytes = col.bytes.as<uint8_t>();
+        d.values = col.values.as<int64_t>();
+        d.valid = col.valid.as<uint8_t>();
+        rel->h_cols[a] = d;
+    }
+    rel->d_cols.alloc(c, sizeof(ColDev) * n_cols);
+    HB_HIP(hipMemcpyAsync(rel->d_cols.get(), rel->h_cols.data(), sizeof(ColDev) * n_cols, hipMemcpyHostToDevice,
+                          c->stream));
+    c->sync();
+    rel->id = c->next_id++;
+    *rel_id = rel->id;
+    c->rels[rel->id] = std::move(rel);
+}
+
+// ------------------------------------------------------------ gram index
+
+static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
+    auto key = std::make_pair(attr, q);
+    auto it = rel.grams.find(key);
+    if (it != rel.grams.end()) return it->second;
+    const uint32_t n = rel.n_rows;
+    GramIndex g;
+    g.attr = attr;
+    g.q = q;
+    DevBuf slots(c, sizeof(uint64_t) * ((size_t)n + 1));
+    g.off.alloc(c, sizeof(uint64_t) * ((size_t)n + 1));
+    const ColDev* dcol = rel.d_cols.as<ColDev>() + attr;
+    HB_HIP(launch_gram_slots(dcol, n, q, slots.as<uint64_t>(), c->stream));
+    zero(c, slots.as<uint64_t>() + n, sizeof(uint64_t));
+    DevBuf tmp(c, sizeof(uint64_t) * scan_tmp_elems((size_t)n + 1));
+    HB_HIP(launch_exclusive_scan_u64(slots.as<uint64_t>(), g.off.as<uint64_t>(), (size_t)n + 1, tmp.as<uint64_t>(),
+                                     c->stream));
+    const uint64_t total = read1(c, g.off.as<uint64_t>() + n);
+    g.codes.alloc(c, sizeof(uint32_t) * (total + 1));
+    g.cnt.alloc(c, sizeof(uint32_t) * n);
+    g.flags.alloc(c, n);
+    DevBuf mx(c, sizeof(unsigned int));
+    zero(c, mx.get(), sizeof(unsigned int));
+    c->timed("gram_build", [&] {
+        return launch_gram_build(dcol, n, q, g.off.as<uint64_t>(), g.codes.as<uint32_t>(), g.cnt.as<uint32_t>(),
+                                 g.flags.as<uint8_t>(), mx.as<unsigned int>(), c->stream);
+    });
+    g.max_cnt = read1(c, mx.as<unsigned int>());
+    auto res = rel.grams.emplace(key, std::move(g));
+    return res.first->second;
+}
+
+// ------------------------------------------------------------ compile
+
+static bool same_pred(const hb_pred& a, const hb_pred& b) {
+    if (a.op != b.op || a.attr != b.attr) return false;
+    switch (a.op) {
+    case HB_ED_LE: return a.k == b.k;
+    case HB_JACCARD_GE: return a.q == b.q && a.num == b.num && a.den == b.den;
+    case HB_ABSDIFF_LE: return a.d == b.d;
+    default: return true;
+    }
+}
+
+static double pred_cost(const Relation& rel, const hb_pred& p) {
+    const Column& col = rel.cols[p.attr];
+    const double L = col.mean_len;
+    switch (p.op) {
+    case HB_EQ: return col.type == HB_COL_STRING ? 1.0 + L / 16.0 : 1.0;
+    case HB_ABSDIFF_LE: return 1.5;
+    case HB_ED_LE: return 4.0 + 17.0 * L * std::max(1.0, std::ceil(L / 64.0));
+    case HB_JACCARD_GE: return 4.0 + 6.0 * std::max(1.0, L - (double)p.q + 1.0);
+    }
+    return 1.0;
+}
+
+static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_rule* rules, uint32_t* ruleset_id) {
+    Relation& rel = get_rel(c, rel_id);
+    if (!rules || !ruleset_id) fail(HB_ERR_INVALID_ARG, "NULL argument");
+    if (n_rules == 0) fail(HB_ERR_INVALID_ARG, "empty rule set");
+    if (n_rules > HB_MAX_RULES) fail(HB_ERR_LIMIT, "more than 64 rules");
+    auto rs = std::make_unique<RuleSet>();
+    rs->rel_id = rel_id;
+    for (uint32_t r = 0; r < n_rules; ++r) {
+        const hb_rule& rule = rules[r];
+        if (rule.n_preds == 0 || !rule.preds) fail(HB_ERR_INVALID_ARG, "rule " + std::to_string(r) + " is empty");
+        if (rule.n_preds > HB_MAX_RULE_PREDS) fail(HB_ERR_LIMIT, "rule " + std::to_string(r) + " has more than 10 predicates");
+        std::vector<uint32_t> ids;
+        int64_t key = -1;
+        for (uint32_t x = 0; x < rule.n_preds; ++x) {
+            const hb_pred& p = rule.preds[x];
+            const std::string where = "rule " + std::to_string(r) + " predicate " + std::to_string(x);
+            if (p.attr >= rel.n_cols) fail(HB_ERR_INVALID_ARG, where + ": attribute out of range");
+            const int32_t t = rel.cols[p.attr].type;
+            switch (p.op) {
+            case HB_EQ:
+                if (key < 0 && t != HB_COL_STRING) key = p.attr;
+                break;
+            case HB_ED_LE:
+                if (t != HB_COL_STRING) fail(HB_ERR_TYPE, where + ": edit distance needs a string attribute");
+                if (p.k < 0 || p.k > HB_MAX_ED_K) fail(HB_ERR_INVALID_ARG, where + ": k must be in [0, 255]");
+                if (rel.cols[p.attr].max_len > HB_MAX_ED_LEN)
+                    fail(HB_ERR_LIMIT, where + ": strings longer than 512 bytes");
+                break;
+            case HB_JACCARD_GE:
+                if (t != HB_COL_STRING) fail(HB_ERR_TYPE, where + ": Jaccard needs a string attribute");
+                if (p.q < 1 || p.q > HB_MAX_Q) fail(HB_ERR_INVALID_ARG, where + ": q must be in [1, 4]");
+                if (p.den == 0 || p.num > p.den) fail(HB_ERR_INVALID_ARG, where + ": need 0 <= num <= den, den > 0");
+                if (rel.cols[p.attr].max_len > HB_MAX_GRAM_LEN)
+                    fail(HB_ERR_LIMIT, where + ": strings longer than 4096 bytes");
+                break;
+            case HB_ABSDIFF_LE:
+                if (t != HB_COL_INT64) fail(HB_ERR_TYPE, where + ": |a-b| <= d needs an int64 attribute");
+                if (p.d < 0) fail(HB_ERR_INVALID_ARG, where + ": d must be >= 0");
+                break;
+            default:
+                fail(HB_ERR_INVALID_ARG, where + ": unknown operator");
+            }
+            uint32_t id = (uint32_t)rs->distinct.size();
+            for (uint32_t y = 0; y < rs->distinct.size(); ++y)
+                if (same_pred(rs->distinct[y], p)) { id = y; break; }
+            if (id == rs->distinct.size()) {
+                if (rs->distinct.size() >= HB_MAX_DISTINCT_PREDS) fail(HB_ERR_LIMIT, "more than 64 distinct predicates");
+                hb_pred np = p;
+                if (np.op != HB_ED_LE) np.k = 0;
+                if (np.op != HB_JACCARD_GE) { np.q = 0; np.num = 0; np.den = 1; }
+                if (np.op != HB_ABSDIFF_LE) np.d = 0;
+                rs->distinct.push_back(np);
+            }
+            if (std::find(ids.begin(), ids.end(), id) == ids.end()) ids.push_back(id);
+        }
+        if (key < 0) fail(HB_ERR_UNBLOCKABLE, "rule " + std::to_string(r) + " has no equality on a categorical/int64 attribute");
+        if (std::find(rs->keys.begin(), rs->keys.end(), (uint32_t)key) == rs->keys.end()) rs->keys.push_back((uint32_t)key);
+        rs->rules.push_back(ids);
+    }
+    if (rs->keys.size() > HB_MAX_KEYS) fail(HB_ERR_LIMIT, "more than 4 distinct blocking keys");
+
+    // q-gram indexes, selectivity (LSH evenness) and cost estimates
+    const size_t np = rs->distinct.size();
+    rs->sp.resize(np);
+    rs->cost.resize(np);
+    rs->buckets.assign(np, std::vector<uint64_t>(kLshK, 0));
+    rs->bucket_n.assign(np, 0);
+    DevBuf hist(c, sizeof(unsigned long long) * kLshK * np);
+    zero(c, hist.get(), hist.size());
+    for (size_t p = 0; p < np; ++p) {
+        const hb_pred& pr = rs->distinct[p];
+        if (pr.op == HB_JACCARD_GE) gram_index(c, rel, pr.attr, pr.q);
+        const int op = pr.op == HB_EQ ? 0 : pr.op == HB_ED_LE ? 1 : pr.op == HB_JACCARD_GE ? 2 : 3;
+        c->timed("lsh", [&] {
+            return launch_lsh_hist(rel.d_cols.as<ColDev>() + pr.attr, rel.n_rows, op, pr.q, pr.d,
+                                   hist.as<unsigned long long>() + p * kLshK, c->stream);
+        });
+    }
+    std::vector<uint64_t> h(kLshK * np);
+    HB_HIP(hipMemcpyAsync(h.data(), hist.get(), sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    double cmax = 0.0;
+    for (size_t p = 0; p < np; ++p) {
+        unsigned __int128 s2 = 0;
+        uint64_t n = 0;
+        for (int b = 0; b < kLshK; ++b) {
+            uint64_t v = h[p * kLshK + b];
+            rs->buckets[p][b] = v;
+            n += v;
+            s2 += (unsigned __int128)v * v;
+        }
+        rs->bucket_n[p] = n;
+        if (n == 0) {
+            rs->sp[p] = 0.0;
+        } else {
+            // sp = sqrt((k * sum b^2 - n^2) / (n^2 (k - 1)))
+            unsigned __int128 num = (unsigned __int128)kLshK * s2 - (unsigned __int128)n * n;
+            unsigned __int128 den = (unsigned __int128)n * n * (kLshK - 1);
+            rs->sp[p] = std::sqrt((double)num / (double)den);
+        }
+        rs->cost[p] = pred_cost(rel, rs->distinct[p]);
+        cmax = std::max(cmax, rs->cost[p]);
+    }
+    for (size_t p = 0; p < np; ++p) rs->cost[p] /= cmax;
+    rs->id = c->next_id++;
+    *ruleset_id = rs->id;
+    c->rulesets[rs->id] = std::move(rs);
+}
+
+// ------------------------------------------------------------ partition
+
+// Rows valid on every attribute in `attrs`, sorted by those attributes
+// (lexicographically, in the given order); returns the row count.
+static uint32_t sort_rows_by(Ctx* c, Relation& rel, const std::vector<uint32_t>& attrs, DevBuf& rows_out) {
+    const uint32_t n = rel.n_rows;
+    DevBuf d_attrs(c, sizeof(uint32_t) * attrs.size());
+    HB_HIP(hipMemcpyAsync(d_attrs.get(), attrs.data(), sizeof(uint32_t) * attrs.size(), hipMemcpyHostToDevice, c->stream));
+    DevBuf flags(c, sizeof(uint32_t) * n), dest(c, sizeof(uint32_t) * n);
+    HB_HIP(launch_multi_valid_flags(rel.d_cols.as<ColDev>(), d_attrs.as<uint32_t>(), (uint32_t)attrs.size(), n,
+                                    flags.as<uint32_t>(), c->stream));
+    DevBuf stmp(c, sizeof(uint32_t) * scan_tmp_elems(n));
+    HB_HIP(launch_exclusive_scan_u32(flags.as<uint32_t>(), dest.as<uint32_t>(), n, stmp.as<uint32_t>(), c->stream));
+    uint32_t last[2];
+    HB_HIP(hipMemcpyAsync(&last[0], dest.as<uint32_t>() + n - 1, 4, hipMemcpyDeviceToHost, c->stream));
+    HB_HIP(hipMemcpyAsync(&last[1], flags.as<uint32_t>() + n - 1, 4, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    const uint32_t nv = last[0] + last[1];
+    rows_out.alloc(c, sizeof(uint32_t) * (nv + 1));
+    if (nv == 0) return 0;
+    HB_HIP(launch_compact_rows(flags.as<uint32_t>(), dest.as<uint32_t>(), n, rows_out.as<uint32_t>(), c->stream));
+    DevBuf keys(c, sizeof(uint64_t) * nv), keys_alt(c, sizeof(uint64_t) * nv), rows_alt(c, sizeof(uint32_t) * nv);
+    DevBuf rtmp(c, radix_tmp_bytes(nv));
+    DevBuf mm(c, 32);
+    // least significant attribute first (LSD over attributes)
+    for (size_t x = attrs.size(); x-- > 0;) {
+        const uint32_t a = attrs[x];
+        zero(c, mm.get(), 32);
+        unsigned long long init_min = ~0ull;
+        HB_HIP(hipMemcpyAsync(mm.get(), &init_min, 8, hipMemcpyHostToDevice, c->stream));
+        HB_HIP(launch_minmax_u64(rel.cols[a].values.as<int64_t>(), rel.cols[a].valid.as<uint8_t>(), n,
+                                 (unsigned long long*)mm.get(), (unsigned long long*)(mm.as<uint8_t>() + 8),
+                                 (unsigned int*)(mm.as<uint8_t>() + 16), c->stream));
+        unsigned long long mmh[2];
+        HB_HIP(hipMemcpyAsync(mmh, mm.get(), 16, hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+        HB_HIP(launch_gather_key(rel.d_cols.as<ColDev>(), a, mmh[0], rows_out.as<uint32_t>(), nv, keys.as<uint64_t>(),
+                                 c->stream));
+        std::vector<int> sh = shifts_for_bits(bit_width(mmh[1] - mmh[0]), 0);
+        bool in_alt = false;
+        c->timed("partition_sort", [&] {
+            return radix_sort_pairs(keys.as<uint64_t>(), rows_out.as<uint32_t>(), keys_alt.as<uint64_t>(),
+                                    rows_alt.as<uint32_t>(), nv, sh.data(), (int)sh.size(), rtmp.get(), &in_alt,
+                                    c->stream);
+        });
+        if (in_alt) HB_HIP(hipMemcpyAsync(rows_out.get(), rows_alt.get(), sizeof(uint32_t) * nv,
+                                          hipMemcpyDeviceToDevice, c->stream));
+    }
+    return nv;
+}
+
+// Groups of equal values over `attrs` among sorted rows: group starts.
+static uint32_t group_rows(Ctx* c, Relation& rel, const std::vector<uint32_t>& attrs, const DevBuf& rows, uint32_t nv,
+                           DevBuf& gstart) {
+    DevBuf d_attrs(c, sizeof(uint32_t) * attrs.size());
+    HB_HIP(hipMemcpyAsync(d_attrs.get(), attrs.data(), sizeof(uint32_t) * attrs.size(), hipMemcpyHostToDevice, c->stream));
+    DevBuf head(c, sizeof(uint32_t) * nv), gid(c, sizeof(uint32_t) * nv);
+    HB_HIP(launch_group_heads(rel.d_cols.as<ColDev>(), d_attrs.as<uint32_t>(), (uint32_t)attrs.size(),
+                              rows.as<uint32_t>(), nv, head.as<uint32_t>(), c->stream));
+    DevBuf stmp(c, sizeof(uint32_t) * scan_tmp_elems(nv));
+    HB_HIP(launch_exclusive_scan_u32(head.as<uint32_t>(), gid.as<uint32_t>(), nv, stmp.as<uint32_t>(), c->stream));
+    uint32_t last[2];
+    HB_HIP(hipMemcpyAsync(&last[0], gid.as<uint32_t>() + nv - 1, 4, hipMemcpyDeviceToHost, c->stream));
+    HB_HIP(hipMemcpyAsync(&last[1], head.as<uint32_t>() + nv - 1, 4, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    const uint32_t ng = last[0] + last[1];
+    gstart.alloc(c, sizeof(uint32_t) * ng);
+    HB_HIP(launch_group_sizes(head.as<uint32_t>(), gid.as<uint32_t>(), nv, ng, gstart.as<uint32_t>(), c->stream));
+    return ng;
+}
+
+static Partition& key_partition(Ctx* c, Relation& rel, uint32_t attr) {
+    auto it = rel.parts.find(attr);
+    if (it != rel.parts.end()) return it->second;
+    Partition P;
+    P.attr = attr;
+    std::vector<uint32_t> attrs{attr};
+    P.n_valid = sort_rows_by(c, rel, attrs, P.perm);
+    P.blk_start.alloc(c, 4);
+    P.blk_size.alloc(c, 4);
+    P.tile_prefix.alloc(c, 8);
+    zero(c, P.tile_prefix.get(), 8);
+    if (P.n_valid >= 2) {
+        DevBuf gstart;
+        const uint32_t ng = group_rows(c, rel, attrs, P.perm, P.n_valid, gstart);
+        DevBuf flags(c, sizeof(uint32_t) * ng), dest(c, sizeof(uint32_t) * ng);
+        HB_HIP(launch_ge2_flags(gstart.as<uint32_t>(), ng, P.n_valid, flags.as<uint32_t>(), c->stream));
+        DevBuf stmp(c, sizeof(uint32_t) * scan_tmp_elems(ng));
+        HB_HIP(launch_exclusive_scan_u32(flags.as<uint32_t>(), dest.as<uint32_t>(), ng, stmp.as<uint32_t>(), c->stream));
+        uint32_t last[2];
+        HB_HIP(hipMemcpyAsync(&last[0], dest.as<uint32_t>() + ng - 1, 4, hipMemcpyDeviceToHost, c->stream));
+        HB_HIP(hipMemcpyAsync(&last[1], flags.as<uint32_t>() + ng - 1, 4, hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+        P.n_blocks = last[0] + last[1];
+        P.blk_start.alloc(c, sizeof(uint32_t) * (P.n_blocks + 1));
+        P.blk_size.alloc(c, sizeof(uint32_t) * (P.n_blocks + 1));
+        DevBuf tiles(c, sizeof(uint64_t) * (P.n_blocks + 1));
+        zero(c, tiles.get(), tiles.size());
+        DevBuf pairs(c, sizeof(unsigned long long));
+        zero(c, pairs.get(), 8);
+        HB_HIP(launch_block_table(gstart.as<uint32_t>(), ng, P.n_valid, dest.as<uint32_t>(), P.blk_start.as<uint32_t>(),
+                                  P.blk_size.as<uint32_t>(), tiles.as<uint64_t>(), pairs.as<unsigned long long>(),
+                                  c->stream));
+        P.tile_prefix.alloc(c, sizeof(uint64_t) * (P.n_blocks + 1));
+        DevBuf ttmp(c, sizeof(uint64_t) * scan_tmp_elems((size_t)P.n_blocks + 1));
+        HB_HIP(launch_exclusive_scan_u64(tiles.as<uint64_t>(), P.tile_prefix.as<uint64_t>(), (size_t)P.n_blocks + 1,
+                                         ttmp.as<uint64_t>(), c->stream));
+        P.n_tiles = read1(c, P.tile_prefix.as<uint64_t>() + P.n_blocks);
+        P.pairs = read1(c, pairs.as<unsigned long long>());
+    }
+    auto res = rel.parts.emplace(attr, std::move(P));
+    return res.first->second;
+}
+
+static uint64_t composite_pairs(Ctx* c, Relation& rel, const std::vector<uint32_t>& attrs) {
+    auto it = rel.composite.find(attrs);
+    if (it != rel.composite.end()) return it->second;
+    DevBuf rows;
+    const uint32_t nv = sort_rows_by(c, rel, attrs, rows);
+    uint64_t total = 0;
+    if (nv >= 2) {
+        DevBuf gstart;
+        const uint32_t ng = group_rows(c, rel, attrs, rows, nv, gstart);
+        DevBuf pairs(c, 8);
+        zero(c, pairs.get(), 8);
+        HB_HIP(launch_group_pairs(gstart.as<uint32_t>(), ng, nv, pairs.as<unsigned long long>(), c->stream));
+        total = read1(c, pairs.as<unsigned long long>());
+    }
+    rel.composite[attrs] = total;
+    return total;
+}
+
+static void partition(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint64_t* n_cand) {
+    Relation& rel = get_rel(c, rel_id);
+    RuleSet& rs = get_rs(c, rs_id, rel_id);
+    for (uint32_t k : rs.keys) key_partition(c, rel, k);
+    // distinct pairs sharing at least one key, by inclusion-exclusion
+    const size_t K = rs.keys.size();
+    __int128 total = 0;
+    for (uint32_t mask = 1; mask < (1u << K); ++mask) {
+        std::vector<uint32_t> S;
+        for (size_t x = 0; x < K; ++x)
+            if (mask & (1u << x)) S.push_back(rs.keys[x]);
+        uint64_t p = S.size() == 1 ? rel.parts.at(S[0]).pairs : composite_pairs(c, rel, S);
+        if (S.size() % 2 == 1) total += p; else total -= p;
+    }
+    rs.candidates = (uint64_t)total;
+    rs.partitioned = true;
+    if (n_cand) *n_cand = rs.candidates;
+}
+
+// ------------------------------------------------------------ match
+
+struct KeyPlan {
+    std::vector<Instr> code;
+    MatchParams mp{};
+};
+
+static uint32_t align_up(uint32_t v, uint32_t a) { return (v + a - 1) / a * a; }
+
+// LDS per workgroup the match kernel aims to stay under (two workgroups per CU)
+constexpr uint32_t kLdsBudget = 80 * 1024;
+
+// Device plan for the blocks of key number `ka`: the sequential path with
+// rules that need an earlier key dropped (the owner check rules those pairs
+// out) and the equality on this key dropped (it holds inside a block).
+static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector<PathRule>& path, size_t ka,
+                           KeyPlan& kp) {
+    const uint32_t key = rs.keys[ka];
+    std::vector<uint32_t> int_attr, str_attr;
+    std::vector<std::pair<uint32_t, uint32_t>> gram_key;
+    auto res_of = [](std::vector<uint32_t>& v, uint32_t a) {
+        auto it = std::find(v.begin(), v.end(), a);
+        if (it != v.end()) return (uint32_t)(it - v.begin());
+        v.push_back(a);
+        return (uint32_t)(v.size() - 1);
+    };
+    std::vector<uint32_t> prev;
+    for (size_t x = 0; x < ka; ++x) prev.push_back(res_of(int_attr, rs.keys[x]));
+
+    std::vector<Instr> code;
+    bool any_rule = false;
+    for (const PathRule& pr : path) {
+        bool impossible = false;
+        for (uint32_t p : pr.preds) {
+            const hb_pred& d = rs.distinct[p];
+            if (d.op == HB_EQ && rel.cols[d.attr].type != HB_COL_STRING)
+                for (size_t x = 0; x < ka; ++x)
+                    if (rs.keys[x] == d.attr) impossible = true;
+        }
+        if (impossible) continue;
+        any_rule = true;
+        const size_t first = code.size();
+        for (uint32_t p : pr.preds) {
+            const hb_pred& d = rs.distinct[p];
+            const int32_t t = rel.cols[d.attr].type;
+            if (d.op == HB_EQ && t != HB_COL_STRING && d.attr == key) continue;
+            Instr in{};
+            in.slot = (uint8_t)p;
+            switch (d.op) {
+            case HB_EQ:
+                if (t == HB_COL_STRING) {
+                    in.op = OP_EQ_STR;
+                    in.res = (uint8_t)res_of(str_attr, d.attr);
+                } else {
+                    in.op = OP_EQ_INT;
+                    in.res = (uint8_t)res_of(int_attr, d.attr);
+                }
+                break;
+            case HB_ABSDIFF_LE:
+                in.op = OP_ABSDIFF;
+                in.res = (uint8_t)res_of(int_attr, d.attr);
+                in.k_or_d = d.d;
+                break;
+            case HB_ED_LE:
+                in.op = OP_ED;
+                in.res = (uint8_t)res_of(str_attr, d.attr);
+                in.k_or_d = d.k;
+                break;
+            case HB_JACCARD_GE: {
+                in.op = OP_JAC;
+                auto gk = std::make_pair(d.attr, d.q);
+                auto it = std::find(gram_key.begin(), gram_key.end(), gk);
+                if (it == gram_key.end()) {
+                    gram_key.push_back(gk);
+                    in.res = (uint8_t)(gram_key.size() - 1);
+                } else {
+                    in.res = (uint8_t)(it - gram_key.begin());
+                }
+                in.num = d.num;
+                in.den = d.den;
+                break;
+            }
+            }
+            code.push_back(in);
+        }
+        Instr cp{};
+        cp.op = OP_CP;
+        code.push_back(cp);
+        const uint16_t cpi = (uint16_t)(code.size() - 1);
+        for (size_t x = first; x < code.size(); ++x) code[x].cp = cpi;
+    }
+    if (!any_rule) return false;
+    if (int_attr.size() > (size_t)kMaxIntRes || str_attr.size() > (size_t)kMaxStrRes ||
+        gram_key.size() > (size_t)kMaxGramRes)
+        fail(HB_ERR_LIMIT, "rule set reads more than 16 int, 8 string or 8 q-gram attributes");
+    if (code.size() > 60000) fail(HB_ERR_LIMIT, "plan too long");
+
+    MatchParams& m = kp.mp;
+    m.n_int = (uint32_t)int_attr.size();
+    m.n_str = (uint32_t)str_attr.size();
+    m.n_gram = (uint32_t)gram_key.size();
+    m.n_prev = (uint32_t)prev.size();
+    for (size_t x = 0; x < int_attr.size(); ++x) m.int_attr[x] = int_attr[x];
+    for (size_t x = 0; x < prev.size(); ++x) m.prev_res[x] = prev[x];
+    uint32_t ed_words = 1;
+    for (size_t x = 0; x < str_attr.size(); ++x) {
+        m.str_attr[x] = str_attr[x];
+        const uint32_t ml = rel.cols[str_attr[x]].max_len;
+        m.str_stride[x] = align_up(std::max<uint32_t>(ml, 4), 4);
+        ed_words = std::max<uint32_t>(ed_words, (ml + 63) / 64);
+    }
+    for (size_t x = 0; x < gram_key.size(); ++x) {
+        GramIndex& g = gram_index(c, rel, gram_key[x].first, gram_key[x].second);
+        m.gram[x] = g.dev();
+        if (m.gram[x].max_cnt == 0) m.gram[x].max_cnt = 1;
+    }
+    m.ed_words = ed_words;
+    // LDS layout: metadata and per-wave tables always; the bulk of each
+    // string / gram resource is staged while the total stays within the
+    // occupancy budget, otherwise that resource is read from HBM.
+    bool any_ed = false;
+    for (const Instr& in : code) any_ed |= in.op == OP_ED;
+    uint32_t wave_bytes = any_ed ? 256 * ed_words * 8 : 0;
+    for (uint32_t x = 0; x < m.n_gram; ++x) wave_bytes += align_up(m.gram[x].max_cnt * 4, 16);
+    wave_bytes = align_up(std::max<uint32_t>(wave_bytes, 16), 16);
+    uint32_t fixed = align_up(m.n_int * kTile * 9, 16) + align_up(m.n_str * kTile * 5, 16) +
+                     align_up(m.n_gram * kTile * 5, 16) + kWaves * wave_bytes + 64;
+    const uint32_t budget = std::min<uint32_t>(c->lds_limit, kLdsBudget);
+    if (fixed > c->lds_limit) fail(HB_ERR_LIMIT, "the rule set's per-tile working set exceeds the device LDS");
+    uint32_t bulk = 0;
+    m.str_global = 0;
+    m.gram_global = 0;
+    for (uint32_t x = 0; x < m.n_str; ++x) {
+        const uint32_t b = kTile * m.str_stride[x];
+        if (fixed + bulk + b <= budget) bulk += b; else m.str_global |= 1u << x;
+    }
+    for (uint32_t x = 0; x < m.n_gram; ++x) {
+        const uint32_t b = align_up(kTile * m.gram[x].max_cnt * 4, 16);
+        if (fixed + bulk + b <= budget) bulk += b; else m.gram_global |= 1u << x;
+    }
+    uint32_t off = 0;
+    m.lds_int = off;
+    off += m.n_int * kTile * 8;
+    m.lds_int_valid = off;
+    off += m.n_int * kTile;
+    off = align_up(off, 16);
+    for (uint32_t x = 0; x < m.n_str; ++x) {
+        m.lds_str[x] = off;
+        if (!((m.str_global >> x) & 1)) off += kTile * m.str_stride[x];
+    }
+    off = align_up(off, 16);
+    m.lds_str_len = off;
+    off += m.n_str * kTile * 4;
+    m.lds_str_valid = off;
+    off += m.n_str * kTile;
+    off = align_up(off, 16);
+    for (uint32_t x = 0; x < m.n_gram; ++x) {
+        m.lds_gram[x] = off;
+        if (!((m.gram_global >> x) & 1)) off += align_up(kTile * m.gram[x].max_cnt * 4, 16);
+    }
+    m.lds_gram_cnt = off;
+    off += m.n_gram * kTile * 4;
+    m.lds_gram_flag = off;
+    off += m.n_gram * kTile;
+    off = align_up(off, 16);
+    m.lds_wave_base = off;
+    uint32_t w = 0;
+    m.lds_wave_peq = w;
+    if (any_ed) w += 256 * ed_words * 8;
+    for (uint32_t x = 0; x < m.n_gram; ++x) {
+        m.lds_wave_igram[x] = w;
+        w += align_up(m.gram[x].max_cnt * 4, 16);
+    }
+    w = align_up(std::max<uint32_t>(w, 16), 16);
+    m.lds_wave_stride = w;
+    off += kWaves * w;
+    m.lds_bytes = align_up(off, 16);
+    if (m.lds_bytes > c->lds_limit)
+        fail(HB_ERR_LIMIT, "the rule set's per-tile working set (" + std::to_string(m.lds_bytes) +
+                               " bytes of LDS) exceeds the device limit");
+
+    const Partition& P = rel.parts.at(key);
+    m.cols = rel.d_cols.as<ColDev>();
+    m.perm = P.perm.as<uint32_t>();
+    m.blk_start = P.blk_start.as<uint32_t>();
+    m.blk_size = P.blk_size.as<uint32_t>();
+    m.tile_prefix = P.tile_prefix.as<uint64_t>();
+    m.n_blocks = P.n_blocks;
+    m.n_tiles = P.n_tiles;
+    m.plan_len = (uint32_t)code.size();
+    if (m.n_tiles >= 0x7FFFFFFFull) fail(HB_ERR_LIMIT, "more than 2^31 tiles in one key partition");
+    kp.code = std::move(code);
+    return true;
+}
+
+static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan) {
+    std::vector<PathRule> path = plan == HB_PLAN_HEURISTIC ? epg_path(rs.sp, rs.cost, rs.rules) : given_path(rs.rules);
+    std::vector<KeyPlan> kps;
+    size_t total_code = 0;
+    for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
+        KeyPlan kp;
+        if (!build_key_plan(c, rel, rs, path, ka, kp)) continue;
+        if (kp.mp.n_tiles == 0) continue;
+        total_code += kp.code.size();
+        kps.push_back(std::move(kp));
+    }
+    DevBuf code(c, sizeof(Instr) * std::max<size_t>(total_code, 1));
+    {
+        std::vector<Instr> all;
+        for (KeyPlan& kp : kps) all.insert(all.end(), kp.code.begin(), kp.code.end());
+        if (!all.empty())
+            HB_HIP(hipMemcpyAsync(code.get(), all.data(), sizeof(Instr) * all.size(), hipMemcpyHostToDevice, c->stream));
+        size_t o = 0;
+        for (KeyPlan& kp : kps) {
+            kp.mp.plan = code.as<Instr>() + o;
+            o += kp.code.size();
+        }
+    }
+    DevBuf counter(c, 8);
+    uint64_t cap = std::max<uint64_t>(1u << 20, rel.n_rows);
+    DevBuf out(c, sizeof(uint64_t) * cap);
+    uint64_t found = 0;
+    uint64_t tiles = 0, launches = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        zero(c, counter.get(), 8);
+        tiles = launches = 0;
+        for (KeyPlan& kp : kps) {
+            kp.mp.out = out.as<uint64_t>();
+            kp.mp.cap = cap;
+            kp.mp.counter = counter.as<unsigned long long>();
+            c->timed("match", [&] { return launch_match(kp.mp, c->stream); });
+            tiles += kp.mp.n_tiles;
+            ++launches;
+        }
+        found = read1(c, counter.as<unsigned long long>());
+        if (found <= cap) break;
+        cap = found;
+        out.alloc(c, sizeof(uint64_t) * cap);
+    }
+    // sort the packed pairs: j bits, then i bits
+    const int nb = bit_width(rel.n_rows > 1 ? rel.n_rows - 1 : 1);
+    std::vector<int> sh = shifts_for_bits(nb, 0);
+    std::vector<int> shi = shifts_for_bits(nb, 32);
+    sh.insert(sh.end(), shi.begin(), shi.end());
+    rs.result.alloc(c, sizeof(uint64_t) * std::max<uint64_t>(found, 1));
+    if (found > 1) {
+        DevBuf alt(c, sizeof(uint64_t) * found);
+        DevBuf rtmp(c, radix_tmp_bytes((uint32_t)found));
+        bool in_alt = false;
+        if (found >= 0xFFFFFFFFull) fail(HB_ERR_LIMIT, "more than 2^32 matched pairs");
+        c->timed("output_sort", [&] {
+            return radix_sort_pairs(out.as<uint64_t>(), nullptr, alt.as<uint64_t>(), nullptr, (uint32_t)found, sh.data(),
+                                    (int)sh.size(), rtmp.get(), &in_alt, c->stream);
+        });
+        HB_HIP(hipMemcpyAsync(rs.result.get(), in_alt ? alt.get() : out.get(), sizeof(uint64_t) * found,
+                              hipMemcpyDeviceToDevice, c->stream));
+    } else if (found == 1) {
+        HB_HIP(hipMemcpyAsync(rs.result.get(), out.get(), 8, hipMemcpyDeviceToDevice, c->stream));
+    }
+    rs.n_result = found;
+    rs.has_result = true;
+    rs.result_plan = plan;
+    c->last.candidate_pairs = rs.candidates;
+    c->last.matched_pairs = found;
+    c->last.tiles = tiles;
+    c->last.launches = launches;
+}
+
+static void match(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, uint64_t* out, int out_on_device, uint64_t cap,
+                  uint64_t* n_pairs) {
+    Relation& rel = get_rel(c, rel_id);
+    RuleSet& rs = get_rs(c, rs_id, rel_id);
+    if (!n_pairs) fail(HB_ERR_INVALID_ARG, "NULL n_pairs");
+    if (plan != HB_PLAN_GIVEN && plan != HB_PLAN_HEURISTIC) fail(HB_ERR_INVALID_ARG, "unknown plan");
+    if (!rs.partitioned) fail(HB_ERR_STATE, "hb_partition must run before hb_match");
+    if (!(rs.has_result && rs.result_plan == plan)) run_match(c, rel, rs, plan);
+    *n_pairs = rs.n_result;
+    if (cap < rs.n_result) fail(HB_ERR_CAPACITY, "output capacity " + std::to_string(cap) + " < " + std::to_string(rs.n_result));
+    if (rs.n_result) {
+        if (!out) fail(HB_ERR_INVALID_ARG, "NULL output buffer");
+        HB_HIP(hipMemcpyAsync(out, rs.result.get(), sizeof(uint64_t) * rs.n_result,
+                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    }
+    c->sync();
+}
+
+}  // namespace hb
+
+// ============================================================ C ABI
+
+using hb::Ctx;
+using hb::Failure;
+
+struct hb_ctx {
+    Ctx c;
+};
+
+template <typename F>
+static hb_status guard(hb_ctx* ctx, F&& f) {
+    if (!ctx) return HB_ERR_INVALID_ARG;
+    try {
+        if (hipSetDevice(ctx->c.device) != hipSuccess) {
+            ctx->c.err = "hipSetDevice failed";
+            return HB_ERR_HIP;
+        }
+        f(&ctx->c);
+        ctx->c.err.clear();
+        return HB_OK;
+    } catch (const Failure& e) {
+        ctx->c.err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        ctx->c.err = "host allocation failed";
+        return HB_ERR_OOM;
+    } catch (const std::exception& e) {
+        ctx->c.err = e.what();
+        return HB_ERR_INVALID_ARG;
+    }
+}
+
+extern "C" {
+
+const char* hb_version(void) { return "hb 0.1 (gfx950)"; }
+
+hb_status hb_create(hb_ctx** out, int device, hb_alloc_fn alloc, hb_free_fn free_fn, void* user, void* stream) {
+    if (!out) return HB_ERR_INVALID_ARG;
+    *out = nullptr;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return HB_ERR_INVALID_ARG;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return HB_ERR_HIP;
+    if (hipSetDevice(device) != hipSuccess) return HB_ERR_HIP;
+    hb_ctx* h = new (std::nothrow) hb_ctx();
+    if (!h) return HB_ERR_OOM;
+    h->c.device = device;
+    h->c.alloc_fn = alloc;
+    h->c.free_fn = free_fn;
+    h->c.user = user;
+    if (stream) {
+        h->c.stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&h->c.stream, hipStreamNonBlocking) != hipSuccess) {
+            delete h;
+            return HB_ERR_HIP;
+        }
+        h->c.own_stream = true;
+    }
+    int lds = 65536;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
+    h->c.lds_limit = (uint32_t)lds;
+    *out = h;
+    return HB_OK;
+}
+
+void hb_destroy(hb_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipStreamSynchronize(ctx->c.stream);
+    ctx->c.drain_profile();
+    ctx->c.rulesets.clear();
+    ctx->c.rels.clear();
+    (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
+    delete ctx;
+}
+
+const char* hb_last_error(const hb_ctx* ctx) { return ctx ? ctx->c.err.c_str() : "NULL context"; }
+
+hb_status hb_load_relation(hb_ctx* ctx, uint32_t n_rows, uint32_t n_cols, const hb_column* cols, int on_device,
+                           uint32_t* rel_id) {
+    return guard(ctx, [&](Ctx* c) { hb::load_relation(c, n_rows, n_cols, cols, on_device, rel_id); });
+}
+
+hb_status hb_release_relation(hb_ctx* ctx, uint32_t rel_id) {
+    return guard(ctx, [&](Ctx* c) {
+        hb::get_rel(c, rel_id);
+        for (auto it = c->rulesets.begin(); it != c->rulesets.end();) {
+            if (it->second->rel_id == rel_id) it = c->rulesets.erase(it); else ++it;
+        }
+        c->rels.erase(rel_id);
+    });
+}
+
+hb_status hb_compile_rules(hb_ctx* ctx, uint32_t rel_id, uint32_t n_rules, const hb_rule* rules, uint32_t* ruleset_id) {
+    return guard(ctx, [&](Ctx* c) { hb::compile_rules(c, rel_id, n_rules, rules, ruleset_id); });
+}
+
+hb_status hb_partition(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, uint64_t* n_candidate_pairs) {
+    return guard(ctx, [&](Ctx* c) { hb::partition(c, rel_id, ruleset_id, n_candidate_pairs); });
+}
+
+hb_status hb_match(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, uint64_t* out_pairs,
+                   int out_on_device, uint64_t capacity, uint64_t* n_pairs) {
+    return guard(ctx, [&](Ctx* c) { hb::match(c, rel_id, ruleset_id, plan, out_pairs, out_on_device, capacity, n_pairs); });
+}
+
+hb_status hb_ruleset_estimates(hb_ctx* ctx, uint32_t ruleset_id, double* sp, double* cost, uint32_t cap, uint32_t* n) {
+    return guard(ctx, [&](Ctx* c) {
+        auto it = c->rulesets.find(ruleset_id);
+        if (it == c->rulesets.end()) hb::fail(HB_ERR_STALE_ID, "unknown rule set id");
+        const auto& rs = *it->second;
+        if (!n) hb::fail(HB_ERR_INVALID_ARG, "NULL n");
+        *n = (uint32_t)rs.distinct.size();
+        for (uint32_t p = 0; p < rs.distinct.size() && p < cap; ++p) {
+            if (sp) sp[p] = rs.sp[p];
+            if (cost) cost[p] = rs.cost[p];
+        }
+    });
+}
+
+hb_status hb_ruleset_buckets(hb_ctx* ctx, uint32_t ruleset_id, uint32_t pred, uint64_t* counts, uint64_t* n_valid) {
+    return guard(ctx, [&](Ctx* c) {
+        auto it = c->rulesets.find(ruleset_id);
+        if (it == c->rulesets.end()) hb::fail(HB_ERR_STALE_ID, "unknown rule set id");
+        const auto& rs = *it->second;
+        if (pred >= rs.distinct.size()) hb::fail(HB_ERR_INVALID_ARG, "predicate index out of range");
+        if (counts) std::memcpy(counts, rs.buckets[pred].data(), sizeof(uint64_t) * hb::kLshK);
+        if (n_valid) *n_valid = rs.bucket_n[pred];
+    });
+}
+
+hb_status hb_epg_path(uint32_t n_preds, const double* sp, const double* cost, uint32_t n_rules,
+                      const uint32_t* rule_len, const uint32_t* rule_preds, uint32_t* out_rules, uint32_t* out_preds,
+                      uint32_t* out_len) {
+    if (!sp || !cost || !rule_len || !rule_preds || !out_rules || !out_preds || !out_len) return HB_ERR_INVALID_ARG;
+    for (uint32_t p = 0; p < n_preds; ++p)
+        if (!(cost[p] > 0.0) || !(sp[p] >= 0.0 && sp[p] <= 1.0)) return HB_ERR_INVALID_ARG;
+    try {
+        std::vector<std::vector<uint32_t>> rules(n_rules);
+        size_t o = 0;
+        for (uint32_t r = 0; r < n_rules; ++r) {
+            for (uint32_t x = 0; x < rule_len[r]; ++x) {
+                uint32_t p = rule_preds[o++];
+                if (p >= n_preds) return HB_ERR_INVALID_ARG;
+                rules[r].push_back(p);
+            }
+        }
+        std::vector<double> vsp(sp, sp + n_preds), vc(cost, cost + n_preds);
+        auto path = hb::epg_path(vsp, vc, rules);
+        uint32_t w = 0;
+        for (uint32_t r = 0; r < path.size(); ++r) {
+            out_rules[r] = path[r].rule;
+            for (uint32_t p : path[r].preds) out_preds[w++] = p;
+        }
+        *out_len = w;
+        return HB_OK;
+    } catch (...) {
+        return HB_ERR_OOM;
+    }
+}
+
+hb_status hb_profile_enable(hb_ctx* ctx, int on) {
+    return guard(ctx, [&](Ctx* c) { c->profiling = on != 0; });
+}
+
+hb_status hb_profile_query(hb_ctx* ctx, const char* name, double* total_ms, uint64_t* launches) {
+    return guard(ctx, [&](Ctx* c) {
+        if (!name) hb::fail(HB_ERR_INVALID_ARG, "NULL name");
+        c->drain_profile();
+        auto it = c->prof.find(name);
+        if (total_ms) *total_ms = it == c->prof.end() ? 0.0 : it->second.ms;
+        if (launches) *launches = it == c->prof.end() ? 0 : it->second.launches;
+    });
+}
+
+hb_status hb_profile_reset(hb_ctx* ctx) {
+    return guard(ctx, [&](Ctx* c) {
+        c->drain_profile();
+        c->prof.clear();
+    });
+}
+
+hb_status hb_last_match_stats(hb_ctx* ctx, hb_match_stats* out) {
+    return guard(ctx, [&](Ctx* c) {
+        if (!out) hb::fail(HB_ERR_INVALID_ARG, "NULL out");
+        *out = c->last;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+// Internal declarations of libhb: device descriptors, plan bytecode, launch
+// wrappers.  Shared by the host code and the HIP kernels of this library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace hb {
+
+constexpr int kTile = 64;        // tuples per tile side (one wave of j's)
+constexpr int kWaves = 4;        // waves per workgroup of the match kernel
+constexpr int kThreads = kWaves * 64;
+constexpr int kLshK = 1024;      // LSH buckets of the selectivity estimate
+constexpr int kMaxIntRes = 16;   // int attributes staged per tile
+constexpr int kMaxStrRes = 8;    // string attributes staged per tile
+constexpr int kMaxGramRes = 8;   // (attribute, q) gram lists staged per tile
+constexpr int kMaxPrevKeys = 3;
+constexpr int kMaxEdWords = 8;   // 512-byte edit-distance patterns
+
+enum ColType : int32_t { COL_STRING = 0, COL_CATEGORICAL = 1, COL_INT64 = 2 };
+
+// One column in device memory.
+struct ColDev {
+    int32_t type;
+    uint32_t max_len;        // STRING: longest value in bytes
+    const uint64_t* off;     // STRING: n+1 offsets
+    const uint8_t* bytes;    // STRING
+    const int64_t* values;   // CATEGORICAL / INT64
+    const uint8_t* valid;    // LSB-first bitmap or nullptr
+};
+
+// Sorted distinct q-gram codes of one (string attribute, q).
+// Row r's list starts at off[r] and holds cnt[r] codes, ascending.  A
+// non-empty string shorter than q has cnt = 1, flag bit 0 set, and the code
+// (len << 24) | big-endian bytes; the empty string has cnt = 0.
+struct GramDev {
+    const uint64_t* off;
+    const uint32_t* cnt;
+    const uint32_t* codes;
+    const uint8_t* flags;
+    uint32_t q;
+    uint32_t max_cnt;
+    uint32_t attr;
+    uint32_t pad;
+};
+
+enum Op : uint8_t { OP_EQ_INT = 0, OP_EQ_STR = 1, OP_ABSDIFF = 2, OP_ED = 3, OP_JAC = 4, OP_CP = 5 };
+
+// One step of the sequential execution path.  `slot` is the distinct
+// predicate's bit in the per-pair reuse masks; `res` indexes the staged
+// resource (int / string / gram list) it reads; `cp` is the index of the
+// rule-end checkpoint that closes this instruction's rule.
+struct Instr {
+    uint8_t op;
+    uint8_t slot;
+    uint8_t res;
+    uint8_t pad0;
+    uint16_t cp;
+    uint16_t pad1;
+    int64_t k_or_d;
+    uint32_t num;
+    uint32_t den;
+};
+static_assert(sizeof(Instr) == 24, "Instr layout");
+
+// Everything the match kernel needs for one (relation, key partition, plan).
+struct MatchParams {
+    const ColDev* cols;
+    // partition of the key: rows sorted by key value; blocks of >= 2 rows
+    const uint32_t* perm;
+    const uint32_t* blk_start;
+    const uint32_t* blk_size;
+    const uint64_t* tile_prefix;   // n_blocks + 1 entries
+    uint32_t n_blocks;
+    uint32_t pad0;
+    uint64_t n_tiles;
+    // plan
+    const Instr* plan;
+    uint32_t plan_len;
+    // staged resources
+    uint32_t n_int, n_str, n_gram, n_prev;
+    uint32_t int_attr[kMaxIntRes];
+    uint32_t str_attr[kMaxStrRes];
+    uint32_t str_stride[kMaxStrRes];
+    GramDev gram[kMaxGramRes];
+    uint32_t prev_res[kMaxPrevKeys];   // int resources of earlier keys (canonical owner)
+    uint32_t ed_words;                 // words of the per-wave pattern-match table
+    uint32_t str_global;               // bit r: string resource r read from HBM, not staged
+    uint32_t gram_global;              // bit r: gram resource r read from HBM, not staged
+    // LDS layout (byte offsets into dynamic shared memory)
+    uint32_t lds_int, lds_int_valid;
+    uint32_t lds_str[kMaxStrRes], lds_str_len, lds_str_valid;
+    uint32_t lds_gram[kMaxGramRes], lds_gram_cnt, lds_gram_flag;
+    uint32_t lds_wave_base, lds_wave_stride;   // per-wave region
+    uint32_t lds_wave_peq, lds_wave_igram[kMaxGramRes];
+    uint32_t lds_bytes;
+    // output
+    uint64_t* out;
+    uint64_t cap;
+    unsigned long long* counter;
+};
+
+// ---------------------------------------------------------------- launches
+// Each returns hipSuccess or the launch error.  All run on `s`.
+
+// max length / total bytes / monotonic check of string offsets
+hipError_t launch_string_stats(const uint64_t* off, uint32_t n, uint32_t* d_max_len,
+                               unsigned long long* d_total, uint32_t* d_bad, hipStream_t s);
+// min / max of int64 values over valid rows (as order-preserving u64)
+hipError_t launch_minmax_u64(const int64_t* vals, const uint8_t* valid, uint32_t n,
+                             unsigned long long* d_min, unsigned long long* d_max,
+                             unsigned int* d_nvalid, hipStream_t s);
+
+// exclusive scan of n values; tmp must hold scan_tmp_elems(n) elements
+size_t scan_tmp_elems(size_t n);
+hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp,
+                                     hipStream_t s);
+hipError_t launch_exclusive_scan_u64(const uint64_t* in, uint64_t* out, size_t n, uint64_t* tmp,
+                                     hipStream_t s);
+
+// LSD radix sort of (u64 key, u32 value) by 8-bit digits at the given shifts.
+// Sorts keys/vals in place using the alternate buffers; returns in
+// *result_in_alt whether the result ended in the alternate buffers.
+size_t radix_tmp_bytes(uint32_t n);
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                            uint32_t n, const int* shifts, int n_shifts, void* tmp,
+                            bool* result_in_alt, hipStream_t s);
+
+// partition helpers
+hipError_t launch_key_extract(const int64_t* vals, const uint8_t* valid, uint32_t n,
+                              unsigned long long key_min, uint64_t* keys, uint32_t* rows,
+                              const uint32_t* dest, hipStream_t s);
+hipError_t launch_valid_flags(const uint8_t* valid, uint32_t n, uint32_t* flags, hipStream_t s);
+hipError_t launch_multi_valid_flags(const ColDev* cols, const uint32_t* attrs, uint32_t n_attrs,
+                                    uint32_t n, uint32_t* flags, hipStream_t s);
+hipError_t launch_gather_key(const ColDev* cols, uint32_t attr, unsigned long long key_min,
+                             const uint32_t* rows, uint32_t n, uint64_t* keys, hipStream_t s);
+hipError_t launch_compact_rows(const uint32_t* flags, const uint32_t* dest, uint32_t n,
+                               uint32_t* rows, hipStream_t s);
+hipError_t launch_group_heads(const ColDev* cols, const uint32_t* attrs, uint32_t n_attrs,
+                              const uint32_t* rows, uint32_t n, uint32_t* head, hipStream_t s);
+hipError_t launch_group_sizes(const uint32_t* head, const uint32_t* gid, uint32_t n,
+                              uint32_t n_groups, uint32_t* start, hipStream_t s);
+hipError_t launch_block_table(const uint32_t* gstart, uint32_t n_groups, uint32_t n_rows,
+                              const uint32_t* dest, uint32_t* blk_start, uint32_t* blk_size,
+                              uint64_t* tiles, unsigned long long* pairs, hipStream_t s);
+hipError_t launch_group_pairs(const uint32_t* gstart, uint32_t n_groups, uint32_t n_rows,
+                              unsigned long long* pairs, hipStream_t s);
+hipError_t launch_ge2_flags(const uint32_t* gstart, uint32_t n_groups, uint32_t n_rows,
+                            uint32_t* flags, hipStream_t s);
+
+// q-gram index
+hipError_t launch_gram_slots(const ColDev* col, uint32_t n, uint32_t q, uint64_t* slots,
+                             hipStream_t s);
+hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const uint64_t* off,
+                             uint32_t* codes, uint32_t* cnt, uint8_t* flags,
+                             unsigned int* d_max_cnt, hipStream_t s);
+
+// LSH bucket histogram of one predicate (op, q, d) over column `col`
+hipError_t launch_lsh_hist(const ColDev* col, uint32_t n, int op, uint32_t q, int64_t d,
+                           unsigned long long* hist, hipStream_t s);
+
+// the match kernel
+hipError_t launch_match(const MatchParams& p, hipStream_t s);
+
+// write pairs in order: out[x] = in[x] (device copy helper for the result)
+hipError_t launch_copy_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s);
+
+}  // namespace hb

@@ -1,0 +1,628 @@
+// Streaming primitives of libhb for gfx950: column statistics, scans, a
+// stable LSD radix sort, partition (grouping by exact key value) helpers,
+// the q-gram index build and the LSH histograms behind the selectivity
+// estimate of Section 4.2.  All are HBM-bound streaming kernels.
+#include "hb_internal.h"
+
+namespace hb {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline bool bit_valid(const uint8_t* valid, uint32_t r) {
+    return valid == nullptr || ((valid[r >> 3] >> (r & 7)) & 1);
+}
+
+__device__ inline uint64_t order_key(int64_t v) { return (uint64_t)v ^ 0x8000000000000000ull; }
+
+// splitmix64 output function (Steele, Lea and Flood, OOPSLA 2014)
+__device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ------------------------------------------------------------ column stats
+
+__global__ void k_string_stats(const uint64_t* __restrict__ off, uint32_t n, uint32_t* max_len,
+                               unsigned long long* total, uint32_t* bad) {
+    uint32_t local_max = 0;
+    unsigned long long local_sum = 0;
+    uint32_t local_bad = 0;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        uint64_t a = off[r], b = off[r + 1];
+        if (b < a) { local_bad = 1; continue; }
+        uint64_t L = b - a;
+        if (L > 0xFFFFFFFFull) { local_bad = 1; continue; }
+        local_max = max(local_max, (uint32_t)L);
+        local_sum += L;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && off[0] != 0) local_bad = 1;
+    // wave reduce then one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) {
+        local_max = max(local_max, (uint32_t)__shfl_xor((int)local_max, o));
+        local_sum += __shfl_xor(local_sum, o);
+        local_bad |= (uint32_t)__shfl_xor((int)local_bad, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(max_len, local_max);
+        atomicAdd(total, local_sum);
+        if (local_bad) atomicOr(bad, 1u);
+    }
+}
+
+__global__ void k_minmax(const int64_t* __restrict__ vals, const uint8_t* __restrict__ valid, uint32_t n,
+                         unsigned long long* mn, unsigned long long* mx, unsigned int* nvalid) {
+    unsigned long long lmin = ~0ull, lmax = 0;
+    unsigned int cnt = 0;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        if (!bit_valid(valid, r)) continue;
+        unsigned long long k = order_key(vals[r]);
+        lmin = min(lmin, k);
+        lmax = max(lmax, k);
+        ++cnt;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lmin = min(lmin, (unsigned long long)__shfl_xor(lmin, o));
+        lmax = max(lmax, (unsigned long long)__shfl_xor(lmax, o));
+        cnt += (unsigned int)__shfl_xor((int)cnt, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(mn, lmin);
+        atomicMax(mx, lmax);
+        atomicAdd(nvalid, cnt);
+    }
+}
+
+// ------------------------------------------------------------ scan
+// Exclusive scan in three phases: per-chunk totals, scan of the totals
+// (recursively), per-chunk scan with the chunk's prefix.
+
+constexpr int kScanItems = 8;
+constexpr size_t kScanChunk = (size_t)kBlock * kScanItems;
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* smem, T* total) {
+    // smem: kBlock / 64 entries
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) smem[wave] = x;
+    __syncthreads();
+    T wprefix = 0, all = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        T t = smem[w];
+        if (w < wave) wprefix += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return wprefix + x - v;
+}
+
+template <typename T>
+__global__ void k_scan_reduce(const T* __restrict__ in, size_t n, T* __restrict__ partial) {
+    __shared__ T smem[kBlock / 64];
+    size_t base = (size_t)blockIdx.x * kScanChunk;
+    T s = 0;
+    for (int it = 0; it < kScanItems; ++it) {
+        size_t idx = base + (size_t)threadIdx.x * kScanItems + it;
+        if (idx < n) s += in[idx];
+    }
+    T total;
+    block_exclusive_scan<T>(s, smem, &total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ void k_scan_final(const T* __restrict__ in, size_t n, const T* __restrict__ prefix,
+                             T* __restrict__ out) {
+    __shared__ T smem[kBlock / 64];
+    size_t base = (size_t)blockIdx.x * kScanChunk;
+    T vals[kScanItems];
+    T s = 0;
+    for (int it = 0; it < kScanItems; ++it) {
+        size_t idx = base + (size_t)threadIdx.x * kScanItems + it;
+        vals[it] = idx < n ? in[idx] : (T)0;
+        s += vals[it];
+    }
+    T total;
+    T ex = block_exclusive_scan<T>(s, smem, &total);
+    T run = ex + (prefix ? prefix[blockIdx.x] : (T)0);
+    for (int it = 0; it < kScanItems; ++it) {
+        size_t idx = base + (size_t)threadIdx.x * kScanItems + it;
+        if (idx < n) out[idx] = run;
+        run += vals[it];
+    }
+}
+
+template <typename T>
+hipError_t scan_impl(const T* in, T* out, size_t n, T* tmp, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + kScanChunk - 1) / kScanChunk;
+    if (blocks == 1) {
+        k_scan_final<T><<<1, kBlock, 0, s>>>(in, n, nullptr, out);
+        return hipGetLastError();
+    }
+    T* partial = tmp;
+    T* rest = tmp + blocks;
+    k_scan_reduce<T><<<(unsigned)blocks, kBlock, 0, s>>>(in, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_impl<T>(partial, partial, blocks, rest, s);
+    if (e != hipSuccess) return e;
+    k_scan_final<T><<<(unsigned)blocks, kBlock, 0, s>>>(in, n, partial, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ radix sort
+
+constexpr int kRsItems = 16;
+constexpr uint32_t kRsChunk = kBlock * kRsItems;
+
+__global__ void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t n, int shift,
+                          uint32_t* __restrict__ hist, uint32_t G) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t base = blockIdx.x * kRsChunk;
+    for (int it = 0; it < kRsItems; ++it) {
+        uint32_t idx = base + it * kBlock + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: elements of a chunk are ranked in (round, wave, lane)
+// order, which is their order in memory.
+__global__ void k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                             uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
+                             int shift, const uint32_t* __restrict__ offs, uint32_t G) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[kBlock / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    base[tid] = offs[(size_t)tid * G + blockIdx.x];
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int it = 0; it < kRsItems; ++it) {
+        for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        uint32_t idx = blockIdx.x * kRsChunk + it * kBlock + tid;
+        bool act = idx < n;
+        uint64_t key = act ? kin[idx] : 0;
+        uint32_t val = (act && vin) ? vin[idx] : 0;
+        uint32_t d = (uint32_t)((key >> shift) & 255);
+        uint64_t peers = __ballot(act);
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bb = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? bb : ~bb;
+        }
+        uint32_t rank = __popcll(peers & lt_mask);
+        if (act && rank == 0) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (act) {
+            uint32_t o = base[d] + rank;
+            for (int w = 0; w < wave; ++w) o += wcnt[w][d];
+            kout[o] = key;
+            if (vout) vout[o] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < kBlock / 64; ++w) add += wcnt[w][tid];
+        base[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ partition
+
+__global__ void k_valid_flags(const uint8_t* __restrict__ valid, uint32_t n, uint32_t* __restrict__ flags) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) flags[r] = bit_valid(valid, r) ? 1u : 0u;
+}
+
+__global__ void k_multi_valid_flags(const ColDev* __restrict__ cols, const uint32_t* __restrict__ attrs,
+                                    uint32_t n_attrs, uint32_t n, uint32_t* __restrict__ flags) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    uint32_t f = 1;
+    for (uint32_t a = 0; a < n_attrs; ++a) f &= bit_valid(cols[attrs[a]].valid, r) ? 1u : 0u;
+    flags[r] = f;
+}
+
+__global__ void k_compact_rows(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ dest,
+                               uint32_t n, uint32_t* __restrict__ rows) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n && flags[r]) rows[dest[r]] = r;
+}
+
+__global__ void k_key_extract(const int64_t* __restrict__ vals, const uint8_t* __restrict__ valid, uint32_t n,
+                              unsigned long long key_min, uint64_t* __restrict__ keys,
+                              uint32_t* __restrict__ rows, const uint32_t* __restrict__ dest) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n || !bit_valid(valid, r)) return;
+    uint32_t o = dest[r];
+    keys[o] = order_key(vals[r]) - key_min;
+    rows[o] = r;
+}
+
+__global__ void k_gather_key(const ColDev* __restrict__ cols, uint32_t attr, unsigned long long key_min,
+                             const uint32_t* __restrict__ rows, uint32_t n, uint64_t* __restrict__ keys) {
+    uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) keys[x] = order_key(cols[attr].values[rows[x]]) - key_min;
+}
+
+__global__ void k_group_heads(const ColDev* __restrict__ cols, const uint32_t* __restrict__ attrs,
+                              uint32_t n_attrs, const uint32_t* __restrict__ rows, uint32_t n,
+                              uint32_t* __restrict__ head) {
+    uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    uint32_t h = 1;
+    if (x > 0) {
+        uint32_t a = rows[x], b = rows[x - 1];
+        h = 0;
+        for (uint32_t k = 0; k < n_attrs; ++k) {
+            const int64_t* v = cols[attrs[k]].values;
+            if (v[a] != v[b]) h = 1;
+        }
+    }
+    head[x] = h;
+}
+
+__global__ void k_group_start(const uint32_t* __restrict__ head, const uint32_t* __restrict__ gid,
+                              uint32_t n, uint32_t* __restrict__ start) {
+    uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n && head[x]) start[gid[x]] = x;
+}
+
+__device__ inline uint32_t group_size(const uint32_t* gstart, uint32_t g, uint32_t n_groups, uint32_t n_rows) {
+    uint32_t e = (g + 1 < n_groups) ? gstart[g + 1] : n_rows;
+    return e - gstart[g];
+}
+
+__global__ void k_ge2_flags(const uint32_t* __restrict__ gstart, uint32_t n_groups, uint32_t n_rows,
+                            uint32_t* __restrict__ flags) {
+    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n_groups) flags[g] = group_size(gstart, g, n_groups, n_rows) >= 2 ? 1u : 0u;
+}
+
+__global__ void k_block_table(const uint32_t* __restrict__ gstart, uint32_t n_groups, uint32_t n_rows,
+                              const uint32_t* __restrict__ dest, uint32_t* __restrict__ blk_start,
+                              uint32_t* __restrict__ blk_size, uint64_t* __restrict__ tiles,
+                              unsigned long long* __restrict__ pairs) {
+    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long p = 0;
+    if (g < n_groups) {
+        uint32_t sz = group_size(gstart, g, n_groups, n_rows);
+        if (sz >= 2) {
+            uint32_t b = dest[g];
+            blk_start[b] = gstart[g];
+            blk_size[b] = sz;
+            uint64_t T = (sz + kTile - 1) / kTile;
+            tiles[b] = T * (T + 1) / 2;
+            p = (unsigned long long)sz * (sz - 1) / 2;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o);
+    if ((threadIdx.x & 63) == 0 && p) atomicAdd(pairs, p);
+}
+
+__global__ void k_group_pairs(const uint32_t* __restrict__ gstart, uint32_t n_groups, uint32_t n_rows,
+                              unsigned long long* __restrict__ pairs) {
+    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long p = 0;
+    if (g < n_groups) {
+        unsigned long long sz = group_size(gstart, g, n_groups, n_rows);
+        p = sz * (sz - 1) / 2;
+    }
+    for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o);
+    if ((threadIdx.x & 63) == 0 && p) atomicAdd(pairs, p);
+}
+
+// ------------------------------------------------------------ q-gram index
+
+__device__ inline uint32_t str_len(const ColDev& c, uint32_t r) { return (uint32_t)(c.off[r + 1] - c.off[r]); }
+
+// slots[r]: room reserved for row r's list (windows, or 1 for a short string)
+__global__ void k_gram_slots(const ColDev* __restrict__ colp, uint32_t n, uint32_t q, uint64_t* __restrict__ slots) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const ColDev c = *colp;
+    uint64_t s = 0;
+    if (bit_valid(c.valid, r)) {
+        uint32_t L = str_len(c, r);
+        s = (L == 0) ? 0 : (L < q ? 1 : L - q + 1);
+    }
+    slots[r] = s;
+}
+
+// One thread per row: write the window codes, insertion-sort them in place,
+// drop repeats.
+__global__ void k_gram_build(const ColDev* __restrict__ colp, uint32_t n, uint32_t q,
+                             const uint64_t* __restrict__ off, uint32_t* __restrict__ codes,
+                             uint32_t* __restrict__ cnt, uint8_t* __restrict__ flags,
+                             unsigned int* __restrict__ max_cnt) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t out_cnt = 0;
+    if (r < n) {
+        const ColDev c = *colp;
+        uint8_t f = 0;
+        if (bit_valid(c.valid, r)) {
+            const uint8_t* s = c.bytes + c.off[r];
+            uint32_t L = str_len(c, r);
+            uint32_t* dst = codes + off[r];
+            if (L > 0 && L < q) {
+                uint32_t v = 0;
+                for (uint32_t x = 0; x < L; ++x) v = (v << 8) | s[x];
+                dst[0] = (L << 24) | v;
+                out_cnt = 1;
+                f = 1;
+            } else if (L >= q) {
+                uint32_t nw = L - q + 1;
+                uint32_t v = 0;
+                for (uint32_t x = 0; x + 1 < q; ++x) v = (v << 8) | s[x];
+                const uint32_t mask = (q == 4) ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
+                for (uint32_t w = 0; w < nw; ++w) {
+                    v = ((v << 8) | s[w + q - 1]) & mask;
+                    // insertion into the sorted prefix dst[0..w)
+                    uint32_t p = w;
+                    while (p > 0 && dst[p - 1] > v) { dst[p] = dst[p - 1]; --p; }
+                    dst[p] = v;
+                }
+                uint32_t u = 0;
+                for (uint32_t w = 0; w < nw; ++w)
+                    if (u == 0 || dst[u - 1] != dst[w]) dst[u++] = dst[w];
+                out_cnt = u;
+            }
+        }
+        cnt[r] = out_cnt;
+        flags[r] = f;
+    }
+    for (int o = 32; o > 0; o >>= 1) out_cnt = max(out_cnt, (uint32_t)__shfl_xor((int)out_cnt, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(max_cnt, out_cnt);
+}
+
+// ------------------------------------------------------------ LSH histogram
+
+__device__ inline uint64_t fnv1a64(const uint8_t* s, uint32_t L) {
+    uint64_t h = 0xCBF29CE484222325ull;
+    for (uint32_t x = 0; x < L; ++x) { h ^= s[x]; h *= 0x100000001B3ull; }
+    return h;
+}
+
+// minimum over the q-gram set of mix64((len << 32) | big-endian bytes)
+__device__ inline uint64_t minhash(const uint8_t* s, uint32_t L, uint32_t q) {
+    if (L == 0) return 0;
+    if (L < q) {
+        uint64_t v = 0;
+        for (uint32_t x = 0; x < L; ++x) v = (v << 8) | s[x];
+        return mix64(((uint64_t)L << 32) | v);
+    }
+    uint64_t best = ~0ull;
+    const uint64_t mask = (1ull << (8 * q)) - 1ull;
+    uint64_t v = 0;
+    for (uint32_t x = 0; x + 1 < q; ++x) v = (v << 8) | s[x];
+    for (uint32_t w = 0; w + q <= L; ++w) {
+        v = ((v << 8) | s[w + q - 1]) & mask;
+        uint64_t h = mix64(((uint64_t)q << 32) | v);
+        best = h < best ? h : best;
+    }
+    return best;
+}
+
+__device__ inline int64_t floor_div(int64_t v, int64_t d) {
+    // floor(v / (d + 1)) for d >= 0
+    if (d == INT64_MAX) return v < 0 ? -1 : 0;
+    int64_t w = d + 1;
+    int64_t qq = v / w, rr = v % w;
+    if (rr != 0 && v < 0) qq -= 1;
+    return qq;
+}
+
+// op: 0 EQ, 1 ED (2-gram MinHash), 2 JACCARD (q-gram MinHash), 3 ABSDIFF
+__global__ void k_lsh_hist(const ColDev* __restrict__ colp, uint32_t n, int op, uint32_t q, int64_t d,
+                           unsigned long long* __restrict__ hist) {
+    __shared__ unsigned int h[kLshK];
+    for (int x = threadIdx.x; x < kLshK; x += blockDim.x) h[x] = 0;
+    __syncthreads();
+    const ColDev c = *colp;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        if (!bit_valid(c.valid, r)) continue;
+        uint64_t hv;
+        if (c.type == COL_STRING) {
+            const uint8_t* s = c.bytes + c.off[r];
+            uint32_t L = str_len(c, r);
+            if (op == 0) hv = mix64(fnv1a64(s, L));
+            else if (op == 1) hv = minhash(s, L, 2);
+            else hv = minhash(s, L, q);
+        } else {
+            int64_t v = c.values[r];
+            if (op == 3) v = floor_div(v, d);
+            hv = mix64((uint64_t)v);
+        }
+        atomicAdd(&h[hv % kLshK], 1u);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < kLshK; x += blockDim.x)
+        if (h[x]) atomicAdd(&hist[x], (unsigned long long)h[x]);
+}
+
+__global__ void k_copy_u64(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t n) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x)
+        out[x] = in[x];
+}
+
+inline unsigned grid_for(uint64_t n, unsigned cap = 65535u * 4) {
+    uint64_t g = (n + kBlock - 1) / kBlock;
+    if (g == 0) g = 1;
+    return (unsigned)(g < cap ? g : cap);
+}
+
+}  // namespace
+
+hipError_t launch_string_stats(const uint64_t* off, uint32_t n, uint32_t* d_max_len,
+                               unsigned long long* d_total, uint32_t* d_bad, hipStream_t s) {
+    k_string_stats<<<grid_for(n, 2048), kBlock, 0, s>>>(off, n, d_max_len, d_total, d_bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax_u64(const int64_t* vals, const uint8_t* valid, uint32_t n,
+                             unsigned long long* d_min, unsigned long long* d_max,
+                             unsigned int* d_nvalid, hipStream_t s) {
+    k_minmax<<<grid_for(n, 2048), kBlock, 0, s>>>(vals, valid, n, d_min, d_max, d_nvalid);
+    return hipGetLastError();
+}
+
+size_t scan_tmp_elems(size_t n) {
+    size_t total = 0;
+    size_t m = n;
+    while (m > kScanChunk) {
+        m = (m + kScanChunk - 1) / kScanChunk;
+        total += m;
+    }
+    return total + 1;
+}
+
+hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp,
+                                     hipStream_t s) {
+    return scan_impl<uint32_t>(in, out, n, tmp, s);
+}
+
+hipError_t launch_exclusive_scan_u64(const uint64_t* in, uint64_t* out, size_t n, uint64_t* tmp,
+                                     hipStream_t s) {
+    return scan_impl<uint64_t>(in, out, n, tmp, s);
+}
+
+size_t radix_tmp_bytes(uint32_t n) {
+    size_t G = (n + kRsChunk - 1) / kRsChunk;
+    if (G == 0) G = 1;
+    size_t hist = 256 * G;
+    return (hist * 2 + scan_tmp_elems(hist)) * sizeof(uint32_t);
+}
+
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                            uint32_t n, const int* shifts, int n_shifts, void* tmp,
+                            bool* result_in_alt, hipStream_t s) {
+    *result_in_alt = false;
+    if (n <= 1) return hipSuccess;
+    uint32_t G = (n + kRsChunk - 1) / kRsChunk;
+    size_t H = (size_t)256 * G;
+    uint32_t* hist = (uint32_t*)tmp;
+    uint32_t* offs = hist + H;
+    uint32_t* stmp = offs + H;
+    uint64_t* kin = keys; uint32_t* vin = vals;
+    uint64_t* kout = keys_alt; uint32_t* vout = vals_alt;
+    for (int p = 0; p < n_shifts; ++p) {
+        k_rs_hist<<<G, kBlock, 0, s>>>(kin, n, shifts[p], hist, G);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = scan_impl<uint32_t>(hist, offs, H, stmp, s);
+        if (e != hipSuccess) return e;
+        k_rs_scatter<<<G, kBlock, 0, s>>>(kin, vin, kout, vout, n, shifts[p], offs, G);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint64_t* tk = kin; kin = kout; kout = tk;
+        uint32_t* tv = vin; vin = vout; vout = tv;
+        *result_in_alt = !*result_in_alt;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_valid_flags(const uint8_t* valid, uint32_t n, uint32_t* flags, hipStream_t s) {
+    k_valid_flags<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(valid, n, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_valid_flags(const ColDev* cols, const uint32_t* attrs, uint32_t n_attrs,
+                                    uint32_t n, uint32_t* flags, hipStream_t s) {
+    k_multi_valid_flags<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(cols, attrs, n_attrs, n, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_rows(const uint32_t* flags, const uint32_t* dest, uint32_t n,
+                               uint32_t* rows, hipStream_t s) {
+    k_compact_rows<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(flags, dest, n, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_extract(const int64_t* vals, const uint8_t* valid, uint32_t n,
+                              unsigned long long key_min, uint64_t* keys, uint32_t* rows,
+                              const uint32_t* dest, hipStream_t s) {
+    k_key_extract<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(vals, valid, n, key_min, keys, rows, dest);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_key(const ColDev* cols, uint32_t attr, unsigned long long key_min,
+                             const uint32_t* rows, uint32_t n, uint64_t* keys, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_gather_key<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(cols, attr, key_min, rows, n, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_heads(const ColDev* cols, const uint32_t* attrs, uint32_t n_attrs,
+                              const uint32_t* rows, uint32_t n, uint32_t* head, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_group_heads<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(cols, attrs, n_attrs, rows, n, head);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_sizes(const uint32_t* head, const uint32_t* gid, uint32_t n,
+                              uint32_t n_groups, uint32_t* start, hipStream_t s) {
+    (void)n_groups;
+    if (n == 0) return hipSuccess;
+    k_group_start<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(head, gid, n, start);
+    return hipGetLastError();
+}
+
+hipError_t launch_ge2_flags(const uint32_t* gstart, uint32_t n_groups, uint32_t n_rows,
+                            uint32_t* flags, hipStream_t s) {
+    if (n_groups == 0) return hipSuccess;
+    k_ge2_flags<<<grid_for(n_groups, 1u << 30), kBlock, 0, s>>>(gstart, n_groups, n_rows, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_table(const uint32_t* gstart, uint32_t n_groups, uint32_t n_rows,
+                              const uint32_t* dest, uint32_t* blk_start, uint32_t* blk_size,
+                              uint64_t* tiles, unsigned long long* pairs, hipStream_t s) {
+    if (n_groups == 0) return hipSuccess;
+    k_block_table<<<grid_for(n_groups, 1u << 30), kBlock, 0, s>>>(gstart, n_groups, n_rows, dest,
+                                                                  blk_start, blk_size, tiles, pairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_pairs(const uint32_t* gstart, uint32_t n_groups, uint32_t n_rows,
+                              unsigned long long* pairs, hipStream_t s) {
+    if (n_groups == 0) return hipSuccess;
+    k_group_pairs<<<grid_for(n_groups, 1u << 30), kBlock, 0, s>>>(gstart, n_groups, n_rows, pairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_slots(const ColDev* col, uint32_t n, uint32_t q, uint64_t* slots, hipStream_t s) {
+    k_gram_slots<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(col, n, q, slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const uint64_t* off,
+                             uint32_t* codes, uint32_t* cnt, uint8_t* flags,
+                             unsigned int* d_max_cnt, hipStream_t s) {
+    k_gram_build<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsh_hist(const ColDev* col, uint32_t n, int op, uint32_t q, int64_t d,
+                           unsigned long long* hist, hipStream_t s) {
+    k_lsh_hist<<<grid_for(n, 1024), kBlock, 0, s>>>(col, n, op, q, d, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_copy_u64<<<grid_for(n, 4096), kBlock, 0, s>>>(in, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace hb

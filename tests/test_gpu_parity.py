@@ -1,0 +1,232 @@
+"""GPU parity: libhb's matched-pair set, through the C ABI, is bit-exact
+against the CPU oracle (sorted packed (i << 32) | j), for both plans."""
+import numpy as np
+import pytest
+
+import oracle
+from gen import ABSDIFF, CATEGORICAL, ED, EQ, INT64, JACCARD, Pred, Relation, int_column, string_column
+from gen import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_04349_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(hb):
+    c = hb.hb_create(0, allocator="torch")
+    yield c
+    c.close()
+
+
+def run(hb, ctx, rel, rules, plan):
+    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+    rs = hb.hb_compile_rules(ctx, rid, rules)
+    n_cand = hb.hb_partition(ctx, rid, rs)
+    out = hb.hb_match(ctx, rid, rs, plan)
+    hb.hb_release_relation(ctx, rid)
+    return out, n_cand
+
+
+def show(case):
+    print(f"[gpu-case] {case}", flush=True)
+
+
+@pytest.mark.parametrize("plan", ["given", "heuristic"])
+def test_person_small(hb, ctx, plan):
+    show(f"person_small {plan}")
+    rel, rules = workloads.person_small()
+    want = oracle.blocking(rel, rules)
+    got, n_cand = run(hb, ctx, rel, rules, plan)
+    assert n_cand == oracle.candidate_count(rel, rules)
+    assert got.dtype == np.uint64
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_small(hb, ctx, seed):
+    kw = dict(n=400 if seed % 3 else 150, long_strings=seed % 4 != 3, n_keys=1 + seed % 3,
+              alphabet=b"ab" if seed % 2 else b"abc", n_key_values=4 if seed % 5 == 0 else 8,
+              n_rules=2 + seed % 5, null_p=0.0 if seed % 7 == 0 else 0.05)
+    show(f"random_small seed={seed} {kw}")
+    rel, rules = workloads.random_small(1000 + seed, **kw)
+    want = oracle.blocking(rel, rules, threads=8)
+    assert np.array_equal(want, oracle.blocking(rel, rules, "full", threads=8))
+    for plan in ("given", "heuristic"):
+        got, n_cand = run(hb, ctx, rel, rules, plan)
+        assert n_cand == oracle.candidate_count(rel, rules)
+        assert np.array_equal(got, want), (plan, len(got), len(want))
+
+
+def _table1(hb):
+    from tests.test_oracle_pins import _table1
+    return _table1()
+
+
+def test_table1(hb, ctx):
+    show("table1")
+    g, rel, rules, preds = _table1(hb)
+    rs_rules = [rules["phi1"], rules["phi2"]]
+    want = oracle.blocking(rel, rs_rules)
+    for plan in ("given", "heuristic"):
+        got, _ = run(hb, ctx, rel, rs_rules, plan)
+        assert np.array_equal(got, want)
+    pairs = {(int(x >> 32), int(x & 0xFFFFFFFF)) for x in want}
+    assert (0, 3) in pairs
+    # phi1 alone is a witness at (t1, t4) but not at (t2, t3) (Example 3)
+    got1, _ = run(hb, ctx, rel, [rules["phi1"]], "heuristic")
+    p1 = {(int(x >> 32), int(x & 0xFFFFFFFF)) for x in got1}
+    assert (0, 3) in p1 and (1, 2) not in p1
+    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_compile_rules(ctx, rid, [rules["phi3"]])
+    assert e.value.status == hb.HB_ERR_UNBLOCKABLE
+    hb.hb_release_relation(ctx, rid)
+
+
+def _one_block_strings(strings, key=7):
+    cols = [string_column("s", strings), int_column("k", [key] * len(strings), CATEGORICAL)]
+    return Relation(cols, len(strings))
+
+
+@pytest.mark.parametrize("k", [0, 1, 3, 8, 40])
+def test_edit_distance_word_boundaries(hb, ctx, k):
+    show(f"ed boundaries k={k}")
+    r = np.random.default_rng(k)
+    strings = []
+    for L in (0, 1, 5, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 200, 255, 256, 257, 400, 512):
+        base = bytes(r.integers(97, 100, size=L).astype(np.uint8))
+        strings.append(base)
+        for e in (1, 2, 5):
+            s = bytearray(base)
+            for _ in range(e):
+                t = int(r.integers(0, 3))
+                if t == 0 and s:
+                    s[int(r.integers(0, len(s)))] = 97 + int(r.integers(0, 3))
+                elif t == 1 and len(s) < 512:
+                    s.insert(int(r.integers(0, len(s) + 1)), 97 + int(r.integers(0, 3)))
+                elif s:
+                    del s[int(r.integers(0, len(s)))]
+            strings.append(bytes(s))
+    rel = _one_block_strings(strings)
+    rules = [[Pred(EQ, 1), Pred(ED, 0, k=k)]]
+    want = oracle.blocking(rel, rules, threads=8)
+    got, _ = run(hb, ctx, rel, rules, "given")
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+def test_jaccard_boundaries(hb, ctx, q):
+    show(f"jaccard q={q}")
+    r = np.random.default_rng(q)
+    strings = [b"", b"a", b"ab", b"abc", b"abcd", b"abcde", b"aaaa", b"abab"]
+    for L in (5, 10, 30, 64, 65, 130):
+        base = bytes(r.integers(97, 101, size=L).astype(np.uint8))
+        strings.append(base)
+        strings.append(base[: L // 2] + b"z" + base[L // 2 + 1:])
+    rel = _one_block_strings(strings)
+    for num, den in ((0, 1), (1, 2), (3, 5), (7, 10), (1, 1), (25, 31)):
+        rules = [[Pred(EQ, 1), Pred(JACCARD, 0, q=q, num=num, den=den)]]
+        want = oracle.blocking(rel, rules)
+        got, _ = run(hb, ctx, rel, rules, "given")
+        assert np.array_equal(got, want), (num, den)
+
+
+def test_plain_scaled_several_tiles(hb, ctx):
+    show("plain_1m scaled to 40k")
+    rel, rules = workloads.plain_1m(n=40_000)
+    keyv = rel.columns[3].values
+    _, cnt = np.unique(keyv, return_counts=True)
+    assert cnt.max() > 3 * 64          # blocks span several tiles with a ragged tail
+    want = oracle.blocking(rel, rules, threads=8)
+    for plan in ("given", "heuristic"):
+        got, n_cand = run(hb, ctx, rel, rules, plan)
+        assert n_cand == int((cnt * (cnt - 1) // 2).sum())
+        assert np.array_equal(got, want), plan
+
+
+def test_device_resident_input(hb, ctx):
+    show("device input")
+    import torch
+    rel, rules = workloads.person_small()
+    dev_cols = []
+    for c in rel.columns:
+        class C:
+            pass
+        d = C()
+        d.type = c.type
+        d.offsets = torch.from_numpy(c.offsets.view(np.int64)).cuda() if c.offsets is not None else None
+        d.data = torch.from_numpy(c.data).cuda() if c.data is not None else None
+        d.values = torch.from_numpy(c.values).cuda() if c.values is not None else None
+        d.valid = None
+        dev_cols.append(d)
+    torch.cuda.synchronize()
+    rid = hb.hb_load_relation(ctx, dev_cols, rel.n_rows, on_device=True)
+    rs = hb.hb_compile_rules(ctx, rid, rules)
+    hb.hb_partition(ctx, rid, rs)
+    out = torch.zeros(4096, dtype=torch.int64, device="cuda")
+    n = hb.hb_match(ctx, rid, rs, "heuristic", out=out)
+    got = out[:n].cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, oracle.blocking(rel, rules))
+    hb.hb_release_relation(ctx, rid)
+
+
+def test_capacity_protocol_and_errors(hb, ctx):
+    show("capacity / errors")
+    import ctypes
+    rel, rules = workloads.person_small()
+    want = oracle.blocking(rel, rules)
+    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+    rs = hb.hb_compile_rules(ctx, rid, rules)
+    n = ctypes.c_uint64()
+    buf = np.zeros(8, dtype=np.uint64)
+    st = hb._lib.hb_match(ctx.h, rid, rs, 1, ctypes.c_void_p(buf.ctypes.data), 0, 8, ctypes.byref(n))
+    assert st == hb.HB_ERR_STATE                      # before hb_partition
+    hb.hb_partition(ctx, rid, rs)
+    st = hb._lib.hb_match(ctx.h, rid, rs, 1, ctypes.c_void_p(buf.ctypes.data), 0, 8, ctypes.byref(n))
+    assert st == hb.HB_ERR_CAPACITY and n.value == len(want)
+    assert np.array_equal(hb.hb_match(ctx, rid, rs, "heuristic"), want)
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_compile_rules(ctx, rid, [[Pred(EQ, 2), Pred(ED, 3, k=1)]])      # ED on an int
+    assert e.value.status == hb.HB_ERR_TYPE
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_compile_rules(ctx, rid, [[Pred(EQ, 2), Pred(JACCARD, 1, q=3, num=4, den=3)]])
+    assert e.value.status == hb.HB_ERR_INVALID_ARG
+    hb.hb_release_relation(ctx, rid)
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_partition(ctx, rid, rs)
+    assert e.value.status == hb.HB_ERR_STALE_ID
+
+
+def test_lsh_buckets_match_oracle(hb, ctx):
+    show("lsh buckets")
+    rel, rules = workloads.person_small()
+    rules = rules + [[Pred(EQ, 2), Pred(ABSDIFF, 3, d=4)], [Pred(EQ, 2), Pred(EQ, 0)]]
+    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+    rs = hb.hb_compile_rules(ctx, rid, rules)
+    sp, cost = hb.hb_ruleset_estimates(ctx, rs)
+    distinct = []
+    for rule in rules:
+        for p in rule:
+            if p not in distinct:
+                distinct.append(p)
+    assert len(sp) == len(distinct)
+    for x, p in enumerate(distinct):
+        counts, n = hb.hb_ruleset_buckets(ctx, rs, x)
+        want, wn = epg.bucket_counts(rel, p)
+        assert n == wn and np.array_equal(counts.astype(np.int64), want), p
+        assert abs(sp[x] - epg.sp_from_counts(want, wn)) < 1e-12
+    assert cost.max() == 1.0 and cost.min() > 0
+    seq, _, _ = epg.sequential_path([[distinct.index(p) for p in r] for r in rules], list(sp), list(cost))
+    assert hb.hb_epg_path(sp, cost, [[distinct.index(p) for p in r] for r in rules]) == [(a, b) for a, b in seq]
+    hb.hb_release_relation(ctx, rid)
+
+
+from oracle import epg  # noqa: E402
