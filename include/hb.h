@@ -52,7 +52,7 @@ typedef enum {
 #define HB_MAX_RULE_PREDS 10     /* predicates per rule (the paper's default bound) */
 #define HB_MAX_DISTINCT_PREDS 64 /* distinct predicates per rule set */
 #define HB_MAX_KEYS 4            /* distinct blocking-key attributes per rule set */
-#define HB_MAX_ED_LEN 512        /* longest string of an attribute used by an edit-distance predicate */
+#define HB_MAX_ED_LEN 256        /* longest string of an attribute used by an edit-distance predicate */
 #define HB_MAX_GRAM_LEN 4096     /* longest string of an attribute used by a Jaccard predicate */
 #define HB_MAX_ED_K 255
 #define HB_MAX_Q 4
@@ -187,6 +187,30 @@ hb_status hb_epg_path(uint32_t n_preds, const double* sp, const double* cost, ui
 hb_status hb_profile_enable(hb_ctx* ctx, int on);
 hb_status hb_profile_query(hb_ctx* ctx, const char* name, double* total_ms, uint64_t* launches);
 hb_status hb_profile_reset(hb_ctx* ctx);
+
+/* Work counters of one instrumented evaluation pass: the same kernels with
+ * counting compiled in (output-neutral and slower; for profiling only).  Per
+ * plan operation kind (index: 0 value equality, 1 |a-b| <= d, 2 string
+ * equality filter, 3 edit-distance filter, 4 Jaccard filter, 5 string
+ * equality, 6 edit distance, 7 Jaccard): the wave-steps that executed it,
+ * the lanes that evaluated it, the lanes for which it held, and its work
+ * units (edit distance: text bytes x 32-bit pattern words run; Jaccard:
+ * merged list elements; string equality: bytes compared).  `pairs` is the
+ * number of candidate pairs evaluated, `lane_ops` the algorithmic int32
+ * lane-operations under the library's per-operation cost model.
+ * Requires hb_partition; leaves the cached hb_match result untouched. */
+#define HB_N_OPKINDS 8
+typedef struct {
+    uint64_t pairs;
+    uint64_t matched;
+    uint64_t launches;
+    uint64_t waves[HB_N_OPKINDS];
+    uint64_t lanes[HB_N_OPKINDS];
+    uint64_t passed[HB_N_OPKINDS];
+    uint64_t work[HB_N_OPKINDS];
+    double lane_ops;
+} hb_work_stats;
+hb_status hb_match_work(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, hb_work_stats* out);
 
 /* Counters of the last hb_match: candidate pairs, pairs matched, launches
  * and tiles of the match kernel. */

@@ -41,7 +41,11 @@ EXPORTED = [
     "hb_create", "hb_destroy", "hb_last_error", "hb_version", "hb_load_relation", "hb_release_relation",
     "hb_compile_rules", "hb_partition", "hb_match", "hb_ruleset_estimates", "hb_ruleset_buckets",
     "hb_epg_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
+    "hb_match_work",
 ]
+
+OP_KINDS = ["eq_value", "absdiff", "eq_string_filter", "ed_filter", "jaccard_filter", "eq_string",
+            "edit_distance", "jaccard"]
 
 
 class HbColumn(ctypes.Structure):
@@ -64,6 +68,12 @@ class HbMatchStats(ctypes.Structure):
                 ("tiles", ctypes.c_uint64), ("launches", ctypes.c_uint64)]
 
 
+class HbWorkStats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_uint64), ("matched", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("waves", ctypes.c_uint64 * 8), ("lanes", ctypes.c_uint64 * 8), ("passed", ctypes.c_uint64 * 8),
+                ("work", ctypes.c_uint64 * 8), ("lane_ops", ctypes.c_double)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -71,6 +81,13 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 def _load_lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libhb.so is not built ({LIB_PATH}); run paper_2410_04349_amd/build.py")
+    # torch bundles its own HIP runtime under the same soname as the system
+    # one libhb links against; loading torch first makes the process use a
+    # single runtime whichever module the caller imports first
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, U32, U64, I32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
     sig = {
@@ -90,6 +107,7 @@ def _load_lib():
         "hb_profile_query": (I32, [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64)]),
         "hb_profile_reset": (I32, [P]),
         "hb_last_match_stats": (I32, [P, ctypes.POINTER(HbMatchStats)]),
+        "hb_match_work": (I32, [P, U32, U32, I32, ctypes.POINTER(HbWorkStats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -320,3 +338,15 @@ def hb_last_match_stats(ctx: Context) -> dict:
     ctx.check(_lib.hb_last_match_stats(ctx.h, ctypes.byref(s)))
     return {"candidate_pairs": s.candidate_pairs, "matched_pairs": s.matched_pairs, "tiles": s.tiles,
             "launches": s.launches}
+
+
+def hb_match_work(ctx: Context, rel_id: int, ruleset_id: int, plan="heuristic") -> dict:
+    """Counters of one instrumented evaluation pass (see include/hb.h)."""
+    pl = _PLAN[plan] if isinstance(plan, str) else int(plan)
+    w = HbWorkStats()
+    ctx.check(_lib.hb_match_work(ctx.h, rel_id, ruleset_id, pl, ctypes.byref(w)))
+    per_op = {}
+    for k, name in enumerate(OP_KINDS):
+        per_op[name] = {"waves": w.waves[k], "lanes": w.lanes[k], "passed": w.passed[k], "work": w.work[k]}
+    return {"pairs": w.pairs, "matched": w.matched, "launches": w.launches, "lane_ops": w.lane_ops,
+            "per_op": per_op}

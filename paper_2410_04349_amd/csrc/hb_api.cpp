@@ -73,7 +73,7 @@ struct Column {
 
 struct GramIndex {
     uint32_t attr = 0, q = 0, max_cnt = 0;
-    DevBuf off, cnt, codes, flags;
+    DevBuf off, cnt, codes, flags, sig;
     GramDev dev() const {
         GramDev g{};
         g.off = off.as<uint64_t>();
@@ -99,6 +99,7 @@ struct Relation {
     std::vector<ColDev> h_cols;
     DevBuf d_cols;
     std::map<std::pair<uint32_t, uint32_t>, GramIndex> grams;
+    std::map<uint32_t, DevBuf> char_sig;
     std::map<uint32_t, Partition> parts;
     std::map<std::vector<uint32_t>, uint64_t> composite;
 };
@@ -353,6 +354,8 @@ static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
                                  g.flags.as<uint8_t>(), mx.as<unsigned int>(), c->stream);
     });
     g.max_cnt = read1(c, mx.as<unsigned int>());
+    g.sig.alloc(c, sizeof(uint64_t) * n);
+    HB_HIP(launch_gram_sig(g.dev(), n, g.sig.as<uint64_t>(), c->stream));
     auto res = rel.grams.emplace(key, std::move(g));
     return res.first->second;
 }
@@ -407,7 +410,7 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
                 if (t != HB_COL_STRING) fail(HB_ERR_TYPE, where + ": edit distance needs a string attribute");
                 if (p.k < 0 || p.k > HB_MAX_ED_K) fail(HB_ERR_INVALID_ARG, where + ": k must be in [0, 255]");
                 if (rel.cols[p.attr].max_len > HB_MAX_ED_LEN)
-                    fail(HB_ERR_LIMIT, where + ": strings longer than 512 bytes");
+                    fail(HB_ERR_LIMIT, where + ": strings longer than 256 bytes");
                 break;
             case HB_JACCARD_GE:
                 if (t != HB_COL_STRING) fail(HB_ERR_TYPE, where + ": Jaccard needs a string attribute");
@@ -646,18 +649,28 @@ static void partition(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint64_t* n_cand)
 struct KeyPlan {
     std::vector<Instr> code;
     MatchParams mp{};
+    DevBuf f64, f32;
 };
 
 static uint32_t align_up(uint32_t v, uint32_t a) { return (v + a - 1) / a * a; }
 
-// LDS per workgroup the match kernel aims to stay under (two workgroups per CU)
-constexpr uint32_t kLdsBudget = 80 * 1024;
+static const uint64_t* char_signature(Ctx* c, Relation& rel, uint32_t attr) {
+    auto it = rel.char_sig.find(attr);
+    if (it != rel.char_sig.end()) return it->second.as<uint64_t>();
+    DevBuf sig(c, sizeof(uint64_t) * rel.n_rows);
+    HB_HIP(launch_char_sig(rel.d_cols.as<ColDev>() + attr, rel.n_rows, sig.as<uint64_t>(), c->stream));
+    const uint64_t* p = sig.as<uint64_t>();
+    rel.char_sig.emplace(attr, std::move(sig));
+    return p;
+}
 
 // Device plan for the blocks of key number `ka`: the sequential path with
 // rules that need an earlier key dropped (the owner check rules those pairs
 // out) and the equality on this key dropped (it holds inside a block).
+// Each rule becomes its cheap steps and filters, in plan order, then its
+// exact similarity predicates, in plan order, then a checkpoint.
 static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector<PathRule>& path, size_t ka,
-                           KeyPlan& kp) {
+                           KeyPlan& kp, bool count) {
     const uint32_t key = rs.keys[ka];
     std::vector<uint32_t> int_attr, str_attr;
     std::vector<std::pair<uint32_t, uint32_t>> gram_key;
@@ -666,6 +679,13 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
         if (it != v.end()) return (uint32_t)(it - v.begin());
         v.push_back(a);
         return (uint32_t)(v.size() - 1);
+    };
+    auto gram_of = [&](uint32_t attr, uint32_t q) {
+        auto gk = std::make_pair(attr, q);
+        auto it = std::find(gram_key.begin(), gram_key.end(), gk);
+        if (it != gram_key.end()) return (uint32_t)(it - gram_key.begin());
+        gram_key.push_back(gk);
+        return (uint32_t)(gram_key.size() - 1);
     };
     std::vector<uint32_t> prev;
     for (size_t x = 0; x < ka; ++x) prev.push_back(res_of(int_attr, rs.keys[x]));
@@ -683,49 +703,59 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
         if (impossible) continue;
         any_rule = true;
         const size_t first = code.size();
+        std::vector<Instr> verify;
         for (uint32_t p : pr.preds) {
             const hb_pred& d = rs.distinct[p];
             const int32_t t = rel.cols[d.attr].type;
             if (d.op == HB_EQ && t != HB_COL_STRING && d.attr == key) continue;
             Instr in{};
             in.slot = (uint8_t)p;
+            Instr f{};
+            f.slot = (uint8_t)(64 + p);
             switch (d.op) {
             case HB_EQ:
                 if (t == HB_COL_STRING) {
+                    f.op = OP_EQF;
+                    f.res = (uint8_t)res_of(str_attr, d.attr);
                     in.op = OP_EQ_STR;
-                    in.res = (uint8_t)res_of(str_attr, d.attr);
+                    in.res = f.res;
+                    code.push_back(f);
+                    verify.push_back(in);
                 } else {
                     in.op = OP_EQ_INT;
                     in.res = (uint8_t)res_of(int_attr, d.attr);
+                    code.push_back(in);
                 }
                 break;
             case HB_ABSDIFF_LE:
                 in.op = OP_ABSDIFF;
                 in.res = (uint8_t)res_of(int_attr, d.attr);
-                in.k_or_d = d.d;
+                in.param = (uint64_t)d.d;
+                code.push_back(in);
                 break;
             case HB_ED_LE:
+                f.op = OP_EDF;
+                f.res = (uint8_t)res_of(str_attr, d.attr);
+                f.param = (uint64_t)d.k;
                 in.op = OP_ED;
-                in.res = (uint8_t)res_of(str_attr, d.attr);
-                in.k_or_d = d.k;
+                in.res = f.res;
+                in.param = (uint64_t)d.k;
+                code.push_back(f);
+                verify.push_back(in);
                 break;
-            case HB_JACCARD_GE: {
+            case HB_JACCARD_GE:
+                f.op = OP_JACF;
+                f.res = (uint8_t)gram_of(d.attr, d.q);
+                f.param = ((uint64_t)d.num << 32) | d.den;
+                in = f;
                 in.op = OP_JAC;
-                auto gk = std::make_pair(d.attr, d.q);
-                auto it = std::find(gram_key.begin(), gram_key.end(), gk);
-                if (it == gram_key.end()) {
-                    gram_key.push_back(gk);
-                    in.res = (uint8_t)(gram_key.size() - 1);
-                } else {
-                    in.res = (uint8_t)(it - gram_key.begin());
-                }
-                in.num = d.num;
-                in.den = d.den;
+                in.slot = (uint8_t)p;
+                code.push_back(f);
+                verify.push_back(in);
                 break;
             }
-            }
-            code.push_back(in);
         }
+        code.insert(code.end(), verify.begin(), verify.end());
         Instr cp{};
         cp.op = OP_CP;
         code.push_back(cp);
@@ -736,8 +766,9 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
     if (int_attr.size() > (size_t)kMaxIntRes || str_attr.size() > (size_t)kMaxStrRes ||
         gram_key.size() > (size_t)kMaxGramRes)
         fail(HB_ERR_LIMIT, "rule set reads more than 16 int, 8 string or 8 q-gram attributes");
-    if (code.size() > 60000) fail(HB_ERR_LIMIT, "plan too long");
+    if (code.size() > (size_t)kMaxPlan) fail(HB_ERR_LIMIT, "plan too long");
 
+    const Partition& P = rel.parts.at(key);
     MatchParams& m = kp.mp;
     m.n_int = (uint32_t)int_attr.size();
     m.n_str = (uint32_t)str_attr.size();
@@ -745,66 +776,53 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
     m.n_prev = (uint32_t)prev.size();
     for (size_t x = 0; x < int_attr.size(); ++x) m.int_attr[x] = int_attr[x];
     for (size_t x = 0; x < prev.size(); ++x) m.prev_res[x] = prev[x];
+    GatherParams gp{};
+    gp.cols = rel.d_cols.as<ColDev>();
+    gp.perm = P.perm.as<uint32_t>();
+    gp.n = P.n_valid;
+    gp.n_int = m.n_int;
+    gp.n_str = m.n_str;
+    gp.n_gram = m.n_gram;
+    for (size_t x = 0; x < int_attr.size(); ++x) gp.int_attr[x] = int_attr[x];
     uint32_t ed_words = 1;
     for (size_t x = 0; x < str_attr.size(); ++x) {
         m.str_attr[x] = str_attr[x];
-        const uint32_t ml = rel.cols[str_attr[x]].max_len;
-        m.str_stride[x] = align_up(std::max<uint32_t>(ml, 4), 4);
-        ed_words = std::max<uint32_t>(ed_words, (ml + 63) / 64);
+        gp.str_attr[x] = str_attr[x];
+        gp.csig[x] = char_signature(c, rel, str_attr[x]);
+        ed_words = std::max<uint32_t>(ed_words, (rel.cols[str_attr[x]].max_len + 63) / 64);
     }
+    uint32_t max_cnt = 1;
     for (size_t x = 0; x < gram_key.size(); ++x) {
         GramIndex& g = gram_index(c, rel, gram_key[x].first, gram_key[x].second);
         m.gram[x] = g.dev();
-        if (m.gram[x].max_cnt == 0) m.gram[x].max_cnt = 1;
+        gp.gram[x] = g.dev();
+        gp.gsig[x] = g.sig.as<uint64_t>();
+        max_cnt = std::max(max_cnt, g.max_cnt);
     }
     m.ed_words = ed_words;
-    // LDS layout: metadata and per-wave tables always; the bulk of each
-    // string / gram resource is staged while the total stays within the
-    // occupancy budget, otherwise that resource is read from HBM.
+    const uint32_t n64 = m.n_int + m.n_str + m.n_gram, n32 = 2 + m.n_str + m.n_gram;
+    const size_t nv = std::max<uint32_t>(P.n_valid, 1);
+    kp.f64.alloc(c, sizeof(uint64_t) * nv * std::max<uint32_t>(n64, 1));
+    kp.f32.alloc(c, sizeof(uint32_t) * nv * n32);
+    gp.f64 = kp.f64.as<uint64_t>();
+    gp.f32 = kp.f32.as<uint32_t>();
+    HB_HIP(launch_gather_features(gp, c->stream));
+
+    // LDS: the j-tile's feature columns, then per wave the pattern-match
+    // table and the current row's q-gram lists
     bool any_ed = false;
     for (const Instr& in : code) any_ed |= in.op == OP_ED;
-    uint32_t wave_bytes = any_ed ? 256 * ed_words * 8 : 0;
-    for (uint32_t x = 0; x < m.n_gram; ++x) wave_bytes += align_up(m.gram[x].max_cnt * 4, 16);
-    wave_bytes = align_up(std::max<uint32_t>(wave_bytes, 16), 16);
-    uint32_t fixed = align_up(m.n_int * kTile * 9, 16) + align_up(m.n_str * kTile * 5, 16) +
-                     align_up(m.n_gram * kTile * 5, 16) + kWaves * wave_bytes + 64;
-    const uint32_t budget = std::min<uint32_t>(c->lds_limit, kLdsBudget);
-    if (fixed > c->lds_limit) fail(HB_ERR_LIMIT, "the rule set's per-tile working set exceeds the device LDS");
-    uint32_t bulk = 0;
-    m.str_global = 0;
-    m.gram_global = 0;
-    for (uint32_t x = 0; x < m.n_str; ++x) {
-        const uint32_t b = kTile * m.str_stride[x];
-        if (fixed + bulk + b <= budget) bulk += b; else m.str_global |= 1u << x;
-    }
-    for (uint32_t x = 0; x < m.n_gram; ++x) {
-        const uint32_t b = align_up(kTile * m.gram[x].max_cnt * 4, 16);
-        if (fixed + bulk + b <= budget) bulk += b; else m.gram_global |= 1u << x;
-    }
     uint32_t off = 0;
-    m.lds_int = off;
-    off += m.n_int * kTile * 8;
-    m.lds_int_valid = off;
-    off += m.n_int * kTile;
-    off = align_up(off, 16);
-    for (uint32_t x = 0; x < m.n_str; ++x) {
-        m.lds_str[x] = off;
-        if (!((m.str_global >> x) & 1)) off += kTile * m.str_stride[x];
-    }
-    off = align_up(off, 16);
-    m.lds_str_len = off;
-    off += m.n_str * kTile * 4;
-    m.lds_str_valid = off;
-    off += m.n_str * kTile;
-    off = align_up(off, 16);
-    for (uint32_t x = 0; x < m.n_gram; ++x) {
-        m.lds_gram[x] = off;
-        if (!((m.gram_global >> x) & 1)) off += align_up(kTile * m.gram[x].max_cnt * 4, 16);
-    }
-    m.lds_gram_cnt = off;
-    off += m.n_gram * kTile * 4;
-    m.lds_gram_flag = off;
-    off += m.n_gram * kTile;
+    m.lds_plan = off;
+    off += (uint32_t)code.size() * (uint32_t)sizeof(Instr);
+    m.lds_f64 = off;
+    off += n64 * kTile * 8;
+    m.lds_i64 = off;
+    off += n64 * kTile * 8;
+    m.lds_f32 = off;
+    off += n32 * kTile * 4;
+    m.lds_i32 = off;
+    off += n32 * kTile * 4;
     off = align_up(off, 16);
     m.lds_wave_base = off;
     uint32_t w = 0;
@@ -812,19 +830,22 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
     if (any_ed) w += 256 * ed_words * 8;
     for (uint32_t x = 0; x < m.n_gram; ++x) {
         m.lds_wave_igram[x] = w;
-        w += align_up(m.gram[x].max_cnt * 4, 16);
+        w += align_up(std::max<uint32_t>(m.gram[x].max_cnt, 1) * 4, 16);
     }
     w = align_up(std::max<uint32_t>(w, 16), 16);
     m.lds_wave_stride = w;
     off += kWaves * w;
+    m.lds_counts = off;
+    if (count) off += ((uint32_t)code.size() * 4 + 1) * 8;
     m.lds_bytes = align_up(off, 16);
     if (m.lds_bytes > c->lds_limit)
         fail(HB_ERR_LIMIT, "the rule set's per-tile working set (" + std::to_string(m.lds_bytes) +
                                " bytes of LDS) exceeds the device limit");
 
-    const Partition& P = rel.parts.at(key);
     m.cols = rel.d_cols.as<ColDev>();
-    m.perm = P.perm.as<uint32_t>();
+    m.feat.f64 = kp.f64.as<uint64_t>();
+    m.feat.f32 = kp.f32.as<uint32_t>();
+    m.feat.n = P.n_valid;
     m.blk_start = P.blk_start.as<uint32_t>();
     m.blk_size = P.blk_size.as<uint32_t>();
     m.tile_prefix = P.tile_prefix.as<uint64_t>();
@@ -836,27 +857,37 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
     return true;
 }
 
-static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan) {
+// Per-operation cost model (int32 lane-ops): a fixed part per evaluated
+// lane plus a part per work unit (edit distance: text byte x 32-bit pattern
+// word; Jaccard: merged list element; string equality: byte compared).
+static const double kOpBase[8] = {1, 4, 3, 12, 12, 2, 4, 4};
+static const double kOpUnit[8] = {0, 0, 0, 0, 0, 1, 17, 3};
+
+static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stats* ws = nullptr) {
     std::vector<PathRule> path = plan == HB_PLAN_HEURISTIC ? epg_path(rs.sp, rs.cost, rs.rules) : given_path(rs.rules);
     std::vector<KeyPlan> kps;
     size_t total_code = 0;
     for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
+        if (rel.parts.at(rs.keys[ka]).n_tiles == 0) continue;
         KeyPlan kp;
-        if (!build_key_plan(c, rel, rs, path, ka, kp)) continue;
-        if (kp.mp.n_tiles == 0) continue;
+        if (!build_key_plan(c, rel, rs, path, ka, kp, ws != nullptr)) continue;
         total_code += kp.code.size();
         kps.push_back(std::move(kp));
     }
     DevBuf code(c, sizeof(Instr) * std::max<size_t>(total_code, 1));
+    DevBuf counts(c, sizeof(unsigned long long) * (total_code * 4 + kps.size() + 1));
+    if (ws) zero(c, counts.get(), counts.size());
     {
         std::vector<Instr> all;
         for (KeyPlan& kp : kps) all.insert(all.end(), kp.code.begin(), kp.code.end());
         if (!all.empty())
             HB_HIP(hipMemcpyAsync(code.get(), all.data(), sizeof(Instr) * all.size(), hipMemcpyHostToDevice, c->stream));
-        size_t o = 0;
+        size_t o = 0, co = 0;
         for (KeyPlan& kp : kps) {
             kp.mp.plan = code.as<Instr>() + o;
+            kp.mp.counts = ws ? counts.as<unsigned long long>() + co : nullptr;
             o += kp.code.size();
+            co += kp.code.size() * 4 + 1;
         }
     }
     DevBuf counter(c, 8);
@@ -876,9 +907,34 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan) {
             ++launches;
         }
         found = read1(c, counter.as<unsigned long long>());
-        if (found <= cap) break;
+        if (ws || found <= cap) break;
         cap = found;
         out.alloc(c, sizeof(uint64_t) * cap);
+    }
+    if (ws) {
+        std::vector<unsigned long long> h(counts.size() / sizeof(unsigned long long));
+        HB_HIP(hipMemcpyAsync(h.data(), counts.get(), counts.size(), hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+        std::memset(ws, 0, sizeof(*ws));
+        size_t co = 0;
+        for (KeyPlan& kp : kps) {
+            for (size_t pc = 0; pc < kp.code.size(); ++pc) {
+                const int op = kp.code[pc].op;
+                if (op >= HB_N_OPKINDS) continue;
+                ws->waves[op] += h[co + pc * 4 + 0];
+                ws->lanes[op] += h[co + pc * 4 + 1];
+                ws->passed[op] += h[co + pc * 4 + 2];
+                ws->work[op] += h[co + pc * 4 + 3];
+            }
+            ws->pairs += h[co + kp.code.size() * 4];
+            co += kp.code.size() * 4 + 1;
+        }
+        double ops = 0.0;
+        for (int op = 0; op < HB_N_OPKINDS; ++op) ops += kOpBase[op] * ws->lanes[op] + kOpUnit[op] * ws->work[op];
+        ws->lane_ops = ops;
+        ws->matched = found;
+        ws->launches = launches;
+        return;
     }
     // sort the packed pairs: j bits, then i bits
     const int nb = bit_width(rel.n_rows > 1 ? rel.n_rows - 1 : 1);
@@ -887,10 +943,10 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan) {
     sh.insert(sh.end(), shi.begin(), shi.end());
     rs.result.alloc(c, sizeof(uint64_t) * std::max<uint64_t>(found, 1));
     if (found > 1) {
+        if (found >= 0xFFFFFFFFull) fail(HB_ERR_LIMIT, "more than 2^32 matched pairs");
         DevBuf alt(c, sizeof(uint64_t) * found);
         DevBuf rtmp(c, radix_tmp_bytes((uint32_t)found));
         bool in_alt = false;
-        if (found >= 0xFFFFFFFFull) fail(HB_ERR_LIMIT, "more than 2^32 matched pairs");
         c->timed("output_sort", [&] {
             return radix_sort_pairs(out.as<uint64_t>(), nullptr, alt.as<uint64_t>(), nullptr, (uint32_t)found, sh.data(),
                                     (int)sh.size(), rtmp.get(), &in_alt, c->stream);
@@ -907,6 +963,15 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan) {
     c->last.matched_pairs = found;
     c->last.tiles = tiles;
     c->last.launches = launches;
+}
+
+static void match_work(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, hb_work_stats* ws) {
+    Relation& rel = get_rel(c, rel_id);
+    RuleSet& rs = get_rs(c, rs_id, rel_id);
+    if (!ws) fail(HB_ERR_INVALID_ARG, "NULL stats");
+    if (plan != HB_PLAN_GIVEN && plan != HB_PLAN_HEURISTIC) fail(HB_ERR_INVALID_ARG, "unknown plan");
+    if (!rs.partitioned) fail(HB_ERR_STATE, "hb_partition must run before hb_match_work");
+    run_match(c, rel, rs, plan, ws);
 }
 
 static void match(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, uint64_t* out, int out_on_device, uint64_t cap,
@@ -1034,6 +1099,10 @@ hb_status hb_partition(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, uint64
 hb_status hb_match(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, uint64_t* out_pairs,
                    int out_on_device, uint64_t capacity, uint64_t* n_pairs) {
     return guard(ctx, [&](Ctx* c) { hb::match(c, rel_id, ruleset_id, plan, out_pairs, out_on_device, capacity, n_pairs); });
+}
+
+hb_status hb_match_work(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, hb_work_stats* out) {
+    return guard(ctx, [&](Ctx* c) { hb::match_work(c, rel_id, ruleset_id, plan, out); });
 }
 
 hb_status hb_ruleset_estimates(hb_ctx* ctx, uint32_t ruleset_id, double* sp, double* cost, uint32_t cap, uint32_t* n) {

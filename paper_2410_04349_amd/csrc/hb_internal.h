@@ -17,7 +17,8 @@ constexpr int kMaxIntRes = 16;   // int attributes staged per tile
 constexpr int kMaxStrRes = 8;    // string attributes staged per tile
 constexpr int kMaxGramRes = 8;   // (attribute, q) gram lists staged per tile
 constexpr int kMaxPrevKeys = 3;
-constexpr int kMaxEdWords = 8;   // 512-byte edit-distance patterns
+constexpr int kMaxEdWords = 4;   // 256-byte edit-distance patterns
+constexpr int kMaxPlan = 1536;   // steps of one key's plan
 
 enum ColType : int32_t { COL_STRING = 0, COL_CATEGORICAL = 1, COL_INT64 = 2 };
 
@@ -46,12 +47,27 @@ struct GramDev {
     uint32_t pad;
 };
 
-enum Op : uint8_t { OP_EQ_INT = 0, OP_EQ_STR = 1, OP_ABSDIFF = 2, OP_ED = 3, OP_JAC = 4, OP_CP = 5 };
+// Plan operations.  Filters are exact necessary conditions of the
+// predicate they precede (a filter that fails proves the predicate false);
+// the verify operations compute the predicate itself.
+enum Op : uint8_t {
+    OP_EQ_INT = 0,   // value equality (categorical / int64)
+    OP_ABSDIFF = 1,  // |a - b| <= d
+    OP_EQF = 2,      // string equality filter: equal length and character signature
+    OP_EDF = 3,      // edit distance filter: |m - n| <= k and signature bound <= k
+    OP_JACF = 4,     // Jaccard filter: q-gram signature bound on the intersection
+    OP_EQ_STR = 5,   // verify: byte equality
+    OP_ED = 6,       // verify: Levenshtein distance <= k (Myers)
+    OP_JAC = 7,      // verify: q-gram Jaccard >= num / den (merge intersection)
+    OP_CP = 8        // rule end: the pair has a witness
+};
 
-// One step of the sequential execution path.  `slot` is the distinct
-// predicate's bit in the per-pair reuse masks; `res` indexes the staged
-// resource (int / string / gram list) it reads; `cp` is the index of the
-// rule-end checkpoint that closes this instruction's rule.
+// One step of the sequential execution path.  `slot` is the step's bit in
+// the per-pair reuse masks (distinct predicates 0..63, their filters
+// 64..127); `res` indexes the int / string / gram resource it reads; `cp`
+// is the index of the checkpoint that closes the rule.
+// `param` is d (|a - b| <= d), k (edit distance) or (num << 32) | den
+// (Jaccard threshold num / den).
 struct Instr {
     uint8_t op;
     uint8_t slot;
@@ -59,17 +75,28 @@ struct Instr {
     uint8_t pad0;
     uint16_t cp;
     uint16_t pad1;
-    int64_t k_or_d;
-    uint32_t num;
-    uint32_t den;
+    uint64_t param;
 };
-static_assert(sizeof(Instr) == 24, "Instr layout");
+static_assert(sizeof(Instr) == 16, "Instr layout");
+
+// Block-major feature columns of one key partition (structure of arrays,
+// position p = p-th row of the key-sorted permutation):
+//   f64[(x) * n + p]: x < n_int: int value; then n_str character signatures;
+//                     then n_gram q-gram signatures
+//   f32[(x) * n + p]: x = 0: row id; 1: validity mask (bit r: int resource r,
+//                     16 + r: string resource r, 24 + r: gram resource r);
+//                     then n_str lengths; then n_gram set sizes
+struct Features {
+    const uint64_t* f64;
+    const uint32_t* f32;
+    uint64_t n;       // positions (rows with a valid key)
+};
 
 // Everything the match kernel needs for one (relation, key partition, plan).
 struct MatchParams {
     const ColDev* cols;
-    // partition of the key: rows sorted by key value; blocks of >= 2 rows
-    const uint32_t* perm;
+    Features feat;
+    // partition of the key: blocks of >= 2 rows
     const uint32_t* blk_start;
     const uint32_t* blk_size;
     const uint64_t* tile_prefix;   // n_blocks + 1 entries
@@ -79,20 +106,16 @@ struct MatchParams {
     // plan
     const Instr* plan;
     uint32_t plan_len;
-    // staged resources
     uint32_t n_int, n_str, n_gram, n_prev;
     uint32_t int_attr[kMaxIntRes];
     uint32_t str_attr[kMaxStrRes];
-    uint32_t str_stride[kMaxStrRes];
     GramDev gram[kMaxGramRes];
     uint32_t prev_res[kMaxPrevKeys];   // int resources of earlier keys (canonical owner)
-    uint32_t ed_words;                 // words of the per-wave pattern-match table
-    uint32_t str_global;               // bit r: string resource r read from HBM, not staged
-    uint32_t gram_global;              // bit r: gram resource r read from HBM, not staged
+    uint32_t ed_words;                 // 64-bit words of the per-wave pattern-match table
     // LDS layout (byte offsets into dynamic shared memory)
-    uint32_t lds_int, lds_int_valid;
-    uint32_t lds_str[kMaxStrRes], lds_str_len, lds_str_valid;
-    uint32_t lds_gram[kMaxGramRes], lds_gram_cnt, lds_gram_flag;
+    uint32_t lds_plan;                 // plan_len instructions
+    uint32_t lds_f64, lds_f32;         // j-tile feature columns
+    uint32_t lds_i64, lds_i32;         // i-tile feature columns
     uint32_t lds_wave_base, lds_wave_stride;   // per-wave region
     uint32_t lds_wave_peq, lds_wave_igram[kMaxGramRes];
     uint32_t lds_bytes;
@@ -100,6 +123,25 @@ struct MatchParams {
     uint64_t* out;
     uint64_t cap;
     unsigned long long* counter;
+    // instrumented pass only: per plan step {waves, lanes, passed, work},
+    // then {pairs evaluated}; nullptr in the normal pass
+    unsigned long long* counts;
+    uint32_t lds_counts;
+};
+
+// Gather of the block-major feature columns.
+struct GatherParams {
+    const ColDev* cols;
+    const uint32_t* perm;
+    uint64_t n;
+    uint32_t n_int, n_str, n_gram;
+    uint32_t int_attr[kMaxIntRes];
+    uint32_t str_attr[kMaxStrRes];
+    const uint64_t* csig[kMaxStrRes];
+    GramDev gram[kMaxGramRes];
+    const uint64_t* gsig[kMaxGramRes];
+    uint64_t* f64;
+    uint32_t* f32;
 };
 
 // ---------------------------------------------------------------- launches
@@ -157,6 +199,13 @@ hipError_t launch_gram_slots(const ColDev* col, uint32_t n, uint32_t q, uint64_t
 hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const uint64_t* off,
                              uint32_t* codes, uint32_t* cnt, uint8_t* flags,
                              unsigned int* d_max_cnt, hipStream_t s);
+
+// character-presence signature of every string of a column
+hipError_t launch_char_sig(const ColDev* col, uint32_t n, uint64_t* sig, hipStream_t s);
+// q-gram signature of every row of a gram index
+hipError_t launch_gram_sig(const GramDev& g, uint32_t n, uint64_t* sig, hipStream_t s);
+// block-major feature columns
+hipError_t launch_gather_features(const GatherParams& p, hipStream_t s);
 
 // LSH bucket histogram of one predicate (op, q, d) over column `col`
 hipError_t launch_lsh_hist(const ColDev* col, uint32_t n, int op, uint32_t q, int64_t d,

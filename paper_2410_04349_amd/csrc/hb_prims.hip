@@ -386,6 +386,68 @@ __global__ void k_gram_build(const ColDev* __restrict__ colp, uint32_t n, uint32
     if ((threadIdx.x & 63) == 0) atomicMax(max_cnt, out_cnt);
 }
 
+
+// ------------------------------------------------------------ features
+
+// bit (c mod 64) for every byte c of the string: a substitution changes at
+// most one set bit on each side, an insertion or deletion at most one, so
+// the edit distance is at least max(|sig_a \ sig_b|, |sig_b \ sig_a|)
+__global__ void k_char_sig(const ColDev* __restrict__ colp, uint32_t n, uint64_t* __restrict__ sig) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const ColDev c = *colp;
+    uint64_t m = 0;
+    if (bit_valid(c.valid, r)) {
+        const uint8_t* s = c.bytes + c.off[r];
+        const uint32_t L = str_len(c, r);
+        for (uint32_t x = 0; x < L; ++x) m |= 1ull << (s[x] & 63);
+    }
+    sig[r] = m;
+}
+
+// bit (hash(code) mod 64) for every distinct q-gram code of the row: a gram
+// in A whose bit is absent from sig_B is not in B, so
+// |A & B| <= |A| - |sig_A \ sig_B|
+__global__ void k_gram_sig(const GramDev g, uint32_t n, uint64_t* __restrict__ sig) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t* codes = g.codes + g.off[r];
+    const uint32_t cnt = g.cnt[r];
+    uint64_t m = 0;
+    for (uint32_t x = 0; x < cnt; ++x) m |= 1ull << (mix64(codes[x]) & 63);
+    sig[r] = m;
+}
+
+__global__ void k_gather_features(const GatherParams P) {
+    const uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    const uint64_t n = P.n;
+    const uint32_t row = P.perm[p];
+    uint32_t vmask = 0;
+    for (uint32_t x = 0; x < P.n_int; ++x) {
+        const ColDev& c = P.cols[P.int_attr[x]];
+        const bool v = bit_valid(c.valid, row);
+        P.f64[x * n + p] = v ? (uint64_t)c.values[row] : 0ull;
+        vmask |= (v ? 1u : 0u) << x;
+    }
+    for (uint32_t x = 0; x < P.n_str; ++x) {
+        const ColDev& c = P.cols[P.str_attr[x]];
+        const bool v = bit_valid(c.valid, row);
+        P.f64[(P.n_int + x) * n + p] = v ? P.csig[x][row] : 0ull;
+        P.f32[(2 + x) * n + p] = v ? (uint32_t)(c.off[row + 1] - c.off[row]) : 0u;
+        vmask |= (v ? 1u : 0u) << (16 + x);
+    }
+    for (uint32_t x = 0; x < P.n_gram; ++x) {
+        const GramDev& g = P.gram[x];
+        const bool v = bit_valid(P.cols[g.attr].valid, row);
+        P.f64[(P.n_int + P.n_str + x) * n + p] = v ? P.gsig[x][row] : 0ull;
+        P.f32[(2 + P.n_str + x) * n + p] = v ? (g.cnt[row] | ((uint32_t)(g.flags[row] & 1) << 31)) : 0u;
+        vmask |= (v ? 1u : 0u) << (24 + x);
+    }
+    P.f32[p] = row;
+    P.f32[n + p] = vmask;
+}
+
 // ------------------------------------------------------------ LSH histogram
 
 __device__ inline uint64_t fnv1a64(const uint8_t* s, uint32_t L) {
@@ -610,6 +672,23 @@ hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const ui
                              uint32_t* codes, uint32_t* cnt, uint8_t* flags,
                              unsigned int* d_max_cnt, hipStream_t s) {
     k_gram_build<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_char_sig(const ColDev* col, uint32_t n, uint64_t* sig, hipStream_t s) {
+    k_char_sig<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(col, n, sig);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_sig(const GramDev& g, uint32_t n, uint64_t* sig, hipStream_t s) {
+    k_gram_sig<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(g, n, sig);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_features(const GatherParams& p, hipStream_t s) {
+    if (p.n == 0) return hipSuccess;
+    k_gather_features<<<grid_for(p.n, 1u << 30), kBlock, 0, s>>>(p);
     return hipGetLastError();
 }
 

@@ -101,7 +101,7 @@ def test_edit_distance_word_boundaries(hb, ctx, k):
     show(f"ed boundaries k={k}")
     r = np.random.default_rng(k)
     strings = []
-    for L in (0, 1, 5, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 200, 255, 256, 257, 400, 512):
+    for L in (0, 1, 5, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 191, 192, 193, 200, 250, 254):
         base = bytes(r.integers(97, 100, size=L).astype(np.uint8))
         strings.append(base)
         for e in (1, 2, 5):
@@ -110,7 +110,7 @@ def test_edit_distance_word_boundaries(hb, ctx, k):
                 t = int(r.integers(0, 3))
                 if t == 0 and s:
                     s[int(r.integers(0, len(s)))] = 97 + int(r.integers(0, 3))
-                elif t == 1 and len(s) < 512:
+                elif t == 1 and len(s) < 256:
                     s.insert(int(r.integers(0, len(s) + 1)), 97 + int(r.integers(0, 3)))
                 elif s:
                     del s[int(r.integers(0, len(s)))]
@@ -120,6 +120,18 @@ def test_edit_distance_word_boundaries(hb, ctx, k):
     want = oracle.blocking(rel, rules, threads=8)
     got, _ = run(hb, ctx, rel, rules, "given")
     assert np.array_equal(got, want)
+
+
+def test_edit_distance_length_limit(hb, ctx):
+    show("ed length limit")
+    rel = _one_block_strings([b"a" * 257, b"a" * 10])
+    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_compile_rules(ctx, rid, [[Pred(EQ, 1), Pred(ED, 0, k=1)]])
+    assert e.value.status == hb.HB_ERR_LIMIT
+    # Jaccard on the same attribute is allowed
+    hb.hb_compile_rules(ctx, rid, [[Pred(EQ, 1), Pred(JACCARD, 0, q=2, num=1, den=2)]])
+    hb.hb_release_relation(ctx, rid)
 
 
 @pytest.mark.parametrize("q", [1, 2, 3, 4])
@@ -230,3 +242,21 @@ def test_lsh_buckets_match_oracle(hb, ctx):
 
 
 from oracle import epg  # noqa: E402
+
+
+def test_work_counters_consistent(hb, ctx):
+    show("work counters")
+    rel, rules = workloads.plain_1m(n=20_000)
+    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+    rs = hb.hb_compile_rules(ctx, rid, rules)
+    n_cand = hb.hb_partition(ctx, rid, rs)
+    got = hb.hb_match(ctx, rid, rs, "heuristic")
+    w = hb.hb_match_work(ctx, rid, rs, "heuristic")
+    assert w["pairs"] == n_cand
+    assert w["matched"] == len(got)
+    assert w["lane_ops"] > 0
+    for name, c in w["per_op"].items():
+        assert c["passed"] <= c["lanes"] <= 64 * c["waves"], name
+    # the cached result is untouched by the instrumented pass
+    assert np.array_equal(hb.hb_match(ctx, rid, rs, "heuristic"), got)
+    hb.hb_release_relation(ctx, rid)
