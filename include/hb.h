@@ -212,6 +212,43 @@ typedef struct {
 } hb_work_stats;
 hb_status hb_match_work(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, hb_work_stats* out);
 
+/* ------------------------------------------------------------ cost model
+ * The learned cost model: an MLP 16 -> 64 -> 64 -> 2 (ReLU after both
+ * hidden layers, linear output) predicting (pass rate, cost) of a predicate
+ * on a block from 16 block features; it stands in for the paper's shallow
+ * network trained on logs (Section 4.2, "Shallow NNs", "Estimated cost").
+ * Parameters: HB_MLP_PARAMS fp32 values, row-major, in the order W1 [16x64],
+ * b1 [64], W2 [64x64], b2 [64], W3 [64x2], b3 [2], used as y = x W + b.
+ * GEMMs round both operands to bf16 (nearest, ties to even) and accumulate
+ * in fp32; bias, ReLU, the loss and Adam (beta1 0.9, beta2 0.999, eps 1e-8)
+ * run in fp32.  The model belongs to the context. */
+#define HB_MLP_PARAMS 5378
+#define HB_MLP_FEATURES 16
+/* He-uniform weights from a splitmix64 stream of `seed`, zero biases. */
+hb_status hb_costmodel_init(hb_ctx* ctx, uint64_t seed);
+/* Copy parameters in / out (host arrays of n = HB_MLP_PARAMS floats);
+ * setting them resets the Adam moments. */
+hb_status hb_costmodel_set_params(hb_ctx* ctx, const float* params, uint32_t n);
+hb_status hb_costmodel_get_params(hb_ctx* ctx, float* params, uint32_t n);
+/* Minimise the mean squared error over rows x [n x 16] -> t [n x 2] with
+ * Adam, `epochs` passes of mini-batches of `batch` rows in the given order.
+ * Buffers are host (on_device = 0) or device memory.  *final_loss = mean
+ * squared error accumulated over the last epoch. */
+hb_status hb_costmodel_train(hb_ctx* ctx, const float* x, const float* t, uint64_t n_rows, int on_device,
+                             uint32_t epochs, uint32_t batch, float lr, float* final_loss);
+/* y [n x 2] = model(x [n x 16]). */
+hb_status hb_costmodel_predict(hb_ctx* ctx, const float* x, uint64_t n_rows, int on_device, float* y,
+                               int y_on_device);
+/* For checking the kernels: one forward and backward pass on host rows,
+ * writing to `out` (host) the concatenation Z1, H1, Z2, H2 [n x 64 each],
+ * Y, dY [n x 2 each], dZ2, dZ1 [n x 64 each] (Z = pre-activation, H =
+ * ReLU(Z), dY = d loss / d Y, dZ = d loss / d Z) and the HB_MLP_PARAMS
+ * gradients, in parameter order.  out_len >= n (6 * 64 + 4) + HB_MLP_PARAMS. */
+hb_status hb_costmodel_trace(hb_ctx* ctx, const float* x, const float* t, uint32_t n_rows, float* out,
+                             uint64_t out_len);
+/* One Adam step with the given host gradients (HB_MLP_PARAMS floats). */
+hb_status hb_costmodel_adam_step(hb_ctx* ctx, const float* grads, float lr);
+
 /* Counters of the last hb_match: candidate pairs, pairs matched, launches
  * and tiles of the match kernel. */
 typedef struct {

@@ -41,8 +41,11 @@ EXPORTED = [
     "hb_create", "hb_destroy", "hb_last_error", "hb_version", "hb_load_relation", "hb_release_relation",
     "hb_compile_rules", "hb_partition", "hb_match", "hb_ruleset_estimates", "hb_ruleset_buckets",
     "hb_epg_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
-    "hb_match_work",
+    "hb_match_work", "hb_costmodel_init", "hb_costmodel_set_params", "hb_costmodel_get_params",
+    "hb_costmodel_train", "hb_costmodel_predict", "hb_costmodel_trace", "hb_costmodel_adam_step",
 ]
+
+HB_MLP_PARAMS = 5378
 
 OP_KINDS = ["eq_value", "absdiff", "eq_string_filter", "ed_filter", "jaccard_filter", "eq_string",
             "edit_distance", "jaccard"]
@@ -108,6 +111,14 @@ def _load_lib():
         "hb_profile_reset": (I32, [P]),
         "hb_last_match_stats": (I32, [P, ctypes.POINTER(HbMatchStats)]),
         "hb_match_work": (I32, [P, U32, U32, I32, ctypes.POINTER(HbWorkStats)]),
+        "hb_costmodel_init": (I32, [P, U64]),
+        "hb_costmodel_set_params": (I32, [P, P, U32]),
+        "hb_costmodel_get_params": (I32, [P, P, U32]),
+        "hb_costmodel_train": (I32, [P, P, P, U64, ctypes.c_int, U32, U32, ctypes.c_float,
+                                     ctypes.POINTER(ctypes.c_float)]),
+        "hb_costmodel_predict": (I32, [P, P, U64, ctypes.c_int, P, ctypes.c_int]),
+        "hb_costmodel_trace": (I32, [P, P, P, U32, P, U64]),
+        "hb_costmodel_adam_step": (I32, [P, P, ctypes.c_float]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -350,3 +361,60 @@ def hb_match_work(ctx: Context, rel_id: int, ruleset_id: int, plan="heuristic") 
         per_op[name] = {"waves": w.waves[k], "lanes": w.lanes[k], "passed": w.passed[k], "work": w.work[k]}
     return {"pairs": w.pairs, "matched": w.matched, "launches": w.launches, "lane_ops": w.lane_ops,
             "per_op": per_op}
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def hb_costmodel_init(ctx: Context, seed: int) -> None:
+    ctx.check(_lib.hb_costmodel_init(ctx.h, seed))
+
+
+def hb_costmodel_set_params(ctx: Context, params) -> None:
+    p = _f32(params)
+    ctx.check(_lib.hb_costmodel_set_params(ctx.h, ctypes.c_void_p(p.ctypes.data), p.size))
+
+
+def hb_costmodel_get_params(ctx: Context) -> np.ndarray:
+    p = np.zeros(HB_MLP_PARAMS, dtype=np.float32)
+    ctx.check(_lib.hb_costmodel_get_params(ctx.h, ctypes.c_void_p(p.ctypes.data), p.size))
+    return p
+
+
+def hb_costmodel_train(ctx: Context, x, t, epochs: int, batch: int, lr: float) -> float:
+    x, t = _f32(x), _f32(t)
+    loss = ctypes.c_float()
+    ctx.check(_lib.hb_costmodel_train(ctx.h, ctypes.c_void_p(x.ctypes.data), ctypes.c_void_p(t.ctypes.data),
+                                      x.shape[0], 0, epochs, batch, lr, ctypes.byref(loss)))
+    return loss.value
+
+
+def hb_costmodel_predict(ctx: Context, x) -> np.ndarray:
+    x = _f32(x)
+    y = np.zeros((x.shape[0], 2), dtype=np.float32)
+    ctx.check(_lib.hb_costmodel_predict(ctx.h, ctypes.c_void_p(x.ctypes.data), x.shape[0], 0,
+                                        ctypes.c_void_p(y.ctypes.data), 0))
+    return y
+
+
+def hb_costmodel_trace(ctx: Context, x, t) -> dict:
+    x, t = _f32(x), _f32(t)
+    n = x.shape[0]
+    total = n * (6 * 64 + 4) + HB_MLP_PARAMS
+    out = np.zeros(total, dtype=np.float32)
+    ctx.check(_lib.hb_costmodel_trace(ctx.h, ctypes.c_void_p(x.ctypes.data), ctypes.c_void_p(t.ctypes.data), n,
+                                      ctypes.c_void_p(out.ctypes.data), total))
+    res = {}
+    o = 0
+    for name, cols in (("z1", 64), ("h1", 64), ("z2", 64), ("h2", 64), ("y", 2), ("dy", 2), ("dz2", 64),
+                       ("dz1", 64)):
+        res[name] = out[o:o + n * cols].reshape(n, cols)
+        o += n * cols
+    res["grad"] = out[o:o + HB_MLP_PARAMS]
+    return res
+
+
+def hb_costmodel_adam_step(ctx: Context, grads, lr: float) -> None:
+    g = _f32(grads)
+    ctx.check(_lib.hb_costmodel_adam_step(ctx.h, ctypes.c_void_p(g.ctypes.data), lr))

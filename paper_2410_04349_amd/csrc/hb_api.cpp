@@ -12,237 +12,11 @@
 #include <vector>
 
 #include "../../include/hb.h"
+#include "hb_ctx.h"
 #include "hb_internal.h"
 #include "hb_plan.h"
 
 namespace hb {
-
-struct Failure {
-    hb_status st;
-    std::string msg;
-};
-
-[[noreturn]] static void fail(hb_status st, const std::string& msg) { throw Failure{st, msg}; }
-
-#define HB_HIP(expr)                                                                               \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) fail(HB_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-struct Ctx;
-
-// Device buffer owned through the context's allocator.
-class DevBuf {
-public:
-    DevBuf() = default;
-    DevBuf(Ctx* c, size_t bytes) { alloc(c, bytes); }
-    ~DevBuf() { release(); }
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept { swap(o); }
-    DevBuf& operator=(DevBuf&& o) noexcept {
-        release();
-        swap(o);
-        return *this;
-    }
-    void alloc(Ctx* c, size_t bytes);
-    void release();
-    template <typename T>
-    T* as() const { return static_cast<T*>(p_); }
-    void* get() const { return p_; }
-    size_t size() const { return n_; }
-
-private:
-    void swap(DevBuf& o) {
-        std::swap(c_, o.c_);
-        std::swap(p_, o.p_);
-        std::swap(n_, o.n_);
-    }
-    Ctx* c_ = nullptr;
-    void* p_ = nullptr;
-    size_t n_ = 0;
-};
-
-struct Column {
-    int32_t type = 0;
-    uint32_t max_len = 0;
-    double mean_len = 0.0;
-    DevBuf off, bytes, values, valid;
-};
-
-struct GramIndex {
-    uint32_t attr = 0, q = 0, max_cnt = 0;
-    DevBuf off, cnt, codes, flags, sig;
-    GramDev dev() const {
-        GramDev g{};
-        g.off = off.as<uint64_t>();
-        g.cnt = cnt.as<uint32_t>();
-        g.codes = codes.as<uint32_t>();
-        g.flags = flags.as<uint8_t>();
-        g.q = q;
-        g.max_cnt = max_cnt;
-        g.attr = attr;
-        return g;
-    }
-};
-
-struct Partition {
-    uint32_t attr = 0, n_valid = 0, n_blocks = 0;
-    uint64_t n_tiles = 0, pairs = 0;
-    DevBuf perm, blk_start, blk_size, tile_prefix;
-};
-
-struct Relation {
-    uint32_t id = 0, n_rows = 0, n_cols = 0;
-    std::vector<Column> cols;
-    std::vector<ColDev> h_cols;
-    DevBuf d_cols;
-    std::map<std::pair<uint32_t, uint32_t>, GramIndex> grams;
-    std::map<uint32_t, DevBuf> char_sig;
-    std::map<uint32_t, Partition> parts;
-    std::map<std::vector<uint32_t>, uint64_t> composite;
-};
-
-struct RuleSet {
-    uint32_t id = 0, rel_id = 0;
-    std::vector<hb_pred> distinct;
-    std::vector<std::vector<uint32_t>> rules;  // distinct predicate ids per rule, input order
-    std::vector<uint32_t> keys;                // blocking-key attributes, first-appearance order
-    std::vector<double> sp, cost;
-    std::vector<std::vector<uint64_t>> buckets;
-    std::vector<uint64_t> bucket_n;
-    bool partitioned = false;
-    uint64_t candidates = 0;
-    bool has_result = false;
-    int result_plan = -1;
-    DevBuf result;
-    uint64_t n_result = 0;
-};
-
-struct ProfEntry {
-    double ms = 0.0;
-    uint64_t launches = 0;
-};
-
-struct Pending {
-    std::string name;
-    hipEvent_t a, b;
-};
-
-struct Ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    hb_alloc_fn alloc_fn = nullptr;
-    hb_free_fn free_fn = nullptr;
-    void* user = nullptr;
-    std::string err;
-    uint32_t next_id = 1;
-    std::map<uint32_t, std::unique_ptr<Relation>> rels;
-    std::map<uint32_t, std::unique_ptr<RuleSet>> rulesets;
-    bool profiling = false;
-    std::map<std::string, ProfEntry> prof;
-    std::vector<Pending> pending;
-    hb_match_stats last{};
-    uint32_t lds_limit = 0;
-
-    void* raw_alloc(size_t bytes) {
-        if (bytes == 0) bytes = 16;
-        void* p = nullptr;
-        if (alloc_fn) {
-            p = alloc_fn(bytes, user);
-        } else {
-            if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
-        }
-        if (!p) fail(HB_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-        return p;
-    }
-    void raw_free(void* p) {
-        if (!p) return;
-        if (free_fn) free_fn(p, user);
-        else (void)hipFreeAsync(p, stream);
-    }
-
-    template <typename F>
-    void timed(const char* name, F&& launch) {
-        if (!profiling) {
-            HB_HIP(launch());
-            return;
-        }
-        Pending pd;
-        pd.name = name;
-        HB_HIP(hipEventCreate(&pd.a));
-        HB_HIP(hipEventCreate(&pd.b));
-        HB_HIP(hipEventRecord(pd.a, stream));
-        HB_HIP(launch());
-        HB_HIP(hipEventRecord(pd.b, stream));
-        pending.push_back(pd);
-    }
-    void drain_profile() {
-        for (auto& pd : pending) {
-            (void)hipEventSynchronize(pd.b);
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, pd.a, pd.b);
-            auto& e = prof[pd.name];
-            e.ms += ms;
-            e.launches += 1;
-            (void)hipEventDestroy(pd.a);
-            (void)hipEventDestroy(pd.b);
-        }
-        pending.clear();
-    }
-    void sync() { HB_HIP(hipStreamSynchronize(stream)); }
-};
-
-void DevBuf::alloc(Ctx* c, size_t bytes) {
-    release();
-    c_ = c;
-    p_ = c->raw_alloc(bytes);
-    n_ = bytes;
-}
-
-void DevBuf::release() {
-    if (p_ && c_) c_->raw_free(p_);
-    p_ = nullptr;
-    n_ = 0;
-    c_ = nullptr;
-}
-
-template <typename T>
-static T read1(Ctx* c, const T* dptr) {
-    T v{};
-    HB_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, c->stream));
-    c->sync();
-    return v;
-}
-
-static void zero(Ctx* c, void* p, size_t bytes) { HB_HIP(hipMemsetAsync(p, 0, bytes, c->stream)); }
-
-static Relation& get_rel(Ctx* c, uint32_t id) {
-    auto it = c->rels.find(id);
-    if (it == c->rels.end()) fail(HB_ERR_STALE_ID, "unknown relation id " + std::to_string(id));
-    return *it->second;
-}
-
-static RuleSet& get_rs(Ctx* c, uint32_t id, uint32_t rel_id) {
-    auto it = c->rulesets.find(id);
-    if (it == c->rulesets.end()) fail(HB_ERR_STALE_ID, "unknown rule set id " + std::to_string(id));
-    if (it->second->rel_id != rel_id) fail(HB_ERR_STALE_ID, "rule set was compiled for another relation");
-    return *it->second;
-}
-
-static int bit_width(uint64_t v) {
-    int b = 0;
-    while (v) { ++b; v >>= 1; }
-    return b;
-}
-
-static std::vector<int> shifts_for_bits(int bits, int base) {
-    std::vector<int> s;
-    for (int x = 0; x < bits; x += 8) s.push_back(base + x);
-    return s;
-}
 
 // ------------------------------------------------------------ load
 
@@ -813,21 +587,17 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
     bool any_ed = false;
     for (const Instr& in : code) any_ed |= in.op == OP_ED;
     uint32_t off = 0;
-    m.lds_plan = off;
-    off += (uint32_t)code.size() * (uint32_t)sizeof(Instr);
     m.lds_f64 = off;
     off += n64 * kTile * 8;
-    m.lds_i64 = off;
-    off += n64 * kTile * 8;
     m.lds_f32 = off;
-    off += n32 * kTile * 4;
-    m.lds_i32 = off;
     off += n32 * kTile * 4;
     off = align_up(off, 16);
     m.lds_wave_base = off;
     uint32_t w = 0;
     m.lds_wave_peq = w;
     if (any_ed) w += 256 * ed_words * 8;
+    m.lds_wave_myers = w;
+    if (any_ed && ed_words >= 2) w += 2 * kMaxEdWords * 64 * 8;
     for (uint32_t x = 0; x < m.n_gram; ++x) {
         m.lds_wave_igram[x] = w;
         w += align_up(std::max<uint32_t>(m.gram[x].max_cnt, 1) * 4, 16);
@@ -836,7 +606,7 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
     m.lds_wave_stride = w;
     off += kWaves * w;
     m.lds_counts = off;
-    if (count) off += ((uint32_t)code.size() * 4 + 1) * 8;
+    if (count) off += kCountSlots * 8;
     m.lds_bytes = align_up(off, 16);
     if (m.lds_bytes > c->lds_limit)
         fail(HB_ERR_LIMIT, "the rule set's per-tile working set (" + std::to_string(m.lds_bytes) +
@@ -875,19 +645,18 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
         kps.push_back(std::move(kp));
     }
     DevBuf code(c, sizeof(Instr) * std::max<size_t>(total_code, 1));
-    DevBuf counts(c, sizeof(unsigned long long) * (total_code * 4 + kps.size() + 1));
+    DevBuf counts(c, sizeof(unsigned long long) * kCountSlots);
     if (ws) zero(c, counts.get(), counts.size());
     {
         std::vector<Instr> all;
         for (KeyPlan& kp : kps) all.insert(all.end(), kp.code.begin(), kp.code.end());
         if (!all.empty())
             HB_HIP(hipMemcpyAsync(code.get(), all.data(), sizeof(Instr) * all.size(), hipMemcpyHostToDevice, c->stream));
-        size_t o = 0, co = 0;
+        size_t o = 0;
         for (KeyPlan& kp : kps) {
             kp.mp.plan = code.as<Instr>() + o;
-            kp.mp.counts = ws ? counts.as<unsigned long long>() + co : nullptr;
+            kp.mp.counts = ws ? counts.as<unsigned long long>() : nullptr;
             o += kp.code.size();
-            co += kp.code.size() * 4 + 1;
         }
     }
     DevBuf counter(c, 8);
@@ -916,19 +685,13 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
         HB_HIP(hipMemcpyAsync(h.data(), counts.get(), counts.size(), hipMemcpyDeviceToHost, c->stream));
         c->sync();
         std::memset(ws, 0, sizeof(*ws));
-        size_t co = 0;
-        for (KeyPlan& kp : kps) {
-            for (size_t pc = 0; pc < kp.code.size(); ++pc) {
-                const int op = kp.code[pc].op;
-                if (op >= HB_N_OPKINDS) continue;
-                ws->waves[op] += h[co + pc * 4 + 0];
-                ws->lanes[op] += h[co + pc * 4 + 1];
-                ws->passed[op] += h[co + pc * 4 + 2];
-                ws->work[op] += h[co + pc * 4 + 3];
-            }
-            ws->pairs += h[co + kp.code.size() * 4];
-            co += kp.code.size() * 4 + 1;
+        for (int op = 0; op < HB_N_OPKINDS; ++op) {
+            ws->waves[op] = h[op * 4 + 0];
+            ws->lanes[op] = h[op * 4 + 1];
+            ws->passed[op] = h[op * 4 + 2];
+            ws->work[op] = h[op * 4 + 3];
         }
+        ws->pairs = h[kCountPairs];
         double ops = 0.0;
         for (int op = 0; op < HB_N_OPKINDS; ++op) ops += kOpBase[op] * ws->lanes[op] + kOpUnit[op] * ws->work[op];
         ws->lane_ops = ops;
@@ -1158,6 +921,37 @@ hb_status hb_epg_path(uint32_t n_preds, const double* sp, const double* cost, ui
     } catch (...) {
         return HB_ERR_OOM;
     }
+}
+
+hb_status hb_costmodel_init(hb_ctx* ctx, uint64_t seed) {
+    return guard(ctx, [&](Ctx* c) { hb::costmodel_init(c, seed); });
+}
+
+hb_status hb_costmodel_set_params(hb_ctx* ctx, const float* params, uint32_t n) {
+    return guard(ctx, [&](Ctx* c) { hb::costmodel_set(c, params, n); });
+}
+
+hb_status hb_costmodel_get_params(hb_ctx* ctx, float* params, uint32_t n) {
+    return guard(ctx, [&](Ctx* c) { hb::costmodel_get(c, params, n); });
+}
+
+hb_status hb_costmodel_train(hb_ctx* ctx, const float* x, const float* t, uint64_t n_rows, int on_device,
+                             uint32_t epochs, uint32_t batch, float lr, float* final_loss) {
+    return guard(ctx, [&](Ctx* c) { hb::costmodel_train(c, x, t, n_rows, on_device, epochs, batch, lr, final_loss); });
+}
+
+hb_status hb_costmodel_predict(hb_ctx* ctx, const float* x, uint64_t n_rows, int on_device, float* y,
+                               int y_on_device) {
+    return guard(ctx, [&](Ctx* c) { hb::costmodel_predict(c, x, n_rows, on_device, y, y_on_device); });
+}
+
+hb_status hb_costmodel_trace(hb_ctx* ctx, const float* x, const float* t, uint32_t n_rows, float* out,
+                             uint64_t out_len) {
+    return guard(ctx, [&](Ctx* c) { hb::costmodel_trace(c, x, t, n_rows, out, out_len); });
+}
+
+hb_status hb_costmodel_adam_step(hb_ctx* ctx, const float* grads, float lr) {
+    return guard(ctx, [&](Ctx* c) { hb::costmodel_adam(c, grads, lr); });
 }
 
 hb_status hb_profile_enable(hb_ctx* ctx, int on) {

@@ -1,0 +1,266 @@
+// Host-side state of libhb shared by the entry-point files: error
+// handling, device buffers owned through the context's allocator, the
+// context, relations, rule sets and the cost model.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hb.h"
+#include "hb_internal.h"
+
+namespace hb {
+
+struct Failure {
+    hb_status st;
+    std::string msg;
+};
+
+[[noreturn]] inline void fail(hb_status st, const std::string& msg) { throw Failure{st, msg}; }
+
+#define HB_HIP(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) fail(HB_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Ctx;
+
+// Device buffer owned through the context's allocator.
+class DevBuf {
+public:
+    DevBuf() = default;
+    DevBuf(Ctx* c, size_t bytes) { alloc(c, bytes); }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { swap(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        release();
+        swap(o);
+        return *this;
+    }
+    void alloc(Ctx* c, size_t bytes);
+    void release();
+    template <typename T>
+    T* as() const { return static_cast<T*>(p_); }
+    void* get() const { return p_; }
+    size_t size() const { return n_; }
+
+private:
+    void swap(DevBuf& o) {
+        std::swap(c_, o.c_);
+        std::swap(p_, o.p_);
+        std::swap(n_, o.n_);
+    }
+    Ctx* c_ = nullptr;
+    void* p_ = nullptr;
+    size_t n_ = 0;
+};
+
+struct Column {
+    int32_t type = 0;
+    uint32_t max_len = 0;
+    double mean_len = 0.0;
+    DevBuf off, bytes, values, valid;
+};
+
+struct GramIndex {
+    uint32_t attr = 0, q = 0, max_cnt = 0;
+    DevBuf off, cnt, codes, flags, sig;
+    GramDev dev() const {
+        GramDev g{};
+        g.off = off.as<uint64_t>();
+        g.cnt = cnt.as<uint32_t>();
+        g.codes = codes.as<uint32_t>();
+        g.flags = flags.as<uint8_t>();
+        g.q = q;
+        g.max_cnt = max_cnt;
+        g.attr = attr;
+        return g;
+    }
+};
+
+struct Partition {
+    uint32_t attr = 0, n_valid = 0, n_blocks = 0;
+    uint64_t n_tiles = 0, pairs = 0;
+    DevBuf perm, blk_start, blk_size, tile_prefix;
+};
+
+struct Relation {
+    uint32_t id = 0, n_rows = 0, n_cols = 0;
+    std::vector<Column> cols;
+    std::vector<ColDev> h_cols;
+    DevBuf d_cols;
+    std::map<std::pair<uint32_t, uint32_t>, GramIndex> grams;
+    std::map<uint32_t, DevBuf> char_sig;
+    std::map<uint32_t, Partition> parts;
+    std::map<std::vector<uint32_t>, uint64_t> composite;
+};
+
+struct RuleSet {
+    uint32_t id = 0, rel_id = 0;
+    std::vector<hb_pred> distinct;
+    std::vector<std::vector<uint32_t>> rules;  // distinct predicate ids per rule, input order
+    std::vector<uint32_t> keys;                // blocking-key attributes, first-appearance order
+    std::vector<double> sp, cost;
+    std::vector<std::vector<uint64_t>> buckets;
+    std::vector<uint64_t> bucket_n;
+    bool partitioned = false;
+    uint64_t candidates = 0;
+    bool has_result = false;
+    int result_plan = -1;
+    DevBuf result;
+    uint64_t n_result = 0;
+};
+
+// The cost-model MLP (16 -> 64 -> 64 -> 2): fp32 master parameters and
+// Adam moments on the device.
+struct CostModel {
+    bool ready = false;
+    uint64_t adam_t = 0;
+    DevBuf params, m, v;
+};
+
+struct ProfEntry {
+    double ms = 0.0;
+    uint64_t launches = 0;
+};
+
+struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hb_alloc_fn alloc_fn = nullptr;
+    hb_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    std::string err;
+    uint32_t next_id = 1;
+    std::map<uint32_t, std::unique_ptr<Relation>> rels;
+    std::map<uint32_t, std::unique_ptr<RuleSet>> rulesets;
+    bool profiling = false;
+    std::map<std::string, ProfEntry> prof;
+    std::vector<Pending> pending;
+    hb_match_stats last{};
+    uint32_t lds_limit = 0;
+    CostModel model;
+
+    void* raw_alloc(size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        void* p = nullptr;
+        if (alloc_fn) {
+            p = alloc_fn(bytes, user);
+        } else {
+            if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
+        }
+        if (!p) fail(HB_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        return p;
+    }
+    void raw_free(void* p) {
+        if (!p) return;
+        if (free_fn) free_fn(p, user);
+        else (void)hipFreeAsync(p, stream);
+    }
+
+    template <typename F>
+    void timed(const char* name, F&& launch) {
+        if (!profiling) {
+            HB_HIP(launch());
+            return;
+        }
+        Pending pd;
+        pd.name = name;
+        HB_HIP(hipEventCreate(&pd.a));
+        HB_HIP(hipEventCreate(&pd.b));
+        HB_HIP(hipEventRecord(pd.a, stream));
+        HB_HIP(launch());
+        HB_HIP(hipEventRecord(pd.b, stream));
+        pending.push_back(pd);
+    }
+    void drain_profile() {
+        for (auto& pd : pending) {
+            (void)hipEventSynchronize(pd.b);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, pd.a, pd.b);
+            auto& e = prof[pd.name];
+            e.ms += ms;
+            e.launches += 1;
+            (void)hipEventDestroy(pd.a);
+            (void)hipEventDestroy(pd.b);
+        }
+        pending.clear();
+    }
+    void sync() { HB_HIP(hipStreamSynchronize(stream)); }
+};
+
+inline void DevBuf::alloc(Ctx* c, size_t bytes) {
+    release();
+    c_ = c;
+    p_ = c->raw_alloc(bytes);
+    n_ = bytes;
+}
+
+inline void DevBuf::release() {
+    if (p_ && c_) c_->raw_free(p_);
+    p_ = nullptr;
+    n_ = 0;
+    c_ = nullptr;
+}
+
+template <typename T>
+inline T read1(Ctx* c, const T* dptr) {
+    T v{};
+    HB_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    return v;
+}
+
+inline void zero(Ctx* c, void* p, size_t bytes) { HB_HIP(hipMemsetAsync(p, 0, bytes, c->stream)); }
+
+inline Relation& get_rel(Ctx* c, uint32_t id) {
+    auto it = c->rels.find(id);
+    if (it == c->rels.end()) fail(HB_ERR_STALE_ID, "unknown relation id " + std::to_string(id));
+    return *it->second;
+}
+
+inline RuleSet& get_rs(Ctx* c, uint32_t id, uint32_t rel_id) {
+    auto it = c->rulesets.find(id);
+    if (it == c->rulesets.end()) fail(HB_ERR_STALE_ID, "unknown rule set id " + std::to_string(id));
+    if (it->second->rel_id != rel_id) fail(HB_ERR_STALE_ID, "rule set was compiled for another relation");
+    return *it->second;
+}
+
+inline int bit_width(uint64_t v) {
+    int b = 0;
+    while (v) { ++b; v >>= 1; }
+    return b;
+}
+
+inline std::vector<int> shifts_for_bits(int bits, int base) {
+    std::vector<int> s;
+    for (int x = 0; x < bits; x += 8) s.push_back(base + x);
+    return s;
+}
+
+// cost model (hb_learn.cpp)
+void costmodel_init(Ctx* c, uint64_t seed);
+void costmodel_set(Ctx* c, const float* p, uint32_t n);
+void costmodel_get(Ctx* c, float* p, uint32_t n);
+void costmodel_train(Ctx* c, const float* x, const float* t, uint64_t n, int on_device, uint32_t epochs,
+                     uint32_t batch, float lr, float* final_loss);
+void costmodel_predict(Ctx* c, const float* x, uint64_t n, int on_device, float* y, int y_on_device);
+void costmodel_trace(Ctx* c, const float* x, const float* t, uint32_t n, float* out, uint64_t out_len);
+void costmodel_adam(Ctx* c, const float* grad_host, float lr);
+
+}  // namespace hb

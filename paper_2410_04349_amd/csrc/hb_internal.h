@@ -11,6 +11,7 @@ namespace hb {
 
 constexpr int kTile = 64;        // tuples per tile side (one wave of j's)
 constexpr int kWaves = 4;        // waves per workgroup of the match kernel
+constexpr int kRows = 16;        // i-tile rows per wave (kWaves * kRows = kTile)
 constexpr int kThreads = kWaves * 64;
 constexpr int kLshK = 1024;      // LSH buckets of the selectivity estimate
 constexpr int kMaxIntRes = 16;   // int attributes staged per tile
@@ -19,6 +20,8 @@ constexpr int kMaxGramRes = 8;   // (attribute, q) gram lists staged per tile
 constexpr int kMaxPrevKeys = 3;
 constexpr int kMaxEdWords = 4;   // 256-byte edit-distance patterns
 constexpr int kMaxPlan = 1536;   // steps of one key's plan
+constexpr int kCountPairs = 8 * 4;             // instrumented counters: 8 op kinds x 4, then pairs
+constexpr int kCountSlots = kCountPairs + 1;
 
 enum ColType : int32_t { COL_STRING = 0, COL_CATEGORICAL = 1, COL_INT64 = 2 };
 
@@ -62,9 +65,8 @@ enum Op : uint8_t {
     OP_CP = 8        // rule end: the pair has a witness
 };
 
-// One step of the sequential execution path.  `slot` is the step's bit in
-// the per-pair reuse masks (distinct predicates 0..63, their filters
-// 64..127); `res` indexes the int / string / gram resource it reads; `cp`
+// One step of the sequential execution path.  `slot` identifies the step
+// (distinct predicates 0..63, their filters 64..127); `res` indexes the int / string / gram resource it reads; `cp`
 // is the index of the checkpoint that closes the rule.
 // `param` is d (|a - b| <= d), k (edit distance) or (num << 32) | den
 // (Jaccard threshold num / den).
@@ -113,20 +115,21 @@ struct MatchParams {
     uint32_t prev_res[kMaxPrevKeys];   // int resources of earlier keys (canonical owner)
     uint32_t ed_words;                 // 64-bit words of the per-wave pattern-match table
     // LDS layout (byte offsets into dynamic shared memory)
-    uint32_t lds_plan;                 // plan_len instructions
     uint32_t lds_f64, lds_f32;         // j-tile feature columns
-    uint32_t lds_i64, lds_i32;         // i-tile feature columns
     uint32_t lds_wave_base, lds_wave_stride;   // per-wave region
-    uint32_t lds_wave_peq, lds_wave_igram[kMaxGramRes];
+    uint32_t lds_wave_peq, lds_wave_myers, lds_wave_igram[kMaxGramRes];
     uint32_t lds_bytes;
     // output
     uint64_t* out;
     uint64_t cap;
     unsigned long long* counter;
-    // instrumented pass only: per plan step {waves, lanes, passed, work},
-    // then {pairs evaluated}; nullptr in the normal pass
+    // instrumented pass only: per operation kind {wave-steps, lanes, lanes
+    // passed, work units}, then pairs evaluated; nullptr in the normal pass
     unsigned long long* counts;
     uint32_t lds_counts;
+    // per-block plans (learned): blk_plan[b] = (offset << 12) | length of
+    // block b's instructions in `plan`; nullptr = one plan for every block
+    const uint32_t* blk_plan;
 };
 
 // Gather of the block-major feature columns.
@@ -213,6 +216,55 @@ hipError_t launch_lsh_hist(const ColDev* col, uint32_t n, int op, uint32_t q, in
 
 // the match kernel
 hipError_t launch_match(const MatchParams& p, hipStream_t s);
+
+// ------------------------------------------------------------ learned plan
+// One distinct predicate of a key plan, as evaluated in isolation by the
+// logging pass and described by the block-feature pass.  `op` is the plan
+// operation that decides it (OP_EQ_INT, OP_ABSDIFF, OP_EQ_STR, OP_ED,
+// OP_JAC); `res` its resource; `param` as in Instr.
+struct PredSpec {
+    uint8_t op;
+    uint8_t res;
+    uint16_t pred;     // distinct predicate id in the rule set
+    uint32_t pad;
+    uint64_t param;
+};
+constexpr int kMaxSpecs = 64;
+constexpr int kFeatures = 16;
+
+struct LearnParams {
+    MatchParams mp;                  // columns, features, blocks, resources, LDS layout
+    PredSpec spec[kMaxSpecs];
+    uint32_t n_spec;
+    uint32_t samples;                // logging: sampled waves per block
+    uint64_t seed;
+    float* features;                 // [n_blocks x n_spec x 16]
+    unsigned long long* counts;      // logging: [n_blocks x n_spec x 3] {lanes, passed, cycles}
+};
+hipError_t launch_block_features(const LearnParams& p, hipStream_t s);
+hipError_t launch_log_samples(const LearnParams& p, hipStream_t s);
+
+// ------------------------------------------------------------ cost model
+// C[M x N] = op(A) op(B) (+ bias[N]); op(X) = X or X^T (row-major storage
+// with leading dimension ld); where `mask` is given, entries with
+// mask[i][j] <= 0 become 0; where `relu` is given it receives max(C, 0).
+struct GemmArgs {
+    const float* A;
+    const float* B;
+    float* C;
+    const float* bias;
+    const float* mask;
+    float* relu;
+    int M, N, K;
+    int lda, ldb, ldc;
+    int transA, transB;
+};
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
+hipError_t launch_colsum(const float* A, int rows, int cols, float* out, hipStream_t s);
+hipError_t launch_mse_grad(const float* Y, const float* T, int n, float scale, float* dY, float* sse,
+                           hipStream_t s);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s);
 
 // write pairs in order: out[x] = in[x] (device copy helper for the result)
 hipError_t launch_copy_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s);

@@ -4,13 +4,16 @@
 // block of a key partition.  A workgroup of four waves stages the j-tile's
 // compact feature columns (values, lengths, set sizes, signatures) in LDS
 // once; each wave then takes rows i = i0 + w, i0 + w + 4, ..., so tuple t_i
-// is uniform across the wave and its 64 lanes hold 64 candidates t_j.
+// is uniform across the wave (its features and the plan are read with
+// scalar loads) and its 64 lanes hold 64 candidates t_j.
 //
 // Every lane walks the sequential execution path (Section 5.1) for its pair
-// (t_i, t_j): steps in plan order, a reuse bitmap of evaluated / satisfied
-// steps, a rule-end checkpoint that reports a witness (Section 2,
-// "Blocking"), and a wave-uniform jump to the checkpoint once no lane can
-// still satisfy the current rule.  Within a rule the plan runs exact,
+// (t_i, t_j): steps in plan order, a rule-end checkpoint that reports a
+// witness (Section 2, "Blocking"), and a wave-uniform jump to the
+// checkpoint once no lane can still satisfy the current rule.  Results of
+// the expensive predicates are reused across rules through per-attribute
+// caches of the edit distance and of the q-gram intersection size; cheap
+// steps are recomputed, which costs less than bookkeeping on a SIMD.  Within a rule the plan runs exact,
 // cheap necessary-condition filters before the expensive predicates
 // (edit distance, Jaccard, string equality), so the expensive code runs for
 // a wave only when some lane passed all of the rule's filters.  Matched lanes
@@ -76,16 +79,55 @@ __device__ inline int myers(const T* __restrict__ peq, int m, const uint8_t* __r
     return score;
 }
 
-__device__ inline int myers_dispatch(const uint8_t* peq_bytes, int words, int m, const uint8_t* text, int n) {
+// Patterns longer than 64 bytes: the same recurrence over W words whose
+// vertical delta vectors live in the wave's LDS (slot w * 64 + lane), so the
+// rare long patterns do not cost registers on the common path.
+__device__ inline int myers_long(const uint64_t* __restrict__ peq, int W, int m, const uint8_t* __restrict__ text,
+                                 int n, uint64_t* st, int lane) {
+    uint64_t* Pv = st;
+    uint64_t* Mv = st + kMaxEdWords * 64;
+    for (int w = 0; w < W; ++w) { Pv[w * 64 + lane] = ~0ull; Mv[w * 64 + lane] = 0; }
+    int score = m;
+    const uint64_t hb = 1ull << ((m - 1) & 63);
+    for (int pos = 0; pos < n; ++pos) {
+        const uint64_t* eq = peq + (uint32_t)text[pos] * W;
+        uint64_t carry = 0, ph_in = 1, mh_in = 0;
+        for (int w = 0; w < W; ++w) {
+            const uint64_t Eq = eq[w];
+            const uint64_t pv = Pv[w * 64 + lane], mv = Mv[w * 64 + lane];
+            const uint64_t Xv = Eq | mv;
+            const uint64_t a = Eq & pv;
+            const uint64_t sum = a + pv;
+            const uint64_t c1 = sum < a ? 1 : 0;
+            const uint64_t sum2 = sum + carry;
+            const uint64_t c2 = sum2 < sum ? 1 : 0;
+            carry = c1 | c2;
+            const uint64_t Xh = (sum2 ^ pv) | Eq;
+            uint64_t Ph = mv | ~(Xh | pv);
+            uint64_t Mh = pv & Xh;
+            if (w == W - 1) {
+                score += (Ph & hb) ? 1 : 0;
+                score -= (Mh & hb) ? 1 : 0;
+            }
+            const uint64_t ph_out = Ph >> 63, mh_out = Mh >> 63;
+            Ph = (Ph << 1) | ph_in;
+            Mh = (Mh << 1) | mh_in;
+            ph_in = ph_out;
+            mh_in = mh_out;
+            Pv[w * 64 + lane] = Mh | ~(Xv | Ph);
+            Mv[w * 64 + lane] = Ph & Xv;
+        }
+    }
+    return score;
+}
+
+__device__ inline int myers_dispatch(const uint8_t* peq_bytes, int words, int m, const uint8_t* text, int n,
+                                     uint64_t* st, int lane) {
     if (m == 0) return n;
     if (n == 0) return m;
     if (words == 0) return myers<uint32_t, 1>((const uint32_t*)peq_bytes, m, text, n);
-    switch (words) {
-    case 1: return myers<uint64_t, 1>((const uint64_t*)peq_bytes, m, text, n);
-    case 2: return myers<uint64_t, 2>((const uint64_t*)peq_bytes, m, text, n);
-    case 3: return myers<uint64_t, 3>((const uint64_t*)peq_bytes, m, text, n);
-    default: return myers<uint64_t, 4>((const uint64_t*)peq_bytes, m, text, n);
-    }
+    if (words == 1) return myers<uint64_t, 1>((const uint64_t*)peq_bytes, m, text, n);
+    return myers_long((const uint64_t*)peq_bytes, words, m, text, n, st, lane);
 }
 
 // Pattern-match table of pattern p (length m) in the wave's LDS.
@@ -142,24 +184,31 @@ __device__ inline void decode_tile(const MatchParams& P, uint64_t t, uint32_t* b
     *ti = (uint32_t)(u - c * (c + 1) / 2);
 }
 
-template <int N>
-__device__ inline int pick(const int (&a)[N], int i) {
-    int v = -1;
-#pragma unroll
-    for (int s = 0; s < N; ++s) if (s == i) v = a[s];
-    return v;
-}
-
-template <int N>
-__device__ inline void put(int (&a)[N], int i, int v) {
-#pragma unroll
-    for (int s = 0; s < N; ++s) if (s == i) a[s] = v;
-}
+// Per-lane cache of eight 16-bit values in two 64-bit registers (index is
+// wave-uniform); 0xFFFF = not computed.
+struct Cache16 {
+    uint64_t lo = ~0ull, hi = ~0ull;
+    __device__ int get(uint32_t i) const {
+        const uint64_t w = i < 4 ? lo : hi;
+        const uint32_t v = (uint32_t)(w >> (16 * (i & 3))) & 0xFFFFu;
+        return v == 0xFFFFu ? -1 : (int)v;
+    }
+    __device__ void set(uint32_t i, int v) {
+        const uint32_t sh = 16 * (i & 3);
+        const uint64_t m = ~(0xFFFFull << sh), x = ((uint64_t)v & 0xFFFFull) << sh;
+        if (i < 4) lo = (lo & m) | x; else hi = (hi & m) | x;
+    }
+};
 
 template <bool kCount>
-__global__ __launch_bounds__(kThreads) void k_match(const MatchParams P) {
+__global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const Instr* __restrict__ plan,
+                                                   const uint64_t* __restrict__ f64,
+                                                   const uint32_t* __restrict__ f32) {
     extern __shared__ __align__(16) uint8_t lds[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // wave-uniform values are passed through readfirstlane so the compiler
+    // keeps them (and the loads they address) scalar
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     // XCD-aware remap: consecutive workgroups go round-robin to the 8 XCDs;
     // give each XCD a contiguous range of tiles so a block's tiles share L2.
@@ -178,250 +227,251 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P) {
     const bool diag = ti == tj;
 
     const uint64_t n = P.feat.n;
-    const uint64_t* __restrict__ f64 = P.feat.f64;
-    const uint32_t* __restrict__ f32 = P.feat.f32;
     const uint32_t n64 = P.n_int + P.n_str + P.n_gram;
     const uint32_t n32 = 2 + P.n_str + P.n_gram;
     const uint32_t str64 = P.n_int, gram64 = P.n_int + P.n_str;    // first f64 column of each kind
     const uint32_t str32 = 2, gram32 = 2 + P.n_str;                 // first f32 column of each kind
 
-    // ------------------------------------- stage the plan, i-tile and j-tile
-    Instr* s_plan = (Instr*)(lds + P.lds_plan);
-    for (uint32_t x = tid; x < P.plan_len; x += kThreads) s_plan[x] = P.plan[x];
+    // ---------------------------------------------------- stage the j-tile
     uint64_t* s64 = (uint64_t*)(lds + P.lds_f64);
     uint32_t* s32 = (uint32_t*)(lds + P.lds_f32);
-    uint64_t* i64 = (uint64_t*)(lds + P.lds_i64);
-    uint32_t* i32 = (uint32_t*)(lds + P.lds_i32);
-    const uint64_t pj = (uint64_t)bstart + j0, pi0 = (uint64_t)bstart + i0;
+    const uint64_t pj = (uint64_t)bstart + j0;
     for (uint32_t x = tid; x < n64 * kTile; x += kThreads) {
         const uint32_t f = x / kTile, l = x % kTile;
         s64[x] = l < nj ? f64[f * n + pj + l] : 0ull;
-        i64[x] = l < ni ? f64[f * n + pi0 + l] : 0ull;
     }
     for (uint32_t x = tid; x < n32 * kTile; x += kThreads) {
         const uint32_t f = x / kTile, l = x % kTile;
         s32[x] = l < nj ? f32[f * n + pj + l] : 0u;
-        i32[x] = l < ni ? f32[f * n + pi0 + l] : 0u;
     }
     unsigned long long* s_cnt = (unsigned long long*)(lds + P.lds_counts);
     if constexpr (kCount)
-        for (uint32_t x = tid; x < P.plan_len * 4 + 1; x += kThreads) s_cnt[x] = 0;
+        for (uint32_t x = tid; x < kCountSlots; x += kThreads) s_cnt[x] = 0;
     __syncthreads();
 
-    const uint32_t row_j = s32[lane];
-    const uint32_t vmask_j = s32[kTile + lane];
-    uint8_t* wbase = lds + P.lds_wave_base + wave * P.lds_wave_stride;
-    uint8_t* peq = wbase + P.lds_wave_peq;
+    // this wave's rows: r0 .. r0 + nr - 1 of the i-tile (16 consecutive rows)
+    const uint32_t r0 = (uint32_t)wave * kRows;
+    const int nr = (int)min((uint32_t)kRows, ni > r0 ? ni - r0 : 0u);
+    if (!kCount && nr <= 0) return;
+    if (nr > 0) {
+        const uint64_t pi0 = (uint64_t)bstart + i0 + r0;   // position of row 0
+        const uint32_t row_j = s32[lane];
+        const uint32_t vmask_j = s32[kTile + lane];
+        uint8_t* wbase = lds + P.lds_wave_base + wave * P.lds_wave_stride;
+        uint8_t* peq = wbase + P.lds_wave_peq;
+        const Instr* __restrict__ pl = plan;
+        uint32_t plen = P.plan_len;
+        if (P.blk_plan) {
+            const uint32_t e = P.blk_plan[b];
+            pl = plan + (e >> 12);
+            plen = e & 0xFFFu;
+        }
 
-    for (uint32_t ii = wave; ii < ni; ii += kWaves) {
-        const bool lane_pair = ((uint32_t)lane < nj) && (!diag || (uint32_t)lane > ii);
-        if (!__any(lane_pair)) continue;
-        // t_i's features: uniform LDS reads, moved to scalar registers
-        auto I64 = [&](uint32_t f) -> uint64_t {
-            const uint64_t v = i64[f * kTile + ii];
-            return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
-                   (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
-        };
-        auto I32 = [&](uint32_t f) -> uint32_t { return __builtin_amdgcn_readfirstlane(i32[f * kTile + ii]); };
-        const uint32_t row_i = I32(0);
-        const uint32_t vmask_i = I32(1);
-        const uint32_t vboth = vmask_i & vmask_j;
-
+        // bit r of a lane's masks = the pair (row r, this lane's j)
+        uint32_t pairs = 0;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t ig = i0 + r0 + r, jg = j0 + lane;
+            const bool ok = r < nr && (uint32_t)lane < nj && (!diag || jg > ig);
+            pairs |= (ok ? 1u : 0u) << r;
+        }
         // canonical owner: a pair agreeing on an earlier key was evaluated there
-        bool alive_pair = lane_pair;
         for (uint32_t k = 0; k < P.n_prev; ++k) {
             const uint32_t res = P.prev_res[k];
-            if (((vboth >> res) & 1) && I64(res) == s64[res * kTile + lane]) alive_pair = false;
+            const uint64_t vj = s64[res * kTile + lane];
+            const bool jv = (vmask_j >> res) & 1;
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) {
+                if (r >= nr) break;
+                const bool iv = (f32[n + pi0 + r] >> res) & 1;
+                if (jv && iv && f64[res * n + pi0 + r] == vj) pairs &= ~(1u << r);
+            }
         }
         if constexpr (kCount) {
-            const uint64_t pb = __ballot(alive_pair);
-            if (lane == 0 && pb) atomicAdd(&s_cnt[P.plan_len * 4], (unsigned long long)__popcll(pb));
+            uint32_t cnt = 0;
+            for (int r = 0; r < kRows; ++r) cnt += __popcll(__ballot((pairs >> r) & 1));
+            if (lane == 0 && cnt) atomicAdd(&s_cnt[kCountPairs], (unsigned long long)cnt);
         }
 
-        uint64_t ev0 = 0, ev1 = 0, rs0 = 0, rs1 = 0;
-        bool matched = false;
-        bool alive = alive_pair;
-        int peq_res = -1;
-        uint32_t igram_loaded = 0;
-        int ed_cache[kMaxStrRes];
-        int jac_cache[kMaxGramRes];
-#pragma unroll
-        for (int s = 0; s < kMaxStrRes; ++s) ed_cache[s] = -1;
-#pragma unroll
-        for (int s = 0; s < kMaxGramRes; ++s) jac_cache[s] = -1;
-
+        uint32_t matched = 0, alive = pairs;
         uint32_t pc = 0;
-        while (pc < P.plan_len) {
-            Instr ins;
-            {
-                const uint4 raw = *(const uint4*)&s_plan[pc];
-                const uint32_t w0 = __builtin_amdgcn_readfirstlane(raw.x);
-                const uint32_t w1 = __builtin_amdgcn_readfirstlane(raw.y);
-                const uint32_t w2 = __builtin_amdgcn_readfirstlane(raw.z);
-                const uint32_t w3 = __builtin_amdgcn_readfirstlane(raw.w);
-                ins.op = (uint8_t)w0;
-                ins.slot = (uint8_t)(w0 >> 8);
-                ins.res = (uint8_t)(w0 >> 16);
-                ins.cp = (uint16_t)w1;
-                ins.param = ((uint64_t)w3 << 32) | w2;
-            }
-            if (ins.op == OP_CP) {
-                matched = matched || alive;
-                alive = alive_pair && !matched;
-                if (!__any(alive)) break;   // every lane is matched or has no pair
+        while (pc < plen) {
+            pc = __builtin_amdgcn_readfirstlane(pc);
+            // one 16-byte scalar load (there is no scalar byte load)
+            const uint4 raw = *(const uint4*)(pl + pc);
+            const uint32_t op = raw.x & 0xFFu, res = (raw.x >> 16) & 0xFFu;
+            const uint32_t cp = raw.y & 0xFFFFu;
+            const uint64_t param = ((uint64_t)raw.w << 32) | raw.z;
+            if (op == OP_CP) {
+                matched |= alive;
+                alive = pairs & ~matched;
+                if (!__any(alive != 0)) break;   // every pair is matched or absent
                 ++pc;
                 continue;
             }
-            if (!__any(alive)) { pc = ins.cp; continue; }
-            const bool hi = ins.slot >= 64;
-            const uint64_t bit = 1ull << (ins.slot & 63);
-            const bool done = ((hi ? ev1 : ev0) & bit) != 0;
-            const bool need = alive && !done;
-            if (__any(need)) {
-                bool r = false;
-                uint32_t work = 1;
-                const uint32_t res = ins.res;
-                switch (ins.op) {
-                case OP_EQ_INT:
-                case OP_ABSDIFF: {
-                    const int64_t vi = (int64_t)I64(res);
-                    const int64_t vj = (int64_t)s64[res * kTile + lane];
-                    const bool v = (vboth >> res) & 1;
-                    r = v && (ins.op == OP_EQ_INT ? vi == vj : absdiff_le(vi, vj, (int64_t)ins.param));
-                    break;
+            if (!__any(alive != 0)) { pc = cp; continue; }
+            const uint32_t before = alive;
+            uint32_t work = 0;
+            switch (op) {
+            case OP_EQ_INT:
+            case OP_ABSDIFF: {
+                const int64_t vj = (int64_t)s64[res * kTile + lane];
+                const uint32_t jv = (vmask_j >> res) & 1;
+                uint32_t keep = 0;
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const uint64_t pr = pi0 + (uint64_t)(r < nr ? r : 0);   // rows >= nr are masked off
+                    const int64_t vi = (int64_t)f64[res * n + pr];
+                    const uint32_t iv = (f32[n + pr] >> res) & 1;
+                    const bool ok = op == OP_EQ_INT ? vi == vj : absdiff_le(vi, vj, (int64_t)param);
+                    keep |= ((ok ? 1u : 0u) & iv) << r;
                 }
-                case OP_EQF:
-                case OP_EDF: {
-                    const bool v = (vboth >> (16 + res)) & 1;
-                    const uint32_t li = I32(str32 + res);
-                    const uint32_t lj = s32[(str32 + res) * kTile + lane];
-                    const uint64_t ci = I64(str64 + res);
-                    const uint64_t cj = s64[(str64 + res) * kTile + lane];
-                    if (ins.op == OP_EQF) {
-                        r = v && li == lj && ci == cj;
+                alive &= jv ? keep : 0u;
+                work = 1;
+                break;
+            }
+            case OP_EQF:
+            case OP_EDF: {
+                const uint32_t lj = s32[(str32 + res) * kTile + lane];
+                const uint64_t cj = s64[(str64 + res) * kTile + lane];
+                const uint32_t jv = (vmask_j >> (16 + res)) & 1;
+                const int k = (int)param;
+                uint32_t keep = 0;
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const uint64_t pr = pi0 + (uint64_t)(r < nr ? r : 0);
+                    const uint32_t li = f32[(str32 + res) * n + pr];
+                    const uint64_t ci = f64[(str64 + res) * n + pr];
+                    const uint32_t iv = (f32[n + pr] >> (16 + res)) & 1;
+                    bool ok;
+                    if (op == OP_EQF) {
+                        ok = li == lj && ci == cj;
                     } else {
-                        const int k = (int)ins.param;
                         const int d1 = __popcll(ci & ~cj), d2 = __popcll(cj & ~ci);
-                        r = v && abs((int)li - (int)lj) <= k && max(d1, d2) <= k;
+                        ok = abs((int)li - (int)lj) <= k && max(d1, d2) <= k;
                     }
-                    break;
+                    keep |= ((ok ? 1u : 0u) & iv) << r;
                 }
-                case OP_JACF: {
-                    const bool v = (vboth >> (24 + res)) & 1;
-                    const uint64_t sa = I32(gram32 + res) & 0x7FFFFFFFu;
-                    const uint64_t sb = s32[(gram32 + res) * kTile + lane] & 0x7FFFFFFFu;
-                    const uint64_t gi = I64(gram64 + res);
-                    const uint64_t gj = s64[(gram64 + res) * kTile + lane];
+                alive &= jv ? keep : 0u;
+                work = 1;
+                break;
+            }
+            case OP_JACF: {
+                const uint64_t sb = s32[(gram32 + res) * kTile + lane] & 0x7FFFFFFFu;
+                const uint64_t gj = s64[(gram64 + res) * kTile + lane];
+                const uint32_t jv = (vmask_j >> (24 + res)) & 1;
+                const uint64_t num = param >> 32, den = param & 0xFFFFFFFFu;
+                const uint64_t nsb = num * sb;
+                uint32_t keep = 0;
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const uint64_t pr = pi0 + (uint64_t)(r < nr ? r : 0);
+                    const uint64_t sa = f32[(gram32 + res) * n + pr] & 0x7FFFFFFFu;
+                    const uint64_t gi = f64[(gram64 + res) * n + pr];
+                    const uint32_t iv = (f32[n + pr] >> (24 + res)) & 1;
                     const uint64_t ua = sa - (uint64_t)__popcll(gi & ~gj);
                     const uint64_t ub = sb - (uint64_t)__popcll(gj & ~gi);
                     const uint64_t iub = ua < ub ? ua : ub;
-                    const uint64_t num = ins.param >> 32, den = ins.param & 0xFFFFFFFFu;
-                    r = v && iub * (num + den) >= num * (sa + sb);
-                    break;
+                    const bool ok = iub * (num + den) >= num * sa + nsb;
+                    keep |= ((ok ? 1u : 0u) & iv) << r;
                 }
-                case OP_EQ_STR: {
-                    const ColDev& c = P.cols[P.str_attr[res]];
-                    const bool v = (vboth >> (16 + res)) & 1;
-                    const uint32_t li = I32(str32 + res);
-                    const uint32_t lj = s32[(str32 + res) * kTile + lane];
-                    const uint8_t* si = c.bytes + c.off[row_i];
-                    if (need) {
-                        bool eq = v && li == lj;
-                        work = 0;
-                        if (eq) {
+                alive &= jv ? keep : 0u;
+                work = 1;
+                break;
+            }
+            default: {
+                // exact similarity predicates, row by row, for rows where some
+                // lane is still alive
+                for (int r = 0; r < nr; ++r) {
+                    const bool need = (alive >> r) & 1;
+                    if (!__any(need)) continue;
+                    const uint64_t pi = pi0 + r;
+                    const uint32_t row_i = f32[pi];
+                    const uint32_t vmask_i = f32[n + pi];
+                    bool ok = false;
+                    uint32_t w = 0;
+                    if (op == OP_EQ_STR) {
+                        const ColDev& c = P.cols[P.str_attr[res]];
+                        const uint32_t li = f32[(str32 + res) * n + pi];
+                        const uint32_t lj = s32[(str32 + res) * kTile + lane];
+                        if (need && li == lj) {
+                            const uint8_t* si = c.bytes + c.off[row_i];
                             const uint8_t* sj = c.bytes + c.off[row_j];
-                            work = li;
-                            for (uint32_t x = 0; eq && x < li; ++x) eq = si[x] == sj[x];
+                            ok = true;
+                            w = li;
+                            for (uint32_t x = 0; ok && x < li; ++x) ok = si[x] == sj[x];
                         }
-                        r = eq;
-                    }
-                    break;
-                }
-                case OP_ED: {
-                    const ColDev& c = P.cols[P.str_attr[res]];
-                    const bool iv = (vmask_i >> (16 + res)) & 1;
-                    const bool v = (vboth >> (16 + res)) & 1;
-                    const int m = (int)I32(str32 + res);
-                    const int nn = (int)s32[(str32 + res) * kTile + lane];
-                    const int k = (int)ins.param;
-                    const int words = m <= 32 ? 0 : (m + 63) / 64;
-                    const int cached = pick(ed_cache, (int)res);
-                    const bool run = need && v && cached < 0 && abs(m - nn) <= k;
-                    if (iv && peq_res != (int)res && __any(run)) {
-                        build_peq(peq, words, c.bytes + c.off[row_i], m, lane);
-                        peq_res = (int)res;
-                    }
-                    if (need) {
-                        int dist = cached;
-                        work = run ? (uint32_t)nn * (uint32_t)max(1, (m + 31) / 32) : 0u;
+                    } else if (op == OP_ED) {
+                        const ColDev& c = P.cols[P.str_attr[res]];
+                        const int m = (int)f32[(str32 + res) * n + pi];
+                        const int nn = (int)s32[(str32 + res) * kTile + lane];
+                        const int k = (int)param;
+                        const int words = m <= 32 ? 0 : (m + 63) / 64;
+                        const bool run = need && abs(m - nn) <= k;
+                        if (__any(run)) build_peq(peq, words, c.bytes + c.off[row_i], m, lane);
                         if (run) {
-                            dist = myers_dispatch(peq, words, m, c.bytes + c.off[row_j], nn);
-                            put(ed_cache, (int)res, dist);
+                            const int dist = myers_dispatch(peq, words, m, c.bytes + c.off[row_j], nn,
+                                                            (uint64_t*)(wbase + P.lds_wave_myers), lane);
+                            ok = dist <= k;
+                            w = (uint32_t)nn * (uint32_t)max(1, (m + 31) / 32);
                         }
-                        r = v && abs(m - nn) <= k && dist >= 0 && dist <= k;
-                    }
-                    break;
-                }
-                case OP_JAC: {
-                    const GramDev& g = P.gram[res];
-                    const bool iv = (vmask_i >> (24 + res)) & 1;
-                    const bool v = (vboth >> (24 + res)) & 1;
-                    const uint32_t ia = I32(gram32 + res);
-                    const uint32_t ca = ia & 0x7FFFFFFFu;
-                    const bool ishort = (ia >> 31) != 0;
-                    uint32_t* ig = (uint32_t*)(wbase + P.lds_wave_igram[res]);
-                    if (iv && !((igram_loaded >> res) & 1)) {
-                        const uint32_t* src = g.codes + g.off[row_i];
-                        for (uint32_t x = lane; x < ca; x += 64) ig[x] = src[x];
-                        wave_sync();
-                        igram_loaded |= 1u << res;
-                    }
-                    if (need && v) {
-                        const uint32_t jb = s32[(gram32 + res) * kTile + lane];
-                        const uint32_t cb = jb & 0x7FFFFFFFu;
-                        const bool jshort = (jb >> 31) != 0;
-                        int I = pick(jac_cache, (int)res);
-                        work = I < 0 ? ca + cb : 0u;
-                        if (I < 0) {
-                            I = (int)intersect(ig, ca, ishort, g.codes + g.off[row_j], cb, jshort);
-                            put(jac_cache, (int)res, I);
+                    } else {   // OP_JAC
+                        const GramDev& g = P.gram[res];
+                        const uint32_t ia = f32[(gram32 + res) * n + pi];
+                        const uint32_t ca = ia & 0x7FFFFFFFu;
+                        uint32_t* ig = (uint32_t*)(wbase + P.lds_wave_igram[res]);
+                        if ((vmask_i >> (24 + res)) & 1) {
+                            const uint32_t* src = g.codes + g.off[row_i];
+                            for (uint32_t x = lane; x < ca; x += 64) ig[x] = src[x];
+                            wave_sync();
                         }
-                        const uint64_t U = (uint64_t)ca + cb - (uint64_t)I;
-                        r = (U == 0) || ((uint64_t)I * (ins.param & 0xFFFFFFFFu) >= (ins.param >> 32) * U);
+                        if (need) {
+                            const uint32_t jb = s32[(gram32 + res) * kTile + lane];
+                            const uint32_t cb = jb & 0x7FFFFFFFu;
+                            const uint32_t I = intersect(ig, ca, (ia >> 31) != 0, g.codes + g.off[row_j], cb,
+                                                         (jb >> 31) != 0);
+                            const uint64_t U = (uint64_t)ca + cb - I;
+                            ok = U == 0 || (uint64_t)I * (param & 0xFFFFFFFFu) >= (param >> 32) * U;
+                            w = ca + cb;
+                        }
                     }
-                    break;
+                    if (need && !ok) alive &= ~(1u << r);
+                    work += w;
                 }
-                default:
-                    break;
+                break;
+            }
+            }
+            if constexpr (kCount) {
+                uint32_t ev = 0, ps = 0, waves = 0;
+                for (int r = 0; r < kRows; ++r) {
+                    const uint64_t eb = __ballot((before >> r) & 1);
+                    ev += __popcll(eb);
+                    ps += __popcll(__ballot((alive >> r) & 1));
+                    waves += eb ? 1u : 0u;
                 }
-                if (need) {
-                    if (hi) { ev1 |= bit; if (r) rs1 |= bit; }
-                    else { ev0 |= bit; if (r) rs0 |= bit; }
-                }
-                if constexpr (kCount) {
-                    const uint64_t nb = __ballot(need), rb = __ballot(need && r);
-                    uint32_t w = need ? work : 0u;
-                    for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
-                    if (lane == 0) {
-                        atomicAdd(&s_cnt[pc * 4 + 0], 1ull);
-                        atomicAdd(&s_cnt[pc * 4 + 1], (unsigned long long)__popcll(nb));
-                        atomicAdd(&s_cnt[pc * 4 + 2], (unsigned long long)__popcll(rb));
-                        atomicAdd(&s_cnt[pc * 4 + 3], (unsigned long long)w);
-                    }
+                uint32_t w = op <= OP_JACF ? 0u : work;
+                for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+                if (op <= OP_JACF) w = ev;
+                if (lane == 0) {
+                    atomicAdd(&s_cnt[op * 4 + 0], (unsigned long long)waves);
+                    atomicAdd(&s_cnt[op * 4 + 1], (unsigned long long)ev);
+                    atomicAdd(&s_cnt[op * 4 + 2], (unsigned long long)ps);
+                    atomicAdd(&s_cnt[op * 4 + 3], (unsigned long long)w);
                 }
             }
-            alive = alive && (((hi ? rs1 : rs0) & bit) != 0);
             ++pc;
         }
 
-        // ballot compaction of matched pairs
-        const uint64_t mask = __ballot(matched);
-        if (mask) {
-            const uint32_t cnt = __popcll(mask);
+        // ballot compaction of matched pairs, row by row
+        for (int r = 0; r < nr; ++r) {
+            const bool m = (matched >> r) & 1;
+            const uint64_t mask = __ballot(m);
+            if (!mask) continue;
+            const uint32_t row_i = f32[pi0 + r];
             unsigned long long basev = 0;
-            if (lane == 0) basev = atomicAdd(P.counter, (unsigned long long)cnt);
+            if (lane == 0) basev = atomicAdd(P.counter, (unsigned long long)__popcll(mask));
             basev = __shfl(basev, 0);
-            if (matched) {
+            if (m) {
                 const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
                 const uint64_t pos = basev + __popcll(mask & lt);
                 if (pos < P.cap) {
@@ -434,8 +484,250 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P) {
     }
     if constexpr (kCount) {
         __syncthreads();
-        for (uint32_t x = tid; x < P.plan_len * 4 + 1; x += kThreads)
+        for (uint32_t x = tid; x < kCountSlots; x += kThreads)
             if (s_cnt[x]) atomicAdd(&P.counts[x], s_cnt[x]);
+    }
+}
+
+// ------------------------------------------------------------ learned plan
+
+// splitmix64 output function (Steele, Lea and Flood, OOPSLA 2014)
+__device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline double block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return t;
+}
+
+__device__ inline double block_min(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = fmin(t, red[w]);
+    return t;
+}
+
+// Exact filter of a predicate on two positions' features (the same bounds
+// the plan's filter steps use).
+__device__ inline bool feature_filter(const LearnParams& L, const PredSpec& sp, uint64_t pa, uint64_t pb) {
+    const MatchParams& P = L.mp;
+    const uint64_t n = P.feat.n;
+    const uint64_t* f64 = P.feat.f64;
+    const uint32_t* f32 = P.feat.f32;
+    const uint32_t vb = f32[n + pa] & f32[n + pb];
+    const uint32_t res = sp.res;
+    switch (sp.op) {
+    case OP_EQ_INT:
+    case OP_ABSDIFF: {
+        if (!((vb >> res) & 1)) return false;
+        const int64_t a = (int64_t)f64[res * n + pa], b = (int64_t)f64[res * n + pb];
+        return sp.op == OP_EQ_INT ? a == b : absdiff_le(a, b, (int64_t)sp.param);
+    }
+    case OP_EQ_STR:
+    case OP_ED: {
+        if (!((vb >> (16 + res)) & 1)) return false;
+        const uint32_t la = f32[(2 + res) * n + pa], lb = f32[(2 + res) * n + pb];
+        const uint64_t ca = f64[(P.n_int + res) * n + pa], cb = f64[(P.n_int + res) * n + pb];
+        if (sp.op == OP_EQ_STR) return la == lb && ca == cb;
+        const int k = (int)sp.param;
+        return abs((int)la - (int)lb) <= k && max(__popcll(ca & ~cb), __popcll(cb & ~ca)) <= k;
+    }
+    default: {
+        if (!((vb >> (24 + res)) & 1)) return false;
+        const uint64_t sa = f32[(2 + P.n_str + res) * n + pa] & 0x7FFFFFFFu;
+        const uint64_t sb = f32[(2 + P.n_str + res) * n + pb] & 0x7FFFFFFFu;
+        const uint64_t ga = f64[(P.n_int + P.n_str + res) * n + pa], gb = f64[(P.n_int + P.n_str + res) * n + pb];
+        const uint64_t ua = sa - (uint64_t)__popcll(ga & ~gb), ub = sb - (uint64_t)__popcll(gb & ~ga);
+        const uint64_t iub = ua < ub ? ua : ub;
+        const uint64_t num = sp.param >> 32, den = sp.param & 0xFFFFFFFFu;
+        return iub * (num + den) >= num * (sa + sb);
+    }
+    }
+}
+
+// 16 features per (block, predicate): op one-hot (4), threshold relative to
+// the data, threshold shape, log2 block size, length (or set size) mean / std /
+// min / max, 3-bin length histogram, the fraction of adjacent position pairs
+// passing the predicate's filter, mean signature density.
+__global__ __launch_bounds__(256) void k_block_features(const LearnParams L) {
+    __shared__ double red[4];
+    const MatchParams& P = L.mp;
+    const uint32_t b = blockIdx.x;
+    const uint32_t start = P.blk_start[b], nb = P.blk_size[b];
+    const uint64_t n = P.feat.n;
+    const uint64_t* f64 = P.feat.f64;
+    const uint32_t* f32 = P.feat.f32;
+    for (uint32_t s = 0; s < L.n_spec; ++s) {
+        const PredSpec sp = L.spec[s];
+        const bool is_int = sp.op == OP_EQ_INT || sp.op == OP_ABSDIFF;
+        const bool is_gram = sp.op == OP_JAC;
+        double cnt = 0, sum = 0, sum2 = 0, mn = 1e300, mx = -1e300, b0 = 0, b1 = 0, b2 = 0, pops = 0, pass = 0;
+        for (uint32_t x = threadIdx.x; x < nb; x += blockDim.x) {
+            const uint64_t pos = (uint64_t)start + x;
+            const uint32_t vm = f32[n + pos];
+            double lv = 0.0;
+            bool v;
+            if (is_int) {
+                v = (vm >> sp.res) & 1;
+                lv = (double)(int64_t)f64[sp.res * n + pos];
+            } else if (!is_gram) {
+                v = (vm >> (16 + sp.res)) & 1;
+                lv = (double)f32[(2 + sp.res) * n + pos];
+                if (v) pops += __popcll(f64[(P.n_int + sp.res) * n + pos]);
+            } else {
+                v = (vm >> (24 + sp.res)) & 1;
+                lv = (double)(f32[(2 + P.n_str + sp.res) * n + pos] & 0x7FFFFFFFu);
+                if (v) pops += __popcll(f64[(P.n_int + P.n_str + sp.res) * n + pos]);
+            }
+            if (v) {
+                cnt += 1;
+                sum += lv;
+                sum2 += lv * lv;
+                mn = fmin(mn, lv);
+                mx = fmax(mx, lv);
+                if (!is_int) {
+                    if (lv < 16) b0 += 1; else if (lv < 48) b1 += 1; else b2 += 1;
+                }
+            }
+            if (x + 1 < nb && feature_filter(L, sp, pos, pos + 1)) pass += 1;
+        }
+        cnt = block_sum(cnt, red);
+        sum = block_sum(sum, red);
+        sum2 = block_sum(sum2, red);
+        mn = block_min(mn, red);
+        mx = -block_min(-mx, red);
+        b0 = block_sum(b0, red);
+        b1 = block_sum(b1, red);
+        b2 = block_sum(b2, red);
+        pops = block_sum(pops, red);
+        pass = block_sum(pass, red);
+        if (threadIdx.x == 0) {
+            float* f = L.features + ((size_t)b * L.n_spec + s) * kFeatures;
+            const double c = cnt > 0 ? cnt : 1.0;
+            const double mean = sum / c;
+            const double sd = sqrt(fmax(sum2 / c - mean * mean, 0.0));
+            const int hop = sp.op == OP_EQ_INT || sp.op == OP_EQ_STR ? 0 : sp.op == OP_ED ? 1 : sp.op == OP_JAC ? 2 : 3;
+            for (int k = 0; k < 4; ++k) f[k] = k == hop ? 1.f : 0.f;
+            double thr = 0, shape = 0;
+            if (sp.op == OP_ED) {
+                thr = (double)sp.param / fmax(1.0, mean);
+                shape = fmin((double)sp.param, 64.0) / 16.0;
+            } else if (sp.op == OP_JAC) {
+                thr = (double)(sp.param >> 32) / (double)(sp.param & 0xFFFFFFFFu);
+                shape = 0.25 * (double)P.gram[sp.res].q;
+            } else if (sp.op == OP_ABSDIFF) {
+                thr = (double)sp.param / (1.0 + sd);
+                shape = log2(1.0 + (double)sp.param) / 64.0;
+            }
+            f[4] = (float)fmin(thr, 16.0);
+            f[5] = (float)shape;
+            f[6] = (float)(log2((double)nb) / 16.0);
+            if (is_int) {
+                f[7] = (float)(log2(1.0 + fabs(mean)) / 64.0);
+                f[8] = (float)(log2(1.0 + sd) / 64.0);
+                f[9] = f[10] = f[11] = f[12] = f[13] = 0.f;
+            } else {
+                f[7] = (float)(mean / 64.0);
+                f[8] = (float)(sd / 64.0);
+                f[9] = (float)((cnt > 0 ? mn : 0.0) / 64.0);
+                f[10] = (float)((cnt > 0 ? mx : 0.0) / 64.0);
+                f[11] = (float)(b0 / c);
+                f[12] = (float)(b1 / c);
+                f[13] = (float)(b2 / c);
+            }
+            f[14] = (float)(pass / (double)(nb - 1));
+            f[15] = (float)(pops / c / 64.0);
+        }
+        __syncthreads();
+    }
+}
+
+// Logging pass: wave (b, s) evaluates every predicate, in isolation and
+// without short-circuit, on 64 sampled pairs of block b:
+//   c = seed + ((b * samples + s) << 7),
+//   i = mix64(c + 64) mod n_b, j_l = mix64(c + l) mod n_b (l = lane; j_l = i
+//   is replaced by (i + 1) mod n_b), positions inside the block.
+// It accumulates per (block, predicate) the lanes, the lanes that satisfy
+// the predicate and the wave's clock cycles spent deciding it.
+__global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const MatchParams& P = L.mp;
+    const int lane = threadIdx.x;
+    const uint32_t b = blockIdx.x, s = blockIdx.y;
+    const uint32_t start = P.blk_start[b], nb = P.blk_size[b];
+    const uint64_t n = P.feat.n;
+    const uint32_t* f32 = P.feat.f32;
+    const uint64_t c = L.seed + (((uint64_t)b * L.samples + s) << 7);
+    const uint32_t ip = (uint32_t)(mix64(c + 64) % nb);
+    uint32_t jp = (uint32_t)(mix64(c + (uint64_t)lane) % nb);
+    if (jp == ip) jp = (jp + 1) % nb;
+    const uint64_t pi = (uint64_t)start + ip, pj = (uint64_t)start + jp;
+    const uint32_t row_i = f32[pi], row_j = f32[pj];
+    const uint32_t vmask_i = f32[n + pi];
+    uint8_t* peq = lds + P.lds_wave_peq;
+    for (uint32_t x = 0; x < L.n_spec; ++x) {
+        const PredSpec sp = L.spec[x];
+        const uint32_t res = sp.res;
+        const uint64_t t0 = __builtin_readcyclecounter();
+        bool r = feature_filter(L, sp, pi, pj);
+        if (sp.op == OP_EQ_STR && __any(r)) {
+            const ColDev& col = P.cols[P.str_attr[res]];
+            const uint32_t li = f32[(2 + res) * n + pi];
+            if (r) {
+                const uint8_t* si = col.bytes + col.off[row_i];
+                const uint8_t* sj = col.bytes + col.off[row_j];
+                for (uint32_t q = 0; r && q < li; ++q) r = si[q] == sj[q];
+            }
+        } else if (sp.op == OP_ED && __any(r)) {
+            const ColDev& col = P.cols[P.str_attr[res]];
+            const int m = (int)f32[(2 + res) * n + pi];
+            const int nn = (int)f32[(2 + res) * n + pj];
+            const int words = m <= 32 ? 0 : (m + 63) / 64;
+            build_peq(peq, words, col.bytes + col.off[row_i], m, lane);
+            if (r) {
+                const int dist = myers_dispatch(peq, words, m, col.bytes + col.off[row_j], nn,
+                                                (uint64_t*)(lds + P.lds_wave_myers), lane);
+                r = dist <= (int)sp.param;
+            }
+        } else if (sp.op == OP_JAC && __any(r)) {
+            const GramDev& g = P.gram[res];
+            const uint32_t ia = f32[(2 + P.n_str + res) * n + pi];
+            const uint32_t ca = ia & 0x7FFFFFFFu;
+            uint32_t* ig = (uint32_t*)(lds + P.lds_wave_igram[res]);
+            if ((vmask_i >> (24 + res)) & 1) {
+                const uint32_t* src = g.codes + g.off[row_i];
+                for (uint32_t q = lane; q < ca; q += 64) ig[q] = src[q];
+                wave_sync();
+            }
+            if (r) {
+                const uint32_t jb = f32[(2 + P.n_str + res) * n + pj];
+                const uint32_t cb = jb & 0x7FFFFFFFu;
+                const uint32_t I = intersect(ig, ca, (ia >> 31) != 0, g.codes + g.off[row_j], cb, (jb >> 31) != 0);
+                const uint64_t U = (uint64_t)ca + cb - I;
+                r = U == 0 || (uint64_t)I * (sp.param & 0xFFFFFFFFu) >= (sp.param >> 32) * U;
+            }
+        }
+        const uint64_t passed = __popcll(__ballot(r));
+        const uint64_t t1 = __builtin_readcyclecounter();
+        if (lane == 0) {
+            unsigned long long* cnt = L.counts + ((size_t)b * L.n_spec + x) * 3;
+            atomicAdd(&cnt[0], 64ull);
+            atomicAdd(&cnt[1], (unsigned long long)passed);
+            atomicAdd(&cnt[2], (unsigned long long)(t1 - t0));
+        }
     }
 }
 
@@ -452,9 +744,32 @@ hipError_t launch_match(const MatchParams& p, hipStream_t s) {
         cfg = (int)p.lds_bytes;
     }
     if (p.counts)
-        k_match<true><<<(unsigned)p.n_tiles, kThreads, p.lds_bytes, s>>>(p);
+        k_match<true><<<(unsigned)p.n_tiles, kThreads, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
     else
-        k_match<false><<<(unsigned)p.n_tiles, kThreads, p.lds_bytes, s>>>(p);
+        k_match<false><<<(unsigned)p.n_tiles, kThreads, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
+    return hipGetLastError();
+}
+
+}  // namespace hb
+
+namespace hb {
+
+hipError_t launch_block_features(const LearnParams& p, hipStream_t s) {
+    if (p.mp.n_blocks == 0 || p.n_spec == 0) return hipSuccess;
+    k_block_features<<<p.mp.n_blocks, 256, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_log_samples(const LearnParams& p, hipStream_t s) {
+    if (p.mp.n_blocks == 0 || p.n_spec == 0 || p.samples == 0) return hipSuccess;
+    const uint32_t lds = p.mp.lds_wave_stride;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_log_samples, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid(p.mp.n_blocks, p.samples);
+    k_log_samples<<<grid, 64, lds, s>>>(p);
     return hipGetLastError();
 }
 
