@@ -8,6 +8,12 @@ hb_partition (key grouping, block table, candidate count), hb_match
 (plan build, pair evaluation, compaction, output sort).  Pairs evaluated =
 the exact number of distinct candidate pairs (the same for every plan).
 
+The learned plan needs a trained cost model: before any timing, logs are
+collected from the small person workload and a 100k-tuple run of the plain
+recipe (a different draw from the timed 1M relation) and the MLP is trained
+on them by the library's kernels.  The heuristic plan is timed the same way
+beside it, and both outputs are checked equal.
+
 Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one
 GPU.
 """
@@ -77,7 +83,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--plan", default="heuristic", choices=["heuristic", "given"])
+    ap.add_argument("--plan", default="learned", choices=["learned", "heuristic", "given"])
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the heuristic plan beside")
     ap.add_argument("--n", type=int, default=1_000_000, help="tuples of the plain workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -111,33 +118,72 @@ def main():
     out = torch.empty(1 << 22, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
 
-    def step():
+    learned = None
+    if args.plan == "learned":
+        t = time.perf_counter()
+        xs, ts = [], []
+        for wrel, wrules in (workloads.person_small(), workloads.plain_1m(n=100_000)):
+            rid = hb.hb_load_relation(ctx, wrel.columns, wrel.n_rows)
+            rs = hb.hb_compile_rules(ctx, rid, wrules)
+            hb.hb_partition(ctx, rid, rs)
+            lg = hb.hb_log_collect(ctx, rid, rs, 4, 7)
+            hb.hb_release_relation(ctx, rid)
+            xs.append(lg["features"])
+            ts.append(lg["labels"])
+        x = np.concatenate(xs)
+        tl = np.concatenate(ts)
+        perm = np.random.default_rng(0).permutation(len(x))
+        hb.hb_costmodel_init(ctx, 3)
+        loss = hb.hb_costmodel_train(ctx, x[perm], tl[perm], epochs=40, batch=256, lr=2e-3)
+        learned = {"train_rows": int(len(x)), "epochs": 40, "final_loss": loss,
+                   "train_s": time.perf_counter() - t}
+        log(f"[bench] cost model trained on {len(x)} log rows in {learned['train_s']:.1f}s, loss {loss:.4g}")
+
+    def step(plan, dst):
         rid = hb.hb_load_relation(ctx, cols, rel.n_rows, on_device=True)
         rs = hb.hb_compile_rules(ctx, rid, rules)
         n_cand = hb.hb_partition(ctx, rid, rs)
-        n_match = hb.hb_match(ctx, rid, rs, args.plan, out=out)
+        n_match = hb.hb_match(ctx, rid, rs, plan, out=dst)
         hb.hb_release_relation(ctx, rid)
         return n_cand, n_match
 
-    for w in range(args.warmup):
-        n_cand, n_match = step()
-        log(f"[bench] warmup {w}: {n_cand} candidate pairs, {n_match} matched")
-    hb.hb_profile_reset(ctx)
-    hb.hb_profile_enable(ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        n_cand, n_match = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    hb.hb_profile_enable(ctx, False)
-    ms_step = (t1 - t0) * 1000.0 / args.steps
-    value = n_cand * args.steps / (t1 - t0)
-    prof = {}
-    for name in ("match", "partition_sort", "gram_build", "lsh", "output_sort"):
-        ms, launches = hb.hb_profile_query(ctx, name)
-        prof[name] = {"ms_total": ms, "launches": launches}
-    log(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step, {value:.3e} pairs/s; kernels {prof}")
+    def timed(plan, dst):
+        for w in range(args.warmup):
+            n_cand, n_match = step(plan, dst)
+            log(f"[bench] {plan} warmup {w}: {n_cand} candidate pairs, {n_match} matched")
+        hb.hb_profile_reset(ctx)
+        hb.hb_profile_enable(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            n_cand, n_match = step(plan, dst)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hb.hb_profile_enable(ctx, False)
+        prof = {}
+        for name in ("match", "partition_sort", "gram_build", "lsh", "output_sort", "learned_plan"):
+            ms, launches = hb.hb_profile_query(ctx, name)
+            prof[name] = {"ms_total": ms, "launches": launches}
+        ms_step = (t1 - t0) * 1000.0 / args.steps
+        log(f"[bench] {plan}: {args.steps} steps, {ms_step:.2f} ms/step, "
+            f"{n_cand * args.steps / (t1 - t0):.3e} pairs/s; kernels {prof}")
+        return n_cand, n_match, t1 - t0, prof
+
+    compare = None
+    if not args.no_compare and args.plan != "heuristic":
+        out_h = torch.empty_like(out)
+        c_h, m_h, dt_h, prof_h = timed("heuristic", out_h)
+        compare = {"plan": "heuristic", "value": c_h * args.steps / dt_h, "ms_per_step": dt_h * 1000.0 / args.steps,
+                   "match_kernel_ms": prof_h["match"]["ms_total"] / max(1, prof_h["match"]["launches"])}
+    n_cand, n_match, dt, prof = timed(args.plan, out)
+    ms_step = dt * 1000.0 / args.steps
+    value = n_cand * args.steps / dt
+    if compare is not None:
+        same = m_h == n_match and bool(torch.equal(out_h[:n_match], out[:n_match]))
+        compare["bit_exact"] = same
+        log(f"[bench] {args.plan} vs heuristic: {value / compare['value']:.3f}x, outputs equal: {same}")
+        if not same:
+            raise SystemExit("learned and heuristic plans disagree")
     match_ms = prof["match"]["ms_total"] / max(1, prof["match"]["launches"])
 
     # algorithmic work of the dominant kernel: one instrumented pass (untimed)
@@ -170,6 +216,8 @@ def main():
                                f"{args.plan} plan", "plan": args.plan, "candidate_pairs": n_cand,
                    "matched_pairs": n_match},
         "kernels_ms_per_step": {k: v["ms_total"] / args.steps for k, v in prof.items()},
+        "compare": compare,
+        "cost_model": learned,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s (int32 lane-ops)",
                      "frac": achieved / peak, "traffic": None, "kernel": "k_match",
                      "kernel_ms": match_ms, "lane_ops_per_launch": ops_per_launch,

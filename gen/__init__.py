@@ -136,7 +136,8 @@ class _Attr(ctypes.Structure):
                 ("editable", ctypes.c_int32), ("zipf_s", ctypes.c_double),
                 ("n_values", ctypes.c_uint32), ("cap", ctypes.c_uint32),
                 ("lo", ctypes.c_int64), ("hi", ctypes.c_int64),
-                ("int_p", ctypes.c_double), ("int_d", ctypes.c_int64)]
+                ("int_p", ctypes.c_double), ("int_d", ctypes.c_int64),
+                ("dep", ctypes.c_int32), ("dep_p", ctypes.c_double)]
 
 
 class _Spec(ctypes.Structure):
@@ -150,7 +151,8 @@ class _Out(ctypes.Structure):
                 ("bytes_cap", ctypes.c_uint64), ("values", ctypes.c_void_p)]
 
 
-_KIND = {"string": 0, "words": 1, "zipf": 2, "codes": 3, "int": 4}
+_KIND = {"string": 0, "words": 1, "zipf": 2, "codes": 3, "int": 4, "keyed": 5}
+_STRING_KINDS = ("string", "words", "keyed")
 
 
 def build_lib(force: bool = False) -> str:
@@ -175,7 +177,7 @@ def _load():
 @dataclass
 class AttrSpec:
     name: str
-    kind: str                     # string | words | zipf | codes | int
+    kind: str                     # string | words | zipf | codes | int | keyed
     alphabet: int = 0
     min_len: int = 0
     max_len: int = 0
@@ -187,6 +189,8 @@ class AttrSpec:
     hi: int = 0
     int_p: float = 0.0
     int_d: int = 0
+    dep: int = -1                 # keyed: index of the key attribute it follows
+    dep_p: float = 0.0            # keyed: probability that a key code is pinned
 
 
 def generate(seed: int, n_base: int, n_dup: int, attrs: Sequence[AttrSpec],
@@ -199,8 +203,8 @@ def generate(seed: int, n_base: int, n_dup: int, attrs: Sequence[AttrSpec],
     keep = []
     for a, s in enumerate(attrs):
         carr[a] = _Attr(_KIND[s.kind], s.alphabet, s.min_len, s.max_len, int(s.editable),
-                        s.zipf_s, s.n_values, s.cap, s.lo, s.hi, s.int_p, s.int_d)
-        if s.kind in ("string", "words"):
+                        s.zipf_s, s.n_values, s.cap, s.lo, s.hi, s.int_p, s.int_d, s.dep, s.dep_p)
+        if s.kind in _STRING_KINDS:
             offs = np.zeros(n + 1, dtype=np.uint64)
             cap = n * (s.max_len + edit_max) + 1
             data = np.zeros(cap, dtype=np.uint8)
@@ -219,7 +223,7 @@ def generate(seed: int, n_base: int, n_dup: int, attrs: Sequence[AttrSpec],
         raise RuntimeError(f"hbgen_generate failed with code {rc}")
     cols = []
     for a, s in enumerate(attrs):
-        if s.kind in ("string", "words"):
+        if s.kind in _STRING_KINDS:
             offs, data = keep[a]
             cols.append(Column(s.name, STRING, offsets=offs, data=data[: int(used[a])].copy()))
         else:

@@ -20,6 +20,12 @@
  *   HBGEN_CODES   categorical key, uniform over n_values distinct random
  *                 codes in [lo, hi]
  *   HBGEN_INT     int64 uniform in [lo, hi]
+ *   HBGEN_KEYED   string correlated with an earlier key attribute `dep`:
+ *                 each key code v is "pinned" with probability dep_p (a
+ *                 draw from a stream seeded by the code); base tuples with a
+ *                 pinned code share one string drawn from that stream, the
+ *                 others draw like HBGEN_STRING (a city column under a zip
+ *                 code, say: constant in some blocks, free in others)
  *
  * Duplicates: each duplicate copies a uniformly drawn base tuple (keys are
  * inherited), then applies E ~ U[edit_min, edit_max] character edits, each
@@ -39,6 +45,7 @@
 #define HBGEN_ZIPF 2
 #define HBGEN_CODES 3
 #define HBGEN_INT 4
+#define HBGEN_KEYED 5
 
 typedef struct {
     int32_t kind;
@@ -51,6 +58,8 @@ typedef struct {
     int64_t lo, hi;        /* INT / CODES range */
     double int_p;          /* INT duplicate perturbation probability */
     int64_t int_d;         /* INT duplicate perturbation magnitude */
+    int32_t dep;           /* KEYED: index of the (earlier) key attribute */
+    double dep_p;          /* KEYED: probability that a key code is pinned */
 } hbgen_attr;
 
 typedef struct {
@@ -176,9 +185,13 @@ int hbgen_generate(const hbgen_spec* spec, const hbgen_attr* attrs,
     if (n == 0 || na == 0) return -2;
     for (uint32_t a = 0; a < na; ++a) {
         const hbgen_attr* at = &attrs[a];
-        if (at->kind == HBGEN_STRING || at->kind == HBGEN_WORDS) {
+        if (at->kind == HBGEN_STRING || at->kind == HBGEN_WORDS || at->kind == HBGEN_KEYED) {
             if (at->min_len > at->max_len || at->max_len + spec->edit_max >= HBGEN_MAXSTR) return -2;
-            if (at->kind == HBGEN_STRING && (at->alphabet < 0 || at->alphabet > 2)) return -2;
+            if (at->kind != HBGEN_WORDS && (at->alphabet < 0 || at->alphabet > 2)) return -2;
+            if (at->kind == HBGEN_KEYED &&
+                (at->dep < 0 || (uint32_t)at->dep >= a ||
+                 (attrs[at->dep].kind != HBGEN_ZIPF && attrs[at->dep].kind != HBGEN_CODES)))
+                return -2;
             if (at->kind == HBGEN_WORDS && at->n_values == 0) return -2;
         } else if (at->kind == HBGEN_ZIPF) {
             if (at->n_values == 0) return -2;
@@ -208,6 +221,19 @@ int hbgen_generate(const hbgen_spec* spec, const hbgen_attr* attrs,
                 uint32_t L = at->min_len + (uint32_t)xo_below(&r, (uint64_t)(at->max_len - at->min_len) + 1);
                 char* p = (char*)malloc(L ? L : 1);
                 for (uint32_t k = 0; k < L; ++k) p[k] = al[xo_below(&r, asz)];
+                sv[(size_t)i * na + a].p = p; sv[(size_t)i * na + a].len = L;
+            }
+        } else if (at->kind == HBGEN_KEYED) {
+            const char* al = ALPHA[at->alphabet];
+            uint32_t asz = (uint32_t)strlen(al);
+            const uint64_t span = (uint64_t)(at->max_len - at->min_len) + 1;
+            for (uint32_t i = 0; i < nb; ++i) {
+                const int64_t v = iv[(size_t)i * na + at->dep];
+                xo256 rv; xo_seed(&rv, attr_seed(spec->seed ^ ((uint64_t)v * 0x9E3779B97F4A7C15ull), a + 0x100u));
+                xo256* src_r = xo_unit(&rv) < at->dep_p ? &rv : &r;
+                uint32_t L = at->min_len + (uint32_t)xo_below(src_r, span);
+                char* p = (char*)malloc(L ? L : 1);
+                for (uint32_t k = 0; k < L; ++k) p[k] = al[xo_below(src_r, asz)];
                 sv[(size_t)i * na + a].p = p; sv[(size_t)i * na + a].len = L;
             }
         } else if (at->kind == HBGEN_WORDS) {
@@ -273,14 +299,15 @@ int hbgen_generate(const hbgen_spec* spec, const hbgen_attr* attrs,
         uint32_t n_edit = 0;
         uint32_t edit_attrs[256];
         for (uint32_t a = 0; a < na && n_edit < 256; ++a)
-            if ((attrs[a].kind == HBGEN_STRING || attrs[a].kind == HBGEN_WORDS) && attrs[a].editable)
+            if ((attrs[a].kind == HBGEN_STRING || attrs[a].kind == HBGEN_WORDS || attrs[a].kind == HBGEN_KEYED) &&
+                attrs[a].editable)
                 edit_attrs[n_edit++] = a;
         for (uint32_t d = 0; d < nd; ++d) {
             uint32_t i = nb + d;
             uint32_t s = (uint32_t)xo_below(&r, nb);
             src[i] = s;
             for (uint32_t a = 0; a < na; ++a) {
-                if (attrs[a].kind == HBGEN_STRING || attrs[a].kind == HBGEN_WORDS) {
+                if (attrs[a].kind == HBGEN_STRING || attrs[a].kind == HBGEN_WORDS || attrs[a].kind == HBGEN_KEYED) {
                     sbuf b = sv[(size_t)s * na + a];
                     char* p = (char*)malloc(b.len + spec->edit_max + 1);
                     memcpy(p, b.p, b.len);
@@ -337,7 +364,7 @@ int hbgen_generate(const hbgen_spec* spec, const hbgen_attr* attrs,
     }
 
     for (uint32_t a = 0; a < na && rc == 0; ++a) {
-        if (attrs[a].kind == HBGEN_STRING || attrs[a].kind == HBGEN_WORDS) {
+        if (attrs[a].kind == HBGEN_STRING || attrs[a].kind == HBGEN_WORDS || attrs[a].kind == HBGEN_KEYED) {
             uint64_t off = 0;
             out[a].offsets[0] = 0;
             for (uint32_t i = 0; i < n; ++i) {

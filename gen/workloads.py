@@ -14,6 +14,14 @@ restated in the design notes.
                  s1,s2,s3 a-z-space len 5-40; key capped Zipf s=1.1 over 50k
                  values, cap 5,000 base tuples per code; i1 U[0,99];
                  i2 U[1900,2024]; five rules of 3-4 predicates.
+  learned_10m    10,000,000 tuples (9M base + 1M duplicates, 1-3 char edits,
+                 ints shifted by U{-2..2} with p=0.3); s1..s4 a-z-space len
+                 5-60; k1, k2 capped Zipf s=1.2 over 500k values, cap 5,000;
+                 s5 (following k1) and s6 (following k2) a-z-space len 5-60,
+                 pinned to one string per key code with p=0.3; i1 U[0,99],
+                 i2 U[1900,2024]; 20 seeded rules, 10 per key, each the key
+                 equality, one predicate on s1..s4 and 1-3 more from the
+                 plain menu (ED<=1..3, J3>=1/2..4/5, |diff|<=2).
   random_small   adversarial small relations for parity (lengths 0, q-1,
                  63/64/65, 127/128/129, 200; nulls; tiny alphabets; several
                  keys; rule sets with the key equality anywhere in a rule).
@@ -72,6 +80,58 @@ def plain_1m(seed: int = SEED_BASE + 2, n: int = 1_000_000):
     cap = max(8, int(round(5000 * min(1.0, scale * 20))))
     rel = generate(seed, n - n_dup, n_dup, plain_1m_attrs(n_values, cap), edit_min=1, edit_max=3)
     return rel, plain_1m_rules()
+
+
+# ------------------------------------------------------------ learned 10M
+
+def learned_10m_attrs(n_values: int = 500_000, cap: int = 5000):
+    free = [AttrSpec(f"s{x}", "string", alphabet=2, min_len=5, max_len=60) for x in range(1, 5)]
+    return free + [
+        AttrSpec("k1", "zipf", zipf_s=1.2, n_values=n_values, cap=cap),
+        AttrSpec("k2", "zipf", zipf_s=1.2, n_values=n_values, cap=cap),
+        AttrSpec("s5", "keyed", alphabet=2, min_len=5, max_len=60, dep=4, dep_p=0.3),
+        AttrSpec("s6", "keyed", alphabet=2, min_len=5, max_len=60, dep=5, dep_p=0.3),
+        AttrSpec("i1", "int", lo=0, hi=99, int_p=0.3, int_d=2),
+        AttrSpec("i2", "int", lo=1900, hi=2024, int_p=0.3, int_d=2),
+    ]
+
+
+def learned_10m_rules(seed: int = SEED_BASE + 3):
+    """20 rules, 10 per key: key equality, one predicate on a free string
+    (s1..s4) and 1-3 more drawn from the plain menu over every non-key
+    attribute (no attribute twice in a rule)."""
+    r = np.random.default_rng(seed)
+    free, keyed, ints = [0, 1, 2, 3], [6, 7], [8, 9]
+    jac = [(1, 2), (3, 5), (7, 10), (4, 5)]
+
+    def string_pred(a):
+        if r.random() < 0.5:
+            return Pred(ED, a, k=int(r.integers(1, 4)))
+        num, den = jac[int(r.integers(0, len(jac)))]
+        return Pred(JACCARD, a, q=3, num=num, den=den)
+
+    rules = []
+    for key in (4, 5):
+        for _ in range(10):
+            anchor = free[int(r.integers(0, len(free)))]
+            rule = [Pred(EQ, key), string_pred(anchor)]
+            others = [a for a in free + keyed + ints if a != anchor]
+            for a in r.choice(others, size=int(r.integers(1, 4)), replace=False):
+                a = int(a)
+                rule.append(Pred(ABSDIFF, a, d=2) if a in ints else string_pred(a))
+            rules.append(rule)
+    return rules
+
+
+def learned_10m(seed: int = SEED_BASE + 4, n: int = 10_000_000):
+    """The 10M-tuple two-key workload; `n` scales it down (same recipe, key
+    cardinality and cap scaled with n) for parity tests."""
+    n_dup = n // 10
+    scale = n / 10_000_000
+    n_values = max(50, int(round(500_000 * scale)))
+    cap = max(8, int(round(5000 * min(1.0, scale * 20))))
+    rel = generate(seed, n - n_dup, n_dup, learned_10m_attrs(n_values, cap), edit_min=1, edit_max=3)
+    return rel, learned_10m_rules()
 
 
 # ------------------------------------------------------------ adversarial

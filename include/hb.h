@@ -147,8 +147,17 @@ hb_status hb_partition(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id,
 /* Evaluation order (output-neutral, Section 4):
  *   HB_PLAN_GIVEN      rules and predicates in the given order;
  *   HB_PLAN_HEURISTIC  the execution plan of Section 4.2 (cost-effectiveness
- *                      order, execution tree, edge scores, DFS order). */
-typedef enum { HB_PLAN_GIVEN = 0, HB_PLAN_HEURISTIC = 1 } hb_plan;
+ *                      order, execution tree, edge scores, DFS order);
+ *   HB_PLAN_LEARNED    a plan per block from the context's cost model (a
+ *                      different plan on each partition, the paper's future
+ *                      topic in Section 8): each rule's predicates ordered by
+ *                      predicted cycles / (1 - probability that some pair of
+ *                      a wave's 16 x 64 batch survives them), rules by
+ *                      predicted witness probability per cycle; a block keeps
+ *                      the heuristic plan unless the model predicts the
+ *                      learned one 2% cheaper.  Needs a cost model
+ *                      (HB_ERR_STATE otherwise). */
+typedef enum { HB_PLAN_GIVEN = 0, HB_PLAN_HEURISTIC = 1, HB_PLAN_LEARNED = 2 } hb_plan;
 
 /* Evaluate the rule set on every candidate pair and return Ca(D): packed
  * uint64 (i << 32) | j with i < j, sorted ascending, each pair once.
@@ -183,7 +192,9 @@ hb_status hb_epg_path(uint32_t n_preds, const double* sp, const double* cost, ui
 
 /* Kernel timing: when enabled, HIP events bracket each kernel launch of the
  * named step on the context stream.  Names: "match", "partition_sort",
- * "gram_build", "lsh", "output_sort". */
+ * "gram_build", "lsh", "output_sort", "log"; and "learned_plan", the host
+ * wall time of building one key partition's per-block learned plans (block
+ * features, model inference and plan choice, with their synchronisation). */
 hb_status hb_profile_enable(hb_ctx* ctx, int on);
 hb_status hb_profile_query(hb_ctx* ctx, const char* name, double* total_ms, uint64_t* launches);
 hb_status hb_profile_reset(hb_ctx* ctx);
@@ -192,12 +203,15 @@ hb_status hb_profile_reset(hb_ctx* ctx);
  * counting compiled in (output-neutral and slower; for profiling only).  Per
  * plan operation kind (index: 0 value equality, 1 |a-b| <= d, 2 string
  * equality filter, 3 edit-distance filter, 4 Jaccard filter, 5 string
- * equality, 6 edit distance, 7 Jaccard): the wave-steps that executed it,
- * the lanes that evaluated it, the lanes for which it held, and its work
- * units (edit distance: text bytes x 32-bit pattern words run; Jaccard:
- * merged list elements; string equality: bytes compared).  `pairs` is the
- * number of candidate pairs evaluated, `lane_ops` the algorithmic int32
- * lane-operations under the library's per-operation cost model.
+ * equality, 6 edit distance, 7 Jaccard): `waves` = the times a wave ran it
+ * for its batch of 16 rows x 64 lanes, `lanes` = the pairs that evaluated
+ * it, `passed` = the pairs for which it held, `work` = its work units (edit
+ * distance: text bytes x 32-bit pattern words run; Jaccard: merged list
+ * elements; string equality: bytes compared; others: pairs).  `pairs` is
+ * the number of candidate pairs evaluated, `lane_ops` the algorithmic int32
+ * lane-operations under the library's per-operation cost model (per pair
+ * evaluated), `batch_ops` the same model charged for every lane of every
+ * batch a step ran on (the SIMD work the plan causes).
  * Requires hb_partition; leaves the cached hb_match result untouched. */
 #define HB_N_OPKINDS 8
 typedef struct {
@@ -209,6 +223,7 @@ typedef struct {
     uint64_t passed[HB_N_OPKINDS];
     uint64_t work[HB_N_OPKINDS];
     double lane_ops;
+    double batch_ops;
 } hb_work_stats;
 hb_status hb_match_work(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, hb_work_stats* out);
 
@@ -249,6 +264,28 @@ hb_status hb_costmodel_trace(hb_ctx* ctx, const float* x, const float* t, uint32
 /* One Adam step with the given host gradients (HB_MLP_PARAMS floats). */
 hb_status hb_costmodel_adam_step(hb_ctx* ctx, const float* grads, float lr);
 
+/* Logging pass for the cost model (the paper trains its estimator on
+ * historical logs, Section 4.2): for every block (of every key partition,
+ * in key order, blocks in ascending key value) and every distinct predicate
+ * evaluated there (ascending id; the partition's own key equality is
+ * implied and skipped), one row of HB_MLP_FEATURES block features and two
+ * labels from `samples` waves of 64 sampled pairs, each pair evaluated on
+ * every predicate without short-circuit: label 0 = fraction of sampled pairs
+ * passing the predicate's first plan step (its exact necessary-condition
+ * filter; for value predicates the predicate itself), label 1 =
+ * log2(1 + clock cycles per wave evaluation of the whole predicate) / 16.
+ * Sampled pairs of wave s of block b (positions inside the block, rows in
+ * ascending row order): c = (seed ^ (key index << 56)) + ((b * samples + s)
+ * << 7); i = h(c + 64) mod n_b; j_l = h(c + l) mod n_b for lane l, replaced
+ * by (i + 1) mod n_b when equal to i; h = the splitmix64 output function.
+ * Outputs (host, any may be NULL): features [cap x 16], labels [cap x 2],
+ * meta [cap x 3] = (key index, block, predicate id), counts [cap x 4] =
+ * (pairs sampled, pairs satisfying, cycles, pairs passing the first step).  If cap_rows is too small the
+ * call returns HB_ERR_CAPACITY with *n_rows = rows needed. */
+hb_status hb_log_collect(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, uint32_t samples, uint64_t seed,
+                         float* features, float* labels, uint32_t* meta, uint64_t* counts, uint64_t cap_rows,
+                         uint64_t* n_rows);
+
 /* Counters of the last hb_match: candidate pairs, pairs matched, launches
  * and tiles of the match kernel. */
 typedef struct {
@@ -256,6 +293,8 @@ typedef struct {
     uint64_t matched_pairs;
     uint64_t tiles;
     uint64_t launches;
+    uint64_t learned_blocks;   /* HB_PLAN_LEARNED: blocks running a learned plan */
+    uint64_t fallback_blocks;  /* HB_PLAN_LEARNED: blocks kept on the heuristic plan */
 } hb_match_stats;
 hb_status hb_last_match_stats(hb_ctx* ctx, hb_match_stats* out);
 

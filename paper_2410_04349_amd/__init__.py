@@ -32,10 +32,11 @@ HB_ERR_STATE = 9
 
 HB_PLAN_GIVEN = 0
 HB_PLAN_HEURISTIC = 1
+HB_PLAN_LEARNED = 2
 
 _COLTYPE = {"string": 0, "categorical": 1, "int64": 2}
 _OP = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3}
-_PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC}
+_PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC, "learned": HB_PLAN_LEARNED}
 
 EXPORTED = [
     "hb_create", "hb_destroy", "hb_last_error", "hb_version", "hb_load_relation", "hb_release_relation",
@@ -43,6 +44,7 @@ EXPORTED = [
     "hb_epg_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
     "hb_match_work", "hb_costmodel_init", "hb_costmodel_set_params", "hb_costmodel_get_params",
     "hb_costmodel_train", "hb_costmodel_predict", "hb_costmodel_trace", "hb_costmodel_adam_step",
+    "hb_log_collect",
 ]
 
 HB_MLP_PARAMS = 5378
@@ -68,13 +70,14 @@ class HbRule(ctypes.Structure):
 
 class HbMatchStats(ctypes.Structure):
     _fields_ = [("candidate_pairs", ctypes.c_uint64), ("matched_pairs", ctypes.c_uint64),
-                ("tiles", ctypes.c_uint64), ("launches", ctypes.c_uint64)]
+                ("tiles", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("learned_blocks", ctypes.c_uint64), ("fallback_blocks", ctypes.c_uint64)]
 
 
 class HbWorkStats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_uint64), ("matched", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("waves", ctypes.c_uint64 * 8), ("lanes", ctypes.c_uint64 * 8), ("passed", ctypes.c_uint64 * 8),
-                ("work", ctypes.c_uint64 * 8), ("lane_ops", ctypes.c_double)]
+                ("work", ctypes.c_uint64 * 8), ("lane_ops", ctypes.c_double), ("batch_ops", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -119,6 +122,7 @@ def _load_lib():
         "hb_costmodel_predict": (I32, [P, P, U64, ctypes.c_int, P, ctypes.c_int]),
         "hb_costmodel_trace": (I32, [P, P, P, U32, P, U64]),
         "hb_costmodel_adam_step": (I32, [P, P, ctypes.c_float]),
+        "hb_log_collect": (I32, [P, U32, U32, U32, U64, P, P, P, P, U64, ctypes.POINTER(U64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -348,7 +352,7 @@ def hb_last_match_stats(ctx: Context) -> dict:
     s = HbMatchStats()
     ctx.check(_lib.hb_last_match_stats(ctx.h, ctypes.byref(s)))
     return {"candidate_pairs": s.candidate_pairs, "matched_pairs": s.matched_pairs, "tiles": s.tiles,
-            "launches": s.launches}
+            "launches": s.launches, "learned_blocks": s.learned_blocks, "fallback_blocks": s.fallback_blocks}
 
 
 def hb_match_work(ctx: Context, rel_id: int, ruleset_id: int, plan="heuristic") -> dict:
@@ -360,7 +364,7 @@ def hb_match_work(ctx: Context, rel_id: int, ruleset_id: int, plan="heuristic") 
     for k, name in enumerate(OP_KINDS):
         per_op[name] = {"waves": w.waves[k], "lanes": w.lanes[k], "passed": w.passed[k], "work": w.work[k]}
     return {"pairs": w.pairs, "matched": w.matched, "launches": w.launches, "lane_ops": w.lane_ops,
-            "per_op": per_op}
+            "batch_ops": w.batch_ops, "per_op": per_op}
 
 
 def _f32(a):
@@ -418,3 +422,22 @@ def hb_costmodel_trace(ctx: Context, x, t) -> dict:
 def hb_costmodel_adam_step(ctx: Context, grads, lr: float) -> None:
     g = _f32(grads)
     ctx.check(_lib.hb_costmodel_adam_step(ctx.h, ctypes.c_void_p(g.ctypes.data), lr))
+
+
+def hb_log_collect(ctx: Context, rel_id: int, ruleset_id: int, samples: int, seed: int) -> dict:
+    """Logging pass (see include/hb.h): features [n x 16], labels [n x 2],
+    meta [n x 3] (key index, block, predicate id), counts [n x 4] (pairs
+    sampled, pairs satisfying, cycles, pairs passing the first step)."""
+    n = ctypes.c_uint64()
+    st = _lib.hb_log_collect(ctx.h, rel_id, ruleset_id, samples, seed, None, None, None, None, 0, ctypes.byref(n))
+    if st not in (HB_OK, HB_ERR_CAPACITY):
+        ctx.check(st)
+    rows = n.value
+    f = np.zeros((max(rows, 1), 16), dtype=np.float32)
+    lab = np.zeros((max(rows, 1), 2), dtype=np.float32)
+    meta = np.zeros((max(rows, 1), 3), dtype=np.uint32)
+    cnt = np.zeros((max(rows, 1), 4), dtype=np.uint64)
+    ctx.check(_lib.hb_log_collect(ctx.h, rel_id, ruleset_id, samples, seed, ctypes.c_void_p(f.ctypes.data),
+                                  ctypes.c_void_p(lab.ctypes.data), ctypes.c_void_p(meta.ctypes.data),
+                                  ctypes.c_void_p(cnt.ctypes.data), rows, ctypes.byref(n)))
+    return {"features": f[:rows], "labels": lab[:rows], "meta": meta[:rows], "counts": cnt[:rows]}

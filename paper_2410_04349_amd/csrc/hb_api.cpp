@@ -124,8 +124,9 @@ static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
     DevBuf mx(c, sizeof(unsigned int));
     zero(c, mx.get(), sizeof(unsigned int));
     c->timed("gram_build", [&] {
+        const uint32_t ml = rel.cols[attr].max_len;
         return launch_gram_build(dcol, n, q, g.off.as<uint64_t>(), g.codes.as<uint32_t>(), g.cnt.as<uint32_t>(),
-                                 g.flags.as<uint8_t>(), mx.as<unsigned int>(), c->stream);
+                                 g.flags.as<uint8_t>(), mx.as<unsigned int>(), ml >= q ? ml - q + 1 : 1, c->stream);
     });
     g.max_cnt = read1(c, mx.as<unsigned int>());
     g.sig.alloc(c, sizeof(uint64_t) * n);
@@ -423,7 +424,7 @@ static void partition(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint64_t* n_cand)
 struct KeyPlan {
     std::vector<Instr> code;
     MatchParams mp{};
-    DevBuf f64, f32;
+    DevBuf f64, f32, blk_plan;
 };
 
 static uint32_t align_up(uint32_t v, uint32_t a) { return (v + a - 1) / a * a; }
@@ -438,92 +439,132 @@ static const uint64_t* char_signature(Ctx* c, Relation& rel, uint32_t attr) {
     return p;
 }
 
-// Device plan for the blocks of key number `ka`: the sequential path with
-// rules that need an earlier key dropped (the owner check rules those pairs
-// out) and the equality on this key dropped (it holds inside a block).
-// Each rule becomes its cheap steps and filters, in plan order, then its
-// exact similarity predicates, in plan order, then a checkpoint.
-static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector<PathRule>& path, size_t ka,
-                           KeyPlan& kp, bool count) {
-    const uint32_t key = rs.keys[ka];
-    std::vector<uint32_t> int_attr, str_attr;
+// Resources of one key partition's plans, fixed by the rule set (not by
+// the evaluation order), so every order of the same rules reads the same
+// gathered feature columns.
+struct KeyRes {
+    std::vector<uint32_t> int_attr, str_attr, prev;
     std::vector<std::pair<uint32_t, uint32_t>> gram_key;
+    std::vector<PredSpec> specs;   // predicates evaluated in this partition, by id
+    bool any_ed = false;
+    bool any_rule = false;
+};
+
+// A rule can hold in key `ka`'s blocks unless it needs an earlier key to
+// agree (the owner check rules those pairs out).
+static bool rule_possible(const Relation& rel, const RuleSet& rs, const std::vector<uint32_t>& preds, size_t ka) {
+    for (uint32_t p : preds) {
+        const hb_pred& d = rs.distinct[p];
+        if (d.op == HB_EQ && rel.cols[d.attr].type != HB_COL_STRING)
+            for (size_t x = 0; x < ka; ++x)
+                if (rs.keys[x] == d.attr) return false;
+    }
+    return true;
+}
+
+static KeyRes key_resources(const Relation& rel, const RuleSet& rs, size_t ka) {
+    KeyRes R;
+    const uint32_t key = rs.keys[ka];
     auto res_of = [](std::vector<uint32_t>& v, uint32_t a) {
         auto it = std::find(v.begin(), v.end(), a);
         if (it != v.end()) return (uint32_t)(it - v.begin());
         v.push_back(a);
         return (uint32_t)(v.size() - 1);
     };
-    auto gram_of = [&](uint32_t attr, uint32_t q) {
-        auto gk = std::make_pair(attr, q);
-        auto it = std::find(gram_key.begin(), gram_key.end(), gk);
-        if (it != gram_key.end()) return (uint32_t)(it - gram_key.begin());
-        gram_key.push_back(gk);
-        return (uint32_t)(gram_key.size() - 1);
-    };
-    std::vector<uint32_t> prev;
-    for (size_t x = 0; x < ka; ++x) prev.push_back(res_of(int_attr, rs.keys[x]));
-
-    std::vector<Instr> code;
-    bool any_rule = false;
-    for (const PathRule& pr : path) {
-        bool impossible = false;
-        for (uint32_t p : pr.preds) {
-            const hb_pred& d = rs.distinct[p];
-            if (d.op == HB_EQ && rel.cols[d.attr].type != HB_COL_STRING)
-                for (size_t x = 0; x < ka; ++x)
-                    if (rs.keys[x] == d.attr) impossible = true;
+    for (size_t x = 0; x < ka; ++x) R.prev.push_back(res_of(R.int_attr, rs.keys[x]));
+    std::vector<bool> used(rs.distinct.size(), false);
+    for (const auto& rule : rs.rules) {
+        if (!rule_possible(rel, rs, rule, ka)) continue;
+        R.any_rule = true;
+        for (uint32_t p : rule) used[p] = true;
+    }
+    for (uint32_t p = 0; p < rs.distinct.size(); ++p) {
+        if (!used[p]) continue;
+        const hb_pred& d = rs.distinct[p];
+        const int32_t t = rel.cols[d.attr].type;
+        if (d.op == HB_EQ && t != HB_COL_STRING && d.attr == key) continue;
+        PredSpec sp{};
+        sp.pred = (uint16_t)p;
+        switch (d.op) {
+        case HB_EQ:
+            if (t == HB_COL_STRING) { sp.op = OP_EQ_STR; sp.res = (uint8_t)res_of(R.str_attr, d.attr); }
+            else { sp.op = OP_EQ_INT; sp.res = (uint8_t)res_of(R.int_attr, d.attr); }
+            break;
+        case HB_ABSDIFF_LE:
+            sp.op = OP_ABSDIFF;
+            sp.res = (uint8_t)res_of(R.int_attr, d.attr);
+            sp.param = (uint64_t)d.d;
+            break;
+        case HB_ED_LE:
+            sp.op = OP_ED;
+            sp.res = (uint8_t)res_of(R.str_attr, d.attr);
+            sp.param = (uint64_t)d.k;
+            R.any_ed = true;
+            break;
+        case HB_JACCARD_GE: {
+            auto gk = std::make_pair(d.attr, d.q);
+            auto it = std::find(R.gram_key.begin(), R.gram_key.end(), gk);
+            if (it == R.gram_key.end()) { R.gram_key.push_back(gk); sp.res = (uint8_t)(R.gram_key.size() - 1); }
+            else sp.res = (uint8_t)(it - R.gram_key.begin());
+            sp.op = OP_JAC;
+            sp.param = ((uint64_t)d.num << 32) | d.den;
+            break;
         }
-        if (impossible) continue;
-        any_rule = true;
+        }
+        R.specs.push_back(sp);
+    }
+    if (R.int_attr.size() > (size_t)kMaxIntRes || R.str_attr.size() > (size_t)kMaxStrRes ||
+        R.gram_key.size() > (size_t)kMaxGramRes)
+        fail(HB_ERR_LIMIT, "rule set reads more than 16 int, 8 string or 8 q-gram attributes");
+    return R;
+}
+
+// Bytecode of a sequential path for key `ka`: each possible rule becomes its
+// cheap steps and filters in path order, then its exact similarity
+// predicates in path order, then a checkpoint.  The equality on this key is
+// dropped (it holds inside a block).
+static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, const std::vector<PathRule>& path,
+                                    size_t ka, const KeyRes& R) {
+    std::vector<Instr> code;
+    auto spec_of = [&](uint32_t p) -> const PredSpec* {
+        for (const PredSpec& sp : R.specs)
+            if (sp.pred == p) return &sp;
+        return nullptr;
+    };
+    for (const PathRule& pr : path) {
+        if (!rule_possible(rel, rs, pr.preds, ka)) continue;
         const size_t first = code.size();
         std::vector<Instr> verify;
         for (uint32_t p : pr.preds) {
-            const hb_pred& d = rs.distinct[p];
-            const int32_t t = rel.cols[d.attr].type;
-            if (d.op == HB_EQ && t != HB_COL_STRING && d.attr == key) continue;
+            const PredSpec* sp = spec_of(p);
+            if (!sp) continue;   // the key's own equality
             Instr in{};
             in.slot = (uint8_t)p;
-            Instr f{};
+            in.res = sp->res;
+            in.param = sp->param;
+            Instr f = in;
             f.slot = (uint8_t)(64 + p);
-            switch (d.op) {
-            case HB_EQ:
-                if (t == HB_COL_STRING) {
-                    f.op = OP_EQF;
-                    f.res = (uint8_t)res_of(str_attr, d.attr);
-                    in.op = OP_EQ_STR;
-                    in.res = f.res;
-                    code.push_back(f);
-                    verify.push_back(in);
-                } else {
-                    in.op = OP_EQ_INT;
-                    in.res = (uint8_t)res_of(int_attr, d.attr);
-                    code.push_back(in);
-                }
-                break;
-            case HB_ABSDIFF_LE:
-                in.op = OP_ABSDIFF;
-                in.res = (uint8_t)res_of(int_attr, d.attr);
-                in.param = (uint64_t)d.d;
+            switch (sp->op) {
+            case OP_EQ_INT:
+            case OP_ABSDIFF:
+                in.op = sp->op;
                 code.push_back(in);
                 break;
-            case HB_ED_LE:
-                f.op = OP_EDF;
-                f.res = (uint8_t)res_of(str_attr, d.attr);
-                f.param = (uint64_t)d.k;
-                in.op = OP_ED;
-                in.res = f.res;
-                in.param = (uint64_t)d.k;
+            case OP_EQ_STR:
+                f.op = OP_EQF;
+                in.op = OP_EQ_STR;
                 code.push_back(f);
                 verify.push_back(in);
                 break;
-            case HB_JACCARD_GE:
+            case OP_ED:
+                f.op = OP_EDF;
+                in.op = OP_ED;
+                code.push_back(f);
+                verify.push_back(in);
+                break;
+            default:
                 f.op = OP_JACF;
-                f.res = (uint8_t)gram_of(d.attr, d.q);
-                f.param = ((uint64_t)d.num << 32) | d.den;
-                in = f;
                 in.op = OP_JAC;
-                in.slot = (uint8_t)p;
                 code.push_back(f);
                 verify.push_back(in);
                 break;
@@ -536,20 +577,24 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
         const uint16_t cpi = (uint16_t)(code.size() - 1);
         for (size_t x = first; x < code.size(); ++x) code[x].cp = cpi;
     }
-    if (!any_rule) return false;
-    if (int_attr.size() > (size_t)kMaxIntRes || str_attr.size() > (size_t)kMaxStrRes ||
-        gram_key.size() > (size_t)kMaxGramRes)
-        fail(HB_ERR_LIMIT, "rule set reads more than 16 int, 8 string or 8 q-gram attributes");
     if (code.size() > (size_t)kMaxPlan) fail(HB_ERR_LIMIT, "plan too long");
+    return code;
+}
 
+// Resources, block-major feature columns and LDS layout of key `ka`'s
+// partition (everything but the plan itself).
+static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& kp, KeyRes& R, bool count) {
+    const uint32_t key = rs.keys[ka];
+    R = key_resources(rel, rs, ka);
+    if (!R.any_rule) return false;
     const Partition& P = rel.parts.at(key);
     MatchParams& m = kp.mp;
-    m.n_int = (uint32_t)int_attr.size();
-    m.n_str = (uint32_t)str_attr.size();
-    m.n_gram = (uint32_t)gram_key.size();
-    m.n_prev = (uint32_t)prev.size();
-    for (size_t x = 0; x < int_attr.size(); ++x) m.int_attr[x] = int_attr[x];
-    for (size_t x = 0; x < prev.size(); ++x) m.prev_res[x] = prev[x];
+    m.n_int = (uint32_t)R.int_attr.size();
+    m.n_str = (uint32_t)R.str_attr.size();
+    m.n_gram = (uint32_t)R.gram_key.size();
+    m.n_prev = (uint32_t)R.prev.size();
+    for (size_t x = 0; x < R.int_attr.size(); ++x) m.int_attr[x] = R.int_attr[x];
+    for (size_t x = 0; x < R.prev.size(); ++x) m.prev_res[x] = R.prev[x];
     GatherParams gp{};
     gp.cols = rel.d_cols.as<ColDev>();
     gp.perm = P.perm.as<uint32_t>();
@@ -557,21 +602,19 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
     gp.n_int = m.n_int;
     gp.n_str = m.n_str;
     gp.n_gram = m.n_gram;
-    for (size_t x = 0; x < int_attr.size(); ++x) gp.int_attr[x] = int_attr[x];
+    for (size_t x = 0; x < R.int_attr.size(); ++x) gp.int_attr[x] = R.int_attr[x];
     uint32_t ed_words = 1;
-    for (size_t x = 0; x < str_attr.size(); ++x) {
-        m.str_attr[x] = str_attr[x];
-        gp.str_attr[x] = str_attr[x];
-        gp.csig[x] = char_signature(c, rel, str_attr[x]);
-        ed_words = std::max<uint32_t>(ed_words, (rel.cols[str_attr[x]].max_len + 63) / 64);
+    for (size_t x = 0; x < R.str_attr.size(); ++x) {
+        m.str_attr[x] = R.str_attr[x];
+        gp.str_attr[x] = R.str_attr[x];
+        gp.csig[x] = char_signature(c, rel, R.str_attr[x]);
+        ed_words = std::max<uint32_t>(ed_words, (rel.cols[R.str_attr[x]].max_len + 63) / 64);
     }
-    uint32_t max_cnt = 1;
-    for (size_t x = 0; x < gram_key.size(); ++x) {
-        GramIndex& g = gram_index(c, rel, gram_key[x].first, gram_key[x].second);
+    for (size_t x = 0; x < R.gram_key.size(); ++x) {
+        GramIndex& g = gram_index(c, rel, R.gram_key[x].first, R.gram_key[x].second);
         m.gram[x] = g.dev();
         gp.gram[x] = g.dev();
         gp.gsig[x] = g.sig.as<uint64_t>();
-        max_cnt = std::max(max_cnt, g.max_cnt);
     }
     m.ed_words = ed_words;
     const uint32_t n64 = m.n_int + m.n_str + m.n_gram, n32 = 2 + m.n_str + m.n_gram;
@@ -583,9 +626,7 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
     HB_HIP(launch_gather_features(gp, c->stream));
 
     // LDS: the j-tile's feature columns, then per wave the pattern-match
-    // table and the current row's q-gram lists
-    bool any_ed = false;
-    for (const Instr& in : code) any_ed |= in.op == OP_ED;
+    // table, the long-pattern Myers state and the current row's q-gram lists
     uint32_t off = 0;
     m.lds_f64 = off;
     off += n64 * kTile * 8;
@@ -595,9 +636,9 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
     m.lds_wave_base = off;
     uint32_t w = 0;
     m.lds_wave_peq = w;
-    if (any_ed) w += 256 * ed_words * 8;
+    if (R.any_ed) w += 256 * ed_words * 8;
     m.lds_wave_myers = w;
-    if (any_ed && ed_words >= 2) w += 2 * kMaxEdWords * 64 * 8;
+    if (R.any_ed && ed_words >= 2) w += 2 * kMaxEdWords * 64 * 8;
     for (uint32_t x = 0; x < m.n_gram; ++x) {
         m.lds_wave_igram[x] = w;
         w += align_up(std::max<uint32_t>(m.gram[x].max_cnt, 1) * 4, 16);
@@ -621,10 +662,248 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
     m.tile_prefix = P.tile_prefix.as<uint64_t>();
     m.n_blocks = P.n_blocks;
     m.n_tiles = P.n_tiles;
-    m.plan_len = (uint32_t)code.size();
     if (m.n_tiles >= 0x7FFFFFFFull) fail(HB_ERR_LIMIT, "more than 2^31 tiles in one key partition");
-    kp.code = std::move(code);
     return true;
+}
+
+static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector<PathRule>& path, size_t ka,
+                           KeyPlan& kp, bool count) {
+    KeyRes R;
+    if (!prepare_key(c, rel, rs, ka, kp, R, count)) return false;
+    kp.code = emit_code(rel, rs, path, ka, R);
+    kp.mp.plan_len = (uint32_t)kp.code.size();
+    return true;
+}
+
+// ------------------------------------------------------------ learned plan
+
+// The model's per-(block, predicate) outputs: the pass rate of the
+// predicate's first plan step (its exact filter) and log-scaled cycles of a
+// wave evaluating the whole predicate.
+struct Estimate {
+    double pass, cycles;
+};
+
+static Estimate decode_estimate(float y0, float y1) {
+    Estimate e;
+    e.pass = std::isfinite(y0) ? std::min(1.0, std::max(0.0, (double)y0)) : 1.0;
+    e.cycles = std::isfinite(y1) ? std::exp2(std::min(30.0, std::max(0.0, 16.0 * (double)y1))) : 1e9;
+    return e;
+}
+
+// Plan operation of each distinct predicate in one key partition (kNoStep:
+// not evaluated there, e.g. the partition's own key equality).
+static constexpr uint8_t kNoStep = 0xFF;
+
+static std::vector<uint8_t> step_kinds(const RuleSet& rs, const KeyRes& R) {
+    std::vector<uint8_t> kind(rs.distinct.size(), kNoStep);
+    for (const PredSpec& sp : R.specs) kind[sp.pred] = (uint8_t)sp.op;
+    return kind;
+}
+
+// Cost of a predicate's first-stage step for one row of a wave batch, in the
+// library's per-operation lane-op units (data-independent).
+static double first_step_cost(uint8_t kind) {
+    switch (kind) {
+    case kNoStep: return 0.0;
+    case OP_EQ_INT: return 1.0;
+    case OP_ABSDIFF: return 4.0;
+    case OP_EQ_STR: return 3.0;
+    default: return 12.0;
+    }
+}
+
+static bool needs_verify(uint8_t kind) { return kind == OP_EQ_STR || kind == OP_ED || kind == OP_JAC; }
+
+// Probability that some pair of a wave batch of `batch` pairs passes a step
+// that each pair passes with probability `pass`.
+static double batch_pass(double pass, double batch) { return 1.0 - std::pow(1.0 - pass, batch); }
+
+// Expected cost of one wave batch running a path: a step runs while some
+// pair of the batch is still alive.  First stage: static step costs, per
+// row; second stage (exact checks): the model's cycles, once the batch
+// survived all of the rule's filters.
+static double expected_cost(const std::vector<uint8_t>& kind, const std::vector<PathRule>& path,
+                            const std::vector<Estimate>& est, double batch) {
+    double total = 0.0;
+    for (const PathRule& pr : path) {
+        double reach = 1.0;
+        for (uint32_t p : pr.preds) {
+            total += reach * first_step_cost(kind[p]) * kRows * 64.0;
+            reach *= batch_pass(est[p].pass, batch);
+        }
+        for (uint32_t p : pr.preds)
+            if (needs_verify(kind[p])) total += reach * est[p].cycles;
+    }
+    return total;
+}
+
+// Per-block order: within a rule, predicates by first-step cost / (1 - q)
+// ascending, q = the probability that some pair of the wave batch passes
+// the step; rules by witness probability (product of pass rates) per
+// expected cost, descending.
+static std::vector<PathRule> learned_path(const RuleSet& rs, const std::vector<uint8_t>& kind,
+                                          const std::vector<Estimate>& est, double batch) {
+    std::vector<PathRule> out;
+    std::vector<double> score;
+    for (uint32_t r = 0; r < rs.rules.size(); ++r) {
+        PathRule pr;
+        pr.rule = r;
+        for (uint32_t p : rs.rules[r])
+            if (std::find(pr.preds.begin(), pr.preds.end(), p) == pr.preds.end()) pr.preds.push_back(p);
+        auto rank = [&](uint32_t p) {
+            return first_step_cost(kind[p]) / std::max(1e-12, 1.0 - batch_pass(est[p].pass, batch));
+        };
+        std::stable_sort(pr.preds.begin(), pr.preds.end(), [&](uint32_t a, uint32_t b) { return rank(a) < rank(b); });
+        double wp = 1.0;
+        for (uint32_t p : pr.preds) wp *= est[p].pass;
+        const double cost = expected_cost(kind, {pr}, est, batch);
+        score.push_back(wp / std::max(cost, 1e-12));
+        out.push_back(pr);
+    }
+    std::vector<size_t> idx(out.size());
+    for (size_t x = 0; x < idx.size(); ++x) idx[x] = x;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return score[a] > score[b]; });
+    std::vector<PathRule> sorted;
+    for (size_t x : idx) sorted.push_back(out[x]);
+    return sorted;
+}
+
+// Features of every (block, predicate) of key `ka` into `feat` (device).
+static void block_features(Ctx* c, const KeyPlan& kp, const KeyRes& R, DevBuf& feat, LearnParams& L) {
+    if (R.specs.size() > (size_t)kMaxSpecs) fail(HB_ERR_LIMIT, "more than 64 predicates in one partition");
+    L = LearnParams{};
+    L.mp = kp.mp;
+    for (size_t x = 0; x < R.specs.size(); ++x) L.spec[x] = R.specs[x];
+    L.n_spec = (uint32_t)R.specs.size();
+    feat.alloc(c, sizeof(float) * kFeatures * std::max<size_t>((size_t)kp.mp.n_blocks * L.n_spec, 1));
+    L.features = feat.as<float>();
+    HB_HIP(launch_block_features(L, c->stream));
+}
+
+// Learned per-block plans for key `ka`: fills kp.code with the distinct
+// plans and kp.blk_plan with each block's (offset << 12) | length.
+static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& kp, const KeyRes& R,
+                             const std::vector<PathRule>& heuristic, uint64_t* n_learned, uint64_t* n_fallback) {
+    if (!c->model.ready) fail(HB_ERR_STATE, "the learned plan needs a cost model (hb_costmodel_train or _set_params)");
+    const uint32_t nb = kp.mp.n_blocks;
+    const uint32_t ns = (uint32_t)R.specs.size();
+    std::vector<float> y((size_t)nb * ns * 2, 0.f);
+    if (ns > 0 && nb > 0) {
+        DevBuf feat;
+        LearnParams L;
+        block_features(c, kp, R, feat, L);
+        costmodel_predict(c, feat.as<float>(), (uint64_t)nb * ns, 1, y.data(), 0);
+    }
+    std::vector<uint32_t> sizes(nb);
+    if (nb) {
+        HB_HIP(hipMemcpyAsync(sizes.data(), kp.mp.blk_size, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+    }
+    std::map<std::vector<uint32_t>, std::pair<uint32_t, uint32_t>> seen;   // flattened path -> (offset, length)
+    std::vector<Instr> all;
+    std::vector<uint32_t> blk(nb);
+    std::vector<Estimate> est(rs.distinct.size(), Estimate{1.0, 1.0});
+    const std::vector<uint8_t> kind = step_kinds(rs, R);
+    for (uint32_t b = 0; b < nb; ++b) {
+        for (uint32_t x = 0; x < ns; ++x)
+            est[R.specs[x].pred] = decode_estimate(y[((size_t)b * ns + x) * 2], y[((size_t)b * ns + x) * 2 + 1]);
+        const double batch = (double)std::min<uint32_t>(sizes[b], kRows) * (double)std::min<uint32_t>(sizes[b], kTile);
+        std::vector<PathRule> lp = learned_path(rs, kind, est, batch);
+        const bool better = expected_cost(kind, lp, est, batch) < 0.98 * expected_cost(kind, heuristic, est, batch);
+        const std::vector<PathRule>& path = better ? lp : heuristic;
+        (better ? *n_learned : *n_fallback) += 1;
+        std::vector<uint32_t> keyv;
+        for (const PathRule& pr : path) {
+            keyv.push_back(0xFFFFFFFFu);
+            keyv.push_back(pr.rule);
+            keyv.insert(keyv.end(), pr.preds.begin(), pr.preds.end());
+        }
+        auto it = seen.find(keyv);
+        if (it == seen.end()) {
+            std::vector<Instr> code = emit_code(rel, rs, path, ka, R);
+            const uint32_t off = (uint32_t)all.size(), len = (uint32_t)code.size();
+            if (off >= (1u << 20) || len >= (1u << 12)) fail(HB_ERR_LIMIT, "too many distinct learned plans");
+            all.insert(all.end(), code.begin(), code.end());
+            it = seen.emplace(keyv, std::make_pair(off, len)).first;
+        }
+        blk[b] = (it->second.first << 12) | it->second.second;
+    }
+    kp.code = std::move(all);
+    kp.blk_plan.alloc(c, sizeof(uint32_t) * std::max<uint32_t>(nb, 1));
+    if (nb) HB_HIP(hipMemcpyAsync(kp.blk_plan.get(), blk.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice, c->stream));
+    kp.mp.blk_plan = kp.blk_plan.as<uint32_t>();
+    kp.mp.plan_len = 0;
+}
+
+static void log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t samples, uint64_t seed, float* features,
+                        float* labels, uint32_t* meta, uint64_t* counts, uint64_t cap, uint64_t* n_rows) {
+    Relation& rel = get_rel(c, rel_id);
+    RuleSet& rs = get_rs(c, rs_id, rel_id);
+    if (!n_rows) fail(HB_ERR_INVALID_ARG, "NULL n_rows");
+    if (samples == 0 || samples > 4096) fail(HB_ERR_INVALID_ARG, "samples must be in [1, 4096]");
+    if (!rs.partitioned) fail(HB_ERR_STATE, "hb_partition must run before hb_log_collect");
+    uint64_t total = 0;
+    struct Part {
+        std::vector<float> f;
+        std::vector<unsigned long long> cnt;
+        std::vector<uint16_t> pred;
+        uint32_t nb = 0, ns = 0;
+    };
+    std::vector<Part> parts(rs.keys.size());
+    for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
+        if (rel.parts.at(rs.keys[ka]).n_tiles == 0) continue;
+        KeyPlan kp;
+        KeyRes R;
+        if (!prepare_key(c, rel, rs, ka, kp, R, false)) continue;
+        DevBuf feat;
+        LearnParams L;
+        block_features(c, kp, R, feat, L);
+        const size_t rows = (size_t)kp.mp.n_blocks * L.n_spec;
+        DevBuf cnt(c, sizeof(unsigned long long) * 4 * std::max<size_t>(rows, 1));
+        zero(c, cnt.get(), cnt.size());
+        L.counts = cnt.as<unsigned long long>();
+        L.samples = samples;
+        L.seed = seed ^ ((uint64_t)ka << 56);
+        c->timed("log", [&] { return launch_log_samples(L, c->stream); });
+        Part& pt = parts[ka];
+        pt.nb = kp.mp.n_blocks;
+        pt.ns = L.n_spec;
+        pt.f.resize(rows * kFeatures);
+        pt.cnt.resize(rows * 4);
+        for (uint32_t x = 0; x < L.n_spec; ++x) pt.pred.push_back(L.spec[x].pred);
+        if (rows) {
+            HB_HIP(hipMemcpyAsync(pt.f.data(), feat.get(), sizeof(float) * pt.f.size(), hipMemcpyDeviceToHost, c->stream));
+            HB_HIP(hipMemcpyAsync(pt.cnt.data(), cnt.get(), sizeof(unsigned long long) * pt.cnt.size(),
+                                  hipMemcpyDeviceToHost, c->stream));
+        }
+        c->sync();
+        total += rows;
+    }
+    *n_rows = total;
+    if (cap < total) fail(HB_ERR_CAPACITY, "row capacity " + std::to_string(cap) + " < " + std::to_string(total));
+    uint64_t o = 0;
+    for (size_t ka = 0; ka < parts.size(); ++ka) {
+        const Part& pt = parts[ka];
+        for (uint32_t b = 0; b < pt.nb; ++b)
+            for (uint32_t x = 0; x < pt.ns; ++x, ++o) {
+                const size_t r = (size_t)b * pt.ns + x;
+                if (features) std::memcpy(features + o * kFeatures, pt.f.data() + r * kFeatures, sizeof(float) * kFeatures);
+                const double lanes = (double)pt.cnt[r * 4 + 0], first = (double)pt.cnt[r * 4 + 3];
+                const double cyc = (double)pt.cnt[r * 4 + 2];
+                if (labels) {
+                    labels[o * 2 + 0] = (float)(lanes > 0 ? first / lanes : 0.0);
+                    labels[o * 2 + 1] = (float)(std::log2(1.0 + (lanes > 0 ? cyc / (lanes / 64.0) : 0.0)) / 16.0);
+                }
+                if (meta) {
+                    meta[o * 3 + 0] = (uint32_t)ka;
+                    meta[o * 3 + 1] = b;
+                    meta[o * 3 + 2] = pt.pred[x];
+                }
+                if (counts)
+                    for (int k = 0; k < 4; ++k) counts[o * 4 + k] = pt.cnt[r * 4 + k];
+            }
+    }
 }
 
 // Per-operation cost model (int32 lane-ops): a fixed part per evaluated
@@ -634,13 +913,20 @@ static const double kOpBase[8] = {1, 4, 3, 12, 12, 2, 4, 4};
 static const double kOpUnit[8] = {0, 0, 0, 0, 0, 1, 17, 3};
 
 static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stats* ws = nullptr) {
-    std::vector<PathRule> path = plan == HB_PLAN_HEURISTIC ? epg_path(rs.sp, rs.cost, rs.rules) : given_path(rs.rules);
+    std::vector<PathRule> path = plan == HB_PLAN_GIVEN ? given_path(rs.rules) : epg_path(rs.sp, rs.cost, rs.rules);
     std::vector<KeyPlan> kps;
     size_t total_code = 0;
+    uint64_t n_learned = 0, n_fallback = 0;
     for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
         if (rel.parts.at(rs.keys[ka]).n_tiles == 0) continue;
         KeyPlan kp;
-        if (!build_key_plan(c, rel, rs, path, ka, kp, ws != nullptr)) continue;
+        if (plan == HB_PLAN_LEARNED) {
+            KeyRes R;
+            if (!prepare_key(c, rel, rs, ka, kp, R, ws != nullptr)) continue;
+            c->host_timed("learned_plan", [&] { learned_key_plan(c, rel, rs, ka, kp, R, path, &n_learned, &n_fallback); });
+        } else if (!build_key_plan(c, rel, rs, path, ka, kp, ws != nullptr)) {
+            continue;
+        }
         total_code += kp.code.size();
         kps.push_back(std::move(kp));
     }
@@ -692,9 +978,15 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
             ws->work[op] = h[op * 4 + 3];
         }
         ws->pairs = h[kCountPairs];
-        double ops = 0.0;
-        for (int op = 0; op < HB_N_OPKINDS; ++op) ops += kOpBase[op] * ws->lanes[op] + kOpUnit[op] * ws->work[op];
+        double ops = 0.0, bops = 0.0;
+        for (int op = 0; op < HB_N_OPKINDS; ++op) {
+            ops += kOpBase[op] * ws->lanes[op] + kOpUnit[op] * ws->work[op];
+            // cheap steps run for every lane of the batch; exact ones per pair
+            bops += op <= OP_JACF ? kOpBase[op] * (double)ws->waves[op] * kRows * 64
+                                  : kOpBase[op] * ws->lanes[op] + kOpUnit[op] * ws->work[op];
+        }
         ws->lane_ops = ops;
+        ws->batch_ops = bops;
         ws->matched = found;
         ws->launches = launches;
         return;
@@ -726,13 +1018,16 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
     c->last.matched_pairs = found;
     c->last.tiles = tiles;
     c->last.launches = launches;
+    c->last.learned_blocks = n_learned;
+    c->last.fallback_blocks = n_fallback;
 }
 
 static void match_work(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, hb_work_stats* ws) {
     Relation& rel = get_rel(c, rel_id);
     RuleSet& rs = get_rs(c, rs_id, rel_id);
     if (!ws) fail(HB_ERR_INVALID_ARG, "NULL stats");
-    if (plan != HB_PLAN_GIVEN && plan != HB_PLAN_HEURISTIC) fail(HB_ERR_INVALID_ARG, "unknown plan");
+    if (plan != HB_PLAN_GIVEN && plan != HB_PLAN_HEURISTIC && plan != HB_PLAN_LEARNED)
+        fail(HB_ERR_INVALID_ARG, "unknown plan");
     if (!rs.partitioned) fail(HB_ERR_STATE, "hb_partition must run before hb_match_work");
     run_match(c, rel, rs, plan, ws);
 }
@@ -742,7 +1037,8 @@ static void match(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, uint64_t* o
     Relation& rel = get_rel(c, rel_id);
     RuleSet& rs = get_rs(c, rs_id, rel_id);
     if (!n_pairs) fail(HB_ERR_INVALID_ARG, "NULL n_pairs");
-    if (plan != HB_PLAN_GIVEN && plan != HB_PLAN_HEURISTIC) fail(HB_ERR_INVALID_ARG, "unknown plan");
+    if (plan != HB_PLAN_GIVEN && plan != HB_PLAN_HEURISTIC && plan != HB_PLAN_LEARNED)
+        fail(HB_ERR_INVALID_ARG, "unknown plan");
     if (!rs.partitioned) fail(HB_ERR_STATE, "hb_partition must run before hb_match");
     if (!(rs.has_result && rs.result_plan == plan)) run_match(c, rel, rs, plan);
     *n_pairs = rs.n_result;
@@ -866,6 +1162,14 @@ hb_status hb_match(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t pl
 
 hb_status hb_match_work(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, hb_work_stats* out) {
     return guard(ctx, [&](Ctx* c) { hb::match_work(c, rel_id, ruleset_id, plan, out); });
+}
+
+hb_status hb_log_collect(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, uint32_t samples, uint64_t seed,
+                         float* features, float* labels, uint32_t* meta, uint64_t* counts, uint64_t cap_rows,
+                         uint64_t* n_rows) {
+    return guard(ctx, [&](Ctx* c) {
+        hb::log_collect(c, rel_id, ruleset_id, samples, seed, features, labels, meta, counts, cap_rows, n_rows);
+    });
 }
 
 hb_status hb_ruleset_estimates(hb_ctx* ctx, uint32_t ruleset_id, double* sp, double* cost, uint32_t cap, uint32_t* n) {

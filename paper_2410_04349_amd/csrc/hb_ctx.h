@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <chrono>
 #include <map>
 #include <memory>
 #include <string>
@@ -187,6 +188,19 @@ struct Ctx {
         HB_HIP(launch());
         HB_HIP(hipEventRecord(pd.b, stream));
         pending.push_back(pd);
+    }
+    // Host wall time of a step (including any synchronisation it does).
+    template <typename F>
+    void host_timed(const char* name, F&& work) {
+        if (!profiling) {
+            work();
+            return;
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        work();
+        auto& e = prof[name];
+        e.ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        e.launches += 1;
     }
     void drain_profile() {
         for (auto& pd : pending) {

@@ -199,9 +199,10 @@ hipError_t launch_ge2_flags(const uint32_t* gstart, uint32_t n_groups, uint32_t 
 // q-gram index
 hipError_t launch_gram_slots(const ColDev* col, uint32_t n, uint32_t q, uint64_t* slots,
                              hipStream_t s);
+// max_windows: the largest L - q + 1 of the column (sizes the LDS scratch)
 hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const uint64_t* off,
                              uint32_t* codes, uint32_t* cnt, uint8_t* flags,
-                             unsigned int* d_max_cnt, hipStream_t s);
+                             unsigned int* d_max_cnt, uint32_t max_windows, hipStream_t s);
 
 // character-presence signature of every string of a column
 hipError_t launch_char_sig(const ColDev* col, uint32_t n, uint64_t* sig, hipStream_t s);

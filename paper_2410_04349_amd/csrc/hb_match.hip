@@ -442,13 +442,13 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const I
             }
             }
             if constexpr (kCount) {
-                uint32_t ev = 0, ps = 0, waves = 0;
+                // batches: this step ran once for the wave's 16-row batch
+                uint32_t ev = 0, ps = 0;
                 for (int r = 0; r < kRows; ++r) {
-                    const uint64_t eb = __ballot((before >> r) & 1);
-                    ev += __popcll(eb);
+                    ev += __popcll(__ballot((before >> r) & 1));
                     ps += __popcll(__ballot((alive >> r) & 1));
-                    waves += eb ? 1u : 0u;
                 }
+                const uint32_t waves = 1;
                 uint32_t w = op <= OP_JACF ? 0u : work;
                 for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
                 if (op <= OP_JACF) w = ev;
@@ -661,7 +661,9 @@ __global__ __launch_bounds__(256) void k_block_features(const LearnParams L) {
 //   i = mix64(c + 64) mod n_b, j_l = mix64(c + l) mod n_b (l = lane; j_l = i
 //   is replaced by (i + 1) mod n_b), positions inside the block.
 // It accumulates per (block, predicate) the lanes, the lanes that satisfy
-// the predicate and the wave's clock cycles spent deciding it.
+// the predicate, the wave's clock cycles spent deciding it and the lanes
+// that pass its first plan step (the exact filter; for value predicates the
+// predicate itself).
 __global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
     extern __shared__ __align__(16) uint8_t lds[];
     const MatchParams& P = L.mp;
@@ -683,6 +685,7 @@ __global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
         const uint32_t res = sp.res;
         const uint64_t t0 = __builtin_readcyclecounter();
         bool r = feature_filter(L, sp, pi, pj);
+        const uint64_t filtered = __popcll(__ballot(r));
         if (sp.op == OP_EQ_STR && __any(r)) {
             const ColDev& col = P.cols[P.str_attr[res]];
             const uint32_t li = f32[(2 + res) * n + pi];
@@ -723,10 +726,11 @@ __global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
         const uint64_t passed = __popcll(__ballot(r));
         const uint64_t t1 = __builtin_readcyclecounter();
         if (lane == 0) {
-            unsigned long long* cnt = L.counts + ((size_t)b * L.n_spec + x) * 3;
+            unsigned long long* cnt = L.counts + ((size_t)b * L.n_spec + x) * 4;
             atomicAdd(&cnt[0], 64ull);
             atomicAdd(&cnt[1], (unsigned long long)passed);
             atomicAdd(&cnt[2], (unsigned long long)(t1 - t0));
+            atomicAdd(&cnt[3], (unsigned long long)filtered);
         }
     }
 }

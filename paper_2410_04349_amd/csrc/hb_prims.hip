@@ -340,12 +340,15 @@ __global__ void k_gram_slots(const ColDev* __restrict__ colp, uint32_t n, uint32
     slots[r] = s;
 }
 
-// One thread per row: write the window codes, insertion-sort them in place,
-// drop repeats.
+// One thread per row: the row's window codes are insertion-sorted in the
+// thread's own LDS segment of `seg` words (seg odd, so the threads of a wave
+// hit distinct banks), repeats dropped, and the list copied out.  seg = 0
+// (rows too long for LDS): the sort runs in place in the output list.
 __global__ void k_gram_build(const ColDev* __restrict__ colp, uint32_t n, uint32_t q,
                              const uint64_t* __restrict__ off, uint32_t* __restrict__ codes,
                              uint32_t* __restrict__ cnt, uint8_t* __restrict__ flags,
-                             unsigned int* __restrict__ max_cnt) {
+                             unsigned int* __restrict__ max_cnt, uint32_t seg) {
+    extern __shared__ uint32_t gram_lds[];
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t out_cnt = 0;
     if (r < n) {
@@ -353,8 +356,9 @@ __global__ void k_gram_build(const ColDev* __restrict__ colp, uint32_t n, uint32
         uint8_t f = 0;
         if (bit_valid(c.valid, r)) {
             const uint8_t* s = c.bytes + c.off[r];
-            uint32_t L = str_len(c, r);
+            const uint32_t L = str_len(c, r);
             uint32_t* dst = codes + off[r];
+            uint32_t* buf = seg ? gram_lds + (size_t)threadIdx.x * seg : dst;
             if (L > 0 && L < q) {
                 uint32_t v = 0;
                 for (uint32_t x = 0; x < L; ++x) v = (v << 8) | s[x];
@@ -362,20 +366,21 @@ __global__ void k_gram_build(const ColDev* __restrict__ colp, uint32_t n, uint32
                 out_cnt = 1;
                 f = 1;
             } else if (L >= q) {
-                uint32_t nw = L - q + 1;
+                const uint32_t nw = L - q + 1;
                 uint32_t v = 0;
                 for (uint32_t x = 0; x + 1 < q; ++x) v = (v << 8) | s[x];
                 const uint32_t mask = (q == 4) ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
                 for (uint32_t w = 0; w < nw; ++w) {
                     v = ((v << 8) | s[w + q - 1]) & mask;
-                    // insertion into the sorted prefix dst[0..w)
                     uint32_t p = w;
-                    while (p > 0 && dst[p - 1] > v) { dst[p] = dst[p - 1]; --p; }
-                    dst[p] = v;
+                    while (p > 0 && buf[p - 1] > v) { buf[p] = buf[p - 1]; --p; }
+                    buf[p] = v;
                 }
                 uint32_t u = 0;
-                for (uint32_t w = 0; w < nw; ++w)
-                    if (u == 0 || dst[u - 1] != dst[w]) dst[u++] = dst[w];
+                for (uint32_t w = 0; w < nw; ++w) {
+                    const uint32_t x = buf[w];
+                    if (u == 0 || dst[u - 1] != x) dst[u++] = x;
+                }
                 out_cnt = u;
             }
         }
@@ -385,7 +390,6 @@ __global__ void k_gram_build(const ColDev* __restrict__ colp, uint32_t n, uint32
     for (int o = 32; o > 0; o >>= 1) out_cnt = max(out_cnt, (uint32_t)__shfl_xor((int)out_cnt, o));
     if ((threadIdx.x & 63) == 0) atomicMax(max_cnt, out_cnt);
 }
-
 
 // ------------------------------------------------------------ features
 
@@ -670,8 +674,20 @@ hipError_t launch_gram_slots(const ColDev* col, uint32_t n, uint32_t q, uint64_t
 
 hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const uint64_t* off,
                              uint32_t* codes, uint32_t* cnt, uint8_t* flags,
-                             unsigned int* d_max_cnt, hipStream_t s) {
-    k_gram_build<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
+                             unsigned int* d_max_cnt, uint32_t max_windows, hipStream_t s) {
+    // LDS segment per thread: the longest row's window count, made odd
+    uint32_t seg = (max_windows < 1 ? 1 : max_windows) | 1u;
+    uint32_t threads = 256;
+    while (threads > 64 && (size_t)threads * seg * 4 > 64 * 1024) threads -= 64;
+    if ((size_t)threads * seg * 4 > 128 * 1024) seg = 0;    // sort in place in HBM instead
+    const size_t lds = (size_t)threads * seg * 4;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_gram_build, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const uint32_t grid = (n + threads - 1) / threads;
+    k_gram_build<<<grid ? grid : 1, threads, lds, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt, seg);
     return hipGetLastError();
 }
 

@@ -1,0 +1,181 @@
+"""GPU tests of the learned plan: the logging pass against the oracle on the
+same sampled pairs, bit-exact output of the learned plan, and its gain in
+algorithmic work over the heuristic plan."""
+import numpy as np
+import pytest
+
+import oracle
+from gen import workloads
+
+pytestmark = pytest.mark.gpu
+
+MASK = (1 << 64) - 1
+
+
+def mix64(z):
+    z &= MASK
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK
+    return z ^ (z >> 31)
+
+
+@pytest.fixture(scope="module")
+def hb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_04349_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(hb):
+    c = hb.hb_create(0, allocator="torch")
+    yield c
+    c.close()
+
+
+def distinct_preds(rules):
+    out = []
+    for r in rules:
+        for p in r:
+            if p not in out:
+                out.append(p)
+    return out
+
+
+def key_blocks(rel, key):
+    """Blocks of the key partition: rows sharing a key value (>= 2), in
+    ascending key value, rows ascending inside a block."""
+    vals = rel.columns[key].values
+    order = np.lexsort((np.arange(rel.n_rows), vals))
+    blocks = []
+    s = 0
+    while s < len(order):
+        e = s
+        while e + 1 < len(order) and vals[order[e + 1]] == vals[order[s]]:
+            e += 1
+        if e > s:
+            blocks.append(order[s:e + 1])
+        s = e + 1
+    return blocks
+
+
+def run(hb, ctx, rel, rules, plan):
+    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+    rs = hb.hb_compile_rules(ctx, rid, rules)
+    hb.hb_partition(ctx, rid, rs)
+    out = hb.hb_match(ctx, rid, rs, plan)
+    stats = hb.hb_last_match_stats(ctx)
+    work = hb.hb_match_work(ctx, rid, rs, plan)
+    hb.hb_release_relation(ctx, rid)
+    return out, stats, work
+
+
+def collect(hb, ctx, rel, rules, samples, seed):
+    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+    rs = hb.hb_compile_rules(ctx, rid, rules)
+    hb.hb_partition(ctx, rid, rs)
+    log = hb.hb_log_collect(ctx, rid, rs, samples, seed)
+    hb.hb_release_relation(ctx, rid)
+    return log
+
+
+def test_log_pass_counts_match_oracle(hb, ctx):
+    print("[gpu-case] log pass counts", flush=True)
+    rel, rules = workloads.plain_1m(n=6000)
+    samples, seed = 2, 12345
+    log = collect(hb, ctx, rel, rules, samples, seed)
+    dp = distinct_preds(rules)
+    key = rules[0][0].attr
+    blocks = key_blocks(rel, key)
+    assert log["meta"][:, 1].max() + 1 == len(blocks)
+    # oracle: the same sampled pairs, each predicate by the definition
+    pairs, where = [], []
+    for b, rows in enumerate(blocks):
+        nb = len(rows)
+        for s in range(samples):
+            c = (seed + ((b * samples + s) << 7)) & MASK
+            i = mix64(c + 64) % nb
+            for l in range(64):
+                j = mix64(c + l) % nb
+                if j == i:
+                    j = (i + 1) % nb
+                pairs.append((int(rows[i]), int(rows[j])))
+                where.append(b)
+    where = np.array(where)
+    checked = 0
+    for row in range(len(log["meta"])):
+        _, b, pid = (int(x) for x in log["meta"][row])
+        pred = dp[pid]
+        sel = np.flatnonzero(where == b)
+        want = sum(oracle.sat(rel, pred, pairs[k][0], pairs[k][1]) for k in sel)
+        assert int(log["counts"][row, 0]) == len(sel)
+        assert int(log["counts"][row, 1]) == want, (b, pred)
+        # the first step is a necessary condition of the predicate
+        assert want <= int(log["counts"][row, 3]) <= len(sel)
+        checked += 1
+    assert checked > 0
+    assert np.all((log["labels"][:, 0] >= 0) & (log["labels"][:, 0] <= 1))
+    assert np.all(log["labels"][:, 1] > 0)
+
+
+def train_model(hb, ctx):
+    xs, ts = [], []
+    for rel, rules in (workloads.person_small(), workloads.plain_1m(n=100_000)):
+        log = collect(hb, ctx, rel, rules, 4, 7)
+        xs.append(log["features"])
+        ts.append(log["labels"])
+    x = np.concatenate(xs)
+    t = np.concatenate(ts)
+    perm = np.random.default_rng(0).permutation(len(x))
+    hb.hb_costmodel_init(ctx, 3)
+    return hb.hb_costmodel_train(ctx, x[perm], t[perm], epochs=40, batch=256, lr=2e-3)
+
+
+@pytest.fixture(scope="module")
+def trained(hb, ctx):
+    loss = train_model(hb, ctx)
+    assert np.isfinite(loss)
+    return loss
+
+
+def test_learned_plan_bitexact_and_cheaper(hb, ctx, trained):
+    print("[gpu-case] learned plan", flush=True)
+    rel, rules = workloads.plain_1m(n=60_000)
+    want = oracle.blocking(rel, rules, threads=8)
+    got_h, st_h, work_h = run(hb, ctx, rel, rules, "heuristic")
+    got_l, st_l, work_l = run(hb, ctx, rel, rules, "learned")
+    assert np.array_equal(got_h, want)
+    assert np.array_equal(got_l, want)
+    assert st_l["learned_blocks"] + st_l["fallback_blocks"] > 0
+    print(f"[gpu-case] batch-ops heuristic {work_h['batch_ops']:.4e} learned {work_l['batch_ops']:.4e} "
+          f"learned blocks {st_l['learned_blocks']} fallback {st_l['fallback_blocks']}", flush=True)
+    for name in work_h["per_op"]:
+        h, l = work_h["per_op"][name], work_l["per_op"][name]
+        print(f"[gpu-case]   {name}: waves {h['waves']} -> {l['waves']}, lanes {h['lanes']} -> {l['lanes']}, "
+              f"work {h['work']} -> {l['work']}", flush=True)
+    # the gain: SIMD work the plan causes (steps run for a wave's whole batch)
+    assert work_l["batch_ops"] < work_h["batch_ops"]
+
+
+def test_learned_plan_two_keys_twenty_rules(hb, ctx, trained):
+    # the 10M two-key recipe at 20k tuples: per-key learned plans, pinned
+    # (key-correlated) string columns
+    print("[gpu-case] learned plan, two keys", flush=True)
+    rel, rules = workloads.learned_10m(n=20_000)
+    want = oracle.blocking(rel, rules, threads=16)
+    got_h, _, work_h = run(hb, ctx, rel, rules, "heuristic")
+    got_l, st_l, work_l = run(hb, ctx, rel, rules, "learned")
+    assert np.array_equal(got_h, want)
+    assert np.array_equal(got_l, want)
+    print(f"[gpu-case] batch-ops heuristic {work_h['batch_ops']:.4e} learned {work_l['batch_ops']:.4e} "
+          f"learned blocks {st_l['learned_blocks']} fallback {st_l['fallback_blocks']}", flush=True)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_learned_plan_random_small(hb, ctx, trained, seed):
+    rel, rules = workloads.random_small(2000 + seed, n=300, n_keys=1 + seed % 3)
+    want = oracle.blocking(rel, rules, threads=8)
+    got, _, _ = run(hb, ctx, rel, rules, "learned")
+    assert np.array_equal(got, want)
