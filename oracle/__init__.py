@@ -55,13 +55,20 @@ def _load():
     global _lib
     if _lib is None:
         lib = ctypes.CDLL(build_lib())
-        lib.ora_levenshtein.restype = ctypes.c_int64
-        lib.ora_jaccard_ge.restype = ctypes.c_int
-        lib.ora_sat.restype = ctypes.c_int
-        lib.ora_rule_witness.restype = ctypes.c_int
-        lib.ora_blocking.restype = ctypes.c_int64
-        lib.ora_candidate_count.restype = ctypes.c_int64
-        lib.ora_eval_pairs.restype = ctypes.c_int
+        P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        # full prototypes: 64-bit sizes must not travel as C ints
+        for name, res, args in (
+                ("ora_levenshtein", ctypes.c_int64, [P, U64, P, U64]),
+                ("ora_qgram_stats", None, [P, U64, P, U64, U32, P, P, P]),
+                ("ora_jaccard_ge", I, [P, U64, P, U64, U32, U32, U32]),
+                ("ora_sat", I, [P, P, U64, U64]),
+                ("ora_rule_witness", I, [P, U32, P, U64, U64]),
+                ("ora_blocking", ctypes.c_int64, [P, U32, U64, U32, P, P, I, I, P, U64]),
+                ("ora_candidate_count", ctypes.c_int64, [P, U64, U32, P, P]),
+                ("ora_eval_pairs", I, [P, U64, U32, P, P, P, U64, I, P])):
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
         _lib = lib
     return _lib
 
