@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="run one 256 MiB device copy first (scale reference for HBM counters)")
+                    help="run one 256 MiB read + 256 MiB write kernel first (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
@@ -106,11 +106,11 @@ def main():
     log(f"[bench] generated {rel.n_rows} tuples in {time.perf_counter() - t:.1f}s")
     torch.cuda.set_device(0)
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+        # one elementwise kernel that reads 256 MiB and writes 256 MiB
+        a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        a.fill_(1)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
     cols = device_columns(rel, torch)
@@ -161,7 +161,8 @@ def main():
         t1 = time.perf_counter()
         hb.hb_profile_enable(ctx, False)
         prof = {}
-        for name in ("match", "partition_sort", "gram_build", "lsh", "output_sort", "learned_plan"):
+        for name in ("match", "partition_sort", "gram_build", "lsh", "output_sort", "learned_plan",
+                     "block_features", "predict", "plan_choice"):
             ms, launches = hb.hb_profile_query(ctx, name)
             prof[name] = {"ms_total": ms, "launches": launches}
         ms_step = (t1 - t0) * 1000.0 / args.steps

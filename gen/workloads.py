@@ -22,6 +22,13 @@ restated in the design notes.
                  i2 U[1900,2024]; 20 seeded rules, 10 per key, each the key
                  equality, one predicate on s1..s4 and 1-3 more from the
                  plain menu (ED<=1..3, J3>=1/2..4/5, |diff|<=2).
+  long_titles_5m 5,000,000 product titles (4.5M base + 0.5M duplicates with
+                 1-8 char edits); title = pseudo-words (30k words of 2-10
+                 a-z letters, Zipf s=1.0 word frequencies) cut to a length
+                 U[20, 200]; brand capped Zipf s=1.3 over 100k values with
+                 cap 18, the smallest cap giving 50M +- 10% candidate pairs
+                 (46,306,524 at 5M); one rule
+                 brand= AND J2(title)>=7/10 AND ED(title)<=8.
   random_small   adversarial small relations for parity (lengths 0, q-1,
                  63/64/65, 127/128/129, 200; nulls; tiny alphabets; several
                  keys; rule sets with the key equality anywhere in a rule).
@@ -132,6 +139,22 @@ def learned_10m(seed: int = SEED_BASE + 4, n: int = 10_000_000):
     cap = max(8, int(round(5000 * min(1.0, scale * 20))))
     rel = generate(seed, n - n_dup, n_dup, learned_10m_attrs(n_values, cap), edit_min=1, edit_max=3)
     return rel, learned_10m_rules()
+
+
+# ------------------------------------------------------------ long titles
+
+def long_titles_5m(seed: int = SEED_BASE + 5, n: int = 5_000_000):
+    """Long strings and skewed keys; `n` scales it down (brand cardinality
+    scaled with n, the cap of 18 tuples per code kept)."""
+    n_dup = n // 10
+    n_values = max(50, int(round(100_000 * n / 5_000_000)))
+    attrs = [
+        AttrSpec("brand", "zipf", zipf_s=1.3, n_values=n_values, cap=18),
+        AttrSpec("title", "words", min_len=20, max_len=200, zipf_s=1.0, n_values=30_000),
+    ]
+    rel = generate(seed, n - n_dup, n_dup, attrs, edit_min=1, edit_max=8)
+    rules = [[Pred(EQ, 0), Pred(JACCARD, 1, q=2, num=7, den=10), Pred(ED, 1, k=8)]]
+    return rel, rules
 
 
 # ------------------------------------------------------------ adversarial

@@ -150,13 +150,17 @@ hb_status hb_partition(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id,
  *                      order, execution tree, edge scores, DFS order);
  *   HB_PLAN_LEARNED    a plan per block from the context's cost model (a
  *                      different plan on each partition, the paper's future
- *                      topic in Section 8): each rule's predicates ordered by
- *                      predicted cycles / (1 - probability that some pair of
- *                      a wave's 16 x 64 batch survives them), rules by
- *                      predicted witness probability per cycle; a block keeps
- *                      the heuristic plan unless the model predicts the
- *                      learned one 2% cheaper.  Needs a cost model
- *                      (HB_ERR_STATE otherwise). */
+ *                      topic in Section 8), rules in the heuristic order:
+ *                      per rule, the first-stage steps (value predicates and
+ *                      exact filters) by step cost / (1 - probability that
+ *                      some pair of the block's wave batch of
+ *                      min(n, 16) x min(n, 64) pairs passes, from the
+ *                      model's predicted pass rate), and the exact checks by
+ *                      predicted cycles; each order is kept only where the
+ *                      model expects it 2% cheaper than the heuristic one.
+ *                      Blocks of fewer than 16 tuples keep the heuristic
+ *                      plan.  Built on the device (no host round trip).
+ *                      Needs a cost model (HB_ERR_STATE otherwise). */
 typedef enum { HB_PLAN_GIVEN = 0, HB_PLAN_HEURISTIC = 1, HB_PLAN_LEARNED = 2 } hb_plan;
 
 /* Evaluate the rule set on every candidate pair and return Ca(D): packed
@@ -192,9 +196,10 @@ hb_status hb_epg_path(uint32_t n_preds, const double* sp, const double* cost, ui
 
 /* Kernel timing: when enabled, HIP events bracket each kernel launch of the
  * named step on the context stream.  Names: "match", "partition_sort",
- * "gram_build", "lsh", "output_sort", "log"; and "learned_plan", the host
- * wall time of building one key partition's per-block learned plans (block
- * features, model inference and plan choice, with their synchronisation). */
+ * "gram_build", "lsh", "output_sort", "log", "block_features",
+ * "plan_choice"; and, as host wall time including synchronisation,
+ * "learned_plan" (building one key partition's per-block learned plans) and
+ * "predict" (cost-model inference inside it). */
 hb_status hb_profile_enable(hb_ctx* ctx, int on);
 hb_status hb_profile_query(hb_ctx* ctx, const char* name, double* total_ms, uint64_t* launches);
 hb_status hb_profile_reset(hb_ctx* ctx);

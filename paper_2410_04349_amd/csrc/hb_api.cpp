@@ -424,7 +424,11 @@ static void partition(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint64_t* n_cand)
 struct KeyPlan {
     std::vector<Instr> code;
     MatchParams mp{};
-    DevBuf f64, f32, blk_plan;
+    DevBuf f64, f32;
+    // learned plans: per-slot plans on the device, the block -> slot map and
+    // the choice kernel's counters (read after matching)
+    bool own_code = false;
+    DevBuf dev_code, blk_slot, choice_stats;
 };
 
 static uint32_t align_up(uint32_t v, uint32_t a) { return (v + a - 1) / a * a; }
@@ -570,6 +574,15 @@ static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, cons
                 break;
             }
         }
+        if (!pr.verify.empty()) {
+            // the exact checks in the given order
+            std::vector<Instr> ordered;
+            for (uint32_t p : pr.verify)
+                for (const Instr& in : verify)
+                    if (in.slot == (uint8_t)p) ordered.push_back(in);
+            if (ordered.size() != verify.size()) fail(HB_ERR_STATE, "internal: verification order mismatch");
+            verify.swap(ordered);
+        }
         code.insert(code.end(), verify.begin(), verify.end());
         Instr cp{};
         cp.op = OP_CP;
@@ -677,163 +690,97 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
 
 // ------------------------------------------------------------ learned plan
 
-// The model's per-(block, predicate) outputs: the pass rate of the
-// predicate's first plan step (its exact filter) and log-scaled cycles of a
-// wave evaluating the whole predicate.
-struct Estimate {
-    double pass, cycles;
-};
-
-static Estimate decode_estimate(float y0, float y1) {
-    Estimate e;
-    e.pass = std::isfinite(y0) ? std::min(1.0, std::max(0.0, (double)y0)) : 1.0;
-    e.cycles = std::isfinite(y1) ? std::exp2(std::min(30.0, std::max(0.0, 16.0 * (double)y1))) : 1e9;
-    return e;
-}
-
-// Plan operation of each distinct predicate in one key partition (kNoStep:
-// not evaluated there, e.g. the partition's own key equality).
-static constexpr uint8_t kNoStep = 0xFF;
-
-static std::vector<uint8_t> step_kinds(const RuleSet& rs, const KeyRes& R) {
-    std::vector<uint8_t> kind(rs.distinct.size(), kNoStep);
-    for (const PredSpec& sp : R.specs) kind[sp.pred] = (uint8_t)sp.op;
-    return kind;
-}
-
-// Cost of a predicate's first-stage step for one row of a wave batch, in the
-// library's per-operation lane-op units (data-independent).
-static double first_step_cost(uint8_t kind) {
-    switch (kind) {
-    case kNoStep: return 0.0;
-    case OP_EQ_INT: return 1.0;
-    case OP_ABSDIFF: return 4.0;
-    case OP_EQ_STR: return 3.0;
-    default: return 12.0;
-    }
-}
-
-static bool needs_verify(uint8_t kind) { return kind == OP_EQ_STR || kind == OP_ED || kind == OP_JAC; }
-
-// Probability that some pair of a wave batch of `batch` pairs passes a step
-// that each pair passes with probability `pass`.
-static double batch_pass(double pass, double batch) { return 1.0 - std::pow(1.0 - pass, batch); }
-
-// Expected cost of one wave batch running a path: a step runs while some
-// pair of the batch is still alive.  First stage: static step costs, per
-// row; second stage (exact checks): the model's cycles, once the batch
-// survived all of the rule's filters.
-static double expected_cost(const std::vector<uint8_t>& kind, const std::vector<PathRule>& path,
-                            const std::vector<Estimate>& est, double batch) {
-    double total = 0.0;
-    for (const PathRule& pr : path) {
-        double reach = 1.0;
-        for (uint32_t p : pr.preds) {
-            total += reach * first_step_cost(kind[p]) * kRows * 64.0;
-            reach *= batch_pass(est[p].pass, batch);
-        }
-        for (uint32_t p : pr.preds)
-            if (needs_verify(kind[p])) total += reach * est[p].cycles;
-    }
-    return total;
-}
-
-// Per-block order: within a rule, predicates by first-step cost / (1 - q)
-// ascending, q = the probability that some pair of the wave batch passes
-// the step; rules by witness probability (product of pass rates) per
-// expected cost, descending.
-static std::vector<PathRule> learned_path(const RuleSet& rs, const std::vector<uint8_t>& kind,
-                                          const std::vector<Estimate>& est, double batch) {
-    std::vector<PathRule> out;
-    std::vector<double> score;
-    for (uint32_t r = 0; r < rs.rules.size(); ++r) {
-        PathRule pr;
-        pr.rule = r;
-        for (uint32_t p : rs.rules[r])
-            if (std::find(pr.preds.begin(), pr.preds.end(), p) == pr.preds.end()) pr.preds.push_back(p);
-        auto rank = [&](uint32_t p) {
-            return first_step_cost(kind[p]) / std::max(1e-12, 1.0 - batch_pass(est[p].pass, batch));
-        };
-        std::stable_sort(pr.preds.begin(), pr.preds.end(), [&](uint32_t a, uint32_t b) { return rank(a) < rank(b); });
-        double wp = 1.0;
-        for (uint32_t p : pr.preds) wp *= est[p].pass;
-        const double cost = expected_cost(kind, {pr}, est, batch);
-        score.push_back(wp / std::max(cost, 1e-12));
-        out.push_back(pr);
-    }
-    std::vector<size_t> idx(out.size());
-    for (size_t x = 0; x < idx.size(); ++x) idx[x] = x;
-    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return score[a] > score[b]; });
-    std::vector<PathRule> sorted;
-    for (size_t x : idx) sorted.push_back(out[x]);
-    return sorted;
-}
-
 // Features of every (block, predicate) of key `ka` into `feat` (device).
-static void block_features(Ctx* c, const KeyPlan& kp, const KeyRes& R, DevBuf& feat, LearnParams& L) {
+static void block_features(Ctx* c, const KeyPlan& kp, const KeyRes& R, DevBuf& feat, LearnParams& L,
+                           uint32_t min_size) {
     if (R.specs.size() > (size_t)kMaxSpecs) fail(HB_ERR_LIMIT, "more than 64 predicates in one partition");
     L = LearnParams{};
     L.mp = kp.mp;
+    L.min_size = min_size;
     for (size_t x = 0; x < R.specs.size(); ++x) L.spec[x] = R.specs[x];
     L.n_spec = (uint32_t)R.specs.size();
     feat.alloc(c, sizeof(float) * kFeatures * std::max<size_t>((size_t)kp.mp.n_blocks * L.n_spec, 1));
     L.features = feat.as<float>();
-    HB_HIP(launch_block_features(L, c->stream));
+    c->timed("block_features", [&] { return launch_block_features(L, c->stream); });
 }
 
-// Learned per-block plans for key `ka`: fills kp.code with the distinct
-// plans and kp.blk_plan with each block's (offset << 12) | length.
+static uint32_t next_pow2(uint32_t v) {
+    uint32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Learned per-block plans for key `ka`, built on the device without a host
+// round trip: block features, cost-model inference (per block and
+// predicate: the first plan step's pass rate and the exact check's cycles)
+// and the plan-choice kernel, which writes each distinct choice's plan.
+// Blocks smaller than one wave batch's rows keep the heuristic plan.
 static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& kp, const KeyRes& R,
-                             const std::vector<PathRule>& heuristic, uint64_t* n_learned, uint64_t* n_fallback) {
+                             const std::vector<PathRule>& heuristic, uint64_t* n_fallback) {
     if (!c->model.ready) fail(HB_ERR_STATE, "the learned plan needs a cost model (hb_costmodel_train or _set_params)");
     const uint32_t nb = kp.mp.n_blocks;
     const uint32_t ns = (uint32_t)R.specs.size();
-    std::vector<float> y((size_t)nb * ns * 2, 0.f);
-    if (ns > 0 && nb > 0) {
-        DevBuf feat;
-        LearnParams L;
-        block_features(c, kp, R, feat, L);
-        costmodel_predict(c, feat.as<float>(), (uint64_t)nb * ns, 1, y.data(), 0);
-    }
-    std::vector<uint32_t> sizes(nb);
-    if (nb) {
-        HB_HIP(hipMemcpyAsync(sizes.data(), kp.mp.blk_size, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream));
-        c->sync();
-    }
-    std::map<std::vector<uint32_t>, std::pair<uint32_t, uint32_t>> seen;   // flattened path -> (offset, length)
-    std::vector<Instr> all;
-    std::vector<uint32_t> blk(nb);
-    std::vector<Estimate> est(rs.distinct.size(), Estimate{1.0, 1.0});
-    const std::vector<uint8_t> kind = step_kinds(rs, R);
-    for (uint32_t b = 0; b < nb; ++b) {
-        for (uint32_t x = 0; x < ns; ++x)
-            est[R.specs[x].pred] = decode_estimate(y[((size_t)b * ns + x) * 2], y[((size_t)b * ns + x) * 2 + 1]);
-        const double batch = (double)std::min<uint32_t>(sizes[b], kRows) * (double)std::min<uint32_t>(sizes[b], kTile);
-        std::vector<PathRule> lp = learned_path(rs, kind, est, batch);
-        const bool better = expected_cost(kind, lp, est, batch) < 0.98 * expected_cost(kind, heuristic, est, batch);
-        const std::vector<PathRule>& path = better ? lp : heuristic;
-        (better ? *n_learned : *n_fallback) += 1;
-        std::vector<uint32_t> keyv;
-        for (const PathRule& pr : path) {
-            keyv.push_back(0xFFFFFFFFu);
-            keyv.push_back(pr.rule);
-            keyv.insert(keyv.end(), pr.preds.begin(), pr.preds.end());
+    kp.code = emit_code(rel, rs, heuristic, ka, R);
+    kp.mp.plan_len = (uint32_t)kp.code.size();
+    // the partition's rules in heuristic order, each with its steps
+    std::vector<int> spec_of(rs.distinct.size(), -1);
+    for (uint32_t x = 0; x < ns; ++x) spec_of[R.specs[x].pred] = (int)x;
+    PlanChoiceParams C{};
+    uint32_t n_rules = 0, seg = 0;
+    bool ok = nb > 0 && ns > 0;
+    for (const PathRule& pr : heuristic) {
+        if (!ok || !rule_possible(rel, rs, pr.preds, ka)) continue;
+        if (n_rules >= (uint32_t)kMaxPlanRules) {
+            ok = false;
+            break;
         }
-        auto it = seen.find(keyv);
-        if (it == seen.end()) {
-            std::vector<Instr> code = emit_code(rel, rs, path, ka, R);
-            const uint32_t off = (uint32_t)all.size(), len = (uint32_t)code.size();
-            if (off >= (1u << 20) || len >= (1u << 12)) fail(HB_ERR_LIMIT, "too many distinct learned plans");
-            all.insert(all.end(), code.begin(), code.end());
-            it = seen.emplace(keyv, std::make_pair(off, len)).first;
+        uint32_t len = 0, nv = 0;
+        for (uint32_t p : pr.preds) {
+            if (spec_of[p] < 0) continue;
+            if (len >= (uint32_t)kMaxRuleSteps) fail(HB_ERR_LIMIT, "rule with more than 10 steps");
+            C.rule_spec[n_rules][len++] = (uint8_t)spec_of[p];
+            const uint8_t op = (uint8_t)R.specs[spec_of[p]].op;
+            nv += op == OP_EQ_STR || op == OP_ED || op == OP_JAC;
         }
-        blk[b] = (it->second.first << 12) | it->second.second;
+        C.rule_len[n_rules++] = (uint8_t)len;
+        seg += len + nv + 1;
     }
-    kp.code = std::move(all);
-    kp.blk_plan.alloc(c, sizeof(uint32_t) * std::max<uint32_t>(nb, 1));
-    if (nb) HB_HIP(hipMemcpyAsync(kp.blk_plan.get(), blk.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice, c->stream));
-    kp.mp.blk_plan = kp.blk_plan.as<uint32_t>();
-    kp.mp.plan_len = 0;
+    // the device rewrite relies on the segment layout of the heuristic plan
+    if (!ok || n_rules == 0 || seg != kp.mp.plan_len) {
+        *n_fallback += nb;
+        return;
+    }
+    DevBuf feat;
+    LearnParams L;
+    block_features(c, kp, R, feat, L, kRows);
+    DevBuf y(c, sizeof(float) * 2 * (size_t)nb * ns);
+    c->host_timed("predict", [&] { costmodel_predict(c, feat.as<float>(), (uint64_t)nb * ns, 1, y.as<float>(), 1); });
+
+    C.y = y.as<float>();
+    C.blk_size = kp.mp.blk_size;
+    C.n_blocks = nb;
+    C.n_spec = ns;
+    C.n_rules = n_rules;
+    C.n_slots = std::min<uint32_t>(kPlanSlots, next_pow2(std::max<uint32_t>(2 * nb, 16)));
+    C.plan_len = kp.mp.plan_len;
+    C.min_size = kRows;
+    for (uint32_t x = 0; x < ns; ++x) C.spec_kind[x] = (uint8_t)R.specs[x].op;
+    DevBuf keys(c, sizeof(unsigned long long) * C.n_slots);
+    kp.dev_code.alloc(c, sizeof(Instr) * (size_t)C.n_slots * C.plan_len);
+    kp.blk_slot.alloc(c, sizeof(uint32_t) * nb);
+    kp.choice_stats.alloc(c, sizeof(unsigned long long) * 3);
+    zero(c, keys.get(), keys.size());
+    zero(c, kp.choice_stats.get(), kp.choice_stats.size());
+    HB_HIP(hipMemcpyAsync(kp.dev_code.get(), kp.code.data(), sizeof(Instr) * kp.code.size(), hipMemcpyHostToDevice,
+                          c->stream));
+    C.keys = keys.as<unsigned long long>();
+    C.code = kp.dev_code.as<Instr>();
+    C.blk_slot = kp.blk_slot.as<uint32_t>();
+    C.stats = kp.choice_stats.as<unsigned long long>();
+    c->timed("plan_choice", [&] { return launch_plan_choice(C, c->stream); });
+    kp.own_code = true;
+    kp.mp.plan = kp.dev_code.as<Instr>();
+    kp.mp.blk_slot = kp.blk_slot.as<uint32_t>();
 }
 
 static void log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t samples, uint64_t seed, float* features,
@@ -858,7 +805,7 @@ static void log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t sample
         if (!prepare_key(c, rel, rs, ka, kp, R, false)) continue;
         DevBuf feat;
         LearnParams L;
-        block_features(c, kp, R, feat, L);
+        block_features(c, kp, R, feat, L, 0);
         const size_t rows = (size_t)kp.mp.n_blocks * L.n_spec;
         DevBuf cnt(c, sizeof(unsigned long long) * 4 * std::max<size_t>(rows, 1));
         zero(c, cnt.get(), cnt.size());
@@ -923,11 +870,11 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
         if (plan == HB_PLAN_LEARNED) {
             KeyRes R;
             if (!prepare_key(c, rel, rs, ka, kp, R, ws != nullptr)) continue;
-            c->host_timed("learned_plan", [&] { learned_key_plan(c, rel, rs, ka, kp, R, path, &n_learned, &n_fallback); });
+            c->host_timed("learned_plan", [&] { learned_key_plan(c, rel, rs, ka, kp, R, path, &n_fallback); });
         } else if (!build_key_plan(c, rel, rs, path, ka, kp, ws != nullptr)) {
             continue;
         }
-        total_code += kp.code.size();
+        if (!kp.own_code) total_code += kp.code.size();
         kps.push_back(std::move(kp));
     }
     DevBuf code(c, sizeof(Instr) * std::max<size_t>(total_code, 1));
@@ -935,13 +882,15 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
     if (ws) zero(c, counts.get(), counts.size());
     {
         std::vector<Instr> all;
-        for (KeyPlan& kp : kps) all.insert(all.end(), kp.code.begin(), kp.code.end());
+        for (KeyPlan& kp : kps)
+            if (!kp.own_code) all.insert(all.end(), kp.code.begin(), kp.code.end());
         if (!all.empty())
             HB_HIP(hipMemcpyAsync(code.get(), all.data(), sizeof(Instr) * all.size(), hipMemcpyHostToDevice, c->stream));
         size_t o = 0;
         for (KeyPlan& kp : kps) {
-            kp.mp.plan = code.as<Instr>() + o;
             kp.mp.counts = ws ? counts.as<unsigned long long>() : nullptr;
+            if (kp.own_code) continue;
+            kp.mp.plan = code.as<Instr>() + o;
             o += kp.code.size();
         }
     }
@@ -962,6 +911,15 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
             ++launches;
         }
         found = read1(c, counter.as<unsigned long long>());
+        if (attempt == 0)
+            for (KeyPlan& kp : kps) {
+                if (!kp.own_code) continue;
+                unsigned long long st[3];
+                HB_HIP(hipMemcpyAsync(st, kp.choice_stats.get(), sizeof(st), hipMemcpyDeviceToHost, c->stream));
+                c->sync();
+                n_learned += st[0];
+                n_fallback += kp.mp.n_blocks - st[0];
+            }
         if (ws || found <= cap) break;
         cap = found;
         out.alloc(c, sizeof(uint64_t) * cap);

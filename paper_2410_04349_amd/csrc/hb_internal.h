@@ -127,9 +127,10 @@ struct MatchParams {
     // passed, work units}, then pairs evaluated; nullptr in the normal pass
     unsigned long long* counts;
     uint32_t lds_counts;
-    // per-block plans (learned): blk_plan[b] = (offset << 12) | length of
-    // block b's instructions in `plan`; nullptr = one plan for every block
-    const uint32_t* blk_plan;
+    // per-block plans (learned): block b runs the plan_len instructions at
+    // plan + blk_slot[b] * plan_len; blk_slot == nullptr: one plan for every
+    // block
+    const uint32_t* blk_slot;
 };
 
 // Gather of the block-major feature columns.
@@ -240,10 +241,40 @@ struct LearnParams {
     uint32_t samples;                // logging: sampled waves per block
     uint64_t seed;
     float* features;                 // [n_blocks x n_spec x 16]
-    unsigned long long* counts;      // logging: [n_blocks x n_spec x 3] {lanes, passed, cycles}
+    uint32_t min_size;               // features: blocks smaller than this get zeros
+    unsigned long long* counts;      // logging: [n_blocks x n_spec x 4] {lanes, passed, cycles, first step passed}
 };
 hipError_t launch_block_features(const LearnParams& p, hipStream_t s);
 hipError_t launch_log_samples(const LearnParams& p, hipStream_t s);
+
+// Per-block plan choice from the cost model's outputs.  Rules keep the
+// heuristic path's order; per block and rule the kernel picks the first-stage
+// order and the verification order.  Equal choices share a plan slot of an
+// open-addressing table keyed by a hash of the choice; the first block to
+// claim a slot writes that slot's plan by permuting the heuristic plan inside
+// each rule's segment (segments keep their positions, so checkpoint targets
+// are unchanged).  Slot 0 is the heuristic plan, also taken by blocks below
+// min_size and when the table is full.
+constexpr int kMaxPlanRules = 64;
+constexpr int kMaxRuleSteps = 10;
+constexpr uint32_t kPlanSlots = 4096;   // power of two
+struct PlanChoiceParams {
+    const float* y;                   // [n_blocks x n_spec x 2] model outputs
+    const uint32_t* blk_size;
+    uint32_t n_blocks, n_spec;
+    uint32_t n_rules;                 // rules of the partition's plan, in heuristic order
+    uint32_t n_slots;                 // table size (power of two, <= kPlanSlots)
+    uint32_t plan_len;                // instructions of one plan
+    uint32_t min_size;
+    uint8_t rule_len[kMaxPlanRules];  // steps per rule
+    uint8_t rule_spec[kMaxPlanRules][kMaxRuleSteps];   // spec index of each step, heuristic order
+    uint8_t spec_kind[kMaxSpecs];     // plan operation of each spec (Op)
+    unsigned long long* keys;         // [n_slots] choice hash per slot, 0 = empty
+    Instr* code;                      // [n_slots x plan_len]; slot 0 holds the heuristic plan
+    uint32_t* blk_slot;               // [n_blocks] out
+    unsigned long long* stats;        // [3] blocks with a learned plan, blocks over capacity, plans written
+};
+hipError_t launch_plan_choice(const PlanChoiceParams& p, hipStream_t s);
 
 // ------------------------------------------------------------ cost model
 // C[M x N] = op(A) op(B) (+ bias[N]); op(X) = X or X^T (row-major storage

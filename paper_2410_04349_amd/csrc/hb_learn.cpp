@@ -207,7 +207,7 @@ void costmodel_predict(Ctx* c, const float* x, uint64_t n, int on_device, float*
         HB_HIP(hipMemcpyAsync(y + r0 * kOut, a.y.get(), sizeof(float) * nb * kOut,
                               y_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
     }
-    c->sync();
+    if (!y_on_device) c->sync();
 }
 
 void costmodel_trace(Ctx* c, const float* x, const float* t, uint32_t n, float* out, uint64_t out_len) {

@@ -261,11 +261,7 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const I
         uint8_t* peq = wbase + P.lds_wave_peq;
         const Instr* __restrict__ pl = plan;
         uint32_t plen = P.plan_len;
-        if (P.blk_plan) {
-            const uint32_t e = P.blk_plan[b];
-            pl = plan + (e >> 12);
-            plen = e & 0xFFFu;
-        }
+        if (P.blk_slot) pl = plan + (size_t)P.blk_slot[b] * plen;
 
         // bit r of a lane's masks = the pair (row r, this lane's j)
         uint32_t pairs = 0;
@@ -498,26 +494,14 @@ __device__ inline uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-__device__ inline double block_sum(double v, double* red) {
+__device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-    return t;
+    return v;
 }
 
-__device__ inline double block_min(double v, double* red) {
+__device__ inline double wave_min(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double t = red[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = fmin(t, red[w]);
-    return t;
+    return v;
 }
 
 // Exact filter of a predicate on two positions' features (the same bounds
@@ -562,11 +546,16 @@ __device__ inline bool feature_filter(const LearnParams& L, const PredSpec& sp, 
 // the data, threshold shape, log2 block size, length (or set size) mean / std /
 // min / max, 3-bin length histogram, the fraction of adjacent position pairs
 // passing the predicate's filter, mean signature density.
-__global__ __launch_bounds__(256) void k_block_features(const LearnParams L) {
-    __shared__ double red[4];
+// One wave per block; blocks below L.min_size get all-zero features.
+__global__ __launch_bounds__(64) void k_block_features(const LearnParams L) {
     const MatchParams& P = L.mp;
     const uint32_t b = blockIdx.x;
     const uint32_t start = P.blk_start[b], nb = P.blk_size[b];
+    if (nb < L.min_size) {
+        float* f = L.features + (size_t)b * L.n_spec * kFeatures;
+        for (uint32_t x = threadIdx.x; x < L.n_spec * kFeatures; x += 64) f[x] = 0.f;
+        return;
+    }
     const uint64_t n = P.feat.n;
     const uint64_t* f64 = P.feat.f64;
     const uint32_t* f32 = P.feat.f32;
@@ -575,7 +564,7 @@ __global__ __launch_bounds__(256) void k_block_features(const LearnParams L) {
         const bool is_int = sp.op == OP_EQ_INT || sp.op == OP_ABSDIFF;
         const bool is_gram = sp.op == OP_JAC;
         double cnt = 0, sum = 0, sum2 = 0, mn = 1e300, mx = -1e300, b0 = 0, b1 = 0, b2 = 0, pops = 0, pass = 0;
-        for (uint32_t x = threadIdx.x; x < nb; x += blockDim.x) {
+        for (uint32_t x = threadIdx.x; x < nb; x += 64) {
             const uint64_t pos = (uint64_t)start + x;
             const uint32_t vm = f32[n + pos];
             double lv = 0.0;
@@ -604,16 +593,16 @@ __global__ __launch_bounds__(256) void k_block_features(const LearnParams L) {
             }
             if (x + 1 < nb && feature_filter(L, sp, pos, pos + 1)) pass += 1;
         }
-        cnt = block_sum(cnt, red);
-        sum = block_sum(sum, red);
-        sum2 = block_sum(sum2, red);
-        mn = block_min(mn, red);
-        mx = -block_min(-mx, red);
-        b0 = block_sum(b0, red);
-        b1 = block_sum(b1, red);
-        b2 = block_sum(b2, red);
-        pops = block_sum(pops, red);
-        pass = block_sum(pass, red);
+        cnt = wave_sum(cnt);
+        sum = wave_sum(sum);
+        sum2 = wave_sum(sum2);
+        mn = wave_min(mn);
+        mx = -wave_min(-mx);
+        b0 = wave_sum(b0);
+        b1 = wave_sum(b1);
+        b2 = wave_sum(b2);
+        pops = wave_sum(pops);
+        pass = wave_sum(pass);
         if (threadIdx.x == 0) {
             float* f = L.features + ((size_t)b * L.n_spec + s) * kFeatures;
             const double c = cnt > 0 ? cnt : 1.0;
@@ -651,7 +640,6 @@ __global__ __launch_bounds__(256) void k_block_features(const LearnParams L) {
             f[14] = (float)(pass / (double)(nb - 1));
             f[15] = (float)(pops / c / 64.0);
         }
-        __syncthreads();
     }
 }
 
@@ -661,9 +649,10 @@ __global__ __launch_bounds__(256) void k_block_features(const LearnParams L) {
 //   i = mix64(c + 64) mod n_b, j_l = mix64(c + l) mod n_b (l = lane; j_l = i
 //   is replaced by (i + 1) mod n_b), positions inside the block.
 // It accumulates per (block, predicate) the lanes, the lanes that satisfy
-// the predicate, the wave's clock cycles spent deciding it and the lanes
-// that pass its first plan step (the exact filter; for value predicates the
-// predicate itself).
+// the predicate, the wave's clock cycles spent on the exact check of every
+// lane whose values are present (not gated by the filter) and the lanes
+// that pass the predicate's first plan step (its exact filter; for value
+// predicates the predicate itself).
 __global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
     extern __shared__ __align__(16) uint8_t lds[];
     const MatchParams& P = L.mp;
@@ -679,34 +668,41 @@ __global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
     const uint64_t pi = (uint64_t)start + ip, pj = (uint64_t)start + jp;
     const uint32_t row_i = f32[pi], row_j = f32[pj];
     const uint32_t vmask_i = f32[n + pi];
+    const uint32_t vb = vmask_i & f32[n + pj];
     uint8_t* peq = lds + P.lds_wave_peq;
     for (uint32_t x = 0; x < L.n_spec; ++x) {
         const PredSpec sp = L.spec[x];
         const uint32_t res = sp.res;
+        const bool first = feature_filter(L, sp, pi, pj);
+        const uint64_t filtered = __popcll(__ballot(first));
         const uint64_t t0 = __builtin_readcyclecounter();
-        bool r = feature_filter(L, sp, pi, pj);
-        const uint64_t filtered = __popcll(__ballot(r));
-        if (sp.op == OP_EQ_STR && __any(r)) {
+        bool r = false;
+        if (sp.op == OP_EQ_INT || sp.op == OP_ABSDIFF) {
+            r = feature_filter(L, sp, pi, pj);
+        } else if (sp.op == OP_EQ_STR) {
             const ColDev& col = P.cols[P.str_attr[res]];
-            const uint32_t li = f32[(2 + res) * n + pi];
-            if (r) {
+            const uint32_t li = f32[(2 + res) * n + pi], lj = f32[(2 + res) * n + pj];
+            if (((vb >> (16 + res)) & 1) && li == lj) {
                 const uint8_t* si = col.bytes + col.off[row_i];
                 const uint8_t* sj = col.bytes + col.off[row_j];
+                r = true;
                 for (uint32_t q = 0; r && q < li; ++q) r = si[q] == sj[q];
             }
-        } else if (sp.op == OP_ED && __any(r)) {
+        } else if (sp.op == OP_ED) {
             const ColDev& col = P.cols[P.str_attr[res]];
+            const bool valid = (vb >> (16 + res)) & 1;
             const int m = (int)f32[(2 + res) * n + pi];
             const int nn = (int)f32[(2 + res) * n + pj];
             const int words = m <= 32 ? 0 : (m + 63) / 64;
-            build_peq(peq, words, col.bytes + col.off[row_i], m, lane);
-            if (r) {
+            if (__any(valid)) build_peq(peq, words, col.bytes + col.off[row_i], m, lane);
+            if (valid) {
                 const int dist = myers_dispatch(peq, words, m, col.bytes + col.off[row_j], nn,
                                                 (uint64_t*)(lds + P.lds_wave_myers), lane);
                 r = dist <= (int)sp.param;
             }
-        } else if (sp.op == OP_JAC && __any(r)) {
+        } else {   // OP_JAC
             const GramDev& g = P.gram[res];
+            const bool valid = (vb >> (24 + res)) & 1;
             const uint32_t ia = f32[(2 + P.n_str + res) * n + pi];
             const uint32_t ca = ia & 0x7FFFFFFFu;
             uint32_t* ig = (uint32_t*)(lds + P.lds_wave_igram[res]);
@@ -715,7 +711,7 @@ __global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
                 for (uint32_t q = lane; q < ca; q += 64) ig[q] = src[q];
                 wave_sync();
             }
-            if (r) {
+            if (valid) {
                 const uint32_t jb = f32[(2 + P.n_str + res) * n + pj];
                 const uint32_t cb = jb & 0x7FFFFFFFu;
                 const uint32_t I = intersect(ig, ca, (ia >> 31) != 0, g.codes + g.off[row_j], cb, (jb >> 31) != 0);
@@ -732,6 +728,202 @@ __global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
             atomicAdd(&cnt[2], (unsigned long long)(t1 - t0));
             atomicAdd(&cnt[3], (unsigned long long)filtered);
         }
+    }
+}
+
+// ------------------------------------------------------------ plan choice
+
+// Probability that some pair of a batch of `batch` pairs survives a step
+// sequence that each pair survives with probability p.
+__device__ inline double batch_any(double p, double batch) {
+    if (p <= 0.0) return 0.0;
+    if (p >= 1.0) return 1.0;
+    return -expm1(batch * log1p(-p));
+}
+
+// First-stage step cost per row, in the library's lane-op units.
+__device__ inline double first_cost(uint8_t op) {
+    switch (op) {
+    case OP_EQ_INT: return 1.0;
+    case OP_ABSDIFF: return 4.0;
+    case OP_EQ_STR: return 3.0;
+    default: return 12.0;
+    }
+}
+
+__device__ inline bool verifies(uint8_t op) { return op == OP_EQ_STR || op == OP_ED || op == OP_JAC; }
+
+struct BlockEst {
+    const float* y;
+    __device__ double pass(uint32_t s) const {
+        const float v = y[2 * s];
+        return isfinite(v) ? fmin(1.0, fmax(0.0, (double)v)) : 1.0;
+    }
+    __device__ double cycles(uint32_t s) const {
+        const float v = y[2 * s + 1];
+        return isfinite(v) ? exp2(fmin(30.0, fmax(0.0, 16.0 * (double)v))) : 1e9;
+    }
+};
+
+// Expected first-stage cost of a wave batch running a rule's steps in
+// order `ord` (indices into the rule's steps): a step runs while some pair
+// of the batch survives every step before it.
+__device__ inline double stage_cost(const PlanChoiceParams& C, uint32_t r, const uint8_t* ord, int len,
+                                    const BlockEst& e, double batch) {
+    double total = 0.0, surv = 1.0, alive = 1.0;
+    for (int k = 0; k < len; ++k) {
+        const uint32_t sx = C.rule_spec[r][ord[k]];
+        total += alive * first_cost(C.spec_kind[sx]);
+        surv *= e.pass(sx);
+        alive = batch_any(surv, batch);
+    }
+    return total;
+}
+
+// Expected cost of the exact checks in order `ord`, each taken to stop half
+// of the rows that reach it.
+__device__ inline double verify_cost(const PlanChoiceParams& C, uint32_t r, const uint8_t* ord, int len,
+                                     const BlockEst& e) {
+    double total = 0.0, w = 1.0;
+    for (int k = 0; k < len; ++k) {
+        total += w * e.cycles(C.rule_spec[r][ord[k]]);
+        w *= 0.5;
+    }
+    return total;
+}
+
+__device__ inline uint64_t pack_order(const uint8_t* ord, int len) {
+    uint64_t code = 0;
+    for (int k = 0; k < len; ++k) code |= (uint64_t)(ord[k] + 1) << (4 * k);
+    return code;
+}
+
+// One thread per block: for every rule, the first-stage order by
+// cost / (1 - q) ascending (q = the probability that some pair of the wave
+// batch passes the step) and the exact checks by predicted cycles
+// ascending, each taken only when the model expects it at least 2% cheaper
+// than the heuristic order.  Writes the block's plan slot.
+__device__ inline void rule_choice(const PlanChoiceParams& C, uint32_t r, const BlockEst& e, double batch,
+                                   uint8_t* fo, uint8_t* vo, int* nv) {
+    const int len = C.rule_len[r];
+    uint8_t id[kMaxRuleSteps], lo[kMaxRuleSteps];
+    double rank[kMaxRuleSteps];
+    for (int k = 0; k < len; ++k) {
+        id[k] = (uint8_t)k;
+        lo[k] = (uint8_t)k;
+        const uint32_t sx = C.rule_spec[r][k];
+        rank[k] = first_cost(C.spec_kind[sx]) / fmax(1e-12, 1.0 - batch_any(e.pass(sx), batch));
+    }
+    for (int a = 1; a < len; ++a)   // stable insertion sort by rank
+        for (int k = a; k > 0 && rank[lo[k]] < rank[lo[k - 1]]; --k) {
+            const uint8_t t = lo[k]; lo[k] = lo[k - 1]; lo[k - 1] = t;
+        }
+    const bool take = stage_cost(C, r, lo, len, e, batch) < 0.98 * stage_cost(C, r, id, len, e, batch);
+    for (int k = 0; k < len; ++k) fo[k] = take ? lo[k] : id[k];
+    // exact checks in first-stage order (the heuristic), or by cycles
+    uint8_t hv[kMaxRuleSteps];
+    int m = 0;
+    for (int k = 0; k < len; ++k)
+        if (verifies(C.spec_kind[C.rule_spec[r][fo[k]]])) hv[m++] = fo[k];
+    uint8_t lv[kMaxRuleSteps];
+    for (int k = 0; k < m; ++k) lv[k] = hv[k];
+    for (int a = 1; a < m; ++a)
+        for (int k = a; k > 0 && e.cycles(C.rule_spec[r][lv[k]]) < e.cycles(C.rule_spec[r][lv[k - 1]]); --k) {
+            const uint8_t t = lv[k]; lv[k] = lv[k - 1]; lv[k - 1] = t;
+        }
+    const bool vtake = verify_cost(C, r, lv, m, e) < 0.98 * verify_cost(C, r, hv, m, e);
+    for (int k = 0; k < m; ++k) vo[k] = vtake ? lv[k] : hv[k];
+    *nv = m;
+}
+
+// The first block to claim a slot writes its plan: every rule segment of the
+// heuristic plan holds [first-stage steps][exact checks][checkpoint] in step
+// order; the segment is rewritten in the chosen orders.
+__device__ inline void write_plan(const PlanChoiceParams& C, uint32_t x, const BlockEst& e, double batch) {
+    Instr* dst = C.code + (size_t)x * C.plan_len;
+    const Instr* base = C.code;
+    for (uint32_t i = 0; i < C.plan_len; ++i) dst[i] = base[i];
+    uint32_t seg = 0;
+    for (uint32_t r = 0; r < C.n_rules; ++r) {
+        uint8_t fo[kMaxRuleSteps], vo[kMaxRuleSteps];
+        int nv = 0;
+        rule_choice(C, r, e, batch, fo, vo, &nv);
+        const int len = C.rule_len[r];
+        int vpos[kMaxRuleSteps];
+        int m = 0;
+        for (int k = 0; k < len; ++k) vpos[k] = verifies(C.spec_kind[C.rule_spec[r][k]]) ? m++ : -1;
+        for (int k = 0; k < len; ++k) dst[seg + k] = base[seg + fo[k]];
+        for (int k = 0; k < nv; ++k) dst[seg + len + k] = base[seg + len + vpos[vo[k]]];
+        seg += (uint32_t)(len + m + 1);
+    }
+}
+
+// One thread per block: for every rule, the first-stage order by
+// cost / (1 - q) ascending (q = the probability that some pair of the wave
+// batch passes the step) and the exact checks by predicted cycles
+// ascending, each taken only when the model expects it at least 2% cheaper
+// than the heuristic order.  Writes the block's plan slot.
+__global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    bool learned = false, overflow = false, wrote = false;
+    if (b < C.n_blocks) {
+        const uint32_t nb = C.blk_size[b];
+        const double batch = (double)min(nb, (uint32_t)kRows) * (double)min(nb, (uint32_t)kTile);
+        BlockEst e{C.y + (size_t)b * C.n_spec * 2};
+        uint64_t h = 0x6A09E667F3BCC909ull;
+        if (nb >= C.min_size) {
+            for (uint32_t r = 0; r < C.n_rules; ++r) {
+                uint8_t fo[kMaxRuleSteps], vo[kMaxRuleSteps];
+                int nv = 0;
+                rule_choice(C, r, e, batch, fo, vo, &nv);
+                const int len = C.rule_len[r];
+                bool same_f = true, same_v = true;
+                for (int k = 0; k < len; ++k) same_f &= fo[k] == k;
+                int m = 0;
+                for (int k = 0; k < len; ++k)
+                    if (verifies(C.spec_kind[C.rule_spec[r][fo[k]]])) same_v &= vo[m++] == fo[k];
+                if (!(same_f && same_v)) {
+                    learned = true;
+                    h = mix64(h ^ ((uint64_t)(r + 1) << 56) ^ pack_order(fo, len));
+                    h = mix64(h ^ pack_order(vo, nv));
+                }
+            }
+        }
+        uint32_t slot = 0;
+        if (learned) {
+            const unsigned long long key = h ? h : 1ull;
+            const uint32_t mask = C.n_slots - 1;
+            uint32_t x = (uint32_t)(key & mask);
+            for (uint32_t probe = 0; probe < C.n_slots; ++probe, x = (x + 1) & mask) {
+                if (x == 0) continue;   // slot 0 is the heuristic plan
+                // most blocks find their choice already present: read first,
+                // and only try to claim an empty slot
+                unsigned long long cur = __hip_atomic_load(&C.keys[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (cur == 0ull) {
+                    cur = atomicCAS(&C.keys[x], 0ull, key);
+                    if (cur == 0ull) {
+                        write_plan(C, x, e, batch);
+                        wrote = true;
+                        slot = x;
+                        break;
+                    }
+                }
+                if (cur == key) {
+                    slot = x;
+                    break;
+                }
+            }
+            overflow = slot == 0;
+            learned = slot != 0;
+        }
+        C.blk_slot[b] = slot;
+    }
+    const uint64_t nl = __popcll(__ballot(learned)), no = __popcll(__ballot(overflow));
+    const uint64_t nw = __popcll(__ballot(wrote));
+    if ((threadIdx.x & 63) == 0) {
+        if (nl) atomicAdd(&C.stats[0], (unsigned long long)nl);
+        if (no) atomicAdd(&C.stats[1], (unsigned long long)no);
+        if (nw) atomicAdd(&C.stats[2], (unsigned long long)nw);
     }
 }
 
@@ -760,7 +952,13 @@ namespace hb {
 
 hipError_t launch_block_features(const LearnParams& p, hipStream_t s) {
     if (p.mp.n_blocks == 0 || p.n_spec == 0) return hipSuccess;
-    k_block_features<<<p.mp.n_blocks, 256, 0, s>>>(p);
+    k_block_features<<<p.mp.n_blocks, 64, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_choice(const PlanChoiceParams& p, hipStream_t s) {
+    if (p.n_blocks == 0) return hipSuccess;
+    k_plan_choice<<<(p.n_blocks + 255) / 256, 256, 0, s>>>(p);
     return hipGetLastError();
 }
 

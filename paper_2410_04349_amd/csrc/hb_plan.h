@@ -8,7 +8,8 @@ namespace hb {
 
 struct PathRule {
     uint32_t rule;
-    std::vector<uint32_t> preds;   // distinct predicate ids in evaluation order
+    std::vector<uint32_t> preds;    // distinct predicate ids in evaluation order
+    std::vector<uint32_t> verify;   // order of the exact checks (empty: as `preds`)
 };
 
 // Rules and predicates in the given order (duplicates within a rule dropped).

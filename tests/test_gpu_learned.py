@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 from gen import workloads
+from learned_util import collect, train_model
 
 pytestmark = pytest.mark.gpu
 
@@ -72,15 +73,6 @@ def run(hb, ctx, rel, rules, plan):
     return out, stats, work
 
 
-def collect(hb, ctx, rel, rules, samples, seed):
-    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
-    rs = hb.hb_compile_rules(ctx, rid, rules)
-    hb.hb_partition(ctx, rid, rs)
-    log = hb.hb_log_collect(ctx, rid, rs, samples, seed)
-    hb.hb_release_relation(ctx, rid)
-    return log
-
-
 def test_log_pass_counts_match_oracle(hb, ctx):
     print("[gpu-case] log pass counts", flush=True)
     rel, rules = workloads.plain_1m(n=6000)
@@ -118,19 +110,6 @@ def test_log_pass_counts_match_oracle(hb, ctx):
     assert checked > 0
     assert np.all((log["labels"][:, 0] >= 0) & (log["labels"][:, 0] <= 1))
     assert np.all(log["labels"][:, 1] > 0)
-
-
-def train_model(hb, ctx):
-    xs, ts = [], []
-    for rel, rules in (workloads.person_small(), workloads.plain_1m(n=100_000)):
-        log = collect(hb, ctx, rel, rules, 4, 7)
-        xs.append(log["features"])
-        ts.append(log["labels"])
-    x = np.concatenate(xs)
-    t = np.concatenate(ts)
-    perm = np.random.default_rng(0).permutation(len(x))
-    hb.hb_costmodel_init(ctx, 3)
-    return hb.hb_costmodel_train(ctx, x[perm], t[perm], epochs=40, batch=256, lr=2e-3)
 
 
 @pytest.fixture(scope="module")
