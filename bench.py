@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plan", default="learned", choices=["learned", "heuristic", "given"])
     ap.add_argument("--no-compare", action="store_true", help="skip timing the heuristic plan beside")
+    ap.add_argument("--save-model", default=None, help="write the trained cost-model parameters (.npy)")
+    ap.add_argument("--model", default=None,
+                    help="load cost-model parameters (.npy) written by --save-model instead of training")
     ap.add_argument("--n", type=int, default=1_000_000, help="tuples of the plain workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -119,7 +122,11 @@ def main():
     torch.cuda.synchronize()
 
     learned = None
-    if args.plan == "learned":
+    if args.plan == "learned" and args.model:
+        hb.hb_costmodel_set_params(ctx, np.load(args.model))
+        learned = {"loaded": args.model}
+        log(f"[bench] cost model loaded from {args.model}")
+    elif args.plan == "learned":
         t = time.perf_counter()
         xs, ts = [], []
         for wrel, wrules in (workloads.person_small(), workloads.plain_1m(n=100_000)):
@@ -138,6 +145,8 @@ def main():
         learned = {"train_rows": int(len(x)), "epochs": 40, "final_loss": loss,
                    "train_s": time.perf_counter() - t}
         log(f"[bench] cost model trained on {len(x)} log rows in {learned['train_s']:.1f}s, loss {loss:.4g}")
+        if args.save_model:
+            np.save(args.save_model, hb.hb_costmodel_get_params(ctx))
 
     def step(plan, dst):
         rid = hb.hb_load_relation(ctx, cols, rel.n_rows, on_device=True)

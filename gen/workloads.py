@@ -29,6 +29,11 @@ restated in the design notes.
                  cap 18, the smallest cap giving 50M +- 10% candidate pairs
                  (46,306,524 at 5M); one rule
                  brand= AND J2(title)>=7/10 AND ED(title)<=8.
+  batched_64     64 independent relations with sizes log-uniform in
+                 [10k, 2M] tuples (each the plain recipe: 15% duplicates,
+                 key capped Zipf s=1.1 with 50 values per 1,000 tuples, cap
+                 5,000), each with its own 1-10 rules: the key equality, one
+                 string predicate and 0-2 more from the plain menu.
   random_small   adversarial small relations for parity (lengths 0, q-1,
                  63/64/65, 127/128/129, 200; nulls; tiny alphabets; several
                  keys; rule sets with the key equality anywhere in a rule).
@@ -139,6 +144,46 @@ def learned_10m(seed: int = SEED_BASE + 4, n: int = 10_000_000):
     cap = max(8, int(round(5000 * min(1.0, scale * 20))))
     rel = generate(seed, n - n_dup, n_dup, learned_10m_attrs(n_values, cap), edit_min=1, edit_max=3)
     return rel, learned_10m_rules()
+
+
+# ------------------------------------------------------------ batched 64
+
+def batched_rules(r: np.random.Generator, n_rules: int):
+    s_attrs, key, ints = [0, 1, 2], 3, [4, 5]
+    jac = [(1, 2), (3, 5), (7, 10), (4, 5)]
+
+    def string_pred(a):
+        if r.random() < 0.5:
+            return Pred(ED, a, k=int(r.integers(1, 4)))
+        num, den = jac[int(r.integers(0, len(jac)))]
+        return Pred(JACCARD, a, q=3, num=num, den=den)
+
+    rules = []
+    for _ in range(n_rules):
+        anchor = s_attrs[int(r.integers(0, 3))]
+        rule = [Pred(EQ, key), string_pred(anchor)]
+        others = [a for a in s_attrs + ints if a != anchor]
+        for a in r.choice(others, size=int(r.integers(0, 3)), replace=False):
+            a = int(a)
+            rule.append(Pred(ABSDIFF, a, d=2) if a in ints else string_pred(a))
+        rules.append(rule)
+    return rules
+
+
+def batched_64(seed: int = SEED_BASE + 6, n_jobs: int = 64, lo: int = 10_000, hi: int = 2_000_000,
+               scale: float = 1.0, cap: int = 5000):
+    """[(relation, rules)] of the batched workload; `scale` multiplies every
+    relation size and `cap` bounds the blocks (smaller for parity tests)."""
+    r = np.random.default_rng(seed)
+    sizes = np.exp(r.uniform(np.log(lo), np.log(hi), size=n_jobs))
+    out = []
+    for k, size in enumerate(sizes):
+        n = max(40, int(round(size * scale)))
+        n_dup = (n * 15) // 100
+        n_values = max(8, int(round(n * 0.05)))
+        rel = generate(seed * 1000 + k, n - n_dup, n_dup, plain_1m_attrs(n_values, cap), edit_min=1, edit_max=3)
+        out.append((rel, batched_rules(r, int(r.integers(1, 11)))))
+    return out
 
 
 # ------------------------------------------------------------ long titles

@@ -303,6 +303,47 @@ typedef struct {
 } hb_match_stats;
 hb_status hb_last_match_stats(hb_ctx* ctx, hb_match_stats* out);
 
+/* ------------------------------------------------------------ batches
+ * Many (relation, rule set) jobs matched together (the paper's pipeline
+ * batches its work for the device, Section 5): every job's key partitions
+ * feed one persistent, work-stealing launch (heaviest partitions first,
+ * workgroups taking items from a global queue), so uneven jobs share the
+ * device without one launch each.  Every job must have run hb_partition;
+ * its relation and rule set must stay loaded while the batch exists
+ * (HB_ERR_STALE_ID on hb_batch_run otherwise).  Results equal hb_match's. */
+#define HB_MAX_BATCH_JOBS 4096
+#define HB_BATCH_GRAPH 1u     /* capture the batch's launches in a HIP graph, replayed by hb_batch_run */
+#define HB_BATCH_AUTOTUNE 2u  /* time work-grab sizes and grid occupancies on the batch's first items; keep the fastest */
+
+typedef struct {
+    uint32_t rel_id;
+    uint32_t ruleset_id;
+} hb_job;
+
+/* Builds every job's partition plans (plan: hb_plan) and the work queue;
+ * flags: HB_BATCH_*.  *batch_id receives the handle. */
+hb_status hb_batch_create(hb_ctx* ctx, const hb_job* jobs, uint32_t n_jobs, int32_t plan, uint32_t flags,
+                          uint32_t* batch_id);
+/* Matches every job (replaying the graph if captured) and sorts each job's
+ * pairs; *n_pairs_total (may be NULL) receives the sum over jobs. */
+hb_status hb_batch_run(hb_ctx* ctx, uint32_t batch_id, uint64_t* n_pairs_total);
+/* Job `job`'s Ca(D) of the last hb_batch_run, as hb_match returns it
+ * (sorted packed pairs; capacity protocol as hb_match). */
+hb_status hb_batch_result(hb_ctx* ctx, uint32_t batch_id, uint32_t job, uint64_t* out_pairs, int out_on_device,
+                          uint64_t capacity, uint64_t* n_pairs);
+
+typedef struct {
+    uint32_t n_jobs, n_partitions;
+    uint64_t work_items;        /* 64 x 64 tiles in the queue */
+    uint32_t grid, grab, occupancy, lds_bytes;
+    int32_t graph;              /* 1 if captured */
+    uint32_t n_tuned;           /* candidates timed by HB_BATCH_AUTOTUNE */
+    double tune_ms[16];         /* their times on the sample, in (occupancy, grab) order */
+    uint64_t fallback_blocks;   /* learned plan: blocks kept on the heuristic plan for structural reasons */
+} hb_batch_info;
+hb_status hb_batch_info_get(hb_ctx* ctx, uint32_t batch_id, hb_batch_info* info);
+hb_status hb_batch_destroy(hb_ctx* ctx, uint32_t batch_id);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,13 +44,28 @@ EXPORTED = [
     "hb_epg_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
     "hb_match_work", "hb_costmodel_init", "hb_costmodel_set_params", "hb_costmodel_get_params",
     "hb_costmodel_train", "hb_costmodel_predict", "hb_costmodel_trace", "hb_costmodel_adam_step",
-    "hb_log_collect",
+    "hb_log_collect", "hb_batch_create", "hb_batch_run", "hb_batch_result", "hb_batch_info_get",
+    "hb_batch_destroy",
 ]
+
+HB_BATCH_GRAPH = 1
+HB_BATCH_AUTOTUNE = 2
 
 HB_MLP_PARAMS = 5378
 
 OP_KINDS = ["eq_value", "absdiff", "eq_string_filter", "ed_filter", "jaccard_filter", "eq_string",
             "edit_distance", "jaccard"]
+
+
+class HbJob(ctypes.Structure):
+    _fields_ = [("rel_id", ctypes.c_uint32), ("ruleset_id", ctypes.c_uint32)]
+
+
+class HbBatchInfo(ctypes.Structure):
+    _fields_ = [("n_jobs", ctypes.c_uint32), ("n_partitions", ctypes.c_uint32), ("work_items", ctypes.c_uint64),
+                ("grid", ctypes.c_uint32), ("grab", ctypes.c_uint32), ("occupancy", ctypes.c_uint32),
+                ("lds_bytes", ctypes.c_uint32), ("graph", ctypes.c_int32), ("n_tuned", ctypes.c_uint32),
+                ("tune_ms", ctypes.c_double * 16), ("fallback_blocks", ctypes.c_uint64)]
 
 
 class HbColumn(ctypes.Structure):
@@ -123,6 +138,11 @@ def _load_lib():
         "hb_costmodel_trace": (I32, [P, P, P, U32, P, U64]),
         "hb_costmodel_adam_step": (I32, [P, P, ctypes.c_float]),
         "hb_log_collect": (I32, [P, U32, U32, U32, U64, P, P, P, P, U64, ctypes.POINTER(U64)]),
+        "hb_batch_create": (I32, [P, ctypes.POINTER(HbJob), U32, I32, U32, ctypes.POINTER(U32)]),
+        "hb_batch_run": (I32, [P, U32, ctypes.POINTER(U64)]),
+        "hb_batch_result": (I32, [P, U32, U32, P, ctypes.c_int, U64, ctypes.POINTER(U64)]),
+        "hb_batch_info_get": (I32, [P, U32, ctypes.POINTER(HbBatchInfo)]),
+        "hb_batch_destroy": (I32, [P, U32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -441,3 +461,52 @@ def hb_log_collect(ctx: Context, rel_id: int, ruleset_id: int, samples: int, see
                                   ctypes.c_void_p(lab.ctypes.data), ctypes.c_void_p(meta.ctypes.data),
                                   ctypes.c_void_p(cnt.ctypes.data), rows, ctypes.byref(n)))
     return {"features": f[:rows], "labels": lab[:rows], "meta": meta[:rows], "counts": cnt[:rows]}
+
+
+# ------------------------------------------------------------ batches
+
+def hb_batch_create(ctx: Context, jobs, plan="heuristic", graph: bool = True, autotune: bool = False) -> int:
+    """jobs: sequence of (rel_id, ruleset_id), each partitioned."""
+    arr = (HbJob * max(1, len(jobs)))(*[HbJob(int(r), int(s)) for r, s in jobs])
+    pl = _PLAN[plan] if isinstance(plan, str) else int(plan)
+    flags = (HB_BATCH_GRAPH if graph else 0) | (HB_BATCH_AUTOTUNE if autotune else 0)
+    bid = ctypes.c_uint32()
+    ctx.check(_lib.hb_batch_create(ctx.h, arr, len(jobs), pl, flags, ctypes.byref(bid)))
+    return bid.value
+
+
+def hb_batch_run(ctx: Context, batch_id: int) -> int:
+    n = ctypes.c_uint64()
+    ctx.check(_lib.hb_batch_run(ctx.h, batch_id, ctypes.byref(n)))
+    return n.value
+
+
+def hb_batch_result(ctx: Context, batch_id: int, job: int, out=None):
+    """Job `job`'s sorted packed pairs: a host numpy array, or written into
+    the torch device tensor `out` (count returned)."""
+    n = ctypes.c_uint64()
+    if out is not None:
+        ctx.check(_lib.hb_batch_result(ctx.h, batch_id, job, ctypes.c_void_p(out.data_ptr()), 1, out.numel(),
+                                       ctypes.byref(n)))
+        return n.value
+    st = _lib.hb_batch_result(ctx.h, batch_id, job, None, 0, 0, ctypes.byref(n))
+    if st == HB_OK:
+        return np.zeros(0, dtype=np.uint64)
+    if st != HB_ERR_CAPACITY:
+        ctx.check(st)
+    buf = np.zeros(max(1, n.value), dtype=np.uint64)
+    ctx.check(_lib.hb_batch_result(ctx.h, batch_id, job, ctypes.c_void_p(buf.ctypes.data), 0, len(buf),
+                                   ctypes.byref(n)))
+    return buf[: n.value]
+
+
+def hb_batch_info(ctx: Context, batch_id: int) -> dict:
+    i = HbBatchInfo()
+    ctx.check(_lib.hb_batch_info_get(ctx.h, batch_id, ctypes.byref(i)))
+    return {"n_jobs": i.n_jobs, "n_partitions": i.n_partitions, "work_items": i.work_items, "grid": i.grid,
+            "grab": i.grab, "occupancy": i.occupancy, "lds_bytes": i.lds_bytes, "graph": bool(i.graph),
+            "tune_ms": list(i.tune_ms[: i.n_tuned]), "fallback_blocks": i.fallback_blocks}
+
+
+def hb_batch_destroy(ctx: Context, batch_id: int) -> None:
+    ctx.check(_lib.hb_batch_destroy(ctx.h, batch_id))

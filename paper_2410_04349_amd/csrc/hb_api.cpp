@@ -14,6 +14,8 @@
 #include "../../include/hb.h"
 #include "hb_ctx.h"
 #include "hb_internal.h"
+#include "hb_abi.h"
+#include "hb_keyplan.h"
 #include "hb_plan.h"
 
 namespace hb {
@@ -421,15 +423,6 @@ static void partition(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint64_t* n_cand)
 
 // ------------------------------------------------------------ match
 
-struct KeyPlan {
-    std::vector<Instr> code;
-    MatchParams mp{};
-    DevBuf f64, f32;
-    // learned plans: per-slot plans on the device, the block -> slot map and
-    // the choice kernel's counters (read after matching)
-    bool own_code = false;
-    DevBuf dev_code, blk_slot, choice_stats;
-};
 
 static uint32_t align_up(uint32_t v, uint32_t a) { return (v + a - 1) / a * a; }
 
@@ -443,16 +436,6 @@ static const uint64_t* char_signature(Ctx* c, Relation& rel, uint32_t attr) {
     return p;
 }
 
-// Resources of one key partition's plans, fixed by the rule set (not by
-// the evaluation order), so every order of the same rules reads the same
-// gathered feature columns.
-struct KeyRes {
-    std::vector<uint32_t> int_attr, str_attr, prev;
-    std::vector<std::pair<uint32_t, uint32_t>> gram_key;
-    std::vector<PredSpec> specs;   // predicates evaluated in this partition, by id
-    bool any_ed = false;
-    bool any_rule = false;
-};
 
 // A rule can hold in key `ka`'s blocks unless it needs an earlier key to
 // agree (the owner check rules those pairs out).
@@ -631,9 +614,10 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     }
     m.ed_words = ed_words;
     const uint32_t n64 = m.n_int + m.n_str + m.n_gram, n32 = 2 + m.n_str + m.n_gram;
-    const size_t nv = std::max<uint32_t>(P.n_valid, 1);
-    kp.f64.alloc(c, sizeof(uint64_t) * nv * std::max<uint32_t>(n64, 1));
-    kp.f32.alloc(c, sizeof(uint32_t) * nv * n32);
+    const uint64_t stride = (uint64_t)P.n_valid + kRows;
+    gp.stride = stride;
+    kp.f64.alloc(c, sizeof(uint64_t) * stride * std::max<uint32_t>(n64, 1));
+    kp.f32.alloc(c, sizeof(uint32_t) * stride * n32);
     gp.f64 = kp.f64.as<uint64_t>();
     gp.f32 = kp.f32.as<uint32_t>();
     HB_HIP(launch_gather_features(gp, c->stream));
@@ -669,7 +653,7 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     m.cols = rel.d_cols.as<ColDev>();
     m.feat.f64 = kp.f64.as<uint64_t>();
     m.feat.f32 = kp.f32.as<uint32_t>();
-    m.feat.n = P.n_valid;
+    m.feat.n = stride;
     m.blk_start = P.blk_start.as<uint32_t>();
     m.blk_size = P.blk_size.as<uint32_t>();
     m.tile_prefix = P.tile_prefix.as<uint64_t>();
@@ -859,21 +843,51 @@ static void log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t sample
 static const double kOpBase[8] = {1, 4, 3, 12, 12, 2, 4, 4};
 static const double kOpUnit[8] = {0, 0, 0, 0, 0, 1, 17, 3};
 
+std::vector<PathRule> plan_path(const RuleSet& rs, int plan) {
+    return plan == HB_PLAN_GIVEN ? given_path(rs.rules) : epg_path(rs.sp, rs.cost, rs.rules);
+}
+
+bool key_plan(Ctx* c, Relation& rel, RuleSet& rs, int plan, const std::vector<PathRule>& path, size_t ka,
+              KeyPlan& kp, bool count, uint64_t* n_fallback) {
+    if (plan != HB_PLAN_LEARNED) return build_key_plan(c, rel, rs, path, ka, kp, count);
+    KeyRes R;
+    if (!prepare_key(c, rel, rs, ka, kp, R, count)) return false;
+    c->host_timed("learned_plan", [&] { learned_key_plan(c, rel, rs, ka, kp, R, path, n_fallback); });
+    return true;
+}
+
+void sort_pairs(Ctx* c, DevBuf& pairs, uint64_t n, uint64_t n_rows, DevBuf& result) {
+    // packed pairs: j bits, then i bits
+    const int nb = bit_width(n_rows > 1 ? n_rows - 1 : 1);
+    std::vector<int> sh = shifts_for_bits(nb, 0);
+    std::vector<int> shi = shifts_for_bits(nb, 32);
+    sh.insert(sh.end(), shi.begin(), shi.end());
+    result.alloc(c, sizeof(uint64_t) * std::max<uint64_t>(n, 1));
+    if (n > 1) {
+        if (n >= 0xFFFFFFFFull) fail(HB_ERR_LIMIT, "more than 2^32 matched pairs");
+        DevBuf alt(c, sizeof(uint64_t) * n);
+        DevBuf rtmp(c, radix_tmp_bytes((uint32_t)n));
+        bool in_alt = false;
+        c->timed("output_sort", [&] {
+            return radix_sort_pairs(pairs.as<uint64_t>(), nullptr, alt.as<uint64_t>(), nullptr, (uint32_t)n, sh.data(),
+                                    (int)sh.size(), rtmp.get(), &in_alt, c->stream);
+        });
+        HB_HIP(hipMemcpyAsync(result.get(), in_alt ? alt.get() : pairs.get(), sizeof(uint64_t) * n,
+                              hipMemcpyDeviceToDevice, c->stream));
+    } else if (n == 1) {
+        HB_HIP(hipMemcpyAsync(result.get(), pairs.get(), 8, hipMemcpyDeviceToDevice, c->stream));
+    }
+}
+
 static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stats* ws = nullptr) {
-    std::vector<PathRule> path = plan == HB_PLAN_GIVEN ? given_path(rs.rules) : epg_path(rs.sp, rs.cost, rs.rules);
+    const std::vector<PathRule> path = plan_path(rs, plan);
     std::vector<KeyPlan> kps;
     size_t total_code = 0;
     uint64_t n_learned = 0, n_fallback = 0;
     for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
         if (rel.parts.at(rs.keys[ka]).n_tiles == 0) continue;
         KeyPlan kp;
-        if (plan == HB_PLAN_LEARNED) {
-            KeyRes R;
-            if (!prepare_key(c, rel, rs, ka, kp, R, ws != nullptr)) continue;
-            c->host_timed("learned_plan", [&] { learned_key_plan(c, rel, rs, ka, kp, R, path, &n_fallback); });
-        } else if (!build_key_plan(c, rel, rs, path, ka, kp, ws != nullptr)) {
-            continue;
-        }
+        if (!key_plan(c, rel, rs, plan, path, ka, kp, ws != nullptr, &n_fallback)) continue;
         if (!kp.own_code) total_code += kp.code.size();
         kps.push_back(std::move(kp));
     }
@@ -949,26 +963,7 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
         ws->launches = launches;
         return;
     }
-    // sort the packed pairs: j bits, then i bits
-    const int nb = bit_width(rel.n_rows > 1 ? rel.n_rows - 1 : 1);
-    std::vector<int> sh = shifts_for_bits(nb, 0);
-    std::vector<int> shi = shifts_for_bits(nb, 32);
-    sh.insert(sh.end(), shi.begin(), shi.end());
-    rs.result.alloc(c, sizeof(uint64_t) * std::max<uint64_t>(found, 1));
-    if (found > 1) {
-        if (found >= 0xFFFFFFFFull) fail(HB_ERR_LIMIT, "more than 2^32 matched pairs");
-        DevBuf alt(c, sizeof(uint64_t) * found);
-        DevBuf rtmp(c, radix_tmp_bytes((uint32_t)found));
-        bool in_alt = false;
-        c->timed("output_sort", [&] {
-            return radix_sort_pairs(out.as<uint64_t>(), nullptr, alt.as<uint64_t>(), nullptr, (uint32_t)found, sh.data(),
-                                    (int)sh.size(), rtmp.get(), &in_alt, c->stream);
-        });
-        HB_HIP(hipMemcpyAsync(rs.result.get(), in_alt ? alt.get() : out.get(), sizeof(uint64_t) * found,
-                              hipMemcpyDeviceToDevice, c->stream));
-    } else if (found == 1) {
-        HB_HIP(hipMemcpyAsync(rs.result.get(), out.get(), 8, hipMemcpyDeviceToDevice, c->stream));
-    }
+    sort_pairs(c, out, found, rel.n_rows, rs.result);
     rs.n_result = found;
     rs.has_result = true;
     rs.result_plan = plan;
@@ -1016,32 +1011,6 @@ static void match(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, uint64_t* o
 using hb::Ctx;
 using hb::Failure;
 
-struct hb_ctx {
-    Ctx c;
-};
-
-template <typename F>
-static hb_status guard(hb_ctx* ctx, F&& f) {
-    if (!ctx) return HB_ERR_INVALID_ARG;
-    try {
-        if (hipSetDevice(ctx->c.device) != hipSuccess) {
-            ctx->c.err = "hipSetDevice failed";
-            return HB_ERR_HIP;
-        }
-        f(&ctx->c);
-        ctx->c.err.clear();
-        return HB_OK;
-    } catch (const Failure& e) {
-        ctx->c.err = e.msg;
-        return e.st;
-    } catch (const std::bad_alloc&) {
-        ctx->c.err = "host allocation failed";
-        return HB_ERR_OOM;
-    } catch (const std::exception& e) {
-        ctx->c.err = e.what();
-        return HB_ERR_INVALID_ARG;
-    }
-}
 
 extern "C" {
 
@@ -1081,6 +1050,7 @@ void hb_destroy(hb_ctx* ctx) {
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
     ctx->c.drain_profile();
+    ctx->c.batches.clear();
     ctx->c.rulesets.clear();
     ctx->c.rels.clear();
     (void)hipStreamSynchronize(ctx->c.stream);

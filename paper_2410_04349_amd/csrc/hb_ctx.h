@@ -139,6 +139,8 @@ struct Pending {
     hipEvent_t a, b;
 };
 
+struct Batch;   // batched matching (hb_batch.cpp)
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -156,6 +158,7 @@ struct Ctx {
     hb_match_stats last{};
     uint32_t lds_limit = 0;
     CostModel model;
+    std::map<uint32_t, std::shared_ptr<Batch>> batches;
 
     void* raw_alloc(size_t bytes) {
         if (bytes == 0) bytes = 16;
@@ -240,7 +243,9 @@ inline T read1(Ctx* c, const T* dptr) {
     return v;
 }
 
-inline void zero(Ctx* c, void* p, size_t bytes) { HB_HIP(hipMemsetAsync(p, 0, bytes, c->stream)); }
+// Clears device memory with the library's own fill kernel (usable under
+// stream capture, unlike a runtime memset node).
+inline void zero(Ctx* c, void* p, size_t bytes) { HB_HIP(launch_zero_bytes(p, bytes, c->stream)); }
 
 inline Relation& get_rel(Ctx* c, uint32_t id) {
     auto it = c->rels.find(id);

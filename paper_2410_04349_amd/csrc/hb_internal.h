@@ -91,7 +91,8 @@ static_assert(sizeof(Instr) == 16, "Instr layout");
 struct Features {
     const uint64_t* f64;
     const uint32_t* f32;
-    uint64_t n;       // positions (rows with a valid key)
+    uint64_t n;       // column stride: positions (rows with a valid key) + kRows zeroed
+                      // pad positions, so a wave's 16-row batch reads in bounds
 };
 
 // Everything the match kernel needs for one (relation, key partition, plan).
@@ -137,7 +138,8 @@ struct MatchParams {
 struct GatherParams {
     const ColDev* cols;
     const uint32_t* perm;
-    uint64_t n;
+    uint64_t n;           // positions
+    uint64_t stride;      // column stride (>= n; positions n .. stride - 1 are zeroed)
     uint32_t n_int, n_str, n_gram;
     uint32_t int_attr[kMaxIntRes];
     uint32_t str_attr[kMaxStrRes];
@@ -232,6 +234,7 @@ struct PredSpec {
     uint64_t param;
 };
 constexpr int kMaxSpecs = 64;
+constexpr uint32_t kFeatureSample = 256;   // positions per block the features are computed on
 constexpr int kFeatures = 16;
 
 struct LearnParams {
@@ -275,6 +278,17 @@ struct PlanChoiceParams {
     unsigned long long* stats;        // [3] blocks with a learned plan, blocks over capacity, plans written
 };
 hipError_t launch_plan_choice(const PlanChoiceParams& p, hipStream_t s);
+
+// Persistent work-stealing matching over n_parts partitions (device array
+// mps, tile prefix over them, total items); `cursor` must be zero at launch.
+hipError_t launch_match_persistent(const MatchParams* mps, const uint64_t* prefix, uint32_t n_parts, uint64_t total,
+                                   unsigned long long* cursor, uint32_t grab, uint32_t grid, uint32_t lds_bytes,
+                                   hipStream_t s);
+hipError_t match_persistent_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
+// p[0 .. n) = v (a kernel, so it may be captured in a graph)
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
+// bytes [p, p + n) = 0 (a kernel)
+hipError_t launch_zero_bytes(void* p, size_t n, hipStream_t s);
 
 // ------------------------------------------------------------ cost model
 // C[M x N] = op(A) op(B) (+ bias[N]); op(X) = X or X^T (row-major storage

@@ -1,0 +1,51 @@
+// Per-key-partition plans of libhb (shared by single and batched matching).
+#pragma once
+
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+#include "hb_ctx.h"
+#include "hb_internal.h"
+#include "hb_plan.h"
+
+namespace hb {
+
+// Resources of one key partition's plans, fixed by the rule set (not by
+// the evaluation order), so every order of the same rules reads the same
+// gathered feature columns.
+struct KeyRes {
+    std::vector<uint32_t> int_attr, str_attr, prev;
+    std::vector<std::pair<uint32_t, uint32_t>> gram_key;
+    std::vector<PredSpec> specs;   // predicates evaluated in this partition, by id
+    bool any_ed = false;
+    bool any_rule = false;
+};
+
+// One key partition ready to match: gathered feature columns, LDS layout
+// and the plan (host bytecode, or per-slot plans already on the device).
+struct KeyPlan {
+    std::vector<Instr> code;
+    MatchParams mp{};
+    DevBuf f64, f32;
+    // learned plans: per-slot plans on the device, the block -> slot map and
+    // the choice kernel's counters (read after matching)
+    bool own_code = false;
+    DevBuf dev_code, blk_slot, choice_stats;
+};
+
+// The evaluation path of a plan kind (given order or the Section 4.2 plan;
+// the learned plan starts from the latter).
+std::vector<PathRule> plan_path(const RuleSet& rs, int plan);
+
+// Builds key `ka`'s partition plan; false if no rule can hold there.
+// Learned plans add the blocks kept on the heuristic plan for structural
+// reasons to *n_fallback.
+bool key_plan(Ctx* c, Relation& rel, RuleSet& rs, int plan, const std::vector<PathRule>& path, size_t ka,
+              KeyPlan& kp, bool count, uint64_t* n_fallback);
+
+// Sorts n packed pairs (i << 32) | j (i, j < n_rows) of `pairs` ascending
+// into `result` (resized to max(n, 1) entries).
+void sort_pairs(Ctx* c, DevBuf& pairs, uint64_t n, uint64_t n_rows, DevBuf& result);
+
+}  // namespace hb

@@ -167,16 +167,31 @@ __device__ inline bool absdiff_le(int64_t a, int64_t b, int64_t d) {
     return diff <= (uint64_t)d;
 }
 
+// Pointers that live in device memory, stated to the compiler: pointers
+// read out of a parameter block in memory are otherwise generic, and
+// generic loads of wave-uniform addresses do not become scalar loads.
+// (The host pass of the single-source build only needs the kernels' stubs.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HB_GLOBAL __attribute__((address_space(1)))
+#else
+#define HB_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ const HB_GLOBAL T* gmem(const T* p) {
+    return (const HB_GLOBAL T*)p;
+}
+
 // tile index -> (block, ti, tj), tiles of a block enumerated column-major
 // over the upper triangle: column tj holds ti = 0..tj.
 __device__ inline void decode_tile(const MatchParams& P, uint64_t t, uint32_t* b, uint32_t* ti, uint32_t* tj) {
+    const HB_GLOBAL uint64_t* tp = gmem(P.tile_prefix);
     uint32_t lo = 0, hi = P.n_blocks - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
-        if (P.tile_prefix[mid] <= t) lo = mid; else hi = mid - 1;
+        if (tp[mid] <= t) lo = mid; else hi = mid - 1;
     }
     *b = lo;
-    const uint64_t u = t - P.tile_prefix[lo];
+    const uint64_t u = t - tp[lo];
     uint64_t c = (uint64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
     while (c * (c + 1) / 2 > u) --c;
     while ((c + 1) * (c + 2) / 2 <= u) ++c;
@@ -200,28 +215,19 @@ struct Cache16 {
     }
 };
 
+// One 64 x 64 tile t of partition P by the whole workgroup: stage the
+// j-tile's features in LDS, then each wave evaluates its 16 i-rows against
+// the 64 j-lanes.  Wave-uniform values are passed through readfirstlane so
+// the compiler keeps them (and the loads they address) scalar.
 template <bool kCount>
-__global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const Instr* __restrict__ plan,
-                                                   const uint64_t* __restrict__ f64,
-                                                   const uint32_t* __restrict__ f32) {
-    extern __shared__ __align__(16) uint8_t lds[];
-    // wave-uniform values are passed through readfirstlane so the compiler
-    // keeps them (and the loads they address) scalar
+__device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL Instr* __restrict__ plan,
+                                           const HB_GLOBAL uint64_t* __restrict__ f64,
+                                           const HB_GLOBAL uint32_t* __restrict__ f32, uint64_t t, uint8_t* lds) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-
-    // XCD-aware remap: consecutive workgroups go round-robin to the 8 XCDs;
-    // give each XCD a contiguous range of tiles so a block's tiles share L2.
-    const uint64_t G = gridDim.x;
-    const uint64_t bid = blockIdx.x;
-    const uint64_t xcd = bid & 7, idx = bid >> 3;
-    const uint64_t q8 = G >> 3, r8 = G & 7;
-    const uint64_t t = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
-    if (t >= P.n_tiles) return;
-
     uint32_t b, ti, tj;
     decode_tile(P, t, &b, &ti, &tj);
-    const uint32_t bstart = P.blk_start[b], bsize = P.blk_size[b];
+    const uint32_t bstart = gmem(P.blk_start)[b], bsize = gmem(P.blk_size)[b];
     const uint32_t i0 = ti * kTile, j0 = tj * kTile;
     const uint32_t ni = min((uint32_t)kTile, bsize - i0), nj = min((uint32_t)kTile, bsize - j0);
     const bool diag = ti == tj;
@@ -259,9 +265,9 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const I
         const uint32_t vmask_j = s32[kTile + lane];
         uint8_t* wbase = lds + P.lds_wave_base + wave * P.lds_wave_stride;
         uint8_t* peq = wbase + P.lds_wave_peq;
-        const Instr* __restrict__ pl = plan;
+        const HB_GLOBAL Instr* __restrict__ pl = plan;
         uint32_t plen = P.plan_len;
-        if (P.blk_slot) pl = plan + (size_t)P.blk_slot[b] * plen;
+        if (P.blk_slot) pl = plan + (size_t)gmem(P.blk_slot)[b] * plen;
 
         // bit r of a lane's masks = the pair (row r, this lane's j)
         uint32_t pairs = 0;
@@ -294,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const I
         while (pc < plen) {
             pc = __builtin_amdgcn_readfirstlane(pc);
             // one 16-byte scalar load (there is no scalar byte load)
-            const uint4 raw = *(const uint4*)(pl + pc);
+            const uint4 raw = *(const HB_GLOBAL uint4*)(pl + pc);
             const uint32_t op = raw.x & 0xFFu, res = (raw.x >> 16) & 0xFFu;
             const uint32_t cp = raw.y & 0xFFFFu;
             const uint64_t param = ((uint64_t)raw.w << 32) | raw.z;
@@ -316,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const I
                 uint32_t keep = 0;
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) {
-                    const uint64_t pr = pi0 + (uint64_t)(r < nr ? r : 0);   // rows >= nr are masked off
+                    const uint64_t pr = pi0 + (uint64_t)r;   // rows >= nr: masked off, read in the pad
                     const int64_t vi = (int64_t)f64[res * n + pr];
                     const uint32_t iv = (f32[n + pr] >> res) & 1;
                     const bool ok = op == OP_EQ_INT ? vi == vj : absdiff_le(vi, vj, (int64_t)param);
@@ -335,7 +341,7 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const I
                 uint32_t keep = 0;
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) {
-                    const uint64_t pr = pi0 + (uint64_t)(r < nr ? r : 0);
+                    const uint64_t pr = pi0 + (uint64_t)r;
                     const uint32_t li = f32[(str32 + res) * n + pr];
                     const uint64_t ci = f64[(str64 + res) * n + pr];
                     const uint32_t iv = (f32[n + pr] >> (16 + res)) & 1;
@@ -353,22 +359,23 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const I
                 break;
             }
             case OP_JACF: {
-                const uint64_t sb = s32[(gram32 + res) * kTile + lane] & 0x7FFFFFFFu;
+                // set sizes are < 2^31: the bound in 32 bits, the products in 64
+                const uint32_t sb = s32[(gram32 + res) * kTile + lane] & 0x7FFFFFFFu;
                 const uint64_t gj = s64[(gram64 + res) * kTile + lane];
                 const uint32_t jv = (vmask_j >> (24 + res)) & 1;
-                const uint64_t num = param >> 32, den = param & 0xFFFFFFFFu;
+                const uint64_t num = param >> 32, nd = num + (param & 0xFFFFFFFFu);
                 const uint64_t nsb = num * sb;
                 uint32_t keep = 0;
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) {
-                    const uint64_t pr = pi0 + (uint64_t)(r < nr ? r : 0);
-                    const uint64_t sa = f32[(gram32 + res) * n + pr] & 0x7FFFFFFFu;
+                    const uint64_t pr = pi0 + (uint64_t)r;
+                    const uint32_t sa = f32[(gram32 + res) * n + pr] & 0x7FFFFFFFu;
                     const uint64_t gi = f64[(gram64 + res) * n + pr];
                     const uint32_t iv = (f32[n + pr] >> (24 + res)) & 1;
-                    const uint64_t ua = sa - (uint64_t)__popcll(gi & ~gj);
-                    const uint64_t ub = sb - (uint64_t)__popcll(gj & ~gi);
-                    const uint64_t iub = ua < ub ? ua : ub;
-                    const bool ok = iub * (num + den) >= num * sa + nsb;
+                    const uint32_t ua = sa - (uint32_t)__popcll(gi & ~gj);
+                    const uint32_t ub = sb - (uint32_t)__popcll(gj & ~gi);
+                    const uint32_t iub = ua < ub ? ua : ub;
+                    const bool ok = (uint64_t)iub * nd >= num * sa + nsb;
                     keep |= ((ok ? 1u : 0u) & iv) << r;
                 }
                 alive &= jv ? keep : 0u;
@@ -485,6 +492,73 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const I
     }
 }
 
+template <bool kCount>
+__global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const Instr* __restrict__ plan,
+                                                   const uint64_t* __restrict__ f64,
+                                                   const uint32_t* __restrict__ f32) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    // XCD-aware remap: consecutive workgroups go round-robin to the 8 XCDs;
+    // give each XCD a contiguous range of tiles so a block's tiles share L2.
+    const uint64_t G = gridDim.x;
+    const uint64_t bid = blockIdx.x;
+    const uint64_t xcd = bid & 7, idx = bid >> 3;
+    const uint64_t q8 = G >> 3, r8 = G & 7;
+    const uint64_t t = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+    if (t >= P.n_tiles) return;
+    match_tile<kCount>(P, gmem(plan), gmem(f64), gmem(f32), t, lds);
+}
+
+// Persistent, work-stealing form over many partitions (of many relations):
+// a workgroup takes `grab` consecutive work items from a global cursor until
+// the queue is exhausted.  Item x belongs to partition p with
+// prefix[p] <= x < prefix[p + 1] (partitions ordered heaviest first).  Every
+// wave reaches every barrier: the loop condition is workgroup-uniform.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_match_persistent(const MatchParams* __restrict__ mps,
+                                                              const uint64_t* __restrict__ prefix, uint32_t n_parts,
+                                                              uint64_t total, unsigned long long* cursor,
+                                                              uint32_t grab) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ unsigned long long s_item;
+    for (;;) {
+        __syncthreads();   // the previous tile's LDS reads and s_item reads are done
+        if (threadIdx.x == 0) s_item = atomicAdd(cursor, (unsigned long long)grab);
+        __syncthreads();
+        const uint64_t first = s_item;
+        if (first >= total) break;
+        const uint64_t last = first + grab < total ? first + grab : total;
+        for (uint64_t item = first; item < last; ++item) {
+            uint32_t lo = 0, hi = n_parts;   // prefix[lo] <= item < prefix[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (prefix[mid] <= item) lo = mid; else hi = mid;
+            }
+            lo = __builtin_amdgcn_readfirstlane(lo);
+            const MatchParams& P = mps[lo];
+            if (item > first) __syncthreads();
+            match_tile<false>(P, gmem(P.plan), gmem(P.feat.f64), gmem(P.feat.f32), item - prefix[lo], lds);
+        }
+    }
+}
+
+// 16-byte stores over the aligned middle, byte stores at the ends.
+__global__ void k_zero_bytes(uint8_t* p, size_t n) {
+    const size_t lead = (16 - ((uintptr_t)p & 15)) & 15;
+    const size_t head = lead < n ? lead : n;
+    const size_t words = (n - head) / 16;
+    const size_t tail = head + words * 16;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t x0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint4* w = (uint4*)(p + head);
+    for (size_t x = x0; x < words; x += stride) w[x] = make_uint4(0u, 0u, 0u, 0u);
+    if (x0 < head) p[x0] = 0;
+    if (x0 < n - tail) p[tail + x0] = 0;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
+    const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) p[x] = v;
+}
+
 // ------------------------------------------------------------ learned plan
 
 // splitmix64 output function (Steele, Lea and Flood, OOPSLA 2014)
@@ -545,7 +619,8 @@ __device__ inline bool feature_filter(const LearnParams& L, const PredSpec& sp, 
 // 16 features per (block, predicate): op one-hot (4), threshold relative to
 // the data, threshold shape, log2 block size, length (or set size) mean / std /
 // min / max, 3-bin length histogram, the fraction of adjacent position pairs
-// passing the predicate's filter, mean signature density.
+// passing the predicate's filter, mean signature density.  Statistics are
+// taken over at most kFeatureSample evenly spaced positions of the block.
 // One wave per block; blocks below L.min_size get all-zero features.
 __global__ __launch_bounds__(64) void k_block_features(const LearnParams L) {
     const MatchParams& P = L.mp;
@@ -559,12 +634,15 @@ __global__ __launch_bounds__(64) void k_block_features(const LearnParams L) {
     const uint64_t n = P.feat.n;
     const uint64_t* f64 = P.feat.f64;
     const uint32_t* f32 = P.feat.f32;
+    const uint32_t ns_pos = nb < kFeatureSample ? nb : kFeatureSample;
     for (uint32_t s = 0; s < L.n_spec; ++s) {
         const PredSpec sp = L.spec[s];
         const bool is_int = sp.op == OP_EQ_INT || sp.op == OP_ABSDIFF;
         const bool is_gram = sp.op == OP_JAC;
         double cnt = 0, sum = 0, sum2 = 0, mn = 1e300, mx = -1e300, b0 = 0, b1 = 0, b2 = 0, pops = 0, pass = 0;
-        for (uint32_t x = threadIdx.x; x < nb; x += 64) {
+        // statistics over at most kFeatureSample evenly spaced positions
+        for (uint32_t u = threadIdx.x; u < ns_pos; u += 64) {
+            const uint32_t x = (uint32_t)(((uint64_t)u * nb) / ns_pos);
             const uint64_t pos = (uint64_t)start + x;
             const uint32_t vm = f32[n + pos];
             double lv = 0.0;
@@ -637,7 +715,7 @@ __global__ __launch_bounds__(64) void k_block_features(const LearnParams L) {
                 f[12] = (float)(b1 / c);
                 f[13] = (float)(b2 / c);
             }
-            f[14] = (float)(pass / (double)(nb - 1));
+            f[14] = (float)(pass / (double)(ns_pos - (ns_pos == nb ? 1 : 0)));
             f[15] = (float)(pops / c / 64.0);
         }
     }
@@ -734,20 +812,21 @@ __global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
 // ------------------------------------------------------------ plan choice
 
 // Probability that some pair of a batch of `batch` pairs survives a step
-// sequence that each pair survives with probability p.
-__device__ inline double batch_any(double p, double batch) {
-    if (p <= 0.0) return 0.0;
-    if (p >= 1.0) return 1.0;
-    return -expm1(batch * log1p(-p));
+// sequence that each pair survives with probability p.  The plan choice
+// only ranks alternatives, so single precision and fast intrinsics do.
+__device__ inline float batch_any(float p, float batch) {
+    if (p <= 0.f) return 0.f;
+    if (p >= 1.f) return 1.f;
+    return 1.f - __expf(batch * __logf(1.f - p));
 }
 
 // First-stage step cost per row, in the library's lane-op units.
-__device__ inline double first_cost(uint8_t op) {
+__device__ inline float first_cost(uint8_t op) {
     switch (op) {
-    case OP_EQ_INT: return 1.0;
-    case OP_ABSDIFF: return 4.0;
-    case OP_EQ_STR: return 3.0;
-    default: return 12.0;
+    case OP_EQ_INT: return 1.f;
+    case OP_ABSDIFF: return 4.f;
+    case OP_EQ_STR: return 3.f;
+    default: return 12.f;
     }
 }
 
@@ -755,22 +834,22 @@ __device__ inline bool verifies(uint8_t op) { return op == OP_EQ_STR || op == OP
 
 struct BlockEst {
     const float* y;
-    __device__ double pass(uint32_t s) const {
+    __device__ float pass(uint32_t s) const {
         const float v = y[2 * s];
-        return isfinite(v) ? fmin(1.0, fmax(0.0, (double)v)) : 1.0;
+        return isfinite(v) ? fminf(1.f, fmaxf(0.f, v)) : 1.f;
     }
-    __device__ double cycles(uint32_t s) const {
+    __device__ float cycles(uint32_t s) const {
         const float v = y[2 * s + 1];
-        return isfinite(v) ? exp2(fmin(30.0, fmax(0.0, 16.0 * (double)v))) : 1e9;
+        return isfinite(v) ? exp2f(fminf(30.f, fmaxf(0.f, 16.f * v))) : 1e9f;
     }
 };
 
 // Expected first-stage cost of a wave batch running a rule's steps in
 // order `ord` (indices into the rule's steps): a step runs while some pair
 // of the batch survives every step before it.
-__device__ inline double stage_cost(const PlanChoiceParams& C, uint32_t r, const uint8_t* ord, int len,
-                                    const BlockEst& e, double batch) {
-    double total = 0.0, surv = 1.0, alive = 1.0;
+__device__ inline float stage_cost(const PlanChoiceParams& C, uint32_t r, const uint8_t* ord, int len,
+                                   const BlockEst& e, float batch) {
+    float total = 0.f, surv = 1.f, alive = 1.f;
     for (int k = 0; k < len; ++k) {
         const uint32_t sx = C.rule_spec[r][ord[k]];
         total += alive * first_cost(C.spec_kind[sx]);
@@ -782,12 +861,12 @@ __device__ inline double stage_cost(const PlanChoiceParams& C, uint32_t r, const
 
 // Expected cost of the exact checks in order `ord`, each taken to stop half
 // of the rows that reach it.
-__device__ inline double verify_cost(const PlanChoiceParams& C, uint32_t r, const uint8_t* ord, int len,
-                                     const BlockEst& e) {
-    double total = 0.0, w = 1.0;
+__device__ inline float verify_cost(const PlanChoiceParams& C, uint32_t r, const uint8_t* ord, int len,
+                                    const BlockEst& e) {
+    float total = 0.f, w = 1.f;
     for (int k = 0; k < len; ++k) {
         total += w * e.cycles(C.rule_spec[r][ord[k]]);
-        w *= 0.5;
+        w *= 0.5f;
     }
     return total;
 }
@@ -803,22 +882,22 @@ __device__ inline uint64_t pack_order(const uint8_t* ord, int len) {
 // batch passes the step) and the exact checks by predicted cycles
 // ascending, each taken only when the model expects it at least 2% cheaper
 // than the heuristic order.  Writes the block's plan slot.
-__device__ inline void rule_choice(const PlanChoiceParams& C, uint32_t r, const BlockEst& e, double batch,
+__device__ inline void rule_choice(const PlanChoiceParams& C, uint32_t r, const BlockEst& e, float batch,
                                    uint8_t* fo, uint8_t* vo, int* nv) {
     const int len = C.rule_len[r];
     uint8_t id[kMaxRuleSteps], lo[kMaxRuleSteps];
-    double rank[kMaxRuleSteps];
+    float rank[kMaxRuleSteps];
     for (int k = 0; k < len; ++k) {
         id[k] = (uint8_t)k;
         lo[k] = (uint8_t)k;
         const uint32_t sx = C.rule_spec[r][k];
-        rank[k] = first_cost(C.spec_kind[sx]) / fmax(1e-12, 1.0 - batch_any(e.pass(sx), batch));
+        rank[k] = first_cost(C.spec_kind[sx]) / fmaxf(1e-20f, 1.f - batch_any(e.pass(sx), batch));
     }
     for (int a = 1; a < len; ++a)   // stable insertion sort by rank
         for (int k = a; k > 0 && rank[lo[k]] < rank[lo[k - 1]]; --k) {
             const uint8_t t = lo[k]; lo[k] = lo[k - 1]; lo[k - 1] = t;
         }
-    const bool take = stage_cost(C, r, lo, len, e, batch) < 0.98 * stage_cost(C, r, id, len, e, batch);
+    const bool take = stage_cost(C, r, lo, len, e, batch) < 0.98f * stage_cost(C, r, id, len, e, batch);
     for (int k = 0; k < len; ++k) fo[k] = take ? lo[k] : id[k];
     // exact checks in first-stage order (the heuristic), or by cycles
     uint8_t hv[kMaxRuleSteps];
@@ -831,7 +910,7 @@ __device__ inline void rule_choice(const PlanChoiceParams& C, uint32_t r, const 
         for (int k = a; k > 0 && e.cycles(C.rule_spec[r][lv[k]]) < e.cycles(C.rule_spec[r][lv[k - 1]]); --k) {
             const uint8_t t = lv[k]; lv[k] = lv[k - 1]; lv[k - 1] = t;
         }
-    const bool vtake = verify_cost(C, r, lv, m, e) < 0.98 * verify_cost(C, r, hv, m, e);
+    const bool vtake = verify_cost(C, r, lv, m, e) < 0.98f * verify_cost(C, r, hv, m, e);
     for (int k = 0; k < m; ++k) vo[k] = vtake ? lv[k] : hv[k];
     *nv = m;
 }
@@ -839,7 +918,7 @@ __device__ inline void rule_choice(const PlanChoiceParams& C, uint32_t r, const 
 // The first block to claim a slot writes its plan: every rule segment of the
 // heuristic plan holds [first-stage steps][exact checks][checkpoint] in step
 // order; the segment is rewritten in the chosen orders.
-__device__ inline void write_plan(const PlanChoiceParams& C, uint32_t x, const BlockEst& e, double batch) {
+__device__ inline void write_plan(const PlanChoiceParams& C, uint32_t x, const BlockEst& e, float batch) {
     Instr* dst = C.code + (size_t)x * C.plan_len;
     const Instr* base = C.code;
     for (uint32_t i = 0; i < C.plan_len; ++i) dst[i] = base[i];
@@ -868,7 +947,7 @@ __global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
     bool learned = false, overflow = false, wrote = false;
     if (b < C.n_blocks) {
         const uint32_t nb = C.blk_size[b];
-        const double batch = (double)min(nb, (uint32_t)kRows) * (double)min(nb, (uint32_t)kTile);
+        const float batch = (float)min(nb, (uint32_t)kRows) * (float)min(nb, (uint32_t)kTile);
         BlockEst e{C.y + (size_t)b * C.n_spec * 2};
         uint64_t h = 0x6A09E667F3BCC909ull;
         if (nb >= C.min_size) {
@@ -943,6 +1022,44 @@ hipError_t launch_match(const MatchParams& p, hipStream_t s) {
         k_match<true><<<(unsigned)p.n_tiles, kThreads, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
     else
         k_match<false><<<(unsigned)p.n_tiles, kThreads, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
+    return hipGetLastError();
+}
+
+hipError_t launch_match_persistent(const MatchParams* mps, const uint64_t* prefix, uint32_t n_parts, uint64_t total,
+                                   unsigned long long* cursor, uint32_t grab, uint32_t grid, uint32_t lds_bytes,
+                                   hipStream_t s) {
+    if (total == 0 || grid == 0) return hipSuccess;
+    static int configured = 0;
+    if (lds_bytes > 65536 && configured < (int)lds_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_match_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_bytes);
+        if (e != hipSuccess) return e;
+        configured = (int)lds_bytes;
+    }
+    k_match_persistent<<<grid, kThreads, lds_bytes, s>>>(mps, prefix, n_parts, total, cursor, grab);
+    return hipGetLastError();
+}
+
+hipError_t match_persistent_occupancy(uint32_t lds_bytes, int* blocks_per_cu) {
+    if (lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_match_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_match_persistent, kThreads, lds_bytes);
+}
+
+hipError_t launch_zero_bytes(void* p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const size_t words = n / 16 + 1;
+    const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 4096);
+    k_zero_bytes<<<blocks, 256, 0, s>>>((uint8_t*)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_fill_u64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
     return hipGetLastError();
 }
 

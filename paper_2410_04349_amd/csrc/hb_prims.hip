@@ -424,8 +424,13 @@ __global__ void k_gram_sig(const GramDev g, uint32_t n, uint64_t* __restrict__ s
 
 __global__ void k_gather_features(const GatherParams P) {
     const uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (p >= P.n) return;
-    const uint64_t n = P.n;
+    if (p >= P.stride) return;
+    const uint64_t n = P.stride;
+    if (p >= P.n) {   // pad position
+        for (uint32_t x = 0; x < P.n_int + P.n_str + P.n_gram; ++x) P.f64[x * n + p] = 0ull;
+        for (uint32_t x = 0; x < 2 + P.n_str + P.n_gram; ++x) P.f32[x * n + p] = 0u;
+        return;
+    }
     const uint32_t row = P.perm[p];
     uint32_t vmask = 0;
     for (uint32_t x = 0; x < P.n_int; ++x) {
@@ -704,7 +709,7 @@ hipError_t launch_gram_sig(const GramDev& g, uint32_t n, uint64_t* sig, hipStrea
 
 hipError_t launch_gather_features(const GatherParams& p, hipStream_t s) {
     if (p.n == 0) return hipSuccess;
-    k_gather_features<<<grid_for(p.n, 1u << 30), kBlock, 0, s>>>(p);
+    k_gather_features<<<grid_for(p.stride, 1u << 30), kBlock, 0, s>>>(p);
     return hipGetLastError();
 }
 
