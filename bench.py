@@ -78,6 +78,112 @@ def cpu_baseline(rel, rules, target_s: float, threads: int):
     return pairs / dt, pairs, dt, used
 
 
+def kernel_source_hash():
+    """sha256 of the match kernel's sources (hb_match.hip, hb_internal.h)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hb_match.hip", "hb_internal.h"):
+        with open(os.path.join(ROOT, "paper_2410_04349_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload, plan):
+    """HBM bytes per k_match launch from the committed PMC summary of this
+    workload and plan, or None when there is none or the kernel's sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_match_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.strip().startswith(("source_sha256", "plan", "traffic_bytes_per_launch")):
+                k, v = line.strip().split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != kernel_source_hash() or fields.get("plan") != plan:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def describe(workload, n_rows, n_rules, plan):
+    text = {
+        "plain_1m": "3 strings 5-40 B, capped-Zipf key (s=1.1, 50 values per 1k tuples, cap 5000), 2 ints, "
+                    "15% duplicates",
+        "learned_10m": "6 strings 5-60 B (2 key-correlated), 2 capped-Zipf keys (s=1.2, 50 values per 1k "
+                       "tuples, cap 5000), 2 ints, 10% duplicates",
+        "long_titles_5m": "product titles 20-200 B of Zipf pseudo-words, capped-Zipf brand key (s=1.3, cap 18), "
+                          "10% duplicates, ED<=8 and 2-gram Jaccard>=0.7",
+    }[workload]
+    return f"{workload}: {n_rows} tuples, {text}, {n_rules} rules, {plan} plan"
+
+
+def run_batched(args):
+    """64 relations of uneven sizes: one persistent, graph-captured,
+    autotuned launch for all of them against one hb_match per relation.  A
+    step = fresh rule sets for every relation, then the matching (batch
+    create + run, or the per-relation calls); relations stay loaded and
+    partitioned."""
+    import numpy as np
+    import torch
+
+    import paper_2410_04349_amd as hb
+    from gen import workloads
+    t = time.perf_counter()
+    jobs = workloads.batched_64(scale=args.n / 24_000_000 if args.n else 1.0)
+    n_rows = sum(r.n_rows for r, _ in jobs)
+    log(f"[bench] generated {len(jobs)} relations, {n_rows} tuples in {time.perf_counter() - t:.1f}s")
+    torch.cuda.set_device(0)
+    ctx = hb.hb_create(0, allocator="torch")
+    rids = [hb.hb_load_relation(ctx, rel.columns, rel.n_rows) for rel, _ in jobs]
+    dst = torch.empty(1 << 23, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+
+    def fresh():
+        ids, cand = [], 0
+        for rid, (_, rules) in zip(rids, jobs):
+            rs = hb.hb_compile_rules(ctx, rid, rules)
+            cand += hb.hb_partition(ctx, rid, rs)
+            ids.append((rid, rs))
+        return ids, cand
+
+    results = {}
+    for mode in ("separate", "batched"):
+        times = []
+        for k in range(args.warmup + args.steps):
+            ids, cand = fresh()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "separate":
+                total = sum(hb.hb_match(ctx, rid, rs, "heuristic", out=dst) for rid, rs in ids)
+            else:
+                bid = hb.hb_batch_create(ctx, ids, "heuristic", graph=True, autotune=(k == 0))
+                total = hb.hb_batch_run(ctx, bid)
+                info = hb.hb_batch_info(ctx, bid)
+                hb.hb_batch_destroy(ctx, bid)
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(time.perf_counter() - t0)
+        results[mode] = {"s_per_step": sum(times) / len(times), "pairs": cand, "matched": int(total)}
+        log(f"[bench] {mode}: {results[mode]}")
+    value = results["batched"]["pairs"] / results["batched"]["s_per_step"]
+    result = {
+        "metric": "tuple pairs evaluated/sec on 1 MI355X, learned vs heuristic plan, bit-exact",
+        "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": results["batched"]["s_per_step"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"batched_64: {len(jobs)} relations, {n_rows} tuples (log-uniform 10k-2M), "
+                               f"1-10 rules each, heuristic plan, one persistent graph launch",
+                   "candidate_pairs": results["batched"]["pairs"], "matched_pairs": results["batched"]["matched"]},
+        "compare": {"mode": "separate hb_match per relation",
+                    "value": results["separate"]["pairs"] / results["separate"]["s_per_step"],
+                    "ms_per_step": results["separate"]["s_per_step"] * 1e3},
+        "batch": info,
+    }
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,11 +194,13 @@ def main():
     ap.add_argument("--save-model", default=None, help="write the trained cost-model parameters (.npy)")
     ap.add_argument("--model", default=None,
                     help="load cost-model parameters (.npy) written by --save-model instead of training")
-    ap.add_argument("--n", type=int, default=1_000_000, help="tuples of the plain workload")
+    ap.add_argument("--workload", default="plain_1m",
+                    choices=["plain_1m", "learned_10m", "long_titles_5m", "batched_64"])
+    ap.add_argument("--n", type=int, default=None, help="tuples (scales the workload's recipe down)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="run one 256 MiB read + 256 MiB write kernel first (scale reference for HBM counters)")
+                    help="run one 2 GiB read + 2 GiB write kernel first (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
@@ -104,13 +212,18 @@ def main():
     import paper_2410_04349_amd as hb
     from gen import workloads
 
+    if args.workload == "batched_64":
+        return run_batched(args)
     t = time.perf_counter()
-    rel, rules = workloads.plain_1m(n=args.n)
+    loader = {"plain_1m": workloads.plain_1m, "learned_10m": workloads.learned_10m,
+              "long_titles_5m": workloads.long_titles_5m}[args.workload]
+    rel, rules = loader(n=args.n) if args.n else loader()
     log(f"[bench] generated {rel.n_rows} tuples in {time.perf_counter() - t:.1f}s")
     torch.cuda.set_device(0)
     if args.copy_calibration:
-        # one elementwise kernel that reads 256 MiB and writes 256 MiB
-        a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        # one elementwise kernel that reads 2 GiB and writes 2 GiB (far larger
+        # than the 256 MB last-level cache, so its traffic is HBM traffic)
+        a = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         torch.neg(a, out=b)
@@ -129,7 +242,12 @@ def main():
     elif args.plan == "learned":
         t = time.perf_counter()
         xs, ts = [], []
-        for wrel, wrules in (workloads.person_small(), workloads.plain_1m(n=100_000)):
+        train_sets = [workloads.person_small(), workloads.plain_1m(n=100_000)]
+        if args.workload == "learned_10m":
+            # a small draw of the same recipe under another seed: logs of the
+            # plain method's runs on this kind of data
+            train_sets.append(workloads.learned_10m(seed=workloads.SEED_BASE + 104, n=200_000))
+        for wrel, wrules in train_sets:
             rid = hb.hb_load_relation(ctx, wrel.columns, wrel.n_rows)
             rs = hb.hb_compile_rules(ctx, rid, wrules)
             hb.hb_partition(ctx, rid, rs)
@@ -221,15 +339,14 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"plain_{args.n}: {args.n} tuples, 3 strings 5-40 B, capped-Zipf key "
-                               f"(s=1.1, 50k values, cap 5000), 2 ints, 15% duplicates, 5 rules, "
-                               f"{args.plan} plan", "plan": args.plan, "candidate_pairs": n_cand,
-                   "matched_pairs": n_match},
+        "config": {"workload": describe(args.workload, rel.n_rows, len(rules), args.plan), "plan": args.plan,
+                   "candidate_pairs": n_cand, "matched_pairs": n_match},
         "kernels_ms_per_step": {k: v["ms_total"] / args.steps for k, v in prof.items()},
         "compare": compare,
         "cost_model": learned,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s (int32 lane-ops)",
-                     "frac": achieved / peak, "traffic": None, "kernel": "k_match",
+                     "frac": achieved / peak, "traffic": recorded_traffic(args.workload, args.plan),
+                     "traffic_unit": "HBM bytes per launch", "kernel": "k_match",
                      "kernel_ms": match_ms, "lane_ops_per_launch": ops_per_launch,
                      "lane_ops_per_pair": work["lane_ops"] / max(1, work["pairs"])},
     }

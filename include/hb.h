@@ -56,6 +56,7 @@ typedef enum {
 #define HB_MAX_GRAM_LEN 4096     /* longest string of an attribute used by a Jaccard predicate */
 #define HB_MAX_ED_K 255
 #define HB_MAX_Q 4
+#define HB_MAX_JACCARD_DEN (1u << 18) /* threshold denominator in lowest terms */
 
 /* Device allocator: return `bytes` bytes of device memory on the context's
  * device (NULL on failure); `user` is passed through. */
@@ -95,6 +96,18 @@ typedef struct {
  * 1 <= n_cols <= 256.  String offsets are validated (HB_ERR_INVALID_ARG). */
 hb_status hb_load_relation(hb_ctx* ctx, uint32_t n_rows, uint32_t n_cols, const hb_column* cols,
                            int on_device, uint32_t* rel_id);
+
+/* As hb_load_relation, but returns once the copies are queued: they, and
+ * the offset validation, run on a second stream of the context, so a
+ * relation's host-to-device copy overlaps the matching of relations loaded
+ * before it (Section 5's pipeline overlaps transfer and compute).  The
+ * relation is finished on its first use by any other call (which waits for
+ * its copies); invalid offsets are reported there (HB_ERR_INVALID_ARG, the
+ * relation stays releasable).  The caller's arrays must stay valid and
+ * unchanged until then; host arrays should be pinned (hipHostMalloc) for
+ * the copy to be asynchronous. */
+hb_status hb_load_relation_async(hb_ctx* ctx, uint32_t n_rows, uint32_t n_cols, const hb_column* cols,
+                                 int on_device, uint32_t* rel_id);
 /* Release a relation and every rule set compiled against it. */
 hb_status hb_release_relation(hb_ctx* ctx, uint32_t rel_id);
 
@@ -122,7 +135,7 @@ typedef struct {
     int64_t k;      /* HB_ED_LE: 0..HB_MAX_ED_K */
     uint32_t q;     /* HB_JACCARD_GE: 1..HB_MAX_Q */
     uint32_t num;   /* HB_JACCARD_GE: threshold num/den, 0 <= num <= den */
-    uint32_t den;   /* HB_JACCARD_GE: den > 0 */
+    uint32_t den;   /* HB_JACCARD_GE: den > 0, <= HB_MAX_JACCARD_DEN in lowest terms */
     int64_t d;      /* HB_ABSDIFF_LE: d >= 0 */
 } hb_pred;
 

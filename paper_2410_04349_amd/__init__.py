@@ -39,7 +39,8 @@ _OP = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3}
 _PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC, "learned": HB_PLAN_LEARNED}
 
 EXPORTED = [
-    "hb_create", "hb_destroy", "hb_last_error", "hb_version", "hb_load_relation", "hb_release_relation",
+    "hb_create", "hb_destroy", "hb_last_error", "hb_version", "hb_load_relation", "hb_load_relation_async",
+    "hb_release_relation",
     "hb_compile_rules", "hb_partition", "hb_match", "hb_ruleset_estimates", "hb_ruleset_buckets",
     "hb_epg_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
     "hb_match_work", "hb_costmodel_init", "hb_costmodel_set_params", "hb_costmodel_get_params",
@@ -117,6 +118,7 @@ def _load_lib():
         "hb_last_error": (ctypes.c_char_p, [P]),
         "hb_version": (ctypes.c_char_p, []),
         "hb_load_relation": (I32, [P, U32, U32, ctypes.POINTER(HbColumn), ctypes.c_int, ctypes.POINTER(U32)]),
+        "hb_load_relation_async": (I32, [P, U32, U32, ctypes.POINTER(HbColumn), ctypes.c_int, ctypes.POINTER(U32)]),
         "hb_release_relation": (I32, [P, U32]),
         "hb_compile_rules": (I32, [P, U32, U32, ctypes.POINTER(HbRule), ctypes.POINTER(U32)]),
         "hb_partition": (I32, [P, U32, U32, ctypes.POINTER(U64)]),
@@ -240,18 +242,33 @@ def hb_last_error(ctx: Context) -> str:
     return _lib.hb_last_error(ctx.h).decode()
 
 
-def hb_load_relation(ctx: Context, columns: Sequence, n_rows: int, on_device: bool = False) -> int:
-    """columns: objects with .type ('string'|'categorical'|'int64') and
-    .offsets/.data (strings), .values (others), .valid (optional bitmap);
-    numpy arrays for host input, torch device tensors for device input."""
+def _columns(columns):
     arr = (HbColumn * len(columns))()
     for k, c in enumerate(columns):
         data = getattr(c, "data", None)
         if data is not None and len(data) == 0:
             data = None
         arr[k] = HbColumn(_COLTYPE[c.type], _ptr(c.offsets), _ptr(data), _ptr(c.values), _ptr(c.valid))
+    return arr
+
+
+def hb_load_relation(ctx: Context, columns: Sequence, n_rows: int, on_device: bool = False) -> int:
+    """columns: objects with .type ('string'|'categorical'|'int64') and
+    .offsets/.data (strings), .values (others), .valid (optional bitmap);
+    numpy arrays for host input, torch device tensors for device input."""
     rid = ctypes.c_uint32()
-    ctx.check(_lib.hb_load_relation(ctx.h, n_rows, len(columns), arr, int(on_device), ctypes.byref(rid)))
+    ctx.check(_lib.hb_load_relation(ctx.h, n_rows, len(columns), _columns(columns), int(on_device),
+                                    ctypes.byref(rid)))
+    return rid.value
+
+
+def hb_load_relation_async(ctx: Context, columns: Sequence, n_rows: int, on_device: bool = False) -> int:
+    """As hb_load_relation, returning once the copies are queued on the
+    context's copy stream; the arrays must stay alive and unchanged until
+    the relation's first use (pinned host memory for an asynchronous copy)."""
+    rid = ctypes.c_uint32()
+    ctx.check(_lib.hb_load_relation_async(ctx.h, n_rows, len(columns), _columns(columns), int(on_device),
+                                          ctypes.byref(rid)))
     return rid.value
 
 

@@ -22,6 +22,126 @@ namespace hb {
 
 // ------------------------------------------------------------ load
 
+// Asynchronous load: every copy and the offset validation run on the
+// context's copy stream; the relation is finished (its validation read
+// back, its column table uploaded) when a later call first uses it.
+static void load_relation_async(Ctx* c, uint32_t n_rows, uint32_t n_cols, const hb_column* cols, int on_device,
+                                uint32_t* rel_id) {
+    if (!cols || !rel_id) fail(HB_ERR_INVALID_ARG, "NULL argument");
+    if (n_rows == 0 || n_rows >= 0x80000000u) fail(HB_ERR_INVALID_ARG, "n_rows must be in [1, 2^31)");
+    if (n_cols == 0 || n_cols > 256) fail(HB_ERR_INVALID_ARG, "n_cols must be in [1, 256]");
+    if (!c->copy_stream) HB_HIP(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+    hipStream_t cs = c->copy_stream;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    auto rel = std::make_unique<Relation>();
+    rel->n_rows = n_rows;
+    rel->n_cols = n_cols;
+    rel->cols.resize(n_cols);
+    const size_t vbytes = (n_rows + 7) / 8;
+    // allocations are stream-ordered on the context stream; the copy stream
+    // starts after them
+    rel->load_stats.alloc(c, 32 * (size_t)n_cols);
+    zero(c, rel->load_stats.get(), rel->load_stats.size());
+    for (uint32_t a = 0; a < n_cols; ++a) {
+        const hb_column& in = cols[a];
+        Column& col = rel->cols[a];
+        col.type = in.type;
+        if (in.type == HB_COL_STRING) {
+            if (!in.offsets) fail(HB_ERR_INVALID_ARG, "string column " + std::to_string(a) + " has no offsets");
+            if (!in.bytes) fail(HB_ERR_INVALID_ARG, "string column " + std::to_string(a) + " has no bytes");
+            col.off.alloc(c, sizeof(uint64_t) * ((size_t)n_rows + 1));
+        } else if (in.type == HB_COL_CATEGORICAL || in.type == HB_COL_INT64) {
+            if (!in.values) fail(HB_ERR_INVALID_ARG, "column " + std::to_string(a) + " has no values");
+            col.values.alloc(c, sizeof(int64_t) * n_rows);
+        } else {
+            fail(HB_ERR_INVALID_ARG, "column " + std::to_string(a) + " has an unknown type");
+        }
+        if (in.valid) col.valid.alloc(c, vbytes);
+    }
+    hipEvent_t allocated;
+    HB_HIP(hipEventCreateWithFlags(&allocated, hipEventDisableTiming));
+    HB_HIP(hipEventRecord(allocated, c->stream));
+    HB_HIP(hipStreamWaitEvent(cs, allocated, 0));
+    (void)hipEventDestroy(allocated);
+    for (uint32_t a = 0; a < n_cols; ++a) {
+        const hb_column& in = cols[a];
+        Column& col = rel->cols[a];
+        if (in.type == HB_COL_STRING) {
+            HB_HIP(hipMemcpyAsync(col.off.get(), in.offsets, sizeof(uint64_t) * ((size_t)n_rows + 1), kind, cs));
+            uint8_t* st = rel->load_stats.as<uint8_t>() + 32 * a;
+            HB_HIP(launch_string_stats(col.off.as<uint64_t>(), n_rows, (uint32_t*)st, (unsigned long long*)(st + 8),
+                                       (uint32_t*)(st + 16), cs));
+        } else if (in.type == HB_COL_CATEGORICAL || in.type == HB_COL_INT64) {
+            HB_HIP(hipMemcpyAsync(col.values.get(), in.values, sizeof(int64_t) * n_rows, kind, cs));
+        }
+        if (in.valid) HB_HIP(hipMemcpyAsync(col.valid.get(), in.valid, vbytes, kind, cs));
+    }
+    // the byte arenas: their sizes are the offsets' last entries
+    for (uint32_t a = 0; a < n_cols; ++a) {
+        const hb_column& in = cols[a];
+        if (in.type != HB_COL_STRING) continue;
+        Column& col = rel->cols[a];
+        uint64_t total;
+        if (on_device) {
+            HB_HIP(hipMemcpyAsync(&total, in.offsets + n_rows, 8, hipMemcpyDeviceToHost, cs));
+            HB_HIP(hipStreamSynchronize(cs));
+        } else {
+            total = in.offsets[n_rows];
+        }
+        col.bytes.alloc(c, total + 16);
+        hipEvent_t e;
+        HB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HB_HIP(hipEventRecord(e, c->stream));
+        HB_HIP(hipStreamWaitEvent(cs, e, 0));
+        (void)hipEventDestroy(e);
+        if (total) HB_HIP(hipMemcpyAsync(col.bytes.get(), in.bytes, total, kind, cs));
+    }
+    HB_HIP(hipEventCreateWithFlags(&rel->ready, hipEventDisableTiming));
+    HB_HIP(hipEventRecord(rel->ready, cs));
+    rel->pending = true;
+    rel->id = c->next_id++;
+    *rel_id = rel->id;
+    c->rels[rel->id] = std::move(rel);
+}
+
+void finish_load(Ctx* c, Relation& rel) {
+    HB_HIP(hipStreamWaitEvent(c->stream, rel.ready, 0));
+    std::vector<uint32_t> h(8 * (size_t)rel.n_cols);
+    HB_HIP(hipMemcpyAsync(h.data(), rel.load_stats.get(), 32 * (size_t)rel.n_cols, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    // invalid offsets keep the relation unusable (every use reports them);
+    // it can still be released
+    for (uint32_t a = 0; a < rel.n_cols; ++a)
+        if (rel.cols[a].type == HB_COL_STRING && h[8 * (size_t)a + 4])
+            fail(HB_ERR_INVALID_ARG, "string offsets of column " + std::to_string(a) + " are invalid");
+    (void)hipEventDestroy(rel.ready);
+    rel.ready = nullptr;
+    rel.pending = false;
+    rel.h_cols.resize(rel.n_cols);
+    for (uint32_t a = 0; a < rel.n_cols; ++a) {
+        Column& col = rel.cols[a];
+        if (col.type == HB_COL_STRING) {
+            const uint32_t* st = h.data() + 8 * (size_t)a;
+            col.max_len = st[0];
+            uint64_t tot;
+            std::memcpy(&tot, st + 2, 8);
+            col.mean_len = (double)tot / (double)rel.n_rows;
+        }
+        ColDev d{};
+        d.type = col.type;
+        d.max_len = col.max_len;
+        d.off = col.off.as<uint64_t>();
+        d.bytes = col.bytes.as<uint8_t>();
+        d.values = col.values.as<int64_t>();
+        d.valid = col.valid.as<uint8_t>();
+        rel.h_cols[a] = d;
+    }
+    rel.d_cols.alloc(c, sizeof(ColDev) * rel.n_cols);
+    HB_HIP(hipMemcpyAsync(rel.d_cols.get(), rel.h_cols.data(), sizeof(ColDev) * rel.n_cols, hipMemcpyHostToDevice,
+                          c->stream));
+    rel.load_stats.release();
+}
+
 static void load_relation(Ctx* c, uint32_t n_rows, uint32_t n_cols, const hb_column* cols, int on_device,
                           uint32_t* rel_id) {
     if (!cols || !rel_id) fail(HB_ERR_INVALID_ARG, "NULL argument");
@@ -175,7 +295,7 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
         std::vector<uint32_t> ids;
         int64_t key = -1;
         for (uint32_t x = 0; x < rule.n_preds; ++x) {
-            const hb_pred& p = rule.preds[x];
+            hb_pred p = rule.preds[x];
             const std::string where = "rule " + std::to_string(r) + " predicate " + std::to_string(x);
             if (p.attr >= rel.n_cols) fail(HB_ERR_INVALID_ARG, where + ": attribute out of range");
             const int32_t t = rel.cols[p.attr].type;
@@ -193,6 +313,12 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
                 if (t != HB_COL_STRING) fail(HB_ERR_TYPE, where + ": Jaccard needs a string attribute");
                 if (p.q < 1 || p.q > HB_MAX_Q) fail(HB_ERR_INVALID_ARG, where + ": q must be in [1, 4]");
                 if (p.den == 0 || p.num > p.den) fail(HB_ERR_INVALID_ARG, where + ": need 0 <= num <= den, den > 0");
+                {   // lowest terms (equal thresholds dedup; the bounds below use 32-bit products)
+                    uint32_t a = p.num, b = p.den;
+                    while (b) { const uint32_t t2 = a % b; a = b; b = t2; }
+                    if (a > 1) { p.num /= a; p.den /= a; }
+                }
+                if (p.den > HB_MAX_JACCARD_DEN) fail(HB_ERR_LIMIT, where + ": threshold denominator above 2^18");
                 if (rel.cols[p.attr].max_len > HB_MAX_GRAM_LEN)
                     fail(HB_ERR_LIMIT, where + ": strings longer than 4096 bytes");
                 break;
@@ -377,8 +503,28 @@ static Partition& key_partition(Ctx* c, Relation& rel, uint32_t attr) {
         DevBuf ttmp(c, sizeof(uint64_t) * scan_tmp_elems((size_t)P.n_blocks + 1));
         HB_HIP(launch_exclusive_scan_u64(tiles.as<uint64_t>(), P.tile_prefix.as<uint64_t>(), (size_t)P.n_blocks + 1,
                                          ttmp.as<uint64_t>(), c->stream));
-        P.n_tiles = read1(c, P.tile_prefix.as<uint64_t>() + P.n_blocks);
-        P.pairs = read1(c, pairs.as<unsigned long long>());
+        // blocks holding at least one full row batch
+        const uint32_t nb = std::max<uint32_t>(P.n_blocks, 1);
+        DevBuf bflags(c, sizeof(uint32_t) * nb), bdest(c, sizeof(uint32_t) * nb);
+        DevBuf btmp(c, sizeof(uint32_t) * scan_tmp_elems(nb));
+        P.big.alloc(c, sizeof(uint32_t) * nb);
+        uint64_t h[2];
+        uint32_t hb2[2] = {0, 0};
+        if (P.n_blocks) {
+            HB_HIP(launch_size_flags(P.blk_size.as<uint32_t>(), P.n_blocks, kRows, bflags.as<uint32_t>(), c->stream));
+            HB_HIP(launch_exclusive_scan_u32(bflags.as<uint32_t>(), bdest.as<uint32_t>(), P.n_blocks,
+                                             btmp.as<uint32_t>(), c->stream));
+            HB_HIP(launch_compact_rows(bflags.as<uint32_t>(), bdest.as<uint32_t>(), P.n_blocks, P.big.as<uint32_t>(),
+                                       c->stream));
+            HB_HIP(hipMemcpyAsync(&hb2[0], bdest.as<uint32_t>() + P.n_blocks - 1, 4, hipMemcpyDeviceToHost, c->stream));
+            HB_HIP(hipMemcpyAsync(&hb2[1], bflags.as<uint32_t>() + P.n_blocks - 1, 4, hipMemcpyDeviceToHost, c->stream));
+        }
+        HB_HIP(hipMemcpyAsync(&h[0], P.tile_prefix.as<uint64_t>() + P.n_blocks, 8, hipMemcpyDeviceToHost, c->stream));
+        HB_HIP(hipMemcpyAsync(&h[1], pairs.get(), 8, hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+        P.n_tiles = h[0];
+        P.pairs = h[1];
+        P.n_big = hb2[0] + hb2[1];
     }
     auto res = rel.parts.emplace(attr, std::move(P));
     return res.first->second;
@@ -675,15 +821,17 @@ static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector
 // ------------------------------------------------------------ learned plan
 
 // Features of every (block, predicate) of key `ka` into `feat` (device).
+// Features of the listed blocks (all blocks when `blocks` is null).
 static void block_features(Ctx* c, const KeyPlan& kp, const KeyRes& R, DevBuf& feat, LearnParams& L,
-                           uint32_t min_size) {
+                           const uint32_t* blocks, uint32_t n_list) {
     if (R.specs.size() > (size_t)kMaxSpecs) fail(HB_ERR_LIMIT, "more than 64 predicates in one partition");
     L = LearnParams{};
     L.mp = kp.mp;
-    L.min_size = min_size;
+    L.blocks = blocks;
+    L.n_list = blocks ? n_list : kp.mp.n_blocks;
     for (size_t x = 0; x < R.specs.size(); ++x) L.spec[x] = R.specs[x];
     L.n_spec = (uint32_t)R.specs.size();
-    feat.alloc(c, sizeof(float) * kFeatures * std::max<size_t>((size_t)kp.mp.n_blocks * L.n_spec, 1));
+    feat.alloc(c, sizeof(float) * kFeatures * std::max<size_t>((size_t)L.n_list * L.n_spec, 1));
     L.features = feat.as<float>();
     c->timed("block_features", [&] { return launch_block_features(L, c->stream); });
 }
@@ -734,37 +882,42 @@ static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyP
         *n_fallback += nb;
         return;
     }
-    DevBuf feat;
-    LearnParams L;
-    block_features(c, kp, R, feat, L, kRows);
-    DevBuf y(c, sizeof(float) * 2 * (size_t)nb * ns);
-    c->host_timed("predict", [&] { costmodel_predict(c, feat.as<float>(), (uint64_t)nb * ns, 1, y.as<float>(), 1); });
-
-    C.y = y.as<float>();
-    C.blk_size = kp.mp.blk_size;
-    C.n_blocks = nb;
-    C.n_spec = ns;
-    C.n_rules = n_rules;
-    C.n_slots = std::min<uint32_t>(kPlanSlots, next_pow2(std::max<uint32_t>(2 * nb, 16)));
-    C.plan_len = kp.mp.plan_len;
-    C.min_size = kRows;
-    for (uint32_t x = 0; x < ns; ++x) C.spec_kind[x] = (uint8_t)R.specs[x].op;
-    DevBuf keys(c, sizeof(unsigned long long) * C.n_slots);
-    kp.dev_code.alloc(c, sizeof(Instr) * (size_t)C.n_slots * C.plan_len);
+    const Partition& part = rel.parts.at(rs.keys[ka]);
+    const uint32_t nl = part.n_big;   // blocks with per-block plans; the rest keep slot 0
     kp.blk_slot.alloc(c, sizeof(uint32_t) * nb);
+    zero(c, kp.blk_slot.get(), kp.blk_slot.size());
     kp.choice_stats.alloc(c, sizeof(unsigned long long) * 3);
-    zero(c, keys.get(), keys.size());
     zero(c, kp.choice_stats.get(), kp.choice_stats.size());
+    kp.own_code = true;
+    kp.mp.blk_slot = kp.blk_slot.as<uint32_t>();
+    kp.dev_code.alloc(c, sizeof(Instr) * (size_t)std::min<uint32_t>(kPlanSlots, next_pow2(std::max<uint32_t>(2 * nl, 16))) *
+                             kp.mp.plan_len);
     HB_HIP(hipMemcpyAsync(kp.dev_code.get(), kp.code.data(), sizeof(Instr) * kp.code.size(), hipMemcpyHostToDevice,
                           c->stream));
+    kp.mp.plan = kp.dev_code.as<Instr>();
+    if (nl == 0) return;
+    DevBuf feat;
+    LearnParams L;
+    block_features(c, kp, R, feat, L, part.big.as<uint32_t>(), nl);
+    DevBuf y(c, sizeof(float) * 2 * (size_t)nl * ns);
+    c->host_timed("predict", [&] { costmodel_predict(c, feat.as<float>(), (uint64_t)nl * ns, 1, y.as<float>(), 1); });
+
+    C.y = y.as<float>();
+    C.blocks = part.big.as<uint32_t>();
+    C.blk_size = kp.mp.blk_size;
+    C.n_blocks = nl;
+    C.n_spec = ns;
+    C.n_rules = n_rules;
+    C.n_slots = std::min<uint32_t>(kPlanSlots, next_pow2(std::max<uint32_t>(2 * nl, 16)));
+    C.plan_len = kp.mp.plan_len;
+    for (uint32_t x = 0; x < ns; ++x) C.spec_kind[x] = (uint8_t)R.specs[x].op;
+    DevBuf keys(c, sizeof(unsigned long long) * C.n_slots);
+    zero(c, keys.get(), keys.size());
     C.keys = keys.as<unsigned long long>();
     C.code = kp.dev_code.as<Instr>();
     C.blk_slot = kp.blk_slot.as<uint32_t>();
     C.stats = kp.choice_stats.as<unsigned long long>();
     c->timed("plan_choice", [&] { return launch_plan_choice(C, c->stream); });
-    kp.own_code = true;
-    kp.mp.plan = kp.dev_code.as<Instr>();
-    kp.mp.blk_slot = kp.blk_slot.as<uint32_t>();
 }
 
 static void log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t samples, uint64_t seed, float* features,
@@ -789,7 +942,7 @@ static void log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t sample
         if (!prepare_key(c, rel, rs, ka, kp, R, false)) continue;
         DevBuf feat;
         LearnParams L;
-        block_features(c, kp, R, feat, L, 0);
+        block_features(c, kp, R, feat, L, nullptr, 0);
         const size_t rows = (size_t)kp.mp.n_blocks * L.n_spec;
         DevBuf cnt(c, sizeof(unsigned long long) * 4 * std::max<size_t>(rows, 1));
         zero(c, cnt.get(), cnt.size());
@@ -1048,12 +1201,14 @@ hb_status hb_create(hb_ctx** out, int device, hb_alloc_fn alloc, hb_free_fn free
 void hb_destroy(hb_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->c.device);
+    if (ctx->c.copy_stream) (void)hipStreamSynchronize(ctx->c.copy_stream);
     (void)hipStreamSynchronize(ctx->c.stream);
     ctx->c.drain_profile();
     ctx->c.batches.clear();
     ctx->c.rulesets.clear();
     ctx->c.rels.clear();
     (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.copy_stream) (void)hipStreamDestroy(ctx->c.copy_stream);
     if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
     delete ctx;
 }
@@ -1065,9 +1220,16 @@ hb_status hb_load_relation(hb_ctx* ctx, uint32_t n_rows, uint32_t n_cols, const 
     return guard(ctx, [&](Ctx* c) { hb::load_relation(c, n_rows, n_cols, cols, on_device, rel_id); });
 }
 
+hb_status hb_load_relation_async(hb_ctx* ctx, uint32_t n_rows, uint32_t n_cols, const hb_column* cols,
+                                 int on_device, uint32_t* rel_id) {
+    return guard(ctx, [&](Ctx* c) { hb::load_relation_async(c, n_rows, n_cols, cols, on_device, rel_id); });
+}
+
 hb_status hb_release_relation(hb_ctx* ctx, uint32_t rel_id) {
     return guard(ctx, [&](Ctx* c) {
-        hb::get_rel(c, rel_id);
+        auto r = c->rels.find(rel_id);
+        if (r == c->rels.end()) hb::fail(HB_ERR_STALE_ID, "unknown relation id " + std::to_string(rel_id));
+        if (r->second->pending) HB_HIP(hipEventSynchronize(r->second->ready));   // its copies are done
         for (auto it = c->rulesets.begin(); it != c->rulesets.end();) {
             if (it->second->rel_id == rel_id) it = c->rulesets.erase(it); else ++it;
         }

@@ -28,7 +28,7 @@ struct Failure {
 #define HB_HIP(expr)                                                                               \
     do {                                                                                           \
         hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) fail(HB_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        if (e_ != hipSuccess) ::hb::fail(HB_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
 struct Ctx;
@@ -92,10 +92,23 @@ struct Partition {
     uint32_t attr = 0, n_valid = 0, n_blocks = 0;
     uint64_t n_tiles = 0, pairs = 0;
     DevBuf perm, blk_start, blk_size, tile_prefix;
+    DevBuf big;           // blocks of >= kRows tuples (the ones with per-block plans)
+    uint32_t n_big = 0;
 };
 
 struct Relation {
     uint32_t id = 0, n_rows = 0, n_cols = 0;
+    // asynchronous load: copies and validation queued on the copy stream,
+    // finished (event wait, validation read back) on first use
+    bool pending = false;
+    hipEvent_t ready = nullptr;
+    DevBuf load_stats;
+    Relation() = default;
+    Relation(const Relation&) = delete;
+    Relation& operator=(const Relation&) = delete;
+    ~Relation() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
     std::vector<Column> cols;
     std::vector<ColDev> h_cols;
     DevBuf d_cols;
@@ -145,6 +158,7 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t copy_stream = nullptr;   // asynchronous loads (created on first use)
     hb_alloc_fn alloc_fn = nullptr;
     hb_free_fn free_fn = nullptr;
     void* user = nullptr;
@@ -247,9 +261,12 @@ inline T read1(Ctx* c, const T* dptr) {
 // stream capture, unlike a runtime memset node).
 inline void zero(Ctx* c, void* p, size_t bytes) { HB_HIP(launch_zero_bytes(p, bytes, c->stream)); }
 
+void finish_load(Ctx* c, Relation& rel);   // hb_api.cpp
+
 inline Relation& get_rel(Ctx* c, uint32_t id) {
     auto it = c->rels.find(id);
     if (it == c->rels.end()) fail(HB_ERR_STALE_ID, "unknown relation id " + std::to_string(id));
+    if (it->second->pending) finish_load(c, *it->second);
     return *it->second;
 }
 

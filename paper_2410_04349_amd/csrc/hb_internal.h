@@ -187,6 +187,8 @@ hipError_t launch_gather_key(const ColDev* cols, uint32_t attr, unsigned long lo
                              const uint32_t* rows, uint32_t n, uint64_t* keys, hipStream_t s);
 hipError_t launch_compact_rows(const uint32_t* flags, const uint32_t* dest, uint32_t n,
                                uint32_t* rows, hipStream_t s);
+// flags[b] = size[b] >= min
+hipError_t launch_size_flags(const uint32_t* size, uint32_t n, uint32_t min, uint32_t* flags, hipStream_t s);
 hipError_t launch_group_heads(const ColDev* cols, const uint32_t* attrs, uint32_t n_attrs,
                               const uint32_t* rows, uint32_t n, uint32_t* head, hipStream_t s);
 hipError_t launch_group_sizes(const uint32_t* head, const uint32_t* gid, uint32_t n,
@@ -243,8 +245,9 @@ struct LearnParams {
     uint32_t n_spec;
     uint32_t samples;                // logging: sampled waves per block
     uint64_t seed;
-    float* features;                 // [n_blocks x n_spec x 16]
-    uint32_t min_size;               // features: blocks smaller than this get zeros
+    float* features;                 // [n_list x n_spec x 16]
+    const uint32_t* blocks;          // features of blocks[0 .. n_list); nullptr: every block
+    uint32_t n_list;
     unsigned long long* counts;      // logging: [n_blocks x n_spec x 4] {lanes, passed, cycles, first step passed}
 };
 hipError_t launch_block_features(const LearnParams& p, hipStream_t s);
@@ -256,19 +259,19 @@ hipError_t launch_log_samples(const LearnParams& p, hipStream_t s);
 // open-addressing table keyed by a hash of the choice; the first block to
 // claim a slot writes that slot's plan by permuting the heuristic plan inside
 // each rule's segment (segments keep their positions, so checkpoint targets
-// are unchanged).  Slot 0 is the heuristic plan, also taken by blocks below
-// min_size and when the table is full.
+// are unchanged).  Slot 0 is the heuristic plan, also taken by blocks not in
+// the list and when the table is full.
 constexpr int kMaxPlanRules = 64;
 constexpr int kMaxRuleSteps = 10;
 constexpr uint32_t kPlanSlots = 4096;   // power of two
 struct PlanChoiceParams {
-    const float* y;                   // [n_blocks x n_spec x 2] model outputs
+    const float* y;                   // [n_blocks x n_spec x 2] model outputs, in list order
+    const uint32_t* blocks;           // the listed blocks (the rest keep slot 0)
     const uint32_t* blk_size;
-    uint32_t n_blocks, n_spec;
+    uint32_t n_blocks, n_spec;        // n_blocks: list length
     uint32_t n_rules;                 // rules of the partition's plan, in heuristic order
     uint32_t n_slots;                 // table size (power of two, <= kPlanSlots)
     uint32_t plan_len;                // instructions of one plan
-    uint32_t min_size;
     uint8_t rule_len[kMaxPlanRules];  // steps per rule
     uint8_t rule_spec[kMaxPlanRules][kMaxRuleSteps];   // spec index of each step, heuristic order
     uint8_t spec_kind[kMaxSpecs];     // plan operation of each spec (Op)

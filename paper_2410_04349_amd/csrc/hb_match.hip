@@ -326,7 +326,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     const int64_t vi = (int64_t)f64[res * n + pr];
                     const uint32_t iv = (f32[n + pr] >> res) & 1;
                     const bool ok = op == OP_EQ_INT ? vi == vj : absdiff_le(vi, vj, (int64_t)param);
-                    keep |= ((ok ? 1u : 0u) & iv) << r;
+                    keep |= ok ? iv << r : 0u;
                 }
                 alive &= jv ? keep : 0u;
                 work = 1;
@@ -338,6 +338,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 const uint64_t cj = s64[(str64 + res) * kTile + lane];
                 const uint32_t jv = (vmask_j >> (16 + res)) & 1;
                 const int k = (int)param;
+                const int pcj = __popcll(cj);
                 uint32_t keep = 0;
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) {
@@ -349,22 +350,28 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     if (op == OP_EQF) {
                         ok = li == lj && ci == cj;
                     } else {
-                        const int d1 = __popcll(ci & ~cj), d2 = __popcll(cj & ~ci);
+                        // |ci \ cj| = |ci| - |ci & cj|, |ci| on the scalar unit
+                        const int both = __popcll(ci & cj);
+                        const int d1 = __popcll(ci) - both, d2 = pcj - both;
                         ok = abs((int)li - (int)lj) <= k && max(d1, d2) <= k;
                     }
-                    keep |= ((ok ? 1u : 0u) & iv) << r;
+                    keep |= ok ? iv << r : 0u;
                 }
                 alive &= jv ? keep : 0u;
                 work = 1;
                 break;
             }
             case OP_JACF: {
-                // set sizes are < 2^31: the bound in 32 bits, the products in 64
+                // I <= |A| - |gA \ gB| and I <= |B| - |gB \ gA| with
+                // |gA \ gB| = |gA| - |gA & gB|: the bound is
+                // |gA & gB| + min(|A| - |gA|, |B| - |gB|).  Set sizes are
+                // <= 4096 and den <= 2^18, so both products fit 32 bits and
+                // take the full-rate 24-bit multiplier.
                 const uint32_t sb = s32[(gram32 + res) * kTile + lane] & 0x7FFFFFFFu;
                 const uint64_t gj = s64[(gram64 + res) * kTile + lane];
                 const uint32_t jv = (vmask_j >> (24 + res)) & 1;
-                const uint64_t num = param >> 32, nd = num + (param & 0xFFFFFFFFu);
-                const uint64_t nsb = num * sb;
+                const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
+                const uint32_t restb = sb - (uint32_t)__popcll(gj);
                 uint32_t keep = 0;
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) {
@@ -372,11 +379,10 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     const uint32_t sa = f32[(gram32 + res) * n + pr] & 0x7FFFFFFFu;
                     const uint64_t gi = f64[(gram64 + res) * n + pr];
                     const uint32_t iv = (f32[n + pr] >> (24 + res)) & 1;
-                    const uint32_t ua = sa - (uint32_t)__popcll(gi & ~gj);
-                    const uint32_t ub = sb - (uint32_t)__popcll(gj & ~gi);
-                    const uint32_t iub = ua < ub ? ua : ub;
-                    const bool ok = (uint64_t)iub * nd >= num * sa + nsb;
-                    keep |= ((ok ? 1u : 0u) & iv) << r;
+                    const uint32_t resta = sa - (uint32_t)__popcll(gi);
+                    const uint32_t iub = (uint32_t)__popcll(gi & gj) + min(resta, restb);
+                    const bool ok = __umul24(iub, nd) >= __umul24(num, sa + sb);
+                    keep |= ok ? iv << r : 0u;
                 }
                 alive &= jv ? keep : 0u;
                 work = 1;
@@ -621,16 +627,13 @@ __device__ inline bool feature_filter(const LearnParams& L, const PredSpec& sp, 
 // min / max, 3-bin length histogram, the fraction of adjacent position pairs
 // passing the predicate's filter, mean signature density.  Statistics are
 // taken over at most kFeatureSample evenly spaced positions of the block.
-// One wave per block; blocks below L.min_size get all-zero features.
+// One wave per listed block (workgroup g: block L.blocks[g], or block g
+// without a list); the features go to row g.
 __global__ __launch_bounds__(64) void k_block_features(const LearnParams L) {
     const MatchParams& P = L.mp;
-    const uint32_t b = blockIdx.x;
+    const uint32_t g = blockIdx.x;
+    const uint32_t b = L.blocks ? L.blocks[g] : g;
     const uint32_t start = P.blk_start[b], nb = P.blk_size[b];
-    if (nb < L.min_size) {
-        float* f = L.features + (size_t)b * L.n_spec * kFeatures;
-        for (uint32_t x = threadIdx.x; x < L.n_spec * kFeatures; x += 64) f[x] = 0.f;
-        return;
-    }
     const uint64_t n = P.feat.n;
     const uint64_t* f64 = P.feat.f64;
     const uint32_t* f32 = P.feat.f32;
@@ -682,7 +685,7 @@ __global__ __launch_bounds__(64) void k_block_features(const LearnParams L) {
         pops = wave_sum(pops);
         pass = wave_sum(pass);
         if (threadIdx.x == 0) {
-            float* f = L.features + ((size_t)b * L.n_spec + s) * kFeatures;
+            float* f = L.features + ((size_t)g * L.n_spec + s) * kFeatures;
             const double c = cnt > 0 ? cnt : 1.0;
             const double mean = sum / c;
             const double sd = sqrt(fmax(sum2 / c - mean * mean, 0.0));
@@ -943,14 +946,15 @@ __device__ inline void write_plan(const PlanChoiceParams& C, uint32_t x, const B
 // ascending, each taken only when the model expects it at least 2% cheaper
 // than the heuristic order.  Writes the block's plan slot.
 __global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     bool learned = false, overflow = false, wrote = false;
-    if (b < C.n_blocks) {
+    if (g < C.n_blocks) {
+        const uint32_t b = C.blocks[g];
         const uint32_t nb = C.blk_size[b];
         const float batch = (float)min(nb, (uint32_t)kRows) * (float)min(nb, (uint32_t)kTile);
-        BlockEst e{C.y + (size_t)b * C.n_spec * 2};
+        BlockEst e{C.y + (size_t)g * C.n_spec * 2};
         uint64_t h = 0x6A09E667F3BCC909ull;
-        if (nb >= C.min_size) {
+        {
             for (uint32_t r = 0; r < C.n_rules; ++r) {
                 uint8_t fo[kMaxRuleSteps], vo[kMaxRuleSteps];
                 int nv = 0;
@@ -1068,8 +1072,8 @@ hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
 namespace hb {
 
 hipError_t launch_block_features(const LearnParams& p, hipStream_t s) {
-    if (p.mp.n_blocks == 0 || p.n_spec == 0) return hipSuccess;
-    k_block_features<<<p.mp.n_blocks, 64, 0, s>>>(p);
+    if (p.n_list == 0 || p.n_spec == 0) return hipSuccess;
+    k_block_features<<<p.n_list, 64, 0, s>>>(p);
     return hipGetLastError();
 }
 

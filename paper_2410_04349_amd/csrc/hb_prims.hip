@@ -234,6 +234,12 @@ __global__ void k_multi_valid_flags(const ColDev* __restrict__ cols, const uint3
     flags[r] = f;
 }
 
+__global__ void k_size_flags(const uint32_t* __restrict__ size, uint32_t n, uint32_t min,
+                             uint32_t* __restrict__ flags) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n) flags[b] = size[b] >= min ? 1u : 0u;
+}
+
 __global__ void k_compact_rows(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ dest,
                                uint32_t n, uint32_t* __restrict__ rows) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -617,6 +623,12 @@ hipError_t launch_multi_valid_flags(const ColDev* cols, const uint32_t* attrs, u
 hipError_t launch_compact_rows(const uint32_t* flags, const uint32_t* dest, uint32_t n,
                                uint32_t* rows, hipStream_t s) {
     k_compact_rows<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(flags, dest, n, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_size_flags(const uint32_t* size, uint32_t n, uint32_t min, uint32_t* flags, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_size_flags<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(size, n, min, flags);
     return hipGetLastError();
 }
 

@@ -144,7 +144,8 @@ def test_jaccard_boundaries(hb, ctx, q):
         strings.append(base)
         strings.append(base[: L // 2] + b"z" + base[L // 2 + 1:])
     rel = _one_block_strings(strings)
-    for num, den in ((0, 1), (1, 2), (3, 5), (7, 10), (1, 1), (25, 31)):
+    for num, den in ((0, 1), (1, 2), (3, 5), (7, 10), (1, 1), (25, 31), (601, 1000), (599, 1000),
+                     ((1 << 18) - 5, 1 << 18), (1, 1 << 18)):
         rules = [[Pred(EQ, 1), Pred(JACCARD, 0, q=q, num=num, den=den)]]
         want = oracle.blocking(rel, rules)
         got, _ = run(hb, ctx, rel, rules, "given")
@@ -211,6 +212,16 @@ def test_capacity_protocol_and_errors(hb, ctx):
     with pytest.raises(hb.HbError) as e:
         hb.hb_compile_rules(ctx, rid, [[Pred(EQ, 2), Pred(JACCARD, 1, q=3, num=4, den=3)]])
     assert e.value.status == hb.HB_ERR_INVALID_ARG
+    # thresholds are kept in lowest terms: 6/10 and 3/5 are one predicate;
+    # a denominator above 2^18 in lowest terms is refused
+    rs2 = hb.hb_compile_rules(ctx, rid, [[Pred(EQ, 2), Pred(JACCARD, 1, q=3, num=6, den=10)],
+                                         [Pred(EQ, 2), Pred(JACCARD, 1, q=3, num=3, den=5)]])
+    sp, _ = hb.hb_ruleset_estimates(ctx, rs2)
+    assert len(sp) == 2
+    hb.hb_compile_rules(ctx, rid, [[Pred(EQ, 2), Pred(JACCARD, 1, q=3, num=2 << 18, den=4 << 18)]])
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_compile_rules(ctx, rid, [[Pred(EQ, 2), Pred(JACCARD, 1, q=3, num=1, den=(1 << 18) + 1)]])
+    assert e.value.status == hb.HB_ERR_LIMIT
     hb.hb_release_relation(ctx, rid)
     with pytest.raises(hb.HbError) as e:
         hb.hb_partition(ctx, rid, rs)
