@@ -151,6 +151,9 @@ def run_batched(args):
     for mode in ("separate", "batched"):
         times = []
         for k in range(args.warmup + args.steps):
+            if k == args.warmup:
+                hb.hb_profile_reset(ctx)
+                hb.hb_profile_enable(ctx, True)
             ids, cand = fresh()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -164,7 +167,13 @@ def run_batched(args):
             torch.cuda.synchronize()
             if k >= args.warmup:
                 times.append(time.perf_counter() - t0)
-        results[mode] = {"s_per_step": sum(times) / len(times), "pairs": cand, "matched": int(total)}
+        hb.hb_profile_enable(ctx, False)
+        kern = {}
+        for name in ("match", "batch_match", "output_sort"):
+            ms, launches = hb.hb_profile_query(ctx, name)
+            kern[name] = ms / args.steps
+        results[mode] = {"s_per_step": sum(times) / len(times), "pairs": cand, "matched": int(total),
+                         "kernel_ms_per_step": kern}
         log(f"[bench] {mode}: {results[mode]}")
     value = results["batched"]["pairs"] / results["batched"]["s_per_step"]
     result = {

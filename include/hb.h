@@ -326,7 +326,8 @@ hb_status hb_last_match_stats(hb_ctx* ctx, hb_match_stats* out);
  * (HB_ERR_STALE_ID on hb_batch_run otherwise).  Results equal hb_match's. */
 #define HB_MAX_BATCH_JOBS 4096
 #define HB_BATCH_GRAPH 1u     /* capture the batch's launches in a HIP graph, replayed by hb_batch_run */
-#define HB_BATCH_AUTOTUNE 2u  /* time work-grab sizes and grid occupancies on the batch's first items; keep the fastest */
+#define HB_BATCH_AUTOTUNE 2u  /* time the launch forms (one workgroup per tile, or a persistent grid at each
+                                 work-grab size and occupancy) on the batch's first items; keep the fastest */
 
 typedef struct {
     uint32_t rel_id;
@@ -348,10 +349,10 @@ hb_status hb_batch_result(hb_ctx* ctx, uint32_t batch_id, uint32_t job, uint64_t
 typedef struct {
     uint32_t n_jobs, n_partitions;
     uint64_t work_items;        /* 64 x 64 tiles in the queue */
-    uint32_t grid, grab, occupancy, lds_bytes;
+    uint32_t grid, grab, occupancy, lds_bytes;   /* grab 0: one workgroup per tile (grid unused) */
     int32_t graph;              /* 1 if captured */
     uint32_t n_tuned;           /* candidates timed by HB_BATCH_AUTOTUNE */
-    double tune_ms[16];         /* their times on the sample, in (occupancy, grab) order */
+    double tune_ms[32];         /* their times on the sample, in (occupancy, grab) order */
     uint64_t fallback_blocks;   /* learned plan: blocks kept on the heuristic plan for structural reasons */
 } hb_batch_info;
 hb_status hb_batch_info_get(hb_ctx* ctx, uint32_t batch_id, hb_batch_info* info);

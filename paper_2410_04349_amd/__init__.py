@@ -66,7 +66,7 @@ class HbBatchInfo(ctypes.Structure):
     _fields_ = [("n_jobs", ctypes.c_uint32), ("n_partitions", ctypes.c_uint32), ("work_items", ctypes.c_uint64),
                 ("grid", ctypes.c_uint32), ("grab", ctypes.c_uint32), ("occupancy", ctypes.c_uint32),
                 ("lds_bytes", ctypes.c_uint32), ("graph", ctypes.c_int32), ("n_tuned", ctypes.c_uint32),
-                ("tune_ms", ctypes.c_double * 16), ("fallback_blocks", ctypes.c_uint64)]
+                ("tune_ms", ctypes.c_double * 32), ("fallback_blocks", ctypes.c_uint64)]
 
 
 class HbColumn(ctypes.Structure):

@@ -42,7 +42,7 @@ struct Batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t learned_blocks = 0, fallback_blocks = 0;
-    double tune_ms[16] = {0};
+    double tune_ms[32] = {0};
     uint32_t n_tuned = 0;
 
     ~Batch() {
@@ -86,17 +86,24 @@ static void upload_params(Ctx* c, Batch& B) {
     HB_HIP(hipMemcpyAsync(B.mps.get(), h.data(), sizeof(MatchParams) * h.size(), hipMemcpyHostToDevice, c->stream));
 }
 
+// grab = 0: one workgroup per item (hardware dispatch); grab > 0: the
+// persistent grid taking `grab` items per atomic.
 static void enqueue(Batch& B, uint64_t total, uint32_t grab, uint32_t grid, hipStream_t s) {
-    HB_HIP(launch_fill_u64(B.cursor.as<unsigned long long>(), 1, 0ull, s));
     HB_HIP(launch_fill_u64(B.counters.as<unsigned long long>(), B.jobs.size(), 0ull, s));
+    if (grab == 0) {
+        HB_HIP(launch_match_multi(B.mps.as<MatchParams>(), B.prefix.as<uint64_t>(), B.n_parts, total, B.lds_bytes, s));
+        return;
+    }
+    HB_HIP(launch_fill_u64(B.cursor.as<unsigned long long>(), 1, 0ull, s));
     HB_HIP(launch_match_persistent(B.mps.as<MatchParams>(), B.prefix.as<uint64_t>(), B.n_parts, total,
                                    B.cursor.as<unsigned long long>(), grab, grid, B.lds_bytes, s));
 }
 
-// Times each (grab, occupancy) candidate on the first items of the queue
-// (the heaviest partitions) and keeps the fastest.
+// Times each launch form on the first items of the queue (the heaviest
+// partitions) and keeps the fastest: one workgroup per item, or the
+// persistent grid at each (grab, occupancy).
 static void autotune(Ctx* c, Batch& B, int max_occ, int n_cu) {
-    static const uint32_t grabs[] = {1, 2, 4, 8};
+    static const uint32_t grabs[] = {0, 1, 2, 4, 8};
     std::vector<uint32_t> occs;
     for (int o = 1; o <= max_occ; o *= 2) occs.push_back((uint32_t)o);
     if (occs.back() != (uint32_t)max_occ) occs.push_back((uint32_t)max_occ);
@@ -108,6 +115,7 @@ static void autotune(Ctx* c, Batch& B, int max_occ, int n_cu) {
     B.n_tuned = 0;
     for (uint32_t occ : occs)
         for (uint32_t g : grabs) {
+            if (g == 0 && occ != occs.front()) continue;   // no grid to size
             const uint32_t grid = (uint32_t)n_cu * occ;
             enqueue(B, sample, g, grid, c->stream);   // warm
             HB_HIP(hipEventRecord(a, c->stream));
@@ -116,7 +124,7 @@ static void autotune(Ctx* c, Batch& B, int max_occ, int n_cu) {
             HB_HIP(hipEventSynchronize(b));
             float ms = 0.f;
             HB_HIP(hipEventElapsedTime(&ms, a, b));
-            if (B.n_tuned < 16) B.tune_ms[B.n_tuned++] = ms;
+            if (B.n_tuned < 32) B.tune_ms[B.n_tuned++] = ms;
             if (ms < best) {
                 best = ms;
                 B.grab = g;
@@ -210,7 +218,7 @@ static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, 
     occ = std::max(occ, 1);
     B->occupancy = (uint32_t)occ;
     B->grid = (uint32_t)(n_cu * occ);
-    B->grab = 1;
+    B->grab = B->total < 0x7FFFFFFFull ? 0 : 1;   // one workgroup per item unless the queue is too long
     if ((flags & HB_BATCH_AUTOTUNE) && B->total > 0) autotune(c, *B, occ, n_cu);
     HB_HIP(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
     HB_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
@@ -307,7 +315,7 @@ static void batch_info(Ctx* c, uint32_t id, hb_batch_info* info) {
     info->lds_bytes = B.lds_bytes;
     info->graph = B.exec != nullptr;
     info->n_tuned = B.n_tuned;
-    for (uint32_t x = 0; x < B.n_tuned && x < 16; ++x) info->tune_ms[x] = B.tune_ms[x];
+    for (uint32_t x = 0; x < B.n_tuned && x < 32; ++x) info->tune_ms[x] = B.tune_ms[x];
     info->fallback_blocks = B.fallback_blocks;
 }
 

@@ -20,6 +20,8 @@ constexpr int kMaxGramRes = 8;   // (attribute, q) gram lists staged per tile
 constexpr int kMaxPrevKeys = 3;
 constexpr int kMaxEdWords = 4;   // 256-byte edit-distance patterns
 constexpr int kMaxPlan = 1536;   // steps of one key's plan
+constexpr int kFilterCache = 8;  // first-stage results kept per wave batch
+constexpr int kGroup = 2;        // thresholds decided by one bound computation
 constexpr int kCountPairs = 8 * 4;             // instrumented counters: 8 op kinds x 4, then pairs
 constexpr int kCountSlots = kCountPairs + 1;
 
@@ -65,9 +67,10 @@ enum Op : uint8_t {
     OP_CP = 8        // rule end: the pair has a witness
 };
 
-// One step of the sequential execution path.  `slot` identifies the step
-// (distinct predicates 0..63, their filters 64..127); `res` indexes the int / string / gram resource it reads; `cp`
-// is the index of the checkpoint that closes the rule.
+// One step of the sequential execution path.  `slot` is the step's
+// filter-cache entry (first-stage steps; >= kFilterCache: not cached);
+// `res` indexes the int / string / gram resource it reads; `cp` is the index
+// of the checkpoint that closes the rule.
 // `param` is d (|a - b| <= d), k (edit distance) or (num << 32) | den
 // (Jaccard threshold num / den).
 struct Instr {
@@ -132,6 +135,12 @@ struct MatchParams {
     // plan + blk_slot[b] * plan_len; blk_slot == nullptr: one plan for every
     // block
     const uint32_t* blk_slot;
+    // filter cache (per wave batch): an instruction's `slot` < kFilterCache
+    // names its entry; fc_group[e] = the entries decided together with e
+    // (the same edit-distance or Jaccard bound, other thresholds), fc_param[e]
+    // = entry e's threshold
+    uint8_t fc_group[kFilterCache];
+    uint64_t fc_param[kFilterCache];
 };
 
 // Gather of the block-major feature columns.
@@ -288,6 +297,9 @@ hipError_t launch_match_persistent(const MatchParams* mps, const uint64_t* prefi
                                    unsigned long long* cursor, uint32_t grab, uint32_t grid, uint32_t lds_bytes,
                                    hipStream_t s);
 hipError_t match_persistent_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
+// One workgroup per work item over the same queue (total < 2^31).
+hipError_t launch_match_multi(const MatchParams* mps, const uint64_t* prefix, uint32_t n_parts, uint64_t total,
+                              uint32_t lds_bytes, hipStream_t s);
 // p[0 .. n) = v (a kernel, so it may be captured in a graph)
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 // bytes [p, p + n) = 0 (a kernel)
