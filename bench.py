@@ -169,7 +169,7 @@ def run_batched(args):
                 times.append(time.perf_counter() - t0)
         hb.hb_profile_enable(ctx, False)
         kern = {}
-        for name in ("match", "batch_match", "output_sort"):
+        for name in ("match", "batch_match", "output_sort", "batch_plans", "batch_capture"):
             ms, launches = hb.hb_profile_query(ctx, name)
             kern[name] = ms / args.steps
         results[mode] = {"s_per_step": sum(times) / len(times), "pairs": cand, "matched": int(total),

@@ -326,7 +326,7 @@ hb_status hb_last_match_stats(hb_ctx* ctx, hb_match_stats* out);
  * (HB_ERR_STALE_ID on hb_batch_run otherwise).  Results equal hb_match's. */
 #define HB_MAX_BATCH_JOBS 4096
 #define HB_BATCH_GRAPH 1u     /* capture the batch's launches in a HIP graph, replayed by hb_batch_run */
-#define HB_BATCH_AUTOTUNE 2u  /* time the launch forms (one workgroup per tile, or a persistent grid at each
+#define HB_BATCH_AUTOTUNE 2u  /* time the launch forms (hb_batch_info.form; the persistent grid at each
                                  work-grab size and occupancy) on the batch's first items; keep the fastest */
 
 typedef struct {
@@ -349,7 +349,10 @@ hb_status hb_batch_result(hb_ctx* ctx, uint32_t batch_id, uint32_t job, uint64_t
 typedef struct {
     uint32_t n_jobs, n_partitions;
     uint64_t work_items;        /* 64 x 64 tiles in the queue */
-    uint32_t grid, grab, occupancy, lds_bytes;   /* grab 0: one workgroup per tile (grid unused) */
+    int32_t form;               /* 0: each partition's own launch on 4 concurrent streams;
+                                   1: one workgroup per tile over the whole queue;
+                                   2: persistent grid (grid workgroups taking grab tiles per atomic) */
+    uint32_t grid, grab, occupancy, lds_bytes;
     int32_t graph;              /* 1 if captured */
     uint32_t n_tuned;           /* candidates timed by HB_BATCH_AUTOTUNE */
     double tune_ms[32];         /* their times on the sample, in (occupancy, grab) order */

@@ -64,6 +64,7 @@ class HbJob(ctypes.Structure):
 
 class HbBatchInfo(ctypes.Structure):
     _fields_ = [("n_jobs", ctypes.c_uint32), ("n_partitions", ctypes.c_uint32), ("work_items", ctypes.c_uint64),
+                ("form", ctypes.c_int32),
                 ("grid", ctypes.c_uint32), ("grab", ctypes.c_uint32), ("occupancy", ctypes.c_uint32),
                 ("lds_bytes", ctypes.c_uint32), ("graph", ctypes.c_int32), ("n_tuned", ctypes.c_uint32),
                 ("tune_ms", ctypes.c_double * 32), ("fallback_blocks", ctypes.c_uint64)]
@@ -520,7 +521,8 @@ def hb_batch_result(ctx: Context, batch_id: int, job: int, out=None):
 def hb_batch_info(ctx: Context, batch_id: int) -> dict:
     i = HbBatchInfo()
     ctx.check(_lib.hb_batch_info_get(ctx.h, batch_id, ctypes.byref(i)))
-    return {"n_jobs": i.n_jobs, "n_partitions": i.n_partitions, "work_items": i.work_items, "grid": i.grid,
+    return {"n_jobs": i.n_jobs, "n_partitions": i.n_partitions, "work_items": i.work_items,
+            "form": ["streams", "multi", "persistent"][i.form], "grid": i.grid,
             "grab": i.grab, "occupancy": i.occupancy, "lds_bytes": i.lds_bytes, "graph": bool(i.graph),
             "tune_ms": list(i.tune_ms[: i.n_tuned]), "fallback_blocks": i.fallback_blocks}
 

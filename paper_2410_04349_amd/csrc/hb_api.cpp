@@ -809,79 +809,11 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     return true;
 }
 
-// Filter-cache entries of a partition's plan: a first-stage step is cached
-// when the same step occurs again (another rule), or when another
-// edit-distance or Jaccard filter reads the same attribute (one bound,
-// several thresholds).  Entries are numbered in plan order, up to
-// kFilterCache; every order of the same rules gets the same entries.
-static void assign_filter_cache(std::vector<Instr>& code, MatchParams& m) {
-    struct Entry {
-        uint8_t op, res;
-        uint64_t param;
-        int count;
-        int index;
-    };
-    std::vector<Entry> es;
-    auto first_stage = [](uint8_t op) {
-        return op == OP_EQ_INT || op == OP_ABSDIFF || op == OP_EQF || op == OP_EDF || op == OP_JACF;
-    };
-    auto find = [&](const Instr& in) -> int {
-        for (size_t e = 0; e < es.size(); ++e)
-            if (es[e].op == in.op && es[e].res == in.res && es[e].param == in.param) return (int)e;
-        return -1;
-    };
-    for (const Instr& in : code) {
-        if (!first_stage(in.op)) continue;
-        const int e = find(in);
-        if (e >= 0) ++es[e].count;
-        else es.push_back(Entry{in.op, in.res, in.param, 1, -1});
-    }
-    int next = 0;
-    for (Entry& e : es) {
-        bool share = e.count >= 2;
-        if (e.op == OP_EDF || e.op == OP_JACF)
-            for (const Entry& f : es)
-                if (&f != &e && f.op == e.op && f.res == e.res) share = true;
-        if (share && next < kFilterCache) e.index = next++;
-    }
-    for (int x = 0; x < kFilterCache; ++x) {
-        m.fc_group[x] = 0;
-        m.fc_param[x] = 0;
-    }
-    // groups: entries of one (op, attribute) bound, at most kGroup each, in
-    // index order (a group's members share one mask)
-    for (const Entry& e : es) {
-        if (e.index < 0) continue;
-        m.fc_param[e.index] = e.param;
-        m.fc_group[e.index] = (uint8_t)(1u << e.index);
-    }
-    for (size_t a = 0; a < es.size(); ++a) {
-        const Entry& e = es[a];
-        if (e.index < 0 || !(e.op == OP_EDF || e.op == OP_JACF) || m.fc_group[e.index] != (uint8_t)(1u << e.index))
-            continue;
-        uint8_t g = 0;
-        int members = 0;
-        for (const Entry& f : es)
-            if (f.index >= 0 && f.op == e.op && f.res == e.res && members < kGroup &&
-                m.fc_group[f.index] == (uint8_t)(1u << f.index)) {
-                g |= (uint8_t)(1u << f.index);
-                ++members;
-            }
-        for (const Entry& f : es)
-            if (f.index >= 0 && ((g >> f.index) & 1)) m.fc_group[f.index] = g;
-    }
-    for (Instr& in : code) {
-        const int e = first_stage(in.op) ? find(in) : -1;
-        in.slot = (uint8_t)(e >= 0 && es[e].index >= 0 ? es[e].index : 0xFF);
-    }
-}
-
 static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector<PathRule>& path, size_t ka,
                            KeyPlan& kp, bool count) {
     KeyRes R;
     if (!prepare_key(c, rel, rs, ka, kp, R, count)) return false;
     kp.code = emit_code(rel, rs, path, ka, R);
-    assign_filter_cache(kp.code, kp.mp);
     kp.mp.plan_len = (uint32_t)kp.code.size();
     return true;
 }
@@ -921,7 +853,6 @@ static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyP
     const uint32_t nb = kp.mp.n_blocks;
     const uint32_t ns = (uint32_t)R.specs.size();
     kp.code = emit_code(rel, rs, heuristic, ka, R);
-    assign_filter_cache(kp.code, kp.mp);
     kp.mp.plan_len = (uint32_t)kp.code.size();
     // the partition's rules in heuristic order, each with its steps
     std::vector<int> spec_of(rs.distinct.size(), -1);

@@ -1,7 +1,10 @@
-// Batched matching: many (relation, rule set) jobs in one persistent,
-// work-stealing launch over all their key partitions, optionally captured
-// in a HIP graph and replayed, with the work-grab size and grid occupancy
-// picked by timing the candidates on a sample of the batch's own items.
+// Batched matching: many (relation, rule set) jobs matched together over
+// one queue of all their key partitions' tiles, heaviest partitions first.
+// Launch forms: every partition's own launch spread over concurrent
+// streams, one workgroup per tile over the whole queue, or a persistent
+// work-stealing grid; the form (and the grid's grab size and occupancy) can
+// be picked by timing them on the batch's first items, and the batch's
+// device work can be captured in a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,7 +40,10 @@ struct Batch {
     std::vector<uint64_t> h_prefix;
     uint64_t total = 0;
     uint32_t n_parts = 0, lds_bytes = 0, grid = 0, grab = 1, occupancy = 1;
+    int form = 0;                     // kFormStreams / kFormMulti / kFormPersistent
     hipStream_t side = nullptr;       // graph launches (capture needs a non-default stream)
+    hipStream_t lanes[4] = {nullptr, nullptr, nullptr, nullptr};   // concurrent partition launches
+    hipEvent_t ev_lane[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -46,6 +52,10 @@ struct Batch {
     uint32_t n_tuned = 0;
 
     ~Batch() {
+        for (int x = 0; x < 4; ++x) {
+            if (ev_lane[x]) (void)hipEventDestroy(ev_lane[x]);
+            if (lanes[x]) (void)hipStreamDestroy(lanes[x]);
+        }
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (ev_in) (void)hipEventDestroy(ev_in);
@@ -53,6 +63,8 @@ struct Batch {
         if (side) (void)hipStreamDestroy(side);
     }
 };
+
+constexpr int kFormStreams = 0, kFormMulti = 1, kFormPersistent = 2;
 
 static Batch& get_batch(Ctx* c, uint32_t id) {
     auto it = c->batches.find(id);
@@ -86,54 +98,101 @@ static void upload_params(Ctx* c, Batch& B) {
     HB_HIP(hipMemcpyAsync(B.mps.get(), h.data(), sizeof(MatchParams) * h.size(), hipMemcpyHostToDevice, c->stream));
 }
 
-// grab = 0: one workgroup per item (hardware dispatch); grab > 0: the
-// persistent grid taking `grab` items per atomic.
-static void enqueue(Batch& B, uint64_t total, uint32_t grab, uint32_t grid, hipStream_t s) {
+// The batch's device work on stream s, in launch form `form`.  Streams:
+// partition p (queue order) runs its own k_match launch on lane p mod 4,
+// after s's counter reset and before s continues.  Multi: one workgroup per
+// queue item.  Persistent: `grid` workgroups taking `grab` items per atomic.
+// `total` < B.total limits the queue to its first items (timing samples;
+// the streams form then runs the partitions those items span).
+static void enqueue(Batch& B, uint64_t total, int form, uint32_t grab, uint32_t grid, hipStream_t s) {
     HB_HIP(launch_fill_u64(B.counters.as<unsigned long long>(), B.jobs.size(), 0ull, s));
-    if (grab == 0) {
+    if (form == kFormMulti) {
         HB_HIP(launch_match_multi(B.mps.as<MatchParams>(), B.prefix.as<uint64_t>(), B.n_parts, total, B.lds_bytes, s));
         return;
     }
-    HB_HIP(launch_fill_u64(B.cursor.as<unsigned long long>(), 1, 0ull, s));
-    HB_HIP(launch_match_persistent(B.mps.as<MatchParams>(), B.prefix.as<uint64_t>(), B.n_parts, total,
-                                   B.cursor.as<unsigned long long>(), grab, grid, B.lds_bytes, s));
+    if (form == kFormPersistent) {
+        HB_HIP(launch_fill_u64(B.cursor.as<unsigned long long>(), 1, 0ull, s));
+        HB_HIP(launch_match_persistent(B.mps.as<MatchParams>(), B.prefix.as<uint64_t>(), B.n_parts, total,
+                                       B.cursor.as<unsigned long long>(), grab, grid, B.lds_bytes, s));
+        return;
+    }
+    HB_HIP(hipEventRecord(B.ev_in, s));
+    for (int x = 0; x < 4; ++x) HB_HIP(hipStreamWaitEvent(B.lanes[x], B.ev_in, 0));
+    for (uint32_t p = 0; p < B.n_parts && B.h_prefix[p] < total; ++p) {
+        const Batch::Job& j = B.jobs[B.kp_job[p]];
+        MatchParams m = B.kps[p].mp;
+        m.out = j.out.as<uint64_t>();
+        m.cap = j.cap;
+        m.counter = B.counters.as<unsigned long long>() + B.kp_job[p];
+        m.counts = nullptr;
+        HB_HIP(launch_match(m, B.lanes[p % 4]));
+    }
+    for (int x = 0; x < 4; ++x) {
+        HB_HIP(hipEventRecord(B.ev_lane[x], B.lanes[x]));
+        HB_HIP(hipStreamWaitEvent(s, B.ev_lane[x], 0));
+    }
 }
 
 // Times each launch form on the first items of the queue (the heaviest
-// partitions) and keeps the fastest: one workgroup per item, or the
-// persistent grid at each (grab, occupancy).
+// partitions) and keeps the fastest: concurrent per-partition launches, one
+// workgroup per item, or the persistent grid at each (grab, occupancy).
 static void autotune(Ctx* c, Batch& B, int max_occ, int n_cu) {
-    static const uint32_t grabs[] = {0, 1, 2, 4, 8};
+    struct Cand {
+        int form;
+        uint32_t grab, occ;
+    };
+    std::vector<Cand> cands{{kFormStreams, 0, 0}};
+    if (B.total < 0x7FFFFFFFull) cands.push_back({kFormMulti, 0, 0});
     std::vector<uint32_t> occs;
     for (int o = 1; o <= max_occ; o *= 2) occs.push_back((uint32_t)o);
     if (occs.back() != (uint32_t)max_occ) occs.push_back((uint32_t)max_occ);
+    for (uint32_t occ : occs)
+        for (uint32_t g : {1u, 4u}) cands.push_back({kFormPersistent, g, occ});
     const uint64_t sample = std::min<uint64_t>(B.total, (uint64_t)n_cu * max_occ * 64);
     hipEvent_t a, b;
     HB_HIP(hipEventCreate(&a));
     HB_HIP(hipEventCreate(&b));
     double best = 1e300;
     B.n_tuned = 0;
-    for (uint32_t occ : occs)
-        for (uint32_t g : grabs) {
-            if (g == 0 && occ != occs.front()) continue;   // no grid to size
-            const uint32_t grid = (uint32_t)n_cu * occ;
-            enqueue(B, sample, g, grid, c->stream);   // warm
-            HB_HIP(hipEventRecord(a, c->stream));
-            enqueue(B, sample, g, grid, c->stream);
-            HB_HIP(hipEventRecord(b, c->stream));
-            HB_HIP(hipEventSynchronize(b));
-            float ms = 0.f;
-            HB_HIP(hipEventElapsedTime(&ms, a, b));
-            if (B.n_tuned < 32) B.tune_ms[B.n_tuned++] = ms;
-            if (ms < best) {
-                best = ms;
-                B.grab = g;
-                B.occupancy = occ;
-                B.grid = grid;
-            }
+    for (const Cand& cd : cands) {
+        const uint32_t grid = (uint32_t)n_cu * std::max<uint32_t>(cd.occ, 1);
+        enqueue(B, sample, cd.form, cd.grab, grid, c->stream);   // warm
+        HB_HIP(hipEventRecord(a, c->stream));
+        enqueue(B, sample, cd.form, cd.grab, grid, c->stream);
+        HB_HIP(hipEventRecord(b, c->stream));
+        HB_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        HB_HIP(hipEventElapsedTime(&ms, a, b));
+        if (B.n_tuned < 32) B.tune_ms[B.n_tuned++] = ms;
+        if (ms < best) {
+            best = ms;
+            B.form = cd.form;
+            B.grab = cd.grab;
+            B.occupancy = std::max<uint32_t>(cd.occ, 1);
+            B.grid = grid;
         }
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+}
+
+static void capture(Ctx* c, Batch& B) {
+    if (B.exec) (void)hipGraphExecDestroy(B.exec);
+    if (B.graph) (void)hipGraphDestroy(B.graph);
+    B.exec = nullptr;
+    B.graph = nullptr;
+    HB_HIP(hipStreamSynchronize(c->stream));
+    HB_HIP(hipStreamBeginCapture(B.side, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue(B, B.total, B.form, B.grab, B.grid, B.side);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(B.side, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    HB_HIP(hipStreamEndCapture(B.side, &B.graph));
+    HB_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
 }
 
 static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, uint32_t flags, uint32_t* id) {
@@ -160,13 +219,15 @@ static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, 
         job.cap = std::max<uint64_t>(1u << 16, rel.n_rows);
         job.out.alloc(c, sizeof(uint64_t) * job.cap);
         const std::vector<PathRule> path = plan_path(rs, plan);
-        for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
-            if (rel.parts.at(rs.keys[ka]).n_tiles == 0) continue;
-            KeyPlan kp;
-            if (!key_plan(c, rel, rs, plan, path, ka, kp, false, &B->fallback_blocks)) continue;
-            kps.push_back(std::move(kp));
-            kp_job.push_back(j);
-        }
+        c->host_timed("batch_plans", [&] {
+            for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
+                if (rel.parts.at(rs.keys[ka]).n_tiles == 0) continue;
+                KeyPlan kp;
+                if (!key_plan(c, rel, rs, plan, path, ka, kp, false, &B->fallback_blocks)) continue;
+                kps.push_back(std::move(kp));
+                kp_job.push_back(j);
+            }
+        });
         B->jobs.push_back(std::move(job));
     }
     // queue order: heaviest partitions first (tiles x plan length)
@@ -218,25 +279,17 @@ static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, 
     occ = std::max(occ, 1);
     B->occupancy = (uint32_t)occ;
     B->grid = (uint32_t)(n_cu * occ);
-    B->grab = B->total < 0x7FFFFFFFull ? 0 : 1;   // one workgroup per item unless the queue is too long
-    if ((flags & HB_BATCH_AUTOTUNE) && B->total > 0) autotune(c, *B, occ, n_cu);
+    B->form = kFormStreams;
+    B->grab = 0;
     HB_HIP(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
     HB_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
     HB_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
-    if (flags & HB_BATCH_GRAPH) {
-        HB_HIP(hipStreamSynchronize(c->stream));
-        HB_HIP(hipStreamBeginCapture(B->side, hipStreamCaptureModeThreadLocal));
-        try {
-            enqueue(*B, B->total, B->grab, B->grid, B->side);
-        } catch (...) {
-            hipGraph_t g = nullptr;
-            (void)hipStreamEndCapture(B->side, &g);
-            if (g) (void)hipGraphDestroy(g);
-            throw;
-        }
-        HB_HIP(hipStreamEndCapture(B->side, &B->graph));
-        HB_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    for (int x = 0; x < 4; ++x) {
+        HB_HIP(hipStreamCreateWithFlags(&B->lanes[x], hipStreamNonBlocking));
+        HB_HIP(hipEventCreateWithFlags(&B->ev_lane[x], hipEventDisableTiming));
     }
+    if ((flags & HB_BATCH_AUTOTUNE) && B->total > 0) autotune(c, *B, occ, n_cu);
+    if (flags & HB_BATCH_GRAPH) c->host_timed("batch_capture", [&] { capture(c, *B); });
     c->sync();
     const uint32_t bid = c->next_id++;
     c->batches[bid] = B;
@@ -248,19 +301,19 @@ static void batch_run(Ctx* c, uint32_t id, uint64_t* n_total) {
     check_alive(c, B);
     std::vector<unsigned long long> cnt(B.jobs.size());
     for (int attempt = 0; attempt < 2; ++attempt) {
-        if (B.exec) {
-            // the side stream runs the graph between the context stream's work
-            HB_HIP(hipEventRecord(B.ev_in, c->stream));
-            HB_HIP(hipStreamWaitEvent(B.side, B.ev_in, 0));
-            c->timed("batch_match", [&] { return hipGraphLaunch(B.exec, B.side); });
-            HB_HIP(hipEventRecord(B.ev_out, B.side));
-            HB_HIP(hipStreamWaitEvent(c->stream, B.ev_out, 0));
-        } else {
-            c->timed("batch_match", [&] {
-                enqueue(B, B.total, B.grab, B.grid, c->stream);
-                return hipSuccess;
-            });
-        }
+        c->timed("batch_match", [&] {
+            if (B.exec) {
+                // the side stream runs the graph between the context stream's work
+                HB_HIP(hipEventRecord(B.ev_out, c->stream));
+                HB_HIP(hipStreamWaitEvent(B.side, B.ev_out, 0));
+                HB_HIP(hipGraphLaunch(B.exec, B.side));
+                HB_HIP(hipEventRecord(B.ev_out, B.side));
+                HB_HIP(hipStreamWaitEvent(c->stream, B.ev_out, 0));
+            } else {
+                enqueue(B, B.total, B.form, B.grab, B.grid, c->stream);
+            }
+            return hipSuccess;
+        });
         HB_HIP(hipMemcpyAsync(cnt.data(), B.counters.get(), sizeof(unsigned long long) * cnt.size(),
                               hipMemcpyDeviceToHost, c->stream));
         c->sync();
@@ -273,7 +326,8 @@ static void batch_run(Ctx* c, uint32_t id, uint64_t* n_total) {
             }
         if (!over) break;
         if (attempt == 1) fail(HB_ERR_STATE, "internal: batch output grew between identical runs");
-        upload_params(c, B);   // the graph reads the parameters from device memory
+        upload_params(c, B);
+        if (B.exec) capture(c, B);   // per-partition launches hold the buffers in their arguments
     }
     uint64_t total = 0;
     for (size_t j = 0; j < B.jobs.size(); ++j) {
@@ -311,6 +365,7 @@ static void batch_info(Ctx* c, uint32_t id, hb_batch_info* info) {
     info->work_items = B.total;
     info->grid = B.grid;
     info->grab = B.grab;
+    info->form = B.form;
     info->occupancy = B.occupancy;
     info->lds_bytes = B.lds_bytes;
     info->graph = B.exec != nullptr;

@@ -20,8 +20,6 @@ constexpr int kMaxGramRes = 8;   // (attribute, q) gram lists staged per tile
 constexpr int kMaxPrevKeys = 3;
 constexpr int kMaxEdWords = 4;   // 256-byte edit-distance patterns
 constexpr int kMaxPlan = 1536;   // steps of one key's plan
-constexpr int kFilterCache = 8;  // first-stage results kept per wave batch
-constexpr int kGroup = 2;        // thresholds decided by one bound computation
 constexpr int kCountPairs = 8 * 4;             // instrumented counters: 8 op kinds x 4, then pairs
 constexpr int kCountSlots = kCountPairs + 1;
 
@@ -67,10 +65,10 @@ enum Op : uint8_t {
     OP_CP = 8        // rule end: the pair has a witness
 };
 
-// One step of the sequential execution path.  `slot` is the step's
-// filter-cache entry (first-stage steps; >= kFilterCache: not cached);
-// `res` indexes the int / string / gram resource it reads; `cp` is the index
-// of the checkpoint that closes the rule.
+// One step of the sequential execution path.  `slot` identifies the step
+// (distinct predicates 0..63, their filters 64..127); `res` indexes the
+// int / string / gram resource it reads; `cp` is the index of the
+// checkpoint that closes the rule.
 // `param` is d (|a - b| <= d), k (edit distance) or (num << 32) | den
 // (Jaccard threshold num / den).
 struct Instr {
@@ -135,12 +133,6 @@ struct MatchParams {
     // plan + blk_slot[b] * plan_len; blk_slot == nullptr: one plan for every
     // block
     const uint32_t* blk_slot;
-    // filter cache (per wave batch): an instruction's `slot` < kFilterCache
-    // names its entry; fc_group[e] = the entries decided together with e
-    // (the same edit-distance or Jaccard bound, other thresholds), fc_param[e]
-    // = entry e's threshold
-    uint8_t fc_group[kFilterCache];
-    uint64_t fc_param[kFilterCache];
 };
 
 // Gather of the block-major feature columns.
@@ -321,6 +313,8 @@ struct GemmArgs {
     int transA, transB;
 };
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
+// y [n x 2] = the cost model on x [n x 16] (inference only, one kernel)
+hipError_t launch_mlp_forward(const float* W, const float* x, uint64_t n, float* y, hipStream_t s);
 hipError_t launch_colsum(const float* A, int rows, int cols, float* out, hipStream_t s);
 hipError_t launch_mse_grad(const float* Y, const float* T, int n, float scale, float* dY, float* sse,
                            hipStream_t s);

@@ -196,18 +196,18 @@ void costmodel_train(Ctx* c, const float* x, const float* t, uint64_t n, int on_
 void costmodel_predict(Ctx* c, const float* x, uint64_t n, int on_device, float* y, int y_on_device) {
     if (!c->model.ready) fail(HB_ERR_STATE, "no cost model");
     if (!x || !y) fail(HB_ERR_INVALID_ARG, "NULL buffer");
-    DevBuf hx;
+    DevBuf hx, hy;
     const float* dx = rows_on_device(c, x, n * kIn, on_device, hx);
-    Acts a;
-    const int b = (int)std::min<uint64_t>(65536, std::max<uint64_t>(n, 1));
-    a.ensure(c, b);
-    for (uint64_t r0 = 0; r0 < n; r0 += b) {
-        const int nb = (int)std::min<uint64_t>(b, n - r0);
-        forward(c, c->model.params.as<float>(), dx + r0 * kIn, nb, a);
-        HB_HIP(hipMemcpyAsync(y + r0 * kOut, a.y.get(), sizeof(float) * nb * kOut,
-                              y_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    float* dy = y;
+    if (!y_on_device) {
+        hy.alloc(c, sizeof(float) * kOut * std::max<uint64_t>(n, 1));
+        dy = hy.as<float>();
     }
-    if (!y_on_device) c->sync();
+    HB_HIP(launch_mlp_forward(c->model.params.as<float>(), dx, n, dy, c->stream));
+    if (!y_on_device) {
+        HB_HIP(hipMemcpyAsync(y, dy, sizeof(float) * kOut * n, hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+    }
 }
 
 void costmodel_trace(Ctx* c, const float* x, const float* t, uint32_t n, float* out, uint64_t out_len) {

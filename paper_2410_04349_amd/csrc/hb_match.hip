@@ -199,21 +199,6 @@ __device__ inline void decode_tile(const MatchParams& P, uint64_t t, uint32_t* b
     *ti = (uint32_t)(u - c * (c + 1) / 2);
 }
 
-// Per-lane cache of eight 16-bit row masks in two 64-bit registers (the
-// index is wave-uniform).
-struct KeepCache {
-    uint64_t lo = 0, hi = 0;
-    __device__ uint32_t get(uint32_t i) const {
-        const uint64_t w = i < 4 ? lo : hi;
-        return (uint32_t)(w >> (16 * (i & 3))) & 0xFFFFu;
-    }
-    __device__ void set(uint32_t i, uint32_t v) {
-        const uint32_t sh = 16 * (i & 3);
-        const uint64_t m = ~(0xFFFFull << sh), x = ((uint64_t)v & 0xFFFFull) << sh;
-        if (i < 4) lo = (lo & m) | x; else hi = (hi & m) | x;
-    }
-};
-
 // One 64 x 64 tile t of partition P by the whole workgroup: stage the
 // j-tile's features in LDS, then each wave evaluates its 16 i-rows against
 // the 64 j-lanes.  Wave-uniform values are passed through readfirstlane so
@@ -296,14 +281,11 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
 
         uint32_t matched = 0, alive = pairs;
         uint32_t pc = 0;
-        // first-stage results of this batch, by filter-cache index
-        uint32_t fvalid = 0;
-        KeepCache fcache;
         while (pc < plen) {
             pc = __builtin_amdgcn_readfirstlane(pc);
             // one 16-byte scalar load (there is no scalar byte load)
             const uint4 raw = *(const HB_GLOBAL uint4*)(pl + pc);
-            const uint32_t op = raw.x & 0xFFu, slot = (raw.x >> 8) & 0xFFu, res = (raw.x >> 16) & 0xFFu;
+            const uint32_t op = raw.x & 0xFFu, res = (raw.x >> 16) & 0xFFu;
             const uint32_t cp = raw.y & 0xFFFFu;
             const uint64_t param = ((uint64_t)raw.w << 32) | raw.z;
             if (op == OP_CP) {
@@ -316,129 +298,77 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             if (!__any(alive != 0)) { pc = cp; continue; }
             const uint32_t before = alive;
             uint32_t work = 0;
-            bool hit = false;
             switch (op) {
             case OP_EQ_INT:
-            case OP_ABSDIFF:
-            case OP_EQF:
-            case OP_EDF:
-            case OP_JACF: {
-                // First-stage steps keep their per-batch result masks in the
-                // filter cache: a predicate repeated in several rules is
-                // computed once, and one edit-distance or Jaccard bound
-                // serves every threshold on the same attribute.
-                const uint32_t u = slot;
-                if (u < (uint32_t)kFilterCache && ((fvalid >> u) & 1)) {
-                    alive &= fcache.get(u);
-                    hit = true;
-                    break;
-                }
-                // thresholds to decide: the cache group, or the step alone
-                uint32_t todo = u < (uint32_t)kFilterCache ? (uint32_t)P.fc_group[u] : (1u << kFilterCache);
+            case OP_ABSDIFF: {
+                const int64_t vj = (int64_t)s64[res * kTile + lane];
+                const uint32_t jv = (vmask_j >> res) & 1;
                 uint32_t keep = 0;
-                if (op == OP_EQ_INT || op == OP_ABSDIFF) {
-                    const int64_t vj = (int64_t)s64[res * kTile + lane];
-                    const uint32_t jv = (vmask_j >> res) & 1;
 #pragma unroll
-                    for (int r = 0; r < kRows; ++r) {
-                        const uint64_t pr = pi0 + (uint64_t)r;   // rows >= nr: masked off, read in the pad
-                        const int64_t vi = (int64_t)f64[res * n + pr];
-                        const uint32_t iv = (f32[n + pr] >> res) & 1;
-                        const bool ok = op == OP_EQ_INT ? vi == vj : absdiff_le(vi, vj, (int64_t)param);
-                        keep |= ok ? iv << r : 0u;
-                    }
-                    keep = jv ? keep : 0u;
-                    if (u < (uint32_t)kFilterCache) {
-                        fcache.set(u, keep);
-                        fvalid |= 1u << u;
-                    }
-                } else if (op == OP_EQF) {
-                    const uint32_t lj = s32[(str32 + res) * kTile + lane];
-                    const uint64_t cj = s64[(str64 + res) * kTile + lane];
-                    const uint32_t jv = (vmask_j >> (16 + res)) & 1;
-#pragma unroll
-                    for (int r = 0; r < kRows; ++r) {
-                        const uint64_t pr = pi0 + (uint64_t)r;
-                        const uint32_t li = f32[(str32 + res) * n + pr];
-                        const uint64_t ci = f64[(str64 + res) * n + pr];
-                        const uint32_t iv = (f32[n + pr] >> (16 + res)) & 1;
-                        keep |= li == lj && ci == cj ? iv << r : 0u;
-                    }
-                    keep = jv ? keep : 0u;
-                    if (u < (uint32_t)kFilterCache) {
-                        fcache.set(u, keep);
-                        fvalid |= 1u << u;
-                    }
-                } else {
-                    // EDF / JACF: one bound per pair, tested against the
-                    // step's threshold and at most one more of its group
-                    // (entry a, then entry b)
-                    const uint32_t ia = todo ? (uint32_t)__builtin_ctz(todo) : kFilterCache;
-                    const uint32_t rest = todo & (todo - 1);
-                    const uint32_t ib = rest ? (uint32_t)__builtin_ctz(rest) : kFilterCache;
-                    const bool two = ib < (uint32_t)kFilterCache && ia < (uint32_t)kFilterCache;
-                    const uint64_t ta = ia < (uint32_t)kFilterCache ? P.fc_param[ia] : param;
-                    const uint64_t tb = two ? P.fc_param[ib] : ta;
-                    uint32_t ka = 0, kb = 0, jv;
-                    if (op == OP_EDF) {
-                        // the smallest k the filter admits:
-                        // max(|m - n|, |ci \ cj|, |cj \ ci|), with
-                        // |ci \ cj| = |ci| - |ci & cj| (|ci| on the scalar unit)
-                        const uint32_t lj = s32[(str32 + res) * kTile + lane];
-                        const uint64_t cj = s64[(str64 + res) * kTile + lane];
-                        jv = (vmask_j >> (16 + res)) & 1;
-                        const int pcj = __popcll(cj);
-#pragma unroll
-                        for (int r = 0; r < kRows; ++r) {
-                            const uint64_t pr = pi0 + (uint64_t)r;
-                            const uint32_t li = f32[(str32 + res) * n + pr];
-                            const uint64_t ci = f64[(str64 + res) * n + pr];
-                            const uint32_t iv = (f32[n + pr] >> (16 + res)) & 1;
-                            const int both = __popcll(ci & cj);
-                            const uint32_t need =
-                                (uint32_t)max(abs((int)li - (int)lj), max(__popcll(ci) - both, pcj - both));
-                            ka |= need <= (uint32_t)ta ? iv << r : 0u;
-                            kb |= need <= (uint32_t)tb ? iv << r : 0u;
-                        }
-                    } else {
-                        // I <= |A| - |gA \ gB| and I <= |B| - |gB \ gA| with
-                        // |gA \ gB| = |gA| - |gA & gB|: the bound is
-                        // |gA & gB| + min(|A| - |gA|, |B| - |gB|), tested as
-                        // bound (num + den) >= num (|A| + |B|).  Set sizes are
-                        // <= 4096 and den <= 2^18, so both products fit 32 bits
-                        // and take the full-rate 24-bit multiplier.
-                        const uint32_t sb = s32[(gram32 + res) * kTile + lane] & 0x7FFFFFFFu;
-                        const uint64_t gj = s64[(gram64 + res) * kTile + lane];
-                        jv = (vmask_j >> (24 + res)) & 1;
-                        const uint32_t restb = sb - (uint32_t)__popcll(gj);
-                        const uint32_t na = (uint32_t)(ta >> 32), nda = na + (uint32_t)(ta & 0xFFFFFFFFu);
-                        const uint32_t nb = (uint32_t)(tb >> 32), ndb = nb + (uint32_t)(tb & 0xFFFFFFFFu);
-#pragma unroll
-                        for (int r = 0; r < kRows; ++r) {
-                            const uint64_t pr = pi0 + (uint64_t)r;
-                            const uint32_t sa = f32[(gram32 + res) * n + pr] & 0x7FFFFFFFu;
-                            const uint64_t gi = f64[(gram64 + res) * n + pr];
-                            const uint32_t iv = (f32[n + pr] >> (24 + res)) & 1;
-                            const uint32_t resta = sa - (uint32_t)__popcll(gi);
-                            const uint32_t bound = (uint32_t)__popcll(gi & gj) + min(resta, restb);
-                            const uint32_t sum = sa + sb;
-                            ka |= __umul24(bound, nda) >= __umul24(na, sum) ? iv << r : 0u;
-                            if (two) kb |= __umul24(bound, ndb) >= __umul24(nb, sum) ? iv << r : 0u;
-                        }
-                    }
-                    ka = jv ? ka : 0u;
-                    kb = jv ? kb : 0u;
-                    if (ia < (uint32_t)kFilterCache) {
-                        fcache.set(ia, ka);
-                        fvalid |= 1u << ia;
-                    }
-                    if (two) {
-                        fcache.set(ib, kb);
-                        fvalid |= 1u << ib;
-                    }
-                    keep = (two && ib == u) ? kb : ka;
+                for (int r = 0; r < kRows; ++r) {
+                    const uint64_t pr = pi0 + (uint64_t)r;   // rows >= nr: masked off, read in the pad
+                    const int64_t vi = (int64_t)f64[res * n + pr];
+                    const uint32_t iv = (f32[n + pr] >> res) & 1;
+                    const bool ok = op == OP_EQ_INT ? vi == vj : absdiff_le(vi, vj, (int64_t)param);
+                    keep |= ok ? iv << r : 0u;
                 }
-                alive &= keep;
+                alive &= jv ? keep : 0u;
+                work = 1;
+                break;
+            }
+            case OP_EQF:
+            case OP_EDF: {
+                const uint32_t lj = s32[(str32 + res) * kTile + lane];
+                const uint64_t cj = s64[(str64 + res) * kTile + lane];
+                const uint32_t jv = (vmask_j >> (16 + res)) & 1;
+                const int k = (int)param;
+                const int pcj = __popcll(cj);
+                uint32_t keep = 0;
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const uint64_t pr = pi0 + (uint64_t)r;
+                    const uint32_t li = f32[(str32 + res) * n + pr];
+                    const uint64_t ci = f64[(str64 + res) * n + pr];
+                    const uint32_t iv = (f32[n + pr] >> (16 + res)) & 1;
+                    bool ok;
+                    if (op == OP_EQF) {
+                        ok = li == lj && ci == cj;
+                    } else {
+                        // |ci \ cj| = |ci| - |ci & cj|, |ci| on the scalar unit
+                        const int both = __popcll(ci & cj);
+                        const int d1 = __popcll(ci) - both, d2 = pcj - both;
+                        ok = abs((int)li - (int)lj) <= k && max(d1, d2) <= k;
+                    }
+                    keep |= ok ? iv << r : 0u;
+                }
+                alive &= jv ? keep : 0u;
+                work = 1;
+                break;
+            }
+            case OP_JACF: {
+                // I <= |A| - |gA \ gB| and I <= |B| - |gB \ gA| with
+                // |gA \ gB| = |gA| - |gA & gB|: the bound is
+                // |gA & gB| + min(|A| - |gA|, |B| - |gB|).  Set sizes are
+                // <= 4096 and den <= 2^18, so both products fit 32 bits and
+                // take the full-rate 24-bit multiplier.
+                const uint32_t sb = s32[(gram32 + res) * kTile + lane] & 0x7FFFFFFFu;
+                const uint64_t gj = s64[(gram64 + res) * kTile + lane];
+                const uint32_t jv = (vmask_j >> (24 + res)) & 1;
+                const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
+                const uint32_t restb = sb - (uint32_t)__popcll(gj);
+                uint32_t keep = 0;
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const uint64_t pr = pi0 + (uint64_t)r;
+                    const uint32_t sa = f32[(gram32 + res) * n + pr] & 0x7FFFFFFFu;
+                    const uint64_t gi = f64[(gram64 + res) * n + pr];
+                    const uint32_t iv = (f32[n + pr] >> (24 + res)) & 1;
+                    const uint32_t resta = sa - (uint32_t)__popcll(gi);
+                    const uint32_t iub = (uint32_t)__popcll(gi & gj) + min(resta, restb);
+                    const bool ok = __umul24(iub, nd) >= __umul24(num, sa + sb);
+                    keep |= ok ? iv << r : 0u;
+                }
+                alive &= jv ? keep : 0u;
                 work = 1;
                 break;
             }
@@ -504,7 +434,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 break;
             }
             }
-            if constexpr (kCount) if (!hit) {
+            if constexpr (kCount) {
                 // batches: this step ran once for the wave's 16-row batch
                 uint32_t ev = 0, ps = 0;
                 for (int r = 0; r < kRows; ++r) {
@@ -573,7 +503,7 @@ __global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const I
 // the queue is exhausted.  Item x belongs to partition p with
 // prefix[p] <= x < prefix[p + 1] (partitions ordered heaviest first).  Every
 // wave reaches every barrier: the loop condition is workgroup-uniform.
-__global__ __launch_bounds__(kThreads) void k_match_persistent(const MatchParams* __restrict__ mps,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_match_persistent(const MatchParams* __restrict__ mps,
                                                               const uint64_t* __restrict__ prefix, uint32_t n_parts,
                                                               uint64_t total, unsigned long long* cursor,
                                                               uint32_t grab) {

@@ -89,7 +89,93 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
     w[x] -= lr * (mx * c1) / (sqrtf(vx * c2) + eps);
 }
 
+// Inference of the whole network, 16 rows per wave step, with the
+// activations never leaving registers.  Each layer computes the transposed
+// product Y^T = W^T X^T: with the matrix instruction's layouts its result
+// D[o][row] sits exactly where the next layer's B operand X^T[k][row] is
+// expected, so no transpose is needed.  W^T tiles are the A operands, kept
+// in registers across the wave's row tiles.  Operands are rounded to bf16
+// as in k_gemm; bias, ReLU and accumulation stay fp32.
+constexpr int kIn = 16, kHid = 64;
+constexpr int kW1 = 0, kB1 = kW1 + kIn * kHid, kW2 = kB1 + kHid, kB2 = kW2 + kHid * kHid;
+constexpr int kW3 = kB2 + kHid, kB3 = kW3 + kHid * 2;
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ W, const float* __restrict__ x,
+                                                     uint64_t n, float* __restrict__ y) {
+    const int l = threadIdx.x & 63;
+    const int r16 = l & 15, kq = (l >> 4) * 4;
+    // A operands: W^T[o][k] = W[k][o]; lane holds A[r16][kq + e]
+    v4s a1[4], a2[4][4], a3[4];
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a1[ot][e] = to_bf16(W[kW1 + (kq + e) * kHid + ot * 16 + r16]);
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a2[ot][kt][e] = to_bf16(W[kW2 + (kt * 16 + kq + e) * kHid + ot * 16 + r16]);
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a3[kt][e] = r16 < 2 ? to_bf16(W[kW3 + (kt * 16 + kq + e) * 2 + r16]) : (short)0;
+    // biases at the D positions o = ot * 16 + kq + e
+    float b1[4][4], b2[4][4], b3[4];
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            b1[ot][e] = W[kB1 + ot * 16 + kq + e];
+            b2[ot][e] = W[kB2 + ot * 16 + kq + e];
+        }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) b3[e] = kq + e < 2 ? W[kB3 + kq + e] : 0.f;
+
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t t = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t * 16 < n; t += waves) {
+        const uint64_t row = t * 16 + r16;
+        // B operand of layer 1: X^T[k][row], lane holds k = kq + e
+        v4s xb;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xb[e] = to_bf16(row < n ? x[row * kIn + kq + e] : 0.f);
+        v4s h1[4];
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[ot], xb, acc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) h1[ot][e] = to_bf16(fmaxf(acc[e] + b1[ot][e], 0.f));
+        }
+        v4s h2[4];
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[ot][kt], h1[kt], acc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) h2[ot][e] = to_bf16(fmaxf(acc[e] + b2[ot][e], 0.f));
+        }
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3[kt], h2[kt], acc, 0, 0, 0);
+        // D[o][row]: o = kq + e, outputs 0 and 1 on lanes 0..15
+        if (kq == 0 && row < n) {
+            y[row * 2 + 0] = acc[0] + b3[0];
+            y[row * 2 + 1] = acc[1] + b3[1];
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_mlp_forward(const float* W, const float* x, uint64_t n, float* y, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t tiles = (n + 15) / 16;
+    const unsigned blocks = (unsigned)std::min<uint64_t>((tiles + 3) / 4, 4096);
+    k_mlp_forward<<<blocks, 256, 0, s>>>(W, x, n, y);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;

@@ -397,6 +397,92 @@ __global__ void k_gram_build(const ColDev* __restrict__ colp, uint32_t n, uint32
     if ((threadIdx.x & 63) == 0) atomicMax(max_cnt, out_cnt);
 }
 
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Long rows: one wave per row.  The row's window codes go to the wave's LDS
+// buffer of `cap` words (a power of two >= the longest row's window count),
+// padded with the largest code, are bitonic-sorted by the 64 lanes, and
+// the distinct values are compacted out with a ballot per 64 entries.
+__global__ __launch_bounds__(256) void k_gram_build_wave(const ColDev* __restrict__ colp, uint32_t n, uint32_t q,
+                                                         const uint64_t* __restrict__ off,
+                                                         uint32_t* __restrict__ codes, uint32_t* __restrict__ cnt,
+                                                         uint8_t* __restrict__ flags,
+                                                         unsigned int* __restrict__ max_cnt, uint32_t cap) {
+    extern __shared__ uint32_t gram_lds[];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t* buf = gram_lds + (size_t)wave * cap;
+    const ColDev c = *colp;
+    const uint32_t mask = (q == 4) ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
+    uint32_t wave_max = 0;
+    for (uint32_t r = blockIdx.x * 4 + wave; r < n; r += gridDim.x * 4) {
+        uint32_t out_cnt = 0;
+        uint8_t f = 0;
+        if (bit_valid(c.valid, r)) {
+            const uint8_t* sp = c.bytes + c.off[r];
+            const uint32_t L = str_len(c, r);
+            uint32_t* dst = codes + off[r];
+            if (L > 0 && L < q) {
+                if (lane == 0) {
+                    uint32_t v = 0;
+                    for (uint32_t x = 0; x < L; ++x) v = (v << 8) | sp[x];
+                    dst[0] = (L << 24) | v;
+                }
+                out_cnt = 1;
+                f = 1;
+            } else if (L >= q) {
+                const uint32_t nw = L - q + 1;
+                uint32_t P = 64;
+                while (P < nw) P <<= 1;
+                for (uint32_t w = lane; w < P; w += 64) {
+                    uint32_t v = 0xFFFFFFFFu;
+                    if (w < nw) {
+                        v = 0;
+                        for (uint32_t x = 0; x < q; ++x) v = (v << 8) | sp[w + x];
+                        v &= mask;
+                    }
+                    buf[w] = v;
+                }
+                wave_lds_sync();
+                for (uint32_t k = 2; k <= P; k <<= 1)
+                    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                        for (uint32_t i = lane; i < P; i += 64) {
+                            const uint32_t pj = i ^ j;
+                            if (pj > i) {
+                                const uint32_t a = buf[i], b = buf[pj];
+                                const bool up = (i & k) == 0;
+                                if (up ? a > b : a < b) {
+                                    buf[i] = b;
+                                    buf[pj] = a;
+                                }
+                            }
+                        }
+                        wave_lds_sync();
+                    }
+                for (uint32_t base = 0; base < nw; base += 64) {
+                    const uint32_t i = base + lane;
+                    const uint32_t x = i < nw ? buf[i] : 0u;
+                    const bool keep = i < nw && (i == 0 || buf[i - 1] != x);
+                    const uint64_t b = __ballot(keep);
+                    const uint32_t rank = (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
+                    if (keep) dst[out_cnt + rank] = x;
+                    out_cnt += (uint32_t)__popcll(b);
+                }
+                wave_lds_sync();   // the buffer is reused by the next row
+            }
+        }
+        if (lane == 0) {
+            cnt[r] = out_cnt;
+            flags[r] = f;
+        }
+        wave_max = max(wave_max, out_cnt);
+    }
+    if (lane == 0) atomicMax(max_cnt, wave_max);
+}
+
 // ------------------------------------------------------------ features
 
 // bit (c mod 64) for every byte c of the string: a substitution changes at
@@ -692,6 +778,20 @@ hipError_t launch_gram_slots(const ColDev* col, uint32_t n, uint32_t q, uint64_t
 hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const uint64_t* off,
                              uint32_t* codes, uint32_t* cnt, uint8_t* flags,
                              unsigned int* d_max_cnt, uint32_t max_windows, hipStream_t s) {
+    if (max_windows > 64 && max_windows <= 4096) {
+        // long rows: a wave per row, sorting in a power-of-two LDS buffer
+        uint32_t cap = 64;
+        while (cap < max_windows) cap <<= 1;
+        const size_t lds = (size_t)4 * cap * 4;
+        if (lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_gram_build_wave,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((n + 3) / 4, 65536));
+        k_gram_build_wave<<<grid, 256, lds, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt, cap);
+        return hipGetLastError();
+    }
     // LDS segment per thread: the longest row's window count, made odd
     uint32_t seg = (max_windows < 1 ? 1 : max_windows) | 1u;
     uint32_t threads = 256;

@@ -137,3 +137,27 @@ def test_training_fits_a_smooth_target(hb, ctx):
     l1 = float(np.mean((y1 - t) ** 2))
     assert l1 < 0.1 * l0, (l0, l1)
     assert abs(loss - l1) < 0.5 * l1 + 1e-3
+
+
+def test_fused_inference_matches_layerwise_forward(hb, ctx):
+    """hb_costmodel_predict runs one fused kernel (activations in
+    registers); the trace runs the layer-by-layer GEMMs checked above.
+    Both round every operand to bf16 and accumulate in fp32, so they agree
+    except where a one-ulp accumulation difference flips an activation's
+    bf16 rounding."""
+    print("[gpu-case] fused inference", flush=True)
+    r = np.random.default_rng(21)
+    x = r.normal(size=(3000, 16)).astype(np.float32)   # not a multiple of 16 rows
+    t = np.zeros((3000, 2), dtype=np.float32)
+    hb.hb_costmodel_init(ctx, 5)
+    fused = hb.hb_costmodel_predict(ctx, x).astype(np.float64)
+    tr = hb.hb_costmodel_trace(ctx, x, t)
+    lay = tr["y"].astype(np.float64)
+    d = np.abs(fused - lay)
+    scale = np.abs(lay).max() + 1e-3
+    assert np.median(d) <= 1e-6 * scale, float(np.median(d))
+    assert d.max() <= 2e-2 * scale, float(d.max())
+    # and against the fp64 oracle forward with bf16 operands, loosely
+    p = unflat(hb.hb_costmodel_get_params(ctx))
+    y64, _ = mlp.forward(p, x.astype(np.float64))
+    assert np.abs(fused - y64).max() <= 0.05 * (np.abs(y64).max() + 1e-3)
