@@ -10,9 +10,11 @@ the exact number of distinct candidate pairs (the same for every plan).
 
 The learned plan needs a trained cost model: before any timing, logs are
 collected from the small person workload and a 100k-tuple run of the plain
-recipe (a different draw from the timed 1M relation) and the MLP is trained
-on them by the library's kernels.  The heuristic plan is timed the same way
-beside it, and both outputs are checked equal.
+recipe (a different draw from the timed 1M relation) -- plus, for the 10M
+and long-title workloads, a 200k-tuple draw of their own recipe under
+another seed -- and the MLP is trained on them by the library's kernels.
+The heuristic plan is timed the same way beside it, and both outputs are
+checked equal.
 
 Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one
 GPU.
@@ -252,10 +254,12 @@ def main():
         t = time.perf_counter()
         xs, ts = [], []
         train_sets = [workloads.person_small(), workloads.plain_1m(n=100_000)]
+        # a small draw of the timed workload's recipe under another seed: logs
+        # of the plain method's runs on this kind of data
         if args.workload == "learned_10m":
-            # a small draw of the same recipe under another seed: logs of the
-            # plain method's runs on this kind of data
             train_sets.append(workloads.learned_10m(seed=workloads.SEED_BASE + 104, n=200_000))
+        elif args.workload == "long_titles_5m":
+            train_sets.append(workloads.long_titles_5m(seed=workloads.SEED_BASE + 105, n=200_000))
         for wrel, wrules in train_sets:
             rid = hb.hb_load_relation(ctx, wrel.columns, wrel.n_rows)
             rs = hb.hb_compile_rules(ctx, rid, wrules)
@@ -297,6 +301,10 @@ def main():
         t1 = time.perf_counter()
         hb.hb_profile_enable(ctx, False)
         prof = {}
+        if plan == "learned":
+            st = hb.hb_last_match_stats(ctx)
+            log(f"[bench] learned plan: {st['learned_blocks']} blocks on {st['learned_plans']} learned plans, "
+                f"{st['fallback_blocks']} on the heuristic plan")
         for name in ("match", "partition_sort", "gram_build", "lsh", "output_sort", "learned_plan",
                      "block_features", "predict", "plan_choice"):
             ms, launches = hb.hb_profile_query(ctx, name)

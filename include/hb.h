@@ -313,6 +313,7 @@ typedef struct {
     uint64_t launches;
     uint64_t learned_blocks;   /* HB_PLAN_LEARNED: blocks running a learned plan */
     uint64_t fallback_blocks;  /* HB_PLAN_LEARNED: blocks kept on the heuristic plan */
+    uint64_t learned_plans;    /* HB_PLAN_LEARNED: distinct per-block plans written */
 } hb_match_stats;
 hb_status hb_last_match_stats(hb_ctx* ctx, hb_match_stats* out);
 
@@ -327,7 +328,8 @@ hb_status hb_last_match_stats(hb_ctx* ctx, hb_match_stats* out);
 #define HB_MAX_BATCH_JOBS 4096
 #define HB_BATCH_GRAPH 1u     /* capture the batch's launches in a HIP graph, replayed by hb_batch_run */
 #define HB_BATCH_AUTOTUNE 2u  /* time the launch forms (hb_batch_info.form; the persistent grid at each
-                                 work-grab size and occupancy) on the batch's first items; keep the fastest */
+                                 work-grab size and occupancy) on the batch's first items; keep the fastest.
+                                 Batches created without it use the context's last tuned form (else form 0) */
 
 typedef struct {
     uint32_t rel_id;

@@ -88,7 +88,8 @@ class HbRule(ctypes.Structure):
 class HbMatchStats(ctypes.Structure):
     _fields_ = [("candidate_pairs", ctypes.c_uint64), ("matched_pairs", ctypes.c_uint64),
                 ("tiles", ctypes.c_uint64), ("launches", ctypes.c_uint64),
-                ("learned_blocks", ctypes.c_uint64), ("fallback_blocks", ctypes.c_uint64)]
+                ("learned_blocks", ctypes.c_uint64), ("fallback_blocks", ctypes.c_uint64),
+                ("learned_plans", ctypes.c_uint64)]
 
 
 class HbWorkStats(ctypes.Structure):
@@ -390,7 +391,8 @@ def hb_last_match_stats(ctx: Context) -> dict:
     s = HbMatchStats()
     ctx.check(_lib.hb_last_match_stats(ctx.h, ctypes.byref(s)))
     return {"candidate_pairs": s.candidate_pairs, "matched_pairs": s.matched_pairs, "tiles": s.tiles,
-            "launches": s.launches, "learned_blocks": s.learned_blocks, "fallback_blocks": s.fallback_blocks}
+            "launches": s.launches, "learned_blocks": s.learned_blocks, "fallback_blocks": s.fallback_blocks,
+            "learned_plans": s.learned_plans}
 
 
 def hb_match_work(ctx: Context, rel_id: int, ruleset_id: int, plan="heuristic") -> dict:

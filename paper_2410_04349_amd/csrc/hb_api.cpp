@@ -1036,7 +1036,7 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
     const std::vector<PathRule> path = plan_path(rs, plan);
     std::vector<KeyPlan> kps;
     size_t total_code = 0;
-    uint64_t n_learned = 0, n_fallback = 0;
+    uint64_t n_learned = 0, n_fallback = 0, n_plans = 0;
     for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
         if (rel.parts.at(rs.keys[ka]).n_tiles == 0) continue;
         KeyPlan kp;
@@ -1086,6 +1086,7 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
                 c->sync();
                 n_learned += st[0];
                 n_fallback += kp.mp.n_blocks - st[0];
+                n_plans += st[2];
             }
         if (ws || found <= cap) break;
         cap = found;
@@ -1126,6 +1127,7 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
     c->last.launches = launches;
     c->last.learned_blocks = n_learned;
     c->last.fallback_blocks = n_fallback;
+    c->last.learned_plans = n_plans;
 }
 
 static void match_work(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, hb_work_stats* ws) {

@@ -288,7 +288,19 @@ static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, 
         HB_HIP(hipStreamCreateWithFlags(&B->lanes[x], hipStreamNonBlocking));
         HB_HIP(hipEventCreateWithFlags(&B->ev_lane[x], hipEventDisableTiming));
     }
-    if ((flags & HB_BATCH_AUTOTUNE) && B->total > 0) autotune(c, *B, occ, n_cu);
+    if ((flags & HB_BATCH_AUTOTUNE) && B->total > 0) {
+        autotune(c, *B, occ, n_cu);
+        c->batch_tuned = true;
+        c->tuned_form = B->form;
+        c->tuned_grab = B->grab;
+        c->tuned_occupancy = B->occupancy;
+    } else if (c->batch_tuned) {
+        B->form = c->tuned_form;
+        B->grab = c->tuned_grab;
+        B->occupancy = std::min<uint32_t>(c->tuned_occupancy, (uint32_t)occ);
+        B->grid = (uint32_t)n_cu * B->occupancy;
+        if (B->form == kFormMulti && B->total >= 0x7FFFFFFFull) B->form = kFormStreams;
+    }
     if (flags & HB_BATCH_GRAPH) c->host_timed("batch_capture", [&] { capture(c, *B); });
     c->sync();
     const uint32_t bid = c->next_id++;

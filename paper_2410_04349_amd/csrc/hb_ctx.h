@@ -173,6 +173,11 @@ struct Ctx {
     uint32_t lds_limit = 0;
     CostModel model;
     std::map<uint32_t, std::shared_ptr<Batch>> batches;
+    // the last autotuned batch launch form, reused by batches created
+    // without autotuning
+    bool batch_tuned = false;
+    int tuned_form = 0;
+    uint32_t tuned_grab = 0, tuned_occupancy = 1;
 
     void* raw_alloc(size_t bytes) {
         if (bytes == 0) bytes = 16;
