@@ -279,12 +279,23 @@ def main():
         if args.save_model:
             np.save(args.save_model, hb.hb_costmodel_get_params(ctx))
 
+    phase = {}
+
     def step(plan, dst):
+        t0 = time.perf_counter()
         rid = hb.hb_load_relation(ctx, cols, rel.n_rows, on_device=True)
+        t1 = time.perf_counter()
         rs = hb.hb_compile_rules(ctx, rid, rules)
+        t2 = time.perf_counter()
         n_cand = hb.hb_partition(ctx, rid, rs)
+        t3 = time.perf_counter()
         n_match = hb.hb_match(ctx, rid, rs, plan, out=dst)
+        t4 = time.perf_counter()
         hb.hb_release_relation(ctx, rid)
+        t5 = time.perf_counter()
+        for k, v in (("load", t1 - t0), ("compile", t2 - t1), ("partition", t3 - t2), ("match", t4 - t3),
+                     ("release", t5 - t4)):
+            phase[k] = phase.get(k, 0.0) + v
         return n_cand, n_match
 
     def timed(plan, dst):
@@ -294,6 +305,7 @@ def main():
         hb.hb_profile_reset(ctx)
         hb.hb_profile_enable(ctx, True)
         torch.cuda.synchronize()
+        phase.clear()
         t0 = time.perf_counter()
         for k in range(args.steps):
             n_cand, n_match = step(plan, dst)
@@ -310,6 +322,8 @@ def main():
             ms, launches = hb.hb_profile_query(ctx, name)
             prof[name] = {"ms_total": ms, "launches": launches}
         ms_step = (t1 - t0) * 1000.0 / args.steps
+        log(f"[bench] {plan}: host wall per step by call (ms): "
+            + ", ".join(f"{k} {v * 1000.0 / args.steps:.2f}" for k, v in phase.items()))
         log(f"[bench] {plan}: {args.steps} steps, {ms_step:.2f} ms/step, "
             f"{n_cand * args.steps / (t1 - t0):.3e} pairs/s; kernels {prof}")
         return n_cand, n_match, t1 - t0, prof

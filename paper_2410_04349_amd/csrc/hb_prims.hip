@@ -39,13 +39,28 @@ __global__ void k_string_stats(const uint64_t* __restrict__ off, uint32_t n, uin
         local_sum += L;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && off[0] != 0) local_bad = 1;
-    // wave reduce then one atomic per wave
+    // wave, then workgroup reduction: one set of atomics per workgroup (the
+    // grid is a few hundred workgroups; atomics on one address serialise)
+    __shared__ uint32_t s_max[kBlock / 64], s_bad[kBlock / 64];
+    __shared__ unsigned long long s_sum[kBlock / 64];
     for (int o = 32; o > 0; o >>= 1) {
         local_max = max(local_max, (uint32_t)__shfl_xor((int)local_max, o));
         local_sum += __shfl_xor(local_sum, o);
         local_bad |= (uint32_t)__shfl_xor((int)local_bad, o);
     }
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        s_max[w] = local_max;
+        s_sum[w] = local_sum;
+        s_bad[w] = local_bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int x = 1; x < kBlock / 64; ++x) {
+            local_max = max(local_max, s_max[x]);
+            local_sum += s_sum[x];
+            local_bad |= s_bad[x];
+        }
         atomicMax(max_len, local_max);
         atomicAdd(total, local_sum);
         if (local_bad) atomicOr(bad, 1u);
@@ -68,7 +83,21 @@ __global__ void k_minmax(const int64_t* __restrict__ vals, const uint8_t* __rest
         lmax = max(lmax, (unsigned long long)__shfl_xor(lmax, o));
         cnt += (unsigned int)__shfl_xor((int)cnt, o);
     }
+    __shared__ unsigned long long s_min[kBlock / 64], s_max[kBlock / 64];
+    __shared__ unsigned int s_cnt[kBlock / 64];
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        s_min[w] = lmin;
+        s_max[w] = lmax;
+        s_cnt[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int x = 1; x < kBlock / 64; ++x) {
+            lmin = min(lmin, s_min[x]);
+            lmax = max(lmax, s_max[x]);
+            cnt += s_cnt[x];
+        }
         atomicMin(mn, lmin);
         atomicMax(mx, lmax);
         atomicAdd(nvalid, cnt);
@@ -629,14 +658,14 @@ inline unsigned grid_for(uint64_t n, unsigned cap = 65535u * 4) {
 
 hipError_t launch_string_stats(const uint64_t* off, uint32_t n, uint32_t* d_max_len,
                                unsigned long long* d_total, uint32_t* d_bad, hipStream_t s) {
-    k_string_stats<<<grid_for(n, 2048), kBlock, 0, s>>>(off, n, d_max_len, d_total, d_bad);
+    k_string_stats<<<grid_for(n, 512), kBlock, 0, s>>>(off, n, d_max_len, d_total, d_bad);
     return hipGetLastError();
 }
 
 hipError_t launch_minmax_u64(const int64_t* vals, const uint8_t* valid, uint32_t n,
                              unsigned long long* d_min, unsigned long long* d_max,
                              unsigned int* d_nvalid, hipStream_t s) {
-    k_minmax<<<grid_for(n, 2048), kBlock, 0, s>>>(vals, valid, n, d_min, d_max, d_nvalid);
+    k_minmax<<<grid_for(n, 512), kBlock, 0, s>>>(vals, valid, n, d_min, d_max, d_nvalid);
     return hipGetLastError();
 }
 
