@@ -759,7 +759,7 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
         gp.gsig[x] = g.sig.as<uint64_t>();
     }
     m.ed_words = ed_words;
-    const uint32_t n64 = m.n_int + m.n_str + m.n_gram, n32 = 2 + m.n_str + m.n_gram;
+    const uint32_t n64 = m.n_int + m.n_str + m.n_gram, n32 = 2 + m.n_str + 2 * m.n_gram;
     const uint64_t stride = (uint64_t)P.n_valid + kRows;
     gp.stride = stride;
     kp.f64.alloc(c, sizeof(uint64_t) * stride * std::max<uint32_t>(n64, 1));

@@ -88,7 +88,11 @@ static_assert(sizeof(Instr) == 16, "Instr layout");
 //                     then n_gram q-gram signatures
 //   f32[(x) * n + p]: x = 0: row id; 1: validity mask (bit r: int resource r,
 //                     16 + r: string resource r, 24 + r: gram resource r);
-//                     then n_str lengths; then n_gram set sizes
+//                     then n_str lengths; then n_gram set sizes (bit 31:
+//                     short-string flag); then n_gram Jaccard-filter words
+//                     ((|A| - popcount(signature)) << 16 | |A|, and 1 for a
+//                     missing value, whose signature is 0: with a threshold
+//                     above 0 that word fails the filter against anything)
 struct Features {
     const uint64_t* f64;
     const uint32_t* f32;

@@ -181,6 +181,41 @@ __device__ __forceinline__ const HB_GLOBAL T* gmem(const T* p) {
     return (const HB_GLOBAL T*)p;
 }
 
+// keep * 2 + (this lane's bit of `lanes`): one add-with-carry that takes
+// the lane mask of a comparison as its carry-in, so a 16-row batch builds
+// its per-lane row bits at one vector instruction per row.
+__device__ __forceinline__ uint32_t push_bit(uint32_t keep, uint64_t lanes) {
+    uint32_t out;
+    uint64_t carry;
+    asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(out), "=s"(carry) : "v"(keep), "s"(lanes));
+    return out;
+}
+
+// popcount(x) + acc in one instruction (the compiler otherwise sums the
+// halves of a 64-bit popcount with a separate three-way add).
+__device__ __forceinline__ uint32_t popc_add(uint32_t x, uint32_t acc) {
+    uint32_t out;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(out) : "v"(x), "v"(acc));
+    return out;
+}
+
+// Opaque copy: keeps the compiler from folding a precomputed per-lane term
+// back into the per-row arithmetic.
+template <typename T>
+__device__ __forceinline__ T opaque(T v) {
+    asm("" : "+v"(v));
+    return v;
+}
+
+// Bit r (r < 16): bit `bit` of the validity word of position p0 + r.  All
+// operands are wave-uniform, so this runs on the scalar unit.
+__device__ __forceinline__ uint32_t row_bits(const HB_GLOBAL uint32_t* __restrict__ vmask, uint64_t p0, uint32_t bit) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = kRows - 1; r >= 0; --r) m = m + m + ((vmask[p0 + r] >> bit) & 1u);
+    return m;
+}
+
 // tile index -> (block, ti, tj), tiles of a block enumerated column-major
 // over the upper triangle: column tj holds ti = 0..tj.
 __device__ inline void decode_tile(const MatchParams& P, uint64_t t, uint32_t* b, uint32_t* ti, uint32_t* tj) {
@@ -218,9 +253,10 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
 
     const uint64_t n = P.feat.n;
     const uint32_t n64 = P.n_int + P.n_str + P.n_gram;
-    const uint32_t n32 = 2 + P.n_str + P.n_gram;
+    const uint32_t n32 = 2 + P.n_str + 2 * P.n_gram;
     const uint32_t str64 = P.n_int, gram64 = P.n_int + P.n_str;    // first f64 column of each kind
     const uint32_t str32 = 2, gram32 = 2 + P.n_str;                 // first f32 column of each kind
+    const uint32_t jf32 = gram32 + P.n_gram;
 
     // ---------------------------------------------------- stage the j-tile
     uint64_t* s64 = (uint64_t*)(lds + P.lds_f64);
@@ -303,72 +339,94 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             case OP_ABSDIFF: {
                 const int64_t vj = (int64_t)s64[res * kTile + lane];
                 const uint32_t jv = (vmask_j >> res) & 1;
+                // |vi - vj| <= d  <=>  vj - d <= vi <= vj + d, the ends
+                // saturated to the int64 range (d >= 0; equality: d = 0)
+                const int64_t d = op == OP_EQ_INT ? 0 : (int64_t)param;
+                const int64_t lo = opaque(vj < INT64_MIN + d ? INT64_MIN : vj - d);
+                const int64_t hi = opaque(vj > INT64_MAX - d ? INT64_MAX : vj + d);
                 uint32_t keep = 0;
 #pragma unroll
-                for (int r = 0; r < kRows; ++r) {
+                for (int r = kRows - 1; r >= 0; --r) {   // bit r of keep: row r
                     const uint64_t pr = pi0 + (uint64_t)r;   // rows >= nr: masked off, read in the pad
                     const int64_t vi = (int64_t)f64[res * n + pr];
-                    const uint32_t iv = (f32[n + pr] >> res) & 1;
-                    const bool ok = op == OP_EQ_INT ? vi == vj : absdiff_le(vi, vj, (int64_t)param);
-                    keep |= ok ? iv << r : 0u;
+                    keep = push_bit(keep, __ballot(vi >= lo) & __ballot(vi <= hi));
                 }
-                alive &= jv ? keep : 0u;
+                alive &= jv ? keep & row_bits(f32 + n, pi0, res) : 0u;
                 work = 1;
                 break;
             }
-            case OP_EQF:
-            case OP_EDF: {
+            case OP_EQF: {
                 const uint32_t lj = s32[(str32 + res) * kTile + lane];
                 const uint64_t cj = s64[(str64 + res) * kTile + lane];
                 const uint32_t jv = (vmask_j >> (16 + res)) & 1;
-                const int k = (int)param;
-                const int pcj = __popcll(cj);
                 uint32_t keep = 0;
 #pragma unroll
-                for (int r = 0; r < kRows; ++r) {
+                for (int r = kRows - 1; r >= 0; --r) {
                     const uint64_t pr = pi0 + (uint64_t)r;
                     const uint32_t li = f32[(str32 + res) * n + pr];
                     const uint64_t ci = f64[(str64 + res) * n + pr];
-                    const uint32_t iv = (f32[n + pr] >> (16 + res)) & 1;
-                    bool ok;
-                    if (op == OP_EQF) {
-                        ok = li == lj && ci == cj;
-                    } else {
-                        // |ci \ cj| = |ci| - |ci & cj|, |ci| on the scalar unit
-                        const int both = __popcll(ci & cj);
-                        const int d1 = __popcll(ci) - both, d2 = pcj - both;
-                        ok = abs((int)li - (int)lj) <= k && max(d1, d2) <= k;
-                    }
-                    keep |= ok ? iv << r : 0u;
+                    keep = push_bit(keep, __ballot(li == lj) & __ballot(ci == cj));
                 }
-                alive &= jv ? keep : 0u;
+                alive &= jv ? keep & row_bits(f32 + n, pi0, 16 + res) : 0u;
+                work = 1;
+                break;
+            }
+            case OP_EDF: {
+                // ED <= k needs |li - lj| <= k and, for the character
+                // signatures, |ci \ cj| <= k and |cj \ ci| <= k, where
+                // |ci \ cj| = |ci| - |ci & cj|: both hold iff
+                // |ci & cj| >= max(|ci| - k, |cj| - k)
+                const int lj = (int)s32[(str32 + res) * kTile + lane];
+                const uint64_t cj = s64[(str64 + res) * kTile + lane];
+                const uint32_t jv = (vmask_j >> (16 + res)) & 1;
+                const int k = (int)param;
+                const int llo = opaque(lj - k), lhi = opaque(lj + k);
+                const int tj = opaque((int)__popcll(cj) - k);
+                const uint32_t cj_lo = (uint32_t)cj, cj_hi = (uint32_t)(cj >> 32);
+                uint32_t keep = 0;
+#pragma unroll
+                for (int r = kRows - 1; r >= 0; --r) {
+                    const uint64_t pr = pi0 + (uint64_t)r;
+                    const int li = (int)f32[(str32 + res) * n + pr];
+                    const uint64_t ci = f64[(str64 + res) * n + pr];
+                    const int both = (int)(__popc((uint32_t)ci & cj_lo) + __popc((uint32_t)(ci >> 32) & cj_hi));
+                    const int t = max((int)__popcll(ci) - k, tj);
+                    keep = push_bit(keep, __ballot(both >= t) & __ballot(li >= llo) & __ballot(li <= lhi));
+                }
+                alive &= jv ? keep & row_bits(f32 + n, pi0, 16 + res) : 0u;
                 work = 1;
                 break;
             }
             case OP_JACF: {
                 // I <= |A| - |gA \ gB| and I <= |B| - |gB \ gA| with
                 // |gA \ gB| = |gA| - |gA & gB|: the bound is
-                // |gA & gB| + min(|A| - |gA|, |B| - |gB|).  Set sizes are
-                // <= 4096 and den <= 2^18, so both products fit 32 bits and
-                // take the full-rate 24-bit multiplier.
-                const uint32_t sb = s32[(gram32 + res) * kTile + lane] & 0x7FFFFFFFu;
+                // |gA & gB| + min(|A| - |gA|, |B| - |gB|), against
+                // I * (num + den) >= num * (|A| + |B|).  Set sizes are
+                // <= 4096 and den <= 2^18, so every product fits 32 bits
+                // and takes the full-rate 24-bit multiplier.  The filter
+                // words carry both sizes, and a missing value's word fails
+                // against anything once num > 0.
+                const uint32_t wb = s32[(jf32 + res) * kTile + lane];
                 const uint64_t gj = s64[(gram64 + res) * kTile + lane];
-                const uint32_t jv = (vmask_j >> (24 + res)) & 1;
                 const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
-                const uint32_t restb = sb - (uint32_t)__popcll(gj);
                 uint32_t keep = 0;
+                if (num == 0) {   // J >= 0: every pair of present values
+                    keep = (vmask_j >> (24 + res)) & 1 ? row_bits(f32 + n, pi0, 24 + res) : 0u;
+                } else {
+                    const uint32_t restb = wb >> 16, rhs_b = opaque(__umul24(num, wb & 0xFFFFu));
+                    const uint32_t gj_lo = (uint32_t)gj, gj_hi = (uint32_t)(gj >> 32);
 #pragma unroll
-                for (int r = 0; r < kRows; ++r) {
-                    const uint64_t pr = pi0 + (uint64_t)r;
-                    const uint32_t sa = f32[(gram32 + res) * n + pr] & 0x7FFFFFFFu;
-                    const uint64_t gi = f64[(gram64 + res) * n + pr];
-                    const uint32_t iv = (f32[n + pr] >> (24 + res)) & 1;
-                    const uint32_t resta = sa - (uint32_t)__popcll(gi);
-                    const uint32_t iub = (uint32_t)__popcll(gi & gj) + min(resta, restb);
-                    const bool ok = __umul24(iub, nd) >= __umul24(num, sa + sb);
-                    keep |= ok ? iv << r : 0u;
+                    for (int r = kRows - 1; r >= 0; --r) {
+                        const uint64_t pr = pi0 + (uint64_t)r;
+                        const uint32_t wa = f32[(jf32 + res) * n + pr];
+                        const uint64_t gi = f64[(gram64 + res) * n + pr];
+                        const uint32_t rest = min(wa >> 16, restb);
+                        const uint32_t iub = popc_add((uint32_t)gi & gj_lo, popc_add((uint32_t)(gi >> 32) & gj_hi, rest));
+                        const bool ok = __umul24(iub, nd) >= num * (wa & 0xFFFFu) + rhs_b;
+                        keep = push_bit(keep, __ballot(ok));
+                    }
                 }
-                alive &= jv ? keep : 0u;
+                alive &= keep;
                 work = 1;
                 break;
             }

@@ -549,7 +549,7 @@ __global__ void k_gather_features(const GatherParams P) {
     const uint64_t n = P.stride;
     if (p >= P.n) {   // pad position
         for (uint32_t x = 0; x < P.n_int + P.n_str + P.n_gram; ++x) P.f64[x * n + p] = 0ull;
-        for (uint32_t x = 0; x < 2 + P.n_str + P.n_gram; ++x) P.f32[x * n + p] = 0u;
+        for (uint32_t x = 0; x < 2 + P.n_str + 2 * P.n_gram; ++x) P.f32[x * n + p] = 0u;
         return;
     }
     const uint32_t row = P.perm[p];
@@ -570,8 +570,11 @@ __global__ void k_gather_features(const GatherParams P) {
     for (uint32_t x = 0; x < P.n_gram; ++x) {
         const GramDev& g = P.gram[x];
         const bool v = bit_valid(P.cols[g.attr].valid, row);
-        P.f64[(P.n_int + P.n_str + x) * n + p] = v ? P.gsig[x][row] : 0ull;
-        P.f32[(2 + P.n_str + x) * n + p] = v ? (g.cnt[row] | ((uint32_t)(g.flags[row] & 1) << 31)) : 0u;
+        const uint64_t sig = v ? P.gsig[x][row] : 0ull;
+        const uint32_t cnt = v ? g.cnt[row] : 0u;
+        P.f64[(P.n_int + P.n_str + x) * n + p] = sig;
+        P.f32[(2 + P.n_str + x) * n + p] = v ? (cnt | ((uint32_t)(g.flags[row] & 1) << 31)) : 0u;
+        P.f32[(2 + P.n_str + P.n_gram + x) * n + p] = v ? ((cnt - (uint32_t)__popcll(sig)) << 16) | cnt : 1u;
         vmask |= (v ? 1u : 0u) << (24 + x);
     }
     P.f32[p] = row;
