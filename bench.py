@@ -91,7 +91,7 @@ def kernel_source_hash():
 
 
 def recorded_traffic(workload, plan):
-    """HBM bytes per k_match launch from the committed PMC summary of this
+    """HBM bytes per match-kernel launch from the committed PMC summary of this
     workload and plan, or None when there is none or the kernel's sources
     changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"k_match_{workload}_hbm_traffic.md")

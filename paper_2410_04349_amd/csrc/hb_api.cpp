@@ -525,6 +525,11 @@ static Partition& key_partition(Ctx* c, Relation& rel, uint32_t attr) {
         P.n_tiles = h[0];
         P.pairs = h[1];
         P.n_big = hb2[0] + hb2[1];
+        if (P.n_tiles && P.n_tiles <= (1ull << 28)) {
+            P.tile_blk.alloc(c, sizeof(uint32_t) * P.n_tiles);
+            HB_HIP(launch_tile_blocks(P.tile_prefix.as<uint64_t>(), P.n_blocks, P.n_tiles, P.tile_blk.as<uint32_t>(),
+                                      c->stream));
+        }
     }
     auto res = rel.parts.emplace(attr, std::move(P));
     return res.first->second;
@@ -760,7 +765,7 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     }
     m.ed_words = ed_words;
     const uint32_t n64 = m.n_int + m.n_str + m.n_gram, n32 = 2 + m.n_str + 2 * m.n_gram;
-    const uint64_t stride = (uint64_t)P.n_valid + kRows;
+    const uint64_t stride = (uint64_t)P.n_valid + kTile;
     gp.stride = stride;
     kp.f64.alloc(c, sizeof(uint64_t) * stride * std::max<uint32_t>(n64, 1));
     kp.f32.alloc(c, sizeof(uint32_t) * stride * n32);
@@ -768,15 +773,9 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     gp.f32 = kp.f32.as<uint32_t>();
     HB_HIP(launch_gather_features(gp, c->stream));
 
-    // LDS: the j-tile's feature columns, then per wave the pattern-match
-    // table, the long-pattern Myers state and the current row's q-gram lists
-    uint32_t off = 0;
-    m.lds_f64 = off;
-    off += n64 * kTile * 8;
-    m.lds_f32 = off;
-    off += n32 * kTile * 4;
-    off = align_up(off, 16);
-    m.lds_wave_base = off;
+    // LDS of the one-wave workgroup: the pattern-match table, the
+    // long-pattern Myers state and the current row's q-gram lists, then the
+    // instrumented pass's counters
     uint32_t w = 0;
     m.lds_wave_peq = w;
     if (R.any_ed) w += 256 * ed_words * 8;
@@ -788,12 +787,10 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     }
     w = align_up(std::max<uint32_t>(w, 16), 16);
     m.lds_wave_stride = w;
-    off += kWaves * w;
-    m.lds_counts = off;
-    if (count) off += kCountSlots * 8;
-    m.lds_bytes = align_up(off, 16);
+    m.lds_counts = w;
+    m.lds_bytes = align_up(w + (count ? kCountSlots * 8 : 0), 16);
     if (m.lds_bytes > c->lds_limit)
-        fail(HB_ERR_LIMIT, "the rule set's per-tile working set (" + std::to_string(m.lds_bytes) +
+        fail(HB_ERR_LIMIT, "the rule set's per-wave working set (" + std::to_string(m.lds_bytes) +
                                " bytes of LDS) exceeds the device limit");
 
     m.cols = rel.d_cols.as<ColDev>();
@@ -803,9 +800,10 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     m.blk_start = P.blk_start.as<uint32_t>();
     m.blk_size = P.blk_size.as<uint32_t>();
     m.tile_prefix = P.tile_prefix.as<uint64_t>();
+    m.tile_blk = P.tile_blk.size() ? P.tile_blk.as<uint32_t>() : nullptr;
     m.n_blocks = P.n_blocks;
     m.n_tiles = P.n_tiles;
-    if (m.n_tiles >= 0x7FFFFFFFull) fail(HB_ERR_LIMIT, "more than 2^31 tiles in one key partition");
+    if (m.n_tiles >= (1ull << 30)) fail(HB_ERR_LIMIT, "more than 2^30 tiles in one key partition");
     return true;
 }
 

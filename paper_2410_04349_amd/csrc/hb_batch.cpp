@@ -103,7 +103,7 @@ static void upload_params(Ctx* c, Batch& B) {
 // after s's counter reset and before s continues.  Multi: one workgroup per
 // queue item.  Persistent: `grid` workgroups taking `grab` items per atomic.
 // `total` < B.total limits the queue to its first items (timing samples;
-// the streams form then runs the partitions those items span).
+// every form then runs exactly those items).
 static void enqueue(Batch& B, uint64_t total, int form, uint32_t grab, uint32_t grid, hipStream_t s) {
     HB_HIP(launch_fill_u64(B.counters.as<unsigned long long>(), B.jobs.size(), 0ull, s));
     if (form == kFormMulti) {
@@ -125,6 +125,7 @@ static void enqueue(Batch& B, uint64_t total, int form, uint32_t grab, uint32_t 
         m.cap = j.cap;
         m.counter = B.counters.as<unsigned long long>() + B.kp_job[p];
         m.counts = nullptr;
+        m.n_tiles = std::min<uint64_t>(m.n_tiles, total - B.h_prefix[p]);   // a sample ends inside p
         HB_HIP(launch_match(m, B.lanes[p % 4]));
     }
     for (int x = 0; x < 4; ++x) {
@@ -142,7 +143,7 @@ static void autotune(Ctx* c, Batch& B, int max_occ, int n_cu) {
         uint32_t grab, occ;
     };
     std::vector<Cand> cands{{kFormStreams, 0, 0}};
-    if (B.total < 0x7FFFFFFFull) cands.push_back({kFormMulti, 0, 0});
+    if (B.total < (1ull << 30)) cands.push_back({kFormMulti, 0, 0});
     std::vector<uint32_t> occs;
     for (int o = 1; o <= max_occ; o *= 2) occs.push_back((uint32_t)o);
     if (occs.back() != (uint32_t)max_occ) occs.push_back((uint32_t)max_occ);
@@ -299,7 +300,7 @@ static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, 
         B->grab = c->tuned_grab;
         B->occupancy = std::min<uint32_t>(c->tuned_occupancy, (uint32_t)occ);
         B->grid = (uint32_t)n_cu * B->occupancy;
-        if (B->form == kFormMulti && B->total >= 0x7FFFFFFFull) B->form = kFormStreams;
+        if (B->form == kFormMulti && B->total >= (1ull << 30)) B->form = kFormStreams;
     }
     if (flags & HB_BATCH_GRAPH) c->host_timed("batch_capture", [&] { capture(c, *B); });
     c->sync();

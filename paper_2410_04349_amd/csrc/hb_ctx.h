@@ -92,6 +92,7 @@ struct Partition {
     uint32_t attr = 0, n_valid = 0, n_blocks = 0;
     uint64_t n_tiles = 0, pairs = 0;
     DevBuf perm, blk_start, blk_size, tile_prefix;
+    DevBuf tile_blk;      // block of each tile (left empty for more than 2^28 tiles)
     DevBuf big;           // blocks of >= kRows tuples (the ones with per-block plans)
     uint32_t n_big = 0;
 };

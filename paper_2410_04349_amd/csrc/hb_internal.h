@@ -10,9 +10,7 @@
 namespace hb {
 
 constexpr int kTile = 64;        // tuples per tile side (one wave of j's)
-constexpr int kWaves = 4;        // waves per workgroup of the match kernel
-constexpr int kRows = 16;        // i-tile rows per wave (kWaves * kRows = kTile)
-constexpr int kThreads = kWaves * 64;
+constexpr int kRows = 16;        // i-rows per wave batch (four batches per 64-row tile)
 constexpr int kLshK = 1024;      // LSH buckets of the selectivity estimate
 constexpr int kMaxIntRes = 16;   // int attributes staged per tile
 constexpr int kMaxStrRes = 8;    // string attributes staged per tile
@@ -96,8 +94,9 @@ static_assert(sizeof(Instr) == 16, "Instr layout");
 struct Features {
     const uint64_t* f64;
     const uint32_t* f32;
-    uint64_t n;       // column stride: positions (rows with a valid key) + kRows zeroed
-                      // pad positions, so a wave's 16-row batch reads in bounds
+    uint64_t n;       // column stride: positions (rows with a valid key) + kTile zeroed
+                      // pad positions, so a 16-row batch and a 64-lane j-tile read
+                      // in bounds
 };
 
 // Everything the match kernel needs for one (relation, key partition, plan).
@@ -108,6 +107,8 @@ struct MatchParams {
     const uint32_t* blk_start;
     const uint32_t* blk_size;
     const uint64_t* tile_prefix;   // n_blocks + 1 entries
+    const uint32_t* tile_blk;      // block of each tile (n_tiles entries), or nullptr:
+                                   // binary search of tile_prefix
     uint32_t n_blocks;
     uint32_t pad0;
     uint64_t n_tiles;
@@ -121,8 +122,7 @@ struct MatchParams {
     uint32_t prev_res[kMaxPrevKeys];   // int resources of earlier keys (canonical owner)
     uint32_t ed_words;                 // 64-bit words of the per-wave pattern-match table
     // LDS layout (byte offsets into dynamic shared memory)
-    uint32_t lds_f64, lds_f32;         // j-tile feature columns
-    uint32_t lds_wave_base, lds_wave_stride;   // per-wave region
+    uint32_t lds_wave_stride;          // bytes of the wave's region (from offset 0)
     uint32_t lds_wave_peq, lds_wave_myers, lds_wave_igram[kMaxGramRes];
     uint32_t lds_bytes;
     // output
@@ -193,6 +193,9 @@ hipError_t launch_gather_key(const ColDev* cols, uint32_t attr, unsigned long lo
 hipError_t launch_compact_rows(const uint32_t* flags, const uint32_t* dest, uint32_t n,
                                uint32_t* rows, hipStream_t s);
 // flags[b] = size[b] >= min
+// tile_blk[t] = block holding tile t (the last b with tile_prefix[b] <= t)
+hipError_t launch_tile_blocks(const uint64_t* tile_prefix, uint32_t n_blocks, uint64_t n_tiles, uint32_t* tile_blk,
+                              hipStream_t s);
 hipError_t launch_size_flags(const uint32_t* size, uint32_t n, uint32_t min, uint32_t* flags, hipStream_t s);
 hipError_t launch_group_heads(const ColDev* cols, const uint32_t* attrs, uint32_t n_attrs,
                               const uint32_t* rows, uint32_t n, uint32_t* head, hipStream_t s);

@@ -220,10 +220,15 @@ __device__ __forceinline__ uint32_t row_bits(const HB_GLOBAL uint32_t* __restric
 // over the upper triangle: column tj holds ti = 0..tj.
 __device__ inline void decode_tile(const MatchParams& P, uint64_t t, uint32_t* b, uint32_t* ti, uint32_t* tj) {
     const HB_GLOBAL uint64_t* tp = gmem(P.tile_prefix);
-    uint32_t lo = 0, hi = P.n_blocks - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (tp[mid] <= t) lo = mid; else hi = mid - 1;
+    uint32_t lo = 0;
+    if (P.tile_blk) {
+        lo = gmem(P.tile_blk)[t];
+    } else {
+        uint32_t hi = P.n_blocks - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (tp[mid] <= t) lo = mid; else hi = mid - 1;
+        }
     }
     *b = lo;
     const uint64_t u = t - tp[lo];
@@ -234,16 +239,18 @@ __device__ inline void decode_tile(const MatchParams& P, uint64_t t, uint32_t* b
     *ti = (uint32_t)(u - c * (c + 1) / 2);
 }
 
-// One 64 x 64 tile t of partition P by the whole workgroup: stage the
-// j-tile's features in LDS, then each wave evaluates its 16 i-rows against
-// the 64 j-lanes.  Wave-uniform values are passed through readfirstlane so
-// the compiler keeps them (and the loads they address) scalar.
+// 16-row batch `batch` of the 64 x 64 tile t of partition P, by one wave:
+// the batch's i-rows are wave-uniform (scalar loads), each lane holds one
+// j-row and reads its features from the columns when a step needs them.
+// Wave-uniform values are passed through readfirstlane so the compiler
+// keeps them (and the loads they address) scalar.
 template <bool kCount>
 __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL Instr* __restrict__ plan,
                                            const HB_GLOBAL uint64_t* __restrict__ f64,
-                                           const HB_GLOBAL uint32_t* __restrict__ f32, uint64_t t, uint8_t* lds) {
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+                                           const HB_GLOBAL uint32_t* __restrict__ f32, uint64_t t, uint8_t* lds,
+                                           int batch) {
+    const int lane = threadIdx.x & 63;
+    const int wave = batch;
     uint32_t b, ti, tj;
     decode_tile(P, t, &b, &ti, &tj);
     const uint32_t bstart = gmem(P.blk_start)[b], bsize = gmem(P.blk_size)[b];
@@ -252,27 +259,19 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
     const bool diag = ti == tj;
 
     const uint64_t n = P.feat.n;
-    const uint32_t n64 = P.n_int + P.n_str + P.n_gram;
-    const uint32_t n32 = 2 + P.n_str + 2 * P.n_gram;
     const uint32_t str64 = P.n_int, gram64 = P.n_int + P.n_str;    // first f64 column of each kind
     const uint32_t str32 = 2, gram32 = 2 + P.n_str;                 // first f32 column of each kind
     const uint32_t jf32 = gram32 + P.n_gram;
 
-    // ---------------------------------------------------- stage the j-tile
-    uint64_t* s64 = (uint64_t*)(lds + P.lds_f64);
-    uint32_t* s32 = (uint32_t*)(lds + P.lds_f32);
+    // j features of this lane: lanes past the block read the next
+    // positions, which the column padding keeps in bounds, and their pairs
+    // are masked off
     const uint64_t pj = (uint64_t)bstart + j0;
-    for (uint32_t x = tid; x < n64 * kTile; x += kThreads) {
-        const uint32_t f = x / kTile, l = x % kTile;
-        s64[x] = l < nj ? f64[f * n + pj + l] : 0ull;
-    }
-    for (uint32_t x = tid; x < n32 * kTile; x += kThreads) {
-        const uint32_t f = x / kTile, l = x % kTile;
-        s32[x] = l < nj ? f32[f * n + pj + l] : 0u;
-    }
+    auto J64 = [&](uint32_t col) -> uint64_t { return f64[col * n + pj + lane]; };
+    auto J32 = [&](uint32_t col) -> uint32_t { return f32[col * n + pj + lane]; };
     unsigned long long* s_cnt = (unsigned long long*)(lds + P.lds_counts);
     if constexpr (kCount)
-        for (uint32_t x = tid; x < kCountSlots; x += kThreads) s_cnt[x] = 0;
+        for (uint32_t x = lane; x < kCountSlots; x += 64) s_cnt[x] = 0;
     __syncthreads();
 
     // this wave's rows: r0 .. r0 + nr - 1 of the i-tile (16 consecutive rows)
@@ -281,33 +280,32 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
     if (!kCount && nr <= 0) return;
     if (nr > 0) {
         const uint64_t pi0 = (uint64_t)bstart + i0 + r0;   // position of row 0
-        const uint32_t row_j = s32[lane];
-        const uint32_t vmask_j = s32[kTile + lane];
-        uint8_t* wbase = lds + P.lds_wave_base + wave * P.lds_wave_stride;
+        const uint32_t row_j = J32(0);
+        const uint32_t vmask_j = J32(1);
+        uint8_t* wbase = lds;
         uint8_t* peq = wbase + P.lds_wave_peq;
         const HB_GLOBAL Instr* __restrict__ pl = plan;
         uint32_t plen = P.plan_len;
         if (P.blk_slot) pl = plan + (size_t)gmem(P.blk_slot)[b] * plen;
 
-        // bit r of a lane's masks = the pair (row r, this lane's j)
+        // bit r of a lane's masks = the pair (row r, this lane's j): lanes
+        // below nj, and on a diagonal tile only j > i (lanes above r0 + r)
+        const uint64_t lanes_j = nj >= 64 ? ~0ull : (1ull << nj) - 1ull;
         uint32_t pairs = 0;
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const uint32_t ig = i0 + r0 + r, jg = j0 + lane;
-            const bool ok = r < nr && (uint32_t)lane < nj && (!diag || jg > ig);
-            pairs |= (ok ? 1u : 0u) << r;
+        for (int r = kRows - 1; r >= 0; --r) {
+            const uint32_t above = r0 + (uint32_t)r + 1u;
+            const uint64_t upper = !diag ? ~0ull : above >= 64 ? 0ull : ~0ull << above;
+            pairs = push_bit(pairs, r < nr ? lanes_j & upper : 0ull);
         }
         // canonical owner: a pair agreeing on an earlier key was evaluated there
         for (uint32_t k = 0; k < P.n_prev; ++k) {
             const uint32_t res = P.prev_res[k];
-            const uint64_t vj = s64[res * kTile + lane];
-            const bool jv = (vmask_j >> res) & 1;
+            const uint64_t vj = J64(res);
+            uint32_t same = 0;
 #pragma unroll
-            for (int r = 0; r < kRows; ++r) {
-                if (r >= nr) break;
-                const bool iv = (f32[n + pi0 + r] >> res) & 1;
-                if (jv && iv && f64[res * n + pi0 + r] == vj) pairs &= ~(1u << r);
-            }
+            for (int r = kRows - 1; r >= 0; --r) same = push_bit(same, __ballot(f64[res * n + pi0 + r] == vj));
+            pairs &= (vmask_j >> res) & 1 ? ~(same & row_bits(f32 + n, pi0, res)) : ~0u;
         }
         if constexpr (kCount) {
             uint32_t cnt = 0;
@@ -337,7 +335,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             switch (op) {
             case OP_EQ_INT:
             case OP_ABSDIFF: {
-                const int64_t vj = (int64_t)s64[res * kTile + lane];
+                const int64_t vj = (int64_t)J64(res);
                 const uint32_t jv = (vmask_j >> res) & 1;
                 // |vi - vj| <= d  <=>  vj - d <= vi <= vj + d, the ends
                 // saturated to the int64 range (d >= 0; equality: d = 0)
@@ -356,8 +354,8 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 break;
             }
             case OP_EQF: {
-                const uint32_t lj = s32[(str32 + res) * kTile + lane];
-                const uint64_t cj = s64[(str64 + res) * kTile + lane];
+                const uint32_t lj = J32(str32 + res);
+                const uint64_t cj = J64(str64 + res);
                 const uint32_t jv = (vmask_j >> (16 + res)) & 1;
                 uint32_t keep = 0;
 #pragma unroll
@@ -376,8 +374,8 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 // signatures, |ci \ cj| <= k and |cj \ ci| <= k, where
                 // |ci \ cj| = |ci| - |ci & cj|: both hold iff
                 // |ci & cj| >= max(|ci| - k, |cj| - k)
-                const int lj = (int)s32[(str32 + res) * kTile + lane];
-                const uint64_t cj = s64[(str64 + res) * kTile + lane];
+                const int lj = (int)J32(str32 + res);
+                const uint64_t cj = J64(str64 + res);
                 const uint32_t jv = (vmask_j >> (16 + res)) & 1;
                 const int k = (int)param;
                 const int llo = opaque(lj - k), lhi = opaque(lj + k);
@@ -406,8 +404,8 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 // and takes the full-rate 24-bit multiplier.  The filter
                 // words carry both sizes, and a missing value's word fails
                 // against anything once num > 0.
-                const uint32_t wb = s32[(jf32 + res) * kTile + lane];
-                const uint64_t gj = s64[(gram64 + res) * kTile + lane];
+                const uint32_t wb = J32(jf32 + res);
+                const uint64_t gj = J64(gram64 + res);
                 const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
                 uint32_t keep = 0;
                 if (num == 0) {   // J >= 0: every pair of present values
@@ -444,7 +442,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     if (op == OP_EQ_STR) {
                         const ColDev& c = P.cols[P.str_attr[res]];
                         const uint32_t li = f32[(str32 + res) * n + pi];
-                        const uint32_t lj = s32[(str32 + res) * kTile + lane];
+                        const uint32_t lj = J32(str32 + res);
                         if (need && li == lj) {
                             const uint8_t* si = c.bytes + c.off[row_i];
                             const uint8_t* sj = c.bytes + c.off[row_j];
@@ -455,7 +453,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     } else if (op == OP_ED) {
                         const ColDev& c = P.cols[P.str_attr[res]];
                         const int m = (int)f32[(str32 + res) * n + pi];
-                        const int nn = (int)s32[(str32 + res) * kTile + lane];
+                        const int nn = (int)J32(str32 + res);
                         const int k = (int)param;
                         const int words = m <= 32 ? 0 : (m + 63) / 64;
                         const bool run = need && abs(m - nn) <= k;
@@ -477,7 +475,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                             wave_sync();
                         }
                         if (need) {
-                            const uint32_t jb = s32[(gram32 + res) * kTile + lane];
+                            const uint32_t jb = J32(gram32 + res);
                             const uint32_t cb = jb & 0x7FFFFFFFu;
                             const uint32_t I = intersect(ig, ca, (ia >> 31) != 0, g.codes + g.off[row_j], cb,
                                                          (jb >> 31) != 0);
@@ -535,84 +533,86 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
     }
     if constexpr (kCount) {
         __syncthreads();
-        for (uint32_t x = tid; x < kCountSlots; x += kThreads)
+        for (uint32_t x = lane; x < kCountSlots; x += 64)
             if (s_cnt[x]) atomicAdd(&P.counts[x], s_cnt[x]);
     }
 }
 
+// Workgroup w (one wave) runs the 16-row batch w % 4 of tile w / 4, so no
+// workgroup holds resources for waves that finished early.  XCD-aware
+// remap: consecutive workgroups go round-robin to the 8 XCDs; each XCD gets
+// a contiguous range of tiles so a block's tiles share its L2.
 template <bool kCount>
-__global__ __launch_bounds__(kThreads) void k_match(const MatchParams P, const Instr* __restrict__ plan,
-                                                   const uint64_t* __restrict__ f64,
-                                                   const uint32_t* __restrict__ f32) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_match(
+    const MatchParams P, const Instr* __restrict__ plan, const uint64_t* __restrict__ f64,
+    const uint32_t* __restrict__ f32) {
     extern __shared__ __align__(16) uint8_t lds[];
-    // XCD-aware remap: consecutive workgroups go round-robin to the 8 XCDs;
-    // give each XCD a contiguous range of tiles so a block's tiles share L2.
     const uint64_t G = gridDim.x;
     const uint64_t bid = blockIdx.x;
     const uint64_t xcd = bid & 7, idx = bid >> 3;
     const uint64_t q8 = G >> 3, r8 = G & 7;
-    const uint64_t t = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+    const uint64_t w = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+    const uint64_t t = w >> 2;
     if (t >= P.n_tiles) return;
-    match_tile<kCount>(P, gmem(plan), gmem(f64), gmem(f32), t, lds);
+    match_tile<kCount>(P, gmem(plan), gmem(f64), gmem(f32), t, lds, (int)(w & 3));
 }
 
-// Persistent, work-stealing form over many partitions (of many relations):
-// a workgroup takes `grab` consecutive work items from a global cursor until
-// the queue is exhausted.  Item x belongs to partition p with
-// prefix[p] <= x < prefix[p + 1] (partitions ordered heaviest first).  Every
-// wave reaches every barrier: the loop condition is workgroup-uniform.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_match_persistent(const MatchParams* __restrict__ mps,
-                                                              const uint64_t* __restrict__ prefix, uint32_t n_parts,
-                                                              uint64_t total, unsigned long long* cursor,
-                                                              uint32_t grab) {
+// partition of queue item x: prefix[p] <= x < prefix[p + 1]
+__device__ inline uint32_t queue_partition(const uint64_t* __restrict__ prefix, uint32_t n_parts, uint64_t x) {
+    uint32_t lo = 0, hi = n_parts;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= x) lo = mid; else hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Persistent grid over a queue of tiles of many partitions: each one-wave
+// workgroup takes `grab` batch units (unit u = batch u % 4 of item u / 4)
+// per atomic until the 4 x total units are gone.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_match_persistent(
+    const MatchParams* __restrict__ mps, const uint64_t* __restrict__ prefix, uint32_t n_parts, uint64_t total,
+    unsigned long long* cursor, uint32_t grab) {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ unsigned long long s_item;
+    const uint64_t units = total * 4;
     for (;;) {
-        __syncthreads();   // the previous tile's LDS reads and s_item reads are done
-        if (threadIdx.x == 0) s_item = atomicAdd(cursor, (unsigned long long)grab);
-        __syncthreads();
-        const uint64_t first = s_item;
-        if (first >= total) break;
-        const uint64_t last = first + grab < total ? first + grab : total;
-        for (uint64_t item = first; item < last; ++item) {
-            uint32_t lo = 0, hi = n_parts;   // prefix[lo] <= item < prefix[hi]
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (prefix[mid] <= item) lo = mid; else hi = mid;
-            }
-            lo = __builtin_amdgcn_readfirstlane(lo);
-            const MatchParams& P = mps[lo];
-            if (item > first) __syncthreads();
-            match_tile<false>(P, gmem(P.plan), gmem(P.feat.f64), gmem(P.feat.f32), item - prefix[lo], lds);
+        unsigned long long got = 0;
+        if (threadIdx.x == 0) got = atomicAdd(cursor, (unsigned long long)grab);
+        got = __shfl(got, 0);
+        // wave-uniform from here on: keep the queue walk on the scalar unit
+        const uint64_t first = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(got >> 32)) << 32) |
+                               __builtin_amdgcn_readfirstlane((uint32_t)got);
+        if (first >= units) break;
+        const uint64_t last = first + grab < units ? first + grab : units;
+        for (uint64_t u = first; u < last; ++u) {
+            const uint64_t item = u >> 2;
+            const uint32_t p = queue_partition(prefix, n_parts, item);
+            const MatchParams& P = mps[p];
+            match_tile<false>(P, gmem(P.plan), gmem(P.feat.f64), gmem(P.feat.f32), item - prefix[p], lds,
+                              (int)(u & 3));
         }
     }
 }
 
-// 16-byte stores over the aligned middle, byte stores at the ends.
-// One workgroup per tile over many partitions (the hardware dispatcher
-// hands out workgroups as compute units free up): item x belongs to
-// partition p with prefix[p] <= x < prefix[p + 1].  XCD-aware remap as in
-// k_match.
-__global__ __launch_bounds__(kThreads) void k_match_multi(const MatchParams* __restrict__ mps,
-                                                         const uint64_t* __restrict__ prefix, uint32_t n_parts,
-                                                         uint64_t total) {
+// One one-wave workgroup per batch unit over the queue of many partitions
+// (the hardware dispatcher hands out workgroups as compute units free up);
+// XCD-aware remap as in k_match.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_match_multi(
+    const MatchParams* __restrict__ mps, const uint64_t* __restrict__ prefix, uint32_t n_parts, uint64_t total) {
     extern __shared__ __align__(16) uint8_t lds[];
     const uint64_t G = gridDim.x;
     const uint64_t bid = blockIdx.x;
     const uint64_t xcd = bid & 7, idx = bid >> 3;
     const uint64_t q8 = G >> 3, r8 = G & 7;
-    const uint64_t item = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+    const uint64_t u = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+    const uint64_t item = u >> 2;
     if (item >= total) return;
-    uint32_t lo = 0, hi = n_parts;   // prefix[lo] <= item < prefix[hi]
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (prefix[mid] <= item) lo = mid; else hi = mid;
-    }
-    lo = __builtin_amdgcn_readfirstlane(lo);
-    const MatchParams& P = mps[lo];
-    match_tile<false>(P, gmem(P.plan), gmem(P.feat.f64), gmem(P.feat.f32), item - prefix[lo], lds);
+    const uint32_t p = queue_partition(prefix, n_parts, item);
+    const MatchParams& P = mps[p];
+    match_tile<false>(P, gmem(P.plan), gmem(P.feat.f64), gmem(P.feat.f32), item - prefix[p], lds, (int)(u & 3));
 }
 
+// 16-byte stores over the aligned middle, byte stores at the ends.
 __global__ void k_zero_bytes(uint8_t* p, size_t n) {
     const size_t lead = (16 - ((uintptr_t)p & 15)) & 15;
     const size_t head = lead < n ? lead : n;
@@ -1078,20 +1078,28 @@ __global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
 
 }  // namespace
 
+// Raises a kernel's dynamic-LDS limit once it needs more than 64 KB.
+static hipError_t allow_lds(const void* fn, int* configured, uint32_t bytes) {
+    if (bytes <= 65536 || *configured >= (int)bytes) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) *configured = (int)bytes;
+    return e;
+}
+
 hipError_t launch_match(const MatchParams& p, hipStream_t s) {
     if (p.n_tiles == 0) return hipSuccess;
-    const void* fn = p.counts ? (const void*)k_match<true> : (const void*)k_match<false>;
+    if (p.n_tiles >= (1ull << 30)) return hipErrorInvalidValue;   // the grid holds 4 x n_tiles workgroups
     static int configured[2] = {0, 0};
-    int& cfg = configured[p.counts ? 1 : 0];
-    if (p.lds_bytes > 65536 && cfg < (int)p.lds_bytes) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
+    const unsigned grid = (unsigned)(p.n_tiles * 4);
+    if (p.counts) {
+        hipError_t e = allow_lds((const void*)k_match<true>, &configured[0], p.lds_bytes);
         if (e != hipSuccess) return e;
-        cfg = (int)p.lds_bytes;
+        k_match<true><<<grid, 64, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
+    } else {
+        hipError_t e = allow_lds((const void*)k_match<false>, &configured[1], p.lds_bytes);
+        if (e != hipSuccess) return e;
+        k_match<false><<<grid, 64, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
     }
-    if (p.counts)
-        k_match<true><<<(unsigned)p.n_tiles, kThreads, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
-    else
-        k_match<false><<<(unsigned)p.n_tiles, kThreads, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
     return hipGetLastError();
 }
 
@@ -1099,39 +1107,30 @@ hipError_t launch_match_persistent(const MatchParams* mps, const uint64_t* prefi
                                    unsigned long long* cursor, uint32_t grab, uint32_t grid, uint32_t lds_bytes,
                                    hipStream_t s) {
     if (total == 0 || grid == 0) return hipSuccess;
+    if (total >= (1ull << 60)) return hipErrorInvalidValue;
     static int configured = 0;
-    if (lds_bytes > 65536 && configured < (int)lds_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_match_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_bytes);
-        if (e != hipSuccess) return e;
-        configured = (int)lds_bytes;
-    }
-    k_match_persistent<<<grid, kThreads, lds_bytes, s>>>(mps, prefix, n_parts, total, cursor, grab);
+    hipError_t e = allow_lds((const void*)k_match_persistent, &configured, lds_bytes);
+    if (e != hipSuccess) return e;
+    k_match_persistent<<<grid, 64, lds_bytes, s>>>(mps, prefix, n_parts, total, cursor, grab);
     return hipGetLastError();
 }
 
 hipError_t launch_match_multi(const MatchParams* mps, const uint64_t* prefix, uint32_t n_parts, uint64_t total,
                               uint32_t lds_bytes, hipStream_t s) {
     if (total == 0) return hipSuccess;
-    if (total >= 0x7FFFFFFFull) return hipErrorInvalidValue;
+    if (total >= (1ull << 30)) return hipErrorInvalidValue;   // the grid holds 4 x total workgroups
     static int configured = 0;
-    if (lds_bytes > 65536 && configured < (int)lds_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_match_multi, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_bytes);
-        if (e != hipSuccess) return e;
-        configured = (int)lds_bytes;
-    }
-    k_match_multi<<<(unsigned)total, kThreads, lds_bytes, s>>>(mps, prefix, n_parts, total);
+    hipError_t e = allow_lds((const void*)k_match_multi, &configured, lds_bytes);
+    if (e != hipSuccess) return e;
+    k_match_multi<<<(unsigned)(total * 4), 64, lds_bytes, s>>>(mps, prefix, n_parts, total);
     return hipGetLastError();
 }
 
 hipError_t match_persistent_occupancy(uint32_t lds_bytes, int* blocks_per_cu) {
-    if (lds_bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_match_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_bytes);
-        if (e != hipSuccess) return e;
-    }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_match_persistent, kThreads, lds_bytes);
+    static int configured = 0;
+    hipError_t e = allow_lds((const void*)k_match_persistent, &configured, lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_match_persistent, 64, lds_bytes);
 }
 
 hipError_t launch_zero_bytes(void* p, size_t n, hipStream_t s) {

@@ -263,6 +263,20 @@ __global__ void k_multi_valid_flags(const ColDev* __restrict__ cols, const uint3
     flags[r] = f;
 }
 
+// One thread per tile: binary search of the tile prefix for its block.
+__global__ void k_tile_blocks(const uint64_t* __restrict__ tp, uint32_t n_blocks, uint64_t n_tiles,
+                              uint32_t* __restrict__ tile_blk) {
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n_tiles;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = n_blocks - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (tp[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        tile_blk[t] = lo;
+    }
+}
+
 __global__ void k_size_flags(const uint32_t* __restrict__ size, uint32_t n, uint32_t min,
                              uint32_t* __restrict__ flags) {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -741,6 +755,13 @@ hipError_t launch_multi_valid_flags(const ColDev* cols, const uint32_t* attrs, u
 hipError_t launch_compact_rows(const uint32_t* flags, const uint32_t* dest, uint32_t n,
                                uint32_t* rows, hipStream_t s) {
     k_compact_rows<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(flags, dest, n, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_blocks(const uint64_t* tile_prefix, uint32_t n_blocks, uint64_t n_tiles, uint32_t* tile_blk,
+                              hipStream_t s) {
+    if (n_tiles == 0 || n_blocks == 0) return hipSuccess;
+    k_tile_blocks<<<grid_for(n_tiles, 1u << 16), kBlock, 0, s>>>(tile_prefix, n_blocks, n_tiles, tile_blk);
     return hipGetLastError();
 }
 
