@@ -168,9 +168,9 @@ hb_status hb_partition(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id,
  *                      exact filters) by step cost / (1 - probability that
  *                      some pair of the block's wave batch of
  *                      min(n, 16) x min(n, 64) pairs passes, from the
- *                      model's predicted pass rate), and the exact checks by
- *                      predicted cycles; each order is kept only where the
- *                      model expects it 2% cheaper than the heuristic one.
+ *                      model's predicted pass rate), kept only where the
+ *                      model expects it 2% cheaper than the heuristic
+ *                      order; the exact checks stay in the heuristic order.
  *                      Blocks of fewer than 16 tuples keep the heuristic
  *                      plan.  Built on the device (no host round trip).
  *                      Needs a cost model (HB_ERR_STATE otherwise). */

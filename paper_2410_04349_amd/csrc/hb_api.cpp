@@ -356,8 +356,18 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
     rs->bucket_n.assign(np, 0);
     DevBuf hist(c, sizeof(unsigned long long) * kLshK * np);
     zero(c, hist.get(), hist.size());
+    // the LSH hash depends on (attribute, operator, q or d), not on the
+    // threshold: predicates that share those share one histogram
+    std::vector<size_t> same(np);
     for (size_t p = 0; p < np; ++p) {
         const hb_pred& pr = rs->distinct[p];
+        same[p] = p;
+        for (size_t y = 0; y < p; ++y) {
+            const hb_pred& py = rs->distinct[y];
+            if (py.attr == pr.attr && py.op == pr.op && (pr.op != HB_JACCARD_GE || py.q == pr.q) &&
+                (pr.op != HB_ABSDIFF_LE || py.d == pr.d)) { same[p] = y; break; }
+        }
+        if (same[p] != p) continue;
         if (pr.op == HB_JACCARD_GE) gram_index(c, rel, pr.attr, pr.q);
         const int op = pr.op == HB_EQ ? 0 : pr.op == HB_ED_LE ? 1 : pr.op == HB_JACCARD_GE ? 2 : 3;
         c->timed("lsh", [&] {
@@ -368,6 +378,8 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
     std::vector<uint64_t> h(kLshK * np);
     HB_HIP(hipMemcpyAsync(h.data(), hist.get(), sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost, c->stream));
     c->sync();
+    for (size_t p = 0; p < np; ++p)
+        if (same[p] != p) std::copy_n(h.begin() + same[p] * kLshK, kLshK, h.begin() + p * kLshK);
     double cmax = 0.0;
     for (size_t p = 0; p < np; ++p) {
         unsigned __int128 s2 = 0;

@@ -46,8 +46,14 @@ __device__ inline int myers(const T* __restrict__ peq, int m, const uint8_t* __r
     for (int w = 0; w < W; ++w) { Pv[w] = ~(T)0; Mv[w] = 0; }
     int score = m;
     const T hb = (T)1 << ((m - 1) % B);
+    // text bytes in batches of four independent loads
+    uint32_t ch[4];
     for (int pos = 0; pos < n; ++pos) {
-        const T* eq = peq + (uint32_t)text[pos] * W;
+        if ((pos & 3) == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ch[k] = pos + k < n ? text[pos + k] : 0u;
+        }
+        const T* eq = peq + ch[pos & 3] * W;
         T carry = 0, ph_in = 1, mh_in = 0;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
@@ -89,8 +95,13 @@ __device__ inline int myers_long(const uint64_t* __restrict__ peq, int W, int m,
     for (int w = 0; w < W; ++w) { Pv[w * 64 + lane] = ~0ull; Mv[w * 64 + lane] = 0; }
     int score = m;
     const uint64_t hb = 1ull << ((m - 1) & 63);
+    uint32_t ch[4];
     for (int pos = 0; pos < n; ++pos) {
-        const uint64_t* eq = peq + (uint32_t)text[pos] * W;
+        if ((pos & 3) == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ch[k] = pos + k < n ? text[pos + k] : 0u;
+        }
+        const uint64_t* eq = peq + ch[pos & 3] * W;
         uint64_t carry = 0, ph_in = 1, mh_in = 0;
         for (int w = 0; w < W; ++w) {
             const uint64_t Eq = eq[w];
@@ -149,15 +160,24 @@ __device__ inline void build_peq(uint8_t* peq_bytes, int words, const uint8_t* _
 
 // |A & B| for sorted distinct code lists; a short string's list is its
 // single whole-string code, comparable only with another short string's.
+// A (the wave's row) is in LDS; B streams from global memory eight codes
+// per batch of independent loads, and a pointer into A advances
+// monotonically (both lists ascend).
 __device__ inline uint32_t intersect(const uint32_t* __restrict__ A, uint32_t ca, bool ashort,
                                      const uint32_t* __restrict__ B, uint32_t cb, bool bshort) {
     if (ashort || bshort) return (ashort && bshort && A[0] == B[0]) ? 1u : 0u;
-    uint32_t ia = 0, ib = 0, I = 0;
-    while (ia < ca && ib < cb) {
-        const uint32_t x = A[ia], y = B[ib];
-        I += x == y ? 1u : 0u;
-        ia += x <= y ? 1u : 0u;
-        ib += y <= x ? 1u : 0u;
+    uint32_t ia = 0, I = 0;
+    for (uint32_t ib = 0; ib < cb && ia < ca; ib += 8) {
+        uint32_t y[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) y[k] = ib + k < cb ? B[ib + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (ib + k < cb) {
+                while (ia < ca && A[ia] < y[k]) ++ia;
+                if (ia < ca && A[ia] == y[k]) { ++I; ++ia; }
+            }
+        }
     }
     return I;
 }
@@ -907,10 +927,6 @@ struct BlockEst {
         const float v = y[2 * s];
         return isfinite(v) ? fminf(1.f, fmaxf(0.f, v)) : 1.f;
     }
-    __device__ float cycles(uint32_t s) const {
-        const float v = y[2 * s + 1];
-        return isfinite(v) ? exp2f(fminf(30.f, fmaxf(0.f, 16.f * v))) : 1e9f;
-    }
 };
 
 // Expected first-stage cost of a wave batch running a rule's steps in
@@ -924,18 +940,6 @@ __device__ inline float stage_cost(const PlanChoiceParams& C, uint32_t r, const 
         total += alive * first_cost(C.spec_kind[sx]);
         surv *= e.pass(sx);
         alive = batch_any(surv, batch);
-    }
-    return total;
-}
-
-// Expected cost of the exact checks in order `ord`, each taken to stop half
-// of the rows that reach it.
-__device__ inline float verify_cost(const PlanChoiceParams& C, uint32_t r, const uint8_t* ord, int len,
-                                    const BlockEst& e) {
-    float total = 0.f, w = 1.f;
-    for (int k = 0; k < len; ++k) {
-        total += w * e.cycles(C.rule_spec[r][ord[k]]);
-        w *= 0.5f;
     }
     return total;
 }
@@ -968,19 +972,13 @@ __device__ inline void rule_choice(const PlanChoiceParams& C, uint32_t r, const 
         }
     const bool take = stage_cost(C, r, lo, len, e, batch) < 0.98f * stage_cost(C, r, id, len, e, batch);
     for (int k = 0; k < len; ++k) fo[k] = take ? lo[k] : id[k];
-    // exact checks in first-stage order (the heuristic), or by cycles
-    uint8_t hv[kMaxRuleSteps];
+    // exact checks in the heuristic's order, whatever the first-stage
+    // order: the model predicts their cost but not how many pairs they
+    // reject, and a cost-only order can put a check that passes nearly
+    // every pair ahead of a selective one
     int m = 0;
     for (int k = 0; k < len; ++k)
-        if (verifies(C.spec_kind[C.rule_spec[r][fo[k]]])) hv[m++] = fo[k];
-    uint8_t lv[kMaxRuleSteps];
-    for (int k = 0; k < m; ++k) lv[k] = hv[k];
-    for (int a = 1; a < m; ++a)
-        for (int k = a; k > 0 && e.cycles(C.rule_spec[r][lv[k]]) < e.cycles(C.rule_spec[r][lv[k - 1]]); --k) {
-            const uint8_t t = lv[k]; lv[k] = lv[k - 1]; lv[k - 1] = t;
-        }
-    const bool vtake = verify_cost(C, r, lv, m, e) < 0.98f * verify_cost(C, r, hv, m, e);
-    for (int k = 0; k < m; ++k) vo[k] = vtake ? lv[k] : hv[k];
+        if (verifies(C.spec_kind[C.rule_spec[r][id[k]]])) vo[m++] = id[k];
     *nv = m;
 }
 

@@ -440,6 +440,85 @@ __global__ void k_gram_build(const ColDev* __restrict__ colp, uint32_t n, uint32
     if ((threadIdx.x & 63) == 0) atomicMax(max_cnt, out_cnt);
 }
 
+// Rows of at most N windows (N a power of two <= 64): one thread per row
+// holds its window codes in registers, padded with the largest code, sorts
+// them with a bitonic network whose indices are all compile-time (so the
+// keys never leave registers), and writes the distinct codes.  The pad
+// value can equal a real q = 4 code; the first nw sorted keys are still the
+// row's multiset because no pad is smaller than a real code.
+template <int N>
+__global__ __launch_bounds__(256) void k_gram_build_reg(const ColDev* __restrict__ colp, uint32_t n, uint32_t q,
+                                                        const uint64_t* __restrict__ off,
+                                                        uint32_t* __restrict__ codes, uint32_t* __restrict__ cnt,
+                                                        uint8_t* __restrict__ flags,
+                                                        unsigned int* __restrict__ max_cnt) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t out_cnt = 0;
+    if (r < n) {
+        const ColDev c = *colp;
+        uint8_t f = 0;
+        if (bit_valid(c.valid, r)) {
+            const uint8_t* s = c.bytes + c.off[r];
+            const uint32_t L = str_len(c, r);
+            uint32_t* dst = codes + off[r];
+            if (L > 0 && L < q) {
+                uint32_t v = 0;
+                for (uint32_t x = 0; x < L; ++x) v = (v << 8) | s[x];
+                dst[0] = (L << 24) | v;
+                out_cnt = 1;
+                f = 1;
+            } else if (L >= q) {
+                const uint32_t nw = L - q + 1;   // <= N (the launch checks the longest row)
+                const uint32_t mask = (q == 4) ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
+                uint32_t b[N + 3];
+#pragma unroll
+                for (int x = 0; x < N + 3; ++x) b[x] = (uint32_t)x < L ? s[x] : 0u;
+                uint32_t k[N];
+                uint32_t v = 0;   // the first q - 1 bytes (constant indices keep b in registers)
+                if (q >= 2) v = b[0];
+                if (q >= 3) v = (v << 8) | b[1];
+                if (q >= 4) v = (v << 8) | b[2];
+#pragma unroll
+                for (int w = 0; w < N; ++w) {
+                    // window w ends at byte w + q - 1 (q <= 4)
+                    const uint32_t e = q == 1 ? b[w] : q == 2 ? b[w + 1] : q == 3 ? b[w + 2] : b[w + 3];
+                    v = ((v << 8) | e) & mask;
+                    k[w] = (uint32_t)w < nw ? v : 0xFFFFFFFFu;
+                }
+#pragma unroll
+                for (int kk = 2; kk <= N; kk <<= 1) {
+#pragma unroll
+                    for (int j = kk >> 1; j > 0; j >>= 1) {
+#pragma unroll
+                        for (int i = 0; i < N; ++i) {
+                            const int l = i ^ j;
+                            if (l > i) {
+                                const uint32_t a = k[i], bb = k[l];
+                                const uint32_t lo = a < bb ? a : bb, hi = a < bb ? bb : a;
+                                if ((i & kk) == 0) { k[i] = lo; k[l] = hi; }
+                                else { k[i] = hi; k[l] = lo; }
+                            }
+                        }
+                    }
+                }
+                uint32_t u = 0;
+#pragma unroll
+                for (int w = 0; w < N; ++w) {
+                    if ((uint32_t)w < nw && (w == 0 || k[w] != k[w - 1])) {
+                        dst[u] = k[w];
+                        ++u;
+                    }
+                }
+                out_cnt = u;
+            }
+        }
+        cnt[r] = out_cnt;
+        flags[r] = f;
+    }
+    for (int o = 32; o > 0; o >>= 1) out_cnt = max(out_cnt, (uint32_t)__shfl_xor((int)out_cnt, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(max_cnt, out_cnt);
+}
+
 __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -615,8 +694,14 @@ __device__ inline uint64_t minhash(const uint8_t* s, uint32_t L, uint32_t q) {
     const uint64_t mask = (1ull << (8 * q)) - 1ull;
     uint64_t v = 0;
     for (uint32_t x = 0; x + 1 < q; ++x) v = (v << 8) | s[x];
+    // the string's bytes in batches of four independent loads
+    uint32_t ch[4];
     for (uint32_t w = 0; w + q <= L; ++w) {
-        v = ((v << 8) | s[w + q - 1]) & mask;
+        if ((w & 3) == 0) {
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k) ch[k] = w + q - 1 + k < L ? s[w + q - 1 + k] : 0u;
+        }
+        v = ((v << 8) | ch[w & 3]) & mask;
         uint64_t h = mix64(((uint64_t)q << 32) | v);
         best = h < best ? h : best;
     }
@@ -843,6 +928,19 @@ hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const ui
         }
         const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((n + 3) / 4, 65536));
         k_gram_build_wave<<<grid, 256, lds, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt, cap);
+        return hipGetLastError();
+    }
+    if (max_windows <= 64) {
+        // short rows: a thread per row, sorting in registers
+        const uint32_t grid = (n + 255) / 256;
+        if (max_windows <= 8)
+            k_gram_build_reg<8><<<grid ? grid : 1, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
+        else if (max_windows <= 16)
+            k_gram_build_reg<16><<<grid ? grid : 1, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
+        else if (max_windows <= 32)
+            k_gram_build_reg<32><<<grid ? grid : 1, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
+        else
+            k_gram_build_reg<64><<<grid ? grid : 1, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
         return hipGetLastError();
     }
     // LDS segment per thread: the longest row's window count, made odd

@@ -152,6 +152,26 @@ def test_jaccard_boundaries(hb, ctx, q):
         assert np.array_equal(got, want), (num, den)
 
 
+@pytest.mark.parametrize("q,max_len", [(1, 8), (2, 9), (3, 18), (4, 35), (3, 66), (4, 67)])
+def test_jaccard_short_rows(hb, ctx, q, max_len):
+    """Rows of at most 64 windows take the per-thread register sort of the
+    q-gram build; each (q, max_len) picks one network size (8 to 64), and
+    the 0xFF bytes make q = 4 codes equal to the sort's pad value."""
+    show(f"jaccard short rows q={q} max_len={max_len}")
+    r = np.random.default_rng(100 * q + max_len)
+    strings = [b"", b"\xff", b"\xff" * q, b"\xff" * max_len, b"\xfe" + b"\xff" * (max_len - 1)]
+    for _ in range(60):
+        L = int(r.integers(0, max_len + 1))
+        alphabet = [97, 98, 255] if r.random() < 0.5 else [97, 98, 99, 100]
+        strings.append(bytes(r.choice(alphabet, size=L).astype(np.uint8)))
+    rel = _one_block_strings(strings)
+    for num, den in ((1, 2), (3, 5), (1, 1), (1, 5)):
+        rules = [[Pred(EQ, 1), Pred(JACCARD, 0, q=q, num=num, den=den)]]
+        want = oracle.blocking(rel, rules)
+        got, _ = run(hb, ctx, rel, rules, "given")
+        assert np.array_equal(got, want), (num, den)
+
+
 def test_plain_scaled_several_tiles(hb, ctx):
     show("plain_1m scaled to 40k")
     rel, rules = workloads.plain_1m(n=40_000)
