@@ -16,8 +16,8 @@ another seed -- and the MLP is trained on them by the library's kernels.
 The heuristic plan is timed the same way beside it, and both outputs are
 checked equal.
 
-Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one
-GPU.
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: the benchmark runs the
+path on one GPU.
 """
 import argparse
 import json
@@ -214,7 +214,7 @@ def main():
                     help="run one 2 GiB read + 2 GiB write kernel first (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
 
     import numpy as np

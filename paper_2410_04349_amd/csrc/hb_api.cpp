@@ -239,18 +239,21 @@ static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
     DevBuf tmp(c, sizeof(uint64_t) * scan_tmp_elems((size_t)n + 1));
     HB_HIP(launch_exclusive_scan_u64(slots.as<uint64_t>(), g.off.as<uint64_t>(), (size_t)n + 1, tmp.as<uint64_t>(),
                                      c->stream));
-    const uint64_t total = read1(c, g.off.as<uint64_t>() + n);
-    g.codes.alloc(c, sizeof(uint32_t) * (total + 1));
+    // no read-back: a row reserves at most one slot per byte, so the
+    // column's byte count bounds the codes, and its longest row's window
+    // count bounds every row's distinct codes (the LDS sizing needs no more)
+    const uint32_t ml = rel.cols[attr].max_len;
+    const uint32_t max_windows = ml >= q ? ml - q + 1 : 1;
+    g.codes.alloc(c, sizeof(uint32_t) * (rel.cols[attr].bytes.size() + 1));
     g.cnt.alloc(c, sizeof(uint32_t) * n);
     g.flags.alloc(c, n);
     DevBuf mx(c, sizeof(unsigned int));
     zero(c, mx.get(), sizeof(unsigned int));
     c->timed("gram_build", [&] {
-        const uint32_t ml = rel.cols[attr].max_len;
         return launch_gram_build(dcol, n, q, g.off.as<uint64_t>(), g.codes.as<uint32_t>(), g.cnt.as<uint32_t>(),
-                                 g.flags.as<uint8_t>(), mx.as<unsigned int>(), ml >= q ? ml - q + 1 : 1, c->stream);
+                                 g.flags.as<uint8_t>(), mx.as<unsigned int>(), max_windows, c->stream);
     });
-    g.max_cnt = read1(c, mx.as<unsigned int>());
+    g.max_cnt = max_windows;
     g.sig.alloc(c, sizeof(uint64_t) * n);
     HB_HIP(launch_gram_sig(g.dev(), n, g.sig.as<uint64_t>(), c->stream));
     auto res = rel.grams.emplace(key, std::move(g));
@@ -755,27 +758,35 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     for (size_t x = 0; x < R.int_attr.size(); ++x) m.int_attr[x] = R.int_attr[x];
     for (size_t x = 0; x < R.prev.size(); ++x) m.prev_res[x] = R.prev[x];
     GatherParams gp{};
-    gp.cols = rel.d_cols.as<ColDev>();
     gp.perm = P.perm.as<uint32_t>();
     gp.n = P.n_valid;
     gp.n_int = m.n_int;
     gp.n_str = m.n_str;
     gp.n_gram = m.n_gram;
-    for (size_t x = 0; x < R.int_attr.size(); ++x) gp.int_attr[x] = R.int_attr[x];
+    for (size_t x = 0; x < R.int_attr.size(); ++x) {
+        const Column& col = rel.cols[R.int_attr[x]];
+        gp.int_valid[x] = col.valid.size() ? col.valid.as<uint8_t>() : nullptr;
+        gp.int_vals[x] = col.values.as<int64_t>();
+    }
     uint32_t ed_words = 1;
     for (size_t x = 0; x < R.str_attr.size(); ++x) {
         m.str_attr[x] = R.str_attr[x];
-        gp.str_attr[x] = R.str_attr[x];
+        const Column& col = rel.cols[R.str_attr[x]];
+        gp.str_valid[x] = col.valid.size() ? col.valid.as<uint8_t>() : nullptr;
+        gp.str_off[x] = col.off.as<uint64_t>();
         gp.csig[x] = char_signature(c, rel, R.str_attr[x]);
         ed_words = std::max<uint32_t>(ed_words, (rel.cols[R.str_attr[x]].max_len + 63) / 64);
     }
     for (size_t x = 0; x < R.gram_key.size(); ++x) {
         GramIndex& g = gram_index(c, rel, R.gram_key[x].first, R.gram_key[x].second);
         m.gram[x] = g.dev();
-        gp.gram[x] = g.dev();
+        const Column& col = rel.cols[g.attr];
+        gp.gram_valid[x] = col.valid.size() ? col.valid.as<uint8_t>() : nullptr;
+        gp.gram_cnt[x] = g.cnt.as<uint32_t>();
+        gp.gram_flags[x] = g.flags.as<uint8_t>();
         gp.gsig[x] = g.sig.as<uint64_t>();
     }
-    m.ed_words = ed_words;
+    m.ed_words = R.any_ed ? ed_words : 0;   // 0: no edit-distance predicate
     const uint32_t n64 = m.n_int + m.n_str + m.n_gram, n32 = 2 + m.n_str + 2 * m.n_gram;
     const uint64_t stride = (uint64_t)P.n_valid + kTile;
     gp.stride = stride;
@@ -791,12 +802,14 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     uint32_t w = 0;
     m.lds_wave_peq = w;
     if (R.any_ed) w += 256 * ed_words * 8;
-    m.lds_wave_myers = w;
-    if (R.any_ed && ed_words >= 2) w += 2 * kMaxEdWords * 64 * 8;
     for (uint32_t x = 0; x < m.n_gram; ++x) {
         m.lds_wave_igram[x] = w;
         w += align_up(std::max<uint32_t>(m.gram[x].max_cnt, 1) * 4, 16);
     }
+    // last, so that kernels holding the long-pattern state in registers
+    // can leave it out
+    m.lds_wave_myers = w;
+    if (R.any_ed && ed_words >= 2) w += 2 * kMaxEdWords * 64 * 8;
     w = align_up(std::max<uint32_t>(w, 16), 16);
     m.lds_wave_stride = w;
     m.lds_counts = w;
@@ -815,7 +828,7 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     m.tile_blk = P.tile_blk.size() ? P.tile_blk.as<uint32_t>() : nullptr;
     m.n_blocks = P.n_blocks;
     m.n_tiles = P.n_tiles;
-    if (m.n_tiles >= (1ull << 30)) fail(HB_ERR_LIMIT, "more than 2^30 tiles in one key partition");
+    if (m.n_tiles > kMaxTiles) fail(HB_ERR_LIMIT, "more than 2^30 - 8 tiles in one key partition");
     return true;
 }
 

@@ -143,7 +143,7 @@ static void autotune(Ctx* c, Batch& B, int max_occ, int n_cu) {
         uint32_t grab, occ;
     };
     std::vector<Cand> cands{{kFormStreams, 0, 0}};
-    if (B.total < (1ull << 30)) cands.push_back({kFormMulti, 0, 0});
+    if (B.total <= kMaxTiles) cands.push_back({kFormMulti, 0, 0});
     std::vector<uint32_t> occs;
     for (int o = 1; o <= max_occ; o *= 2) occs.push_back((uint32_t)o);
     if (occs.back() != (uint32_t)max_occ) occs.push_back((uint32_t)max_occ);
@@ -300,7 +300,7 @@ static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, 
         B->grab = c->tuned_grab;
         B->occupancy = std::min<uint32_t>(c->tuned_occupancy, (uint32_t)occ);
         B->grid = (uint32_t)n_cu * B->occupancy;
-        if (B->form == kFormMulti && B->total >= (1ull << 30)) B->form = kFormStreams;
+        if (B->form == kFormMulti && B->total > kMaxTiles) B->form = kFormStreams;
     }
     if (flags & HB_BATCH_GRAPH) c->host_timed("batch_capture", [&] { capture(c, *B); });
     c->sync();

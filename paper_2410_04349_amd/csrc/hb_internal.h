@@ -11,6 +11,7 @@ namespace hb {
 
 constexpr int kTile = 64;        // tuples per tile side (one wave of j's)
 constexpr int kRows = 16;        // i-rows per wave batch (four batches per 64-row tile)
+constexpr uint64_t kMaxTiles = (1ull << 30) - 8;   // one launch's grid: 4 x tiles, rounded up to 32 < 2^32
 constexpr int kLshK = 1024;      // LSH buckets of the selectivity estimate
 constexpr int kMaxIntRes = 16;   // int attributes staged per tile
 constexpr int kMaxStrRes = 8;    // string attributes staged per tile
@@ -120,7 +121,7 @@ struct MatchParams {
     uint32_t str_attr[kMaxStrRes];
     GramDev gram[kMaxGramRes];
     uint32_t prev_res[kMaxPrevKeys];   // int resources of earlier keys (canonical owner)
-    uint32_t ed_words;                 // 64-bit words of the per-wave pattern-match table
+    uint32_t ed_words;                 // 64-bit words of the pattern-match table (0: no edit distance)
     // LDS layout (byte offsets into dynamic shared memory)
     uint32_t lds_wave_stride;          // bytes of the wave's region (from offset 0)
     uint32_t lds_wave_peq, lds_wave_myers, lds_wave_igram[kMaxGramRes];
@@ -139,17 +140,23 @@ struct MatchParams {
     const uint32_t* blk_slot;
 };
 
-// Gather of the block-major feature columns.
+// Gather of the block-major feature columns: grid.y = 1 + n_int + n_str +
+// n_gram slices (row id and validity mask, then one per resource), each
+// thread one (position, slice), with every column's pointers given
+// directly so a thread's loads depend only on its row.
 struct GatherParams {
-    const ColDev* cols;
     const uint32_t* perm;
     uint64_t n;           // positions
     uint64_t stride;      // column stride (>= n; positions n .. stride - 1 are zeroed)
     uint32_t n_int, n_str, n_gram;
-    uint32_t int_attr[kMaxIntRes];
-    uint32_t str_attr[kMaxStrRes];
+    const uint8_t* int_valid[kMaxIntRes];     // nullptr: every row valid
+    const int64_t* int_vals[kMaxIntRes];
+    const uint8_t* str_valid[kMaxStrRes];
+    const uint64_t* str_off[kMaxStrRes];
     const uint64_t* csig[kMaxStrRes];
-    GramDev gram[kMaxGramRes];
+    const uint8_t* gram_valid[kMaxGramRes];
+    const uint32_t* gram_cnt[kMaxGramRes];
+    const uint8_t* gram_flags[kMaxGramRes];
     const uint64_t* gsig[kMaxGramRes];
     uint64_t* f64;
     uint32_t* f32;

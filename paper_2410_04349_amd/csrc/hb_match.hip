@@ -219,6 +219,14 @@ __device__ __forceinline__ uint32_t popc_add(uint32_t x, uint32_t acc) {
     return out;
 }
 
+// a * b + c on the signed 24-bit multiplier (|a|, |b| < 2^23), one
+// full-rate instruction; the caller keeps the result within int32.
+__device__ __forceinline__ int mad_i24(int a, int b, int c) {
+    int out;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(out) : "v"(a), "s"(b), "v"(c));
+    return out;
+}
+
 // Opaque copy: keeps the compiler from folding a precomputed per-lane term
 // back into the per-row arithmetic.
 template <typename T>
@@ -264,7 +272,7 @@ __device__ inline void decode_tile(const MatchParams& P, uint64_t t, uint32_t* b
 // j-row and reads its features from the columns when a step needs them.
 // Wave-uniform values are passed through readfirstlane so the compiler
 // keeps them (and the loads they address) scalar.
-template <bool kCount>
+template <bool kCount, bool kLongEd = false>
 __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL Instr* __restrict__ plan,
                                            const HB_GLOBAL uint64_t* __restrict__ f64,
                                            const HB_GLOBAL uint32_t* __restrict__ f32, uint64_t t, uint8_t* lds,
@@ -339,6 +347,9 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             pc = __builtin_amdgcn_readfirstlane(pc);
             // one 16-byte scalar load (there is no scalar byte load)
             const uint4 raw = *(const HB_GLOBAL uint4*)(pl + pc);
+            // every word is needed before the step's own loads: one 16-byte
+            // load and one wait, not a dependent load per field
+            asm volatile("" ::"s"(raw.x), "s"(raw.y), "s"(raw.z), "s"(raw.w));
             const uint32_t op = raw.x & 0xFFu, res = (raw.x >> 16) & 0xFFu;
             const uint32_t cp = raw.y & 0xFFFFu;
             const uint64_t param = ((uint64_t)raw.w << 32) | raw.z;
@@ -430,6 +441,24 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 uint32_t keep = 0;
                 if (num == 0) {   // J >= 0: every pair of present values
                     keep = (vmask_j >> (24 + res)) & 1 ? row_bits(f32 + n, pi0, 24 + res) : 0u;
+                } else if (nd <= (1u << 18)) {
+                    // num + den <= 2^18: I * (num + den) - num * |B| stays
+                    // within int32, so one signed 24-bit multiply-add and a
+                    // compare against the row's num * |A| (a scalar) decide
+                    // the row
+                    const uint32_t restb = wb >> 16;
+                    const int neg_b = opaque(-(int)(num * (wb & 0xFFFFu)));
+                    const uint32_t gj_lo = (uint32_t)gj, gj_hi = (uint32_t)(gj >> 32);
+#pragma unroll
+                    for (int r = kRows - 1; r >= 0; --r) {
+                        const uint64_t pr = pi0 + (uint64_t)r;
+                        const uint32_t wa = f32[(jf32 + res) * n + pr];
+                        const uint64_t gi = f64[(gram64 + res) * n + pr];
+                        const uint32_t rest = min(wa >> 16, restb);
+                        const uint32_t iub = popc_add((uint32_t)gi & gj_lo, popc_add((uint32_t)(gi >> 32) & gj_hi, rest));
+                        const int lhs = mad_i24((int)iub, (int)nd, neg_b);
+                        keep = push_bit(keep, __ballot(lhs >= (int)(num * (wa & 0xFFFFu))));
+                    }
                 } else {
                     const uint32_t restb = wb >> 16, rhs_b = opaque(__umul24(num, wb & 0xFFFFu));
                     const uint32_t gj_lo = (uint32_t)gj, gj_hi = (uint32_t)(gj >> 32);
@@ -479,8 +508,20 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                         const bool run = need && abs(m - nn) <= k;
                         if (__any(run)) build_peq(peq, words, c.bytes + c.off[row_i], m, lane);
                         if (run) {
-                            const int dist = myers_dispatch(peq, words, m, c.bytes + c.off[row_j], nn,
-                                                            (uint64_t*)(wbase + P.lds_wave_myers), lane);
+                            const uint8_t* tj = c.bytes + c.off[row_j];
+                            int dist;
+                            if constexpr (kLongEd) {
+                                // patterns of up to four words, state in registers
+                                dist = m == 0 ? nn : nn == 0 ? m
+                                     : words == 0 ? myers<uint32_t, 1>((const uint32_t*)peq, m, tj, nn)
+                                     : words == 1 ? myers<uint64_t, 1>((const uint64_t*)peq, m, tj, nn)
+                                     : words == 2 ? myers<uint64_t, 2>((const uint64_t*)peq, m, tj, nn)
+                                     : words == 3 ? myers<uint64_t, 3>((const uint64_t*)peq, m, tj, nn)
+                                                  : myers<uint64_t, 4>((const uint64_t*)peq, m, tj, nn);
+                            } else {
+                                dist = myers_dispatch(peq, words, m, tj, nn, (uint64_t*)(wbase + P.lds_wave_myers),
+                                                      lane);
+                            }
                             ok = dist <= k;
                             w = (uint32_t)nn * (uint32_t)max(1, (m + 31) / 32);
                         }
@@ -531,8 +572,10 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             ++pc;
         }
 
-        // ballot compaction of matched pairs, row by row
-        for (int r = 0; r < nr; ++r) {
+        // ballot compaction of matched pairs, row by row (most batches
+        // have none)
+        const int out_rows = __any(matched != 0) ? nr : 0;
+        for (int r = 0; r < out_rows; ++r) {
             const bool m = (matched >> r) & 1;
             const uint64_t mask = __ballot(m);
             if (!mask) continue;
@@ -558,23 +601,42 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
     }
 }
 
-// Workgroup w (one wave) runs the 16-row batch w % 4 of tile w / 4, so no
-// workgroup holds resources for waves that finished early.  XCD-aware
-// remap: consecutive workgroups go round-robin to the 8 XCDs; each XCD gets
-// a contiguous range of tiles so a block's tiles share its L2.
+// Batch unit (tile * 4 + batch) of workgroup `bid` in a grid of a
+// multiple of 32 workgroups.  Workgroups go round-robin to the 8 XCDs
+// (bid % 8); XCD x runs tiles x, x + 8, x + 16, ... in order, the four
+// batches of a tile back to back.  A tile's four waves share its j-rows in
+// one L2, and every XCD gets an even share of heavy and light tiles.
+__device__ __forceinline__ uint64_t batch_unit(uint64_t bid) {
+    const uint64_t x = bid & 7, g = bid >> 3;
+    return (((g >> 2) * 8 + x) << 2) | (g & 3);
+}
+
+// One wave per workgroup, one 16-row batch per wave (batch_unit), so no
+// workgroup holds resources for waves that finished early.
 template <bool kCount>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_match(
     const MatchParams P, const Instr* __restrict__ plan, const uint64_t* __restrict__ f64,
     const uint32_t* __restrict__ f32) {
     extern __shared__ __align__(16) uint8_t lds[];
-    const uint64_t G = gridDim.x;
-    const uint64_t bid = blockIdx.x;
-    const uint64_t xcd = bid & 7, idx = bid >> 3;
-    const uint64_t q8 = G >> 3, r8 = G & 7;
-    const uint64_t w = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+    const uint64_t w = batch_unit(blockIdx.x);
     const uint64_t t = w >> 2;
     if (t >= P.n_tiles) return;
     match_tile<kCount>(P, gmem(plan), gmem(f64), gmem(f32), t, lds, (int)(w & 3));
+}
+
+// k_match for partitions with edit-distance patterns past 64 bytes: the
+// Myers state of up to four words lives in registers (no LDS for it, so
+// more waves fit), at a register count the short-pattern kernel does not
+// pay.
+template <bool kCount>
+__global__ __launch_bounds__(64) void k_match_long(const MatchParams P, const Instr* __restrict__ plan,
+                                                   const uint64_t* __restrict__ f64,
+                                                   const uint32_t* __restrict__ f32) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const uint64_t w = batch_unit(blockIdx.x);
+    const uint64_t t = w >> 2;
+    if (t >= P.n_tiles) return;
+    match_tile<kCount, true>(P, gmem(plan), gmem(f64), gmem(f32), t, lds, (int)(w & 3));
 }
 
 // partition of queue item x: prefix[p] <= x < prefix[p + 1]
@@ -615,16 +677,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
 }
 
 // One one-wave workgroup per batch unit over the queue of many partitions
-// (the hardware dispatcher hands out workgroups as compute units free up);
-// XCD-aware remap as in k_match.
+// (the hardware dispatcher hands out workgroups as compute units free up),
+// mapped to XCDs as in k_match.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_match_multi(
     const MatchParams* __restrict__ mps, const uint64_t* __restrict__ prefix, uint32_t n_parts, uint64_t total) {
     extern __shared__ __align__(16) uint8_t lds[];
-    const uint64_t G = gridDim.x;
-    const uint64_t bid = blockIdx.x;
-    const uint64_t xcd = bid & 7, idx = bid >> 3;
-    const uint64_t q8 = G >> 3, r8 = G & 7;
-    const uint64_t u = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+    const uint64_t u = batch_unit(blockIdx.x);
     const uint64_t item = u >> 2;
     if (item >= total) return;
     const uint32_t p = queue_partition(prefix, n_parts, item);
@@ -1086,9 +1144,24 @@ static hipError_t allow_lds(const void* fn, int* configured, uint32_t bytes) {
 
 hipError_t launch_match(const MatchParams& p, hipStream_t s) {
     if (p.n_tiles == 0) return hipSuccess;
-    if (p.n_tiles >= (1ull << 30)) return hipErrorInvalidValue;   // the grid holds 4 x n_tiles workgroups
-    static int configured[2] = {0, 0};
-    const unsigned grid = (unsigned)(p.n_tiles * 4);
+    if (p.n_tiles > kMaxTiles) return hipErrorInvalidValue;   // the grid holds 4 x n_tiles workgroups
+    static int configured[4] = {0, 0, 0, 0};
+    const unsigned grid = (unsigned)((p.n_tiles * 4 + 31) & ~31ull);   // batch_unit needs a multiple of 32
+    if (p.ed_words >= 2) {
+        // the register-state kernel leaves out the LDS Myers region (the
+        // layout's last one)
+        MatchParams q = p;
+        q.lds_counts = p.lds_wave_myers;
+        q.lds_bytes = (q.lds_counts + (p.counts ? kCountSlots * 8 : 0) + 15) & ~15u;
+        const void* fn = p.counts ? (const void*)k_match_long<true> : (const void*)k_match_long<false>;
+        hipError_t e = allow_lds(fn, &configured[p.counts ? 2 : 3], q.lds_bytes);
+        if (e != hipSuccess) return e;
+        if (p.counts)
+            k_match_long<true><<<grid, 64, q.lds_bytes, s>>>(q, q.plan, q.feat.f64, q.feat.f32);
+        else
+            k_match_long<false><<<grid, 64, q.lds_bytes, s>>>(q, q.plan, q.feat.f64, q.feat.f32);
+        return hipGetLastError();
+    }
     if (p.counts) {
         hipError_t e = allow_lds((const void*)k_match<true>, &configured[0], p.lds_bytes);
         if (e != hipSuccess) return e;
@@ -1116,11 +1189,11 @@ hipError_t launch_match_persistent(const MatchParams* mps, const uint64_t* prefi
 hipError_t launch_match_multi(const MatchParams* mps, const uint64_t* prefix, uint32_t n_parts, uint64_t total,
                               uint32_t lds_bytes, hipStream_t s) {
     if (total == 0) return hipSuccess;
-    if (total >= (1ull << 30)) return hipErrorInvalidValue;   // the grid holds 4 x total workgroups
+    if (total > kMaxTiles) return hipErrorInvalidValue;   // the grid holds 4 x total workgroups
     static int configured = 0;
     hipError_t e = allow_lds((const void*)k_match_multi, &configured, lds_bytes);
     if (e != hipSuccess) return e;
-    k_match_multi<<<(unsigned)(total * 4), 64, lds_bytes, s>>>(mps, prefix, n_parts, total);
+    k_match_multi<<<(unsigned)((total * 4 + 31) & ~31ull), 64, lds_bytes, s>>>(mps, prefix, n_parts, total);
     return hipGetLastError();
 }
 

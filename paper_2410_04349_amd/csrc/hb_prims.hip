@@ -618,7 +618,14 @@ __global__ void k_char_sig(const ColDev* __restrict__ colp, uint32_t n, uint64_t
     if (bit_valid(c.valid, r)) {
         const uint8_t* s = c.bytes + c.off[r];
         const uint32_t L = str_len(c, r);
-        for (uint32_t x = 0; x < L; ++x) m |= 1ull << (s[x] & 63);
+        for (uint32_t x = 0; x < L; x += 8) {   // eight independent loads per batch
+            uint32_t v[8];
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) v[k] = x + k < L ? s[x + k] : 0u;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k)
+                if (x + k < L) m |= 1ull << (v[k] & 63);
+        }
     }
     sig[r] = m;
 }
@@ -632,7 +639,14 @@ __global__ void k_gram_sig(const GramDev g, uint32_t n, uint64_t* __restrict__ s
     const uint32_t* codes = g.codes + g.off[r];
     const uint32_t cnt = g.cnt[r];
     uint64_t m = 0;
-    for (uint32_t x = 0; x < cnt; ++x) m |= 1ull << (mix64(codes[x]) & 63);
+    for (uint32_t x = 0; x < cnt; x += 8) {   // eight independent loads per batch
+        uint32_t v[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) v[k] = x + k < cnt ? codes[x + k] : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k)
+            if (x + k < cnt) m |= 1ull << (mix64(v[k]) & 63);
+    }
     sig[r] = m;
 }
 
@@ -640,38 +654,42 @@ __global__ void k_gather_features(const GatherParams P) {
     const uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (p >= P.stride) return;
     const uint64_t n = P.stride;
-    if (p >= P.n) {   // pad position
-        for (uint32_t x = 0; x < P.n_int + P.n_str + P.n_gram; ++x) P.f64[x * n + p] = 0ull;
-        for (uint32_t x = 0; x < 2 + P.n_str + 2 * P.n_gram; ++x) P.f32[x * n + p] = 0u;
+    const uint32_t y = blockIdx.y;
+    const bool pad = p >= P.n;
+    const uint32_t row = pad ? 0u : P.perm[p];
+    if (y == 0) {   // row id and validity mask
+        uint32_t vmask = 0;
+        if (!pad) {
+            for (uint32_t x = 0; x < P.n_int; ++x) vmask |= (bit_valid(P.int_valid[x], row) ? 1u : 0u) << x;
+            for (uint32_t x = 0; x < P.n_str; ++x) vmask |= (bit_valid(P.str_valid[x], row) ? 1u : 0u) << (16 + x);
+            for (uint32_t x = 0; x < P.n_gram; ++x) vmask |= (bit_valid(P.gram_valid[x], row) ? 1u : 0u) << (24 + x);
+        }
+        P.f32[p] = pad ? 0u : row;
+        P.f32[n + p] = vmask;
         return;
     }
-    const uint32_t row = P.perm[p];
-    uint32_t vmask = 0;
-    for (uint32_t x = 0; x < P.n_int; ++x) {
-        const ColDev& c = P.cols[P.int_attr[x]];
-        const bool v = bit_valid(c.valid, row);
-        P.f64[x * n + p] = v ? (uint64_t)c.values[row] : 0ull;
-        vmask |= (v ? 1u : 0u) << x;
+    uint32_t x = y - 1;
+    if (x < P.n_int) {
+        const bool v = !pad && bit_valid(P.int_valid[x], row);
+        P.f64[x * n + p] = v ? (uint64_t)P.int_vals[x][row] : 0ull;
+        return;
     }
-    for (uint32_t x = 0; x < P.n_str; ++x) {
-        const ColDev& c = P.cols[P.str_attr[x]];
-        const bool v = bit_valid(c.valid, row);
+    x -= P.n_int;
+    if (x < P.n_str) {
+        const bool v = !pad && bit_valid(P.str_valid[x], row);
         P.f64[(P.n_int + x) * n + p] = v ? P.csig[x][row] : 0ull;
-        P.f32[(2 + x) * n + p] = v ? (uint32_t)(c.off[row + 1] - c.off[row]) : 0u;
-        vmask |= (v ? 1u : 0u) << (16 + x);
+        P.f32[(2 + x) * n + p] = v ? (uint32_t)(P.str_off[x][row + 1] - P.str_off[x][row]) : 0u;
+        return;
     }
-    for (uint32_t x = 0; x < P.n_gram; ++x) {
-        const GramDev& g = P.gram[x];
-        const bool v = bit_valid(P.cols[g.attr].valid, row);
-        const uint64_t sig = v ? P.gsig[x][row] : 0ull;
-        const uint32_t cnt = v ? g.cnt[row] : 0u;
-        P.f64[(P.n_int + P.n_str + x) * n + p] = sig;
-        P.f32[(2 + P.n_str + x) * n + p] = v ? (cnt | ((uint32_t)(g.flags[row] & 1) << 31)) : 0u;
-        P.f32[(2 + P.n_str + P.n_gram + x) * n + p] = v ? ((cnt - (uint32_t)__popcll(sig)) << 16) | cnt : 1u;
-        vmask |= (v ? 1u : 0u) << (24 + x);
-    }
-    P.f32[p] = row;
-    P.f32[n + p] = vmask;
+    x -= P.n_str;
+    const bool v = !pad && bit_valid(P.gram_valid[x], row);
+    const uint64_t sig = v ? P.gsig[x][row] : 0ull;
+    const uint32_t cnt = v ? P.gram_cnt[x][row] : 0u;
+    P.f64[(P.n_int + P.n_str + x) * n + p] = sig;
+    P.f32[(2 + P.n_str + x) * n + p] = v ? (cnt | ((uint32_t)(P.gram_flags[x][row] & 1) << 31)) : 0u;
+    // the Jaccard-filter word: 1 marks a missing value (pads: 0)
+    P.f32[(2 + P.n_str + P.n_gram + x) * n + p] =
+        v ? ((cnt - (uint32_t)__popcll(sig)) << 16) | cnt : pad ? 0u : 1u;
 }
 
 // ------------------------------------------------------------ LSH histogram
@@ -972,7 +990,8 @@ hipError_t launch_gram_sig(const GramDev& g, uint32_t n, uint64_t* sig, hipStrea
 
 hipError_t launch_gather_features(const GatherParams& p, hipStream_t s) {
     if (p.n == 0) return hipSuccess;
-    k_gather_features<<<grid_for(p.stride, 1u << 30), kBlock, 0, s>>>(p);
+    const dim3 grid(grid_for(p.stride, 1u << 30), 1 + p.n_int + p.n_str + p.n_gram);
+    k_gather_features<<<grid, kBlock, 0, s>>>(p);
     return hipGetLastError();
 }
 
