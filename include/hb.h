@@ -59,7 +59,8 @@ typedef enum {
 #define HB_MAX_JACCARD_DEN (1u << 18) /* threshold denominator in lowest terms */
 
 /* Device allocator: return `bytes` bytes of device memory on the context's
- * device (NULL on failure); `user` is passed through. */
+ * device, aligned to at least 16 bytes (NULL on failure; a misaligned block
+ * fails the call with HB_ERR_OOM); `user` is passed through. */
 typedef void* (*hb_alloc_fn)(size_t bytes, void* user);
 typedef void (*hb_free_fn)(void* ptr, void* user);
 
@@ -320,16 +321,27 @@ hb_status hb_last_match_stats(hb_ctx* ctx, hb_match_stats* out);
 /* ------------------------------------------------------------ batches
  * Many (relation, rule set) jobs matched together (the paper's pipeline
  * batches its work for the device, Section 5): every job's key partitions
- * feed one persistent, work-stealing launch (heaviest partitions first,
- * workgroups taking items from a global queue), so uneven jobs share the
- * device without one launch each.  Every job must have run hb_partition;
- * its relation and rule set must stay loaded while the batch exists
- * (HB_ERR_STALE_ID on hb_batch_run otherwise).  Results equal hb_match's. */
+ * form one queue of 64 x 64 tiles (heaviest partitions first) that runs in
+ * one of three launch forms -- each partition's match launch on four
+ * concurrent streams (0), one workgroup per 16-row batch of a tile over the
+ * whole queue (1), or a persistent grid whose workgroups take batches from
+ * a global cursor (2) -- optionally captured in a HIP graph, so uneven jobs
+ * share the device.  Every job must have run hb_partition; its relation
+ * and rule set must stay loaded while the batch exists (HB_ERR_STALE_ID on
+ * hb_batch_run otherwise).  Results equal hb_match's in every form. */
 #define HB_MAX_BATCH_JOBS 4096
 #define HB_BATCH_GRAPH 1u     /* capture the batch's launches in a HIP graph, replayed by hb_batch_run */
 #define HB_BATCH_AUTOTUNE 2u  /* time the launch forms (hb_batch_info.form; the persistent grid at each
                                  work-grab size and occupancy) on the batch's first items; keep the fastest.
-                                 Batches created without it use the context's last tuned form (else form 0) */
+                                 Batches created without it (or a forced form) use the context's last tuned
+                                 form (else form 0) */
+/* Force a launch form (not with HB_BATCH_AUTOTUNE; HB_ERR_INVALID_ARG otherwise).  The persistent form
+ * takes one batch per grab at the occupancy the LDS footprint allows; the one-workgroup-per-batch form
+ * needs at most 2^30 - 8 tiles in the queue (HB_ERR_LIMIT otherwise). */
+#define HB_BATCH_FORM_STREAMS 0x100u
+#define HB_BATCH_FORM_MULTI 0x200u
+#define HB_BATCH_FORM_PERSISTENT 0x300u
+#define HB_BATCH_FORM_MASK 0x300u
 
 typedef struct {
     uint32_t rel_id;

@@ -51,6 +51,7 @@ EXPORTED = [
 
 HB_BATCH_GRAPH = 1
 HB_BATCH_AUTOTUNE = 2
+HB_BATCH_FORM = {"streams": 0x100, "multi": 0x200, "persistent": 0x300}
 
 HB_MLP_PARAMS = 5378
 
@@ -485,11 +486,15 @@ def hb_log_collect(ctx: Context, rel_id: int, ruleset_id: int, samples: int, see
 
 # ------------------------------------------------------------ batches
 
-def hb_batch_create(ctx: Context, jobs, plan="heuristic", graph: bool = True, autotune: bool = False) -> int:
-    """jobs: sequence of (rel_id, ruleset_id), each partitioned."""
+def hb_batch_create(ctx: Context, jobs, plan="heuristic", graph: bool = True, autotune: bool = False,
+                    form=None) -> int:
+    """jobs: sequence of (rel_id, ruleset_id), each partitioned; form: None
+    (tuned or remembered), "streams", "multi" or "persistent"."""
     arr = (HbJob * max(1, len(jobs)))(*[HbJob(int(r), int(s)) for r, s in jobs])
     pl = _PLAN[plan] if isinstance(plan, str) else int(plan)
     flags = (HB_BATCH_GRAPH if graph else 0) | (HB_BATCH_AUTOTUNE if autotune else 0)
+    if form is not None:
+        flags |= HB_BATCH_FORM[form]
     bid = ctypes.c_uint32()
     ctx.check(_lib.hb_batch_create(ctx.h, arr, len(jobs), pl, flags, ctypes.byref(bid)))
     return bid.value

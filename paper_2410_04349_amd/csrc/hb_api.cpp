@@ -247,11 +247,9 @@ static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
     g.codes.alloc(c, sizeof(uint32_t) * (rel.cols[attr].bytes.size() + 1));
     g.cnt.alloc(c, sizeof(uint32_t) * n);
     g.flags.alloc(c, n);
-    DevBuf mx(c, sizeof(unsigned int));
-    zero(c, mx.get(), sizeof(unsigned int));
     c->timed("gram_build", [&] {
         return launch_gram_build(dcol, n, q, g.off.as<uint64_t>(), g.codes.as<uint32_t>(), g.cnt.as<uint32_t>(),
-                                 g.flags.as<uint8_t>(), mx.as<unsigned int>(), max_windows, c->stream);
+                                 g.flags.as<uint8_t>(), max_windows, c->stream);
     });
     g.max_cnt = max_windows;
     g.sig.alloc(c, sizeof(uint64_t) * n);
@@ -424,6 +422,21 @@ static uint32_t sort_rows_by(Ctx* c, Relation& rel, const std::vector<uint32_t>&
                                     flags.as<uint32_t>(), c->stream));
     DevBuf stmp(c, sizeof(uint32_t) * scan_tmp_elems(n));
     HB_HIP(launch_exclusive_scan_u32(flags.as<uint32_t>(), dest.as<uint32_t>(), n, stmp.as<uint32_t>(), c->stream));
+    // every attribute's min / max (they size the radix passes) is read back
+    // with the row count, in one synchronisation
+    const size_t na = attrs.size();
+    DevBuf mm(c, 32 * na);
+    std::vector<unsigned long long> init(4 * na, 0ull);
+    for (size_t x = 0; x < na; ++x) init[4 * x] = ~0ull;
+    HB_HIP(hipMemcpyAsync(mm.get(), init.data(), 32 * na, hipMemcpyHostToDevice, c->stream));
+    for (size_t x = 0; x < na; ++x) {
+        uint8_t* e = mm.as<uint8_t>() + 32 * x;
+        HB_HIP(launch_minmax_u64(rel.cols[attrs[x]].values.as<int64_t>(), rel.cols[attrs[x]].valid.as<uint8_t>(), n,
+                                 (unsigned long long*)e, (unsigned long long*)(e + 8), (unsigned int*)(e + 16),
+                                 c->stream));
+    }
+    std::vector<unsigned long long> mmh(4 * na);
+    HB_HIP(hipMemcpyAsync(mmh.data(), mm.get(), 32 * na, hipMemcpyDeviceToHost, c->stream));
     uint32_t last[2];
     HB_HIP(hipMemcpyAsync(&last[0], dest.as<uint32_t>() + n - 1, 4, hipMemcpyDeviceToHost, c->stream));
     HB_HIP(hipMemcpyAsync(&last[1], flags.as<uint32_t>() + n - 1, 4, hipMemcpyDeviceToHost, c->stream));
@@ -434,22 +447,13 @@ static uint32_t sort_rows_by(Ctx* c, Relation& rel, const std::vector<uint32_t>&
     HB_HIP(launch_compact_rows(flags.as<uint32_t>(), dest.as<uint32_t>(), n, rows_out.as<uint32_t>(), c->stream));
     DevBuf keys(c, sizeof(uint64_t) * nv), keys_alt(c, sizeof(uint64_t) * nv), rows_alt(c, sizeof(uint32_t) * nv);
     DevBuf rtmp(c, radix_tmp_bytes(nv));
-    DevBuf mm(c, 32);
     // least significant attribute first (LSD over attributes)
-    for (size_t x = attrs.size(); x-- > 0;) {
+    for (size_t x = na; x-- > 0;) {
         const uint32_t a = attrs[x];
-        zero(c, mm.get(), 32);
-        unsigned long long init_min = ~0ull;
-        HB_HIP(hipMemcpyAsync(mm.get(), &init_min, 8, hipMemcpyHostToDevice, c->stream));
-        HB_HIP(launch_minmax_u64(rel.cols[a].values.as<int64_t>(), rel.cols[a].valid.as<uint8_t>(), n,
-                                 (unsigned long long*)mm.get(), (unsigned long long*)(mm.as<uint8_t>() + 8),
-                                 (unsigned int*)(mm.as<uint8_t>() + 16), c->stream));
-        unsigned long long mmh[2];
-        HB_HIP(hipMemcpyAsync(mmh, mm.get(), 16, hipMemcpyDeviceToHost, c->stream));
-        c->sync();
-        HB_HIP(launch_gather_key(rel.d_cols.as<ColDev>(), a, mmh[0], rows_out.as<uint32_t>(), nv, keys.as<uint64_t>(),
+        const unsigned long long lo = mmh[4 * x], hi = mmh[4 * x + 1];
+        HB_HIP(launch_gather_key(rel.d_cols.as<ColDev>(), a, lo, rows_out.as<uint32_t>(), nv, keys.as<uint64_t>(),
                                  c->stream));
-        std::vector<int> sh = shifts_for_bits(bit_width(mmh[1] - mmh[0]), 0);
+        std::vector<int> sh = shifts_for_bits(bit_width(hi - lo), 0);
         bool in_alt = false;
         c->timed("partition_sort", [&] {
             return radix_sort_pairs(keys.as<uint64_t>(), rows_out.as<uint32_t>(), keys_alt.as<uint64_t>(),
@@ -540,7 +544,7 @@ static Partition& key_partition(Ctx* c, Relation& rel, uint32_t attr) {
         P.n_tiles = h[0];
         P.pairs = h[1];
         P.n_big = hb2[0] + hb2[1];
-        if (P.n_tiles && P.n_tiles <= (1ull << 28)) {
+        if (P.n_tiles && P.n_tiles <= kMaxTiles) {   // more tiles cannot be matched in one launch
             P.tile_blk.alloc(c, sizeof(uint32_t) * P.n_tiles);
             HB_HIP(launch_tile_blocks(P.tile_prefix.as<uint64_t>(), P.n_blocks, P.n_tiles, P.tile_blk.as<uint32_t>(),
                                       c->stream));
@@ -825,7 +829,7 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     m.blk_start = P.blk_start.as<uint32_t>();
     m.blk_size = P.blk_size.as<uint32_t>();
     m.tile_prefix = P.tile_prefix.as<uint64_t>();
-    m.tile_blk = P.tile_blk.size() ? P.tile_blk.as<uint32_t>() : nullptr;
+    m.tile_blk = P.tile_blk.as<uint32_t>();
     m.n_blocks = P.n_blocks;
     m.n_tiles = P.n_tiles;
     if (m.n_tiles > kMaxTiles) fail(HB_ERR_LIMIT, "more than 2^30 - 8 tiles in one key partition");

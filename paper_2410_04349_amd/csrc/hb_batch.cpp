@@ -201,7 +201,10 @@ static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, 
     if (n_jobs == 0 || n_jobs > HB_MAX_BATCH_JOBS) fail(HB_ERR_INVALID_ARG, "n_jobs must be in [1, HB_MAX_BATCH_JOBS]");
     if (plan != HB_PLAN_GIVEN && plan != HB_PLAN_HEURISTIC && plan != HB_PLAN_LEARNED)
         fail(HB_ERR_INVALID_ARG, "unknown plan");
-    if (flags & ~(uint32_t)(HB_BATCH_GRAPH | HB_BATCH_AUTOTUNE)) fail(HB_ERR_INVALID_ARG, "unknown batch flags");
+    if (flags & ~(uint32_t)(HB_BATCH_GRAPH | HB_BATCH_AUTOTUNE | HB_BATCH_FORM_MASK))
+        fail(HB_ERR_INVALID_ARG, "unknown batch flags");
+    if ((flags & HB_BATCH_AUTOTUNE) && (flags & HB_BATCH_FORM_MASK))
+        fail(HB_ERR_INVALID_ARG, "a forced launch form excludes autotuning");
     auto B = std::make_shared<Batch>();
     B->plan = plan;
     B->flags = flags;
@@ -289,7 +292,13 @@ static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, 
         HB_HIP(hipStreamCreateWithFlags(&B->lanes[x], hipStreamNonBlocking));
         HB_HIP(hipEventCreateWithFlags(&B->ev_lane[x], hipEventDisableTiming));
     }
-    if ((flags & HB_BATCH_AUTOTUNE) && B->total > 0) {
+    if (flags & HB_BATCH_FORM_MASK) {
+        const uint32_t f = flags & HB_BATCH_FORM_MASK;
+        B->form = f == HB_BATCH_FORM_MULTI ? kFormMulti : f == HB_BATCH_FORM_PERSISTENT ? kFormPersistent : kFormStreams;
+        B->grab = 1;
+        if (B->form == kFormMulti && B->total > kMaxTiles)
+            fail(HB_ERR_LIMIT, "more than 2^30 - 8 tiles for the one-workgroup-per-batch form");
+    } else if ((flags & HB_BATCH_AUTOTUNE) && B->total > 0) {
         autotune(c, *B, occ, n_cu);
         c->batch_tuned = true;
         c->tuned_form = B->form;

@@ -92,7 +92,7 @@ struct Partition {
     uint32_t attr = 0, n_valid = 0, n_blocks = 0;
     uint64_t n_tiles = 0, pairs = 0;
     DevBuf perm, blk_start, blk_size, tile_prefix;
-    DevBuf tile_blk;      // block of each tile (left empty for more than 2^28 tiles)
+    DevBuf tile_blk;      // block of each tile
     DevBuf big;           // blocks of >= kRows tuples (the ones with per-block plans)
     uint32_t n_big = 0;
 };
@@ -189,6 +189,10 @@ struct Ctx {
             if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
         }
         if (!p) fail(HB_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        if (reinterpret_cast<uintptr_t>(p) & 15) {   // kernels read 16-byte words and aligned dwords
+            raw_free(p);
+            fail(HB_ERR_OOM, "the allocator returned a block not aligned to 16 bytes");
+        }
         return p;
     }
     void raw_free(void* p) {

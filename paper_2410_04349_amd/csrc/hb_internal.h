@@ -44,7 +44,7 @@ struct GramDev {
     const uint32_t* codes;
     const uint8_t* flags;
     uint32_t q;
-    uint32_t max_cnt;
+    uint32_t max_cnt;   // bound on a row's code count: the longest row's window count
     uint32_t attr;
     uint32_t pad;
 };
@@ -108,8 +108,7 @@ struct MatchParams {
     const uint32_t* blk_start;
     const uint32_t* blk_size;
     const uint64_t* tile_prefix;   // n_blocks + 1 entries
-    const uint32_t* tile_blk;      // block of each tile (n_tiles entries), or nullptr:
-                                   // binary search of tile_prefix
+    const uint32_t* tile_blk;      // block of each tile (n_tiles entries)
     uint32_t n_blocks;
     uint32_t pad0;
     uint64_t n_tiles;
@@ -219,10 +218,10 @@ hipError_t launch_ge2_flags(const uint32_t* gstart, uint32_t n_groups, uint32_t 
 // q-gram index
 hipError_t launch_gram_slots(const ColDev* col, uint32_t n, uint32_t q, uint64_t* slots,
                              hipStream_t s);
-// max_windows: the largest L - q + 1 of the column (sizes the LDS scratch)
+// max_windows: the largest L - q + 1 of the column (<= 4096; picks the
+// sort: registers up to 64 windows, a wave's LDS beyond)
 hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const uint64_t* off,
-                             uint32_t* codes, uint32_t* cnt, uint8_t* flags,
-                             unsigned int* d_max_cnt, uint32_t max_windows, hipStream_t s);
+                             uint32_t* codes, uint32_t* cnt, uint8_t* flags, uint32_t max_windows, hipStream_t s);
 
 // character-presence signature of every string of a column
 hipError_t launch_char_sig(const ColDev* col, uint32_t n, uint64_t* sig, hipStream_t s);

@@ -248,16 +248,7 @@ __device__ __forceinline__ uint32_t row_bits(const HB_GLOBAL uint32_t* __restric
 // over the upper triangle: column tj holds ti = 0..tj.
 __device__ inline void decode_tile(const MatchParams& P, uint64_t t, uint32_t* b, uint32_t* ti, uint32_t* tj) {
     const HB_GLOBAL uint64_t* tp = gmem(P.tile_prefix);
-    uint32_t lo = 0;
-    if (P.tile_blk) {
-        lo = gmem(P.tile_blk)[t];
-    } else {
-        uint32_t hi = P.n_blocks - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (tp[mid] <= t) lo = mid; else hi = mid - 1;
-        }
-    }
+    const uint32_t lo = gmem(P.tile_blk)[t];
     *b = lo;
     const uint64_t u = t - tp[lo];
     uint64_t c = (uint64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);

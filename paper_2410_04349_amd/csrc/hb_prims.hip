@@ -389,57 +389,6 @@ __global__ void k_gram_slots(const ColDev* __restrict__ colp, uint32_t n, uint32
     slots[r] = s;
 }
 
-// One thread per row: the row's window codes are insertion-sorted in the
-// thread's own LDS segment of `seg` words (seg odd, so the threads of a wave
-// hit distinct banks), repeats dropped, and the list copied out.  seg = 0
-// (rows too long for LDS): the sort runs in place in the output list.
-__global__ void k_gram_build(const ColDev* __restrict__ colp, uint32_t n, uint32_t q,
-                             const uint64_t* __restrict__ off, uint32_t* __restrict__ codes,
-                             uint32_t* __restrict__ cnt, uint8_t* __restrict__ flags,
-                             unsigned int* __restrict__ max_cnt, uint32_t seg) {
-    extern __shared__ uint32_t gram_lds[];
-    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t out_cnt = 0;
-    if (r < n) {
-        const ColDev c = *colp;
-        uint8_t f = 0;
-        if (bit_valid(c.valid, r)) {
-            const uint8_t* s = c.bytes + c.off[r];
-            const uint32_t L = str_len(c, r);
-            uint32_t* dst = codes + off[r];
-            uint32_t* buf = seg ? gram_lds + (size_t)threadIdx.x * seg : dst;
-            if (L > 0 && L < q) {
-                uint32_t v = 0;
-                for (uint32_t x = 0; x < L; ++x) v = (v << 8) | s[x];
-                dst[0] = (L << 24) | v;
-                out_cnt = 1;
-                f = 1;
-            } else if (L >= q) {
-                const uint32_t nw = L - q + 1;
-                uint32_t v = 0;
-                for (uint32_t x = 0; x + 1 < q; ++x) v = (v << 8) | s[x];
-                const uint32_t mask = (q == 4) ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
-                for (uint32_t w = 0; w < nw; ++w) {
-                    v = ((v << 8) | s[w + q - 1]) & mask;
-                    uint32_t p = w;
-                    while (p > 0 && buf[p - 1] > v) { buf[p] = buf[p - 1]; --p; }
-                    buf[p] = v;
-                }
-                uint32_t u = 0;
-                for (uint32_t w = 0; w < nw; ++w) {
-                    const uint32_t x = buf[w];
-                    if (u == 0 || dst[u - 1] != x) dst[u++] = x;
-                }
-                out_cnt = u;
-            }
-        }
-        cnt[r] = out_cnt;
-        flags[r] = f;
-    }
-    for (int o = 32; o > 0; o >>= 1) out_cnt = max(out_cnt, (uint32_t)__shfl_xor((int)out_cnt, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(max_cnt, out_cnt);
-}
-
 // Rows of at most N windows (N a power of two <= 64): one thread per row
 // holds its window codes in registers, padded with the largest code, sorts
 // them with a bitonic network whose indices are all compile-time (so the
@@ -450,8 +399,7 @@ template <int N>
 __global__ __launch_bounds__(256) void k_gram_build_reg(const ColDev* __restrict__ colp, uint32_t n, uint32_t q,
                                                         const uint64_t* __restrict__ off,
                                                         uint32_t* __restrict__ codes, uint32_t* __restrict__ cnt,
-                                                        uint8_t* __restrict__ flags,
-                                                        unsigned int* __restrict__ max_cnt) {
+                                                        uint8_t* __restrict__ flags) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t out_cnt = 0;
     if (r < n) {
@@ -470,9 +418,25 @@ __global__ __launch_bounds__(256) void k_gram_build_reg(const ColDev* __restrict
             } else if (L >= q) {
                 const uint32_t nw = L - q + 1;   // <= N (the launch checks the longest row)
                 const uint32_t mask = (q == 4) ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
+                // the string's bytes through aligned dword loads (one per
+                // four bytes; the column's buffer is 16-byte aligned and has
+                // 16 bytes of slack at its end), realigned with funnel shifts
+                constexpr int kD = (N + 3 + 3) / 4 + 1;
+                const uintptr_t addr = (uintptr_t)s;
+                const uint32_t* wp = (const uint32_t*)(addr & ~(uintptr_t)3);
+                const uint32_t sh = (uint32_t)(addr & 3);
+                const uint32_t nd = (sh + L + 3) >> 2;   // dwords holding [s, s + L)
+                uint32_t d[kD];
+#pragma unroll
+                for (int i = 0; i < kD; ++i) d[i] = (uint32_t)i < nd ? wp[i] : 0u;
                 uint32_t b[N + 3];
 #pragma unroll
-                for (int x = 0; x < N + 3; ++x) b[x] = (uint32_t)x < L ? s[x] : 0u;
+                for (int i = 0; i + 1 < kD; ++i) {
+                    const uint32_t a = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+                        if (4 * i + y < N + 3) b[4 * i + y] = (uint32_t)(4 * i + y) < L ? (a >> (8 * y)) & 0xFFu : 0u;
+                }
                 uint32_t k[N];
                 uint32_t v = 0;   // the first q - 1 bytes (constant indices keep b in registers)
                 if (q >= 2) v = b[0];
@@ -515,8 +479,6 @@ __global__ __launch_bounds__(256) void k_gram_build_reg(const ColDev* __restrict
         cnt[r] = out_cnt;
         flags[r] = f;
     }
-    for (int o = 32; o > 0; o >>= 1) out_cnt = max(out_cnt, (uint32_t)__shfl_xor((int)out_cnt, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(max_cnt, out_cnt);
 }
 
 __device__ inline void wave_lds_sync() {
@@ -532,14 +494,12 @@ __device__ inline void wave_lds_sync() {
 __global__ __launch_bounds__(256) void k_gram_build_wave(const ColDev* __restrict__ colp, uint32_t n, uint32_t q,
                                                          const uint64_t* __restrict__ off,
                                                          uint32_t* __restrict__ codes, uint32_t* __restrict__ cnt,
-                                                         uint8_t* __restrict__ flags,
-                                                         unsigned int* __restrict__ max_cnt, uint32_t cap) {
+                                                         uint8_t* __restrict__ flags, uint32_t cap) {
     extern __shared__ uint32_t gram_lds[];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t* buf = gram_lds + (size_t)wave * cap;
     const ColDev c = *colp;
     const uint32_t mask = (q == 4) ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
-    uint32_t wave_max = 0;
     for (uint32_t r = blockIdx.x * 4 + wave; r < n; r += gridDim.x * 4) {
         uint32_t out_cnt = 0;
         uint8_t f = 0;
@@ -600,9 +560,7 @@ __global__ __launch_bounds__(256) void k_gram_build_wave(const ColDev* __restric
             cnt[r] = out_cnt;
             flags[r] = f;
         }
-        wave_max = max(wave_max, out_cnt);
     }
-    if (lane == 0) atomicMax(max_cnt, wave_max);
 }
 
 // ------------------------------------------------------------ features
@@ -932,9 +890,9 @@ hipError_t launch_gram_slots(const ColDev* col, uint32_t n, uint32_t q, uint64_t
 }
 
 hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const uint64_t* off,
-                             uint32_t* codes, uint32_t* cnt, uint8_t* flags,
-                             unsigned int* d_max_cnt, uint32_t max_windows, hipStream_t s) {
-    if (max_windows > 64 && max_windows <= 4096) {
+                             uint32_t* codes, uint32_t* cnt, uint8_t* flags, uint32_t max_windows, hipStream_t s) {
+    if (max_windows > 4096) return hipErrorInvalidValue;   // Jaccard attributes hold <= 4096-byte strings
+    if (max_windows > 64) {
         // long rows: a wave per row, sorting in a power-of-two LDS buffer
         uint32_t cap = 64;
         while (cap < max_windows) cap <<= 1;
@@ -945,35 +903,19 @@ hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const ui
             if (e != hipSuccess) return e;
         }
         const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((n + 3) / 4, 65536));
-        k_gram_build_wave<<<grid, 256, lds, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt, cap);
+        k_gram_build_wave<<<grid, 256, lds, s>>>(col, n, q, off, codes, cnt, flags, cap);
         return hipGetLastError();
     }
-    if (max_windows <= 64) {
-        // short rows: a thread per row, sorting in registers
-        const uint32_t grid = (n + 255) / 256;
-        if (max_windows <= 8)
-            k_gram_build_reg<8><<<grid ? grid : 1, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
-        else if (max_windows <= 16)
-            k_gram_build_reg<16><<<grid ? grid : 1, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
-        else if (max_windows <= 32)
-            k_gram_build_reg<32><<<grid ? grid : 1, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
-        else
-            k_gram_build_reg<64><<<grid ? grid : 1, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt);
-        return hipGetLastError();
-    }
-    // LDS segment per thread: the longest row's window count, made odd
-    uint32_t seg = (max_windows < 1 ? 1 : max_windows) | 1u;
-    uint32_t threads = 256;
-    while (threads > 64 && (size_t)threads * seg * 4 > 64 * 1024) threads -= 64;
-    if ((size_t)threads * seg * 4 > 128 * 1024) seg = 0;    // sort in place in HBM instead
-    const size_t lds = (size_t)threads * seg * 4;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gram_build, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    const uint32_t grid = (n + threads - 1) / threads;
-    k_gram_build<<<grid ? grid : 1, threads, lds, s>>>(col, n, q, off, codes, cnt, flags, d_max_cnt, seg);
+    // short rows: a thread per row, sorting in registers
+    const uint32_t grid = std::max<uint32_t>(1, (n + 255) / 256);
+    if (max_windows <= 8)
+        k_gram_build_reg<8><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags);
+    else if (max_windows <= 16)
+        k_gram_build_reg<16><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags);
+    else if (max_windows <= 32)
+        k_gram_build_reg<32><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags);
+    else
+        k_gram_build_reg<64><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags);
     return hipGetLastError();
 }
 

@@ -85,6 +85,38 @@ def test_batch_without_graph_and_learned(hb, ctx, batched):
     hb.hb_batch_destroy(ctx, bid)
 
 
+@pytest.mark.parametrize("form,graph", [("streams", True), ("multi", False), ("persistent", True)])
+def test_batch_each_form_matches_oracle(hb, ctx, batched, form, graph):
+    """Every launch form, forced, on a mix of the batched jobs, a two-key
+    job and a long-title job (edit-distance patterns past 64 bytes, the
+    Myers state in LDS for the queue kernels, in registers for the
+    per-partition launches)."""
+    jobs, want, ids = batched
+    print(f"[gpu-case] forced form {form}, graph {graph}", flush=True)
+    extra = [workloads.random_small(4100, n=400, n_keys=2), workloads.long_titles_5m(n=3000)]
+    extra_want = [oracle.blocking(r, ru, threads=16) for r, ru in extra]
+    extra_ids = load_jobs(hb, ctx, extra)
+    sel = list(range(0, len(jobs), 4))
+    bid = hb.hb_batch_create(ctx, [ids[k] for k in sel] + extra_ids, "heuristic", graph=graph, form=form)
+    info = hb.hb_batch_info(ctx, bid)
+    assert info["form"] == form
+    hb.hb_batch_run(ctx, bid)
+    for x, k in enumerate(sel):
+        assert np.array_equal(hb.hb_batch_result(ctx, bid, x), want[k]), (form, k)
+    for x in range(len(extra)):
+        assert np.array_equal(hb.hb_batch_result(ctx, bid, len(sel) + x), extra_want[x]), (form, "extra", x)
+    hb.hb_batch_destroy(ctx, bid)
+    for rid, _ in extra_ids:
+        hb.hb_release_relation(ctx, rid)
+
+
+def test_batch_forced_form_with_autotune_rejected(hb, ctx, batched):
+    _, _, ids = batched
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_batch_create(ctx, ids[:2], "heuristic", graph=False, autotune=True, form="multi")
+    assert e.value.status == hb.HB_ERR_INVALID_ARG
+
+
 def test_batch_multi_key_and_regrow(hb, ctx):
     print("[gpu-case] multi-key jobs and output regrow", flush=True)
     jobs = [workloads.random_small(3000 + s, n=300, n_keys=1 + s % 3) for s in range(6)]

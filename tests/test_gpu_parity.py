@@ -172,6 +172,50 @@ def test_jaccard_short_rows(hb, ctx, q, max_len):
         assert np.array_equal(got, want), (num, den)
 
 
+def test_block_size_sweep(hb, ctx):
+    """Blocks of every size around the 16-row batch and 64-row tile edges
+    (and one of 200 rows: a 4 x 4 tile triangle with a ragged last tile),
+    placed in shuffled key order: every pair of a block, or just those that
+    pass the filters, against the oracle."""
+    show("block size sweep")
+    r = np.random.default_rng(7)
+    sizes = [1, 2, 3, 15, 16, 17, 31, 32, 33, 47, 48, 49, 63, 64, 65, 79, 80, 81, 127, 128, 129, 200]
+    keys = np.concatenate([np.full(n, 1000 + k) for k, n in enumerate(sizes)])
+    r.shuffle(keys)
+    n = len(keys)
+    strings = [bytes(r.integers(97, 100, size=int(r.integers(4, 12))).astype(np.uint8)) for _ in range(n)]
+    ints = [int(v) for v in r.integers(0, 20, size=n)]
+    rel = Relation([string_column("s", strings), int_column("k", keys.tolist(), CATEGORICAL),
+                    int_column("i", ints)], n)
+    for rules in ([[Pred(EQ, 1)]],
+                  [[Pred(EQ, 1), Pred(ED, 0, k=2)], [Pred(EQ, 1), Pred(ABSDIFF, 2, d=1)]],
+                  [[Pred(EQ, 1), Pred(JACCARD, 0, q=2, num=1, den=2), Pred(ABSDIFF, 2, d=5)]]):
+        want = oracle.blocking(rel, rules)
+        got, n_cand = run(hb, ctx, rel, rules, "given")
+        assert n_cand == sum(m * (m - 1) // 2 for m in sizes)
+        assert np.array_equal(got, want), rules
+
+
+def test_degenerate_partitions(hb, ctx):
+    """No block of two rows (every key distinct), a key that is always
+    missing, and a one-row relation: no candidates and an empty result."""
+    show("degenerate partitions")
+    strings = [b"abc", b"abd", b"xyz", b"abc"]
+    cases = [
+        Relation([string_column("s", strings), int_column("k", [1, 2, 3, 4], CATEGORICAL)], 4),
+        Relation([string_column("s", strings), int_column("k", [None] * 4, CATEGORICAL)], 4),
+        Relation([string_column("s", strings[:1]), int_column("k", [5], CATEGORICAL)], 1),
+    ]
+    for rel in cases:
+        for plan in ("given", "heuristic"):
+            rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+            rs = hb.hb_compile_rules(ctx, rid, [[Pred(EQ, 1), Pred(ED, 0, k=1)]])
+            assert hb.hb_partition(ctx, rid, rs) == 0
+            out = hb.hb_match(ctx, rid, rs, plan)
+            assert len(out) == 0
+            hb.hb_release_relation(ctx, rid)
+
+
 def test_plain_scaled_several_tiles(hb, ctx):
     show("plain_1m scaled to 40k")
     rel, rules = workloads.plain_1m(n=40_000)
