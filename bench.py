@@ -345,6 +345,12 @@ def main():
             raise SystemExit("learned and heuristic plans disagree")
     match_ms = prof["match"]["ms_total"] / max(1, prof["match"]["launches"])
 
+    # blocking quality against the generator's duplicate links (untimed)
+    from gen import true_pairs
+    from paper_2410_04349_amd.quality import quality
+    qual = quality(out[:n_match].cpu().numpy().view(np.uint64), true_pairs(rel), rel.n_rows)
+    log(f"[bench] quality: {qual}")
+
     # algorithmic work of the dominant kernel: one instrumented pass (untimed)
     rid = hb.hb_load_relation(ctx, cols, rel.n_rows, on_device=True)
     rs = hb.hb_compile_rules(ctx, rid, rules)
@@ -375,6 +381,7 @@ def main():
         "kernels_ms_per_step": {k: v["ms_total"] / args.steps for k, v in prof.items()},
         "compare": compare,
         "cost_model": learned,
+        "quality": qual,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s (int32 lane-ops)",
                      "frac": achieved / peak, "traffic": recorded_traffic(args.workload, args.plan),
                      "traffic_unit": "HBM bytes per launch", "kernel": "k_match",

@@ -93,6 +93,43 @@ class Relation:
         return Relation(cols, len(rows), dup)
 
 
+def entity_ids(rel: Relation) -> np.ndarray:
+    """Ground-truth entity of every row: a base tuple is its own entity and
+    a generated duplicate belongs to its source's (links followed to the
+    root).  Relations without duplicate links give one entity per row."""
+    n = rel.n_rows
+    ent = np.arange(n, dtype=np.int64)
+    if rel.dup_src is None:
+        return ent
+    src = np.asarray(rel.dup_src, dtype=np.int64)
+    for _ in range(64):   # links point at earlier generations; a few hops reach the root
+        nxt = np.where(src[ent] >= 0, src[ent], ent)
+        if np.array_equal(nxt, ent):
+            break
+        ent = nxt
+    return ent
+
+
+def true_pairs(rel: Relation) -> np.ndarray:
+    """Every pair (i, j), i < j, of rows of one ground-truth entity, packed
+    (i << 32) | j and sorted (the layout of the library's result)."""
+    ent = entity_ids(rel)
+    order = np.lexsort((np.arange(len(ent)), ent))   # by entity, rows ascending within
+    e = ent[order]
+    starts = np.flatnonzero(np.r_[True, e[1:] != e[:-1]])
+    sizes = np.diff(np.r_[starts, len(e)])
+    out = []
+    for m in np.unique(sizes[sizes >= 2]):   # every group of one size at once
+        base = starts[sizes == m]
+        a, b = np.triu_indices(int(m), k=1)
+        ra = order[base[:, None] + a[None, :]].astype(np.uint64).ravel()
+        rb = order[base[:, None] + b[None, :]].astype(np.uint64).ravel()
+        out.append((ra << np.uint64(32)) | rb)
+    if not out:
+        return np.zeros(0, dtype=np.uint64)
+    return np.sort(np.concatenate(out))
+
+
 @dataclass(frozen=True)
 class Pred:
     op: str
