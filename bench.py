@@ -198,6 +198,9 @@ def run_batched(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--strategies", action="store_true",
+                    help="also time the comparison orders (given, cheapest, selective, random_preds, "
+                         "random_rules) on the same workload; outputs must equal the timed plan's")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plan", default="learned", choices=["learned", "heuristic", "given"])
@@ -345,6 +348,20 @@ def main():
             raise SystemExit("learned and heuristic plans disagree")
     match_ms = prof["match"]["ms_total"] / max(1, prof["match"]["launches"])
 
+    strategies = None
+    if args.strategies:
+        strategies = {}
+        out_s = torch.empty_like(out)
+        for sname in ("given", "heuristic", "cheapest", "selective", "random_preds", "random_rules"):
+            c_s, m_s, dt_s, prof_s = timed(sname, out_s)
+            same = m_s == n_match and bool(torch.equal(out_s[:m_s], out[:n_match]))
+            if not same:
+                raise SystemExit(f"plan {sname} disagrees with {args.plan}")
+            strategies[sname] = {"ms_per_step": dt_s * 1000.0 / args.steps,
+                                 "match_kernel_ms": prof_s["match"]["ms_total"] / max(1, prof_s["match"]["launches"]),
+                                 "bit_exact": same}
+        log(f"[bench] strategies: {strategies}")
+
     # blocking quality against the generator's duplicate links (untimed)
     from gen import true_pairs
     from paper_2410_04349_amd.quality import quality
@@ -382,6 +399,7 @@ def main():
         "compare": compare,
         "cost_model": learned,
         "quality": qual,
+        "strategies": strategies,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s (int32 lane-ops)",
                      "frac": achieved / peak, "traffic": recorded_traffic(args.workload, args.plan),
                      "traffic_unit": "HBM bytes per launch", "kernel": "k_match",

@@ -174,8 +174,27 @@ hb_status hb_partition(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id,
  *                      order; the exact checks stay in the heuristic order.
  *                      Blocks of fewer than 16 tuples keep the heuristic
  *                      plan.  Built on the device (no host round trip).
- *                      Needs a cost model (HB_ERR_STATE otherwise). */
-typedef enum { HB_PLAN_GIVEN = 0, HB_PLAN_HEURISTIC = 1, HB_PLAN_LEARNED = 2 } hb_plan;
+ *                      Needs a cost model (HB_ERR_STATE otherwise).
+ * The ordering strategies the paper's experiments compare against
+ * (Section 6, "Tests on EPG"), for studies; each is output-neutral:
+ *   HB_PLAN_CHEAPEST     the execution tree with predicates ranked cheapest
+ *                        first ("COrder");
+ *   HB_PLAN_SELECTIVE    ranked most selective (lowest sp) first ("SOrder");
+ *   HB_PLAN_RANDOM_PREDS the heuristic path with each rule's predicates in a
+ *                        random order ("noPO");
+ *   HB_PLAN_RANDOM_RULES the heuristic path with the rules in a random order
+ *                        ("noRO").
+ * The random orders are drawn from a fixed seed (splitmix64 of the rule
+ * set's first predicate ids), so repeated calls evaluate identically. */
+typedef enum {
+    HB_PLAN_GIVEN = 0,
+    HB_PLAN_HEURISTIC = 1,
+    HB_PLAN_LEARNED = 2,
+    HB_PLAN_CHEAPEST = 3,
+    HB_PLAN_SELECTIVE = 4,
+    HB_PLAN_RANDOM_PREDS = 5,
+    HB_PLAN_RANDOM_RULES = 6
+} hb_plan;
 
 /* Evaluate the rule set on every candidate pair and return Ca(D): packed
  * uint64 (i << 32) | j with i < j, sorted ascending, each pair once.
@@ -207,6 +226,13 @@ hb_status hb_ruleset_buckets(hb_ctx* ctx, uint32_t ruleset_id, uint32_t pred, ui
 hb_status hb_epg_path(uint32_t n_preds, const double* sp, const double* cost, uint32_t n_rules,
                       const uint32_t* rule_len, const uint32_t* rule_preds, uint32_t* out_rules,
                       uint32_t* out_preds, uint32_t* out_len);
+
+/* Pure host: as hb_epg_path, for any plan but HB_PLAN_LEARNED (which is
+ * chosen per block on the device): the path hb_match evaluates for a rule
+ * set with these estimates.  HB_ERR_INVALID_ARG for an unknown plan. */
+hb_status hb_plan_path(uint32_t plan, uint32_t n_preds, const double* sp, const double* cost, uint32_t n_rules,
+                       const uint32_t* rule_len, const uint32_t* rule_preds, uint32_t* out_rules,
+                       uint32_t* out_preds, uint32_t* out_len);
 
 /* Kernel timing: when enabled, HIP events bracket each kernel launch of the
  * named step on the context stream.  Names: "match", "partition_sort",

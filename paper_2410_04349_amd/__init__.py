@@ -36,13 +36,16 @@ HB_PLAN_LEARNED = 2
 
 _COLTYPE = {"string": 0, "categorical": 1, "int64": 2}
 _OP = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3}
-_PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC, "learned": HB_PLAN_LEARNED}
+HB_PLAN_CHEAPEST, HB_PLAN_SELECTIVE, HB_PLAN_RANDOM_PREDS, HB_PLAN_RANDOM_RULES = 3, 4, 5, 6
+_PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC, "learned": HB_PLAN_LEARNED,
+         "cheapest": HB_PLAN_CHEAPEST, "selective": HB_PLAN_SELECTIVE,
+         "random_preds": HB_PLAN_RANDOM_PREDS, "random_rules": HB_PLAN_RANDOM_RULES}
 
 EXPORTED = [
     "hb_create", "hb_destroy", "hb_last_error", "hb_version", "hb_load_relation", "hb_load_relation_async",
     "hb_release_relation",
     "hb_compile_rules", "hb_partition", "hb_match", "hb_ruleset_estimates", "hb_ruleset_buckets",
-    "hb_epg_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
+    "hb_epg_path", "hb_plan_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
     "hb_match_work", "hb_costmodel_init", "hb_costmodel_set_params", "hb_costmodel_get_params",
     "hb_costmodel_train", "hb_costmodel_predict", "hb_costmodel_trace", "hb_costmodel_adam_step",
     "hb_log_collect", "hb_batch_create", "hb_batch_run", "hb_batch_result", "hb_batch_info_get",
@@ -129,6 +132,7 @@ def _load_lib():
         "hb_ruleset_estimates": (I32, [P, U32, P, P, U32, ctypes.POINTER(U32)]),
         "hb_ruleset_buckets": (I32, [P, U32, U32, P, ctypes.POINTER(U64)]),
         "hb_epg_path": (I32, [U32, P, P, U32, P, P, P, P, ctypes.POINTER(U32)]),
+        "hb_plan_path": (I32, [U32, U32, P, P, U32, P, P, P, P, ctypes.POINTER(U32)]),
         "hb_profile_enable": (I32, [P, ctypes.c_int]),
         "hb_profile_query": (I32, [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64)]),
         "hb_profile_reset": (I32, [P]),
@@ -349,6 +353,12 @@ def hb_ruleset_buckets(ctx: Context, ruleset_id: int, pred: int) -> Tuple[np.nda
 
 def hb_epg_path(sp: Sequence[float], cost: Sequence[float], rules: Sequence[Sequence[int]]):
     """Pure host: [(rule, [pred ids])] in sequential-path order."""
+    return hb_plan_path("heuristic", sp, cost, rules)
+
+
+def hb_plan_path(plan, sp: Sequence[float], cost: Sequence[float], rules: Sequence[Sequence[int]]):
+    """Pure host: the path of `plan` (any but "learned"): [(rule, [pred ids])]."""
+    pl = _PLAN[plan] if isinstance(plan, str) else int(plan)
     sp = np.ascontiguousarray(sp, dtype=np.float64)
     cost = np.ascontiguousarray(cost, dtype=np.float64)
     lens = np.array([len(r) for r in rules], dtype=np.uint32)
@@ -358,12 +368,12 @@ def hb_epg_path(sp: Sequence[float], cost: Sequence[float], rules: Sequence[Sequ
     out_rules = np.zeros(max(1, len(rules)), dtype=np.uint32)
     out_preds = np.zeros(max(1, int(lens.sum())), dtype=np.uint32)
     n = ctypes.c_uint32()
-    st = _lib.hb_epg_path(len(sp), ctypes.c_void_p(sp.ctypes.data), ctypes.c_void_p(cost.ctypes.data),
-                          len(rules), ctypes.c_void_p(lens.ctypes.data), ctypes.c_void_p(flat.ctypes.data),
-                          ctypes.c_void_p(out_rules.ctypes.data), ctypes.c_void_p(out_preds.ctypes.data),
-                          ctypes.byref(n))
+    st = _lib.hb_plan_path(pl, len(sp), ctypes.c_void_p(sp.ctypes.data), ctypes.c_void_p(cost.ctypes.data),
+                           len(rules), ctypes.c_void_p(lens.ctypes.data), ctypes.c_void_p(flat.ctypes.data),
+                           ctypes.c_void_p(out_rules.ctypes.data), ctypes.c_void_p(out_preds.ctypes.data),
+                           ctypes.byref(n))
     if st != HB_OK:
-        raise HbError(st, "hb_epg_path failed")
+        raise HbError(st, "hb_plan_path failed")
     res = []
     o = 0
     for r in out_rules[: len(rules)]:

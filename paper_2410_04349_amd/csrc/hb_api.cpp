@@ -1023,9 +1023,30 @@ static void log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t sample
 static const double kOpBase[8] = {1, 4, 3, 12, 12, 2, 4, 4};
 static const double kOpUnit[8] = {0, 0, 0, 0, 0, 1, 17, 3};
 
-std::vector<PathRule> plan_path(const RuleSet& rs, int plan) {
-    return plan == HB_PLAN_GIVEN ? given_path(rs.rules) : epg_path(rs.sp, rs.cost, rs.rules);
+// Seed of the random-order strategies: the rule set's predicate ids mixed
+// together (fixed per rule set, so repeated calls evaluate identically).
+static uint64_t strategy_seed(const std::vector<std::vector<uint32_t>>& rules) {
+    uint64_t h = 0x48425053ull;
+    for (const auto& r : rules)
+        for (uint32_t p : r) h = h * 0x100000001B3ull + p + 1;
+    return h;
 }
+
+static std::vector<PathRule> strategy_path(const std::vector<double>& sp, const std::vector<double>& cost,
+                                           const std::vector<std::vector<uint32_t>>& rules, int plan) {
+    switch (plan) {
+    case HB_PLAN_GIVEN: return given_path(rules);
+    case HB_PLAN_CHEAPEST: return epg_path(sp, cost, rules, Rank::kCheapest);
+    case HB_PLAN_SELECTIVE: return epg_path(sp, cost, rules, Rank::kMostSelective);
+    case HB_PLAN_RANDOM_PREDS: return shuffled_path(epg_path(sp, cost, rules), true, false, strategy_seed(rules));
+    case HB_PLAN_RANDOM_RULES: return shuffled_path(epg_path(sp, cost, rules), false, true, strategy_seed(rules));
+    default: return epg_path(sp, cost, rules);   // heuristic; the learned plan starts from it
+    }
+}
+
+std::vector<PathRule> plan_path(const RuleSet& rs, int plan) { return strategy_path(rs.sp, rs.cost, rs.rules, plan); }
+
+bool valid_plan(int plan) { return plan >= HB_PLAN_GIVEN && plan <= HB_PLAN_RANDOM_RULES; }
 
 bool key_plan(Ctx* c, Relation& rel, RuleSet& rs, int plan, const std::vector<PathRule>& path, size_t ka,
               KeyPlan& kp, bool count, uint64_t* n_fallback) {
@@ -1161,8 +1182,7 @@ static void match_work(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, hb_wor
     Relation& rel = get_rel(c, rel_id);
     RuleSet& rs = get_rs(c, rs_id, rel_id);
     if (!ws) fail(HB_ERR_INVALID_ARG, "NULL stats");
-    if (plan != HB_PLAN_GIVEN && plan != HB_PLAN_HEURISTIC && plan != HB_PLAN_LEARNED)
-        fail(HB_ERR_INVALID_ARG, "unknown plan");
+    if (!valid_plan(plan)) fail(HB_ERR_INVALID_ARG, "unknown plan");
     if (!rs.partitioned) fail(HB_ERR_STATE, "hb_partition must run before hb_match_work");
     run_match(c, rel, rs, plan, ws);
 }
@@ -1172,8 +1192,7 @@ static void match(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, uint64_t* o
     Relation& rel = get_rel(c, rel_id);
     RuleSet& rs = get_rs(c, rs_id, rel_id);
     if (!n_pairs) fail(HB_ERR_INVALID_ARG, "NULL n_pairs");
-    if (plan != HB_PLAN_GIVEN && plan != HB_PLAN_HEURISTIC && plan != HB_PLAN_LEARNED)
-        fail(HB_ERR_INVALID_ARG, "unknown plan");
+    if (!valid_plan(plan)) fail(HB_ERR_INVALID_ARG, "unknown plan");
     if (!rs.partitioned) fail(HB_ERR_STATE, "hb_partition must run before hb_match");
     if (!(rs.has_result && rs.result_plan == plan)) run_match(c, rel, rs, plan);
     *n_pairs = rs.n_result;
@@ -1319,7 +1338,15 @@ hb_status hb_ruleset_buckets(hb_ctx* ctx, uint32_t ruleset_id, uint32_t pred, ui
 hb_status hb_epg_path(uint32_t n_preds, const double* sp, const double* cost, uint32_t n_rules,
                       const uint32_t* rule_len, const uint32_t* rule_preds, uint32_t* out_rules, uint32_t* out_preds,
                       uint32_t* out_len) {
+    return hb_plan_path(HB_PLAN_HEURISTIC, n_preds, sp, cost, n_rules, rule_len, rule_preds, out_rules, out_preds,
+                        out_len);
+}
+
+hb_status hb_plan_path(uint32_t plan, uint32_t n_preds, const double* sp, const double* cost, uint32_t n_rules,
+                       const uint32_t* rule_len, const uint32_t* rule_preds, uint32_t* out_rules, uint32_t* out_preds,
+                       uint32_t* out_len) {
     if (!sp || !cost || !rule_len || !rule_preds || !out_rules || !out_preds || !out_len) return HB_ERR_INVALID_ARG;
+    if (!hb::valid_plan((int)plan) || plan == HB_PLAN_LEARNED) return HB_ERR_INVALID_ARG;
     for (uint32_t p = 0; p < n_preds; ++p)
         if (!(cost[p] > 0.0) || !(sp[p] >= 0.0 && sp[p] <= 1.0)) return HB_ERR_INVALID_ARG;
     try {
@@ -1333,7 +1360,7 @@ hb_status hb_epg_path(uint32_t n_preds, const double* sp, const double* cost, ui
             }
         }
         std::vector<double> vsp(sp, sp + n_preds), vc(cost, cost + n_preds);
-        auto path = hb::epg_path(vsp, vc, rules);
+        auto path = hb::strategy_path(vsp, vc, rules, (int)plan);
         uint32_t w = 0;
         for (uint32_t r = 0; r < path.size(); ++r) {
             out_rules[r] = path[r].rule;

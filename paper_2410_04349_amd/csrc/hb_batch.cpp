@@ -199,8 +199,7 @@ static void capture(Ctx* c, Batch& B) {
 static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, uint32_t flags, uint32_t* id) {
     if (!id || (!jobs && n_jobs)) fail(HB_ERR_INVALID_ARG, "NULL argument");
     if (n_jobs == 0 || n_jobs > HB_MAX_BATCH_JOBS) fail(HB_ERR_INVALID_ARG, "n_jobs must be in [1, HB_MAX_BATCH_JOBS]");
-    if (plan != HB_PLAN_GIVEN && plan != HB_PLAN_HEURISTIC && plan != HB_PLAN_LEARNED)
-        fail(HB_ERR_INVALID_ARG, "unknown plan");
+    if (!valid_plan(plan)) fail(HB_ERR_INVALID_ARG, "unknown plan");
     if (flags & ~(uint32_t)(HB_BATCH_GRAPH | HB_BATCH_AUTOTUNE | HB_BATCH_FORM_MASK))
         fail(HB_ERR_INVALID_ARG, "unknown batch flags");
     if ((flags & HB_BATCH_AUTOTUNE) && (flags & HB_BATCH_FORM_MASK))

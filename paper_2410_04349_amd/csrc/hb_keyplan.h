@@ -37,6 +37,7 @@ struct KeyPlan {
 // The evaluation path of a plan kind (given order or the Section 4.2 plan;
 // the learned plan starts from the latter).
 std::vector<PathRule> plan_path(const RuleSet& rs, int plan);
+bool valid_plan(int plan);   // an hb_plan value
 
 // Builds key `ka`'s partition plan; false if no rule can hold there.
 // Learned plans add the blocks kept on the heuristic plan for structural

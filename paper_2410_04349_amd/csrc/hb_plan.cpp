@@ -2,6 +2,10 @@
 //
 // Input: per distinct predicate an estimated selectivity sp (probability of
 // being satisfied) and a normalised cost; rules as lists of predicate ids.
+// The ranking of step 1 can be swapped for cheapest-first or most-selective-
+// first, and the resulting path's predicate or rule order shuffled: the
+// ordering strategies the paper's experiments compare EPG with.
+//
 // Output: the sequential execution path of Section 5.1 -- rules in the
 // order a depth-first walk of the execution tree reaches their leaves, each
 // with its predicates in root-to-leaf order.
@@ -47,10 +51,12 @@ std::vector<PathRule> given_path(const std::vector<std::vector<uint32_t>>& rules
 }
 
 std::vector<PathRule> epg_path(const std::vector<double>& sp, const std::vector<double>& cost,
-                               const std::vector<std::vector<uint32_t>>& rules) {
+                               const std::vector<std::vector<uint32_t>>& rules, Rank by) {
     const size_t np = sp.size();
-    std::vector<double> ce(np);
-    for (size_t p = 0; p < np; ++p) ce[p] = (1.0 - sp[p]) / cost[p];
+    std::vector<double> ce(np);   // larger ranks first
+    for (size_t p = 0; p < np; ++p)
+        ce[p] = by == Rank::kCheapest ? -cost[p] : by == Rank::kMostSelective ? 1.0 - sp[p]
+                                                                              : (1.0 - sp[p]) / cost[p];
     std::vector<uint32_t> order(np);
     for (size_t p = 0; p < np; ++p) order[p] = (uint32_t)p;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return ce[a] > ce[b]; });
@@ -109,6 +115,24 @@ std::vector<PathRule> epg_path(const std::vector<double>& sp, const std::vector<
     };
     visit(0);
     return out;
+}
+
+std::vector<PathRule> shuffled_path(std::vector<PathRule> path, bool shuffle_preds, bool shuffle_rules,
+                                    uint64_t seed) {
+    uint64_t st = seed;
+    auto next = [&st]() {   // splitmix64 (Steele, Lea and Flood)
+        uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto shuffle = [&next](auto& v) {   // Fisher-Yates
+        for (size_t i = v.size(); i > 1; --i) std::swap(v[i - 1], v[next() % i]);
+    };
+    if (shuffle_preds)
+        for (PathRule& pr : path) shuffle(pr.preds);
+    if (shuffle_rules) shuffle(path);
+    return path;
 }
 
 }  // namespace hb

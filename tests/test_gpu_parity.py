@@ -172,6 +172,19 @@ def test_jaccard_short_rows(hb, ctx, q, max_len):
         assert np.array_equal(got, want), (num, den)
 
 
+@pytest.mark.parametrize("plan", ["cheapest", "selective", "random_preds", "random_rules"])
+def test_every_strategy_matches_oracle(hb, ctx, plan):
+    """The comparison strategies reorder evaluation only: bit-exact results."""
+    show(f"strategy {plan}")
+    for seed in range(4):
+        rel, rules = workloads.random_small(seed + 500)
+        got, _ = run(hb, ctx, rel, rules, plan)
+        assert np.array_equal(got, oracle.blocking(rel, rules)), seed
+    rel, rules = workloads.plain_1m(n=20_000)
+    got, _ = run(hb, ctx, rel, rules, plan)
+    assert np.array_equal(got, oracle.blocking(rel, rules, threads=16))
+
+
 def test_block_size_sweep(hb, ctx):
     """Blocks of every size around the 16-row batch and 64-row tile edges
     (and one of 200 rows: a 4 x 4 tile triangle with a ragged last tile),
