@@ -390,8 +390,8 @@ typedef struct {
     uint32_t n_jobs, n_partitions;
     uint64_t work_items;        /* 64 x 64 tiles in the queue */
     int32_t form;               /* 0: each partition's own launch on 4 concurrent streams;
-                                   1: one workgroup per tile over the whole queue;
-                                   2: persistent grid (grid workgroups taking grab tiles per atomic) */
+                                   1: one one-wave workgroup per 16-row batch of a tile over the whole queue;
+                                   2: persistent grid (grid workgroups taking grab batches per atomic) */
     uint32_t grid, grab, occupancy, lds_bytes;
     int32_t graph;              /* 1 if captured */
     uint32_t n_tuned;           /* candidates timed by HB_BATCH_AUTOTUNE */

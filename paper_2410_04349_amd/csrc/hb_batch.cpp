@@ -1,8 +1,8 @@
 // Batched matching: many (relation, rule set) jobs matched together over
 // one queue of all their key partitions' tiles, heaviest partitions first.
 // Launch forms: every partition's own launch spread over concurrent
-// streams, one workgroup per tile over the whole queue, or a persistent
-// work-stealing grid; the form (and the grid's grab size and occupancy) can
+// streams, one one-wave workgroup per 16-row batch of a tile over the whole
+// queue, or a persistent work-stealing grid; the form (and the grid's grab size and occupancy) can
 // be picked by timing them on the batch's first items, and the batch's
 // device work can be captured in a HIP graph and replayed.
 #include <hip/hip_runtime.h>

@@ -1,23 +1,27 @@
 // The pair-evaluation kernel of libhb (gfx950).
 //
-// Work unit: a 64 x 64 tile (i-tile, j-tile) of the upper triangle of one
-// block of a key partition.  A workgroup of four waves stages the j-tile's
-// compact feature columns (values, lengths, set sizes, signatures) in LDS
-// once; each wave then takes rows i = i0 + w, i0 + w + 4, ..., so tuple t_i
-// is uniform across the wave (its features and the plan are read with
-// scalar loads) and its 64 lanes hold 64 candidates t_j.
+// Work unit: a 16-row batch of a 64 x 64 tile (i-tile, j-tile) of the upper
+// triangle of one block of a key partition, run by a one-wave workgroup
+// (four per tile).  The batch's 16 tuples t_i are uniform across the wave:
+// their feature columns (values, lengths, set sizes, signatures) and the
+// plan are read with scalar loads; each of the 64 lanes holds one candidate
+// t_j and reads its features from the same columns.  A lane keeps 16-bit
+// masks (bit r: the pair (row r, its t_j)) of the pairs still alive in the
+// current rule and of those already matched.
 //
-// Every lane walks the sequential execution path (Section 5.1) for its pair
-// (t_i, t_j): steps in plan order, a rule-end checkpoint that reports a
-// witness (Section 2, "Blocking"), and a wave-uniform jump to the
-// checkpoint once no lane can still satisfy the current rule.  Results of
-// the expensive predicates are reused across rules through per-attribute
-// caches of the edit distance and of the q-gram intersection size; cheap
-// steps are recomputed, which costs less than bookkeeping on a SIMD.  Within a rule the plan runs exact,
-// cheap necessary-condition filters before the expensive predicates
-// (edit distance, Jaccard, string equality), so the expensive code runs for
-// a wave only when some lane passed all of the rule's filters.  Matched lanes
-// are compacted with a ballot, one atomic per wave-row.
+// The wave walks the sequential execution path (Section 5.1) for its 1,024
+// pairs: steps in plan order, a rule-end checkpoint that records witnesses
+// (Section 2, "Blocking"), and a wave-uniform jump to the checkpoint once no
+// pair of the batch can still satisfy the current rule.  Within a rule the
+// plan runs exact, cheap necessary-condition filters first (value
+// predicates, length and character-signature bounds for edit distance, the
+// q-gram signature bound for Jaccard), one vector instruction sequence per
+// row appending the row's result bit with an add-with-carry; the expensive
+// predicates (edit distance, Jaccard, string equality) then run row by row
+// only where some lane passed every filter of the rule.  Predicates shared
+// by several rules are evaluated again in each (a cache cost more registers
+// than it saved).  Matched lanes are compacted with a ballot, one atomic
+// per wave-row.
 //
 // Edit distance: Myers' bit-parallel algorithm in Hyyro's formulation for
 // the Levenshtein distance (pattern = t_i, one bit per pattern byte, the
