@@ -198,6 +198,9 @@ def run_batched(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--host-io", action="store_true",
+                    help="also time steps whose input comes from pinned host memory and whose result goes "
+                         "back to the host (the PCIe-inclusive rate; never the reported value)")
     ap.add_argument("--strategies", action="store_true",
                     help="also time the comparison orders (given, cheapest, selective, random_preds, "
                          "random_rules) on the same workload; outputs must equal the timed plan's")
@@ -348,6 +351,39 @@ def main():
             raise SystemExit("learned and heuristic plans disagree")
     match_ms = prof["match"]["ms_total"] / max(1, prof["match"]["launches"])
 
+    pcie = None
+    if args.host_io:
+        # the same relation in pinned host memory; the result copied back each step
+        from gen import Column
+        def pinned(a):
+            return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).pin_memory().numpy()
+        hcols = [Column(c.name, c.type, offsets=pinned(c.offsets), data=pinned(c.data), values=pinned(c.values),
+                        valid=pinned(c.valid)) for c in rel.columns]
+        in_bytes = sum(sum(a.nbytes for a in (c.offsets, c.data, c.values, c.valid) if a is not None) for c in hcols)
+
+        def host_step():
+            rid = hb.hb_load_relation(ctx, hcols, rel.n_rows, on_device=False)
+            rs = hb.hb_compile_rules(ctx, rid, rules)
+            nc = hb.hb_partition(ctx, rid, rs)
+            res = hb.hb_match(ctx, rid, rs, args.plan)
+            hb.hb_release_relation(ctx, rid)
+            return nc, res
+
+        for _ in range(args.warmup):
+            host_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            nc, res = host_step()
+        torch.cuda.synchronize()
+        dt_h = time.perf_counter() - t0
+        same = np.array_equal(res, out[:n_match].cpu().numpy().view(np.uint64))
+        if not same:
+            raise SystemExit("host-input result disagrees with the device-input result")
+        pcie = {"value": nc * args.steps / dt_h, "unit": "pairs/s", "ms_per_step": dt_h * 1000.0 / args.steps,
+                "input_bytes": int(in_bytes), "output_bytes": int(res.nbytes), "bit_exact": same}
+        log(f"[bench] host input and output: {pcie}")
+
     strategies = None
     if args.strategies:
         strategies = {}
@@ -400,6 +436,7 @@ def main():
         "cost_model": learned,
         "quality": qual,
         "strategies": strategies,
+        "pcie_inclusive": pcie,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s (int32 lane-ops)",
                      "frac": achieved / peak, "traffic": recorded_traffic(args.workload, args.plan),
                      "traffic_unit": "HBM bytes per launch", "kernel": "k_match",

@@ -252,7 +252,10 @@ static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
                                  g.flags.as<uint8_t>(), max_windows, c->stream);
     });
     g.max_cnt = max_windows;
-    g.sig.alloc(c, sizeof(uint64_t) * n);
+    // long rows get a 256-bit signature: with ~100 codes a 64-bit one is
+    // mostly ones and the Jaccard filter bound barely prunes
+    g.sig_words = max_windows > 64 ? kLongSigWords : 1;
+    g.sig.alloc(c, sizeof(uint64_t) * n * g.sig_words);
     HB_HIP(launch_gram_sig(g.dev(), n, g.sig.as<uint64_t>(), c->stream));
     auto res = rel.grams.emplace(key, std::move(g));
     return res.first->second;
@@ -781,9 +784,14 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
         gp.csig[x] = char_signature(c, rel, R.str_attr[x]);
         ed_words = std::max<uint32_t>(ed_words, (rel.cols[R.str_attr[x]].max_len + 63) / 64);
     }
+    uint32_t gram_cols = 0;   // f64 columns of the q-gram signatures
     for (size_t x = 0; x < R.gram_key.size(); ++x) {
         GramIndex& g = gram_index(c, rel, R.gram_key[x].first, R.gram_key[x].second);
         m.gram[x] = g.dev();
+        m.gram[x].sig_col = gram_cols;
+        gp.gram_words[x] = g.sig_words;
+        gp.gram_col[x] = gram_cols;
+        gram_cols += g.sig_words;
         const Column& col = rel.cols[g.attr];
         gp.gram_valid[x] = col.valid.size() ? col.valid.as<uint8_t>() : nullptr;
         gp.gram_cnt[x] = g.cnt.as<uint32_t>();
@@ -791,7 +799,7 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
         gp.gsig[x] = g.sig.as<uint64_t>();
     }
     m.ed_words = R.any_ed ? ed_words : 0;   // 0: no edit-distance predicate
-    const uint32_t n64 = m.n_int + m.n_str + m.n_gram, n32 = 2 + m.n_str + 2 * m.n_gram;
+    const uint32_t n64 = m.n_int + m.n_str + gram_cols, n32 = 2 + m.n_str + 2 * m.n_gram;
     const uint64_t stride = (uint64_t)P.n_valid + kTile;
     gp.stride = stride;
     kp.f64.alloc(c, sizeof(uint64_t) * stride * std::max<uint32_t>(n64, 1));

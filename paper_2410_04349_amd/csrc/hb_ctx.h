@@ -73,7 +73,7 @@ struct Column {
 };
 
 struct GramIndex {
-    uint32_t attr = 0, q = 0, max_cnt = 0;
+    uint32_t attr = 0, q = 0, max_cnt = 0, sig_words = 1;
     DevBuf off, cnt, codes, flags, sig;
     GramDev dev() const {
         GramDev g{};
@@ -84,6 +84,7 @@ struct GramIndex {
         g.q = q;
         g.max_cnt = max_cnt;
         g.attr = attr;
+        g.sig_words = sig_words;
         return g;
     }
 };

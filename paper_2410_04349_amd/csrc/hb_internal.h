@@ -18,6 +18,7 @@ constexpr int kMaxStrRes = 8;    // string attributes staged per tile
 constexpr int kMaxGramRes = 8;   // (attribute, q) gram lists staged per tile
 constexpr int kMaxPrevKeys = 3;
 constexpr int kMaxEdWords = 4;   // 256-byte edit-distance patterns
+constexpr uint32_t kLongSigWords = 4;   // q-gram signature words of attributes past 64 windows
 constexpr int kMaxPlan = 1536;   // steps of one key's plan
 constexpr int kCountPairs = 8 * 4;             // instrumented counters: 8 op kinds x 4, then pairs
 constexpr int kCountSlots = kCountPairs + 1;
@@ -46,6 +47,8 @@ struct GramDev {
     uint32_t q;
     uint32_t max_cnt;   // bound on a row's code count: the longest row's window count
     uint32_t attr;
+    uint32_t sig_words;   // 64-bit words of a row's q-gram signature (1, or 4 past 64 windows)
+    uint32_t sig_col;     // first f64 feature column of the signature, counted from the first gram column
     uint32_t pad;
 };
 
@@ -84,12 +87,14 @@ static_assert(sizeof(Instr) == 16, "Instr layout");
 // Block-major feature columns of one key partition (structure of arrays,
 // position p = p-th row of the key-sorted permutation):
 //   f64[(x) * n + p]: x < n_int: int value; then n_str character signatures;
-//                     then n_gram q-gram signatures
+//                     then the q-gram signatures, sig_words columns per gram
+//                     resource (word w of resource r at column
+//                     n_int + n_str + gram[r].sig_col + w)
 //   f32[(x) * n + p]: x = 0: row id; 1: validity mask (bit r: int resource r,
 //                     16 + r: string resource r, 24 + r: gram resource r);
 //                     then n_str lengths; then n_gram set sizes (bit 31:
 //                     short-string flag); then n_gram Jaccard-filter words
-//                     ((|A| - popcount(signature)) << 16 | |A|, and 1 for a
+//                     ((|A| - popcount(signature words)) << 16 | |A|, and 1 for a
 //                     missing value, whose signature is 0: with a threshold
 //                     above 0 that word fails the filter against anything)
 struct Features {
@@ -156,7 +161,8 @@ struct GatherParams {
     const uint8_t* gram_valid[kMaxGramRes];
     const uint32_t* gram_cnt[kMaxGramRes];
     const uint8_t* gram_flags[kMaxGramRes];
-    const uint64_t* gsig[kMaxGramRes];
+    const uint64_t* gsig[kMaxGramRes];        // sig_words words per row
+    uint32_t gram_words[kMaxGramRes], gram_col[kMaxGramRes];
     uint64_t* f64;
     uint32_t* f32;
 };

@@ -431,11 +431,36 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 // words carry both sizes, and a missing value's word fails
                 // against anything once num > 0.
                 const uint32_t wb = J32(jf32 + res);
-                const uint64_t gj = J64(gram64 + res);
+                const uint32_t gcol = gram64 + P.gram[res].sig_col;
+                const uint64_t gj = J64(gcol);
                 const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
                 uint32_t keep = 0;
                 if (num == 0) {   // J >= 0: every pair of present values
                     keep = (vmask_j >> (24 + res)) & 1 ? row_bits(f32 + n, pi0, 24 + res) : 0u;
+                } else if (P.gram[res].sig_words != 1) {
+                    // four-word signature (long strings): the same bound, the
+                    // intersection popcount summed over the words
+                    const uint32_t restb = wb >> 16, rhs_b = opaque(__umul24(num, wb & 0xFFFFu));
+                    uint32_t gjw[2 * kLongSigWords];
+#pragma unroll
+                    for (uint32_t w = 0; w < kLongSigWords; ++w) {
+                        const uint64_t v = J64(gcol + w);
+                        gjw[2 * w] = (uint32_t)v;
+                        gjw[2 * w + 1] = (uint32_t)(v >> 32);
+                    }
+#pragma unroll
+                    for (int r = kRows - 1; r >= 0; --r) {
+                        const uint64_t pr = pi0 + (uint64_t)r;
+                        const uint32_t wa = f32[(jf32 + res) * n + pr];
+                        uint32_t iub = min(wa >> 16, restb);
+#pragma unroll
+                        for (uint32_t w = 0; w < kLongSigWords; ++w) {
+                            const uint64_t gi = f64[(gcol + w) * n + pr];
+                            iub = popc_add((uint32_t)gi & gjw[2 * w], popc_add((uint32_t)(gi >> 32) & gjw[2 * w + 1], iub));
+                        }
+                        const bool ok = __umul24(iub, nd) >= num * (wa & 0xFFFFu) + rhs_b;
+                        keep = push_bit(keep, __ballot(ok));
+                    }
                 } else if (nd <= (1u << 18)) {
                     // num + den <= 2^18: I * (num + den) - num * |B| stays
                     // within int32, so one signed 24-bit multiply-add and a
@@ -448,7 +473,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     for (int r = kRows - 1; r >= 0; --r) {
                         const uint64_t pr = pi0 + (uint64_t)r;
                         const uint32_t wa = f32[(jf32 + res) * n + pr];
-                        const uint64_t gi = f64[(gram64 + res) * n + pr];
+                        const uint64_t gi = f64[gcol * n + pr];
                         const uint32_t rest = min(wa >> 16, restb);
                         const uint32_t iub = popc_add((uint32_t)gi & gj_lo, popc_add((uint32_t)(gi >> 32) & gj_hi, rest));
                         const int lhs = mad_i24((int)iub, (int)nd, neg_b);
@@ -461,7 +486,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     for (int r = kRows - 1; r >= 0; --r) {
                         const uint64_t pr = pi0 + (uint64_t)r;
                         const uint32_t wa = f32[(jf32 + res) * n + pr];
-                        const uint64_t gi = f64[(gram64 + res) * n + pr];
+                        const uint64_t gi = f64[gcol * n + pr];
                         const uint32_t rest = min(wa >> 16, restb);
                         const uint32_t iub = popc_add((uint32_t)gi & gj_lo, popc_add((uint32_t)(gi >> 32) & gj_hi, rest));
                         const bool ok = __umul24(iub, nd) >= num * (wa & 0xFFFFu) + rhs_b;
@@ -752,8 +777,13 @@ __device__ inline bool feature_filter(const LearnParams& L, const PredSpec& sp, 
         if (!((vb >> (24 + res)) & 1)) return false;
         const uint64_t sa = f32[(2 + P.n_str + res) * n + pa] & 0x7FFFFFFFu;
         const uint64_t sb = f32[(2 + P.n_str + res) * n + pb] & 0x7FFFFFFFu;
-        const uint64_t ga = f64[(P.n_int + P.n_str + res) * n + pa], gb = f64[(P.n_int + P.n_str + res) * n + pb];
-        const uint64_t ua = sa - (uint64_t)__popcll(ga & ~gb), ub = sb - (uint64_t)__popcll(gb & ~ga);
+        const uint32_t gc = P.n_int + P.n_str + P.gram[res].sig_col;
+        uint64_t ua = sa, ub = sb;
+        for (uint32_t w = 0; w < P.gram[res].sig_words; ++w) {
+            const uint64_t ga = f64[(gc + w) * n + pa], gb = f64[(gc + w) * n + pb];
+            ua -= (uint64_t)__popcll(ga & ~gb);
+            ub -= (uint64_t)__popcll(gb & ~ga);
+        }
         const uint64_t iub = ua < ub ? ua : ub;
         const uint64_t num = sp.param >> 32, den = sp.param & 0xFFFFFFFFu;
         return iub * (num + den) >= num * (sa + sb);
@@ -799,7 +829,7 @@ __global__ __launch_bounds__(64) void k_block_features(const LearnParams L) {
             } else {
                 v = (vm >> (24 + sp.res)) & 1;
                 lv = (double)(f32[(2 + P.n_str + sp.res) * n + pos] & 0x7FFFFFFFu);
-                if (v) pops += __popcll(f64[(P.n_int + P.n_str + sp.res) * n + pos]);
+                if (v) pops += __popcll(f64[(P.n_int + P.n_str + P.gram[sp.res].sig_col) * n + pos]);
             }
             if (v) {
                 cnt += 1;

@@ -588,24 +588,29 @@ __global__ void k_char_sig(const ColDev* __restrict__ colp, uint32_t n, uint64_t
     sig[r] = m;
 }
 
-// bit (hash(code) mod 64) for every distinct q-gram code of the row: a gram
-// in A whose bit is absent from sig_B is not in B, so
-// |A & B| <= |A| - |sig_A \ sig_B|
+// bit (hash(code) mod 64 W) of a W-word signature for every distinct q-gram
+// code of the row: a gram in A whose bit is absent from sig_B is not in B,
+// so |A & B| <= |A| - |sig_A \ sig_B|
 __global__ void k_gram_sig(const GramDev g, uint32_t n, uint64_t* __restrict__ sig) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const uint32_t* codes = g.codes + g.off[r];
     const uint32_t cnt = g.cnt[r];
-    uint64_t m = 0;
+    const uint32_t W = g.sig_words, bits = 64u * W - 1u;   // W is 1 or 4: 64 W bits
+    uint64_t m[kLongSigWords] = {0, 0, 0, 0};
     for (uint32_t x = 0; x < cnt; x += 8) {   // eight independent loads per batch
         uint32_t v[8];
 #pragma unroll
         for (uint32_t k = 0; k < 8; ++k) v[k] = x + k < cnt ? codes[x + k] : 0u;
 #pragma unroll
         for (uint32_t k = 0; k < 8; ++k)
-            if (x + k < cnt) m |= 1ull << (mix64(v[k]) & 63);
+            if (x + k < cnt) {
+                const uint32_t b = (uint32_t)(mix64(v[k]) & bits);
+#pragma unroll
+                for (uint32_t w = 0; w < kLongSigWords; ++w) m[w] |= (b >> 6) == w ? 1ull << (b & 63) : 0ull;
+            }
     }
-    sig[r] = m;
+    for (uint32_t w = 0; w < W; ++w) sig[(size_t)r * W + w] = m[w];
 }
 
 __global__ void k_gather_features(const GatherParams P) {
@@ -641,13 +646,18 @@ __global__ void k_gather_features(const GatherParams P) {
     }
     x -= P.n_str;
     const bool v = !pad && bit_valid(P.gram_valid[x], row);
-    const uint64_t sig = v ? P.gsig[x][row] : 0ull;
+    const uint32_t W = P.gram_words[x];
+    uint32_t pop = 0;
+    for (uint32_t w = 0; w < W; ++w) {
+        const uint64_t sig = v ? P.gsig[x][(size_t)row * W + w] : 0ull;
+        P.f64[(P.n_int + P.n_str + P.gram_col[x] + w) * n + p] = sig;
+        pop += (uint32_t)__popcll(sig);
+    }
     const uint32_t cnt = v ? P.gram_cnt[x][row] : 0u;
-    P.f64[(P.n_int + P.n_str + x) * n + p] = sig;
     P.f32[(2 + P.n_str + x) * n + p] = v ? (cnt | ((uint32_t)(P.gram_flags[x][row] & 1) << 31)) : 0u;
     // the Jaccard-filter word: 1 marks a missing value (pads: 0)
     P.f32[(2 + P.n_str + P.n_gram + x) * n + p] =
-        v ? ((cnt - (uint32_t)__popcll(sig)) << 16) | cnt : pad ? 0u : 1u;
+        v ? ((cnt - pop) << 16) | cnt : pad ? 0u : 1u;
 }
 
 // ------------------------------------------------------------ LSH histogram
