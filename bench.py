@@ -177,6 +177,16 @@ def run_batched(args):
         results[mode] = {"s_per_step": sum(times) / len(times), "pairs": cand, "matched": int(total),
                          "kernel_ms_per_step": kern}
         log(f"[bench] {mode}: {results[mode]}")
+    # the batch's per-job results must equal each relation's own hb_match (untimed)
+    ids, _ = fresh()
+    bid = hb.hb_batch_create(ctx, ids, "heuristic", graph=False)
+    hb.hb_batch_run(ctx, bid)
+    same = all(np.array_equal(hb.hb_batch_result(ctx, bid, k), hb.hb_match(ctx, rid, rs, "heuristic"))
+               for k, (rid, rs) in enumerate(ids))
+    hb.hb_batch_destroy(ctx, bid)
+    if not same:
+        raise SystemExit("batched results differ from per-relation matching")
+    log("[bench] batched results equal per-relation results: True")
     value = results["batched"]["pairs"] / results["batched"]["s_per_step"]
     result = {
         "metric": "tuple pairs evaluated/sec on 1 MI355X, learned vs heuristic plan, bit-exact",
@@ -188,7 +198,7 @@ def run_batched(args):
                    "candidate_pairs": results["batched"]["pairs"], "matched_pairs": results["batched"]["matched"]},
         "compare": {"mode": "separate hb_match per relation",
                     "value": results["separate"]["pairs"] / results["separate"]["s_per_step"],
-                    "ms_per_step": results["separate"]["s_per_step"] * 1e3},
+                    "ms_per_step": results["separate"]["s_per_step"] * 1e3, "bit_exact": same},
         "batch": info,
     }
     ctx.close()

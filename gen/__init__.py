@@ -71,7 +71,7 @@ class Relation:
         for c in self.columns:
             valid = None
             if c.valid is not None:
-                bits = np.array([c.is_valid(int(r)) for r in rows], dtype=np.uint8)
+                bits = np.unpackbits(c.valid, bitorder="little")[rows]
                 valid = pack_bits(bits)
             if c.type == STRING:
                 starts = c.offsets[rows].astype(np.int64)
@@ -79,9 +79,12 @@ class Relation:
                 lens = ends - starts
                 offs = np.zeros(len(rows) + 1, dtype=np.uint64)
                 np.cumsum(lens, out=offs[1:])
-                if len(rows):
-                    idx = np.concatenate([np.arange(s, e) for s, e in zip(starts, ends)]) if lens.sum() else np.zeros(0, np.int64)
-                    data = c.data[idx].copy() if len(idx) else np.zeros(0, np.uint8)
+                total = int(lens.sum())
+                if total:
+                    # byte k of the result comes from starts[row of k] + (k - offs[row of k])
+                    owner = np.repeat(np.arange(len(rows)), lens)
+                    idx = starts[owner] + (np.arange(total) - offs[:-1].astype(np.int64)[owner])
+                    data = c.data[idx].copy()
                 else:
                     data = np.zeros(0, np.uint8)
                 cols.append(Column(c.name, c.type, offsets=offs, data=data, valid=valid))
