@@ -29,6 +29,7 @@ _LIB = os.path.join(_HERE, "libhbgen.so")
 
 STRING, CATEGORICAL, INT64 = "string", "categorical", "int64"
 EQ, ED, JACCARD, ABSDIFF = "eq", "ed", "jaccard", "absdiff"
+EQ_CONST, EQ_CROSS = "eq_const", "eq_cross"   # t.A = c (side 0) / s.A = c (side 1); t.A = s.B
 
 
 @dataclass
@@ -142,6 +143,9 @@ class Pred:
     num: int = 0        # Jaccard threshold num/den
     den: int = 1
     d: int = 0          # ABSDIFF threshold |a-b| <= d
+    attr_b: int = 0     # EQ_CROSS: the attribute B of t.A = s.B
+    side: int = 0       # EQ_CONST: 0 for t.A = c, 1 for s.A = c
+    c: int = 0          # EQ_CONST: the constant
 
 
 def pack_bits(bits: np.ndarray) -> np.ndarray:

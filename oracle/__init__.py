@@ -25,7 +25,7 @@ _SRC = os.path.join(_HERE, "hboracle.cpp")
 _LIB = os.path.join(_HERE, "libhboracle.so")
 
 _TYPES = {"string": 0, "categorical": 1, "int64": 2}
-_OPS = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3}
+_OPS = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3, "eq_const": 4, "eq_cross": 5}
 
 
 class _Col(ctypes.Structure):
@@ -36,7 +36,8 @@ class _Col(ctypes.Structure):
 class _Pred(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("attr", ctypes.c_uint32), ("k", ctypes.c_int64),
                 ("q", ctypes.c_uint32), ("num", ctypes.c_uint32), ("den", ctypes.c_uint32),
-                ("d", ctypes.c_int64)]
+                ("d", ctypes.c_int64), ("attr_b", ctypes.c_uint32), ("side", ctypes.c_int32),
+                ("c", ctypes.c_int64)]
 
 
 def build_lib(force: bool = False) -> str:
@@ -65,7 +66,8 @@ def _load():
                 ("ora_rule_witness", I, [P, U32, P, U64, U64]),
                 ("ora_blocking", ctypes.c_int64, [P, U32, U64, U32, P, P, I, I, P, U64]),
                 ("ora_candidate_count", ctypes.c_int64, [P, U64, U32, P, P]),
-                ("ora_eval_pairs", I, [P, U64, U32, P, P, P, U64, I, P])):
+                ("ora_eval_pairs", I, [P, U64, U32, P, P, P, U64, I, P]),
+                ("ora_ordered", I, [U32, P, P])):
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
@@ -107,7 +109,8 @@ class _Marshal:
 
 
 def to_cpred(p):
-    return _Pred(_OPS[p.op], p.attr, p.k, p.q, p.num, p.den, p.d)
+    return _Pred(_OPS[p.op], p.attr, p.k, p.q, p.num, p.den, p.d, getattr(p, "attr_b", 0),
+                 getattr(p, "side", 0), getattr(p, "c", 0))
 
 
 def levenshtein(a: bytes, b: bytes) -> int:
@@ -135,8 +138,18 @@ def rule_witness(rel, rule, i: int, j: int) -> bool:
     return bool(_load().ora_rule_witness(m.cols, len(rule), m.preds, i, j))
 
 
+def ordered(rules) -> bool:
+    """True if some predicate tells t from s (t.A = c, s.A = c, or t.A = s.B
+    over two different attributes): Ca then lists ordered pairs."""
+    flat = [p for r in rules for p in r]
+    lens = (ctypes.c_uint32 * max(1, len(rules)))(*[len(r) for r in rules])
+    preds = (_Pred * max(1, len(flat)))(*[to_cpred(p) for p in flat])
+    return bool(_load().ora_ordered(len(rules), lens, preds))
+
+
 def blocking(rel, rules, mode: str = "blocked", threads: int = 1) -> np.ndarray:
-    """Ca(D, Delta): sorted uint64 array of (i << 32) | j, i < j."""
+    """Ca(D, Delta): sorted uint64 array of (i << 32) | j (t bound to row i,
+    s to row j); i < j unless the rule set is ordered."""
     m = _Marshal(rel, rules)
     md = {"blocked": 0, "full": 1}[mode]
     lib = _load()

@@ -8,15 +8,27 @@
  * no blocking, fusion or reordering beyond what that definition states.
  *
  * What it computes (Section 2, "Rule-based blocking" and Section 4 opening):
- *   Ca(D, Delta) = { (i, j) : i < j, some rule phi in Delta has every
- *                    predicate of its precondition X satisfied by (t_i, t_j) }
+ *   Ca(D, Delta) = { (i, j) : some rule phi in Delta has every predicate of
+ *                    its precondition X satisfied by the valuation t -> t_i,
+ *                    s -> t_j }
+ * over the pairs of a partition (Section 2, "Blocking").  With only
+ * predicates of the forms t.A = s.A and t.A ~ s.A (a symmetric measure) the
+ * two valuations of a pair agree, and each pair is listed once, as i < j.
+ * A rule set with a predicate t.A = c or s.A = c, or t.A = s.B over two
+ * different attributes, is "ordered": its valuations of (t_i, t_j) and
+ * (t_j, t_i) may differ, and Ca lists every ordered pair (i, j), i != j,
+ * whose valuation has a witness.
  * evaluated naively: every rule, every predicate, in input order (the
  * "naive approach" at the start of Section 4).
  *
  * Readings of points the paper leaves open (each also listed in the design
  * notes):
- *   - pairs are unordered, i < j, reported by 0-based row index, packed as
- *     (i << 32) | j and sorted ascending;
+ *   - pairs are reported by 0-based row index, packed as (i << 32) | j
+ *     (i the tuple bound to t, j the one bound to s) and sorted ascending;
+ *     unordered (i < j) unless the rule set is ordered (above);
+ *   - t.A = c holds iff t's A is present and equals c (an int64 constant on
+ *     a categorical or int64 attribute); t.A = s.B iff both values are
+ *     present and equal (Section 2, "Semantics": tuple relational calculus);
  *   - a missing value fails every predicate, including missing = missing
  *     (Table 1 marks missing values; Example 3 and the Section 4 remark on
  *     (t1, t5) treat a missing value as failing equality and similarity);
@@ -49,7 +61,7 @@
 extern "C" {
 
 enum { ORA_STRING = 0, ORA_CATEGORICAL = 1, ORA_INT64 = 2 };
-enum { ORA_EQ = 0, ORA_ED = 1, ORA_JACCARD = 2, ORA_ABSDIFF = 3 };
+enum { ORA_EQ = 0, ORA_ED = 1, ORA_JACCARD = 2, ORA_ABSDIFF = 3, ORA_CONST = 4, ORA_CROSS = 5 };
 
 struct ora_col {
     int32_t type;
@@ -67,6 +79,9 @@ struct ora_pred {
     uint32_t num;
     uint32_t den;
     int64_t d;
+    uint32_t attr_b;  /* ORA_CROSS: the attribute B of t.A = s.B */
+    int32_t side;     /* ORA_CONST: 0 for t.A = c, 1 for s.A = c */
+    int64_t c;        /* ORA_CONST: the constant */
 };
 
 }  // extern "C"
@@ -142,9 +157,17 @@ struct GramCache {
     }
 };
 
-/* h(t_i, t_j) |= p */
+/* h(t_i, t_j) |= p, with h(t) = t_i and h(s) = t_j */
 bool sat(const ora_col* cols, const ora_pred& p, uint64_t i, uint64_t j, const GramCache* gc) {
     const ora_col& c = cols[p.attr];
+    if (p.op == ORA_CONST) {
+        const uint64_t row = p.side == 0 ? i : j;
+        return is_valid(c, row) && c.values[row] == p.c;
+    }
+    if (p.op == ORA_CROSS) {
+        const ora_col& b = cols[p.attr_b];
+        return is_valid(c, i) && is_valid(b, j) && c.values[i] == b.values[j];
+    }
     if (!is_valid(c, i) || !is_valid(c, j)) return false;
     switch (p.op) {
     case ORA_EQ:
@@ -174,6 +197,15 @@ bool sat(const ora_col* cols, const ora_pred& p, uint64_t i, uint64_t j, const G
 struct RuleSet {
     std::vector<std::vector<ora_pred>> rules;
 };
+
+/* Does some predicate tell t from s (a constant on one side, or an
+ * equality across two different attributes)? */
+bool ordered_rules(const RuleSet& rs) {
+    for (const auto& rule : rs.rules)
+        for (const auto& p : rule)
+            if (p.op == ORA_CONST || (p.op == ORA_CROSS && p.attr != p.attr_b)) return true;
+    return false;
+}
 
 RuleSet unpack_rules(uint32_t n_rules, const uint32_t* rule_len, const ora_pred* preds) {
     RuleSet rs;
@@ -247,6 +279,10 @@ void ora_qgram_stats(const uint8_t* a, uint64_t la, const uint8_t* b, uint64_t l
     inter_union(A, B, inter, uni);
 }
 
+int ora_ordered(uint32_t n_rules, const uint32_t* rule_len, const ora_pred* preds) {
+    return ordered_rules(unpack_rules(n_rules, rule_len, preds)) ? 1 : 0;
+}
+
 int ora_jaccard_ge(const uint8_t* a, uint64_t la, const uint8_t* b, uint64_t lb, uint32_t q,
                    uint32_t num, uint32_t den) {
     uint64_t I, U;
@@ -266,7 +302,8 @@ int ora_rule_witness(const ora_col* cols, uint32_t n_preds, const ora_pred* pred
 }
 
 /* Ca(D, Delta) as a sorted list of packed pairs.
- * mode 0: blocked (pairs sharing some rule's key); mode 1: every i < j.
+ * mode 0: blocked (pairs sharing some rule's key); mode 1: every pair of
+ * rows (both orders for an ordered rule set).
  * Returns the number of pairs (written up to `cap`), -2 if a rule has no
  * key in blocked mode. */
 int64_t ora_blocking(const ora_col* cols, uint32_t n_cols, uint64_t n_rows, uint32_t n_rules,
@@ -279,6 +316,7 @@ int64_t ora_blocking(const ora_col* cols, uint32_t n_cols, uint64_t n_rows, uint
     GramCache gc;
     gc.build(cols, n_rows, preds, np);
     if (n_threads < 1) n_threads = 1;
+    const bool ordered = ordered_rules(rs);
 
     std::vector<uint64_t> result;
     std::mutex mu;
@@ -289,8 +327,14 @@ int64_t ora_blocking(const ora_col* cols, uint32_t n_cols, uint64_t n_rows, uint
             for (;;) {
                 uint64_t i = next.fetch_add(1);
                 if (i >= n_rows) break;
-                for (uint64_t j = i + 1; j < n_rows; ++j)
-                    if (witness_exists(cols, rs, i, j, &gc)) local.push_back(pack(i, j));
+                for (uint64_t j = i + 1; j < n_rows; ++j) {
+                    if (!ordered) {
+                        if (witness_exists(cols, rs, i, j, &gc)) local.push_back(pack(i, j));
+                        continue;
+                    }
+                    if (witness_exists(cols, rs, i, j, &gc)) local.push_back((i << 32) | j);
+                    if (witness_exists(cols, rs, j, i, &gc)) local.push_back((j << 32) | i);
+                }
             }
             std::lock_guard<std::mutex> g(mu);
             result.insert(result.end(), local.begin(), local.end());
@@ -313,8 +357,15 @@ int64_t ora_blocking(const ora_col* cols, uint32_t n_cols, uint64_t n_rows, uint
                 if (g >= groups.size()) break;
                 const auto& rows = groups[g];
                 for (size_t x = 0; x < rows.size(); ++x)
-                    for (size_t y = x + 1; y < rows.size(); ++y)
-                        if (witness_exists(cols, rs, rows[x], rows[y], &gc)) local.push_back(pack(rows[x], rows[y]));
+                    for (size_t y = x + 1; y < rows.size(); ++y) {
+                        const uint64_t a = rows[x], b = rows[y];
+                        if (!ordered) {
+                            if (witness_exists(cols, rs, a, b, &gc)) local.push_back(pack(a, b));
+                            continue;
+                        }
+                        if (witness_exists(cols, rs, a, b, &gc)) local.push_back((a << 32) | b);
+                        if (witness_exists(cols, rs, b, a, &gc)) local.push_back((b << 32) | a);
+                    }
             }
             std::lock_guard<std::mutex> g(mu);
             result.insert(result.end(), local.begin(), local.end());
@@ -347,8 +398,9 @@ int64_t ora_candidate_count(const ora_col* cols, uint64_t n_rows, uint32_t n_rul
     return (int64_t)all.size();
 }
 
-/* For each given pair (packed (i << 32) | j), flags[x] = 1 iff it is in
- * Ca(D, Delta), by the definition (no blocking involved). */
+/* For each given pair (packed (i << 32) | j), flags[x] = 1 iff some rule
+ * is a witness at the valuation t -> t_i, s -> t_j, by the definition (no
+ * blocking involved). */
 int ora_eval_pairs(const ora_col* cols, uint64_t n_rows, uint32_t n_rules, const uint32_t* rule_len,
                    const ora_pred* preds, const uint64_t* pairs, uint64_t n_pairs, int n_threads,
                    uint8_t* flags) {
