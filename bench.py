@@ -214,6 +214,9 @@ def main():
     ap.add_argument("--strategies", action="store_true",
                     help="also time the comparison orders (given, cheapest, selective, random_preds, "
                          "random_rules) on the same workload; outputs must equal the timed plan's")
+    ap.add_argument("--grammar", action="store_true",
+                    help="also time plain_1m under a rule set with t.i1 = 7 (ordered output) and check it "
+                         "against the symmetric result")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plan", default="learned", choices=["learned", "heuristic", "given"])
@@ -297,11 +300,11 @@ def main():
 
     phase = {}
 
-    def step(plan, dst):
+    def step(plan, dst, rules_=None):
         t0 = time.perf_counter()
         rid = hb.hb_load_relation(ctx, cols, rel.n_rows, on_device=True)
         t1 = time.perf_counter()
-        rs = hb.hb_compile_rules(ctx, rid, rules)
+        rs = hb.hb_compile_rules(ctx, rid, rules if rules_ is None else rules_)
         t2 = time.perf_counter()
         n_cand = hb.hb_partition(ctx, rid, rs)
         t3 = time.perf_counter()
@@ -314,9 +317,9 @@ def main():
             phase[k] = phase.get(k, 0.0) + v
         return n_cand, n_match
 
-    def timed(plan, dst):
+    def timed(plan, dst, rules_=None):
         for w in range(args.warmup):
-            n_cand, n_match = step(plan, dst)
+            n_cand, n_match = step(plan, dst, rules_)
             log(f"[bench] {plan} warmup {w}: {n_cand} candidate pairs, {n_match} matched")
         hb.hb_profile_reset(ctx)
         hb.hb_profile_enable(ctx, True)
@@ -324,7 +327,7 @@ def main():
         phase.clear()
         t0 = time.perf_counter()
         for k in range(args.steps):
-            n_cand, n_match = step(plan, dst)
+            n_cand, n_match = step(plan, dst, rules_)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         hb.hb_profile_enable(ctx, False)
@@ -408,6 +411,32 @@ def main():
                                  "bit_exact": same}
         log(f"[bench] strategies: {strategies}")
 
+    grammar = None
+    if args.grammar:
+        # the same relation under rules that tell t from s: ordered output,
+        # both valuations of each candidate pair in one visit
+        from gen.workloads import plain_1m_ordered_rules
+        if args.workload != "plain_1m":
+            raise SystemExit("--grammar runs on plain_1m")
+        out_o = torch.empty(2 * out.numel(), dtype=out.dtype, device=out.device)
+        c_o, m_o, dt_o, prof_o = timed("heuristic", out_o, plain_1m_ordered_rules())
+        pairs_o = out_o[:m_o].cpu().numpy().view(np.uint64)
+        sym = out[:n_match].cpu().numpy().view(np.uint64)
+        both = np.concatenate([sym, (sym << np.uint64(32)) | (sym >> np.uint64(32))])
+        # every symmetric match is listed in both orders; the rest have t.i1 = 7
+        covered = bool(np.all(np.isin(both, pairs_o)))
+        extra = np.setdiff1d(pairs_o, both)
+        i1 = rel.columns[4].values
+        t_ok = bool(np.all(i1[(extra >> np.uint64(32)).astype(np.int64)] == 7))
+        if not (covered and t_ok):
+            raise SystemExit("ordered rule set result is inconsistent with the symmetric one")
+        grammar = {"rules": "plain_1m rules + (key= and t.i1 = 7 and ED(s1) <= 3): ordered output",
+                   "value": c_o * args.steps / dt_o, "unit": "pairs/s", "ms_per_step": dt_o * 1000.0 / args.steps,
+                   "match_kernel_ms": prof_o["match"]["ms_total"] / max(1, prof_o["match"]["launches"]),
+                   "matched_ordered_pairs": int(m_o), "symmetric_in_both_orders": covered,
+                   "others_have_t_i1_7": t_ok}
+        log(f"[bench] grammar: {grammar}")
+
     # blocking quality against the generator's duplicate links (untimed)
     from gen import true_pairs
     from paper_2410_04349_amd.quality import quality
@@ -446,6 +475,7 @@ def main():
         "cost_model": learned,
         "quality": qual,
         "strategies": strategies,
+        "grammar": grammar,
         "pcie_inclusive": pcie,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s (int32 lane-ops)",
                      "frac": achieved / peak, "traffic": recorded_traffic(args.workload, args.plan),

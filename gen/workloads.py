@@ -42,7 +42,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (ABSDIFF, CATEGORICAL, ED, EQ, INT64, JACCARD, STRING, AttrSpec,
+from . import (ABSDIFF, CATEGORICAL, ED, EQ, EQ_CONST, INT64, JACCARD, STRING, AttrSpec,
                Column, Pred, Relation, generate, pack_bits)
 
 SEED_BASE = 0x48420000
@@ -81,6 +81,14 @@ def plain_1m_rules():
         [Pred(EQ, key), Pred(ABSDIFF, i2, d=2), Pred(ED, s1, k=3), Pred(JACCARD, s3, q=3, num=4, den=5)],
         [Pred(EQ, key), Pred(JACCARD, s2, q=3, num=1, den=2), Pred(ABSDIFF, i1, d=2), Pred(ED, s3, k=2)],
     ]
+
+
+def plain_1m_ordered_rules():
+    """plain_1m's rules plus one that tells t from s: t.i1 = 7 and
+    ED(s1) <= 3.  The rule set is ordered (each symmetric match is listed
+    in both orders)."""
+    s1, s2, s3, key, i1, i2 = range(6)
+    return plain_1m_rules() + [[Pred(EQ, key), Pred(EQ_CONST, i1, side=0, c=7), Pred(ED, s1, k=3)]]
 
 
 def plain_1m(seed: int = SEED_BASE + 2, n: int = 1_000_000):

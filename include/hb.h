@@ -113,8 +113,9 @@ hb_status hb_load_relation_async(hb_ctx* ctx, uint32_t n_rows, uint32_t n_cols, 
 hb_status hb_release_relation(hb_ctx* ctx, uint32_t rel_id);
 
 /* ------------------------------------------------------------ rules
- * Predicates of the form t.A = s.A and t.A ~ s.A (Section 2, "Predicates"),
- * with these similarity measures:
+ * Predicates of the forms t.A = s.A, t.A ~ s.A, t.A = c and t.A = s.B
+ * (Section 2, "Predicates"); a valuation binds t to a pair's first tuple and
+ * s to its second (Section 2, "Semantics").  The operators:
  *   HB_EQ          byte-exact equality (STRING) or value equality
  *                  (CATEGORICAL, INT64);
  *   HB_ED_LE       Levenshtein distance over bytes <= k        (STRING);
@@ -122,13 +123,30 @@ hb_status hb_release_relation(hb_ctx* ctx, uint32_t rel_id);
  *                  set of distinct length-q byte windows, {s} for a non-empty
  *                  string shorter than q, empty for the empty string, and
  *                  J(empty, empty) = 1                          (STRING);
- *   HB_ABSDIFF_LE  |a - b| <= d, exact over int64                (INT64).
+ *   HB_ABSDIFF_LE  |a - b| <= d, exact over int64                (INT64);
+ *   HB_EQ_CONST    t.A = c (side 0) or s.A = c (side 1): the tuple's value
+ *                  is present and equals the int64 constant c
+ *                                                   (CATEGORICAL, INT64);
+ *   HB_EQ_CROSS    t.A = s.B: t's value of A and s's value of B (attr_b) are
+ *                  both present and equal     (CATEGORICAL, INT64 for both).
+ * A missing value fails every predicate.  A rule set with an HB_EQ_CONST,
+ * or an HB_EQ_CROSS over two different attributes, is *ordered*: its two
+ * valuations of a pair may differ, and hb_match lists ordered pairs (see
+ * there).  HB_EQ_CROSS with attr_b = attr is an equality (unordered), but
+ * never a blocking key.
  * A rule (an MD X -> t.eid = s.eid, Section 2, "Rules") is a conjunction;
  * a rule set is their disjunction.  Every rule must contain an HB_EQ on a
  * CATEGORICAL or INT64 attribute: its first one (in the given order) is the
  * rule's blocking key (the partition key of Section 5.3).
  */
-typedef enum { HB_EQ = 0, HB_ED_LE = 1, HB_JACCARD_GE = 2, HB_ABSDIFF_LE = 3 } hb_op;
+typedef enum {
+    HB_EQ = 0,
+    HB_ED_LE = 1,
+    HB_JACCARD_GE = 2,
+    HB_ABSDIFF_LE = 3,
+    HB_EQ_CONST = 4,
+    HB_EQ_CROSS = 5
+} hb_op;
 
 typedef struct {
     int32_t op;     /* hb_op */
@@ -138,6 +156,9 @@ typedef struct {
     uint32_t num;   /* HB_JACCARD_GE: threshold num/den, 0 <= num <= den */
     uint32_t den;   /* HB_JACCARD_GE: den > 0, <= HB_MAX_JACCARD_DEN in lowest terms */
     int64_t d;      /* HB_ABSDIFF_LE: d >= 0 */
+    uint32_t attr_b;  /* HB_EQ_CROSS: column index of B */
+    int32_t side;     /* HB_EQ_CONST: 0 = t.A = c, 1 = s.A = c */
+    int64_t c;        /* HB_EQ_CONST: the constant */
 } hb_pred;
 
 typedef struct {
@@ -197,7 +218,13 @@ typedef enum {
 } hb_plan;
 
 /* Evaluate the rule set on every candidate pair and return Ca(D): packed
- * uint64 (i << 32) | j with i < j, sorted ascending, each pair once.
+ * uint64 (i << 32) | j with i < j, sorted ascending, each pair once.  For
+ * an ordered rule set (see the predicates), every ordered pair (i, j),
+ * i != j, whose valuation t -> row i, s -> row j has a witness, sorted
+ * ascending; each candidate pair is still visited once, its symmetric
+ * predicates evaluated once for both orders.  Ordered rule sets take the
+ * given, heuristic and strategy plans; HB_PLAN_LEARNED, hb_match_work,
+ * hb_log_collect and batches reject them (HB_ERR_INVALID_ARG).
  * `out_pairs` holds `capacity` entries in host memory (out_on_device = 0)
  * or device memory (1).  If capacity is too small the call returns
  * HB_ERR_CAPACITY with *n_pairs = the size needed; the result stays cached

@@ -35,7 +35,7 @@ HB_PLAN_HEURISTIC = 1
 HB_PLAN_LEARNED = 2
 
 _COLTYPE = {"string": 0, "categorical": 1, "int64": 2}
-_OP = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3}
+_OP = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3, "eq_const": 4, "eq_cross": 5}
 HB_PLAN_CHEAPEST, HB_PLAN_SELECTIVE, HB_PLAN_RANDOM_PREDS, HB_PLAN_RANDOM_RULES = 3, 4, 5, 6
 _PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC, "learned": HB_PLAN_LEARNED,
          "cheapest": HB_PLAN_CHEAPEST, "selective": HB_PLAN_SELECTIVE,
@@ -82,7 +82,8 @@ class HbColumn(ctypes.Structure):
 class HbPred(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("attr", ctypes.c_uint32), ("k", ctypes.c_int64),
                 ("q", ctypes.c_uint32), ("num", ctypes.c_uint32), ("den", ctypes.c_uint32),
-                ("d", ctypes.c_int64)]
+                ("d", ctypes.c_int64), ("attr_b", ctypes.c_uint32), ("side", ctypes.c_int32),
+                ("c", ctypes.c_int64)]
 
 
 class HbRule(ctypes.Structure):
@@ -289,7 +290,8 @@ def _c_rules(rules):
     for r, rule in enumerate(rules):
         preds = (HbPred * max(1, len(rule)))()
         for x, p in enumerate(rule):
-            preds[x] = HbPred(_OP[p.op], p.attr, p.k, p.q, p.num, p.den, p.d)
+            preds[x] = HbPred(_OP[p.op], p.attr, p.k, p.q, p.num, p.den, p.d, getattr(p, "attr_b", 0),
+                              getattr(p, "side", 0), getattr(p, "c", 0))
         keep.append(preds)
         crules[r] = HbRule(len(rule), ctypes.cast(preds, ctypes.POINTER(HbPred)))
     return crules, keep
@@ -297,7 +299,9 @@ def _c_rules(rules):
 
 def hb_compile_rules(ctx: Context, rel_id: int, rules) -> int:
     """rules: list of rules, each a list of predicates with fields
-    op ('eq'|'ed'|'jaccard'|'absdiff'), attr, k, q, num, den, d."""
+    op ('eq'|'ed'|'jaccard'|'absdiff'|'eq_const'|'eq_cross'), attr, k, q,
+    num, den, d, attr_b (t.A = s.B), side and c (t.A = c: side 0; s.A = c:
+    side 1)."""
     crules, keep = _c_rules(rules)
     rs = ctypes.c_uint32()
     ctx.check(_lib.hb_compile_rules(ctx.h, rel_id, len(rules), crules, ctypes.byref(rs)))

@@ -269,6 +269,8 @@ static bool same_pred(const hb_pred& a, const hb_pred& b) {
     case HB_ED_LE: return a.k == b.k;
     case HB_JACCARD_GE: return a.q == b.q && a.num == b.num && a.den == b.den;
     case HB_ABSDIFF_LE: return a.d == b.d;
+    case HB_EQ_CONST: return a.side == b.side && a.c == b.c;
+    case HB_EQ_CROSS: return a.attr_b == b.attr_b;
     default: return true;
     }
 }
@@ -281,6 +283,8 @@ static double pred_cost(const Relation& rel, const hb_pred& p) {
     case HB_ABSDIFF_LE: return 1.5;
     case HB_ED_LE: return 4.0 + 17.0 * L * std::max(1.0, std::ceil(L / 64.0));
     case HB_JACCARD_GE: return 4.0 + 6.0 * std::max(1.0, L - (double)p.q + 1.0);
+    case HB_EQ_CONST: return 1.0;
+    case HB_EQ_CROSS: return 2.0;   // one compare per valuation
     }
     return 1.0;
 }
@@ -330,6 +334,17 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
                 if (t != HB_COL_INT64) fail(HB_ERR_TYPE, where + ": |a-b| <= d needs an int64 attribute");
                 if (p.d < 0) fail(HB_ERR_INVALID_ARG, where + ": d must be >= 0");
                 break;
+            case HB_EQ_CONST:
+                if (t == HB_COL_STRING) fail(HB_ERR_TYPE, where + ": t.A = c needs a categorical or int64 attribute");
+                if (p.side != 0 && p.side != 1) fail(HB_ERR_INVALID_ARG, where + ": side must be 0 (t) or 1 (s)");
+                rs->ordered = true;
+                break;
+            case HB_EQ_CROSS:
+                if (p.attr_b >= rel.n_cols) fail(HB_ERR_INVALID_ARG, where + ": attribute B out of range");
+                if (t == HB_COL_STRING || rel.cols[p.attr_b].type == HB_COL_STRING)
+                    fail(HB_ERR_TYPE, where + ": t.A = s.B needs categorical or int64 attributes");
+                if (p.attr_b != p.attr) rs->ordered = true;
+                break;
             default:
                 fail(HB_ERR_INVALID_ARG, where + ": unknown operator");
             }
@@ -342,6 +357,8 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
                 if (np.op != HB_ED_LE) np.k = 0;
                 if (np.op != HB_JACCARD_GE) { np.q = 0; np.num = 0; np.den = 1; }
                 if (np.op != HB_ABSDIFF_LE) np.d = 0;
+                if (np.op != HB_EQ_CROSS) np.attr_b = 0;
+                if (np.op != HB_EQ_CONST) { np.side = 0; np.c = 0; }
                 rs->distinct.push_back(np);
             }
             if (std::find(ids.begin(), ids.end(), id) == ids.end()) ids.push_back(id);
@@ -373,7 +390,9 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
         }
         if (same[p] != p) continue;
         if (pr.op == HB_JACCARD_GE) gram_index(c, rel, pr.attr, pr.q);
-        const int op = pr.op == HB_EQ ? 0 : pr.op == HB_ED_LE ? 1 : pr.op == HB_JACCARD_GE ? 2 : 3;
+        // t.A = c and t.A = s.B take the equality hash of A: their sp is
+        // that of t.A = s.A (it orders predicates only)
+        const int op = pr.op == HB_ED_LE ? 1 : pr.op == HB_JACCARD_GE ? 2 : pr.op == HB_ABSDIFF_LE ? 3 : 0;
         c->timed("lsh", [&] {
             return launch_lsh_hist(rel.d_cols.as<ColDev>() + pr.attr, rel.n_rows, op, pr.q, pr.d,
                                    hist.as<unsigned long long>() + p * kLshK, c->stream);
@@ -661,6 +680,21 @@ static KeyRes key_resources(const Relation& rel, const RuleSet& rs, size_t ka) {
             sp.param = (uint64_t)d.k;
             R.any_ed = true;
             break;
+        case HB_EQ_CONST:
+            sp.op = OP_CONST;
+            sp.res = (uint8_t)res_of(R.int_attr, d.attr);
+            sp.aux = (uint8_t)d.side;
+            sp.param = (uint64_t)d.c;
+            break;
+        case HB_EQ_CROSS:
+            sp.res = (uint8_t)res_of(R.int_attr, d.attr);
+            if (d.attr_b == d.attr) {
+                sp.op = OP_EQ_INT;
+            } else {
+                sp.op = OP_XEQ;
+                sp.aux = (uint8_t)res_of(R.int_attr, d.attr_b);
+            }
+            break;
         case HB_JACCARD_GE: {
             auto gk = std::make_pair(d.attr, d.q);
             auto it = std::find(R.gram_key.begin(), R.gram_key.end(), gk);
@@ -701,12 +735,15 @@ static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, cons
             Instr in{};
             in.slot = (uint8_t)p;
             in.res = sp->res;
+            in.aux = sp->aux;
             in.param = sp->param;
             Instr f = in;
             f.slot = (uint8_t)(64 + p);
             switch (sp->op) {
             case OP_EQ_INT:
             case OP_ABSDIFF:
+            case OP_CONST:
+            case OP_XEQ:
                 in.op = sp->op;
                 code.push_back(in);
                 break;
@@ -762,6 +799,7 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     m.n_str = (uint32_t)R.str_attr.size();
     m.n_gram = (uint32_t)R.gram_key.size();
     m.n_prev = (uint32_t)R.prev.size();
+    m.ordered = rs.ordered ? 1u : 0u;
     for (size_t x = 0; x < R.int_attr.size(); ++x) m.int_attr[x] = R.int_attr[x];
     for (size_t x = 0; x < R.prev.size(); ++x) m.prev_res[x] = R.prev[x];
     GatherParams gp{};
@@ -962,6 +1000,7 @@ static void log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t sample
     if (!n_rows) fail(HB_ERR_INVALID_ARG, "NULL n_rows");
     if (samples == 0 || samples > 4096) fail(HB_ERR_INVALID_ARG, "samples must be in [1, 4096]");
     if (!rs.partitioned) fail(HB_ERR_STATE, "hb_partition must run before hb_log_collect");
+    if (rs.ordered) fail(HB_ERR_INVALID_ARG, "cost-model logs take rule sets of t.A = s.A and t.A ~ s.A predicates only");
     uint64_t total = 0;
     struct Part {
         std::vector<float> f;
@@ -1089,6 +1128,8 @@ void sort_pairs(Ctx* c, DevBuf& pairs, uint64_t n, uint64_t n_rows, DevBuf& resu
 }
 
 static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stats* ws = nullptr) {
+    if (rs.ordered && (ws || plan == HB_PLAN_LEARNED))
+        fail(HB_ERR_INVALID_ARG, "learned plans and work counts take rule sets of t.A = s.A and t.A ~ s.A predicates only");
     const std::vector<PathRule> path = plan_path(rs, plan);
     std::vector<KeyPlan> kps;
     size_t total_code = 0;

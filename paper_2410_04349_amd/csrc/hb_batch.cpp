@@ -213,6 +213,7 @@ static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, 
         Relation& rel = get_rel(c, jobs[j].rel_id);
         RuleSet& rs = get_rs(c, jobs[j].ruleset_id, jobs[j].rel_id);
         if (!rs.partitioned) fail(HB_ERR_STATE, "hb_partition must run on every job before hb_batch_create");
+        if (rs.ordered) fail(HB_ERR_INVALID_ARG, "batches take rule sets of t.A = s.A and t.A ~ s.A predicates only");
         Batch::Job job;
         job.rel_id = jobs[j].rel_id;
         job.rs_id = jobs[j].ruleset_id;

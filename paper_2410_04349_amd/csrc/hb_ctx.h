@@ -125,6 +125,7 @@ struct RuleSet {
     std::vector<hb_pred> distinct;
     std::vector<std::vector<uint32_t>> rules;  // distinct predicate ids per rule, input order
     std::vector<uint32_t> keys;                // blocking-key attributes, first-appearance order
+    bool ordered = false;                      // a predicate tells t from s: ordered output
     std::vector<double> sp, cost;
     std::vector<std::vector<uint64_t>> buckets;
     std::vector<uint64_t> bucket_n;

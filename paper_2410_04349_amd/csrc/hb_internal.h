@@ -64,7 +64,11 @@ enum Op : uint8_t {
     OP_EQ_STR = 5,   // verify: byte equality
     OP_ED = 6,       // verify: Levenshtein distance <= k (Myers)
     OP_JAC = 7,      // verify: q-gram Jaccard >= num / den (merge intersection)
-    OP_CP = 8        // rule end: the pair has a witness
+    OP_CP = 8,       // rule end: the pair has a witness
+    // predicates that tell t from s (ordered rule sets only; the pair's two
+    // valuations get a mask each)
+    OP_CONST = 9,    // t.A = c (aux 0) or s.A = c (aux 1); param = c
+    OP_XEQ = 10      // t.A = s.B: res = A, aux = B (both int resources)
 };
 
 // One step of the sequential execution path.  `slot` identifies the step
@@ -77,7 +81,7 @@ struct Instr {
     uint8_t op;
     uint8_t slot;
     uint8_t res;
-    uint8_t pad0;
+    uint8_t aux;    // OP_CONST: side; OP_XEQ: resource of B
     uint16_t cp;
     uint16_t pad1;
     uint64_t param;
@@ -115,7 +119,7 @@ struct MatchParams {
     const uint64_t* tile_prefix;   // n_blocks + 1 entries
     const uint32_t* tile_blk;      // block of each tile (n_tiles entries)
     uint32_t n_blocks;
-    uint32_t pad0;
+    uint32_t ordered;   // 1: the rule set tells t from s (both valuations of a pair, ordered output)
     uint64_t n_tiles;
     // plan
     const Instr* plan;
@@ -252,7 +256,8 @@ struct PredSpec {
     uint8_t op;
     uint8_t res;
     uint16_t pred;     // distinct predicate id in the rule set
-    uint32_t pad;
+    uint8_t aux;       // as Instr::aux
+    uint8_t pad[3];
     uint64_t param;
 };
 constexpr int kMaxSpecs = 64;

@@ -267,7 +267,12 @@ __device__ inline void decode_tile(const MatchParams& P, uint64_t t, uint32_t* b
 // j-row and reads its features from the columns when a step needs them.
 // Wave-uniform values are passed through readfirstlane so the compiler
 // keeps them (and the loads they address) scalar.
-template <bool kCount, bool kLongEd = false>
+// kOrd (rule sets that tell t from s): the pair (row r, lane j) has two
+// valuations, t -> row, s -> lane ("forward") and t -> lane, s -> row
+// ("backward"), each with its own alive and matched masks; symmetric steps
+// run once for the union and narrow both, and each valuation that reaches
+// a checkpoint emits its ordered pair.
+template <bool kCount, bool kLongEd = false, bool kOrd = false>
 __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL Instr* __restrict__ plan,
                                            const HB_GLOBAL uint64_t* __restrict__ f64,
                                            const HB_GLOBAL uint32_t* __restrict__ f32, uint64_t t, uint8_t* lds,
@@ -337,6 +342,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
         }
 
         uint32_t matched = 0, alive = pairs;
+        uint32_t fwd = pairs, bwd = pairs, matched_b = 0;   // kOrd only: alive = fwd | bwd
         uint32_t pc = 0;
         while (pc < plen) {
             pc = __builtin_amdgcn_readfirstlane(pc);
@@ -349,13 +355,55 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             const uint32_t cp = raw.y & 0xFFFFu;
             const uint64_t param = ((uint64_t)raw.w << 32) | raw.z;
             if (op == OP_CP) {
-                matched |= alive;
-                alive = pairs & ~matched;
+                if constexpr (kOrd) {
+                    matched |= fwd;
+                    matched_b |= bwd;
+                    fwd = pairs & ~matched;
+                    bwd = pairs & ~matched_b;
+                    alive = fwd | bwd;
+                } else {
+                    matched |= alive;
+                    alive = pairs & ~matched;
+                }
                 if (!__any(alive != 0)) break;   // every pair is matched or absent
                 ++pc;
                 continue;
             }
             if (!__any(alive != 0)) { pc = cp; continue; }
+            if constexpr (kOrd) {
+                if (op >= OP_CONST) {
+                    // a predicate that tells t from s: one mask per valuation
+                    const uint32_t aux = (raw.x >> 24) & 0xFFu;
+                    uint32_t kf, kb;
+                    if (op == OP_CONST) {   // t.A = c (aux 0) or s.A = c (aux 1), A = res
+                        const int64_t c = (int64_t)param;
+                        const uint32_t lane_hit = ((vmask_j >> res) & 1) && (int64_t)J64(res) == c ? ~0u : 0u;
+                        uint32_t rows = 0;
+#pragma unroll
+                        for (int r = kRows - 1; r >= 0; --r)
+                            rows = push_bit(rows, __ballot((int64_t)f64[res * n + pi0 + (uint64_t)r] == c));
+                        rows &= row_bits(f32 + n, pi0, res);
+                        kf = aux == 0 ? rows : lane_hit;
+                        kb = aux == 0 ? lane_hit : rows;
+                    } else {   // OP_XEQ: t.A = s.B, A = res, B = aux
+                        const int64_t ja = (int64_t)J64(res), jb = (int64_t)J64(aux);
+                        uint32_t f = 0, g = 0;
+#pragma unroll
+                        for (int r = kRows - 1; r >= 0; --r) {
+                            const uint64_t pr = pi0 + (uint64_t)r;
+                            f = push_bit(f, __ballot((int64_t)f64[res * n + pr] == jb));   // t = row: row.A = lane.B
+                            g = push_bit(g, __ballot((int64_t)f64[aux * n + pr] == ja));   // t = lane: lane.A = row.B
+                        }
+                        kf = (vmask_j >> aux) & 1 ? f & row_bits(f32 + n, pi0, res) : 0u;
+                        kb = (vmask_j >> res) & 1 ? g & row_bits(f32 + n, pi0, aux) : 0u;
+                    }
+                    fwd &= kf;
+                    bwd &= kb;
+                    alive = fwd | bwd;
+                    ++pc;
+                    continue;
+                }
+            }
             const uint32_t before = alive;
             uint32_t work = 0;
             switch (op) {
@@ -571,6 +619,10 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 break;
             }
             }
+            if constexpr (kOrd) {   // a symmetric step narrows both valuations alike
+                fwd &= alive;
+                bwd &= alive;
+            }
             if constexpr (kCount) {
                 // batches: this step ran once for the wave's 16-row batch
                 uint32_t ev = 0, ps = 0;
@@ -594,7 +646,29 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
 
         // ballot compaction of matched pairs, row by row (most batches
         // have none)
-        const int out_rows = __any(matched != 0) ? nr : 0;
+        if constexpr (kOrd) {
+            // forward matches as (row, lane), backward ones as (lane, row)
+            const int out_rows = __any((matched | matched_b) != 0) ? nr : 0;
+            for (int r = 0; r < out_rows; ++r) {
+                const uint64_t row_i = f32[pi0 + r];
+#pragma unroll
+                for (int dir = 0; dir < 2; ++dir) {
+                    const bool m = (((dir == 0 ? matched : matched_b)) >> r) & 1;
+                    const uint64_t mask = __ballot(m);
+                    if (!mask) continue;
+                    unsigned long long basev = 0;
+                    if (lane == 0) basev = atomicAdd(P.counter, (unsigned long long)__popcll(mask));
+                    basev = __shfl(basev, 0);
+                    if (m) {
+                        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+                        const uint64_t pos = basev + __popcll(mask & lt);
+                        if (pos < P.cap)
+                            P.out[pos] = dir == 0 ? (row_i << 32) | row_j : ((uint64_t)row_j << 32) | row_i;
+                    }
+                }
+            }
+        }
+        const int out_rows = kOrd ? 0 : __any(matched != 0) ? nr : 0;
         for (int r = 0; r < out_rows; ++r) {
             const bool m = (matched >> r) & 1;
             const uint64_t mask = __ballot(m);
@@ -657,6 +731,27 @@ __global__ __launch_bounds__(64) void k_match_long(const MatchParams P, const In
     const uint64_t t = w >> 2;
     if (t >= P.n_tiles) return;
     match_tile<kCount, true>(P, gmem(plan), gmem(f64), gmem(f32), t, lds, (int)(w & 3));
+}
+
+// k_match and k_match_long for ordered rule sets (no instrumented pass).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_match_ord(
+    const MatchParams P, const Instr* __restrict__ plan, const uint64_t* __restrict__ f64,
+    const uint32_t* __restrict__ f32) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const uint64_t w = batch_unit(blockIdx.x);
+    const uint64_t t = w >> 2;
+    if (t >= P.n_tiles) return;
+    match_tile<false, false, true>(P, gmem(plan), gmem(f64), gmem(f32), t, lds, (int)(w & 3));
+}
+
+__global__ __launch_bounds__(64) void k_match_long_ord(const MatchParams P, const Instr* __restrict__ plan,
+                                                       const uint64_t* __restrict__ f64,
+                                                       const uint32_t* __restrict__ f32) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const uint64_t w = batch_unit(blockIdx.x);
+    const uint64_t t = w >> 2;
+    if (t >= P.n_tiles) return;
+    match_tile<false, true, true>(P, gmem(plan), gmem(f64), gmem(f32), t, lds, (int)(w & 3));
 }
 
 // partition of queue item x: prefix[p] <= x < prefix[p + 1]
@@ -1170,8 +1265,24 @@ static hipError_t allow_lds(const void* fn, int* configured, uint32_t bytes) {
 hipError_t launch_match(const MatchParams& p, hipStream_t s) {
     if (p.n_tiles == 0) return hipSuccess;
     if (p.n_tiles > kMaxTiles) return hipErrorInvalidValue;   // the grid holds 4 x n_tiles workgroups
-    static int configured[4] = {0, 0, 0, 0};
+    static int configured[6] = {0, 0, 0, 0, 0, 0};
     const unsigned grid = (unsigned)((p.n_tiles * 4 + 31) & ~31ull);   // batch_unit needs a multiple of 32
+    if (p.ordered) {
+        if (p.counts) return hipErrorInvalidValue;   // no instrumented pass for ordered rule sets
+        if (p.ed_words >= 2) {
+            MatchParams q = p;
+            q.lds_counts = p.lds_wave_myers;
+            q.lds_bytes = (q.lds_counts + 15) & ~15u;
+            hipError_t e = allow_lds((const void*)k_match_long_ord, &configured[5], q.lds_bytes);
+            if (e != hipSuccess) return e;
+            k_match_long_ord<<<grid, 64, q.lds_bytes, s>>>(q, q.plan, q.feat.f64, q.feat.f32);
+        } else {
+            hipError_t e = allow_lds((const void*)k_match_ord, &configured[4], p.lds_bytes);
+            if (e != hipSuccess) return e;
+            k_match_ord<<<grid, 64, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
+        }
+        return hipGetLastError();
+    }
     if (p.ed_words >= 2) {
         // the register-state kernel leaves out the LDS Myers region (the
         // layout's last one)

@@ -122,7 +122,7 @@ def eval_in_chunks(rel, rules, pairs, chunk=200_000):
     return out
 
 
-def check(hb, ctx, rel, rules, n_sample, seed, plans=("heuristic", "learned"), max_sample=None):
+def check(hb, ctx, rel, rules, n_sample, seed, plans=("heuristic", "learned"), max_sample=None, ordered=False):
     rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
     rs = hb.hb_compile_rules(ctx, rid, rules)
     n_cand = hb.hb_partition(ctx, rid, rs)
@@ -146,6 +146,8 @@ def check(hb, ctx, rel, rules, n_sample, seed, plans=("heuristic", "learned"), m
     sample = sample_pairs(rel, keys, n_sample, seed)
     if max_sample is not None and len(sample) > max_sample:
         sample = np.sort(np.random.default_rng(seed).choice(sample, size=max_sample, replace=False))
+    if ordered:   # both valuations of every sampled pair
+        sample = np.unique(np.concatenate([sample, (sample << np.uint64(32)) | (sample >> np.uint64(32))]))
     want = ev(sample)
     have = np.isin(sample, got)
     assert np.array_equal(have, want), int(np.sum(have != want))
@@ -161,6 +163,14 @@ def test_plain_1m_full_size(hb, ctx):
 def test_long_titles_5m_full_size(hb, ctx):
     rel, rules = workloads.long_titles_5m()
     check(hb, ctx, rel, rules, 200_000, 2)
+
+
+def test_plain_1m_ordered_full_size(hb, ctx):
+    """plain_1m under a rule set with t.i1 = 7 (ordered output), in the
+    benchmark's grammar leg: every listed ordered pair confirmed by the
+    oracle's valuation, both orders of a candidate sample checked."""
+    rel, _ = workloads.plain_1m()
+    check(hb, ctx, rel, workloads.plain_1m_ordered_rules(), 150_000, 4, plans=("heuristic",), ordered=True)
 
 
 def test_learned_10m_full_size(hb, ctx):

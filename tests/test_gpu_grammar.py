@@ -1,0 +1,148 @@
+"""GPU parity of the predicates t.A = c, s.A = c and t.A = s.B: libhb's
+ordered listing of Ca, through the C ABI, is bit-exact against the oracle's,
+for every non-learned plan, across tiles and their diagonals, with two keys,
+and with edit-distance patterns past 64 bytes.  Calls the ordered path does
+not take are refused."""
+import numpy as np
+import pytest
+
+import oracle
+from gen import (CATEGORICAL, ED, EQ, EQ_CONST, EQ_CROSS, INT64, Pred, Relation, int_column,
+                 string_column)
+from test_oracle_grammar import KEY, hand_relation, random_relation, random_rules
+
+pytestmark = pytest.mark.gpu
+
+PLANS = ["given", "heuristic", "cheapest", "selective", "random_preds", "random_rules"]
+
+
+@pytest.fixture(scope="module")
+def hb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_04349_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(hb):
+    c = hb.hb_create(0, allocator="torch")
+    yield c
+    c.close()
+
+
+def show(case):
+    print(f"[gpu-case] {case}", flush=True)
+
+
+def match_all(hb, ctx, rel, rules, plans):
+    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+    rs = hb.hb_compile_rules(ctx, rid, rules)
+    hb.hb_partition(ctx, rid, rs)
+    outs = {p: hb.hb_match(ctx, rid, rs, p) for p in plans}
+    hb.hb_release_relation(ctx, rid)
+    return outs
+
+
+def check(hb, ctx, rel, rules, plans=PLANS):
+    want = oracle.blocking(rel, rules, threads=8)
+    for plan, got in match_all(hb, ctx, rel, rules, plans).items():
+        assert np.array_equal(got, want), (plan, len(got), len(want))
+    return want
+
+
+def test_hand_worked(hb, ctx):
+    show("grammar: hand-worked relation")
+    rel = hand_relation()
+    for rules in ([[KEY, Pred(EQ_CONST, 1, side=0, c=1)]],
+                  [[KEY, Pred(EQ_CONST, 2, side=1, c=1)]],
+                  [[KEY, Pred(EQ_CROSS, 1, attr_b=2)]],
+                  [[KEY, Pred(EQ_CONST, 2, side=1, c=1)], [KEY, Pred(EQ, 1)]],
+                  [[KEY, Pred(EQ_CROSS, 1, attr_b=1)]]):
+        check(hb, ctx, rel, rules)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_small(hb, ctx, seed):
+    show(f"grammar: random seed {seed}")
+    check(hb, ctx, random_relation(seed, n=200), random_rules(seed))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_several_tiles(hb, ctx, seed):
+    # blocks of ~250 rows: 4 x 4 tile triangles with ragged edges and diagonals
+    show(f"grammar: several tiles, seed {seed}")
+    rel = random_relation(50 + seed, n=2000, n_keys=8)
+    rules = random_rules(50 + seed)
+    if not oracle.ordered(rules):
+        rules = rules + [[KEY, Pred(EQ_CONST, 1, side=1, c=2)]]
+    want = check(hb, ctx, rel, rules)
+    assert len(want) > 0
+
+
+def test_two_keys(hb, ctx):
+    # a pair sharing both keys is evaluated in the first key's partition only
+    show("grammar: two keys")
+    r = np.random.default_rng(11)
+    n = 1500
+    k1 = int_column("k1", [int(x) for x in r.integers(0, 6, size=n)], CATEGORICAL)
+    k2 = int_column("k2", [int(x) for x in r.integers(0, 5, size=n)], INT64)
+    a = int_column("a", [int(x) for x in r.integers(0, 3, size=n)], CATEGORICAL)
+    b = int_column("b", [int(x) for x in r.integers(0, 3, size=n)], INT64)
+    rel = Relation([k1, k2, a, b], n)
+    rules = [[Pred(EQ, 0), Pred(EQ_CROSS, 2, attr_b=3), Pred(EQ_CONST, 3, side=0, c=1)],
+             [Pred(EQ, 1), Pred(EQ_CONST, 2, side=1, c=0)],
+             [Pred(EQ, 1), Pred(EQ, 2), Pred(EQ, 3)]]
+    check(hb, ctx, rel, rules)
+
+
+def test_long_edit_distance_patterns(hb, ctx):
+    # strings past 64 bytes take the register-state Myers kernel
+    show("grammar: long edit-distance patterns")
+    r = np.random.default_rng(5)
+    n = 600
+    base = [bytes(r.integers(97, 100, size=int(r.integers(60, 140))).astype(np.uint8)) for _ in range(n // 2)]
+    strings = []
+    for s in base:
+        strings.append(s)
+        t = bytearray(s)
+        for _ in range(int(r.integers(0, 4))):
+            t[int(r.integers(0, len(t)))] = int(r.integers(97, 100))
+        strings.append(bytes(t))
+    rel = Relation([int_column("k", [int(x) for x in r.integers(0, 4, size=n)], CATEGORICAL),
+                    string_column("s", strings),
+                    int_column("a", [int(x) for x in r.integers(0, 2, size=n)], CATEGORICAL)], n)
+    rules = [[Pred(EQ, 0), Pred(EQ_CONST, 2, side=0, c=1), Pred(ED, 1, k=3)]]
+    want = check(hb, ctx, rel, rules, plans=["given", "heuristic"])
+    assert len(want) > 0
+
+
+def test_refused_calls(hb, ctx):
+    show("grammar: refused calls")
+    rel = hand_relation()
+    rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
+    rs = hb.hb_compile_rules(ctx, rid, [[KEY, Pred(EQ_CONST, 1, side=0, c=1)]])
+    hb.hb_partition(ctx, rid, rs)
+    for call in (lambda: hb.hb_match(ctx, rid, rs, "learned"),
+                 lambda: hb.hb_match_work(ctx, rid, rs, "heuristic"),
+                 lambda: hb.hb_batch_create(ctx, [(rid, rs)], "heuristic", graph=False)):
+        with pytest.raises(hb.HbError) as e:
+            call()
+        assert e.value.status == hb.HB_ERR_INVALID_ARG
+    s = string_column("s", [b"x"] * rel.n_rows)
+    rid2 = hb.hb_load_relation(ctx, rel.columns + [s], rel.n_rows)
+    for rule, status in (([KEY, Pred(EQ_CONST, 3, side=0, c=1)], hb.HB_ERR_TYPE),     # constant on a string
+                         ([KEY, Pred(EQ_CROSS, 1, attr_b=3)], hb.HB_ERR_TYPE),        # B is a string
+                         ([KEY, Pred(EQ_CROSS, 1, attr_b=9)], hb.HB_ERR_INVALID_ARG),
+                         ([KEY, Pred(EQ_CONST, 1, side=2, c=1)], hb.HB_ERR_INVALID_ARG),
+                         ([Pred(EQ_CROSS, 0, attr_b=0)], hb.HB_ERR_UNBLOCKABLE)):   # never a key
+        with pytest.raises(hb.HbError) as e:
+            hb.hb_compile_rules(ctx, rid2, [rule])
+        assert e.value.status == status, rule
+    # the plain path is unaffected: the same relation with a symmetric rule
+    rs3 = hb.hb_compile_rules(ctx, rid, [[KEY, Pred(EQ, 1)]])
+    hb.hb_partition(ctx, rid, rs3)
+    assert np.array_equal(hb.hb_match(ctx, rid, rs3, "heuristic"), oracle.blocking(rel, [[KEY, Pred(EQ, 1)]]))
+    hb.hb_release_relation(ctx, rid)
+    hb.hb_release_relation(ctx, rid2)
