@@ -25,7 +25,7 @@ _SRC = os.path.join(_HERE, "hboracle.cpp")
 _LIB = os.path.join(_HERE, "libhboracle.so")
 
 _TYPES = {"string": 0, "categorical": 1, "int64": 2}
-_OPS = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3, "eq_const": 4, "eq_cross": 5}
+_OPS = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3, "eq_const": 4, "eq_cross": 5, "ed_cross": 6}
 
 
 class _Col(ctypes.Structure):
@@ -140,7 +140,8 @@ def rule_witness(rel, rule, i: int, j: int) -> bool:
 
 def ordered(rules) -> bool:
     """True if some predicate tells t from s (t.A = c, s.A = c, or t.A = s.B
-    over two different attributes): Ca then lists ordered pairs."""
+    or t.A ~ s.B over two different attributes): Ca then lists ordered
+    pairs."""
     flat = [p for r in rules for p in r]
     lens = (ctypes.c_uint32 * max(1, len(rules)))(*[len(r) for r in rules])
     preds = (_Pred * max(1, len(flat)))(*[to_cpred(p) for p in flat])

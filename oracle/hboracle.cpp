@@ -29,6 +29,8 @@
  *   - t.A = c holds iff t's A is present and equals c (an int64 constant on
  *     a categorical or int64 attribute); t.A = s.B iff both values are
  *     present and equal (Section 2, "Semantics": tuple relational calculus);
+ *     t.A ~ s.B with edit distance iff both strings are present and the
+ *     Levenshtein distance from t's A to s's B is at most k;
  *   - a missing value fails every predicate, including missing = missing
  *     (Table 1 marks missing values; Example 3 and the Section 4 remark on
  *     (t1, t5) treat a missing value as failing equality and similarity);
@@ -61,7 +63,7 @@
 extern "C" {
 
 enum { ORA_STRING = 0, ORA_CATEGORICAL = 1, ORA_INT64 = 2 };
-enum { ORA_EQ = 0, ORA_ED = 1, ORA_JACCARD = 2, ORA_ABSDIFF = 3, ORA_CONST = 4, ORA_CROSS = 5 };
+enum { ORA_EQ = 0, ORA_ED = 1, ORA_JACCARD = 2, ORA_ABSDIFF = 3, ORA_CONST = 4, ORA_CROSS = 5, ORA_ED_CROSS = 6 };
 
 struct ora_col {
     int32_t type;
@@ -79,7 +81,7 @@ struct ora_pred {
     uint32_t num;
     uint32_t den;
     int64_t d;
-    uint32_t attr_b;  /* ORA_CROSS: the attribute B of t.A = s.B */
+    uint32_t attr_b;  /* ORA_CROSS, ORA_ED_CROSS: the attribute B of t.A = s.B, t.A ~ s.B */
     int32_t side;     /* ORA_CONST: 0 for t.A = c, 1 for s.A = c */
     int64_t c;        /* ORA_CONST: the constant */
 };
@@ -168,6 +170,10 @@ bool sat(const ora_col* cols, const ora_pred& p, uint64_t i, uint64_t j, const G
         const ora_col& b = cols[p.attr_b];
         return is_valid(c, i) && is_valid(b, j) && c.values[i] == b.values[j];
     }
+    if (p.op == ORA_ED_CROSS) {
+        const ora_col& b = cols[p.attr_b];
+        return is_valid(c, i) && is_valid(b, j) && levenshtein(str_at(c, i), str_at(b, j)) <= p.k;
+    }
     if (!is_valid(c, i) || !is_valid(c, j)) return false;
     switch (p.op) {
     case ORA_EQ:
@@ -198,12 +204,12 @@ struct RuleSet {
     std::vector<std::vector<ora_pred>> rules;
 };
 
-/* Does some predicate tell t from s (a constant on one side, or an
- * equality across two different attributes)? */
+/* Does some predicate tell t from s (a constant on one side, or a
+ * comparison across two different attributes)? */
 bool ordered_rules(const RuleSet& rs) {
     for (const auto& rule : rs.rules)
         for (const auto& p : rule)
-            if (p.op == ORA_CONST || (p.op == ORA_CROSS && p.attr != p.attr_b)) return true;
+            if (p.op == ORA_CONST || ((p.op == ORA_CROSS || p.op == ORA_ED_CROSS) && p.attr != p.attr_b)) return true;
     return false;
 }
 

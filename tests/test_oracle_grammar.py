@@ -1,5 +1,6 @@
-"""Pins of the oracle's predicates t.A = c, s.A = c and t.A = s.B (Section 2,
-"Predicates" and "Semantics") and of its ordered listing of Ca (CPU only).
+"""Pins of the oracle's predicates t.A = c, s.A = c, t.A = s.B and t.A ~ s.B
+under edit distance (Section 2, "Predicates" and "Semantics") and of its
+ordered listing of Ca (CPU only).
 
 A valuation binds t to the pair's first row and s to its second; a rule set
 with a predicate that tells t from s lists every ordered pair whose valuation
@@ -11,7 +12,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gen import CATEGORICAL, ED, EQ, EQ_CONST, EQ_CROSS, INT64, Pred, Relation, int_column, string_column
+from gen import (CATEGORICAL, ED, ED_CROSS, EQ, EQ_CONST, EQ_CROSS, INT64, Pred, Relation, int_column,
+                 string_column)
 
 
 def P(i, j):
@@ -68,11 +70,30 @@ def test_hand_worked_mixed_rule_set():
     assert np.array_equal(got, pairs((0, 1), (0, 2), (1, 2), (2, 0), (2, 1), (3, 4)))
 
 
+def test_hand_worked_cross_edit_distance():
+    #  row  k  x      y
+    #   0   1  abc    abd
+    #   1   1  xyz    abc
+    #   2   1  abd    -
+    # ED(t.x, s.y): (0,1) abc/abc 0; (0,2) y missing; (1,0) xyz/abd 3;
+    # (1,2) y missing; (2,0) abd/abd 0; (2,1) abd/abc 1
+    rel = Relation([int_column("k", [1, 1, 1], CATEGORICAL), string_column("x", [b"abc", b"xyz", b"abd"]),
+                    string_column("y", [b"abd", b"abc", None])], 3)
+    got0 = oracle.blocking(rel, [[KEY, Pred(ED_CROSS, 1, attr_b=2, k=0)]])
+    assert np.array_equal(got0, pairs((0, 1), (2, 0)))
+    got1 = oracle.blocking(rel, [[KEY, Pred(ED_CROSS, 1, attr_b=2, k=1)]])
+    assert np.array_equal(got1, pairs((0, 1), (2, 0), (2, 1)))
+    got3 = oracle.blocking(rel, [[KEY, Pred(ED_CROSS, 1, attr_b=2, k=3)]])
+    assert np.array_equal(got3, pairs((0, 1), (1, 0), (2, 0), (2, 1)))
+
+
 def test_ordered_flag():
     assert not oracle.ordered([[KEY, Pred(EQ, 1)]])
     assert not oracle.ordered([[KEY, Pred(EQ_CROSS, 1, attr_b=1)]])
     assert oracle.ordered([[KEY, Pred(EQ_CROSS, 1, attr_b=2)]])
     assert oracle.ordered([[KEY], [KEY, Pred(EQ_CONST, 1, side=1, c=0)]])
+    assert oracle.ordered([[KEY, Pred(ED_CROSS, 1, attr_b=2, k=1)]])
+    assert not oracle.ordered([[KEY, Pred(ED_CROSS, 1, attr_b=1, k=1)]])
 
 
 def random_relation(seed, n=160, n_keys=6, dom=4, p_missing=0.1):
@@ -88,18 +109,22 @@ def random_relation(seed, n=160, n_keys=6, dom=4, p_missing=0.1):
     c = int_column("c", vals(dom), INT64)
     s = string_column("s", [bytes(r.integers(97, 100, size=int(r.integers(1, 6))).astype(np.uint8))
                             for _ in range(n)])
-    return Relation([k, a, b, c, s], n)
+    u = string_column("u", [None if r.random() < p_missing else
+                            bytes(r.integers(97, 100, size=int(r.integers(0, 6))).astype(np.uint8))
+                            for _ in range(n)])
+    return Relation([k, a, b, c, s, u], n)
 
 
 def random_rules(seed):
     """1-3 rules over the key, each with 1-3 of: a constant on t or s, a
-    cross-attribute equality, a plain equality, an edit distance."""
+    cross-attribute equality, a plain equality, an edit distance, an edit
+    distance across the two string attributes."""
     r = np.random.default_rng(seed)
     rules = []
     for _ in range(int(r.integers(1, 4))):
         rule = [KEY]
         for _ in range(int(r.integers(1, 4))):
-            kind = int(r.integers(0, 4))
+            kind = int(r.integers(0, 5))
             if kind == 0:
                 rule.append(Pred(EQ_CONST, int(r.integers(1, 4)), side=int(r.integers(0, 2)), c=int(r.integers(0, 4))))
             elif kind == 1:
@@ -107,8 +132,11 @@ def random_rules(seed):
                 rule.append(Pred(EQ_CROSS, int(a), attr_b=int(b)))
             elif kind == 2:
                 rule.append(Pred(EQ, int(r.integers(1, 4))))
-            else:
+            elif kind == 3:
                 rule.append(Pred(ED, 4, k=int(r.integers(0, 3))))
+            else:
+                a = int(r.integers(4, 6))
+                rule.append(Pred(ED_CROSS, a, attr_b=9 - a, k=int(r.integers(0, 3))))
         rules.append(rule)
     return rules
 
@@ -119,6 +147,8 @@ def transpose_pred(p):
         return Pred(EQ_CONST, p.attr, side=1 - p.side, c=p.c)
     if p.op == EQ_CROSS:
         return Pred(EQ_CROSS, p.attr_b, attr_b=p.attr)
+    if p.op == ED_CROSS:   # the distance is symmetric in its two strings
+        return Pred(ED_CROSS, p.attr_b, attr_b=p.attr, k=p.k)
     return p
 
 
@@ -143,6 +173,10 @@ def test_cross_on_one_attribute_is_equality(seed):
         got = oracle.blocking(rel, [[KEY, Pred(EQ_CROSS, a, attr_b=a)]])
         want = oracle.blocking(rel, [[KEY, Pred(EQ, a)]])
         assert np.array_equal(got, want)
+    for a in (4, 5):
+        for k in (0, 2):
+            got = oracle.blocking(rel, [[KEY, Pred(ED_CROSS, a, attr_b=a, k=k)]])
+            assert np.array_equal(got, oracle.blocking(rel, [[KEY, Pred(ED, a, k=k)]]))
 
 
 @pytest.mark.parametrize("seed", range(6))
