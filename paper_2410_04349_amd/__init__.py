@@ -35,7 +35,7 @@ HB_PLAN_HEURISTIC = 1
 HB_PLAN_LEARNED = 2
 
 _COLTYPE = {"string": 0, "categorical": 1, "int64": 2}
-_OP = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3, "eq_const": 4, "eq_cross": 5}
+_OP = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3, "eq_const": 4, "eq_cross": 5, "ed_cross": 6}
 HB_PLAN_CHEAPEST, HB_PLAN_SELECTIVE, HB_PLAN_RANDOM_PREDS, HB_PLAN_RANDOM_RULES = 3, 4, 5, 6
 _PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC, "learned": HB_PLAN_LEARNED,
          "cheapest": HB_PLAN_CHEAPEST, "selective": HB_PLAN_SELECTIVE,
@@ -299,9 +299,9 @@ def _c_rules(rules):
 
 def hb_compile_rules(ctx: Context, rel_id: int, rules) -> int:
     """rules: list of rules, each a list of predicates with fields
-    op ('eq'|'ed'|'jaccard'|'absdiff'|'eq_const'|'eq_cross'), attr, k, q,
-    num, den, d, attr_b (t.A = s.B), side and c (t.A = c: side 0; s.A = c:
-    side 1)."""
+    op ('eq'|'ed'|'jaccard'|'absdiff'|'eq_const'|'eq_cross'|'ed_cross'),
+    attr, k, q, num, den, d, attr_b (t.A = s.B, t.A ~ s.B), side and c
+    (t.A = c: side 0; s.A = c: side 1)."""
     crules, keep = _c_rules(rules)
     rs = ctypes.c_uint32()
     ctx.check(_lib.hb_compile_rules(ctx.h, rel_id, len(rules), crules, ctypes.byref(rs)))

@@ -271,6 +271,7 @@ static bool same_pred(const hb_pred& a, const hb_pred& b) {
     case HB_ABSDIFF_LE: return a.d == b.d;
     case HB_EQ_CONST: return a.side == b.side && a.c == b.c;
     case HB_EQ_CROSS: return a.attr_b == b.attr_b;
+    case HB_ED_CROSS_LE: return a.attr_b == b.attr_b && a.k == b.k;
     default: return true;
     }
 }
@@ -285,6 +286,10 @@ static double pred_cost(const Relation& rel, const hb_pred& p) {
     case HB_JACCARD_GE: return 4.0 + 6.0 * std::max(1.0, L - (double)p.q + 1.0);
     case HB_EQ_CONST: return 1.0;
     case HB_EQ_CROSS: return 2.0;   // one compare per valuation
+    case HB_ED_CROSS_LE: {          // one Myers run per valuation
+        const double M = std::max(L, rel.cols[p.attr_b].mean_len);
+        return 2.0 * (4.0 + 17.0 * M * std::max(1.0, std::ceil(M / 64.0)));
+    }
     }
     return 1.0;
 }
@@ -345,6 +350,16 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
                     fail(HB_ERR_TYPE, where + ": t.A = s.B needs categorical or int64 attributes");
                 if (p.attr_b != p.attr) rs->ordered = true;
                 break;
+            case HB_ED_CROSS_LE:
+                if (p.attr_b >= rel.n_cols) fail(HB_ERR_INVALID_ARG, where + ": attribute B out of range");
+                if (t != HB_COL_STRING || rel.cols[p.attr_b].type != HB_COL_STRING)
+                    fail(HB_ERR_TYPE, where + ": t.A ~ s.B (edit distance) needs string attributes");
+                if (p.k < 0 || p.k > HB_MAX_ED_K) fail(HB_ERR_INVALID_ARG, where + ": k must be in [0, 255]");
+                if (rel.cols[p.attr].max_len > HB_MAX_ED_LEN || rel.cols[p.attr_b].max_len > HB_MAX_ED_LEN)
+                    fail(HB_ERR_LIMIT, where + ": strings longer than 256 bytes");
+                if (p.attr_b == p.attr) p.op = HB_ED_LE;   // the plain edit distance
+                else rs->ordered = true;
+                break;
             default:
                 fail(HB_ERR_INVALID_ARG, where + ": unknown operator");
             }
@@ -354,10 +369,10 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
             if (id == rs->distinct.size()) {
                 if (rs->distinct.size() >= HB_MAX_DISTINCT_PREDS) fail(HB_ERR_LIMIT, "more than 64 distinct predicates");
                 hb_pred np = p;
-                if (np.op != HB_ED_LE) np.k = 0;
+                if (np.op != HB_ED_LE && np.op != HB_ED_CROSS_LE) np.k = 0;
                 if (np.op != HB_JACCARD_GE) { np.q = 0; np.num = 0; np.den = 1; }
                 if (np.op != HB_ABSDIFF_LE) np.d = 0;
-                if (np.op != HB_EQ_CROSS) np.attr_b = 0;
+                if (np.op != HB_EQ_CROSS && np.op != HB_ED_CROSS_LE) np.attr_b = 0;
                 if (np.op != HB_EQ_CONST) { np.side = 0; np.c = 0; }
                 rs->distinct.push_back(np);
             }
@@ -390,9 +405,11 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
         }
         if (same[p] != p) continue;
         if (pr.op == HB_JACCARD_GE) gram_index(c, rel, pr.attr, pr.q);
-        // t.A = c and t.A = s.B take the equality hash of A: their sp is
-        // that of t.A = s.A (it orders predicates only)
-        const int op = pr.op == HB_ED_LE ? 1 : pr.op == HB_JACCARD_GE ? 2 : pr.op == HB_ABSDIFF_LE ? 3 : 0;
+        // t.A = c and t.A = s.B take the equality hash of A, t.A ~ s.B the
+        // edit-distance hash of A: their sp is that of the predicate on A
+        // alone (it orders predicates only)
+        const int op = pr.op == HB_ED_LE || pr.op == HB_ED_CROSS_LE ? 1
+                     : pr.op == HB_JACCARD_GE ? 2 : pr.op == HB_ABSDIFF_LE ? 3 : 0;
         c->timed("lsh", [&] {
             return launch_lsh_hist(rel.d_cols.as<ColDev>() + pr.attr, rel.n_rows, op, pr.q, pr.d,
                                    hist.as<unsigned long long>() + p * kLshK, c->stream);
@@ -695,6 +712,13 @@ static KeyRes key_resources(const Relation& rel, const RuleSet& rs, size_t ka) {
                 sp.aux = (uint8_t)res_of(R.int_attr, d.attr_b);
             }
             break;
+        case HB_ED_CROSS_LE:   // attr_b != attr (compile turns A = B into HB_ED_LE)
+            sp.op = OP_XED;
+            sp.res = (uint8_t)res_of(R.str_attr, d.attr);
+            sp.aux = (uint8_t)res_of(R.str_attr, d.attr_b);
+            sp.param = (uint64_t)d.k;
+            R.any_ed = true;
+            break;
         case HB_JACCARD_GE: {
             auto gk = std::make_pair(d.attr, d.q);
             auto it = std::find(R.gram_key.begin(), R.gram_key.end(), gk);
@@ -744,6 +768,7 @@ static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, cons
             case OP_ABSDIFF:
             case OP_CONST:
             case OP_XEQ:
+            case OP_XED:
                 in.op = sp->op;
                 code.push_back(in);
                 break;

@@ -68,7 +68,8 @@ enum Op : uint8_t {
     // predicates that tell t from s (ordered rule sets only; the pair's two
     // valuations get a mask each)
     OP_CONST = 9,    // t.A = c (aux 0) or s.A = c (aux 1); param = c
-    OP_XEQ = 10      // t.A = s.B: res = A, aux = B (both int resources)
+    OP_XEQ = 10,     // t.A = s.B: res = A, aux = B (both int resources)
+    OP_XED = 11      // Levenshtein(t.A, s.B) <= k: res = A, aux = B (string resources), param = k
 };
 
 // One step of the sequential execution path.  `slot` identifies the step
@@ -81,7 +82,7 @@ struct Instr {
     uint8_t op;
     uint8_t slot;
     uint8_t res;
-    uint8_t aux;    // OP_CONST: side; OP_XEQ: resource of B
+    uint8_t aux;    // OP_CONST: side; OP_XEQ, OP_XED: resource of B
     uint16_t cp;
     uint16_t pad1;
     uint64_t param;

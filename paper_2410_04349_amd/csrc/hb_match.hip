@@ -385,6 +385,54 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                         rows &= row_bits(f32 + n, pi0, res);
                         kf = aux == 0 ? rows : lane_hit;
                         kb = aux == 0 ? lane_hit : rows;
+                    } else if (op == OP_XED) {
+                        // Levenshtein(t.A, s.B) <= k, A = res, B = aux: forward
+                        // runs the row's A against the lane's B, backward the
+                        // row's B against the lane's A (the distance is
+                        // symmetric in its strings), row by row where some
+                        // lane needs it, the pattern table built from the row
+                        const int k = (int)param;
+                        kf = 0;
+                        kb = 0;
+                        for (int r = 0; r < nr; ++r) {
+                            const uint64_t pi = pi0 + r;
+                            const uint32_t row_i = f32[pi];
+                            const uint32_t vmask_i = f32[n + pi];
+#pragma unroll 1
+                            for (int dir = 0; dir < 2; ++dir) {
+                                const uint32_t pa = dir == 0 ? res : aux;   // row side (pattern)
+                                const uint32_t ta = dir == 0 ? aux : res;   // lane side (text)
+                                const bool need = (((dir == 0 ? fwd : bwd) >> r) & 1) &&
+                                                  ((vmask_i >> (16 + pa)) & 1) && ((vmask_j >> (16 + ta)) & 1);
+                                const int m = (int)f32[(str32 + pa) * n + pi];
+                                const int nn = (int)J32(str32 + ta);
+                                const bool run = need && abs(m - nn) <= k;
+                                if (!__any(run)) continue;
+                                const ColDev& cp = P.cols[P.str_attr[pa]];
+                                const ColDev& ct = P.cols[P.str_attr[ta]];
+                                const int words = m <= 32 ? 0 : (m + 63) / 64;
+                                build_peq(peq, words, cp.bytes + cp.off[row_i], m, lane);
+                                if (run) {
+                                    const uint8_t* tj = ct.bytes + ct.off[row_j];
+                                    int dist;
+                                    if constexpr (kLongEd) {
+                                        dist = m == 0 ? nn : nn == 0 ? m
+                                             : words == 0 ? myers<uint32_t, 1>((const uint32_t*)peq, m, tj, nn)
+                                             : words == 1 ? myers<uint64_t, 1>((const uint64_t*)peq, m, tj, nn)
+                                             : words == 2 ? myers<uint64_t, 2>((const uint64_t*)peq, m, tj, nn)
+                                             : words == 3 ? myers<uint64_t, 3>((const uint64_t*)peq, m, tj, nn)
+                                                          : myers<uint64_t, 4>((const uint64_t*)peq, m, tj, nn);
+                                    } else {
+                                        dist = myers_dispatch(peq, words, m, tj, nn,
+                                                              (uint64_t*)(wbase + P.lds_wave_myers), lane);
+                                    }
+                                    if (dist <= k) {
+                                        if (dir == 0) kf |= 1u << r;
+                                        else kb |= 1u << r;
+                                    }
+                                }
+                            }
+                        }
                     } else {   // OP_XEQ: t.A = s.B, A = res, B = aux
                         const int64_t ja = (int64_t)J64(res), jb = (int64_t)J64(aux);
                         uint32_t f = 0, g = 0;

@@ -1,13 +1,13 @@
-"""GPU parity of the predicates t.A = c, s.A = c and t.A = s.B: libhb's
-ordered listing of Ca, through the C ABI, is bit-exact against the oracle's,
-for every non-learned plan, across tiles and their diagonals, with two keys,
-and with edit-distance patterns past 64 bytes.  Calls the ordered path does
-not take are refused."""
+"""GPU parity of the predicates t.A = c, s.A = c, t.A = s.B and t.A ~ s.B
+(edit distance): libhb's ordered listing of Ca, through the C ABI, is
+bit-exact against the oracle's, for every non-learned plan, across tiles and
+their diagonals, with two keys, and with edit-distance patterns past 64
+bytes.  Calls the ordered path does not take are refused."""
 import numpy as np
 import pytest
 
 import oracle
-from gen import (CATEGORICAL, ED, EQ, EQ_CONST, EQ_CROSS, INT64, Pred, Relation, int_column,
+from gen import (CATEGORICAL, ED, ED_CROSS, EQ, EQ_CONST, EQ_CROSS, INT64, Pred, Relation, int_column,
                  string_column)
 from test_oracle_grammar import KEY, hand_relation, random_relation, random_rules
 
@@ -81,6 +81,17 @@ def test_several_tiles(hb, ctx, seed):
     assert len(want) > 0
 
 
+def test_cross_edit_distance_short_strings(hb, ctx):
+    # both valuations of t.s ~ s.u over short strings (empty and missing
+    # values included), with and without a constant beside
+    show("grammar: cross edit distance")
+    rel = random_relation(77, n=1200, n_keys=5)
+    for rules in ([[KEY, Pred(ED_CROSS, 4, attr_b=5, k=1)]],
+                  [[KEY, Pred(ED_CROSS, 5, attr_b=4, k=2), Pred(EQ_CONST, 1, side=0, c=2)],
+                   [KEY, Pred(ED, 4, k=0), Pred(EQ_CROSS, 2, attr_b=3)]]):
+        assert len(check(hb, ctx, rel, rules)) > 0
+
+
 def test_two_keys(hb, ctx):
     # a pair sharing both keys is evaluated in the first key's partition only
     show("grammar: two keys")
@@ -110,12 +121,24 @@ def test_long_edit_distance_patterns(hb, ctx):
         for _ in range(int(r.integers(0, 4))):
             t[int(r.integers(0, len(t)))] = int(r.integers(97, 100))
         strings.append(bytes(t))
+    # a second string column: each row's string with 0-5 substitutions, or
+    # a short unrelated one
+    other = []
+    for s in strings:
+        t = bytearray(s)
+        for _ in range(int(r.integers(0, 6))):
+            t[int(r.integers(0, len(t)))] = int(r.integers(97, 100))
+        other.append(bytes(t) if r.random() < 0.8 else bytes(r.integers(97, 100, size=5).astype(np.uint8)))
     rel = Relation([int_column("k", [int(x) for x in r.integers(0, 4, size=n)], CATEGORICAL),
                     string_column("s", strings),
-                    int_column("a", [int(x) for x in r.integers(0, 2, size=n)], CATEGORICAL)], n)
-    rules = [[Pred(EQ, 0), Pred(EQ_CONST, 2, side=0, c=1), Pred(ED, 1, k=3)]]
-    want = check(hb, ctx, rel, rules, plans=["given", "heuristic"])
-    assert len(want) > 0
+                    int_column("a", [int(x) for x in r.integers(0, 2, size=n)], CATEGORICAL),
+                    string_column("o", other)], n)
+    for rules in ([[Pred(EQ, 0), Pred(EQ_CONST, 2, side=0, c=1), Pred(ED, 1, k=3)]],
+                  [[Pred(EQ, 0), Pred(ED_CROSS, 1, attr_b=3, k=4)]],
+                  [[Pred(EQ, 0), Pred(ED_CROSS, 3, attr_b=1, k=2), Pred(EQ_CONST, 2, side=1, c=0)],
+                   [Pred(EQ, 0), Pred(ED, 3, k=1)]]):
+        want = check(hb, ctx, rel, rules, plans=["given", "heuristic"])
+        assert len(want) > 0
 
 
 def test_refused_calls(hb, ctx):
@@ -136,6 +159,8 @@ def test_refused_calls(hb, ctx):
                          ([KEY, Pred(EQ_CROSS, 1, attr_b=3)], hb.HB_ERR_TYPE),        # B is a string
                          ([KEY, Pred(EQ_CROSS, 1, attr_b=9)], hb.HB_ERR_INVALID_ARG),
                          ([KEY, Pred(EQ_CONST, 1, side=2, c=1)], hb.HB_ERR_INVALID_ARG),
+                         ([KEY, Pred(ED_CROSS, 1, attr_b=3, k=1)], hb.HB_ERR_TYPE),     # A is an int
+                         ([KEY, Pred(ED_CROSS, 3, attr_b=3, k=300)], hb.HB_ERR_INVALID_ARG),
                          ([Pred(EQ_CROSS, 0, attr_b=0)], hb.HB_ERR_UNBLOCKABLE)):   # never a key
         with pytest.raises(hb.HbError) as e:
             hb.hb_compile_rules(ctx, rid2, [rule])
