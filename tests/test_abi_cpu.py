@@ -74,3 +74,31 @@ def test_no_gpu_fails_loudly():
     with pytest.raises(hb.HbError) as e:
         hb.hb_create(0, allocator="hip")
     assert e.value.status == hb.HB_ERR_HIP
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structs have the header's field offsets and
+    sizes (compiled against include/hb.h with the host C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"hb_pred": hb.HbPred, "hb_rule": hb.HbRule, "hb_column": hb.HbColumn, "hb_job": hb.HbJob,
+               "hb_batch_info": hb.HbBatchInfo, "hb_match_stats": hb.HbMatchStats,
+               "hb_work_stats": hb.HbWorkStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hb.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
