@@ -408,12 +408,12 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                                 const int nn = (int)J32(str32 + ta);
                                 const bool run = need && abs(m - nn) <= k;
                                 if (!__any(run)) continue;
-                                const ColDev& cp = P.cols[P.str_attr[pa]];
-                                const ColDev& ct = P.cols[P.str_attr[ta]];
+                                const ColDev& col_p = P.cols[P.str_attr[pa]];
+                                const ColDev& col_t = P.cols[P.str_attr[ta]];
                                 const int words = m <= 32 ? 0 : (m + 63) / 64;
-                                build_peq(peq, words, cp.bytes + cp.off[row_i], m, lane);
+                                build_peq(peq, words, col_p.bytes + col_p.off[row_i], m, lane);
                                 if (run) {
-                                    const uint8_t* tj = ct.bytes + ct.off[row_j];
+                                    const uint8_t* tj = col_t.bytes + col_t.off[row_j];
                                     int dist;
                                     if constexpr (kLongEd) {
                                         dist = m == 0 ? nn : nn == 0 ? m
@@ -781,8 +781,10 @@ __global__ __launch_bounds__(64) void k_match_long(const MatchParams P, const In
     match_tile<kCount, true>(P, gmem(plan), gmem(f64), gmem(f32), t, lds, (int)(w & 3));
 }
 
-// k_match and k_match_long for ordered rule sets (no instrumented pass).
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_match_ord(
+// k_match and k_match_long for ordered rule sets (no instrumented pass;
+// the two valuations' masks need a few more registers than k_match, so the
+// occupancy hint is six waves, which keeps every value out of scratch).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_match_ord(
     const MatchParams P, const Instr* __restrict__ plan, const uint64_t* __restrict__ f64,
     const uint32_t* __restrict__ f32) {
     extern __shared__ __align__(16) uint8_t lds[];
