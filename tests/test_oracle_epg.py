@@ -112,3 +112,102 @@ def test_mix64_and_fnv_published_vectors():
     # FNV-1a 64: offset basis for the empty input, and the "a" test vector
     assert epg.fnv1a64(b"") == 0xCBF29CE484222325
     assert epg.fnv1a64(b"a") == 0xAF63DC4C8601EC8C
+
+
+def test_mix64_published_stream():
+    # the first four outputs of splitmix64 from state 0: the output function
+    # of s * 0x9E3779B97F4A7C15 for s = 1..4 (Steele, Lea and Flood 2014)
+    g = 0x9E3779B97F4A7C15
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    assert [epg.mix64((s * g) & epg.MASK) for s in range(1, 5)] == want
+    assert epg.mix64(0) == 0   # every step of the output function keeps 0 at 0
+
+
+# ------------------------------------------------ LSH buckets (selectivity)
+# The buckets only order the plan (they never change which pairs match), so
+# sp itself stays unpinned; these pin the bucket functions the estimate and
+# the device histograms are built from.
+
+def _cols(values=None, strings=None):
+    from gen import INT64, STRING, int_column, string_column
+    if strings is not None:
+        return string_column("s", strings)
+    return int_column("v", values, INT64)
+
+
+def test_gram_code_injective():
+    """Distinct strings of up to 4 bytes get distinct codes: exhaustively
+    over every string of at most 2 bytes, and up to 4 bytes over an alphabet
+    holding the extreme byte values."""
+    import itertools
+    seen = {}
+    for L in range(3):
+        for t in itertools.product(range(256), repeat=L):
+            s = bytes(t)
+            c = epg.gram_code(s)
+            assert c not in seen, (s, seen.get(c))
+            seen[c] = s
+    alpha = [0x00, 0x01, 0x61, 0x62, 0x7F, 0x80, 0xFE, 0xFF]
+    seen = {}
+    for L in range(5):
+        for t in itertools.product(alpha, repeat=L):
+            s = bytes(t)
+            c = epg.gram_code(s)
+            assert c not in seen, (s, seen.get(c))
+            seen[c] = s
+
+
+def test_gram_code_hand_values():
+    assert epg.gram_code(b"") == 0
+    assert epg.gram_code(b"a") == 0x1_00000061
+    assert epg.gram_code(b"ab") == 0x2_00006162
+    assert epg.gram_code(b"\x00") == 0x1_00000000        # not the empty string's code
+    assert epg.gram_code(b"\x00\x00") == 0x2_00000000    # nor the one-byte zero's
+    assert epg.gram_code(b"\xff\xff\xff\xff") == 0x4_FFFFFFFF
+
+
+def test_equality_bucket_of_a_published_value():
+    # the value whose splitmix64 output is published: 0xE220A8397B1DCDAF
+    # mod 1024 = 0x1AF = 431 (the value as an int64 is negative)
+    v = 0x9E3779B97F4A7C15 - (1 << 64)
+    col = _cols(values=[v, 0])
+    from gen import EQ, Pred
+    assert epg.lsh_bucket(col, Pred(EQ, 0), 0) == 431
+    assert epg.lsh_bucket(col, Pred(EQ, 0), 1) == 0     # the output function maps 0 to 0
+
+
+def test_range_buckets_group_windows_of_d_plus_one():
+    from gen import ABSDIFF, Pred
+    for d in (0, 1, 4, 9):
+        vals = list(range(-2 * (d + 1), 3 * (d + 1)))
+        col = _cols(values=vals)
+        b = [epg.lsh_bucket(col, Pred(ABSDIFF, 0, d=d), i) for i in range(len(vals))]
+        for i, v in enumerate(vals):
+            if 0 <= v <= d:
+                assert b[i] == 0, (d, v)    # floor(v / (d + 1)) = 0, and 0 maps to bucket 0
+            # v and v + d + 1 are a window apart: same offset in the next window
+            same = [b[x] for x, w in enumerate(vals) if w // (d + 1) == v // (d + 1)]
+            assert len(set(same)) == 1 and len(same) == d + 1
+
+
+def test_minhash_equal_gram_sets_equal_buckets():
+    from gen import ED, JACCARD, Pred
+    # pairs of different strings with the same gram set
+    same_sets = [(b"abab", b"baba", 2), (b"aaaa", b"aa", 2), (b"abcabc", b"bcabca", 3), (b"xy", b"xy", 3)]
+    for a, b, q in same_sets:
+        assert epg.qgram_set(a, q) == epg.qgram_set(b, q)
+        col = _cols(strings=[a, b])
+        p = Pred(JACCARD, 0, q=q, num=1, den=2)
+        assert epg.lsh_bucket(col, p, 0) == epg.lsh_bucket(col, p, 1)
+        if q == 2:
+            pe = Pred(ED, 0, k=1)
+            assert epg.lsh_bucket(col, pe, 0) == epg.lsh_bucket(col, pe, 1)
+
+
+def test_minhash_is_the_least_gram_hash():
+    for s, q in ((b"kitten", 2), (b"sitting", 3), (b"ab", 3), (b"mississippi", 2)):
+        hs = [epg.mix64(epg.gram_code(g)) for g in epg.qgram_set(s, q)]
+        assert epg.minhash(s, q) == min(hs)
+    assert epg.minhash(b"", 2) == 0          # no gram: the reading's value
+    # a string shorter than q is its own single gram
+    assert epg.minhash(b"ab", 3) == epg.mix64(0x2_00006162)

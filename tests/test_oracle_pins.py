@@ -348,3 +348,54 @@ def test_candidate_count_inclusion_exclusion_two_keys(seed):
     b = rel.columns[k1].values
     expect = _group_pairs([a]) + _group_pairs([b]) - _group_pairs([a, b])
     assert oracle.candidate_count(rel, rules) == expect
+
+
+# ------------------------------------------------------- |a - b| <= d (range)
+
+I64_MIN, I64_MAX = -(1 << 63), (1 << 63) - 1
+
+
+def _absdiff_sat(a, b, d):
+    rel = Relation([int_column("v", [a, b], INT64)], 2)
+    return oracle.sat(rel, Pred(ABSDIFF, 0, d=d), 0, 1)
+
+
+# (a, b, d, expected), each expected value worked out by hand from the
+# difference written beside it
+_ABSDIFF_CASES = [
+    (5, 3, 2, True),     # difference 2 = d
+    (3, 5, 2, True),     # the same pair the other way round
+    (5, 3, 1, False),    # difference 2 = d + 1
+    (5, 3, 3, True),     # difference 2 = d - 1
+    (7, 7, 0, True),     # d = 0: equal values
+    (7, 8, 0, False),    # d = 0: difference 1
+    (-4, 4, 8, True),    # across zero: difference 8 = d
+    (-4, 4, 7, False),   # difference 8 = d + 1
+    (I64_MAX, 0, I64_MAX, True),           # difference 2^63 - 1 = d
+    (I64_MAX, 0, I64_MAX - 1, False),      # difference 2^63 - 1 = d + 1
+    (0, I64_MIN, I64_MAX, False),          # difference 2^63 > every int64 d
+    (I64_MAX, -1, I64_MAX, False),         # difference 2^63: wraps to INT64_MIN in 64 bits
+    (I64_MAX, I64_MIN, I64_MAX, False),    # difference 2^64 - 1: wraps to -1 in 64 bits
+    (I64_MIN, I64_MAX, 0, False),          # the same, the other way round
+    (I64_MIN, I64_MIN + 1, 0, False),      # difference 1 at the bottom of the range
+    (I64_MIN, I64_MIN + 1, 1, True),
+    (I64_MAX - 2, I64_MAX, 2, True),       # difference 2 at the top of the range
+    (I64_MAX - 2, I64_MAX, 1, False),
+]
+
+
+@pytest.mark.parametrize("a,b,d,want", _ABSDIFF_CASES)
+def test_absdiff_hand_worked(a, b, d, want):
+    assert _absdiff_sat(a, b, d) is want
+    assert _absdiff_sat(b, a, d) is want
+
+
+def test_absdiff_count_closed_form():
+    """For a fixed a and d, exactly 2d + 1 integers b have |a - b| <= d (the
+    window a - d .. a + d); a strict test would count 2d - 1, a one-sided
+    one d + 1."""
+    bs = list(range(-40, 41))
+    rel = Relation([int_column("v", [0] + bs, INT64)], 1 + len(bs))
+    for d in range(0, 12):
+        got = sum(oracle.sat(rel, Pred(ABSDIFF, 0, d=d), 0, 1 + x) for x in range(len(bs)))
+        assert got == 2 * d + 1, d
