@@ -339,6 +339,20 @@ hb_status hb_costmodel_trace(hb_ctx* ctx, const float* x, const float* t, uint32
                              uint64_t out_len);
 /* One Adam step with the given host gradients (HB_MLP_PARAMS floats). */
 hb_status hb_costmodel_adam_step(hb_ctx* ctx, const float* grads, float lr);
+/* Persist the context's model and read it back, so a model trained on the
+ * logs of earlier runs plans later ones (the paper trains its estimator
+ * offline on historical logs, Section 4.2, "Shallow NNs").  File layout,
+ * little-endian: the 8 bytes "HBCMODEL"; uint32 version (1); uint32 inputs,
+ * hidden width, outputs and parameter count (16, 64, 2, HB_MLP_PARAMS);
+ * uint32 0; HB_MLP_PARAMS fp32 parameters in the order above; uint64 FNV-1a
+ * 64 hash of those parameter bytes.  hb_costmodel_save needs a model
+ * (HB_ERR_STATE) and writes `path` whole or not at all (a temporary file
+ * renamed over it); hb_costmodel_load checks every field, the size and the
+ * hash (HB_ERR_INVALID_ARG on any mismatch or I/O failure, leaving the
+ * context's model unchanged) and resets the Adam moments, as
+ * hb_costmodel_set_params does.  `path` is a NUL-terminated file name. */
+hb_status hb_costmodel_save(hb_ctx* ctx, const char* path);
+hb_status hb_costmodel_load(hb_ctx* ctx, const char* path);
 
 /* Logging pass for the cost model (the paper trains its estimator on
  * historical logs, Section 4.2): for every block (of every key partition,

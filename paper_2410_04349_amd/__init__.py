@@ -48,6 +48,7 @@ EXPORTED = [
     "hb_epg_path", "hb_plan_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
     "hb_match_work", "hb_costmodel_init", "hb_costmodel_set_params", "hb_costmodel_get_params",
     "hb_costmodel_train", "hb_costmodel_predict", "hb_costmodel_trace", "hb_costmodel_adam_step",
+    "hb_costmodel_save", "hb_costmodel_load",
     "hb_log_collect", "hb_batch_create", "hb_batch_run", "hb_batch_result", "hb_batch_info_get",
     "hb_batch_destroy",
 ]
@@ -147,6 +148,8 @@ def _load_lib():
         "hb_costmodel_predict": (I32, [P, P, U64, ctypes.c_int, P, ctypes.c_int]),
         "hb_costmodel_trace": (I32, [P, P, P, U32, P, U64]),
         "hb_costmodel_adam_step": (I32, [P, P, ctypes.c_float]),
+        "hb_costmodel_save": (I32, [P, ctypes.c_char_p]),
+        "hb_costmodel_load": (I32, [P, ctypes.c_char_p]),
         "hb_log_collect": (I32, [P, U32, U32, U32, U64, P, P, P, P, U64, ctypes.POINTER(U64)]),
         "hb_batch_create": (I32, [P, ctypes.POINTER(HbJob), U32, I32, U32, ctypes.POINTER(U32)]),
         "hb_batch_run": (I32, [P, U32, ctypes.POINTER(U64)]),
@@ -477,6 +480,14 @@ def hb_costmodel_trace(ctx: Context, x, t) -> dict:
 def hb_costmodel_adam_step(ctx: Context, grads, lr: float) -> None:
     g = _f32(grads)
     ctx.check(_lib.hb_costmodel_adam_step(ctx.h, ctypes.c_void_p(g.ctypes.data), lr))
+
+
+def hb_costmodel_save(ctx: Context, path: str) -> None:
+    ctx.check(_lib.hb_costmodel_save(ctx.h, os.fsencode(path)))
+
+
+def hb_costmodel_load(ctx: Context, path: str) -> None:
+    ctx.check(_lib.hb_costmodel_load(ctx.h, os.fsencode(path)))
 
 
 def hb_log_collect(ctx: Context, rel_id: int, ruleset_id: int, samples: int, seed: int) -> dict:

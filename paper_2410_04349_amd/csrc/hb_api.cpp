@@ -1478,6 +1478,14 @@ hb_status hb_costmodel_adam_step(hb_ctx* ctx, const float* grads, float lr) {
     return guard(ctx, [&](Ctx* c) { hb::costmodel_adam(c, grads, lr); });
 }
 
+hb_status hb_costmodel_save(hb_ctx* ctx, const char* path) {
+    return guard(ctx, [&](Ctx* c) { hb::costmodel_save(c, path); });
+}
+
+hb_status hb_costmodel_load(hb_ctx* ctx, const char* path) {
+    return guard(ctx, [&](Ctx* c) { hb::costmodel_load(c, path); });
+}
+
 hb_status hb_profile_enable(hb_ctx* ctx, int on) {
     return guard(ctx, [&](Ctx* c) { c->profiling = on != 0; });
 }

@@ -310,5 +310,7 @@ void costmodel_train(Ctx* c, const float* x, const float* t, uint64_t n, int on_
 void costmodel_predict(Ctx* c, const float* x, uint64_t n, int on_device, float* y, int y_on_device);
 void costmodel_trace(Ctx* c, const float* x, const float* t, uint32_t n, float* out, uint64_t out_len);
 void costmodel_adam(Ctx* c, const float* grad_host, float lr);
+void costmodel_save(Ctx* c, const char* path);
+void costmodel_load(Ctx* c, const char* path);
 
 }  // namespace hb

@@ -5,6 +5,7 @@
 // estimates predicate costs from logs (Section 4.2, "Shallow NNs",
 // "Estimated cost"; Adam and ReLU as in the paper's defaults, Section 6).
 #include <cmath>
+#include <cstdio>
 
 #include "hb_ctx.h"
 
@@ -231,6 +232,84 @@ void costmodel_trace(Ctx* c, const float* x, const float* t, uint32_t n, float* 
     }
     HB_HIP(hipMemcpyAsync(o, a.grad.get(), sizeof(float) * kParams, hipMemcpyDeviceToHost, c->stream));
     c->sync();
+}
+
+// Model file (little-endian): the 8 bytes "HBCMODEL", u32 version (1),
+// u32 inputs, hidden width, outputs and parameter count (16, 64, 2, 5378),
+// u32 0, the fp32 parameters in hb.h's order, and the FNV-1a 64 hash of the
+// parameter bytes.
+namespace {
+constexpr char kMagic[8] = {'H', 'B', 'C', 'M', 'O', 'D', 'E', 'L'};
+constexpr uint32_t kFileVersion = 1;
+
+uint64_t fnv1a64(const uint8_t* p, size_t n) {
+    uint64_t h = 0xCBF29CE484222325ull;
+    for (size_t x = 0; x < n; ++x) {
+        h ^= p[x];
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+
+struct FileCloser {
+    FILE* f;
+    ~FileCloser() {
+        if (f) std::fclose(f);
+    }
+};
+}  // namespace
+
+void costmodel_save(Ctx* c, const char* path) {
+    if (!path || !*path) fail(HB_ERR_INVALID_ARG, "NULL or empty path");
+    std::vector<float> w(kParams);
+    costmodel_get(c, w.data(), kParams);
+    const uint32_t head[6] = {kFileVersion, (uint32_t)kIn, (uint32_t)kHid, (uint32_t)kOut, (uint32_t)kParams, 0u};
+    const uint64_t sum = fnv1a64((const uint8_t*)w.data(), sizeof(float) * kParams);
+    // write a temporary file beside the target, then rename it over the target
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        FileCloser fc{std::fopen(tmp.c_str(), "wb")};
+        if (!fc.f) fail(HB_ERR_INVALID_ARG, "cannot open " + tmp + " for writing");
+        const bool ok = std::fwrite(kMagic, 1, sizeof(kMagic), fc.f) == sizeof(kMagic) &&
+                        std::fwrite(head, sizeof(uint32_t), 6, fc.f) == 6 &&
+                        std::fwrite(w.data(), sizeof(float), kParams, fc.f) == (size_t)kParams &&
+                        std::fwrite(&sum, sizeof(sum), 1, fc.f) == 1;
+        const bool closed = std::fclose(fc.f) == 0;
+        fc.f = nullptr;
+        if (!ok || !closed) {
+            std::remove(tmp.c_str());
+            fail(HB_ERR_INVALID_ARG, "write to " + tmp + " failed");
+        }
+    }
+    if (std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        fail(HB_ERR_INVALID_ARG, std::string("cannot rename the model file to ") + path);
+    }
+}
+
+void costmodel_load(Ctx* c, const char* path) {
+    if (!path || !*path) fail(HB_ERR_INVALID_ARG, "NULL or empty path");
+    FileCloser fc{std::fopen(path, "rb")};
+    if (!fc.f) fail(HB_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    char magic[8];
+    uint32_t head[6];
+    std::vector<float> w(kParams);
+    uint64_t sum = 0;
+    if (std::fread(magic, 1, 8, fc.f) != 8 || std::memcmp(magic, kMagic, 8) != 0)
+        fail(HB_ERR_INVALID_ARG, std::string(path) + " is not a cost-model file");
+    if (std::fread(head, sizeof(uint32_t), 6, fc.f) != 6 || head[0] != kFileVersion)
+        fail(HB_ERR_INVALID_ARG, std::string(path) + ": unknown cost-model file version");
+    if (head[1] != (uint32_t)kIn || head[2] != (uint32_t)kHid || head[3] != (uint32_t)kOut ||
+        head[4] != (uint32_t)kParams || head[5] != 0u)
+        fail(HB_ERR_INVALID_ARG, std::string(path) + ": the model's shape is not 16 -> 64 -> 64 -> 2");
+    if (std::fread(w.data(), sizeof(float), kParams, fc.f) != (size_t)kParams ||
+        std::fread(&sum, sizeof(sum), 1, fc.f) != 1)
+        fail(HB_ERR_INVALID_ARG, std::string(path) + ": truncated cost-model file");
+    char extra;
+    if (std::fread(&extra, 1, 1, fc.f) != 0) fail(HB_ERR_INVALID_ARG, std::string(path) + ": trailing bytes");
+    if (fnv1a64((const uint8_t*)w.data(), sizeof(float) * kParams) != sum)
+        fail(HB_ERR_INVALID_ARG, std::string(path) + ": parameter checksum mismatch");
+    costmodel_set(c, w.data(), kParams);
 }
 
 void costmodel_adam(Ctx* c, const float* grad_host, float lr) {

@@ -161,3 +161,51 @@ def test_fused_inference_matches_layerwise_forward(hb, ctx):
     p = unflat(hb.hb_costmodel_get_params(ctx))
     y64, _ = mlp.forward(p, x.astype(np.float64))
     assert np.abs(fused - y64).max() <= 0.05 * (np.abs(y64).max() + 1e-3)
+
+
+def test_save_load_round_trip(hb, ctx, tmp_path):
+    """hb_costmodel_save / hb_costmodel_load through the C ABI: the loaded
+    parameters are bit-identical in a fresh context and predict the same;
+    a corrupted, truncated or foreign file is refused and leaves the
+    context's model as it was."""
+    print("[gpu-case] costmodel save/load", flush=True)
+    r = np.random.default_rng(31)
+    x = r.normal(size=(700, 16)).astype(np.float32)
+    t = (np.tanh(x[:, :2]) * 0.5).astype(np.float32)
+    hb.hb_costmodel_init(ctx, 17)
+    hb.hb_costmodel_train(ctx, x, t, epochs=3, batch=128, lr=1e-3)
+    want = hb.hb_costmodel_get_params(ctx)
+    path = str(tmp_path / "model.hbcm")
+    hb.hb_costmodel_save(ctx, path)
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"HBCMODEL" and len(raw) == 8 + 6 * 4 + hb.HB_MLP_PARAMS * 4 + 8
+    assert np.array_equal(np.frombuffer(raw[32:32 + hb.HB_MLP_PARAMS * 4], dtype="<f4"), want)
+
+    other = hb.hb_create(0, allocator="torch")
+    try:
+        with pytest.raises(hb.HbError) as e:   # nothing to save yet
+            hb.hb_costmodel_save(other, str(tmp_path / "none.hbcm"))
+        assert e.value.status == hb.HB_ERR_STATE
+        hb.hb_costmodel_load(other, path)
+        got = hb.hb_costmodel_get_params(other)
+        assert got.view(np.uint32).tolist() == want.view(np.uint32).tolist()
+        assert np.array_equal(hb.hb_costmodel_predict(other, x), hb.hb_costmodel_predict(ctx, x))
+        # refused files leave the loaded model untouched
+        bad = bytearray(raw)
+        bad[40] ^= 1   # one parameter bit: checksum mismatch
+        cases = {"flip.hbcm": bytes(bad), "short.hbcm": raw[:-9], "long.hbcm": raw + b"\0",
+                 "magic.hbcm": b"HBXMODEL" + raw[8:]}
+        shape = bytearray(raw)
+        shape[16] = 32   # hidden width 32
+        cases["shape.hbcm"] = bytes(shape)
+        for name, data in cases.items():
+            p = tmp_path / name
+            p.write_bytes(data)
+            with pytest.raises(hb.HbError) as e:
+                hb.hb_costmodel_load(other, str(p))
+            assert e.value.status == hb.HB_ERR_INVALID_ARG, name
+        with pytest.raises(hb.HbError):
+            hb.hb_costmodel_load(other, str(tmp_path / "missing.hbcm"))
+        assert np.array_equal(hb.hb_costmodel_get_params(other), want)
+    finally:
+        other.close()
