@@ -284,10 +284,14 @@ hb_status hb_profile_reset(hb_ctx* ctx);
  * it, `passed` = the pairs for which it held, `work` = its work units (edit
  * distance: text bytes x 32-bit pattern words run; Jaccard: merged list
  * elements; string equality: bytes compared; others: pairs).  `pairs` is
- * the number of candidate pairs evaluated, `lane_ops` the algorithmic int32
- * lane-operations under the library's per-operation cost model (per pair
- * evaluated), `batch_ops` the same model charged for every lane of every
- * batch a step ran on (the SIMD work the plan causes).
+ * the number of candidate pairs evaluated.  `lane_ops` is the algorithmic
+ * int32 lane-operations of the pairs evaluated: value equality 2, |a-b| <= d
+ * 4, each exact filter 4, string equality 2 + 1 per byte, edit distance 17
+ * per work unit (Myers), Jaccard 3 per merged element.  `issued_ops` is the
+ * same count with what the kernel issues per operation (12 for each
+ * signature filter, 1 for value equality, 3 for the string-equality
+ * filter), and `batch_ops` that issued count charged for every lane of
+ * every batch a cheap step ran on (the SIMD work the plan causes).
  * Requires hb_partition; leaves the cached hb_match result untouched. */
 #define HB_N_OPKINDS 8
 typedef struct {
@@ -300,6 +304,7 @@ typedef struct {
     uint64_t work[HB_N_OPKINDS];
     double lane_ops;
     double batch_ops;
+    double issued_ops;
 } hb_work_stats;
 hb_status hb_match_work(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, hb_work_stats* out);
 

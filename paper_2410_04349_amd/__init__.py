@@ -101,7 +101,8 @@ class HbMatchStats(ctypes.Structure):
 class HbWorkStats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_uint64), ("matched", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("waves", ctypes.c_uint64 * 8), ("lanes", ctypes.c_uint64 * 8), ("passed", ctypes.c_uint64 * 8),
-                ("work", ctypes.c_uint64 * 8), ("lane_ops", ctypes.c_double), ("batch_ops", ctypes.c_double)]
+                ("work", ctypes.c_uint64 * 8), ("lane_ops", ctypes.c_double), ("batch_ops", ctypes.c_double),
+                ("issued_ops", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -422,7 +423,7 @@ def hb_match_work(ctx: Context, rel_id: int, ruleset_id: int, plan="heuristic") 
     for k, name in enumerate(OP_KINDS):
         per_op[name] = {"waves": w.waves[k], "lanes": w.lanes[k], "passed": w.passed[k], "work": w.work[k]}
     return {"pairs": w.pairs, "matched": w.matched, "launches": w.launches, "lane_ops": w.lane_ops,
-            "batch_ops": w.batch_ops, "per_op": per_op}
+            "batch_ops": w.batch_ops, "issued_ops": w.issued_ops, "per_op": per_op}
 
 
 def _f32(a):

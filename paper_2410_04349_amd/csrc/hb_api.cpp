@@ -294,6 +294,8 @@ static double pred_cost(const Relation& rel, const hb_pred& p) {
     return 1.0;
 }
 
+static const uint64_t* char_signature(Ctx* c, Relation& rel, uint32_t attr);
+
 static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_rule* rules, uint32_t* ruleset_id) {
     Relation& rel = get_rel(c, rel_id);
     if (!rules || !ruleset_id) fail(HB_ERR_INVALID_ARG, "NULL argument");
@@ -443,6 +445,13 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
         cmax = std::max(cmax, rs->cost[p]);
     }
     for (size_t p = 0; p < np; ++p) rs->cost[p] /= cmax;
+    // the character signatures every string step reads, built here with the
+    // q-gram indexes so that matching only reads per-relation indexes
+    for (const hb_pred& d : rs->distinct) {
+        if ((d.op == HB_EQ && rel.cols[d.attr].type == HB_COL_STRING) || d.op == HB_ED_LE || d.op == HB_ED_CROSS_LE)
+            char_signature(c, rel, d.attr);
+        if (d.op == HB_ED_CROSS_LE) char_signature(c, rel, d.attr_b);
+    }
     rs->id = c->next_id++;
     *ruleset_id = rs->id;
     c->rulesets[rs->id] = std::move(rs);
@@ -1089,11 +1098,19 @@ static void log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t sample
     }
 }
 
-// Per-operation cost model (int32 lane-ops): a fixed part per evaluated
-// lane plus a part per work unit (edit distance: text byte x 32-bit pattern
-// word; Jaccard: merged list element; string equality: byte compared).
-static const double kOpBase[8] = {1, 4, 3, 12, 12, 2, 4, 4};
-static const double kOpUnit[8] = {0, 0, 0, 0, 0, 1, 17, 3};
+// Algorithmic cost model of pair evaluation (int32 lane-ops): a fixed part
+// per evaluated lane plus a part per work unit (edit distance: text byte x
+// 32-bit pattern word; Jaccard: merged list element; string equality: byte
+// compared).  Value equality 2, |a-b| <= d 4, every exact filter 4 (a length
+// or signature bound), string equality 2 + 1 per byte, Myers 17 per text
+// byte and pattern word, the sorted merge 3 per element.
+static const double kAlgBase[8] = {2, 4, 4, 4, 4, 2, 0, 0};
+static const double kAlgUnit[8] = {0, 0, 0, 0, 0, 1, 17, 3};
+// What the kernel issues per evaluated lane for the same operations (its
+// signature filters take about 12 int32 operations: popcounts, a 24-bit
+// multiply-add and the compare; the rest as above).
+static const double kIssBase[8] = {1, 4, 3, 12, 12, 2, 4, 4};
+static const double kIssUnit[8] = {0, 0, 0, 0, 0, 1, 17, 3};
 
 // Seed of the random-order strategies: the rule set's predicate ids mixed
 // together (fixed per rule set, so repeated calls evaluate identically).
@@ -1226,14 +1243,16 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
             ws->work[op] = h[op * 4 + 3];
         }
         ws->pairs = h[kCountPairs];
-        double ops = 0.0, bops = 0.0;
+        double ops = 0.0, iss = 0.0, bops = 0.0;
         for (int op = 0; op < HB_N_OPKINDS; ++op) {
-            ops += kOpBase[op] * ws->lanes[op] + kOpUnit[op] * ws->work[op];
+            ops += kAlgBase[op] * ws->lanes[op] + kAlgUnit[op] * ws->work[op];
+            iss += kIssBase[op] * ws->lanes[op] + kIssUnit[op] * ws->work[op];
             // cheap steps run for every lane of the batch; exact ones per pair
-            bops += op <= OP_JACF ? kOpBase[op] * (double)ws->waves[op] * kRows * 64
-                                  : kOpBase[op] * ws->lanes[op] + kOpUnit[op] * ws->work[op];
+            bops += op <= OP_JACF ? kIssBase[op] * (double)ws->waves[op] * kRows * 64
+                                  : kIssBase[op] * ws->lanes[op] + kIssUnit[op] * ws->work[op];
         }
         ws->lane_ops = ops;
+        ws->issued_ops = iss;
         ws->batch_ops = bops;
         ws->matched = found;
         ws->launches = launches;
