@@ -236,6 +236,29 @@ typedef enum {
 hb_status hb_match(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan,
                    uint64_t* out_pairs, int out_on_device, uint64_t capacity, uint64_t* n_pairs);
 
+/* hb_match for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  It
+ * allocates nothing (no hipMalloc, no hipFree, no call of the context's
+ * allocator): every device buffer of the call (block-major feature
+ * columns, plan code, the unsorted pairs, the sort's histograms) is carved
+ * from a scratch array of HB_NOALLOC_SCRATCH_BYTES that the library holds
+ * on each device it runs on until the process ends; its address is taken
+ * once per device by hb_create.  Every plan but HB_PLAN_LEARNED (its
+ * per-block plans need buffers of their own: HB_ERR_INVALID_ARG); the
+ * result equals hb_match's.  `out_pairs` is DEVICE memory of `capacity`
+ * entries; it also serves as the sort's second buffer, so its contents
+ * beyond the result are undefined.  *n_pairs = the pairs found; capacity
+ * below that: HB_ERR_CAPACITY (nothing is cached: a retry evaluates
+ * again).  A call whose buffers do not fit the array (about 2M tuples of
+ * six attributes) returns HB_ERR_LIMIT.  Calls on one device share its
+ * array: calls that overlap in time on one device race (the array keeps
+ * the last call's contents; each call clears what must start at zero).
+ * Requires hb_partition; q-gram indexes and character signatures are built
+ * by hb_compile_rules. */
+#define HB_NOALLOC_SCRATCH_BYTES (256u << 20)
+hb_status hb_match_noalloc(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan,
+                           uint64_t* out_pairs, uint64_t capacity, uint64_t* n_pairs);
+
 /* ------------------------------------------------------------ introspection */
 
 /* Per distinct predicate of a rule set (in first-appearance order): its

@@ -44,7 +44,7 @@ _PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC, "learned": HB_P
 EXPORTED = [
     "hb_create", "hb_destroy", "hb_last_error", "hb_version", "hb_load_relation", "hb_load_relation_async",
     "hb_release_relation",
-    "hb_compile_rules", "hb_partition", "hb_match", "hb_ruleset_estimates", "hb_ruleset_buckets",
+    "hb_compile_rules", "hb_partition", "hb_match", "hb_match_noalloc", "hb_ruleset_estimates", "hb_ruleset_buckets",
     "hb_epg_path", "hb_plan_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
     "hb_match_work", "hb_costmodel_init", "hb_costmodel_set_params", "hb_costmodel_get_params",
     "hb_costmodel_train", "hb_costmodel_predict", "hb_costmodel_trace", "hb_costmodel_adam_step",
@@ -132,6 +132,7 @@ def _load_lib():
         "hb_compile_rules": (I32, [P, U32, U32, ctypes.POINTER(HbRule), ctypes.POINTER(U32)]),
         "hb_partition": (I32, [P, U32, U32, ctypes.POINTER(U64)]),
         "hb_match": (I32, [P, U32, U32, I32, P, ctypes.c_int, U64, ctypes.POINTER(U64)]),
+        "hb_match_noalloc": (I32, [P, U32, U32, I32, P, U64, ctypes.POINTER(U64)]),
         "hb_ruleset_estimates": (I32, [P, U32, P, P, U32, ctypes.POINTER(U32)]),
         "hb_ruleset_buckets": (I32, [P, U32, U32, P, ctypes.POINTER(U64)]),
         "hb_epg_path": (I32, [U32, P, P, U32, P, P, P, P, ctypes.POINTER(U32)]),
@@ -191,12 +192,14 @@ class Context:
     def __init__(self, device: int = 0, allocator: str = "torch", stream=None):
         self.device = device
         self._held = {}
+        self.alloc_calls = 0   # device allocations the library asked for
         self._alloc_cb = ALLOC_FN(0)
         self._free_cb = FREE_FN(0)
         if allocator == "torch":
             import torch
 
             def _alloc(nbytes, user):
+                self.alloc_calls += 1
                 try:
                     t = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{device}")
                 except RuntimeError:
@@ -339,6 +342,17 @@ def hb_match(ctx: Context, rel_id: int, ruleset_id: int, plan="heuristic", out=N
     ctx.check(_lib.hb_match(ctx.h, rel_id, ruleset_id, pl, ctypes.c_void_p(buf.ctypes.data), 0, len(buf),
                             ctypes.byref(n)))
     return buf[: n.value]
+
+
+def hb_match_noalloc(ctx: Context, rel_id: int, ruleset_id: int, plan, out, capacity: int = None) -> int:
+    """hb_match into the torch device tensor `out` (uint64/int64) without any
+    device allocation (see include/hb.h); returns the pair count."""
+    pl = _PLAN[plan] if isinstance(plan, str) else int(plan)
+    n = ctypes.c_uint64()
+    cap = out.numel() if capacity is None else capacity
+    ctx.check(_lib.hb_match_noalloc(ctx.h, rel_id, ruleset_id, pl, ctypes.c_void_p(out.data_ptr()), cap,
+                                    ctypes.byref(n)))
+    return n.value
 
 
 def hb_ruleset_estimates(ctx: Context, ruleset_id: int) -> Tuple[np.ndarray, np.ndarray]:

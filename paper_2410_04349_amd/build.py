@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhb.so")
-SOURCES = ["hb_api.cpp", "hb_batch.cpp", "hb_plan.cpp", "hb_learn.cpp", "hb_prims.hip", "hb_match.hip", "hb_mlp.hip"]
+SOURCES = ["hb_api.cpp", "hb_batch.cpp", "hb_plan.cpp", "hb_learn.cpp", "hb_prims.hip", "hb_match.hip", "hb_mlp.hip", "hb_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

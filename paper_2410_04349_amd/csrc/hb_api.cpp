@@ -227,6 +227,7 @@ static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
     auto key = std::make_pair(attr, q);
     auto it = rel.grams.find(key);
     if (it != rel.grams.end()) return it->second;
+    if (c->arena) fail(HB_ERR_STATE, "internal: q-gram index built inside an allocation-free call");
     const uint32_t n = rel.n_rows;
     GramIndex g;
     g.attr = attr;
@@ -647,6 +648,7 @@ static uint32_t align_up(uint32_t v, uint32_t a) { return (v + a - 1) / a * a; }
 static const uint64_t* char_signature(Ctx* c, Relation& rel, uint32_t attr) {
     auto it = rel.char_sig.find(attr);
     if (it != rel.char_sig.end()) return it->second.as<uint64_t>();
+    if (c->arena) fail(HB_ERR_STATE, "internal: character signature built inside an allocation-free call");
     DevBuf sig(c, sizeof(uint64_t) * rel.n_rows);
     HB_HIP(launch_char_sig(rel.d_cols.as<ColDev>() + attr, rel.n_rows, sig.as<uint64_t>(), c->stream));
     const uint64_t* p = sig.as<uint64_t>();
@@ -1298,6 +1300,92 @@ static void match(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, uint64_t* o
     c->sync();
 }
 
+// hb_match without allocation: the same plans (all but the learned one,
+// whose per-block plans need buffers of their own), kernels and sort, with
+// every device buffer of the call carved in turn from the device's scratch
+// array, and the sorted pairs written to the caller's device buffer.  The
+// indexes a match reads (q-gram indexes, character signatures) are built by
+// hb_compile_rules, so nothing is cached here.
+static void match_noalloc(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, uint64_t* out, uint64_t cap,
+                          uint64_t* n_pairs) {
+    Relation& rel = get_rel(c, rel_id);
+    RuleSet& rs = get_rs(c, rs_id, rel_id);
+    if (!n_pairs) fail(HB_ERR_INVALID_ARG, "NULL n_pairs");
+    if (!valid_plan(plan)) fail(HB_ERR_INVALID_ARG, "unknown plan");
+    if (plan == HB_PLAN_LEARNED) fail(HB_ERR_INVALID_ARG, "hb_match_noalloc takes every plan but the learned one");
+    if (!rs.partitioned) fail(HB_ERR_STATE, "hb_partition must run before hb_match_noalloc");
+    if (!c->scratch) fail(HB_ERR_HIP, "no scratch array on this device: " + c->scratch_err);
+    *n_pairs = 0;
+    struct ArenaScope {
+        Ctx* c;
+        ArenaScope(Ctx* cc, uint8_t* base, size_t bytes) : c(cc) {
+            c->arena = base;
+            c->arena_cap = bytes;
+            c->arena_used = 0;
+        }
+        ~ArenaScope() {
+            c->arena = nullptr;
+            c->arena_cap = c->arena_used = 0;
+        }
+    } scope(c, c->scratch, (size_t)HB_NOALLOC_SCRATCH_BYTES);
+
+    const std::vector<PathRule> path = plan_path(rs, plan);
+    std::vector<KeyPlan> kps;
+    size_t total_code = 0;
+    for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
+        if (rel.parts.at(rs.keys[ka]).n_tiles == 0) continue;
+        KeyPlan kp;
+        if (!build_key_plan(c, rel, rs, path, ka, kp, false)) continue;
+        total_code += kp.code.size();
+        kps.push_back(std::move(kp));
+    }
+    DevBuf counter(c, 8);
+    zero(c, counter.get(), 8);   // the array keeps the previous call's contents
+    DevBuf code(c, sizeof(Instr) * std::max<size_t>(total_code, 1));
+    std::vector<Instr> all;
+    for (KeyPlan& kp : kps) all.insert(all.end(), kp.code.begin(), kp.code.end());
+    if (!all.empty())
+        HB_HIP(hipMemcpyAsync(code.get(), all.data(), sizeof(Instr) * all.size(), hipMemcpyHostToDevice, c->stream));
+    // the rest of the array: unsorted pairs, then the sort's histograms
+    const size_t left = c->arena_cap - std::min(c->arena_cap, ((c->arena_used + 255) & ~(size_t)255) + 512);
+    uint64_t cap_s = std::min<uint64_t>(left / 8, 0xFFFFFFFEull);
+    while (cap_s > 0 && cap_s * 8 + radix_tmp_bytes((uint32_t)cap_s) > left) cap_s -= std::max<uint64_t>(cap_s / 64, 1);
+    DevBuf unsorted(c, sizeof(uint64_t) * std::max<uint64_t>(cap_s, 1));
+    size_t o = 0;
+    for (KeyPlan& kp : kps) {
+        kp.mp.counts = nullptr;
+        kp.mp.plan = code.as<Instr>() + o;
+        o += kp.code.size();
+        kp.mp.out = unsorted.as<uint64_t>();
+        kp.mp.cap = cap_s;
+        kp.mp.counter = counter.as<unsigned long long>();
+        HB_HIP(launch_match(kp.mp, c->stream));
+    }
+    const uint64_t found = read1(c, counter.as<unsigned long long>());
+    *n_pairs = found;
+    if (cap < found) fail(HB_ERR_CAPACITY, "output capacity " + std::to_string(cap) + " < " + std::to_string(found));
+    if (cap_s < found)
+        fail(HB_ERR_LIMIT, "the scratch array holds " + std::to_string(cap_s) + " unsorted pairs, the call found " +
+                               std::to_string(found));
+    if (found && !out) fail(HB_ERR_INVALID_ARG, "NULL output buffer");
+    if (found > 1) {
+        // the caller's buffer is the sort's second buffer
+        const int nb = bit_width(rel.n_rows > 1 ? rel.n_rows - 1 : 1);
+        std::vector<int> sh = shifts_for_bits(nb, 0);
+        std::vector<int> shi = shifts_for_bits(nb, 32);
+        sh.insert(sh.end(), shi.begin(), shi.end());
+        DevBuf rtmp(c, radix_tmp_bytes((uint32_t)found));
+        bool in_alt = false;
+        HB_HIP(radix_sort_pairs(unsorted.as<uint64_t>(), nullptr, out, nullptr, (uint32_t)found, sh.data(),
+                                (int)sh.size(), rtmp.get(), &in_alt, c->stream));
+        if (!in_alt)
+            HB_HIP(hipMemcpyAsync(out, unsorted.get(), sizeof(uint64_t) * found, hipMemcpyDeviceToDevice, c->stream));
+    } else if (found == 1) {
+        HB_HIP(hipMemcpyAsync(out, unsorted.get(), 8, hipMemcpyDeviceToDevice, c->stream));
+    }
+    c->sync();
+}
+
 }  // namespace hb
 
 // ============================================================ C ABI
@@ -1335,6 +1423,8 @@ hb_status hb_create(hb_ctx** out, int device, hb_alloc_fn alloc, hb_free_fn free
     int lds = 65536;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
     h->c.lds_limit = (uint32_t)lds;
+    // this device's copy of the allocation-free entry point's scratch array
+    h->c.scratch = hb::scratch_address(device, &h->c.scratch_err);
     *out = h;
     return HB_OK;
 }
@@ -1389,6 +1479,11 @@ hb_status hb_partition(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, uint64
 hb_status hb_match(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, uint64_t* out_pairs,
                    int out_on_device, uint64_t capacity, uint64_t* n_pairs) {
     return guard(ctx, [&](Ctx* c) { hb::match(c, rel_id, ruleset_id, plan, out_pairs, out_on_device, capacity, n_pairs); });
+}
+
+hb_status hb_match_noalloc(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, uint64_t* out_pairs,
+                           uint64_t capacity, uint64_t* n_pairs) {
+    return guard(ctx, [&](Ctx* c) { hb::match_noalloc(c, rel_id, ruleset_id, plan, out_pairs, capacity, n_pairs); });
 }
 
 hb_status hb_match_work(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, hb_work_stats* out) {

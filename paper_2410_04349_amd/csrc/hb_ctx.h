@@ -59,10 +59,12 @@ private:
         std::swap(c_, o.c_);
         std::swap(p_, o.p_);
         std::swap(n_, o.n_);
+        std::swap(borrowed_, o.borrowed_);
     }
     Ctx* c_ = nullptr;
     void* p_ = nullptr;
     size_t n_ = 0;
+    bool borrowed_ = false;   // carved from the context's arena: never freed
 };
 
 struct Column {
@@ -181,6 +183,24 @@ struct Ctx {
     bool batch_tuned = false;
     int tuned_form = 0;
     uint32_t tuned_grab = 0, tuned_occupancy = 1;
+    // the device's scratch array of the allocation-free entry point (its
+    // address on this device, or null with the reason in scratch_err)
+    uint8_t* scratch = nullptr;
+    std::string scratch_err;
+    // arena mode: while `arena` is set, every DevBuf::alloc takes the next
+    // 256-byte-aligned piece of [arena, arena + arena_cap) and no buffer is
+    // freed; the owner of the arena resets it when its call ends
+    uint8_t* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+
+    void* arena_take(size_t bytes) {
+        const size_t at = (arena_used + 255) & ~(size_t)255;
+        if (bytes > arena_cap || at > arena_cap - bytes)
+            fail(HB_ERR_LIMIT, "the call needs more than the " + std::to_string(arena_cap) +
+                                   " bytes of the scratch array (" + std::to_string(at + bytes) + " asked)");
+        arena_used = at + bytes;
+        return arena + at;
+    }
 
     void* raw_alloc(size_t bytes) {
         if (bytes == 0) bytes = 16;
@@ -205,7 +225,7 @@ struct Ctx {
 
     template <typename F>
     void timed(const char* name, F&& launch) {
-        if (!profiling) {
+        if (!profiling || arena) {   // no events inside an allocation-free call
             HB_HIP(launch());
             return;
         }
@@ -250,15 +270,21 @@ struct Ctx {
 inline void DevBuf::alloc(Ctx* c, size_t bytes) {
     release();
     c_ = c;
-    p_ = c->raw_alloc(bytes);
+    if (c->arena) {
+        p_ = c->arena_take(bytes == 0 ? 16 : bytes);
+        borrowed_ = true;
+    } else {
+        p_ = c->raw_alloc(bytes);
+    }
     n_ = bytes;
 }
 
 inline void DevBuf::release() {
-    if (p_ && c_) c_->raw_free(p_);
+    if (p_ && c_ && !borrowed_) c_->raw_free(p_);
     p_ = nullptr;
     n_ = 0;
     c_ = nullptr;
+    borrowed_ = false;
 }
 
 template <typename T>
@@ -300,6 +326,11 @@ inline std::vector<int> shifts_for_bits(int bits, int base) {
     for (int x = 0; x < bits; x += 8) s.push_back(base + x);
     return s;
 }
+
+// Address of this device's copy of the allocation-free entry point's
+// scratch array (hb_noalloc.hip); the device must be current.  Null, with
+// the reason in *err, when the runtime cannot give it.
+uint8_t* scratch_address(int device, std::string* err);
 
 // cost model (hb_learn.cpp)
 void costmodel_init(Ctx* c, uint64_t seed);
