@@ -260,8 +260,11 @@ def run_batched(args):
     print(json.dumps(result), flush=True)
 
 
-PROFILE_NAMES = ("match", "partition_sort", "gram_build", "lsh", "output_sort", "learned_plan",
-                 "block_features", "predict", "plan_choice")
+PROFILE_NAMES = ("match", "partition_sort", "gram_slots", "gram_build", "gram_sig", "char_sig", "lsh", "gather",
+                 "output_sort", "learned_plan", "block_features", "predict", "plan_choice")
+# steps bound by HBM bandwidth (their algorithmic bytes come from the library)
+STREAMING = ("gram_slots", "gram_build", "gram_sig", "char_sig", "lsh", "partition_sort", "gather", "output_sort")
+PEAK_HBM = 8.0e12   # bytes/s
 
 
 def train_cost_model(hb, ctx, workloads, np):
@@ -378,7 +381,8 @@ def main():
         of the plans alternating from step to step (A B, B A, ...), each
         step bracketed by device synchronisation; kernel times per plan
         from the library's HIP events."""
-        legs = {p: {"s": 0.0, "phase": {}, "prof": {n: [0.0, 0] for n in PROFILE_NAMES}} for p in plans}
+        legs = {p: {"s": 0.0, "phase": {}, "prof": {n: [0.0, 0] for n in PROFILE_NAMES},
+                    "bytes": {n: 0.0 for n in STREAMING}} for p in plans}
         for w in range(args.warmup):
             for p in plans:
                 n_cand, n_match = step(p, outs[p], {}, rules_)
@@ -397,6 +401,8 @@ def main():
                     ms, launches = hb.hb_profile_query(ctx, name)
                     legs[p]["prof"][name][0] += ms
                     legs[p]["prof"][name][1] += launches
+                for name in STREAMING:
+                    legs[p]["bytes"][name] += hb.hb_profile_bytes(ctx, name)
         hb.hb_profile_enable(ctx, False)
         for p in plans:
             L = legs[p]
@@ -439,6 +445,20 @@ def main():
         if not same:
             raise SystemExit("learned and heuristic plans disagree")
     prof = L["prof"]
+    # effective bandwidth of the streaming steps: algorithmic bytes / kernel time
+    streaming = {}
+    tot_b, tot_ms = 0.0, 0.0
+    for name in STREAMING:
+        ms, b = prof[name][0], L["bytes"][name]
+        if ms > 0:
+            streaming[name] = {"ms_per_step": ms / args.steps, "gb_per_step": b / args.steps / 1e9,
+                               "gb_per_s": b / (ms * 1e-3) / 1e9, "hbm_frac": b / (ms * 1e-3) / PEAK_HBM}
+            tot_b += b
+            tot_ms += ms
+    if tot_ms > 0:
+        streaming["all"] = {"ms_per_step": tot_ms / args.steps, "gb_per_step": tot_b / args.steps / 1e9,
+                            "gb_per_s": tot_b / (tot_ms * 1e-3) / 1e9, "hbm_frac": tot_b / (tot_ms * 1e-3) / PEAK_HBM}
+    log(f"[bench] streaming steps: {streaming}")
 
     pcie = None
     if args.host_io:
@@ -554,6 +574,7 @@ def main():
         "config": {"workload": describe(args.workload, rel.n_rows, len(rules), args.plan), "plan": args.plan,
                    "candidate_pairs": n_cand, "matched_pairs": n_match},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "streaming": streaming,
         "host_ms_per_step": {k: v * 1000.0 / args.steps for k, v in L["phase"].items()},
         "compare": compare,
         "cost_model": learned,

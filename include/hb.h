@@ -290,12 +290,20 @@ hb_status hb_plan_path(uint32_t plan, uint32_t n_preds, const double* sp, const 
 
 /* Kernel timing: when enabled, HIP events bracket each kernel launch of the
  * named step on the context stream.  Names: "match", "partition_sort",
- * "gram_build", "lsh", "output_sort", "log", "block_features",
- * "plan_choice"; and, as host wall time including synchronisation,
- * "learned_plan" (building one key partition's per-block learned plans) and
- * "predict" (cost-model inference inside it). */
+ * "gram_slots", "gram_build", "gram_sig", "char_sig", "lsh", "gather",
+ * "output_sort", "log", "block_features", "plan_choice"; and, as host wall
+ * time including synchronisation, "learned_plan" (building one key
+ * partition's per-block learned plans) and "predict" (cost-model inference
+ * inside it). */
 hb_status hb_profile_enable(hb_ctx* ctx, int on);
 hb_status hb_profile_query(hb_ctx* ctx, const char* name, double* total_ms, uint64_t* launches);
+/* Algorithmic HBM bytes of the timed launches counted under `name` since
+ * the last reset: what each launch must read once and write once (for
+ * "match": its feature columns; for the streaming steps "gram_slots",
+ * "gram_build", "gram_sig", "char_sig", "lsh", "partition_sort",
+ * "gather", "output_sort": their inputs and outputs), so bytes / time is
+ * the step's effective bandwidth. */
+hb_status hb_profile_bytes(hb_ctx* ctx, const char* name, double* bytes);
 hb_status hb_profile_reset(hb_ctx* ctx);
 
 /* Work counters of one instrumented evaluation pass: the same kernels with
@@ -306,7 +314,9 @@ hb_status hb_profile_reset(hb_ctx* ctx);
  * for its batch of 16 rows x 64 lanes, `lanes` = the pairs that evaluated
  * it, `passed` = the pairs for which it held, `work` = its work units (edit
  * distance: text bytes x 32-bit pattern words run; Jaccard: merged list
- * elements; string equality: bytes compared; others: pairs).  `pairs` is
+ * elements; string equality: bytes compared; kinds 0-4: the times a wave
+ * ran it in the one-pair-per-lane form, when at most one pair per lane was
+ * left, which `waves` does not count).  `pairs` is
  * the number of candidate pairs evaluated.  `lane_ops` is the algorithmic
  * int32 lane-operations of the pairs evaluated: value equality 2, |a-b| <= d
  * 4, each exact filter 4, string equality 2 + 1 per byte, edit distance 17

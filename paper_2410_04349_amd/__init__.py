@@ -45,7 +45,7 @@ EXPORTED = [
     "hb_create", "hb_destroy", "hb_last_error", "hb_version", "hb_load_relation", "hb_load_relation_async",
     "hb_release_relation",
     "hb_compile_rules", "hb_partition", "hb_match", "hb_match_noalloc", "hb_ruleset_estimates", "hb_ruleset_buckets",
-    "hb_epg_path", "hb_plan_path", "hb_profile_enable", "hb_profile_query", "hb_profile_reset", "hb_last_match_stats",
+    "hb_epg_path", "hb_plan_path", "hb_profile_enable", "hb_profile_query", "hb_profile_bytes", "hb_profile_reset", "hb_last_match_stats",
     "hb_match_work", "hb_costmodel_init", "hb_costmodel_set_params", "hb_costmodel_get_params",
     "hb_costmodel_train", "hb_costmodel_predict", "hb_costmodel_trace", "hb_costmodel_adam_step",
     "hb_costmodel_save", "hb_costmodel_load",
@@ -139,6 +139,7 @@ def _load_lib():
         "hb_plan_path": (I32, [U32, U32, P, P, U32, P, P, P, P, ctypes.POINTER(U32)]),
         "hb_profile_enable": (I32, [P, ctypes.c_int]),
         "hb_profile_query": (I32, [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64)]),
+        "hb_profile_bytes": (I32, [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)]),
         "hb_profile_reset": (I32, [P]),
         "hb_last_match_stats": (I32, [P, ctypes.POINTER(HbMatchStats)]),
         "hb_match_work": (I32, [P, U32, U32, I32, ctypes.POINTER(HbWorkStats)]),
@@ -414,6 +415,12 @@ def hb_profile_query(ctx: Context, name: str) -> Tuple[float, int]:
     n = ctypes.c_uint64()
     ctx.check(_lib.hb_profile_query(ctx.h, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def hb_profile_bytes(ctx: Context, name: str) -> float:
+    b = ctypes.c_double()
+    ctx.check(_lib.hb_profile_bytes(ctx.h, name.encode(), ctypes.byref(b)))
+    return b.value
 
 
 def hb_profile_reset(ctx: Context) -> None:

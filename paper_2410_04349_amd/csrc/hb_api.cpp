@@ -223,6 +223,9 @@ static void load_relation(Ctx* c, uint32_t n_rows, uint32_t n_cols, const hb_col
 
 // ------------------------------------------------------------ gram index
 
+// Bytes of a string column's arena (allocated with 16 bytes of padding).
+static double arena_bytes(const Column& col) { return col.bytes.size() >= 16 ? (double)(col.bytes.size() - 16) : 0.0; }
+
 static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
     auto key = std::make_pair(attr, q);
     auto it = rel.grams.find(key);
@@ -235,11 +238,16 @@ static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
     DevBuf slots(c, sizeof(uint64_t) * ((size_t)n + 1));
     g.off.alloc(c, sizeof(uint64_t) * ((size_t)n + 1));
     const ColDev* dcol = rel.d_cols.as<ColDev>() + attr;
-    HB_HIP(launch_gram_slots(dcol, n, q, slots.as<uint64_t>(), c->stream));
+    // algorithmic bytes: T string bytes, W <= T windows (codes), n rows
+    const double T = arena_bytes(rel.cols[attr]), nr = (double)n + 1.0;
+    const double W = std::max(0.0, T - (double)(q - 1) * (double)n);
+    c->timed("gram_slots", [&] { return launch_gram_slots(dcol, n, q, slots.as<uint64_t>(), c->stream); }, 16.0 * nr);
     zero(c, slots.as<uint64_t>() + n, sizeof(uint64_t));
     DevBuf tmp(c, sizeof(uint64_t) * scan_tmp_elems((size_t)n + 1));
-    HB_HIP(launch_exclusive_scan_u64(slots.as<uint64_t>(), g.off.as<uint64_t>(), (size_t)n + 1, tmp.as<uint64_t>(),
-                                     c->stream));
+    c->timed("gram_slots", [&] {
+        return launch_exclusive_scan_u64(slots.as<uint64_t>(), g.off.as<uint64_t>(), (size_t)n + 1, tmp.as<uint64_t>(),
+                                         c->stream);
+    }, 16.0 * nr);
     // no read-back: a row reserves at most one slot per byte, so the
     // column's byte count bounds the codes, and its longest row's window
     // count bounds every row's distinct codes (the LDS sizing needs no more)
@@ -251,13 +259,14 @@ static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
     c->timed("gram_build", [&] {
         return launch_gram_build(dcol, n, q, g.off.as<uint64_t>(), g.codes.as<uint32_t>(), g.cnt.as<uint32_t>(),
                                  g.flags.as<uint8_t>(), max_windows, c->stream);
-    });
+    }, 16.0 * nr + T + 4.0 * W + 5.0 * (double)n);
     g.max_cnt = max_windows;
     // long rows get a 256-bit signature: with ~100 codes a 64-bit one is
     // mostly ones and the Jaccard filter bound barely prunes
     g.sig_words = max_windows > 64 ? kLongSigWords : 1;
     g.sig.alloc(c, sizeof(uint64_t) * n * g.sig_words);
-    HB_HIP(launch_gram_sig(g.dev(), n, g.sig.as<uint64_t>(), c->stream));
+    c->timed("gram_sig", [&] { return launch_gram_sig(g.dev(), n, g.sig.as<uint64_t>(), c->stream); },
+             12.0 * (double)n + 4.0 * W + 8.0 * g.sig_words * (double)n);
     auto res = rel.grams.emplace(key, std::move(g));
     return res.first->second;
 }
@@ -413,10 +422,13 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
         // alone (it orders predicates only)
         const int op = pr.op == HB_ED_LE || pr.op == HB_ED_CROSS_LE ? 1
                      : pr.op == HB_JACCARD_GE ? 2 : pr.op == HB_ABSDIFF_LE ? 3 : 0;
+        const Column& lc = rel.cols[pr.attr];
+        const double lsh_bytes = lc.type == HB_COL_STRING ? 8.0 * ((double)rel.n_rows + 1.0) + arena_bytes(lc)
+                                                         : 8.0 * (double)rel.n_rows;
         c->timed("lsh", [&] {
             return launch_lsh_hist(rel.d_cols.as<ColDev>() + pr.attr, rel.n_rows, op, pr.q, pr.d,
                                    hist.as<unsigned long long>() + p * kLshK, c->stream);
-        });
+        }, lsh_bytes);
     }
     std::vector<uint64_t> h(kLshK * np);
     HB_HIP(hipMemcpyAsync(h.data(), hist.get(), sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost, c->stream));
@@ -504,11 +516,13 @@ static uint32_t sort_rows_by(Ctx* c, Relation& rel, const std::vector<uint32_t>&
                                  c->stream));
         std::vector<int> sh = shifts_for_bits(bit_width(hi - lo), 0);
         bool in_alt = false;
+        // per 8-bit pass: the histogram reads the keys, the scatter reads
+        // and writes keys and row ids
         c->timed("partition_sort", [&] {
             return radix_sort_pairs(keys.as<uint64_t>(), rows_out.as<uint32_t>(), keys_alt.as<uint64_t>(),
                                     rows_alt.as<uint32_t>(), nv, sh.data(), (int)sh.size(), rtmp.get(), &in_alt,
                                     c->stream);
-        });
+        }, 32.0 * (double)nv * (double)sh.size());
         if (in_alt) HB_HIP(hipMemcpyAsync(rows_out.get(), rows_alt.get(), sizeof(uint32_t) * nv,
                                           hipMemcpyDeviceToDevice, c->stream));
     }
@@ -650,7 +664,8 @@ static const uint64_t* char_signature(Ctx* c, Relation& rel, uint32_t attr) {
     if (it != rel.char_sig.end()) return it->second.as<uint64_t>();
     if (c->arena) fail(HB_ERR_STATE, "internal: character signature built inside an allocation-free call");
     DevBuf sig(c, sizeof(uint64_t) * rel.n_rows);
-    HB_HIP(launch_char_sig(rel.d_cols.as<ColDev>() + attr, rel.n_rows, sig.as<uint64_t>(), c->stream));
+    c->timed("char_sig", [&] { return launch_char_sig(rel.d_cols.as<ColDev>() + attr, rel.n_rows, sig.as<uint64_t>(), c->stream); },
+             16.0 * (double)rel.n_rows + arena_bytes(rel.cols[attr]));
     const uint64_t* p = sig.as<uint64_t>();
     rel.char_sig.emplace(attr, std::move(sig));
     return p;
@@ -880,7 +895,14 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     kp.f32.alloc(c, sizeof(uint32_t) * stride * n32);
     gp.f64 = kp.f64.as<uint64_t>();
     gp.f32 = kp.f32.as<uint32_t>();
-    HB_HIP(launch_gather_features(gp, c->stream));
+    // reads: the permutation, per int column its value, per string column
+    // two offsets and the character signature, per q-gram column count,
+    // flag and signature words; writes: every feature column
+    const double nvp = (double)P.n_valid;
+    const double gather_in = nvp * (4.0 + 8.0 * m.n_int + 24.0 * m.n_str + 5.0 * m.n_gram + 8.0 * gram_cols);
+    const double feat_bytes = (double)stride * (8.0 * n64 + 4.0 * n32);
+    c->timed("gather", [&] { return launch_gather_features(gp, c->stream); }, gather_in + feat_bytes);
+    kp.feat_bytes = feat_bytes;
 
     // LDS of the one-wave workgroup: the pattern-match table, the
     // long-pattern Myers state and the current row's q-gram lists, then the
@@ -1163,7 +1185,7 @@ void sort_pairs(Ctx* c, DevBuf& pairs, uint64_t n, uint64_t n_rows, DevBuf& resu
         c->timed("output_sort", [&] {
             return radix_sort_pairs(pairs.as<uint64_t>(), nullptr, alt.as<uint64_t>(), nullptr, (uint32_t)n, sh.data(),
                                     (int)sh.size(), rtmp.get(), &in_alt, c->stream);
-        });
+        }, 24.0 * (double)n * (double)sh.size());
         HB_HIP(hipMemcpyAsync(result.get(), in_alt ? alt.get() : pairs.get(), sizeof(uint64_t) * n,
                               hipMemcpyDeviceToDevice, c->stream));
     } else if (n == 1) {
@@ -1214,7 +1236,7 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
             kp.mp.out = out.as<uint64_t>();
             kp.mp.cap = cap;
             kp.mp.counter = counter.as<unsigned long long>();
-            c->timed("match", [&] { return launch_match(kp.mp, c->stream); });
+            c->timed("match", [&] { return launch_match(kp.mp, c->stream); }, kp.feat_bytes);
             tiles += kp.mp.n_tiles;
             ++launches;
         }
@@ -1247,10 +1269,13 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
         ws->pairs = h[kCountPairs];
         double ops = 0.0, iss = 0.0, bops = 0.0;
         for (int op = 0; op < HB_N_OPKINDS; ++op) {
-            ops += kAlgBase[op] * ws->lanes[op] + kAlgUnit[op] * ws->work[op];
-            iss += kIssBase[op] * ws->lanes[op] + kIssUnit[op] * ws->work[op];
-            // cheap steps run for every lane of the batch; exact ones per pair
-            bops += op <= OP_JACF ? kIssBase[op] * (double)ws->waves[op] * kRows * 64
+            const double units = op <= OP_JACF ? 0.0 : (double)ws->work[op];   // filters: no work units
+            ops += kAlgBase[op] * ws->lanes[op] + kAlgUnit[op] * units;
+            iss += kIssBase[op] * ws->lanes[op] + kIssUnit[op] * units;
+            // cheap steps run for every lane of every row of the batch, or
+            // for every lane once in the one-pair-per-lane form; exact ones
+            // per pair
+            bops += op <= OP_JACF ? kIssBase[op] * ((double)ws->waves[op] * kRows + (double)ws->work[op]) * 64
                                   : kIssBase[op] * ws->lanes[op] + kIssUnit[op] * ws->work[op];
         }
         ws->lane_ops = ops;
@@ -1611,6 +1636,15 @@ hb_status hb_profile_query(hb_ctx* ctx, const char* name, double* total_ms, uint
         auto it = c->prof.find(name);
         if (total_ms) *total_ms = it == c->prof.end() ? 0.0 : it->second.ms;
         if (launches) *launches = it == c->prof.end() ? 0 : it->second.launches;
+    });
+}
+
+hb_status hb_profile_bytes(hb_ctx* ctx, const char* name, double* bytes) {
+    return guard(ctx, [&](Ctx* c) {
+        if (!name || !bytes) hb::fail(HB_ERR_INVALID_ARG, "NULL argument");
+        c->drain_profile();
+        auto it = c->prof.find(name);
+        *bytes = it == c->prof.end() ? 0.0 : it->second.bytes;
     });
 }
 

@@ -150,11 +150,13 @@ struct CostModel {
 struct ProfEntry {
     double ms = 0.0;
     uint64_t launches = 0;
+    double bytes = 0.0;   // algorithmic HBM bytes of the launches
 };
 
 struct Pending {
     std::string name;
     hipEvent_t a, b;
+    double bytes = 0.0;
 };
 
 struct Batch;   // batched matching (hb_batch.cpp)
@@ -223,14 +225,17 @@ struct Ctx {
         else (void)hipFreeAsync(p, stream);
     }
 
+    // `bytes`: the launch's algorithmic HBM bytes (each input it must read
+    // once, each output it must write once)
     template <typename F>
-    void timed(const char* name, F&& launch) {
+    void timed(const char* name, F&& launch, double bytes = 0.0) {
         if (!profiling || arena) {   // no events inside an allocation-free call
             HB_HIP(launch());
             return;
         }
         Pending pd;
         pd.name = name;
+        pd.bytes = bytes;
         HB_HIP(hipEventCreate(&pd.a));
         HB_HIP(hipEventCreate(&pd.b));
         HB_HIP(hipEventRecord(pd.a, stream));
@@ -259,6 +264,7 @@ struct Ctx {
             auto& e = prof[pd.name];
             e.ms += ms;
             e.launches += 1;
+            e.bytes += pd.bytes;
             (void)hipEventDestroy(pd.a);
             (void)hipEventDestroy(pd.b);
         }

@@ -28,6 +28,7 @@ struct KeyPlan {
     std::vector<Instr> code;
     MatchParams mp{};
     DevBuf f64, f32;
+    double feat_bytes = 0.0;   // bytes of the feature columns (the match kernel reads each once)
     // learned plans: per-slot plans on the device, the block -> slot map and
     // the choice kernel's counters (read after matching)
     bool own_code = false;

@@ -454,7 +454,68 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             }
             const uint32_t before = alive;
             uint32_t work = 0;
-            switch (op) {
+            const bool single = op <= OP_JACF && !__any((alive & (alive - 1u)) != 0u);
+            if (single) {
+                // At most one pair left per lane (the usual state after a
+                // rule's first filter): each lane evaluates only its own
+                // pair, reading that row's features with per-lane loads,
+                // instead of the batch's 16 rows.  The arithmetic is the
+                // batch form's, row for row.
+                const uint32_t r = alive != 0u ? (uint32_t)__builtin_ctz(alive) : 0u;
+                const uint64_t pr = pi0 + r;
+                const uint32_t vmask_i = f32[n + pr];
+                bool ok = false;
+                switch (op) {
+                case OP_EQ_INT:
+                case OP_ABSDIFF: {
+                    const int64_t vj = (int64_t)J64(res);
+                    const int64_t d = op == OP_EQ_INT ? 0 : (int64_t)param;
+                    const int64_t lo = vj < INT64_MIN + d ? INT64_MIN : vj - d;
+                    const int64_t hi = vj > INT64_MAX - d ? INT64_MAX : vj + d;
+                    const int64_t vi = (int64_t)f64[res * n + pr];
+                    ok = ((vmask_j & vmask_i) >> res) & 1 && vi >= lo && vi <= hi;
+                    break;
+                }
+                case OP_EQF: {
+                    const uint32_t li = f32[(str32 + res) * n + pr];
+                    const uint64_t ci = f64[(str64 + res) * n + pr];
+                    ok = ((vmask_j & vmask_i) >> (16 + res)) & 1 && li == J32(str32 + res) && ci == J64(str64 + res);
+                    break;
+                }
+                case OP_EDF: {
+                    const int lj = (int)J32(str32 + res);
+                    const uint64_t cj = J64(str64 + res);
+                    const int k = (int)param;
+                    const int li = (int)f32[(str32 + res) * n + pr];
+                    const uint64_t ci = f64[(str64 + res) * n + pr];
+                    const int both = (int)(__popc((uint32_t)ci & (uint32_t)cj) +
+                                           __popc((uint32_t)(ci >> 32) & (uint32_t)(cj >> 32)));
+                    const int t = max((int)__popcll(ci) - k, (int)__popcll(cj) - k);
+                    ok = ((vmask_j & vmask_i) >> (16 + res)) & 1 && both >= t && li >= lj - k && li <= lj + k;
+                    break;
+                }
+                default: {   // OP_JACF: the bound of the batch form, in exact 64-bit arithmetic
+                    const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
+                    if (num == 0) {
+                        ok = ((vmask_j & vmask_i) >> (24 + res)) & 1;
+                        break;
+                    }
+                    const uint32_t gcol = gram64 + P.gram[res].sig_col;
+                    const uint32_t wb = J32(jf32 + res);
+                    const uint32_t wa = f32[(jf32 + res) * n + pr];
+                    uint32_t iub = min(wa >> 16, wb >> 16);
+                    const uint32_t words = P.gram[res].sig_words;
+                    for (uint32_t w = 0; w < words; ++w) {
+                        const uint64_t gi = f64[(gcol + w) * n + pr], gj = J64(gcol + w);
+                        iub += (uint32_t)__popcll(gi & gj);
+                    }
+                    ok = (uint64_t)iub * nd >= (uint64_t)num * ((wa & 0xFFFFu) + (wb & 0xFFFFu));
+                    break;
+                }
+                }
+                alive = ok ? alive : 0u;
+                work = 1;
+            } else switch (op) {
             case OP_EQ_INT:
             case OP_ABSDIFF: {
                 const int64_t vj = (int64_t)J64(res);
@@ -678,10 +739,12 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     ev += __popcll(__ballot((before >> r) & 1));
                     ps += __popcll(__ballot((alive >> r) & 1));
                 }
-                const uint32_t waves = 1;
+                // filters: `waves` counts steps in the 16-row form, `work`
+                // steps in the one-pair-per-lane form
+                const uint32_t waves = op <= OP_JACF && single ? 0u : 1u;
                 uint32_t w = op <= OP_JACF ? 0u : work;
                 for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
-                if (op <= OP_JACF) w = ev;
+                if (op <= OP_JACF) w = single ? 1u : 0u;
                 if (lane == 0) {
                     atomicAdd(&s_cnt[op * 4 + 0], (unsigned long long)waves);
                     atomicAdd(&s_cnt[op * 4 + 1], (unsigned long long)ev);

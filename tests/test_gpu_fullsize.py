@@ -1,16 +1,29 @@
-"""Parity at full workload sizes, where the oracle cannot enumerate every
-candidate pair: every emitted pair is checked by the oracle (soundness); a
-seeded sample of candidate pairs, drawn uniformly over each key's candidate
-pairs, plus every (duplicate, source) pair, is checked for membership
-(completeness on the sample); the candidate count is checked against the
-closed form.  Runs both plans, the learned one with a freshly trained model,
-in the launch configuration the benchmark times."""
+"""Parity at full workload sizes.  Every emitted pair is checked by the
+oracle (soundness).  Whole blocks are checked exhaustively: the result
+restricted to the rows of the largest blocks of each key (several 64 x 64
+tiles each), or of a seeded draw of blocks, equals the oracle's Ca of the
+sub-relation on those rows (Ca is defined pairwise, so a row subset's
+result is the full result restricted to it).  Where the oracle enumerated
+the whole workload on a host CPU (tests/golden/fullsize_digests.json,
+written by tests/golden/make_fullsize_digests.py), the sorted pair list's
+count and sha256 equal the oracle's.  A seeded sample of candidate pairs,
+drawn uniformly over each key's candidate pairs, plus every (duplicate,
+source) pair, is checked for membership; the candidate count is checked
+against the closed form.  Runs both plans, the learned one with a freshly
+trained model, in the launch configuration the benchmark times."""
+import hashlib
+import importlib.util
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 from gen import EQ, STRING, workloads
 from learned_util import train_model
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -122,7 +135,87 @@ def eval_in_chunks(rel, rules, pairs, chunk=200_000):
     return out
 
 
-def check(hb, ctx, rel, rules, n_sample, seed, plans=("heuristic", "learned"), max_sample=None, ordered=False):
+def _digests():
+    spec = importlib.util.spec_from_file_location("make_fullsize_digests",
+                                                  os.path.join(GOLDEN, "make_fullsize_digests.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    path = os.path.join(GOLDEN, "fullsize_digests.json")
+    table = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            table = json.load(fh)
+    return mod, table
+
+
+def sha256_pairs(p):
+    return hashlib.sha256(np.ascontiguousarray(p, dtype="<u8").tobytes()).hexdigest()
+
+
+def check_digest(name, rel, got):
+    """The whole result against the oracle's, by count and sha256 of the
+    sorted packed list (when the oracle's full enumeration is on file), and
+    the result restricted to each block set on file against the oracle's
+    Ca of that sub-relation.  Returns whether the full enumeration was on
+    file."""
+    mod, table = _digests()
+    full = name in table
+    if full:
+        rec = table[name]
+        assert mod.relation_digest(rel) == rec["relation_sha256"], "the generator's output changed: rerun the script"
+        assert len(got) == rec["matched_pairs"]
+        assert sha256_pairs(got) == rec["pairs_sha256"]
+        print(f"[gpu-case] {name}: all {len(got)} pairs equal the oracle's full enumeration (sha256)", flush=True)
+    for bname, rec in sorted(table.items()):
+        if not bname.startswith(name + "/"):
+            continue
+        rows = mod.digest_rows(rel, rec["blocks"])
+        assert mod.rows_digest(rows) == rec["rows_sha256"]
+        mapped = restrict(got, rows)
+        assert len(mapped) == rec["matched_pairs"] and sha256_pairs(mapped) == rec["pairs_sha256"], bname
+        print(f"[gpu-case] {bname}: {len(rows)} rows, {len(mapped)} matches equal the oracle's (sha256)", flush=True)
+    return full
+
+
+def block_rows(rel, key, largest=0, draw=0, seed=0, max_size=None):
+    """Rows of whole blocks of `key`: its `largest` largest blocks and a
+    seeded draw of `draw` other blocks of at least two (and at most
+    `max_size`) rows."""
+    vals = rel.columns[key].values
+    ok = valid_mask(rel.columns[key], rel.n_rows)
+    idx = np.flatnonzero(ok)
+    uniq, inv, cnt = np.unique(vals[idx], return_inverse=True, return_counts=True)
+    order = np.argsort(-cnt, kind="stable")
+    chosen = list(order[:largest])
+    rest = order[largest:]
+    rest = rest[(cnt[rest] >= 2) & (cnt[rest] <= (max_size or cnt.max()))]
+    if draw and len(rest):
+        chosen += list(np.random.default_rng(seed).choice(rest, size=min(draw, len(rest)), replace=False))
+    return idx[np.isin(inv, np.asarray(chosen, dtype=np.int64))]
+
+
+def restrict(got, rows):
+    """The pairs of `got` with both rows in `rows` (ascending), renumbered
+    to positions in `rows`; the order is kept."""
+    i, j = got >> np.uint64(32), got & np.uint64(0xFFFFFFFF)
+    inside = np.isin(i, rows) & np.isin(j, rows)
+    mi = np.searchsorted(rows, i[inside]).astype(np.uint64)
+    mj = np.searchsorted(rows, j[inside]).astype(np.uint64)
+    return (mi << np.uint64(32)) | mj
+
+
+def check_blocks(rel, rules, got, rows):
+    """Ca(D) restricted to pairs of `rows` equals the oracle's Ca of the
+    sub-relation on `rows`, element by element."""
+    rows = np.unique(rows)
+    want = oracle.blocking(rel.take(rows), rules, threads=16)
+    mapped = restrict(got, rows)
+    assert np.array_equal(mapped, want), (len(mapped), len(want))
+    print(f"[gpu-case] whole blocks: {len(rows)} rows, {len(want)} matches, equal to the oracle's", flush=True)
+
+
+def check(hb, ctx, rel, rules, n_sample, seed, plans=("heuristic", "learned"), max_sample=None, ordered=False,
+          name=None, blocks=None):
     rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
     rs = hb.hb_compile_rules(ctx, rid, rules)
     n_cand = hb.hb_partition(ctx, rid, rs)
@@ -153,16 +246,26 @@ def check(hb, ctx, rel, rules, n_sample, seed, plans=("heuristic", "learned"), m
     assert np.array_equal(have, want), int(np.sum(have != want))
     print(f"[gpu-case] {len(got)} matches all confirmed; {len(sample)} sampled pairs, "
           f"{int(want.sum())} matching, agree", flush=True)
+    for spec in blocks or ():
+        check_blocks(rel, rules, got, np.concatenate([block_rows(rel, **b) for b in spec]))
+    if name is not None and not check_digest(name, rel, got):
+        print(f"[gpu-case] {name}: no full oracle enumeration on file (whole blocks and samples only)", flush=True)
 
 
 def test_plain_1m_full_size(hb, ctx):
+    """Whole result against the oracle's full enumeration; the two largest
+    blocks (about 5,000 rows, 79 tiles wide) exhaustively."""
     rel, rules = workloads.plain_1m()
-    check(hb, ctx, rel, rules, 300_000, 1)
+    check(hb, ctx, rel, rules, 300_000, 1, name="plain_1m",
+          blocks=[[{"key": 3, "largest": 2}]])
 
 
 def test_long_titles_5m_full_size(hb, ctx):
+    """Whole result against the oracle's full enumeration; a seeded draw of
+    4,000 whole brand blocks exhaustively."""
     rel, rules = workloads.long_titles_5m()
-    check(hb, ctx, rel, rules, 200_000, 2)
+    check(hb, ctx, rel, rules, 200_000, 2, name="long_titles_5m",
+          blocks=[[{"key": 0, "largest": 1, "draw": 4000, "seed": 5}]])
 
 
 def test_plain_1m_ordered_full_size(hb, ctx):
@@ -177,6 +280,11 @@ def test_learned_10m_full_size(hb, ctx):
     """The two-key, 20-rule, 10M-tuple workload: candidate count against
     the inclusion-exclusion closed form, every emitted pair confirmed by the
     oracle, a sample of both keys' candidate pairs checked, both plans
-    equal."""
+    equal; a seeded draw of whole blocks of each key against the oracle
+    here, and the largest block of each key (about 5,000 rows, where this
+    oracle evaluates some 10^4 pairs per second) against its result on
+    file."""
     rel, rules = workloads.learned_10m()
-    check(hb, ctx, rel, rules, 150_000, 3, max_sample=300_000)
+    check(hb, ctx, rel, rules, 150_000, 3, max_sample=300_000, name="learned_10m",
+          blocks=[[{"key": 4, "draw": 300, "seed": 6, "max_size": 150},
+                   {"key": 5, "draw": 300, "seed": 7, "max_size": 150}]])
