@@ -766,19 +766,28 @@ static KeyRes key_resources(const Relation& rel, const RuleSet& rs, size_t ka) {
 // Bytecode of a sequential path for key `ka`: each possible rule becomes its
 // cheap steps and filters in path order, then its exact similarity
 // predicates in path order, then a checkpoint.  The equality on this key is
-// dropped (it holds inside a block).
+// dropped (it holds inside a block).  Consecutive rules whose first step is
+// the same cheap step share it, as rules sharing a prefix share the
+// execution tree's edge (Section 4.2): the step runs once as a guard, the
+// rules run their remaining steps on the pairs that passed it, and a
+// group end returns to every pair (not for rule sets that tell t from s).
+// `segs` (optional) receives each rule's segment: its first instruction,
+// its first-stage steps (in path order) and its guard step.
 static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, const std::vector<PathRule>& path,
-                                    size_t ka, const KeyRes& R) {
-    std::vector<Instr> code;
+                                    size_t ka, const KeyRes& R, std::vector<RuleSeg>* segs = nullptr) {
     auto spec_of = [&](uint32_t p) -> const PredSpec* {
         for (const PredSpec& sp : R.specs)
             if (sp.pred == p) return &sp;
         return nullptr;
     };
+    struct RuleCode {
+        std::vector<Instr> first, verify;
+        std::vector<uint32_t> first_preds;
+    };
+    std::vector<RuleCode> rc;
     for (const PathRule& pr : path) {
         if (!rule_possible(rel, rs, pr.preds, ka)) continue;
-        const size_t first = code.size();
-        std::vector<Instr> verify;
+        RuleCode r;
         for (uint32_t p : pr.preds) {
             const PredSpec* sp = spec_of(p);
             if (!sp) continue;   // the key's own equality
@@ -796,43 +805,84 @@ static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, cons
             case OP_XEQ:
             case OP_XED:
                 in.op = sp->op;
-                code.push_back(in);
+                r.first.push_back(in);
                 break;
             case OP_EQ_STR:
                 f.op = OP_EQF;
                 in.op = OP_EQ_STR;
-                code.push_back(f);
-                verify.push_back(in);
+                r.first.push_back(f);
+                r.verify.push_back(in);
                 break;
             case OP_ED:
                 f.op = OP_EDF;
                 in.op = OP_ED;
-                code.push_back(f);
-                verify.push_back(in);
+                r.first.push_back(f);
+                r.verify.push_back(in);
                 break;
             default:
                 f.op = OP_JACF;
                 in.op = OP_JAC;
-                code.push_back(f);
-                verify.push_back(in);
+                r.first.push_back(f);
+                r.verify.push_back(in);
                 break;
             }
+            r.first_preds.push_back(p);
         }
         if (!pr.verify.empty()) {
             // the exact checks in the given order
             std::vector<Instr> ordered;
             for (uint32_t p : pr.verify)
-                for (const Instr& in : verify)
+                for (const Instr& in : r.verify)
                     if (in.slot == (uint8_t)p) ordered.push_back(in);
-            if (ordered.size() != verify.size()) fail(HB_ERR_STATE, "internal: verification order mismatch");
-            verify.swap(ordered);
+            if (ordered.size() != r.verify.size()) fail(HB_ERR_STATE, "internal: verification order mismatch");
+            r.verify.swap(ordered);
         }
-        code.insert(code.end(), verify.begin(), verify.end());
-        Instr cp{};
-        cp.op = OP_CP;
-        code.push_back(cp);
-        const uint16_t cpi = (uint16_t)(code.size() - 1);
-        for (size_t x = first; x < code.size(); ++x) code[x].cp = cpi;
+        rc.push_back(std::move(r));
+    }
+    auto same_step = [](const Instr& a, const Instr& b) {
+        return a.op == b.op && a.op <= OP_JACF && a.res == b.res && a.aux == b.aux && a.param == b.param;
+    };
+    std::vector<Instr> code;
+    if (segs) segs->clear();
+    for (size_t x = 0; x < rc.size();) {
+        size_t y = x + 1;   // [x, y): rules sharing their first step
+        if (!rs.ordered && !rc[x].first.empty())
+            while (y < rc.size() && !rc[y].first.empty() && same_step(rc[y].first[0], rc[x].first[0])) ++y;
+        const bool group = y - x >= 2;
+        size_t guard_at = 0;
+        if (group) {
+            Instr g = rc[x].first[0];
+            g.aux = g.op;
+            g.op = OP_GUARD;
+            guard_at = code.size();
+            code.push_back(g);
+        }
+        for (size_t k = x; k < y; ++k) {
+            RuleCode& r = rc[k];
+            const size_t skip = group ? 1 : 0;
+            const size_t first = code.size();
+            code.insert(code.end(), r.first.begin() + skip, r.first.end());
+            code.insert(code.end(), r.verify.begin(), r.verify.end());
+            Instr cp{};
+            cp.op = OP_CP;
+            code.push_back(cp);
+            const uint16_t cpi = (uint16_t)(code.size() - 1);
+            for (size_t i = first; i < code.size(); ++i) code[i].cp = cpi;
+            if (segs) {
+                RuleSeg sg;
+                sg.start = (uint32_t)first;
+                sg.first_preds.assign(r.first_preds.begin() + skip, r.first_preds.end());
+                sg.guard_pred = group ? (int)r.first_preds[0] : -1;
+                segs->push_back(std::move(sg));
+            }
+        }
+        if (group) {
+            Instr e{};
+            e.op = OP_ENDGUARD;
+            code.push_back(e);
+            code[guard_at].cp = (uint16_t)(code.size() - 1);
+        }
+        x = y;
     }
     if (code.size() > (size_t)kMaxPlan) fail(HB_ERR_LIMIT, "plan too long");
     return code;
@@ -983,35 +1033,27 @@ static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyP
     if (!c->model.ready) fail(HB_ERR_STATE, "the learned plan needs a cost model (hb_costmodel_train or _set_params)");
     const uint32_t nb = kp.mp.n_blocks;
     const uint32_t ns = (uint32_t)R.specs.size();
-    kp.code = emit_code(rel, rs, heuristic, ka, R);
+    std::vector<RuleSeg> segs;
+    kp.code = emit_code(rel, rs, heuristic, ka, R, &segs);
     kp.mp.plan_len = (uint32_t)kp.code.size();
-    // the partition's rules in heuristic order, each with its steps
+    // the partition's rules in heuristic order: where each rule's segment
+    // starts, its first-stage steps and the guard step it sits under
     std::vector<int> spec_of(rs.distinct.size(), -1);
     for (uint32_t x = 0; x < ns; ++x) spec_of[R.specs[x].pred] = (int)x;
     PlanChoiceParams C{};
-    uint32_t n_rules = 0, seg = 0;
-    bool ok = nb > 0 && ns > 0;
-    for (const PathRule& pr : heuristic) {
-        if (!ok || !rule_possible(rel, rs, pr.preds, ka)) continue;
-        if (n_rules >= (uint32_t)kMaxPlanRules) {
-            ok = false;
-            break;
-        }
-        uint32_t len = 0, nv = 0;
-        for (uint32_t p : pr.preds) {
-            if (spec_of[p] < 0) continue;
-            if (len >= (uint32_t)kMaxRuleSteps) fail(HB_ERR_LIMIT, "rule with more than 10 steps");
-            C.rule_spec[n_rules][len++] = (uint8_t)spec_of[p];
-            const uint8_t op = (uint8_t)R.specs[spec_of[p]].op;
-            nv += op == OP_EQ_STR || op == OP_ED || op == OP_JAC;
-        }
-        C.rule_len[n_rules++] = (uint8_t)len;
-        seg += len + nv + 1;
-    }
-    // the device rewrite relies on the segment layout of the heuristic plan
-    if (!ok || n_rules == 0 || seg != kp.mp.plan_len) {
+    const uint32_t n_rules = (uint32_t)segs.size();
+    const bool ok = nb > 0 && ns > 0 && n_rules > 0 && n_rules <= (uint32_t)kMaxPlanRules;
+    if (!ok) {
         *n_fallback += nb;
         return;
+    }
+    for (uint32_t r = 0; r < n_rules; ++r) {
+        const RuleSeg& sg = segs[r];
+        if (sg.first_preds.size() > (size_t)kMaxRuleSteps) fail(HB_ERR_LIMIT, "rule with more than 10 steps");
+        C.rule_len[r] = (uint8_t)sg.first_preds.size();
+        C.rule_seg[r] = (uint16_t)sg.start;
+        C.rule_guard[r] = sg.guard_pred < 0 ? (uint8_t)0xFF : (uint8_t)spec_of[sg.guard_pred];
+        for (size_t k = 0; k < sg.first_preds.size(); ++k) C.rule_spec[r][k] = (uint8_t)spec_of[sg.first_preds[k]];
     }
     const Partition& part = rel.parts.at(rs.keys[ka]);
     const uint32_t nl = part.n_big;   // blocks with per-block plans; the rest keep slot 0
@@ -1273,7 +1315,7 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
             ops += kAlgBase[op] * ws->lanes[op] + kAlgUnit[op] * units;
             iss += kIssBase[op] * ws->lanes[op] + kIssUnit[op] * units;
             // cheap steps run for every lane of every row of the batch, or
-            // for every lane once in the one-pair-per-lane form; exact ones
+            // for every lane once per round of the per-lane form; exact ones
             // per pair
             bops += op <= OP_JACF ? kIssBase[op] * ((double)ws->waves[op] * kRows + (double)ws->work[op]) * 64
                                   : kIssBase[op] * ws->lanes[op] + kIssUnit[op] * ws->work[op];

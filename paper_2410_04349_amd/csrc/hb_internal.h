@@ -11,6 +11,7 @@ namespace hb {
 
 constexpr int kTile = 64;        // tuples per tile side (one wave of j's)
 constexpr int kRows = 16;        // i-rows per wave batch (four batches per 64-row tile)
+constexpr int kSparseRows = 4;   // a filter step runs per lane, live row by live row, when no lane has more
 constexpr uint64_t kMaxTiles = (1ull << 30) - 8;   // one launch's grid: 4 x tiles, rounded up to 32 < 2^32
 constexpr int kLshK = 1024;      // LSH buckets of the selectivity estimate
 constexpr int kMaxIntRes = 16;   // int attributes staged per tile
@@ -69,7 +70,13 @@ enum Op : uint8_t {
     // valuations get a mask each)
     OP_CONST = 9,    // t.A = c (aux 0) or s.A = c (aux 1); param = c
     OP_XEQ = 10,     // t.A = s.B: res = A, aux = B (both int resources)
-    OP_XED = 11      // Levenshtein(t.A, s.B) <= k: res = A, aux = B (string resources), param = k
+    OP_XED = 11,     // Levenshtein(t.A, s.B) <= k: res = A, aux = B (string resources), param = k
+    // a first-stage step shared by consecutive rules (the execution tree's
+    // shared edge, Section 4.2): OP_GUARD evaluates the step whose operation
+    // is in `aux` once, and the rules up to the OP_ENDGUARD at `cp` start
+    // from the pairs that pass it; OP_ENDGUARD returns to every pair
+    OP_GUARD = 12,
+    OP_ENDGUARD = 13
 };
 
 // One step of the sequential execution path.  `slot` identifies the step
@@ -298,7 +305,9 @@ struct PlanChoiceParams {
     uint32_t n_rules;                 // rules of the partition's plan, in heuristic order
     uint32_t n_slots;                 // table size (power of two, <= kPlanSlots)
     uint32_t plan_len;                // instructions of one plan
-    uint8_t rule_len[kMaxPlanRules];  // steps per rule
+    uint8_t rule_len[kMaxPlanRules];  // first-stage steps per rule (a shared guard step excluded)
+    uint16_t rule_seg[kMaxPlanRules]; // first instruction of each rule's segment
+    uint8_t rule_guard[kMaxPlanRules];   // spec index of the rule's shared guard step, 0xFF: none
     uint8_t rule_spec[kMaxPlanRules][kMaxRuleSteps];   // spec index of each step, heuristic order
     uint8_t spec_kind[kMaxSpecs];     // plan operation of each spec (Op)
     unsigned long long* keys;         // [n_slots] choice hash per slot, 0 = empty

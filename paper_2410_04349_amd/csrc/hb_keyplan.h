@@ -24,6 +24,15 @@ struct KeyRes {
 
 // One key partition ready to match: gathered feature columns, LDS layout
 // and the plan (host bytecode, or per-slot plans already on the device).
+// One rule's segment of a key plan (emit_code): its first instruction,
+// the distinct predicates of its first-stage steps in plan order, and the
+// predicate of the guard step it shares with its neighbours (-1: none).
+struct RuleSeg {
+    uint32_t start = 0;
+    std::vector<uint32_t> first_preds;
+    int guard_pred = -1;
+};
+
 struct KeyPlan {
     std::vector<Instr> code;
     MatchParams mp{};

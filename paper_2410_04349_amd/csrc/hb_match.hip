@@ -18,10 +18,13 @@
 // q-gram signature bound for Jaccard), one vector instruction sequence per
 // row appending the row's result bit with an add-with-carry; the expensive
 // predicates (edit distance, Jaccard, string equality) then run row by row
-// only where some lane passed every filter of the rule.  Predicates shared
-// by several rules are evaluated again in each (a cache cost more registers
-// than it saved).  Matched lanes are compacted with a ballot, one atomic
-// per wave-row.
+// only where some lane passed every filter of the rule.  Once few pairs
+// are left, a filter step runs per lane, one live row per round, instead
+// of over the 16 rows.  Consecutive rules that start with the same cheap
+// step share it (a guard step, run once); predicates shared further down
+// are evaluated again in each rule (a cache cost more registers than it
+// saved).  Matched lanes are compacted with a ballot, one atomic per
+// wave-row.
 //
 // Edit distance: Myers' bit-parallel algorithm in Hyyro's formulation for
 // the Levenshtein distance (pattern = t_i, one bit per pattern byte, the
@@ -341,8 +344,15 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             if (lane == 0 && cnt) atomicAdd(&s_cnt[kCountPairs], (unsigned long long)cnt);
         }
 
+        // the per-lane form pays per-lane loads each round: taken when no
+        // lane has more than min(4, rows / 2) live rows
+        const uint32_t sparse_max = (uint32_t)min(kSparseRows, nr >> 1);
         uint32_t matched = 0, alive = pairs;
         uint32_t fwd = pairs, bwd = pairs, matched_b = 0;   // kOrd only: alive = fwd | bwd
+        // the pairs a rule starts from: every pair, or inside a group of
+        // rules those that passed the group's shared step (until its end)
+        uint32_t base = pairs, group_end = 0;
+        bool in_group = false;
         uint32_t pc = 0;
         while (pc < plen) {
             pc = __builtin_amdgcn_readfirstlane(pc);
@@ -351,7 +361,8 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             // every word is needed before the step's own loads: one 16-byte
             // load and one wait, not a dependent load per field
             asm volatile("" ::"s"(raw.x), "s"(raw.y), "s"(raw.z), "s"(raw.w));
-            const uint32_t op = raw.x & 0xFFu, res = (raw.x >> 16) & 0xFFu;
+            uint32_t op = raw.x & 0xFFu;
+            const uint32_t res = (raw.x >> 16) & 0xFFu;
             const uint32_t cp = raw.y & 0xFFFFu;
             const uint64_t param = ((uint64_t)raw.w << 32) | raw.z;
             if (op == OP_CP) {
@@ -363,13 +374,27 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     alive = fwd | bwd;
                 } else {
                     matched |= alive;
-                    alive = pairs & ~matched;
+                    alive = base & ~matched;
                 }
-                if (!__any(alive != 0)) break;   // every pair is matched or absent
+                if (!__any(alive != 0)) {
+                    if (!in_group) break;   // every pair is matched or absent
+                    pc = group_end;         // the group's rules have no pair left
+                    continue;
+                }
+                ++pc;
+                continue;
+            }
+            if (op == OP_ENDGUARD) {
+                base = pairs;
+                in_group = false;
+                alive = pairs & ~matched;
+                if (!__any(alive != 0)) break;
                 ++pc;
                 continue;
             }
             if (!__any(alive != 0)) { pc = cp; continue; }
+            const bool guard = op == OP_GUARD;
+            if (guard) op = (raw.x >> 24) & 0xFFu;   // the shared step's own operation
             if constexpr (kOrd) {
                 if (op >= OP_CONST) {
                     // a predicate that tells t from s: one mask per valuation
@@ -454,67 +479,73 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             }
             const uint32_t before = alive;
             uint32_t work = 0;
-            const bool single = op <= OP_JACF && !__any((alive & (alive - 1u)) != 0u);
+            // Few pairs left per lane (the usual state after a rule's first
+            // filter): each lane evaluates only its own live pairs, one row
+            // per round, reading that row's features with per-lane loads,
+            // instead of the batch's 16 rows.  The arithmetic is the batch
+            // form's, row for row.
+            const bool single = op <= OP_JACF && !__any(__popc(alive) > sparse_max);
             if (single) {
-                // At most one pair left per lane (the usual state after a
-                // rule's first filter): each lane evaluates only its own
-                // pair, reading that row's features with per-lane loads,
-                // instead of the batch's 16 rows.  The arithmetic is the
-                // batch form's, row for row.
-                const uint32_t r = alive != 0u ? (uint32_t)__builtin_ctz(alive) : 0u;
-                const uint64_t pr = pi0 + r;
-                const uint32_t vmask_i = f32[n + pr];
-                bool ok = false;
-                switch (op) {
-                case OP_EQ_INT:
-                case OP_ABSDIFF: {
-                    const int64_t vj = (int64_t)J64(res);
-                    const int64_t d = op == OP_EQ_INT ? 0 : (int64_t)param;
-                    const int64_t lo = vj < INT64_MIN + d ? INT64_MIN : vj - d;
-                    const int64_t hi = vj > INT64_MAX - d ? INT64_MAX : vj + d;
-                    const int64_t vi = (int64_t)f64[res * n + pr];
-                    ok = ((vmask_j & vmask_i) >> res) & 1 && vi >= lo && vi <= hi;
-                    break;
-                }
-                case OP_EQF: {
-                    const uint32_t li = f32[(str32 + res) * n + pr];
-                    const uint64_t ci = f64[(str64 + res) * n + pr];
-                    ok = ((vmask_j & vmask_i) >> (16 + res)) & 1 && li == J32(str32 + res) && ci == J64(str64 + res);
-                    break;
-                }
-                case OP_EDF: {
-                    const int lj = (int)J32(str32 + res);
-                    const uint64_t cj = J64(str64 + res);
-                    const int k = (int)param;
-                    const int li = (int)f32[(str32 + res) * n + pr];
-                    const uint64_t ci = f64[(str64 + res) * n + pr];
-                    const int both = (int)(__popc((uint32_t)ci & (uint32_t)cj) +
-                                           __popc((uint32_t)(ci >> 32) & (uint32_t)(cj >> 32)));
-                    const int t = max((int)__popcll(ci) - k, (int)__popcll(cj) - k);
-                    ok = ((vmask_j & vmask_i) >> (16 + res)) & 1 && both >= t && li >= lj - k && li <= lj + k;
-                    break;
-                }
-                default: {   // OP_JACF: the bound of the batch form, in exact 64-bit arithmetic
-                    const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
-                    if (num == 0) {
-                        ok = ((vmask_j & vmask_i) >> (24 + res)) & 1;
+                uint32_t rem = alive, keep = 0, rounds = 0;
+                while (__any(rem != 0u)) {
+                    ++rounds;
+                    const uint32_t r = rem != 0u ? (uint32_t)__builtin_ctz(rem) : 0u;
+                    const uint64_t pr = pi0 + r;
+                    const uint32_t vmask_i = f32[n + pr];
+                    bool ok = false;
+                    switch (op) {
+                    case OP_EQ_INT:
+                    case OP_ABSDIFF: {
+                        const int64_t vj = (int64_t)J64(res);
+                        const int64_t d = op == OP_EQ_INT ? 0 : (int64_t)param;
+                        const int64_t lo = vj < INT64_MIN + d ? INT64_MIN : vj - d;
+                        const int64_t hi = vj > INT64_MAX - d ? INT64_MAX : vj + d;
+                        const int64_t vi = (int64_t)f64[res * n + pr];
+                        ok = ((vmask_j & vmask_i) >> res) & 1 && vi >= lo && vi <= hi;
                         break;
                     }
-                    const uint32_t gcol = gram64 + P.gram[res].sig_col;
-                    const uint32_t wb = J32(jf32 + res);
-                    const uint32_t wa = f32[(jf32 + res) * n + pr];
-                    uint32_t iub = min(wa >> 16, wb >> 16);
-                    const uint32_t words = P.gram[res].sig_words;
-                    for (uint32_t w = 0; w < words; ++w) {
-                        const uint64_t gi = f64[(gcol + w) * n + pr], gj = J64(gcol + w);
-                        iub += (uint32_t)__popcll(gi & gj);
+                    case OP_EQF: {
+                        const uint32_t li = f32[(str32 + res) * n + pr];
+                        const uint64_t ci = f64[(str64 + res) * n + pr];
+                        ok = ((vmask_j & vmask_i) >> (16 + res)) & 1 && li == J32(str32 + res) && ci == J64(str64 + res);
+                        break;
                     }
-                    ok = (uint64_t)iub * nd >= (uint64_t)num * ((wa & 0xFFFFu) + (wb & 0xFFFFu));
-                    break;
+                    case OP_EDF: {
+                        const int lj = (int)J32(str32 + res);
+                        const uint64_t cj = J64(str64 + res);
+                        const int k = (int)param;
+                        const int li = (int)f32[(str32 + res) * n + pr];
+                        const uint64_t ci = f64[(str64 + res) * n + pr];
+                        const int both = (int)(__popc((uint32_t)ci & (uint32_t)cj) +
+                                               __popc((uint32_t)(ci >> 32) & (uint32_t)(cj >> 32)));
+                        const int t = max((int)__popcll(ci) - k, (int)__popcll(cj) - k);
+                        ok = ((vmask_j & vmask_i) >> (16 + res)) & 1 && both >= t && li >= lj - k && li <= lj + k;
+                        break;
+                    }
+                    default: {   // OP_JACF: the bound of the batch form, in exact 64-bit arithmetic
+                        const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
+                        if (num == 0) {
+                            ok = ((vmask_j & vmask_i) >> (24 + res)) & 1;
+                            break;
+                        }
+                        const uint32_t gcol = gram64 + P.gram[res].sig_col;
+                        const uint32_t wb = J32(jf32 + res);
+                        const uint32_t wa = f32[(jf32 + res) * n + pr];
+                        uint32_t iub = min(wa >> 16, wb >> 16);
+                        const uint32_t words = P.gram[res].sig_words;
+                        for (uint32_t w = 0; w < words; ++w) {
+                            const uint64_t gi = f64[(gcol + w) * n + pr], gj = J64(gcol + w);
+                            iub += (uint32_t)__popcll(gi & gj);
+                        }
+                        ok = (uint64_t)iub * nd >= (uint64_t)num * ((wa & 0xFFFFu) + (wb & 0xFFFFu));
+                        break;
+                    }
+                    }
+                    if (rem != 0u && ok) keep |= 1u << r;
+                    rem &= rem - 1u;
                 }
-                }
-                alive = ok ? alive : 0u;
-                work = 1;
+                alive = keep;
+                work = rounds;
             } else switch (op) {
             case OP_EQ_INT:
             case OP_ABSDIFF: {
@@ -732,6 +763,11 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 fwd &= alive;
                 bwd &= alive;
             }
+            if (guard) {   // the group's rules start from the pairs that passed
+                base = alive;
+                in_group = true;
+                group_end = cp;
+            }
             if constexpr (kCount) {
                 // batches: this step ran once for the wave's 16-row batch
                 uint32_t ev = 0, ps = 0;
@@ -740,17 +776,21 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     ps += __popcll(__ballot((alive >> r) & 1));
                 }
                 // filters: `waves` counts steps in the 16-row form, `work`
-                // steps in the one-pair-per-lane form
+                // steps in the per-lane form
                 const uint32_t waves = op <= OP_JACF && single ? 0u : 1u;
                 uint32_t w = op <= OP_JACF ? 0u : work;
                 for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
-                if (op <= OP_JACF) w = single ? 1u : 0u;
+                if (op <= OP_JACF) w = single ? work : 0u;
                 if (lane == 0) {
                     atomicAdd(&s_cnt[op * 4 + 0], (unsigned long long)waves);
                     atomicAdd(&s_cnt[op * 4 + 1], (unsigned long long)ev);
                     atomicAdd(&s_cnt[op * 4 + 2], (unsigned long long)ps);
                     atomicAdd(&s_cnt[op * 4 + 3], (unsigned long long)w);
                 }
+            }
+            if (guard && !__any(alive != 0)) {   // no pair passed the shared step: past the group
+                pc = cp;
+                continue;
             }
             ++pc;
         }
@@ -1191,13 +1231,20 @@ __global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
 
 // ------------------------------------------------------------ plan choice
 
-// Probability that some pair of a batch of `batch` pairs survives a step
-// sequence that each pair survives with probability p.  The plan choice
-// only ranks alternatives, so single precision and fast intrinsics do.
-__device__ inline float batch_any(float p, float batch) {
-    if (p <= 0.f) return 0.f;
-    if (p >= 1.f) return 1.f;
-    return 1.f - __expf(batch * __logf(1.f - p));
+// The shape of a block's wave batches: rows per batch, lanes, and the
+// per-lane form's threshold (a filter step runs lane by lane, one live row
+// per round, when no lane has more live rows than that).
+struct BatchShape {
+    float rows, lanes;
+    int sparse;
+};
+
+__device__ inline BatchShape batch_shape(uint32_t nb) {
+    BatchShape b;
+    b.rows = (float)min(nb, (uint32_t)kRows);
+    b.lanes = (float)min(nb, (uint32_t)kTile);
+    b.sparse = min(kSparseRows, (int)min(nb, (uint32_t)kRows) >> 1);
+    return b;
 }
 
 // First-stage step cost per row, in the library's lane-op units.
@@ -1210,7 +1257,39 @@ __device__ inline float first_cost(uint8_t op) {
     }
 }
 
-__device__ inline bool verifies(uint8_t op) { return op == OP_EQ_STR || op == OP_ED || op == OP_JAC; }
+// Cost of one round of the per-lane form against one row of the batch form
+// (per-lane loads instead of scalar ones, and the round's control).
+constexpr float kSparseRound = 2.f;
+
+// Expected cost of a first-stage step of per-row cost c reached with
+// per-pair survival probability s (each pair independently): with X the
+// live rows of a lane, X ~ Binomial(rows, s), the batch form costs c x rows
+// when some lane has more than `sparse` live rows; otherwise the per-lane
+// form takes one round per live row of the fullest lane, so the expected
+// cost is c (rows (1 - A_T) + kSparseRound sum_{m < T} (A_T - A_m)) with
+// A_m = P(X <= m)^lanes.  The plan choice only ranks alternatives, so
+// single precision and fast intrinsics do.
+__device__ inline float step_cost(float c, float s, const BatchShape& b) {
+    if (s <= 0.f) return 0.f;
+    const int T = b.sparse;
+    float F[kSparseRows + 1];
+    if (s >= 1.f) {
+        for (int m = 0; m <= T; ++m) F[m] = (float)m >= b.rows ? 1.f : 0.f;
+    } else {
+        const float q = 1.f - s;
+        float pm = __expf(b.rows * __logf(q));   // P(X = 0)
+        F[0] = pm;
+        for (int m = 1; m <= T; ++m) {
+            pm = (float)m <= b.rows ? pm * (b.rows - (float)(m - 1)) / (float)m * (s / q) : 0.f;
+            F[m] = fminf(1.f, F[m - 1] + pm);
+        }
+    }
+    auto A = [&](int m) { return F[m] <= 0.f ? 0.f : F[m] >= 1.f ? 1.f : __expf(b.lanes * __logf(F[m])); };
+    const float at = A(T);
+    float rounds = 0.f;
+    for (int m = 0; m < T; ++m) rounds += at - A(m);
+    return c * (b.rows * (1.f - at) + kSparseRound * rounds);
+}
 
 struct BlockEst {
     const float* y;
@@ -1221,16 +1300,15 @@ struct BlockEst {
 };
 
 // Expected first-stage cost of a wave batch running a rule's steps in
-// order `ord` (indices into the rule's steps): a step runs while some pair
-// of the batch survives every step before it.
+// order `ord` (indices into the rule's steps).
 __device__ inline float stage_cost(const PlanChoiceParams& C, uint32_t r, const uint8_t* ord, int len,
-                                   const BlockEst& e, float batch) {
-    float total = 0.f, surv = 1.f, alive = 1.f;
+                                   const BlockEst& e, const BatchShape& b) {
+    // a rule under a shared guard step starts from the pairs that passed it
+    float total = 0.f, surv = C.rule_guard[r] == 0xFF ? 1.f : e.pass(C.rule_guard[r]);
     for (int k = 0; k < len; ++k) {
         const uint32_t sx = C.rule_spec[r][ord[k]];
-        total += alive * first_cost(C.spec_kind[sx]);
+        total += step_cost(first_cost(C.spec_kind[sx]), surv, b);
         surv *= e.pass(sx);
-        alive = batch_any(surv, batch);
     }
     return total;
 }
@@ -1241,89 +1319,87 @@ __device__ inline uint64_t pack_order(const uint8_t* ord, int len) {
     return code;
 }
 
-// One thread per block: for every rule, the first-stage order by
-// cost / (1 - q) ascending (q = the probability that some pair of the wave
-// batch passes the step) and the exact checks by predicted cycles
-// ascending, each taken only when the model expects it at least 2% cheaper
-// than the heuristic order.  Writes the block's plan slot.
-__device__ inline void rule_choice(const PlanChoiceParams& C, uint32_t r, const BlockEst& e, float batch,
-                                   uint8_t* fo, uint8_t* vo, int* nv) {
+// Per block and rule: the first-stage order.  Steps after the first run
+// mostly in the per-lane form, whose cost follows the pairs still alive, so
+// they are ranked by cost / (1 - pass rate) ascending (the order that
+// minimises the expected cost of independent filters paid per pair); every
+// step is tried as the first one (the batch form's cost), and the cheapest
+// order under stage_cost is taken when the model expects it at least 2%
+// cheaper than the heuristic order.
+__device__ inline void rule_choice(const PlanChoiceParams& C, uint32_t r, const BlockEst& e, const BatchShape& b,
+                                   uint8_t* fo) {
     const int len = C.rule_len[r];
-    uint8_t id[kMaxRuleSteps], lo[kMaxRuleSteps];
+    uint8_t id[kMaxRuleSteps], lo[kMaxRuleSteps], cand[kMaxRuleSteps];
     float rank[kMaxRuleSteps];
     for (int k = 0; k < len; ++k) {
         id[k] = (uint8_t)k;
         lo[k] = (uint8_t)k;
         const uint32_t sx = C.rule_spec[r][k];
-        rank[k] = first_cost(C.spec_kind[sx]) / fmaxf(1e-20f, 1.f - batch_any(e.pass(sx), batch));
+        rank[k] = first_cost(C.spec_kind[sx]) / fmaxf(1e-20f, 1.f - e.pass(sx));
     }
     for (int a = 1; a < len; ++a)   // stable insertion sort by rank
         for (int k = a; k > 0 && rank[lo[k]] < rank[lo[k - 1]]; --k) {
             const uint8_t t = lo[k]; lo[k] = lo[k - 1]; lo[k - 1] = t;
         }
-    const bool take = stage_cost(C, r, lo, len, e, batch) < 0.98f * stage_cost(C, r, id, len, e, batch);
-    for (int k = 0; k < len; ++k) fo[k] = take ? lo[k] : id[k];
-    // exact checks in the heuristic's order, whatever the first-stage
+    float best = 3.0e38f;
+    uint8_t best_first = lo[0];
+    for (int f = 0; f < len; ++f) {   // candidate first step lo[f], the rest in rank order
+        cand[0] = lo[f];
+        for (int k = 0, o = 1; k < len; ++k)
+            if (k != f) cand[o++] = lo[k];
+        const float cost = stage_cost(C, r, cand, len, e, b);
+        if (cost < best) {
+            best = cost;
+            best_first = lo[f];
+        }
+    }
+    cand[0] = best_first;
+    for (int k = 0, o = 1; k < len; ++k)
+        if (lo[k] != best_first) cand[o++] = lo[k];
+    const bool take = best < 0.98f * stage_cost(C, r, id, len, e, b);
+    for (int k = 0; k < len; ++k) fo[k] = take ? cand[k] : id[k];
+    // the exact checks keep the heuristic's order, whatever the first-stage
     // order: the model predicts their cost but not how many pairs they
     // reject, and a cost-only order can put a check that passes nearly
     // every pair ahead of a selective one
-    int m = 0;
-    for (int k = 0; k < len; ++k)
-        if (verifies(C.spec_kind[C.rule_spec[r][id[k]]])) vo[m++] = id[k];
-    *nv = m;
 }
 
-// The first block to claim a slot writes its plan: every rule segment of the
-// heuristic plan holds [first-stage steps][exact checks][checkpoint] in step
-// order; the segment is rewritten in the chosen orders.
-__device__ inline void write_plan(const PlanChoiceParams& C, uint32_t x, const BlockEst& e, float batch) {
+// The first block to claim a slot writes its plan: the heuristic plan with
+// each rule's first-stage steps (at the start of its segment) in the chosen
+// order; exact checks, checkpoints and guard steps keep their places.
+__device__ inline void write_plan(const PlanChoiceParams& C, uint32_t x, const BlockEst& e, const BatchShape& batch) {
     Instr* dst = C.code + (size_t)x * C.plan_len;
     const Instr* base = C.code;
     for (uint32_t i = 0; i < C.plan_len; ++i) dst[i] = base[i];
-    uint32_t seg = 0;
     for (uint32_t r = 0; r < C.n_rules; ++r) {
-        uint8_t fo[kMaxRuleSteps], vo[kMaxRuleSteps];
-        int nv = 0;
-        rule_choice(C, r, e, batch, fo, vo, &nv);
-        const int len = C.rule_len[r];
-        int vpos[kMaxRuleSteps];
-        int m = 0;
-        for (int k = 0; k < len; ++k) vpos[k] = verifies(C.spec_kind[C.rule_spec[r][k]]) ? m++ : -1;
-        for (int k = 0; k < len; ++k) dst[seg + k] = base[seg + fo[k]];
-        for (int k = 0; k < nv; ++k) dst[seg + len + k] = base[seg + len + vpos[vo[k]]];
-        seg += (uint32_t)(len + m + 1);
+        uint8_t fo[kMaxRuleSteps];
+        rule_choice(C, r, e, batch, fo);
+        const uint32_t seg = C.rule_seg[r];
+        for (int k = 0; k < (int)C.rule_len[r]; ++k) dst[seg + k] = base[seg + fo[k]];
     }
 }
 
-// One thread per block: for every rule, the first-stage order by
-// cost / (1 - q) ascending (q = the probability that some pair of the wave
-// batch passes the step) and the exact checks by predicted cycles
-// ascending, each taken only when the model expects it at least 2% cheaper
-// than the heuristic order.  Writes the block's plan slot.
+// One thread per block: for every rule, the first-stage order of
+// rule_choice (exact checks keep the heuristic's order).  Writes the
+// block's plan slot.
 __global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     bool learned = false, overflow = false, wrote = false;
     if (g < C.n_blocks) {
         const uint32_t b = C.blocks[g];
-        const uint32_t nb = C.blk_size[b];
-        const float batch = (float)min(nb, (uint32_t)kRows) * (float)min(nb, (uint32_t)kTile);
+        const BatchShape batch = batch_shape(C.blk_size[b]);
         BlockEst e{C.y + (size_t)g * C.n_spec * 2};
         uint64_t h = 0x6A09E667F3BCC909ull;
         {
             for (uint32_t r = 0; r < C.n_rules; ++r) {
-                uint8_t fo[kMaxRuleSteps], vo[kMaxRuleSteps];
-                int nv = 0;
-                rule_choice(C, r, e, batch, fo, vo, &nv);
+                uint8_t fo[kMaxRuleSteps];
+                rule_choice(C, r, e, batch, fo);
                 const int len = C.rule_len[r];
-                bool same_f = true, same_v = true;
-                for (int k = 0; k < len; ++k) same_f &= fo[k] == k;
-                int m = 0;
-                for (int k = 0; k < len; ++k)
-                    if (verifies(C.spec_kind[C.rule_spec[r][fo[k]]])) same_v &= vo[m++] == fo[k];
-                if (!(same_f && same_v)) {
+                bool same = true;
+                for (int k = 0; k < len; ++k) same &= fo[k] == k;
+                if (!same) {
                     learned = true;
                     h = mix64(h ^ ((uint64_t)(r + 1) << 56) ^ pack_order(fo, len));
-                    h = mix64(h ^ pack_order(vo, nv));
                 }
             }
         }

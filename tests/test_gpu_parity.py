@@ -344,8 +344,8 @@ def test_work_counters_consistent(hb, ctx):
     assert w["matched"] == len(got)
     assert w["lane_ops"] > 0
     for k, (name, c) in enumerate(w["per_op"].items()):
-        # filter kinds (the first five): `work` counts steps in the
-        # one-pair-per-lane form, at most 64 pairs each
+        # filter kinds (the first five): `work` counts rounds of the
+        # per-lane form, at most 64 pairs each
         single = c["work"] if k < 5 else 0
         assert c["passed"] <= c["lanes"] <= 16 * 64 * c["waves"] + 64 * single, name
     # the cached result is untouched by the instrumented pass
