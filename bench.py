@@ -313,6 +313,8 @@ def main():
     ap.add_argument("--workload", default="learned_10m",
                     choices=["plain_1m", "learned_10m", "long_titles_5m", "batched_64"])
     ap.add_argument("--n", type=int, default=None, help="tuples (scales the workload's recipe down)")
+    ap.add_argument("--rows", type=int, default=64, choices=[16, 32, 64],
+                    help="i-rows per wave batch of hb_match (hb_set_rows_per_wave)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle seconds per thread setting")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -347,6 +349,7 @@ def main():
         del a, b
     cols = device_columns(rel, torch)
     ctx = hb.hb_create(0, allocator="torch")
+    hb.hb_set_rows_per_wave(ctx, args.rows)
     torch.cuda.synchronize()
 
     learned = None
@@ -393,10 +396,13 @@ def main():
             for p in (plans if k % 2 == 0 else plans[::-1]):
                 hb.hb_profile_reset(ctx)
                 torch.cuda.synchronize()
+                a0 = torch.cuda.memory_stats().get("num_device_alloc", 0)
                 t0 = time.perf_counter()
                 res[p] = step(p, outs[p], legs[p]["phase"], rules_)
                 torch.cuda.synchronize()
                 legs[p]["s"] += time.perf_counter() - t0
+                legs[p]["device_allocs"] = legs[p].get("device_allocs", 0) + \
+                    torch.cuda.memory_stats().get("num_device_alloc", 0) - a0
                 for name in PROFILE_NAMES:
                     ms, launches = hb.hb_profile_query(ctx, name)
                     legs[p]["prof"][name][0] += ms
@@ -413,13 +419,17 @@ def main():
             L["match_ms_launch"] = m[0] / max(1, m[1])
             L["match_ms_step"] = m[0] / args.steps
             log(f"[bench] {p}: host wall per step by call (ms): "
-                + ", ".join(f"{k} {v * 1000.0 / args.steps:.2f}" for k, v in L["phase"].items()))
+                + ", ".join(f"{k} {v * 1000.0 / args.steps:.2f}" for k, v in L["phase"].items())
+                + f"; device allocations in the timed steps: {L.get('device_allocs', 0)}")
+            log(f"[bench] {p}: kernel ms per step: "
+                + ", ".join(f"{k} {v[0] / args.steps:.2f}" for k, v in L["prof"].items() if v[1]))
             log(f"[bench] {p}: {args.steps} steps, {L['ms_step']:.2f} ms/step, {L['value']:.3e} pairs/s, "
                 f"match kernel {L['match_ms_step']:.3f} ms/step ({m[1] // args.steps} launches per step)")
             if p == "learned":
                 st = hb.hb_last_match_stats(ctx)
                 log(f"[bench] learned plan: {st['learned_blocks']} blocks on {st['learned_plans']} learned plans, "
-                    f"{st['fallback_blocks']} on the heuristic plan")
+                    f"{st['fallback_blocks']} on the heuristic plan; predicted cost of the listed blocks "
+                    f"{st['predicted_heuristic']:.4g} (heuristic) -> {st['predicted_chosen']:.4g}")
         return legs
 
     plans = [args.plan]
@@ -437,6 +447,7 @@ def main():
         same = H["n_match"] == n_match and bool(torch.equal(outs["heuristic"][:n_match], out[:n_match]))
         compare = {"plan": "heuristic", "value": H["value"], "ms_per_step": H["ms_step"],
                    "match_kernel_ms_per_step": H["match_ms_step"], "bit_exact": same,
+                   "kernels_ms_per_step": {k: v[0] / args.steps for k, v in H["prof"].items()},
                    "order": "alternating per step (ABBA...)",
                    "step_ratio": value / H["value"],
                    "match_kernel_ratio": H["match_ms_step"] / max(1e-9, L["match_ms_step"])}
@@ -572,7 +583,7 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": describe(args.workload, rel.n_rows, len(rules), args.plan), "plan": args.plan,
-                   "candidate_pairs": n_cand, "matched_pairs": n_match},
+                   "candidate_pairs": n_cand, "matched_pairs": n_match, "rows_per_wave": args.rows},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
         "streaming": streaming,
         "host_ms_per_step": {k: v * 1000.0 / args.steps for k, v in L["phase"].items()},

@@ -259,6 +259,14 @@ hb_status hb_match(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t pl
 hb_status hb_match_noalloc(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan,
                            uint64_t* out_pairs, uint64_t capacity, uint64_t* n_pairs);
 
+/* Launch shape of hb_match and hb_match_noalloc on this context: the i-rows
+ * a wave evaluates per batch against its 64 j-lanes, 16 (four batches per
+ * 64 x 64 tile), 32 (two) or 64 (one; the default).  Larger batches pay each
+ * plan step's fixed cost once for more pairs; the result is the same.  Ordered
+ * rule sets and batches keep 16; hb_match_work follows the setting.  Other
+ * values: HB_ERR_INVALID_ARG. */
+hb_status hb_set_rows_per_wave(hb_ctx* ctx, uint32_t rows);
+
 /* ------------------------------------------------------------ introspection */
 
 /* Per distinct predicate of a rule set (in first-appearance order): its
@@ -314,9 +322,10 @@ hb_status hb_profile_reset(hb_ctx* ctx);
  * for its batch of 16 rows x 64 lanes, `lanes` = the pairs that evaluated
  * it, `passed` = the pairs for which it held, `work` = its work units (edit
  * distance: text bytes x 32-bit pattern words run; Jaccard: merged list
- * elements; string equality: bytes compared; kinds 0-4: the times a wave
- * ran it in the one-pair-per-lane form, when at most one pair per lane was
- * left, which `waves` does not count).  `pairs` is
+ * elements; string equality: bytes compared; kinds 0-4: the rounds a wave
+ * ran it in the per-lane form, one live row per lane and round, taken when
+ * no lane had more than four live rows; `waves` does not count those
+ * steps).  A wave batch holds the context's rows per wave (16, 32 or 64).  `pairs` is
  * the number of candidate pairs evaluated.  `lane_ops` is the algorithmic
  * int32 lane-operations of the pairs evaluated: value equality 2, |a-b| <= d
  * 4, each exact filter 4, string equality 2 + 1 per byte, edit distance 17
@@ -424,6 +433,13 @@ typedef struct {
     uint64_t learned_blocks;   /* HB_PLAN_LEARNED: blocks running a learned plan */
     uint64_t fallback_blocks;  /* HB_PLAN_LEARNED: blocks kept on the heuristic plan */
     uint64_t learned_plans;    /* HB_PLAN_LEARNED: distinct per-block plans written */
+    /* HB_PLAN_LEARNED: the cost model's predicted cost (abstract units) of the
+     * blocks that may take a per-block plan, under the heuristic plan and
+     * under the plans it chose, summed over key partitions.  A partition
+     * whose predicted saving is under 3% runs the heuristic plan throughout
+     * (its blocks count as fallback). */
+    double predicted_heuristic;
+    double predicted_chosen;
 } hb_match_stats;
 hb_status hb_last_match_stats(hb_ctx* ctx, hb_match_stats* out);
 

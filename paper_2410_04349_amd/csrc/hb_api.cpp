@@ -593,7 +593,7 @@ static Partition& key_partition(Ctx* c, Relation& rel, uint32_t attr) {
         uint64_t h[2];
         uint32_t hb2[2] = {0, 0};
         if (P.n_blocks) {
-            HB_HIP(launch_size_flags(P.blk_size.as<uint32_t>(), P.n_blocks, kRows, bflags.as<uint32_t>(), c->stream));
+            HB_HIP(launch_size_flags(P.blk_size.as<uint32_t>(), P.n_blocks, kTile, bflags.as<uint32_t>(), c->stream));
             HB_HIP(launch_exclusive_scan_u32(bflags.as<uint32_t>(), bdest.as<uint32_t>(), P.n_blocks,
                                              btmp.as<uint32_t>(), c->stream));
             HB_HIP(launch_compact_rows(bflags.as<uint32_t>(), bdest.as<uint32_t>(), P.n_blocks, P.big.as<uint32_t>(),
@@ -976,6 +976,14 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
         fail(HB_ERR_LIMIT, "the rule set's per-wave working set (" + std::to_string(m.lds_bytes) +
                                " bytes of LDS) exceeds the device limit");
 
+    m.rows = c->rows_per_wave;
+    {   // no validity bitmap on any attribute a step reads (keys included)
+        bool all = true;
+        for (uint32_t a : R.int_attr) all = all && rel.cols[a].valid.size() == 0;
+        for (uint32_t a : R.str_attr) all = all && rel.cols[a].valid.size() == 0;
+        for (const auto& gk : R.gram_key) all = all && rel.cols[gk.first].valid.size() == 0;
+        m.all_valid = all ? 1u : 0u;
+    }
     m.cols = rel.d_cols.as<ColDev>();
     m.feat.f64 = kp.f64.as<uint64_t>();
     m.feat.f32 = kp.f32.as<uint32_t>();
@@ -1027,7 +1035,8 @@ static uint32_t next_pow2(uint32_t v) {
 // round trip: block features, cost-model inference (per block and
 // predicate: the first plan step's pass rate and the exact check's cycles)
 // and the plan-choice kernel, which writes each distinct choice's plan.
-// Blocks smaller than one wave batch's rows keep the heuristic plan.
+// Blocks smaller than one 64 x 64 tile keep the heuristic plan (their
+// pairs are few; features and choices would cost more than they save).
 static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& kp, const KeyRes& R,
                              const std::vector<PathRule>& heuristic, uint64_t* n_fallback) {
     if (!c->model.ready) fail(HB_ERR_STATE, "the learned plan needs a cost model (hb_costmodel_train or _set_params)");
@@ -1083,6 +1092,7 @@ static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyP
     C.n_rules = n_rules;
     C.n_slots = std::min<uint32_t>(kPlanSlots, next_pow2(std::max<uint32_t>(2 * nl, 16)));
     C.plan_len = kp.mp.plan_len;
+    C.rows = kp.mp.rows == 64 ? 64u : kp.mp.rows == 32 ? 32u : 16u;
     for (uint32_t x = 0; x < ns; ++x) C.spec_kind[x] = (uint8_t)R.specs[x].op;
     DevBuf keys(c, sizeof(unsigned long long) * C.n_slots);
     zero(c, keys.get(), keys.size());
@@ -1090,7 +1100,23 @@ static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyP
     C.code = kp.dev_code.as<Instr>();
     C.blk_slot = kp.blk_slot.as<uint32_t>();
     C.stats = kp.choice_stats.as<unsigned long long>();
+    DevBuf cost(c, 2 * sizeof(float));
+    zero(c, cost.get(), cost.size());
+    C.cost = cost.as<float>();
     c->timed("plan_choice", [&] { return launch_plan_choice(C, c->stream); });
+    // per-block plans only pay when the model expects them to save at least
+    // 3% of the partition's cost: each distinct plan is fetched through the
+    // scalar cache, so near-equal plans run slower than one shared plan;
+    // otherwise every block runs the heuristic plan (slot 0)
+    float pc[2];
+    HB_HIP(hipMemcpyAsync(pc, cost.get(), sizeof(pc), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    kp.predicted[0] = pc[0];
+    kp.predicted[1] = pc[1];
+    if (!(pc[1] < 0.97f * pc[0])) {
+        kp.mp.blk_slot = nullptr;
+        kp.discarded = true;
+    }
 }
 
 static void log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t samples, uint64_t seed, float* features,
@@ -1242,6 +1268,7 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
     std::vector<KeyPlan> kps;
     size_t total_code = 0;
     uint64_t n_learned = 0, n_fallback = 0, n_plans = 0;
+    double pred_h = 0.0, pred_c = 0.0;
     for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
         if (rel.parts.at(rs.keys[ka]).n_tiles == 0) continue;
         KeyPlan kp;
@@ -1286,6 +1313,12 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
         if (attempt == 0)
             for (KeyPlan& kp : kps) {
                 if (!kp.own_code) continue;
+                pred_h += kp.predicted[0];
+                pred_c += kp.predicted[1];
+                if (kp.discarded) {
+                    n_fallback += kp.mp.n_blocks;
+                    continue;
+                }
                 unsigned long long st[3];
                 HB_HIP(hipMemcpyAsync(st, kp.choice_stats.get(), sizeof(st), hipMemcpyDeviceToHost, c->stream));
                 c->sync();
@@ -1317,7 +1350,7 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
             // cheap steps run for every lane of every row of the batch, or
             // for every lane once per round of the per-lane form; exact ones
             // per pair
-            bops += op <= OP_JACF ? kIssBase[op] * ((double)ws->waves[op] * kRows + (double)ws->work[op]) * 64
+            bops += op <= OP_JACF ? kIssBase[op] * ((double)ws->waves[op] * c->rows_per_wave + (double)ws->work[op]) * 64
                                   : kIssBase[op] * ws->lanes[op] + kIssUnit[op] * ws->work[op];
         }
         ws->lane_ops = ops;
@@ -1338,6 +1371,8 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
     c->last.learned_blocks = n_learned;
     c->last.fallback_blocks = n_fallback;
     c->last.learned_plans = n_plans;
+    c->last.predicted_heuristic = pred_h;
+    c->last.predicted_chosen = pred_c;
 }
 
 static void match_work(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, hb_work_stats* ws) {
@@ -1551,6 +1586,14 @@ hb_status hb_match(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t pl
 hb_status hb_match_noalloc(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, uint64_t* out_pairs,
                            uint64_t capacity, uint64_t* n_pairs) {
     return guard(ctx, [&](Ctx* c) { hb::match_noalloc(c, rel_id, ruleset_id, plan, out_pairs, capacity, n_pairs); });
+}
+
+hb_status hb_set_rows_per_wave(hb_ctx* ctx, uint32_t rows) {
+    return guard(ctx, [&](Ctx* c) {
+        if (rows != 16 && rows != 32 && rows != 64) hb::fail(HB_ERR_INVALID_ARG, "rows per wave batch must be 16, 32 or 64");
+        c->rows_per_wave = rows;
+        for (auto& it : c->rulesets) it.second->has_result = false;   // a later hb_match evaluates again
+    });
 }
 
 hb_status hb_match_work(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, hb_work_stats* out) {

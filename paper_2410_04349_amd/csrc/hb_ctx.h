@@ -96,7 +96,7 @@ struct Partition {
     uint64_t n_tiles = 0, pairs = 0;
     DevBuf perm, blk_start, blk_size, tile_prefix;
     DevBuf tile_blk;      // block of each tile
-    DevBuf big;           // blocks of >= kRows tuples (the ones with per-block plans)
+    DevBuf big;           // blocks of >= kTile tuples (the ones with per-block plans)
     uint32_t n_big = 0;
 };
 
@@ -178,6 +178,7 @@ struct Ctx {
     std::vector<Pending> pending;
     hb_match_stats last{};
     uint32_t lds_limit = 0;
+    uint32_t rows_per_wave = 64;   // i-rows per wave batch of hb_match's launches (16, 32 or 64)
     CostModel model;
     std::map<uint32_t, std::shared_ptr<Batch>> batches;
     // the last autotuned batch launch form, reused by batches created

@@ -154,6 +154,12 @@ struct MatchParams {
     // plan + blk_slot[b] * plan_len; blk_slot == nullptr: one plan for every
     // block
     const uint32_t* blk_slot;
+    // i-rows per wave batch of the plain launch: 16 (four batches per tile),
+    // 32 (two) or 64 (one); ordered rule sets and the batch kernels use 16
+    uint32_t rows;
+    // 1: no attribute the plan reads has a missing value (the validity mask
+    // words are not read)
+    uint32_t all_valid;
 };
 
 // Gather of the block-major feature columns: grid.y = 1 + n_int + n_str +
@@ -296,7 +302,10 @@ hipError_t launch_log_samples(const LearnParams& p, hipStream_t s);
 // the list and when the table is full.
 constexpr int kMaxPlanRules = 64;
 constexpr int kMaxRuleSteps = 10;
-constexpr uint32_t kPlanSlots = 4096;   // power of two
+// Distinct plans of a partition (power of two): a wave fetches its plan's
+// steps through the scalar cache, and many distinct copies of a long plan
+// cost more in fetch misses than their orders save
+constexpr uint32_t kPlanSlots = 256;
 struct PlanChoiceParams {
     const float* y;                   // [n_blocks x n_spec x 2] model outputs, in list order
     const uint32_t* blocks;           // the listed blocks (the rest keep slot 0)
@@ -305,6 +314,7 @@ struct PlanChoiceParams {
     uint32_t n_rules;                 // rules of the partition's plan, in heuristic order
     uint32_t n_slots;                 // table size (power of two, <= kPlanSlots)
     uint32_t plan_len;                // instructions of one plan
+    uint32_t rows;                    // i-rows per wave batch of the launch (16, 32 or 64)
     uint8_t rule_len[kMaxPlanRules];  // first-stage steps per rule (a shared guard step excluded)
     uint16_t rule_seg[kMaxPlanRules]; // first instruction of each rule's segment
     uint8_t rule_guard[kMaxPlanRules];   // spec index of the rule's shared guard step, 0xFF: none
@@ -314,6 +324,7 @@ struct PlanChoiceParams {
     Instr* code;                      // [n_slots x plan_len]; slot 0 holds the heuristic plan
     uint32_t* blk_slot;               // [n_blocks] out
     unsigned long long* stats;        // [3] blocks with a learned plan, blocks over capacity, plans written
+    float* cost;                      // [2] predicted cost of the listed blocks: heuristic plan, chosen plans
 };
 hipError_t launch_plan_choice(const PlanChoiceParams& p, hipStream_t s);
 

@@ -41,6 +41,8 @@ struct KeyPlan {
     // learned plans: per-slot plans on the device, the block -> slot map and
     // the choice kernel's counters (read after matching)
     bool own_code = false;
+    float predicted[2] = {0.f, 0.f};   // model cost of the listed blocks: heuristic plan, chosen plans
+    bool discarded = false;   // the per-block plans were not worth their fetch cost: every block runs slot 0
     DevBuf dev_code, blk_slot, choice_stats;
 };
 

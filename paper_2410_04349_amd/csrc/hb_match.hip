@@ -31,6 +31,8 @@
 // pattern-match table built once per row in the wave's LDS), 32-bit words
 // for patterns <= 32 bytes, 64-bit words with carry chains up to 256 bytes.
 // Jaccard: merge intersection of the sorted distinct q-gram codes.
+#include <type_traits>
+
 #include "hb_internal.h"
 
 namespace hb {
@@ -242,13 +244,49 @@ __device__ __forceinline__ T opaque(T v) {
     return v;
 }
 
-// Bit r (r < 16): bit `bit` of the validity word of position p0 + r.  All
+// Bit r (r < kR): bit `bit` of the validity word of position p0 + r.  All
 // operands are wave-uniform, so this runs on the scalar unit.
-__device__ __forceinline__ uint32_t row_bits(const HB_GLOBAL uint32_t* __restrict__ vmask, uint64_t p0, uint32_t bit) {
-    uint32_t m = 0;
+// Row mask of a batch of kR rows (bit r: row r): 32 bits up to 32 rows,
+// 64 beyond.
+template <int kR>
+using RowMask = typename std::conditional<(kR > 32), uint64_t, uint32_t>::type;
+
+template <typename M>
+__device__ __forceinline__ uint32_t popc_rows(M m) {
+    if constexpr (sizeof(M) == 8) return (uint32_t)__popcll(m); else return (uint32_t)__popc(m);
+}
+template <typename M>
+__device__ __forceinline__ uint32_t ctz_rows(M m) {
+    if constexpr (sizeof(M) == 8) return (uint32_t)__builtin_ctzll(m); else return (uint32_t)__builtin_ctz(m);
+}
+
+// Builds a lane's row mask one row at a time, from the last row to the
+// first, with push_bit (one add-with-carry per row); 64-row masks fill two
+// 32-bit halves.  Row indices are compile-time in the unrolled loops, so
+// the choice of half costs nothing.
+template <int kR>
+struct RowPush {
+    uint32_t lo = 0, hi = 0;
+    __device__ __forceinline__ void push(int r, uint64_t lanes) {
+        if (kR > 32 && r >= 32) hi = push_bit(hi, lanes);
+        else lo = push_bit(lo, lanes);
+    }
+    __device__ __forceinline__ RowMask<kR> get() const {
+        if constexpr (kR > 32) return ((uint64_t)hi << 32) | lo; else return lo;
+    }
+};
+
+template <int kR>
+__device__ __forceinline__ RowMask<kR> row_bits(const HB_GLOBAL uint32_t* __restrict__ vmask, uint64_t p0,
+                                                 uint32_t bit) {
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
-    for (int r = kRows - 1; r >= 0; --r) m = m + m + ((vmask[p0 + r] >> bit) & 1u);
-    return m;
+    for (int r = kR - 1; r >= 0; --r) {
+        const uint32_t v = (vmask[p0 + r] >> bit) & 1u;
+        if (kR > 32 && r >= 32) hi = hi + hi + v;
+        else lo = lo + lo + v;
+    }
+    if constexpr (kR > 32) return ((uint64_t)hi << 32) | lo; else return lo;
 }
 
 // tile index -> (block, ti, tj), tiles of a block enumerated column-major
@@ -275,11 +313,13 @@ __device__ inline void decode_tile(const MatchParams& P, uint64_t t, uint32_t* b
 // ("backward"), each with its own alive and matched masks; symmetric steps
 // run once for the union and narrow both, and each valuation that reaches
 // a checkpoint emits its ordered pair.
-template <bool kCount, bool kLongEd = false, bool kOrd = false>
+template <bool kCount, bool kLongEd = false, bool kOrd = false, int kR = kRows>
 __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL Instr* __restrict__ plan,
                                            const HB_GLOBAL uint64_t* __restrict__ f64,
                                            const HB_GLOBAL uint32_t* __restrict__ f32, uint64_t t, uint8_t* lds,
                                            int batch) {
+    using Mask = RowMask<kR>;
+    constexpr Mask kAll = ~(Mask)0;
     const int lane = threadIdx.x & 63;
     const int wave = batch;
     uint32_t b, ti, tj;
@@ -306,13 +346,18 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
     __syncthreads();
 
     // this wave's rows: r0 .. r0 + nr - 1 of the i-tile (16 consecutive rows)
-    const uint32_t r0 = (uint32_t)wave * kRows;
-    const int nr = (int)min((uint32_t)kRows, ni > r0 ? ni - r0 : 0u);
+    const uint32_t r0 = (uint32_t)wave * kR;
+    const int nr = (int)min((uint32_t)kR, ni > r0 ? ni - r0 : 0u);
     if (!kCount && nr <= 0) return;
     if (nr > 0) {
         const uint64_t pi0 = (uint64_t)bstart + i0 + r0;   // position of row 0
         const uint32_t row_j = J32(0);
-        const uint32_t vmask_j = J32(1);
+        // validity: every row valid on every attribute the plan reads when
+        // the relation has no missing values there (the mask words are then
+        // not read)
+        const bool all_valid = P.all_valid != 0;
+        const uint32_t vmask_j = all_valid ? ~0u : J32(1);
+        auto rvalid = [&](uint32_t bit) -> Mask { return all_valid ? kAll : row_bits<kR>(f32 + n, pi0, bit); };
         uint8_t* wbase = lds;
         uint8_t* peq = wbase + P.lds_wave_peq;
         const HB_GLOBAL Instr* __restrict__ pl = plan;
@@ -322,36 +367,42 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
         // bit r of a lane's masks = the pair (row r, this lane's j): lanes
         // below nj, and on a diagonal tile only j > i (lanes above r0 + r)
         const uint64_t lanes_j = nj >= 64 ? ~0ull : (1ull << nj) - 1ull;
-        uint32_t pairs = 0;
+        Mask pairs;
+        {
+            RowPush<kR> acc;
 #pragma unroll
-        for (int r = kRows - 1; r >= 0; --r) {
-            const uint32_t above = r0 + (uint32_t)r + 1u;
-            const uint64_t upper = !diag ? ~0ull : above >= 64 ? 0ull : ~0ull << above;
-            pairs = push_bit(pairs, r < nr ? lanes_j & upper : 0ull);
+            for (int r = kR - 1; r >= 0; --r) {
+                const uint32_t above = r0 + (uint32_t)r + 1u;
+                const uint64_t upper = !diag ? ~0ull : above >= 64 ? 0ull : ~0ull << above;
+                acc.push(r, r < nr ? lanes_j & upper : 0ull);
+            }
+            pairs = acc.get();
         }
         // canonical owner: a pair agreeing on an earlier key was evaluated there
         for (uint32_t k = 0; k < P.n_prev; ++k) {
             const uint32_t res = P.prev_res[k];
             const uint64_t vj = J64(res);
-            uint32_t same = 0;
+            RowPush<kR> acc;
 #pragma unroll
-            for (int r = kRows - 1; r >= 0; --r) same = push_bit(same, __ballot(f64[res * n + pi0 + r] == vj));
-            pairs &= (vmask_j >> res) & 1 ? ~(same & row_bits(f32 + n, pi0, res)) : ~0u;
+            for (int r = kR - 1; r >= 0; --r) acc.push(r, __ballot(f64[res * n + pi0 + r] == vj));
+            const Mask same = acc.get();
+            pairs &= (vmask_j >> res) & 1 ? ~(same & rvalid(res)) : kAll;
         }
         if constexpr (kCount) {
             uint32_t cnt = 0;
-            for (int r = 0; r < kRows; ++r) cnt += __popcll(__ballot((pairs >> r) & 1));
+            for (int r = 0; r < kR; ++r) cnt += __popcll(__ballot((pairs >> r) & 1));
             if (lane == 0 && cnt) atomicAdd(&s_cnt[kCountPairs], (unsigned long long)cnt);
         }
 
         // the per-lane form pays per-lane loads each round: taken when no
         // lane has more than min(4, rows / 2) live rows
         const uint32_t sparse_max = (uint32_t)min(kSparseRows, nr >> 1);
-        uint32_t matched = 0, alive = pairs;
-        uint32_t fwd = pairs, bwd = pairs, matched_b = 0;   // kOrd only: alive = fwd | bwd
+        Mask matched = 0, alive = pairs;
+        Mask fwd = pairs, bwd = pairs, matched_b = 0;   // kOrd only: alive = fwd | bwd
         // the pairs a rule starts from: every pair, or inside a group of
         // rules those that passed the group's shared step (until its end)
-        uint32_t base = pairs, group_end = 0;
+        Mask base = pairs;
+        uint32_t group_end = 0;
         bool in_group = false;
         uint32_t pc = 0;
         while (pc < plen) {
@@ -399,15 +450,16 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 if (op >= OP_CONST) {
                     // a predicate that tells t from s: one mask per valuation
                     const uint32_t aux = (raw.x >> 24) & 0xFFu;
-                    uint32_t kf, kb;
+                    Mask kf, kb;
                     if (op == OP_CONST) {   // t.A = c (aux 0) or s.A = c (aux 1), A = res
                         const int64_t c = (int64_t)param;
-                        const uint32_t lane_hit = ((vmask_j >> res) & 1) && (int64_t)J64(res) == c ? ~0u : 0u;
-                        uint32_t rows = 0;
+                        const Mask lane_hit = ((vmask_j >> res) & 1) && (int64_t)J64(res) == c ? kAll : (Mask)0;
+                        RowPush<kR> acc;
 #pragma unroll
-                        for (int r = kRows - 1; r >= 0; --r)
-                            rows = push_bit(rows, __ballot((int64_t)f64[res * n + pi0 + (uint64_t)r] == c));
-                        rows &= row_bits(f32 + n, pi0, res);
+                        for (int r = kR - 1; r >= 0; --r)
+                            acc.push(r, __ballot((int64_t)f64[res * n + pi0 + (uint64_t)r] == c));
+                        Mask rows = acc.get();
+                        rows &= rvalid(res);
                         kf = aux == 0 ? rows : lane_hit;
                         kb = aux == 0 ? lane_hit : rows;
                     } else if (op == OP_XED) {
@@ -452,23 +504,24 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                                                               (uint64_t*)(wbase + P.lds_wave_myers), lane);
                                     }
                                     if (dist <= k) {
-                                        if (dir == 0) kf |= 1u << r;
-                                        else kb |= 1u << r;
+                                        if (dir == 0) kf |= (Mask)1 << r;
+                                        else kb |= (Mask)1 << r;
                                     }
                                 }
                             }
                         }
                     } else {   // OP_XEQ: t.A = s.B, A = res, B = aux
                         const int64_t ja = (int64_t)J64(res), jb = (int64_t)J64(aux);
-                        uint32_t f = 0, g = 0;
+                        RowPush<kR> fa, ga;
 #pragma unroll
-                        for (int r = kRows - 1; r >= 0; --r) {
+                        for (int r = kR - 1; r >= 0; --r) {
                             const uint64_t pr = pi0 + (uint64_t)r;
-                            f = push_bit(f, __ballot((int64_t)f64[res * n + pr] == jb));   // t = row: row.A = lane.B
-                            g = push_bit(g, __ballot((int64_t)f64[aux * n + pr] == ja));   // t = lane: lane.A = row.B
+                            fa.push(r, __ballot((int64_t)f64[res * n + pr] == jb));   // t = row: row.A = lane.B
+                            ga.push(r, __ballot((int64_t)f64[aux * n + pr] == ja));   // t = lane: lane.A = row.B
                         }
-                        kf = (vmask_j >> aux) & 1 ? f & row_bits(f32 + n, pi0, res) : 0u;
-                        kb = (vmask_j >> res) & 1 ? g & row_bits(f32 + n, pi0, aux) : 0u;
+                        const Mask f = fa.get(), g = ga.get();
+                        kf = (vmask_j >> aux) & 1 ? f & rvalid(res) : (Mask)0;
+                        kb = (vmask_j >> res) & 1 ? g & rvalid(aux) : (Mask)0;
                     }
                     fwd &= kf;
                     bwd &= kb;
@@ -477,21 +530,22 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     continue;
                 }
             }
-            const uint32_t before = alive;
+            const Mask before = alive;
             uint32_t work = 0;
             // Few pairs left per lane (the usual state after a rule's first
             // filter): each lane evaluates only its own live pairs, one row
             // per round, reading that row's features with per-lane loads,
             // instead of the batch's 16 rows.  The arithmetic is the batch
             // form's, row for row.
-            const bool single = op <= OP_JACF && !__any(__popc(alive) > sparse_max);
+            const bool single = op <= OP_JACF && !__any(popc_rows(alive) > sparse_max);
             if (single) {
-                uint32_t rem = alive, keep = 0, rounds = 0;
-                while (__any(rem != 0u)) {
+                Mask rem = alive, keep = 0;
+                uint32_t rounds = 0;
+                while (__any(rem != 0)) {
                     ++rounds;
-                    const uint32_t r = rem != 0u ? (uint32_t)__builtin_ctz(rem) : 0u;
+                    const uint32_t r = rem != 0 ? ctz_rows(rem) : 0u;
                     const uint64_t pr = pi0 + r;
-                    const uint32_t vmask_i = f32[n + pr];
+                    const uint32_t vmask_i = all_valid ? ~0u : f32[n + pr];
                     bool ok = false;
                     switch (op) {
                     case OP_EQ_INT:
@@ -541,8 +595,8 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                         break;
                     }
                     }
-                    if (rem != 0u && ok) keep |= 1u << r;
-                    rem &= rem - 1u;
+                    if (rem != 0 && ok) keep |= (Mask)1 << r;
+                    rem &= rem - 1;
                 }
                 alive = keep;
                 work = rounds;
@@ -556,14 +610,14 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 const int64_t d = op == OP_EQ_INT ? 0 : (int64_t)param;
                 const int64_t lo = opaque(vj < INT64_MIN + d ? INT64_MIN : vj - d);
                 const int64_t hi = opaque(vj > INT64_MAX - d ? INT64_MAX : vj + d);
-                uint32_t keep = 0;
+                RowPush<kR> acc;
 #pragma unroll
-                for (int r = kRows - 1; r >= 0; --r) {   // bit r of keep: row r
+                for (int r = kR - 1; r >= 0; --r) {   // bit r of keep: row r
                     const uint64_t pr = pi0 + (uint64_t)r;   // rows >= nr: masked off, read in the pad
                     const int64_t vi = (int64_t)f64[res * n + pr];
-                    keep = push_bit(keep, __ballot(vi >= lo) & __ballot(vi <= hi));
+                    acc.push(r, __ballot(vi >= lo) & __ballot(vi <= hi));
                 }
-                alive &= jv ? keep & row_bits(f32 + n, pi0, res) : 0u;
+                alive &= jv ? acc.get() & rvalid(res) : (Mask)0;
                 work = 1;
                 break;
             }
@@ -571,15 +625,15 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 const uint32_t lj = J32(str32 + res);
                 const uint64_t cj = J64(str64 + res);
                 const uint32_t jv = (vmask_j >> (16 + res)) & 1;
-                uint32_t keep = 0;
+                RowPush<kR> acc;
 #pragma unroll
-                for (int r = kRows - 1; r >= 0; --r) {
+                for (int r = kR - 1; r >= 0; --r) {
                     const uint64_t pr = pi0 + (uint64_t)r;
                     const uint32_t li = f32[(str32 + res) * n + pr];
                     const uint64_t ci = f64[(str64 + res) * n + pr];
-                    keep = push_bit(keep, __ballot(li == lj) & __ballot(ci == cj));
+                    acc.push(r, __ballot(li == lj) & __ballot(ci == cj));
                 }
-                alive &= jv ? keep & row_bits(f32 + n, pi0, 16 + res) : 0u;
+                alive &= jv ? acc.get() & rvalid(16 + res) : (Mask)0;
                 work = 1;
                 break;
             }
@@ -595,17 +649,17 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 const int llo = opaque(lj - k), lhi = opaque(lj + k);
                 const int tj = opaque((int)__popcll(cj) - k);
                 const uint32_t cj_lo = (uint32_t)cj, cj_hi = (uint32_t)(cj >> 32);
-                uint32_t keep = 0;
+                RowPush<kR> acc;
 #pragma unroll
-                for (int r = kRows - 1; r >= 0; --r) {
+                for (int r = kR - 1; r >= 0; --r) {
                     const uint64_t pr = pi0 + (uint64_t)r;
                     const int li = (int)f32[(str32 + res) * n + pr];
                     const uint64_t ci = f64[(str64 + res) * n + pr];
                     const int both = (int)(__popc((uint32_t)ci & cj_lo) + __popc((uint32_t)(ci >> 32) & cj_hi));
                     const int t = max((int)__popcll(ci) - k, tj);
-                    keep = push_bit(keep, __ballot(both >= t) & __ballot(li >= llo) & __ballot(li <= lhi));
+                    acc.push(r, __ballot(both >= t) & __ballot(li >= llo) & __ballot(li <= lhi));
                 }
-                alive &= jv ? keep & row_bits(f32 + n, pi0, 16 + res) : 0u;
+                alive &= jv ? acc.get() & rvalid(16 + res) : (Mask)0;
                 work = 1;
                 break;
             }
@@ -622,9 +676,10 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                 const uint32_t gcol = gram64 + P.gram[res].sig_col;
                 const uint64_t gj = J64(gcol);
                 const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
-                uint32_t keep = 0;
+                Mask keep = 0;
+                RowPush<kR> acc;
                 if (num == 0) {   // J >= 0: every pair of present values
-                    keep = (vmask_j >> (24 + res)) & 1 ? row_bits(f32 + n, pi0, 24 + res) : 0u;
+                    keep = (vmask_j >> (24 + res)) & 1 ? rvalid(24 + res) : (Mask)0;
                 } else if (P.gram[res].sig_words != 1) {
                     // four-word signature (long strings): the same bound, the
                     // intersection popcount summed over the words
@@ -637,7 +692,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                         gjw[2 * w + 1] = (uint32_t)(v >> 32);
                     }
 #pragma unroll
-                    for (int r = kRows - 1; r >= 0; --r) {
+                    for (int r = kR - 1; r >= 0; --r) {
                         const uint64_t pr = pi0 + (uint64_t)r;
                         const uint32_t wa = f32[(jf32 + res) * n + pr];
                         uint32_t iub = min(wa >> 16, restb);
@@ -647,8 +702,9 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                             iub = popc_add((uint32_t)gi & gjw[2 * w], popc_add((uint32_t)(gi >> 32) & gjw[2 * w + 1], iub));
                         }
                         const bool ok = __umul24(iub, nd) >= num * (wa & 0xFFFFu) + rhs_b;
-                        keep = push_bit(keep, __ballot(ok));
+                        acc.push(r, __ballot(ok));
                     }
+                    keep = acc.get();
                 } else if (nd <= (1u << 18)) {
                     // num + den <= 2^18: I * (num + den) - num * |B| stays
                     // within int32, so one signed 24-bit multiply-add and a
@@ -658,28 +714,30 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                     const int neg_b = opaque(-(int)(num * (wb & 0xFFFFu)));
                     const uint32_t gj_lo = (uint32_t)gj, gj_hi = (uint32_t)(gj >> 32);
 #pragma unroll
-                    for (int r = kRows - 1; r >= 0; --r) {
+                    for (int r = kR - 1; r >= 0; --r) {
                         const uint64_t pr = pi0 + (uint64_t)r;
                         const uint32_t wa = f32[(jf32 + res) * n + pr];
                         const uint64_t gi = f64[gcol * n + pr];
                         const uint32_t rest = min(wa >> 16, restb);
                         const uint32_t iub = popc_add((uint32_t)gi & gj_lo, popc_add((uint32_t)(gi >> 32) & gj_hi, rest));
                         const int lhs = mad_i24((int)iub, (int)nd, neg_b);
-                        keep = push_bit(keep, __ballot(lhs >= (int)(num * (wa & 0xFFFFu))));
+                        acc.push(r, __ballot(lhs >= (int)(num * (wa & 0xFFFFu))));
                     }
+                    keep = acc.get();
                 } else {
                     const uint32_t restb = wb >> 16, rhs_b = opaque(__umul24(num, wb & 0xFFFFu));
                     const uint32_t gj_lo = (uint32_t)gj, gj_hi = (uint32_t)(gj >> 32);
 #pragma unroll
-                    for (int r = kRows - 1; r >= 0; --r) {
+                    for (int r = kR - 1; r >= 0; --r) {
                         const uint64_t pr = pi0 + (uint64_t)r;
                         const uint32_t wa = f32[(jf32 + res) * n + pr];
                         const uint64_t gi = f64[gcol * n + pr];
                         const uint32_t rest = min(wa >> 16, restb);
                         const uint32_t iub = popc_add((uint32_t)gi & gj_lo, popc_add((uint32_t)(gi >> 32) & gj_hi, rest));
                         const bool ok = __umul24(iub, nd) >= num * (wa & 0xFFFFu) + rhs_b;
-                        keep = push_bit(keep, __ballot(ok));
+                        acc.push(r, __ballot(ok));
                     }
+                    keep = acc.get();
                 }
                 alive &= keep;
                 work = 1;
@@ -753,7 +811,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                             w = ca + cb;
                         }
                     }
-                    if (need && !ok) alive &= ~(1u << r);
+                    if (need && !ok) alive &= ~((Mask)1 << r);
                     work += w;
                 }
                 break;
@@ -771,7 +829,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             if constexpr (kCount) {
                 // batches: this step ran once for the wave's 16-row batch
                 uint32_t ev = 0, ps = 0;
-                for (int r = 0; r < kRows; ++r) {
+                for (int r = 0; r < kR; ++r) {
                     ev += __popcll(__ballot((before >> r) & 1));
                     ps += __popcll(__ballot((alive >> r) & 1));
                 }
@@ -846,42 +904,48 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
     }
 }
 
-// Batch unit (tile * 4 + batch) of workgroup `bid` in a grid of a
-// multiple of 32 workgroups.  Workgroups go round-robin to the 8 XCDs
-// (bid % 8); XCD x runs tiles x, x + 8, x + 16, ... in order, the four
-// batches of a tile back to back.  A tile's four waves share its j-rows in
-// one L2, and every XCD gets an even share of heavy and light tiles.
+// Batch unit (tile * B + batch, B = 64 / rows batches per tile) of
+// workgroup `bid` in a grid of a multiple of 32 workgroups.  Workgroups go
+// round-robin to the 8 XCDs (bid % 8); XCD x runs tiles x, x + 8, x + 16,
+// ... in order, the B batches of a tile back to back.  A tile's waves share
+// its j-rows in one L2, and every XCD gets an even share of heavy and light
+// tiles.
+template <int kLogB = 2>
 __device__ __forceinline__ uint64_t batch_unit(uint64_t bid) {
     const uint64_t x = bid & 7, g = bid >> 3;
-    return (((g >> 2) * 8 + x) << 2) | (g & 3);
+    return (((g >> kLogB) * 8 + x) << kLogB) | (g & ((1u << kLogB) - 1u));
 }
 
-// One wave per workgroup, one 16-row batch per wave (batch_unit), so no
+// One wave per workgroup, one batch of kR rows per wave (batch_unit), so no
 // workgroup holds resources for waves that finished early.
-template <bool kCount>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_match(
+template <bool kCount, int kR = kRows>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kR > 32 ? 7 : 8))) void k_match(
     const MatchParams P, const Instr* __restrict__ plan, const uint64_t* __restrict__ f64,
     const uint32_t* __restrict__ f32) {
     extern __shared__ __align__(16) uint8_t lds[];
-    const uint64_t w = batch_unit(blockIdx.x);
-    const uint64_t t = w >> 2;
+    constexpr int kLogB = kR == 16 ? 2 : kR == 32 ? 1 : 0;
+    const uint64_t w = batch_unit<kLogB>(blockIdx.x);
+    const uint64_t t = w >> kLogB;
     if (t >= P.n_tiles) return;
-    match_tile<kCount>(P, gmem(plan), gmem(f64), gmem(f32), t, lds, (int)(w & 3));
+    match_tile<kCount, false, false, kR>(P, gmem(plan), gmem(f64), gmem(f32), t, lds,
+                                         (int)(w & ((1u << kLogB) - 1u)));
 }
 
 // k_match for partitions with edit-distance patterns past 64 bytes: the
 // Myers state of up to four words lives in registers (no LDS for it, so
 // more waves fit), at a register count the short-pattern kernel does not
 // pay.
-template <bool kCount>
+template <bool kCount, int kR = kRows>
 __global__ __launch_bounds__(64) void k_match_long(const MatchParams P, const Instr* __restrict__ plan,
                                                    const uint64_t* __restrict__ f64,
                                                    const uint32_t* __restrict__ f32) {
     extern __shared__ __align__(16) uint8_t lds[];
-    const uint64_t w = batch_unit(blockIdx.x);
-    const uint64_t t = w >> 2;
+    constexpr int kLogB = kR == 16 ? 2 : kR == 32 ? 1 : 0;
+    const uint64_t w = batch_unit<kLogB>(blockIdx.x);
+    const uint64_t t = w >> kLogB;
     if (t >= P.n_tiles) return;
-    match_tile<kCount, true>(P, gmem(plan), gmem(f64), gmem(f32), t, lds, (int)(w & 3));
+    match_tile<kCount, true, false, kR>(P, gmem(plan), gmem(f64), gmem(f32), t, lds,
+                                        (int)(w & ((1u << kLogB) - 1u)));
 }
 
 // k_match and k_match_long for ordered rule sets (no instrumented pass).
@@ -1239,11 +1303,11 @@ struct BatchShape {
     int sparse;
 };
 
-__device__ inline BatchShape batch_shape(uint32_t nb) {
+__device__ inline BatchShape batch_shape(uint32_t nb, uint32_t rows) {
     BatchShape b;
-    b.rows = (float)min(nb, (uint32_t)kRows);
+    b.rows = (float)min(nb, rows);
     b.lanes = (float)min(nb, (uint32_t)kTile);
-    b.sparse = min(kSparseRows, (int)min(nb, (uint32_t)kRows) >> 1);
+    b.sparse = min(kSparseRows, (int)min(nb, rows) >> 1);
     return b;
 }
 
@@ -1260,17 +1324,24 @@ __device__ inline float first_cost(uint8_t op) {
 // Cost of one round of the per-lane form against one row of the batch form
 // (per-lane loads instead of scalar ones, and the round's control).
 constexpr float kSparseRound = 2.f;
+// Fixed cost of running a step at all (instruction fetch and decode, the
+// wave-wide tests, the lane's feature loads), in the same units: measured
+// at about 20 rows of a signature filter's 12, so a step the batch never
+// reaches saves far more than a cheaper step it does.
+constexpr float kStepFixed = 240.f;
 
 // Expected cost of a first-stage step of per-row cost c reached with
-// per-pair survival probability s (each pair independently): with X the
-// live rows of a lane, X ~ Binomial(rows, s), the batch form costs c x rows
-// when some lane has more than `sparse` live rows; otherwise the per-lane
-// form takes one round per live row of the fullest lane, so the expected
-// cost is c (rows (1 - A_T) + kSparseRound sum_{m < T} (A_T - A_m)) with
-// A_m = P(X <= m)^lanes.  The plan choice only ranks alternatives, so
+// per-pair survival probability s (each pair independently): the fixed cost
+// when some pair of the batch is alive (probability 1 - (1 - s)^pairs),
+// plus, with X the live rows of a lane, X ~ Binomial(rows, s), the batch
+// form's c x rows when some lane has more than `sparse` live rows; otherwise
+// the per-lane form takes one round per live row of the fullest lane, so the
+// variable part is c (rows (1 - A_T) + kSparseRound sum_{m < T} (A_T - A_m))
+// with A_m = P(X <= m)^lanes.  The plan choice only ranks alternatives, so
 // single precision and fast intrinsics do.
 __device__ inline float step_cost(float c, float s, const BatchShape& b) {
     if (s <= 0.f) return 0.f;
+    const float any = s >= 1.f ? 1.f : 1.f - __expf(b.rows * b.lanes * __logf(1.f - s));
     const int T = b.sparse;
     float F[kSparseRows + 1];
     if (s >= 1.f) {
@@ -1288,7 +1359,7 @@ __device__ inline float step_cost(float c, float s, const BatchShape& b) {
     const float at = A(T);
     float rounds = 0.f;
     for (int m = 0; m < T; ++m) rounds += at - A(m);
-    return c * (b.rows * (1.f - at) + kSparseRound * rounds);
+    return kStepFixed * any + c * (b.rows * (1.f - at) + kSparseRound * rounds);
 }
 
 struct BlockEst {
@@ -1324,10 +1395,10 @@ __device__ inline uint64_t pack_order(const uint8_t* ord, int len) {
 // they are ranked by cost / (1 - pass rate) ascending (the order that
 // minimises the expected cost of independent filters paid per pair); every
 // step is tried as the first one (the batch form's cost), and the cheapest
-// order under stage_cost is taken when the model expects it at least 2%
+// order under stage_cost is taken when the model expects it at least 10%
 // cheaper than the heuristic order.
 __device__ inline void rule_choice(const PlanChoiceParams& C, uint32_t r, const BlockEst& e, const BatchShape& b,
-                                   uint8_t* fo) {
+                                   uint8_t* fo, float* cost_heuristic = nullptr, float* cost_chosen = nullptr) {
     const int len = C.rule_len[r];
     uint8_t id[kMaxRuleSteps], lo[kMaxRuleSteps], cand[kMaxRuleSteps];
     float rank[kMaxRuleSteps];
@@ -1356,8 +1427,11 @@ __device__ inline void rule_choice(const PlanChoiceParams& C, uint32_t r, const 
     cand[0] = best_first;
     for (int k = 0, o = 1; k < len; ++k)
         if (lo[k] != best_first) cand[o++] = lo[k];
-    const bool take = best < 0.98f * stage_cost(C, r, id, len, e, b);
+    const float heur = stage_cost(C, r, id, len, e, b);
+    const bool take = best < 0.9f * heur;
     for (int k = 0; k < len; ++k) fo[k] = take ? cand[k] : id[k];
+    if (cost_heuristic) *cost_heuristic += heur;
+    if (cost_chosen) *cost_chosen += take ? best : heur;
     // the exact checks keep the heuristic's order, whatever the first-stage
     // order: the model predicts their cost but not how many pairs they
     // reject, and a cost-only order can put a check that passes nearly
@@ -1387,13 +1461,14 @@ __global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
     bool learned = false, overflow = false, wrote = false;
     if (g < C.n_blocks) {
         const uint32_t b = C.blocks[g];
-        const BatchShape batch = batch_shape(C.blk_size[b]);
+        const BatchShape batch = batch_shape(C.blk_size[b], C.rows);
         BlockEst e{C.y + (size_t)g * C.n_spec * 2};
         uint64_t h = 0x6A09E667F3BCC909ull;
+        float heur = 0.f, chosen = 0.f;   // predicted cost per wave batch, both plans
         {
             for (uint32_t r = 0; r < C.n_rules; ++r) {
                 uint8_t fo[kMaxRuleSteps];
-                rule_choice(C, r, e, batch, fo);
+                rule_choice(C, r, e, batch, fo, &heur, &chosen);
                 const int len = C.rule_len[r];
                 bool same = true;
                 for (int k = 0; k < len; ++k) same &= fo[k] == k;
@@ -1403,6 +1478,12 @@ __global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
                 }
             }
         }
+        // the block's predicted cost under either plan, weighted by its
+        // wave batches (its pairs over the pairs of a batch)
+        const float nbf = (float)C.blk_size[b];
+        const float w = 0.5f * nbf * (nbf - 1.f) / (batch.rows * batch.lanes);
+        atomicAdd(&C.cost[0], w * heur);
+        atomicAdd(&C.cost[1], w * chosen);
         uint32_t slot = 0;
         if (learned) {
             const unsigned long long key = h ? h : 1ull;
@@ -1451,6 +1532,34 @@ static hipError_t allow_lds(const void* fn, int* configured, uint32_t bytes) {
     return e;
 }
 
+// The plain kernels at kR rows per batch (64 / kR batches per tile).
+template <int kR>
+static hipError_t launch_match_rows(const MatchParams& p, hipStream_t s) {
+    static int configured[4] = {0, 0, 0, 0};
+    const unsigned grid = (unsigned)((p.n_tiles * (kTile / kR) + 31) & ~31ull);   // batch_unit: multiple of 32
+    if (p.ed_words >= 2) {   // the register-state kernel leaves out the LDS Myers region
+        MatchParams q = p;
+        q.lds_counts = p.lds_wave_myers;
+        q.lds_bytes = (q.lds_counts + (p.counts ? kCountSlots * 8 : 0) + 15) & ~15u;
+        const void* fn = p.counts ? (const void*)k_match_long<true, kR> : (const void*)k_match_long<false, kR>;
+        hipError_t e = allow_lds(fn, &configured[p.counts ? 2 : 1], q.lds_bytes);
+        if (e != hipSuccess) return e;
+        if (p.counts)
+            k_match_long<true, kR><<<grid, 64, q.lds_bytes, s>>>(q, q.plan, q.feat.f64, q.feat.f32);
+        else
+            k_match_long<false, kR><<<grid, 64, q.lds_bytes, s>>>(q, q.plan, q.feat.f64, q.feat.f32);
+        return hipGetLastError();
+    }
+    const void* fn = p.counts ? (const void*)k_match<true, kR> : (const void*)k_match<false, kR>;
+    hipError_t e = allow_lds(fn, &configured[p.counts ? 3 : 0], p.lds_bytes);
+    if (e != hipSuccess) return e;
+    if (p.counts)
+        k_match<true, kR><<<grid, 64, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
+    else
+        k_match<false, kR><<<grid, 64, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
+    return hipGetLastError();
+}
+
 hipError_t launch_match(const MatchParams& p, hipStream_t s) {
     if (p.n_tiles == 0) return hipSuccess;
     if (p.n_tiles > kMaxTiles) return hipErrorInvalidValue;   // the grid holds 4 x n_tiles workgroups
@@ -1472,12 +1581,29 @@ hipError_t launch_match(const MatchParams& p, hipStream_t s) {
         }
         return hipGetLastError();
     }
+    // 32- or 64-row batches (two or one per tile) for the plain kernels and
+    // their instrumented pass when asked: a step's fixed cost is paid once
+    // per 2,048 or 4,096 pairs instead of 1,024
+    if (p.rows == 64) return launch_match_rows<64>(p, s);
+    const bool r32 = p.rows == 32;
+    const unsigned grid32 = (unsigned)((p.n_tiles * 2 + 31) & ~31ull);
+    static int configured32[4] = {0, 0, 0, 0};
     if (p.ed_words >= 2) {
         // the register-state kernel leaves out the LDS Myers region (the
         // layout's last one)
         MatchParams q = p;
         q.lds_counts = p.lds_wave_myers;
         q.lds_bytes = (q.lds_counts + (p.counts ? kCountSlots * 8 : 0) + 15) & ~15u;
+        if (r32) {
+            const void* fn = p.counts ? (const void*)k_match_long<true, 32> : (const void*)k_match_long<false, 32>;
+            hipError_t e = allow_lds(fn, &configured32[p.counts ? 2 : 1], q.lds_bytes);
+            if (e != hipSuccess) return e;
+            if (p.counts)
+                k_match_long<true, 32><<<grid32, 64, q.lds_bytes, s>>>(q, q.plan, q.feat.f64, q.feat.f32);
+            else
+                k_match_long<false, 32><<<grid32, 64, q.lds_bytes, s>>>(q, q.plan, q.feat.f64, q.feat.f32);
+            return hipGetLastError();
+        }
         const void* fn = p.counts ? (const void*)k_match_long<true> : (const void*)k_match_long<false>;
         hipError_t e = allow_lds(fn, &configured[p.counts ? 2 : 3], q.lds_bytes);
         if (e != hipSuccess) return e;
@@ -1485,6 +1611,16 @@ hipError_t launch_match(const MatchParams& p, hipStream_t s) {
             k_match_long<true><<<grid, 64, q.lds_bytes, s>>>(q, q.plan, q.feat.f64, q.feat.f32);
         else
             k_match_long<false><<<grid, 64, q.lds_bytes, s>>>(q, q.plan, q.feat.f64, q.feat.f32);
+        return hipGetLastError();
+    }
+    if (r32) {
+        const void* fn = p.counts ? (const void*)k_match<true, 32> : (const void*)k_match<false, 32>;
+        hipError_t e = allow_lds(fn, &configured32[p.counts ? 3 : 0], p.lds_bytes);
+        if (e != hipSuccess) return e;
+        if (p.counts)
+            k_match<true, 32><<<grid32, 64, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
+        else
+            k_match<false, 32><<<grid32, 64, p.lds_bytes, s>>>(p, p.plan, p.feat.f64, p.feat.f32);
         return hipGetLastError();
     }
     if (p.counts) {
