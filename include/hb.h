@@ -186,19 +186,25 @@ hb_status hb_partition(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id,
 /* Evaluation order (output-neutral, Section 4):
  *   HB_PLAN_GIVEN      rules and predicates in the given order;
  *   HB_PLAN_HEURISTIC  the execution plan of Section 4.2 (cost-effectiveness
- *                      order, execution tree, edge scores, DFS order);
+ *                      order, execution tree, edge scores, DFS order); rules
+ *                      whose first steps are the same cheap step on the
+ *                      same attribute (any threshold) are placed together
+ *                      and share one guard step at the loosest threshold;
  *   HB_PLAN_LEARNED    a plan per block from the context's cost model (a
  *                      different plan on each partition, the paper's future
- *                      topic in Section 8), rules in the heuristic order:
+ *                      topic in Section 8), rules as in the heuristic plan:
  *                      per rule, the first-stage steps (value predicates and
- *                      exact filters) by step cost / (1 - probability that
- *                      some pair of the block's wave batch of
- *                      min(n, 16) x min(n, 64) pairs passes, from the
- *                      model's predicted pass rate), kept only where the
- *                      model expects it 2% cheaper than the heuristic
+ *                      exact filters) ordered to minimise their expected
+ *                      cost on the block's wave batch of min(n, rows) x
+ *                      min(n, 64) pairs under the model's predicted pass
+ *                      rates, each step tried as the first, kept only where
+ *                      the model expects it 10% cheaper than the heuristic
  *                      order; the exact checks stay in the heuristic order.
- *                      Blocks of fewer than 16 tuples keep the heuristic
- *                      plan.  Built on the device (no host round trip).
+ *                      Blocks of fewer than 64 tuples keep the heuristic
+ *                      plan, and so does every block of a key partition
+ *                      where the model expects the per-block plans to save
+ *                      under 3% in all.  Built on the device; one 8-byte
+ *                      read-back per key partition.
  *                      Needs a cost model (HB_ERR_STATE otherwise).
  * The ordering strategies the paper's experiments compare against
  * (Section 6, "Tests on EPG"), for studies; each is output-neutral:
@@ -266,6 +272,15 @@ hb_status hb_match_noalloc(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, in
  * rule sets and batches keep 16; hb_match_work follows the setting.  Other
  * values: HB_ERR_INVALID_ARG. */
 hb_status hb_set_rows_per_wave(hb_ctx* ctx, uint32_t rows);
+
+/* Second launch-shape setting of this context: a filter step of a wave
+ * batch runs per lane (each lane evaluates only its own live rows, one per
+ * round) when no lane has more than `max_rows` live rows and `max_rows` is
+ * at most half the batch's rows; otherwise it runs for every row of the
+ * batch.  0 (the default) takes the tuned threshold of the batch size.
+ * Applies to every match launch of the context; the result is the same.
+ * Values above 32: HB_ERR_INVALID_ARG. */
+hb_status hb_set_sparse_rows(hb_ctx* ctx, uint32_t max_rows);
 
 /* ------------------------------------------------------------ introspection */
 

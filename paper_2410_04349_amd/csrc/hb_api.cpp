@@ -774,7 +774,7 @@ static KeyRes key_resources(const Relation& rel, const RuleSet& rs, size_t ka) {
 // `segs` (optional) receives each rule's segment: its first instruction,
 // its first-stage steps (in path order) and its guard step.
 static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, const std::vector<PathRule>& path,
-                                    size_t ka, const KeyRes& R, std::vector<RuleSeg>* segs = nullptr) {
+                                    size_t ka, const KeyRes& R, bool regroup, std::vector<RuleSeg>* segs = nullptr) {
     auto spec_of = [&](uint32_t p) -> const PredSpec* {
         for (const PredSpec& sp : R.specs)
             if (sp.pred == p) return &sp;
@@ -842,16 +842,67 @@ static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, cons
     auto same_step = [](const Instr& a, const Instr& b) {
         return a.op == b.op && a.op <= OP_JACF && a.res == b.res && a.aux == b.aux && a.param == b.param;
     };
+    // the same cheap step on the same attribute, at any threshold
+    auto same_kind = [](const Instr& a, const Instr& b) {
+        return a.op == b.op && a.op <= OP_JACF && a.res == b.res && a.aux == b.aux;
+    };
+    // a passes every pair b passes (a and b of one kind): the larger
+    // distance bound, the lower Jaccard threshold num / den
+    auto looser = [](const Instr& a, const Instr& b) {
+        switch (a.op) {
+        case OP_ABSDIFF: return (int64_t)a.param >= (int64_t)b.param;
+        case OP_EDF: return (uint32_t)a.param >= (uint32_t)b.param;
+        case OP_JACF: {
+            const uint64_t na = a.param >> 32, da = a.param & 0xFFFFFFFFu;
+            const uint64_t nb = b.param >> 32, db = b.param & 0xFFFFFFFFu;
+            return na * db <= nb * da;
+        }
+        default: return a.param == b.param;
+        }
+    };
+    const bool share = !rs.ordered;
+    if (share && regroup) {
+        // rules whose first steps are of one kind are placed together, at
+        // the first one's place, so that one guard serves them all (the
+        // listing is a union over rules, so their order is free)
+        std::vector<RuleCode> placed;
+        std::vector<bool> used(rc.size(), false);
+        for (size_t x = 0; x < rc.size(); ++x) {
+            if (used[x]) continue;
+            used[x] = true;
+            if (rc[x].first.empty() || rc[x].first[0].op > OP_JACF) {
+                placed.push_back(std::move(rc[x]));
+                continue;
+            }
+            const Instr head = rc[x].first[0];   // a copy: `placed` grows below
+            placed.push_back(std::move(rc[x]));
+            for (size_t y = x + 1; y < rc.size(); ++y)
+                if (!used[y] && !rc[y].first.empty() && same_kind(rc[y].first[0], head)) {
+                    used[y] = true;
+                    placed.push_back(std::move(rc[y]));
+                }
+        }
+        rc.swap(placed);
+    }
     std::vector<Instr> code;
     if (segs) segs->clear();
     for (size_t x = 0; x < rc.size();) {
-        size_t y = x + 1;   // [x, y): rules sharing their first step
-        if (!rs.ordered && !rc[x].first.empty())
-            while (y < rc.size() && !rc[y].first.empty() && same_step(rc[y].first[0], rc[x].first[0])) ++y;
+        // [x, y): rules sharing their first step; with regrouping, rules
+        // whose first steps are of one kind, under a guard at the loosest
+        // threshold among them (a pair failing it fails each rule's own)
+        size_t y = x + 1;
+        size_t owner = x;   // the rule whose first step the guard is
+        if (share && !rc[x].first.empty())
+            while (y < rc.size() && !rc[y].first.empty() &&
+                   (regroup ? same_kind(rc[y].first[0], rc[x].first[0]) : same_step(rc[y].first[0], rc[x].first[0]))) {
+                if (looser(rc[y].first[0], rc[owner].first[0]) && !looser(rc[owner].first[0], rc[y].first[0]))
+                    owner = y;
+                ++y;
+            }
         const bool group = y - x >= 2;
         size_t guard_at = 0;
         if (group) {
-            Instr g = rc[x].first[0];
+            Instr g = rc[owner].first[0];
             g.aux = g.op;
             g.op = OP_GUARD;
             guard_at = code.size();
@@ -859,7 +910,8 @@ static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, cons
         }
         for (size_t k = x; k < y; ++k) {
             RuleCode& r = rc[k];
-            const size_t skip = group ? 1 : 0;
+            // a rule whose first step is the guard's does not repeat it
+            const size_t skip = group && same_step(r.first[0], rc[owner].first[0]) ? 1 : 0;
             const size_t first = code.size();
             code.insert(code.end(), r.first.begin() + skip, r.first.end());
             code.insert(code.end(), r.verify.begin(), r.verify.end());
@@ -872,7 +924,7 @@ static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, cons
                 RuleSeg sg;
                 sg.start = (uint32_t)first;
                 sg.first_preds.assign(r.first_preds.begin() + skip, r.first_preds.end());
-                sg.guard_pred = group ? (int)r.first_preds[0] : -1;
+                sg.guard_pred = group ? (int)rc[owner].first_preds[0] : -1;
                 segs->push_back(std::move(sg));
             }
         }
@@ -977,6 +1029,7 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
                                " bytes of LDS) exceeds the device limit");
 
     m.rows = c->rows_per_wave;
+    m.sparse_rows = c->sparse_rows;
     {   // no validity bitmap on any attribute a step reads (keys included)
         bool all = true;
         for (uint32_t a : R.int_attr) all = all && rel.cols[a].valid.size() == 0;
@@ -998,11 +1051,15 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     return true;
 }
 
-static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, const std::vector<PathRule>& path, size_t ka,
+// Guards across thresholds (rules regrouped) for the heuristic and learned
+// plans; the comparison orders keep their rule order.
+static bool regroups(int plan) { return plan == HB_PLAN_HEURISTIC || plan == HB_PLAN_LEARNED; }
+
+static bool build_key_plan(Ctx* c, Relation& rel, RuleSet& rs, int plan, const std::vector<PathRule>& path, size_t ka,
                            KeyPlan& kp, bool count) {
     KeyRes R;
     if (!prepare_key(c, rel, rs, ka, kp, R, count)) return false;
-    kp.code = emit_code(rel, rs, path, ka, R);
+    kp.code = emit_code(rel, rs, path, ka, R, regroups(plan));
     kp.mp.plan_len = (uint32_t)kp.code.size();
     return true;
 }
@@ -1043,7 +1100,7 @@ static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyP
     const uint32_t nb = kp.mp.n_blocks;
     const uint32_t ns = (uint32_t)R.specs.size();
     std::vector<RuleSeg> segs;
-    kp.code = emit_code(rel, rs, heuristic, ka, R, &segs);
+    kp.code = emit_code(rel, rs, heuristic, ka, R, true, &segs);
     kp.mp.plan_len = (uint32_t)kp.code.size();
     // the partition's rules in heuristic order: where each rule's segment
     // starts, its first-stage steps and the guard step it sits under
@@ -1093,6 +1150,7 @@ static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyP
     C.n_slots = std::min<uint32_t>(kPlanSlots, next_pow2(std::max<uint32_t>(2 * nl, 16)));
     C.plan_len = kp.mp.plan_len;
     C.rows = kp.mp.rows == 64 ? 64u : kp.mp.rows == 32 ? 32u : 16u;
+    C.sparse_rows = kp.mp.sparse_rows;
     for (uint32_t x = 0; x < ns; ++x) C.spec_kind[x] = (uint8_t)R.specs[x].op;
     DevBuf keys(c, sizeof(unsigned long long) * C.n_slots);
     zero(c, keys.get(), keys.size());
@@ -1231,7 +1289,7 @@ bool valid_plan(int plan) { return plan >= HB_PLAN_GIVEN && plan <= HB_PLAN_RAND
 
 bool key_plan(Ctx* c, Relation& rel, RuleSet& rs, int plan, const std::vector<PathRule>& path, size_t ka,
               KeyPlan& kp, bool count, uint64_t* n_fallback) {
-    if (plan != HB_PLAN_LEARNED) return build_key_plan(c, rel, rs, path, ka, kp, count);
+    if (plan != HB_PLAN_LEARNED) return build_key_plan(c, rel, rs, plan, path, ka, kp, count);
     KeyRes R;
     if (!prepare_key(c, rel, rs, ka, kp, R, count)) return false;
     c->host_timed("learned_plan", [&] { learned_key_plan(c, rel, rs, ka, kp, R, path, n_fallback); });
@@ -1437,7 +1495,7 @@ static void match_noalloc(Ctx* c, uint32_t rel_id, uint32_t rs_id, int plan, uin
     for (size_t ka = 0; ka < rs.keys.size(); ++ka) {
         if (rel.parts.at(rs.keys[ka]).n_tiles == 0) continue;
         KeyPlan kp;
-        if (!build_key_plan(c, rel, rs, path, ka, kp, false)) continue;
+        if (!build_key_plan(c, rel, rs, plan, path, ka, kp, false)) continue;
         total_code += kp.code.size();
         kps.push_back(std::move(kp));
     }
@@ -1593,6 +1651,14 @@ hb_status hb_set_rows_per_wave(hb_ctx* ctx, uint32_t rows) {
         if (rows != 16 && rows != 32 && rows != 64) hb::fail(HB_ERR_INVALID_ARG, "rows per wave batch must be 16, 32 or 64");
         c->rows_per_wave = rows;
         for (auto& it : c->rulesets) it.second->has_result = false;   // a later hb_match evaluates again
+    });
+}
+
+hb_status hb_set_sparse_rows(hb_ctx* ctx, uint32_t max_rows) {
+    return guard(ctx, [&](Ctx* c) {
+        if (max_rows > (uint32_t)hb::kMaxSparseRows) hb::fail(HB_ERR_INVALID_ARG, "the per-lane threshold must be at most 32");
+        c->sparse_rows = max_rows;
+        for (auto& it : c->rulesets) it.second->has_result = false;
     });
 }
 

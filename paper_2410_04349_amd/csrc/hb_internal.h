@@ -11,7 +11,14 @@ namespace hb {
 
 constexpr int kTile = 64;        // tuples per tile side (one wave of j's)
 constexpr int kRows = 16;        // i-rows per wave batch (four batches per 64-row tile)
-constexpr int kSparseRows = 4;   // a filter step runs per lane, live row by live row, when no lane has more
+// A filter step runs per lane, live row by live row, when no lane has more
+// live rows than the threshold (capped at half the batch's rows): the
+// context's setting (hb_set_sparse_rows), or 0 for the default of the batch
+// size.
+constexpr int kMaxSparseRows = 32;
+__host__ __device__ constexpr uint32_t sparse_rows(uint32_t setting, uint32_t rows) {
+    return setting ? setting : rows >= 64 ? 8u : 4u;
+}
 constexpr uint64_t kMaxTiles = (1ull << 30) - 8;   // one launch's grid: 4 x tiles, rounded up to 32 < 2^32
 constexpr int kLshK = 1024;      // LSH buckets of the selectivity estimate
 constexpr int kMaxIntRes = 16;   // int attributes staged per tile
@@ -157,6 +164,8 @@ struct MatchParams {
     // i-rows per wave batch of the plain launch: 16 (four batches per tile),
     // 32 (two) or 64 (one); ordered rule sets and the batch kernels use 16
     uint32_t rows;
+    // the per-lane form's threshold setting (0: the default of the batch size)
+    uint32_t sparse_rows;
     // 1: no attribute the plan reads has a missing value (the validity mask
     // words are not read)
     uint32_t all_valid;
@@ -315,6 +324,7 @@ struct PlanChoiceParams {
     uint32_t n_slots;                 // table size (power of two, <= kPlanSlots)
     uint32_t plan_len;                // instructions of one plan
     uint32_t rows;                    // i-rows per wave batch of the launch (16, 32 or 64)
+    uint32_t sparse_rows;             // the per-lane form's threshold setting (0: default)
     uint8_t rule_len[kMaxPlanRules];  // first-stage steps per rule (a shared guard step excluded)
     uint16_t rule_seg[kMaxPlanRules]; // first instruction of each rule's segment
     uint8_t rule_guard[kMaxPlanRules];   // spec index of the rule's shared guard step, 0xFF: none

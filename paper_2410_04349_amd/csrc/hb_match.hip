@@ -396,7 +396,7 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
 
         // the per-lane form pays per-lane loads each round: taken when no
         // lane has more than min(4, rows / 2) live rows
-        const uint32_t sparse_max = (uint32_t)min(kSparseRows, nr >> 1);
+        const uint32_t sparse_max = min(sparse_rows(P.sparse_rows, kR), (uint32_t)nr >> 1);
         Mask matched = 0, alive = pairs;
         Mask fwd = pairs, bwd = pairs, matched_b = 0;   // kOrd only: alive = fwd | bwd
         // the pairs a rule starts from: every pair, or inside a group of
@@ -1303,11 +1303,11 @@ struct BatchShape {
     int sparse;
 };
 
-__device__ inline BatchShape batch_shape(uint32_t nb, uint32_t rows) {
+__device__ inline BatchShape batch_shape(uint32_t nb, uint32_t rows, uint32_t sparse_setting) {
     BatchShape b;
     b.rows = (float)min(nb, rows);
     b.lanes = (float)min(nb, (uint32_t)kTile);
-    b.sparse = min(kSparseRows, (int)min(nb, rows) >> 1);
+    b.sparse = (int)min(min(sparse_rows(sparse_setting, rows), (uint32_t)kMaxSparseRows), min(nb, rows) >> 1);
     return b;
 }
 
@@ -1343,7 +1343,7 @@ __device__ inline float step_cost(float c, float s, const BatchShape& b) {
     if (s <= 0.f) return 0.f;
     const float any = s >= 1.f ? 1.f : 1.f - __expf(b.rows * b.lanes * __logf(1.f - s));
     const int T = b.sparse;
-    float F[kSparseRows + 1];
+    float F[kMaxSparseRows + 1];
     if (s >= 1.f) {
         for (int m = 0; m <= T; ++m) F[m] = (float)m >= b.rows ? 1.f : 0.f;
     } else {
@@ -1461,7 +1461,7 @@ __global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
     bool learned = false, overflow = false, wrote = false;
     if (g < C.n_blocks) {
         const uint32_t b = C.blocks[g];
-        const BatchShape batch = batch_shape(C.blk_size[b], C.rows);
+        const BatchShape batch = batch_shape(C.blk_size[b], C.rows, C.sparse_rows);
         BlockEst e{C.y + (size_t)g * C.n_spec * 2};
         uint64_t h = 0x6A09E667F3BCC909ull;
         float heur = 0.f, chosen = 0.f;   // predicted cost per wave batch, both plans

@@ -346,9 +346,9 @@ def test_work_counters_consistent(hb, ctx):
     for k, (name, c) in enumerate(w["per_op"].items()):
         # filter kinds (the first five): `work` counts rounds of the
         # per-lane form, at most 64 pairs each; a wave batch holds the
-        # context's 32 rows
+        # context's 64 rows (the default)
         single = c["work"] if k < 5 else 0
-        assert c["passed"] <= c["lanes"] <= 32 * 64 * c["waves"] + 64 * single, name
+        assert c["passed"] <= c["lanes"] <= 64 * 64 * c["waves"] + 64 * single, name
     # the cached result is untouched by the instrumented pass
     assert np.array_equal(hb.hb_match(ctx, rid, rs, "heuristic"), got)
     hb.hb_release_relation(ctx, rid)
