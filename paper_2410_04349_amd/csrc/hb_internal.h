@@ -17,7 +17,7 @@ constexpr int kRows = 16;        // i-rows per wave batch (four batches per 64-r
 // size.
 constexpr int kMaxSparseRows = 32;
 __host__ __device__ constexpr uint32_t sparse_rows(uint32_t setting, uint32_t rows) {
-    return setting ? setting : rows >= 64 ? 8u : 4u;
+    return setting ? setting : rows >= 64 ? 16u : rows >= 32 ? 8u : 4u;
 }
 constexpr uint64_t kMaxTiles = (1ull << 30) - 8;   // one launch's grid: 4 x tiles, rounded up to 32 < 2^32
 constexpr int kLshK = 1024;      // LSH buckets of the selectivity estimate

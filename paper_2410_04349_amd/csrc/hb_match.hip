@@ -539,67 +539,111 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
             // form's, row for row.
             const bool single = op <= OP_JACF && !__any(popc_rows(alive) > sparse_max);
             if (single) {
-                Mask rem = alive, keep = 0;
-                uint32_t rounds = 0;
-                while (__any(rem != 0)) {
-                    ++rounds;
-                    const uint32_t r = rem != 0 ? ctz_rows(rem) : 0u;
-                    const uint64_t pr = pi0 + r;
-                    const uint32_t vmask_i = all_valid ? ~0u : f32[n + pr];
-                    bool ok = false;
-                    switch (op) {
-                    case OP_EQ_INT:
-                    case OP_ABSDIFF: {
-                        const int64_t vj = (int64_t)J64(res);
-                        const int64_t d = op == OP_EQ_INT ? 0 : (int64_t)param;
-                        const int64_t lo = vj < INT64_MIN + d ? INT64_MIN : vj - d;
-                        const int64_t hi = vj > INT64_MAX - d ? INT64_MAX : vj + d;
-                        const int64_t vi = (int64_t)f64[res * n + pr];
-                        ok = ((vmask_j & vmask_i) >> res) & 1 && vi >= lo && vi <= hi;
-                        break;
+                // one live row per lane and round; the operation's lane-side
+                // operands are read once, the row's from its column with a
+                // uniform base and a 32-bit lane offset.  A lane whose own
+                // value is missing fails every row at once; a row's validity
+                // bit `vbit` is read only where the relation has missing
+                // values (kValid false).
+                const uint32_t* vcol = f32 + n + pi0;   // the rows' validity words
+                auto rounds = [&](auto valid_tag, bool lane_ok, uint32_t vbit, auto&& test) -> uint32_t {
+                    constexpr bool kValid = decltype(valid_tag)::value;
+                    Mask rem = lane_ok ? alive : (Mask)0, keep = 0;
+                    uint32_t n_rounds = 0;
+                    while (__any(rem != 0)) {
+                        ++n_rounds;
+                        const uint32_t r = rem != 0 ? ctz_rows(rem) : 0u;
+                        // every load of the round issued together: no
+                        // short-circuit between the conditions
+                        bool ok = test(r);
+                        if constexpr (!kValid) ok = ok & (((vcol[r] >> vbit) & 1) != 0);
+                        if (rem != 0 && ok) keep |= (Mask)1 << r;
+                        rem &= rem - 1;
                     }
-                    case OP_EQF: {
-                        const uint32_t li = f32[(str32 + res) * n + pr];
-                        const uint64_t ci = f64[(str64 + res) * n + pr];
-                        ok = ((vmask_j & vmask_i) >> (16 + res)) & 1 && li == J32(str32 + res) && ci == J64(str64 + res);
-                        break;
-                    }
-                    case OP_EDF: {
-                        const int lj = (int)J32(str32 + res);
-                        const uint64_t cj = J64(str64 + res);
-                        const int k = (int)param;
-                        const int li = (int)f32[(str32 + res) * n + pr];
-                        const uint64_t ci = f64[(str64 + res) * n + pr];
+                    alive = keep;
+                    return n_rounds;
+                };
+                auto rounds_of = [&](bool lane_ok, uint32_t vbit, auto&& test) -> uint32_t {
+                    return all_valid ? rounds(std::true_type{}, lane_ok, vbit, test)
+                                     : rounds(std::false_type{}, lane_ok, vbit, test);
+                };
+                switch (op) {
+                case OP_EQ_INT:
+                case OP_ABSDIFF: {
+                    const int64_t vj = (int64_t)J64(res);
+                    const int64_t d = op == OP_EQ_INT ? 0 : (int64_t)param;
+                    const int64_t lo = vj < INT64_MIN + d ? INT64_MIN : vj - d;
+                    const int64_t hi = vj > INT64_MAX - d ? INT64_MAX : vj + d;
+                    const int64_t* col = (const int64_t*)f64 + (uint64_t)res * n + pi0;
+                    work = rounds_of((vmask_j >> res) & 1, res, [&](uint32_t r) {
+                        const int64_t vi = col[r];
+                        return (vi >= lo) & (vi <= hi);
+                    });
+                    break;
+                }
+                case OP_EQF: {
+                    const uint32_t lj = J32(str32 + res);
+                    const uint64_t cj = J64(str64 + res);
+                    const uint32_t* lcol = f32 + (uint64_t)(str32 + res) * n + pi0;
+                    const uint64_t* ccol = f64 + (uint64_t)(str64 + res) * n + pi0;
+                    work = rounds_of((vmask_j >> (16 + res)) & 1, 16 + res, [&](uint32_t r) {
+                        return (lcol[r] == lj) & (ccol[r] == cj);
+                    });
+                    break;
+                }
+                case OP_EDF: {
+                    const int lj = (int)J32(str32 + res);
+                    const uint64_t cj = J64(str64 + res);
+                    const int k = (int)param;
+                    const int tj = (int)__popcll(cj) - k;
+                    const uint32_t* lcol = f32 + (uint64_t)(str32 + res) * n + pi0;
+                    const uint64_t* ccol = f64 + (uint64_t)(str64 + res) * n + pi0;
+                    work = rounds_of((vmask_j >> (16 + res)) & 1, 16 + res, [&](uint32_t r) {
+                        const int li = (int)lcol[r];
+                        const uint64_t ci = ccol[r];
                         const int both = (int)(__popc((uint32_t)ci & (uint32_t)cj) +
                                                __popc((uint32_t)(ci >> 32) & (uint32_t)(cj >> 32)));
-                        const int t = max((int)__popcll(ci) - k, (int)__popcll(cj) - k);
-                        ok = ((vmask_j & vmask_i) >> (16 + res)) & 1 && both >= t && li >= lj - k && li <= lj + k;
-                        break;
-                    }
-                    default: {   // OP_JACF: the bound of the batch form, in exact 64-bit arithmetic
-                        const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
-                        if (num == 0) {
-                            ok = ((vmask_j & vmask_i) >> (24 + res)) & 1;
-                            break;
-                        }
-                        const uint32_t gcol = gram64 + P.gram[res].sig_col;
-                        const uint32_t wb = J32(jf32 + res);
-                        const uint32_t wa = f32[(jf32 + res) * n + pr];
-                        uint32_t iub = min(wa >> 16, wb >> 16);
-                        const uint32_t words = P.gram[res].sig_words;
-                        for (uint32_t w = 0; w < words; ++w) {
-                            const uint64_t gi = f64[(gcol + w) * n + pr], gj = J64(gcol + w);
-                            iub += (uint32_t)__popcll(gi & gj);
-                        }
-                        ok = (uint64_t)iub * nd >= (uint64_t)num * ((wa & 0xFFFFu) + (wb & 0xFFFFu));
-                        break;
-                    }
-                    }
-                    if (rem != 0 && ok) keep |= (Mask)1 << r;
-                    rem &= rem - 1;
+                        const int t = max((int)__popcll(ci) - k, tj);
+                        return (both >= t) & (li >= lj - k) & (li <= lj + k);
+                    });
+                    break;
                 }
-                alive = keep;
-                work = rounds;
+                default: {   // OP_JACF: the bound of the batch form, in exact 64-bit arithmetic
+                    const uint32_t num = (uint32_t)(param >> 32), nd = num + (uint32_t)(param & 0xFFFFFFFFu);
+                    if (num == 0) {   // every pair of present values
+                        work = rounds_of((vmask_j >> (24 + res)) & 1, 24 + res, [](uint32_t) { return true; });
+                        break;
+                    }
+                    // the filter words fail a missing value against anything
+                    // (num > 0): no validity bit is read
+                    const uint32_t gcol = gram64 + P.gram[res].sig_col;
+                    const uint32_t wb = J32(jf32 + res);
+                    const uint32_t* wcol = f32 + (uint64_t)(jf32 + res) * n + pi0;
+                    const uint64_t* gcol0 = f64 + (uint64_t)gcol * n + pi0;
+                    if (P.gram[res].sig_words == 1) {
+                        const uint64_t gj = J64(gcol);
+                        work = rounds(std::true_type{}, true, 0, [&](uint32_t r) {
+                            const uint32_t wa = wcol[r];
+                            const uint64_t gi = gcol0[r];
+                            const uint32_t iub = min(wa >> 16, wb >> 16) + (uint32_t)__popcll(gi & gj);
+                            return (uint64_t)iub * nd >= (uint64_t)num * ((wa & 0xFFFFu) + (wb & 0xFFFFu));
+                        });
+                    } else {   // the four-word signature of long strings
+                        uint64_t gjw[kLongSigWords];
+#pragma unroll
+                        for (uint32_t w = 0; w < kLongSigWords; ++w) gjw[w] = J64(gcol + w);
+                        work = rounds(std::true_type{}, true, 0, [&](uint32_t r) {
+                            const uint32_t wa = wcol[r];
+                            uint32_t iub = min(wa >> 16, wb >> 16);
+#pragma unroll
+                            for (uint32_t w = 0; w < kLongSigWords; ++w)
+                                iub += (uint32_t)__popcll(gcol0[(uint64_t)w * n + r] & gjw[w]);
+                            return (uint64_t)iub * nd >= (uint64_t)num * ((wa & 0xFFFFu) + (wb & 0xFFFFu));
+                        });
+                    }
+                    break;
+                }
+                }
             } else switch (op) {
             case OP_EQ_INT:
             case OP_ABSDIFF: {
