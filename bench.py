@@ -260,10 +260,10 @@ def run_batched(args):
     print(json.dumps(result), flush=True)
 
 
-PROFILE_NAMES = ("match", "partition_sort", "gram_slots", "gram_build", "gram_sig", "char_sig", "lsh", "gather",
+PROFILE_NAMES = ("match", "partition_sort", "gram_slots", "gram_build", "char_sig", "lsh", "gather",
                  "output_sort", "learned_plan", "block_features", "predict", "plan_choice")
 # steps bound by HBM bandwidth (their algorithmic bytes come from the library)
-STREAMING = ("gram_slots", "gram_build", "gram_sig", "char_sig", "lsh", "partition_sort", "gather", "output_sort")
+STREAMING = ("gram_slots", "gram_build", "char_sig", "lsh", "partition_sort", "gather", "output_sort")
 PEAK_HBM = 8.0e12   # bytes/s
 
 

@@ -203,8 +203,9 @@ hb_status hb_partition(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id,
  *                      Blocks of fewer than 64 tuples keep the heuristic
  *                      plan, and so does every block of a key partition
  *                      where the model expects the per-block plans to save
- *                      under 3% in all.  Built on the device; one 8-byte
- *                      read-back per key partition.
+ *                      under 25% in all (hb_set_learned_min_saving).  Built
+ *                      on the device; one 8-byte read-back per key
+ *                      partition.
  *                      Needs a cost model (HB_ERR_STATE otherwise).
  * The ordering strategies the paper's experiments compare against
  * (Section 6, "Tests on EPG"), for studies; each is output-neutral:
@@ -282,6 +283,14 @@ hb_status hb_set_rows_per_wave(hb_ctx* ctx, uint32_t rows);
  * Values above 32: HB_ERR_INVALID_ARG. */
 hb_status hb_set_sparse_rows(hb_ctx* ctx, uint32_t max_rows);
 
+/* HB_PLAN_LEARNED keeps a key partition's per-block plans only when the
+ * cost model predicts they save at least `min_saving` of the partition's
+ * cost under the heuristic plan (default 0.25: distinct plans miss the
+ * scalar cache that one shared plan hits, and smaller predicted savings did
+ * not hold up in measurement); 0 keeps every per-block plan.  Values
+ * outside [0, 1): HB_ERR_INVALID_ARG. */
+hb_status hb_set_learned_min_saving(hb_ctx* ctx, float min_saving);
+
 /* ------------------------------------------------------------ introspection */
 
 /* Per distinct predicate of a rule set (in first-appearance order): its
@@ -313,8 +322,9 @@ hb_status hb_plan_path(uint32_t plan, uint32_t n_preds, const double* sp, const 
 
 /* Kernel timing: when enabled, HIP events bracket each kernel launch of the
  * named step on the context stream.  Names: "match", "partition_sort",
- * "gram_slots", "gram_build", "gram_sig", "char_sig", "lsh", "gather",
- * "output_sort", "log", "block_features", "plan_choice"; and, as host wall
+ * "gram_slots", "gram_build" (the q-gram codes and signatures), "char_sig",
+ * "lsh", "gather", "output_sort", "log", "block_features", "plan_choice";
+ * and, as host wall
  * time including synchronisation, "learned_plan" (building one key
  * partition's per-block learned plans) and "predict" (cost-model inference
  * inside it). */
@@ -323,7 +333,7 @@ hb_status hb_profile_query(hb_ctx* ctx, const char* name, double* total_ms, uint
 /* Algorithmic HBM bytes of the timed launches counted under `name` since
  * the last reset: what each launch must read once and write once (for
  * "match": its feature columns; for the streaming steps "gram_slots",
- * "gram_build", "gram_sig", "char_sig", "lsh", "partition_sort",
+ * "gram_build", "char_sig", "lsh", "partition_sort",
  * "gather", "output_sort": their inputs and outputs), so bytes / time is
  * the step's effective bandwidth. */
 hb_status hb_profile_bytes(hb_ctx* ctx, const char* name, double* bytes);
@@ -451,7 +461,8 @@ typedef struct {
     /* HB_PLAN_LEARNED: the cost model's predicted cost (abstract units) of the
      * blocks that may take a per-block plan, under the heuristic plan and
      * under the plans it chose, summed over key partitions.  A partition
-     * whose predicted saving is under 3% runs the heuristic plan throughout
+     * whose predicted saving is under the context's minimum
+     * (hb_set_learned_min_saving) runs the heuristic plan throughout
      * (its blocks count as fallback). */
     double predicted_heuristic;
     double predicted_chosen;

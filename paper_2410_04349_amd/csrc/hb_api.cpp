@@ -256,17 +256,15 @@ static GramIndex& gram_index(Ctx* c, Relation& rel, uint32_t attr, uint32_t q) {
     g.codes.alloc(c, sizeof(uint32_t) * (rel.cols[attr].bytes.size() + 1));
     g.cnt.alloc(c, sizeof(uint32_t) * n);
     g.flags.alloc(c, n);
-    c->timed("gram_build", [&] {
-        return launch_gram_build(dcol, n, q, g.off.as<uint64_t>(), g.codes.as<uint32_t>(), g.cnt.as<uint32_t>(),
-                                 g.flags.as<uint8_t>(), max_windows, c->stream);
-    }, 16.0 * nr + T + 4.0 * W + 5.0 * (double)n);
-    g.max_cnt = max_windows;
     // long rows get a 256-bit signature: with ~100 codes a 64-bit one is
     // mostly ones and the Jaccard filter bound barely prunes
     g.sig_words = max_windows > 64 ? kLongSigWords : 1;
     g.sig.alloc(c, sizeof(uint64_t) * n * g.sig_words);
-    c->timed("gram_sig", [&] { return launch_gram_sig(g.dev(), n, g.sig.as<uint64_t>(), c->stream); },
-             12.0 * (double)n + 4.0 * W + 8.0 * g.sig_words * (double)n);
+    c->timed("gram_build", [&] {
+        return launch_gram_build(dcol, n, q, g.off.as<uint64_t>(), g.codes.as<uint32_t>(), g.cnt.as<uint32_t>(),
+                                 g.flags.as<uint8_t>(), g.sig.as<uint64_t>(), max_windows, c->stream);
+    }, 16.0 * nr + T + 4.0 * W + 5.0 * (double)n + 8.0 * g.sig_words * (double)n);
+    g.max_cnt = max_windows;
     auto res = rel.grams.emplace(key, std::move(g));
     return res.first->second;
 }
@@ -1001,9 +999,28 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     // two offsets and the character signature, per q-gram column count,
     // flag and signature words; writes: every feature column
     const double nvp = (double)P.n_valid;
-    const double gather_in = nvp * (4.0 + 8.0 * m.n_int + 24.0 * m.n_str + 5.0 * m.n_gram + 8.0 * gram_cols);
+    const double per_row_in = 8.0 * m.n_int + 24.0 * m.n_str + 5.0 * m.n_gram + 8.0 * gram_cols;
     const double feat_bytes = (double)stride * (8.0 * n64 + 4.0 * n32);
-    c->timed("gather", [&] { return launch_gather_features(gp, c->stream); }, gather_in + feat_bytes);
+    gp.n64 = n64;
+    gp.n32 = n32;
+    if (c->arena) {
+        // allocation-free: one pass, each column read at the permuted rows
+        c->timed("gather", [&] { return launch_gather_features(gp, c->stream); },
+                 nvp * (4.0 + per_row_in) + feat_bytes);
+    } else {
+        // two passes: a read of one feature at a random row moves a whole
+        // cache line for 4-8 useful bytes; packed into row records first
+        // (sequential reads), the permuted reads move whole records
+        gp.n_rows = rel.n_rows;
+        gp.rec_words = (uint32_t)align_up(2 * n64 + n32 - 1, 4);
+        DevBuf rec(c, sizeof(uint32_t) * (size_t)gp.rec_words * std::max<uint32_t>(rel.n_rows, 1));
+        gp.rec = rec.as<uint32_t>();
+        const double rec_bytes = 4.0 * gp.rec_words;
+        c->timed("gather", [&] { return launch_pack_records(gp, c->stream); },
+                 (double)rel.n_rows * (per_row_in + rec_bytes));
+        c->timed("gather", [&] { return launch_gather_records(gp, c->stream); },
+                 nvp * (4.0 + rec_bytes) + feat_bytes);
+    }
     kp.feat_bytes = feat_bytes;
 
     // LDS of the one-wave workgroup: the pattern-match table, the
@@ -1162,16 +1179,18 @@ static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyP
     zero(c, cost.get(), cost.size());
     C.cost = cost.as<float>();
     c->timed("plan_choice", [&] { return launch_plan_choice(C, c->stream); });
-    // per-block plans only pay when the model expects them to save at least
-    // 3% of the partition's cost: each distinct plan is fetched through the
-    // scalar cache, so near-equal plans run slower than one shared plan;
-    // otherwise every block runs the heuristic plan (slot 0)
+    // per-block plans are kept only when the model expects them to save at
+    // least a quarter of the partition's cost; otherwise every block runs
+    // the heuristic plan (slot 0).  Each distinct plan is fetched through
+    // the scalar cache, which one shared plan does not miss, and predicted
+    // savings of 11-20% on the two-key recipes measured 1-3% slower
+    // kernels, so smaller predicted savings are not trusted
     float pc[2];
     HB_HIP(hipMemcpyAsync(pc, cost.get(), sizeof(pc), hipMemcpyDeviceToHost, c->stream));
     c->sync();
     kp.predicted[0] = pc[0];
     kp.predicted[1] = pc[1];
-    if (!(pc[1] < 0.97f * pc[0])) {
+    if (c->learned_min_saving > 0.f && !(pc[1] < (1.f - c->learned_min_saving) * pc[0])) {
         kp.mp.blk_slot = nullptr;
         kp.discarded = true;
     }
@@ -1651,6 +1670,14 @@ hb_status hb_set_rows_per_wave(hb_ctx* ctx, uint32_t rows) {
         if (rows != 16 && rows != 32 && rows != 64) hb::fail(HB_ERR_INVALID_ARG, "rows per wave batch must be 16, 32 or 64");
         c->rows_per_wave = rows;
         for (auto& it : c->rulesets) it.second->has_result = false;   // a later hb_match evaluates again
+    });
+}
+
+hb_status hb_set_learned_min_saving(hb_ctx* ctx, float min_saving) {
+    return guard(ctx, [&](Ctx* c) {
+        if (!(min_saving >= 0.f && min_saving < 1.f)) hb::fail(HB_ERR_INVALID_ARG, "the minimum saving must be in [0, 1)");
+        c->learned_min_saving = min_saving;
+        for (auto& it : c->rulesets) it.second->has_result = false;
     });
 }
 

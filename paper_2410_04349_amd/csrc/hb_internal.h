@@ -192,6 +192,13 @@ struct GatherParams {
     uint32_t gram_words[kMaxGramRes], gram_col[kMaxGramRes];
     uint64_t* f64;
     uint32_t* f32;
+    // row records (the two-pass gather): n_rows records of rec_words u32
+    // words each, in row order: the row's f64 features (two words each,
+    // in column order), then its f32 features from column 1 on (validity
+    // mask, lengths, q-gram counts, filter words), zero-padded to a
+    // multiple of four words
+    uint32_t* rec;
+    uint32_t n_rows, rec_words, n64, n32;
 };
 
 // ---------------------------------------------------------------- launches
@@ -252,16 +259,23 @@ hipError_t launch_ge2_flags(const uint32_t* gstart, uint32_t n_groups, uint32_t 
 hipError_t launch_gram_slots(const ColDev* col, uint32_t n, uint32_t q, uint64_t* slots,
                              hipStream_t s);
 // max_windows: the largest L - q + 1 of the column (<= 4096; picks the
-// sort: registers up to 64 windows, a wave's LDS beyond)
+// sort: registers up to 64 windows, a wave's LDS beyond).  Also writes each
+// row's q-gram signature (bit mix64(code) mod 64 W set for every distinct
+// code): W = 1 word per row up to 64 windows, kLongSigWords beyond.
 hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const uint64_t* off,
-                             uint32_t* codes, uint32_t* cnt, uint8_t* flags, uint32_t max_windows, hipStream_t s);
+                             uint32_t* codes, uint32_t* cnt, uint8_t* flags, uint64_t* sig, uint32_t max_windows,
+                             hipStream_t s);
 
 // character-presence signature of every string of a column
 hipError_t launch_char_sig(const ColDev* col, uint32_t n, uint64_t* sig, hipStream_t s);
-// q-gram signature of every row of a gram index
-hipError_t launch_gram_sig(const GramDev& g, uint32_t n, uint64_t* sig, hipStream_t s);
-// block-major feature columns
+// block-major feature columns, read column by column at the permuted rows
+// (no temporary; for allocation-free calls)
 hipError_t launch_gather_features(const GatherParams& p, hipStream_t s);
+// the same columns in two passes: each row's features packed into its
+// record in row order (sequential reads), then whole records moved to the
+// permuted positions and split into columns (p.rec holds the records)
+hipError_t launch_pack_records(const GatherParams& p, hipStream_t s);
+hipError_t launch_gather_records(const GatherParams& p, hipStream_t s);
 
 // LSH bucket histogram of one predicate (op, q, d) over column `col`
 hipError_t launch_lsh_hist(const ColDev* col, uint32_t n, int op, uint32_t q, int64_t d,

@@ -1387,22 +1387,25 @@ __device__ inline float step_cost(float c, float s, const BatchShape& b) {
     if (s <= 0.f) return 0.f;
     const float any = s >= 1.f ? 1.f : 1.f - __expf(b.rows * b.lanes * __logf(1.f - s));
     const int T = b.sparse;
-    float F[kMaxSparseRows + 1];
+    // F_m = P(X <= m) and A_m = F_m^lanes, accumulated in one pass (no
+    // array): sum_{m<T} (A_T - A_m) = T A_T - sum_{m<T} A_m
+    auto A = [&](float F) { return F <= 0.f ? 0.f : F >= 1.f ? 1.f : __expf(b.lanes * __logf(F)); };
+    float sum_a = 0.f, at;
     if (s >= 1.f) {
-        for (int m = 0; m <= T; ++m) F[m] = (float)m >= b.rows ? 1.f : 0.f;
+        for (int m = 0; m < T; ++m) sum_a += (float)m >= b.rows ? 1.f : 0.f;
+        at = (float)T >= b.rows ? 1.f : 0.f;
     } else {
         const float q = 1.f - s;
         float pm = __expf(b.rows * __logf(q));   // P(X = 0)
-        F[0] = pm;
+        float F = pm;
         for (int m = 1; m <= T; ++m) {
+            sum_a += A(F);   // A_{m-1}
             pm = (float)m <= b.rows ? pm * (b.rows - (float)(m - 1)) / (float)m * (s / q) : 0.f;
-            F[m] = fminf(1.f, F[m - 1] + pm);
+            F = fminf(1.f, F + pm);
         }
+        at = A(F);
     }
-    auto A = [&](int m) { return F[m] <= 0.f ? 0.f : F[m] >= 1.f ? 1.f : __expf(b.lanes * __logf(F[m])); };
-    const float at = A(T);
-    float rounds = 0.f;
-    for (int m = 0; m < T; ++m) rounds += at - A(m);
+    const float rounds = (float)T * at - sum_a;
     return kStepFixed * any + c * (b.rows * (1.f - at) + kSparseRound * rounds);
 }
 
@@ -1500,9 +1503,10 @@ __device__ inline void write_plan(const PlanChoiceParams& C, uint32_t x, const B
 // One thread per block: for every rule, the first-stage order of
 // rule_choice (exact checks keep the heuristic's order).  Writes the
 // block's plan slot.
-__global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
+__global__ __launch_bounds__(64) void k_plan_choice(const PlanChoiceParams C) {
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     bool learned = false, overflow = false, wrote = false;
+    float cost_h = 0.f, cost_c = 0.f;   // this block's predicted cost under either plan
     if (g < C.n_blocks) {
         const uint32_t b = C.blocks[g];
         const BatchShape batch = batch_shape(C.blk_size[b], C.rows, C.sparse_rows);
@@ -1526,8 +1530,8 @@ __global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
         // wave batches (its pairs over the pairs of a batch)
         const float nbf = (float)C.blk_size[b];
         const float w = 0.5f * nbf * (nbf - 1.f) / (batch.rows * batch.lanes);
-        atomicAdd(&C.cost[0], w * heur);
-        atomicAdd(&C.cost[1], w * chosen);
+        cost_h = w * heur;
+        cost_c = w * chosen;
         uint32_t slot = 0;
         if (learned) {
             const unsigned long long key = h ? h : 1ull;
@@ -1556,6 +1560,15 @@ __global__ __launch_bounds__(256) void k_plan_choice(const PlanChoiceParams C) {
             learned = slot != 0;
         }
         C.blk_slot[b] = slot;
+    }
+    // one atomic per wave for the partition's totals
+    for (int o = 32; o > 0; o >>= 1) {
+        cost_h += __shfl_xor(cost_h, o);
+        cost_c += __shfl_xor(cost_c, o);
+    }
+    if ((threadIdx.x & 63) == 0 && (cost_h != 0.f || cost_c != 0.f)) {
+        atomicAdd(&C.cost[0], cost_h);
+        atomicAdd(&C.cost[1], cost_c);
     }
     const uint64_t nl = __popcll(__ballot(learned)), no = __popcll(__ballot(overflow));
     const uint64_t nw = __popcll(__ballot(wrote));
@@ -1735,7 +1748,9 @@ hipError_t launch_block_features(const LearnParams& p, hipStream_t s) {
 
 hipError_t launch_plan_choice(const PlanChoiceParams& p, hipStream_t s) {
     if (p.n_blocks == 0) return hipSuccess;
-    k_plan_choice<<<(p.n_blocks + 255) / 256, 256, 0, s>>>(p);
+    // one wave per 64 blocks: a thread's work is long and serial, so the
+    // blocks are spread over as many compute units as they fill
+    k_plan_choice<<<(p.n_blocks + 63) / 64, 64, 0, s>>>(p);
     return hipGetLastError();
 }
 

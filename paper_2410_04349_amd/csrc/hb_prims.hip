@@ -389,19 +389,25 @@ __global__ void k_gram_slots(const ColDev* __restrict__ colp, uint32_t n, uint32
     slots[r] = s;
 }
 
+// The signature bit of a q-gram code: bit (mix64(code) mod 64 W) of the
+// row's W-word signature.
+__device__ __forceinline__ uint32_t sig_bit(uint32_t code, uint32_t bits) { return (uint32_t)(mix64(code) & bits); }
+
 // Rows of at most N windows (N a power of two <= 64): one thread per row
 // holds its window codes in registers, padded with the largest code, sorts
 // them with a bitonic network whose indices are all compile-time (so the
-// keys never leave registers), and writes the distinct codes.  The pad
-// value can equal a real q = 4 code; the first nw sorted keys are still the
-// row's multiset because no pad is smaller than a real code.
+// keys never leave registers), and writes the distinct codes and the
+// row's one-word signature (a bit per distinct code).  The pad value can
+// equal a real q = 4 code; the first nw sorted keys are still the row's
+// multiset because no pad is smaller than a real code.
 template <int N>
 __global__ __launch_bounds__(256) void k_gram_build_reg(const ColDev* __restrict__ colp, uint32_t n, uint32_t q,
                                                         const uint64_t* __restrict__ off,
                                                         uint32_t* __restrict__ codes, uint32_t* __restrict__ cnt,
-                                                        uint8_t* __restrict__ flags) {
+                                                        uint8_t* __restrict__ flags, uint64_t* __restrict__ sig) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t out_cnt = 0;
+    uint64_t m = 0;
     if (r < n) {
         const ColDev c = *colp;
         uint8_t f = 0;
@@ -413,6 +419,7 @@ __global__ __launch_bounds__(256) void k_gram_build_reg(const ColDev* __restrict
                 uint32_t v = 0;
                 for (uint32_t x = 0; x < L; ++x) v = (v << 8) | s[x];
                 dst[0] = (L << 24) | v;
+                m = 1ull << sig_bit((L << 24) | v, 63u);
                 out_cnt = 1;
                 f = 1;
             } else if (L >= q) {
@@ -470,6 +477,7 @@ __global__ __launch_bounds__(256) void k_gram_build_reg(const ColDev* __restrict
                 for (int w = 0; w < N; ++w) {
                     if ((uint32_t)w < nw && (w == 0 || k[w] != k[w - 1])) {
                         dst[u] = k[w];
+                        m |= 1ull << sig_bit(k[w], 63u);
                         ++u;
                     }
                 }
@@ -478,6 +486,7 @@ __global__ __launch_bounds__(256) void k_gram_build_reg(const ColDev* __restrict
         }
         cnt[r] = out_cnt;
         flags[r] = f;
+        sig[r] = m;
     }
 }
 
@@ -490,19 +499,24 @@ __device__ inline void wave_lds_sync() {
 // Long rows: one wave per row.  The row's window codes go to the wave's LDS
 // buffer of `cap` words (a power of two >= the longest row's window count),
 // padded with the largest code, are bitonic-sorted by the 64 lanes, and
-// the distinct values are compacted out with a ballot per 64 entries.
+// the distinct values are compacted out with a ballot per 64 entries; each
+// lane sets the signature bits of the codes it kept (kLongSigWords words)
+// and the wave ORs them together.
 __global__ __launch_bounds__(256) void k_gram_build_wave(const ColDev* __restrict__ colp, uint32_t n, uint32_t q,
                                                          const uint64_t* __restrict__ off,
                                                          uint32_t* __restrict__ codes, uint32_t* __restrict__ cnt,
-                                                         uint8_t* __restrict__ flags, uint32_t cap) {
+                                                         uint8_t* __restrict__ flags, uint32_t cap,
+                                                         uint64_t* __restrict__ sig) {
     extern __shared__ uint32_t gram_lds[];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t* buf = gram_lds + (size_t)wave * cap;
     const ColDev c = *colp;
     const uint32_t mask = (q == 4) ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
+    constexpr uint32_t kBits = 64u * kLongSigWords - 1u;
     for (uint32_t r = blockIdx.x * 4 + wave; r < n; r += gridDim.x * 4) {
         uint32_t out_cnt = 0;
         uint8_t f = 0;
+        uint64_t m[kLongSigWords] = {0, 0, 0, 0};
         if (bit_valid(c.valid, r)) {
             const uint8_t* sp = c.bytes + c.off[r];
             const uint32_t L = str_len(c, r);
@@ -512,6 +526,9 @@ __global__ __launch_bounds__(256) void k_gram_build_wave(const ColDev* __restric
                     uint32_t v = 0;
                     for (uint32_t x = 0; x < L; ++x) v = (v << 8) | sp[x];
                     dst[0] = (L << 24) | v;
+                    const uint32_t b = sig_bit((L << 24) | v, kBits);
+#pragma unroll
+                    for (uint32_t w = 0; w < kLongSigWords; ++w) m[w] |= (b >> 6) == w ? 1ull << (b & 63) : 0ull;
                 }
                 out_cnt = 1;
                 f = 1;
@@ -550,15 +567,30 @@ __global__ __launch_bounds__(256) void k_gram_build_wave(const ColDev* __restric
                     const bool keep = i < nw && (i == 0 || buf[i - 1] != x);
                     const uint64_t b = __ballot(keep);
                     const uint32_t rank = (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
-                    if (keep) dst[out_cnt + rank] = x;
+                    if (keep) {
+                        dst[out_cnt + rank] = x;
+                        const uint32_t sb = sig_bit(x, kBits);
+#pragma unroll
+                        for (uint32_t w = 0; w < kLongSigWords; ++w) m[w] |= (sb >> 6) == w ? 1ull << (sb & 63) : 0ull;
+                    }
                     out_cnt += (uint32_t)__popcll(b);
                 }
                 wave_lds_sync();   // the buffer is reused by the next row
             }
         }
+        // the wave's signature: OR over the lanes
+#pragma unroll
+        for (uint32_t w = 0; w < kLongSigWords; ++w)
+            for (int o = 32; o > 0; o >>= 1) m[w] |= __shfl_xor(m[w], o);
         if (lane == 0) {
             cnt[r] = out_cnt;
             flags[r] = f;
+        }
+        if (lane < kLongSigWords) {
+            uint64_t v = m[0];
+#pragma unroll
+            for (uint32_t w = 1; w < kLongSigWords; ++w) v = lane == w ? m[w] : v;
+            sig[(size_t)r * kLongSigWords + lane] = v;
         }
     }
 }
@@ -591,28 +623,6 @@ __global__ void k_char_sig(const ColDev* __restrict__ colp, uint32_t n, uint64_t
 // bit (hash(code) mod 64 W) of a W-word signature for every distinct q-gram
 // code of the row: a gram in A whose bit is absent from sig_B is not in B,
 // so |A & B| <= |A| - |sig_A \ sig_B|
-__global__ void k_gram_sig(const GramDev g, uint32_t n, uint64_t* __restrict__ sig) {
-    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const uint32_t* codes = g.codes + g.off[r];
-    const uint32_t cnt = g.cnt[r];
-    const uint32_t W = g.sig_words, bits = 64u * W - 1u;   // W is 1 or 4: 64 W bits
-    uint64_t m[kLongSigWords] = {0, 0, 0, 0};
-    for (uint32_t x = 0; x < cnt; x += 8) {   // eight independent loads per batch
-        uint32_t v[8];
-#pragma unroll
-        for (uint32_t k = 0; k < 8; ++k) v[k] = x + k < cnt ? codes[x + k] : 0u;
-#pragma unroll
-        for (uint32_t k = 0; k < 8; ++k)
-            if (x + k < cnt) {
-                const uint32_t b = (uint32_t)(mix64(v[k]) & bits);
-#pragma unroll
-                for (uint32_t w = 0; w < kLongSigWords; ++w) m[w] |= (b >> 6) == w ? 1ull << (b & 63) : 0ull;
-            }
-    }
-    for (uint32_t w = 0; w < W; ++w) sig[(size_t)r * W + w] = m[w];
-}
-
 __global__ void k_gather_features(const GatherParams P) {
     const uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (p >= P.stride) return;
@@ -900,7 +910,8 @@ hipError_t launch_gram_slots(const ColDev* col, uint32_t n, uint32_t q, uint64_t
 }
 
 hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const uint64_t* off,
-                             uint32_t* codes, uint32_t* cnt, uint8_t* flags, uint32_t max_windows, hipStream_t s) {
+                             uint32_t* codes, uint32_t* cnt, uint8_t* flags, uint64_t* sig, uint32_t max_windows,
+                             hipStream_t s) {
     if (max_windows > 4096) return hipErrorInvalidValue;   // Jaccard attributes hold <= 4096-byte strings
     if (max_windows > 64) {
         // long rows: a wave per row, sorting in a power-of-two LDS buffer
@@ -913,19 +924,19 @@ hipError_t launch_gram_build(const ColDev* col, uint32_t n, uint32_t q, const ui
             if (e != hipSuccess) return e;
         }
         const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((n + 3) / 4, 65536));
-        k_gram_build_wave<<<grid, 256, lds, s>>>(col, n, q, off, codes, cnt, flags, cap);
+        k_gram_build_wave<<<grid, 256, lds, s>>>(col, n, q, off, codes, cnt, flags, cap, sig);
         return hipGetLastError();
     }
     // short rows: a thread per row, sorting in registers
     const uint32_t grid = std::max<uint32_t>(1, (n + 255) / 256);
     if (max_windows <= 8)
-        k_gram_build_reg<8><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags);
+        k_gram_build_reg<8><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, sig);
     else if (max_windows <= 16)
-        k_gram_build_reg<16><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags);
+        k_gram_build_reg<16><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, sig);
     else if (max_windows <= 32)
-        k_gram_build_reg<32><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags);
+        k_gram_build_reg<32><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, sig);
     else
-        k_gram_build_reg<64><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags);
+        k_gram_build_reg<64><<<grid, 256, 0, s>>>(col, n, q, off, codes, cnt, flags, sig);
     return hipGetLastError();
 }
 
@@ -935,8 +946,99 @@ hipError_t launch_char_sig(const ColDev* col, uint32_t n, uint64_t* sig, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_gram_sig(const GramDev& g, uint32_t n, uint64_t* sig, hipStream_t s) {
-    k_gram_sig<<<grid_for(n, 1u << 30), kBlock, 0, s>>>(g, n, sig);
+
+// One wave per 64 rows: each lane builds its row's record (the features
+// the column-wise gather would write at the row's position) in LDS, at an
+// odd word stride so the lanes' rows fall in distinct banks; the wave then
+// writes the 64 records out as one contiguous run of full cache lines.
+__global__ __launch_bounds__(64) void k_pack_records(const GatherParams P) {
+    extern __shared__ uint32_t rec_lds[];
+    const uint32_t lane = threadIdx.x, row0 = blockIdx.x * 64u, row = row0 + lane;
+    const uint32_t RW = P.rec_words, RWp = RW + 1;
+    uint32_t* rec = rec_lds + lane * RWp;
+    if (row < P.n_rows) {
+        uint32_t vmask = 0;
+        for (uint32_t x = 0; x < P.n_int; ++x) vmask |= (bit_valid(P.int_valid[x], row) ? 1u : 0u) << x;
+        for (uint32_t x = 0; x < P.n_str; ++x) vmask |= (bit_valid(P.str_valid[x], row) ? 1u : 0u) << (16 + x);
+        for (uint32_t x = 0; x < P.n_gram; ++x) vmask |= (bit_valid(P.gram_valid[x], row) ? 1u : 0u) << (24 + x);
+        auto put64 = [&](uint32_t col, uint64_t v) {
+            rec[2 * col] = (uint32_t)v;
+            rec[2 * col + 1] = (uint32_t)(v >> 32);
+        };
+        uint32_t* r32 = rec + 2 * P.n64 - 1;   // f32 column k at r32[k], k >= 1
+        r32[1] = vmask;
+        for (uint32_t x = 0; x < P.n_int; ++x) {
+            const bool v = (vmask >> x) & 1;
+            put64(x, v ? (uint64_t)P.int_vals[x][row] : 0ull);
+        }
+        for (uint32_t x = 0; x < P.n_str; ++x) {
+            const bool v = (vmask >> (16 + x)) & 1;
+            put64(P.n_int + x, v ? P.csig[x][row] : 0ull);
+            r32[2 + x] = v ? (uint32_t)(P.str_off[x][row + 1] - P.str_off[x][row]) : 0u;
+        }
+        for (uint32_t x = 0; x < P.n_gram; ++x) {
+            const bool v = (vmask >> (24 + x)) & 1;
+            const uint32_t W = P.gram_words[x];
+            uint32_t pop = 0;
+            for (uint32_t w = 0; w < W; ++w) {
+                const uint64_t sig = v ? P.gsig[x][(size_t)row * W + w] : 0ull;
+                put64(P.n_int + P.n_str + P.gram_col[x] + w, sig);
+                pop += (uint32_t)__popcll(sig);
+            }
+            const uint32_t cnt = v ? P.gram_cnt[x][row] : 0u;
+            r32[2 + P.n_str + x] = v ? (cnt | ((uint32_t)(P.gram_flags[x][row] & 1) << 31)) : 0u;
+            // the Jaccard-filter word: 1 marks a missing value
+            r32[2 + P.n_str + P.n_gram + x] = v ? ((cnt - pop) << 16) | cnt : 1u;
+        }
+        for (uint32_t w = 2 * P.n64 + P.n32 - 1; w < RW; ++w) rec[w] = 0u;
+    }
+    __syncthreads();
+    const uint32_t rows_here = min(64u, P.n_rows - row0);
+    uint32_t* dst = P.rec + (size_t)row0 * RW;
+    for (uint32_t q = 0; q < rows_here; ++q)
+        for (uint32_t w = lane; w < RW; w += 64) dst[(size_t)q * RW + w] = rec_lds[q * RWp + w];
+}
+
+// One wave per 64 positions: the wave reads the 64 permuted rows' records
+// one record per step (a contiguous run, lane w taking word w) into LDS;
+// each lane then splits its position's record into the feature columns
+// (pads: zeros, row id 0), one coalesced store per column.
+__global__ __launch_bounds__(64) void k_gather_records(const GatherParams P) {
+    extern __shared__ uint32_t rec_lds[];
+    const uint32_t lane = threadIdx.x;
+    const uint64_t p0 = (uint64_t)blockIdx.x * 64u, p = p0 + lane;
+    const uint64_t n = P.stride;
+    const uint32_t RW = P.rec_words, RWp = RW + 1;
+    const bool pad = p >= P.n;
+    const uint32_t row = pad ? 0u : P.perm[p];
+    for (uint32_t q = 0; q < 64; ++q) {
+        const uint32_t rq = __builtin_amdgcn_readlane(row, q);
+        const bool padq = p0 + q >= P.n;
+        const uint32_t* src = P.rec + (size_t)rq * RW;
+        for (uint32_t w = lane; w < RW; w += 64) rec_lds[q * RWp + w] = padq ? 0u : src[w];
+    }
+    __syncthreads();
+    if (p >= P.stride) return;
+    const uint32_t* rec = rec_lds + lane * RWp;
+    P.f32[p] = row;
+    const uint32_t w64 = 2 * P.n64, wend = w64 + P.n32 - 1;
+    for (uint32_t k = 0; 2 * k < w64; ++k) P.f64[(uint64_t)k * n + p] = ((uint64_t)rec[2 * k + 1] << 32) | rec[2 * k];
+    for (uint32_t w = w64; w < wend; ++w) P.f32[(uint64_t)(1 + w - w64) * n + p] = rec[w];
+}
+
+hipError_t launch_pack_records(const GatherParams& p, hipStream_t s) {
+    if (p.n_rows == 0) return hipSuccess;
+    const size_t lds = (size_t)64 * (p.rec_words + 1) * 4;
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    k_pack_records<<<(p.n_rows + 63) / 64, 64, lds, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_records(const GatherParams& p, hipStream_t s) {
+    if (p.n == 0) return hipSuccess;
+    const size_t lds = (size_t)64 * (p.rec_words + 1) * 4;
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    k_gather_records<<<(unsigned)((p.stride + 63) / 64), 64, lds, s>>>(p);
     return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ def hb():
 @pytest.fixture(scope="module")
 def ctx(hb):
     c = hb.hb_create(0, allocator="torch")
+    hb.hb_set_learned_min_saving(c, 0.0)   # every per-block plan kept: their parity
     assert np.isfinite(train_model(hb, c))
     yield c
     c.close()

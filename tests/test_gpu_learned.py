@@ -32,6 +32,9 @@ def hb():
 @pytest.fixture(scope="module")
 def ctx(hb):
     c = hb.hb_create(0, allocator="torch")
+    # parity of the per-block plans: every one kept, whatever its predicted
+    # saving (the gain test restores the default)
+    hb.hb_set_learned_min_saving(c, 0.0)
     yield c
     c.close()
 
@@ -144,6 +147,7 @@ def test_learned_plan_two_keys_twenty_rules(hb, ctx, trained):
     assert np.array_equal(got_l, want)
     print(f"[gpu-case] batch-ops heuristic {work_h['batch_ops']:.4e} learned {work_l['batch_ops']:.4e} "
           f"learned blocks {st_l['learned_blocks']} fallback {st_l['fallback_blocks']}", flush=True)
+    assert st_l["learned_blocks"] > 0   # per-block plans ran
 
 
 def kernel_ms(hb, ctx, rid, rs, plan, reps):
@@ -163,9 +167,11 @@ def kernel_ms(hb, ctx, rid, rs, plan, reps):
 def test_learned_plan_gain_two_keys_1m(hb, ctx, trained):
     """What the trained network gains: the match kernel's time under the
     learned plan against the heuristic plan on a 1M-tuple draw of the
-    two-key recipe (equal outputs), plans timed in alternation; the learned
-    plan must not be slower than the heuristic by more than 3%."""
+    two-key recipe (equal outputs), plans timed in alternation, under the
+    default minimum predicted saving; the learned plan must not be slower
+    than the heuristic by more than 3%."""
     print("[gpu-case] learned plan gain, two keys, 1M", flush=True)
+    hb.hb_set_learned_min_saving(ctx, 0.25)
     rel, rules = workloads.learned_10m(n=1_000_000)
     rid = hb.hb_load_relation(ctx, rel.columns, rel.n_rows)
     rs = hb.hb_compile_rules(ctx, rid, rules)
@@ -179,6 +185,7 @@ def test_learned_plan_gain_two_keys_1m(hb, ctx, trained):
         l += kernel_ms(hb, ctx, rid, rs, "learned", 1)
         h += kernel_ms(hb, ctx, rid, rs, "heuristic", 1)
     hb.hb_release_relation(ctx, rid)
+    hb.hb_set_learned_min_saving(ctx, 0.0)
     print(f"[gpu-case] match kernel heuristic {h / 6:.3f} ms, learned {l / 6:.3f} ms, "
           f"gain {h / l:.3f}x; learned blocks {st['learned_blocks']} on {st['learned_plans']} plans, "
           f"predicted cost {st['predicted_heuristic']:.4g} -> {st['predicted_chosen']:.4g}", flush=True)

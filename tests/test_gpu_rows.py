@@ -27,6 +27,7 @@ def hb():
 def ctx(hb, request):
     c = hb.hb_create(0, allocator="torch")
     hb.hb_set_rows_per_wave(c, request.param)
+    hb.hb_set_learned_min_saving(c, 0.0)   # every per-block plan kept: their parity
     c.rows = request.param
     yield c
     c.close()
@@ -124,3 +125,38 @@ def test_rows_option_refused(hb, ctx):
         with pytest.raises(hb.HbError) as e:
             hb.hb_set_rows_per_wave(ctx, bad)
         assert e.value.status == hb.HB_ERR_INVALID_ARG
+
+
+_ORACLE = {}   # oracle results shared by the parametrized cases
+
+
+def test_launch_settings_refused(hb, ctx):
+    """The per-lane threshold above 32 and a minimum saving outside [0, 1)
+    are refused; accepted values leave the result unchanged (covered by the
+    sweeps above at the defaults)."""
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_set_sparse_rows(ctx, 33)
+    assert e.value.status == hb.HB_ERR_INVALID_ARG
+    for bad in (-0.1, 1.0, float("nan")):
+        with pytest.raises(hb.HbError) as e:
+            hb.hb_set_learned_min_saving(ctx, bad)
+        assert e.value.status == hb.HB_ERR_INVALID_ARG
+    hb.hb_set_sparse_rows(ctx, 0)
+    hb.hb_set_learned_min_saving(ctx, 0.0)
+
+
+@pytest.mark.parametrize("sparse", [1, 32])
+def test_sparse_threshold_extremes(hb, ctx, sparse):
+    """The per-lane form at its extremes (one live row per lane; up to 32):
+    bit-exact against the oracle on the two-key recipe."""
+    show(ctx, f"per-lane threshold {sparse}")
+    if "two_keys_20k" not in _ORACLE:
+        rel, rules = workloads.learned_10m(n=20_000)
+        _ORACLE["two_keys_20k"] = (rel, rules, oracle.blocking(rel, rules, threads=8))
+    rel, rules, want = _ORACLE["two_keys_20k"]
+    hb.hb_set_sparse_rows(ctx, sparse)
+    try:
+        got, _ = run(hb, ctx, rel, rules, "heuristic")
+    finally:
+        hb.hb_set_sparse_rows(ctx, 0)
+    assert np.array_equal(got, want)
