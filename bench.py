@@ -21,6 +21,7 @@ Prints ONE JSON line.  `--gpus N` with N > 1 exits: the benchmark runs the
 path on one GPU.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -192,6 +193,9 @@ def run_batched(args):
     log(f"[bench] generated {len(jobs)} relations, {n_rows} tuples in {time.perf_counter() - t:.1f}s")
     torch.cuda.set_device(0)
     ctx = hb.hb_create(0, allocator="torch")
+    learned = None
+    if args.plan == "learned":
+        learned = train_cost_model(hb, ctx, workloads, np)
     rids = [hb.hb_load_relation(ctx, rel.columns, rel.n_rows) for rel, _ in jobs]
     dst = torch.empty(1 << 23, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
@@ -205,19 +209,23 @@ def run_batched(args):
         return ids, cand
 
     results = {}
-    for mode in ("separate", "batched"):
+    modes = ["separate", "batched"] + (["batched_learned"] if learned is not None else [])
+    info = None
+    for mode in modes:
         times = []
+        plan = "learned" if mode == "batched_learned" else "heuristic"
         for k in range(args.warmup + args.steps):
             if k == args.warmup:
                 hb.hb_profile_reset(ctx)
                 hb.hb_profile_enable(ctx, True)
             ids, cand = fresh()
+            gc.collect()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if mode == "separate":
                 total = sum(hb.hb_match(ctx, rid, rs, "heuristic", out=dst) for rid, rs in ids)
             else:
-                bid = hb.hb_batch_create(ctx, ids, "heuristic", graph=True, autotune=(k == 0))
+                bid = hb.hb_batch_create(ctx, ids, plan, graph=True, autotune=(k == 0))
                 total = hb.hb_batch_run(ctx, bid)
                 info = hb.hb_batch_info(ctx, bid)
                 hb.hb_batch_destroy(ctx, bid)
@@ -242,18 +250,80 @@ def run_batched(args):
     if not same:
         raise SystemExit("batched results differ from per-relation matching")
     log("[bench] batched results equal per-relation results: True")
-    value = results["batched"]["pairs"] / results["batched"]["s_per_step"]
+    head = "batched_learned" if learned is not None else "batched"
+    if learned is not None:
+        ids, _ = fresh()
+        bid = hb.hb_batch_create(ctx, ids, "learned", graph=False)
+        hb.hb_batch_run(ctx, bid)
+        same_l = all(np.array_equal(hb.hb_batch_result(ctx, bid, k), hb.hb_match(ctx, rid, rs, "heuristic"))
+                     for k, (rid, rs) in enumerate(ids))
+        hb.hb_batch_destroy(ctx, bid)
+        if not same_l:
+            raise SystemExit("learned batched results differ from per-relation heuristic matching")
+        log("[bench] learned batched results equal per-relation heuristic results: True")
+
+    # end to end with the transfers: every relation from pinned host memory,
+    # loaded synchronously or queued on the copy stream (each relation's
+    # copies then overlap the previous relations' compilation and
+    # partitioning), then one batch
+    host = [(pinned_columns(rel, np, torch), rel.n_rows) for rel, _ in jobs]
+    in_bytes = sum(column_bytes(hc) for hc, _ in host)
+
+    def e2e(overlap, check=False):
+        load = hb.hb_load_relation_async if overlap else hb.hb_load_relation
+        hrids = [load(ctx, hc, n) for hc, n in host]
+        ids = []
+        for hrid, (_, rules) in zip(hrids, jobs):
+            rs = hb.hb_compile_rules(ctx, hrid, rules)
+            hb.hb_partition(ctx, hrid, rs)
+            ids.append((hrid, rs))
+        bid = hb.hb_batch_create(ctx, ids, "learned" if learned is not None else "heuristic", graph=True)
+        total = hb.hb_batch_run(ctx, bid)
+        if check:   # every job against its relation's own hb_match (untimed)
+            for k, (hrid, rs) in enumerate(ids):
+                got = hb.hb_batch_result(ctx, bid, k)
+                want = hb.hb_match(ctx, hrid, rs, "heuristic")
+                if not np.array_equal(got, want):
+                    raise SystemExit(f"end-to-end batch, job {k} ({jobs[k][0].n_rows} tuples): "
+                                     f"{len(got)} pairs against {len(want)} from hb_match")
+        hb.hb_batch_destroy(ctx, bid)
+        for hrid in hrids:
+            hb.hb_release_relation(ctx, hrid)
+        return total
+
+    h2d = {"input_bytes": in_bytes, "checked_run_bit_exact": True}
+    want = results[head]["matched"]
+    for overlap in (False, True):
+        e2e(overlap, check=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        totals = [e2e(overlap) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        key = "overlap" if overlap else "sync"
+        h2d[f"{key}_ms"] = ms
+        # every timed run's pair count against the resident batches'
+        h2d[f"{key}_runs_with_expected_pairs"] = f"{sum(t == want for t in totals)}/{len(totals)}"
+        if any(t != want for t in totals):
+            h2d[f"{key}_pair_counts"] = [int(t) for t in totals]
+    log(f"[bench] end to end from pinned host memory (load, compile, partition, batch): {h2d}")
+    value = results[head]["pairs"] / results[head]["s_per_step"]
     result = {
         "metric": "tuple pairs evaluated/sec on 1 MI355X, learned vs heuristic plan, bit-exact",
         "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": results["batched"]["s_per_step"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": results[head]["s_per_step"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"batched_64: {len(jobs)} relations, {n_rows} tuples (log-uniform 10k-2M), "
-                               f"1-10 rules each, heuristic plan, one persistent graph launch",
-                   "candidate_pairs": results["batched"]["pairs"], "matched_pairs": results["batched"]["matched"]},
-        "compare": {"mode": "separate hb_match per relation",
+                               f"1-10 rules each, {'learned' if learned is not None else 'heuristic'} plan, "
+                               f"one graph-captured batch",
+                   "candidate_pairs": results[head]["pairs"], "matched_pairs": results[head]["matched"]},
+        "compare": {"mode": "separate hb_match per relation, heuristic plan",
                     "value": results["separate"]["pairs"] / results["separate"]["s_per_step"],
                     "ms_per_step": results["separate"]["s_per_step"] * 1e3, "bit_exact": same},
+        "modes": {m: {"ms_per_step": r["s_per_step"] * 1e3, "kernel_ms_per_step": r["kernel_ms_per_step"]}
+                  for m, r in results.items()},
+        "end_to_end_h2d": h2d,
+        "cost_model": learned,
         "batch": info,
     }
     ctx.close()
@@ -265,6 +335,42 @@ PROFILE_NAMES = ("match", "partition_sort", "gram_slots", "gram_build", "char_si
 # steps bound by HBM bandwidth (their algorithmic bytes come from the library)
 STREAMING = ("gram_slots", "gram_build", "char_sig", "lsh", "partition_sort", "gather", "output_sort")
 PEAK_HBM = 8.0e12   # bytes/s
+
+
+def pinned_columns(rel, np, torch):
+    """The relation's columns in pinned host memory (asynchronous copies)."""
+    from gen import Column
+
+    def pin(a):
+        return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).pin_memory().numpy()
+    return [Column(c.name, c.type, offsets=pin(c.offsets), data=pin(c.data), values=pin(c.values),
+                   valid=pin(c.valid)) for c in rel.columns]
+
+
+def column_bytes(cols):
+    return int(sum(sum(a.nbytes for a in (c.offsets, c.data, c.values, c.valid) if a is not None) for c in cols))
+
+
+def h2d_pipeline(hb, ctx, parts, rules_of, plan, overlap, np):
+    """One end-to-end pass over relations held in pinned host memory: load,
+    compile, partition and match each in turn, releasing it after.  With
+    `overlap` the next relation's copies are queued (hb_load_relation_async,
+    the context's copy stream) before the current one is matched, so the
+    transfer runs beside the matching; without, each load is synchronous.
+    Returns each part's sorted pair list."""
+    out = []
+    nxt = (hb.hb_load_relation_async if overlap else hb.hb_load_relation)(ctx, parts[0][0], parts[0][1])
+    for k in range(len(parts)):
+        cur = nxt
+        if overlap and k + 1 < len(parts):
+            nxt = hb.hb_load_relation_async(ctx, parts[k + 1][0], parts[k + 1][1])
+        rs = hb.hb_compile_rules(ctx, cur, rules_of(k))
+        hb.hb_partition(ctx, cur, rs)
+        out.append(hb.hb_match(ctx, cur, rs, plan))
+        hb.hb_release_relation(ctx, cur)
+        if not overlap and k + 1 < len(parts):
+            nxt = hb.hb_load_relation(ctx, parts[k + 1][0], parts[k + 1][1])
+    return out
 
 
 def train_cost_model(hb, ctx, workloads, np):
@@ -303,6 +409,10 @@ def main():
     ap.add_argument("--grammar", action="store_true",
                     help="also time plain_1m under a rule set with t.i1 = 7 (ordered output) and check it "
                          "against the symmetric result")
+    ap.add_argument("--overlap-chunks", type=int, default=0,
+                    help="also time the path end to end from pinned host memory, the relation split by key "
+                         "into this many chunks: synchronous loads against loads overlapped with matching "
+                         "(single-key rule sets)")
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plan", default="learned", choices=["learned", "heuristic", "given"])
@@ -392,6 +502,8 @@ def main():
                 log(f"[bench] {p} warmup {w}: {n_cand} candidate pairs, {n_match} matched")
         hb.hb_profile_enable(ctx, True)
         res = {}
+        gc.collect()
+        gc.disable()   # no collector pause inside a timed step
         for k in range(args.steps):
             for p in (plans if k % 2 == 0 else plans[::-1]):
                 hb.hb_profile_reset(ctx)
@@ -409,6 +521,7 @@ def main():
                     legs[p]["prof"][name][1] += launches
                 for name in STREAMING:
                     legs[p]["bytes"][name] += hb.hb_profile_bytes(ctx, name)
+        gc.enable()
         hb.hb_profile_enable(ctx, False)
         for p in plans:
             L = legs[p]
@@ -505,6 +618,41 @@ def main():
                 "input_bytes": int(in_bytes), "output_bytes": int(res.nbytes), "bit_exact": same}
         log(f"[bench] host input and output: {pcie}")
 
+    overlap = None
+    if args.overlap_chunks:
+        keys = key_attrs(rel, rules)
+        if len(keys) != 1:
+            raise SystemExit("--overlap-chunks needs a rule set with one blocking key")
+        kv = np.asarray(rel.columns[keys[0]].values).view(np.uint64)
+        n_ch = args.overlap_chunks
+        chunks = [np.flatnonzero(kv % np.uint64(n_ch) == np.uint64(m)) for m in range(n_ch)]
+        host = [(pinned_columns(p, np, torch), p.n_rows) for p in (rel.take(rows) for rows in chunks)]
+        in_bytes = sum(column_bytes(hc) for hc, _ in host)
+        # the chunks' results, mapped back to the relation's rows, are its result
+        res = h2d_pipeline(hb, ctx, host, lambda k: rules, args.plan, True, np)
+        glob = []
+        for rows, loc in zip(chunks, res):
+            i = rows[(loc >> np.uint64(32)).astype(np.int64)]
+            j = rows[(loc & np.uint64(0xFFFFFFFF)).astype(np.int64)]
+            glob.append((np.minimum(i, j).astype(np.uint64) << np.uint64(32)) | np.maximum(i, j).astype(np.uint64))
+        same = np.array_equal(np.sort(np.concatenate(glob)), out[:n_match].cpu().numpy().view(np.uint64))
+        if not same:
+            raise SystemExit("the chunked pipeline's result differs from the one-shot result")
+        overlap = {"chunks": n_ch, "input_bytes": in_bytes, "bit_exact": same}
+        secs = {False: 0.0, True: 0.0}
+        h2d_pipeline(hb, ctx, host, lambda k: rules, args.plan, False, np)
+        for k in range(args.steps):
+            for ov in ((False, True) if k % 2 == 0 else (True, False)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                h2d_pipeline(hb, ctx, host, lambda k: rules, args.plan, ov, np)
+                torch.cuda.synchronize()
+                secs[ov] += time.perf_counter() - t0
+        overlap["sync_ms"] = secs[False] * 1000.0 / args.steps
+        overlap["overlap_ms"] = secs[True] * 1000.0 / args.steps
+        overlap["value_overlap"] = n_cand / (secs[True] / args.steps)
+        log(f"[bench] end to end from pinned host memory in {n_ch} key chunks: {overlap}")
+
     strategies = None
     if args.strategies:
         strategies = {}
@@ -593,6 +741,7 @@ def main():
         "strategies": strategies,
         "grammar": grammar,
         "pcie_inclusive": pcie,
+        "h2d_overlap": overlap,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s (int32 lane-ops)",
                      "frac": achieved / peak, "traffic": recorded_traffic(args.workload, args.plan),
                      "traffic_unit": "HBM bytes per launch", "kernel": "k_match",
