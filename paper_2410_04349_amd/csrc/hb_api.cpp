@@ -1175,24 +1175,37 @@ static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyP
     C.code = kp.dev_code.as<Instr>();
     C.blk_slot = kp.blk_slot.as<uint32_t>();
     C.stats = kp.choice_stats.as<unsigned long long>();
-    DevBuf cost(c, 2 * sizeof(float));
-    zero(c, cost.get(), cost.size());
-    C.cost = cost.as<float>();
+    kp.choice_cost.alloc(c, 2 * sizeof(float));
+    zero(c, kp.choice_cost.get(), kp.choice_cost.size());
+    C.cost = kp.choice_cost.as<float>();
     c->timed("plan_choice", [&] { return launch_plan_choice(C, c->stream); });
-    // per-block plans are kept only when the model expects them to save at
-    // least a quarter of the partition's cost; otherwise every block runs
-    // the heuristic plan (slot 0).  Each distinct plan is fetched through
-    // the scalar cache, which one shared plan does not miss, and predicted
-    // savings of 11-20% on the two-key recipes measured 1-3% slower
-    // kernels, so smaller predicted savings are not trusted
-    float pc[2];
-    HB_HIP(hipMemcpyAsync(pc, cost.get(), sizeof(pc), hipMemcpyDeviceToHost, c->stream));
+    kp.cost_pending = true;
+}
+
+void settle_learned(Ctx* c, std::vector<KeyPlan>& kps) {
+    bool any = false;
+    for (KeyPlan& kp : kps)
+        if (kp.cost_pending) {
+            HB_HIP(hipMemcpyAsync(kp.predicted, kp.choice_cost.get(), sizeof(kp.predicted), hipMemcpyDeviceToHost,
+                                  c->stream));
+            any = true;
+        }
+    if (!any) return;
     c->sync();
-    kp.predicted[0] = pc[0];
-    kp.predicted[1] = pc[1];
-    if (c->learned_min_saving > 0.f && !(pc[1] < (1.f - c->learned_min_saving) * pc[0])) {
-        kp.mp.blk_slot = nullptr;
-        kp.discarded = true;
+    // per-block plans are kept only when the model expects them to save at
+    // least the context's minimum (a quarter by default) of the partition's
+    // cost; otherwise every block runs the heuristic plan (slot 0).  Each
+    // distinct plan is fetched through the scalar cache, which one shared
+    // plan does not miss, and predicted savings of 11-20% on the two-key
+    // recipes measured 1-3% slower kernels
+    for (KeyPlan& kp : kps) {
+        if (!kp.cost_pending) continue;
+        kp.cost_pending = false;
+        const float* pc = kp.predicted;
+        if (c->learned_min_saving > 0.f && !(pc[1] < (1.f - c->learned_min_saving) * pc[0])) {
+            kp.mp.blk_slot = nullptr;
+            kp.discarded = true;
+        }
     }
 }
 
@@ -1353,6 +1366,7 @@ static void run_match(Ctx* c, Relation& rel, RuleSet& rs, int plan, hb_work_stat
         if (!kp.own_code) total_code += kp.code.size();
         kps.push_back(std::move(kp));
     }
+    settle_learned(c, kps);
     DevBuf code(c, sizeof(Instr) * std::max<size_t>(total_code, 1));
     DevBuf counts(c, sizeof(unsigned long long) * kCountSlots);
     if (ws) zero(c, counts.get(), counts.size());

@@ -244,6 +244,7 @@ static void batch_create(Ctx* c, const hb_job* jobs, uint32_t n_jobs, int plan, 
         B->kp_job.push_back(kp_job[x]);
     }
     B->n_parts = (uint32_t)B->kps.size();
+    settle_learned(c, B->kps);   // one read-back for every learned partition
     // plans: the shared-code ones in one device buffer
     size_t total_code = 0;
     for (const KeyPlan& kp : B->kps)

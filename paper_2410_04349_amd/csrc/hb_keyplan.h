@@ -43,8 +43,15 @@ struct KeyPlan {
     bool own_code = false;
     float predicted[2] = {0.f, 0.f};   // model cost of the listed blocks: heuristic plan, chosen plans
     bool discarded = false;   // the per-block plans were not worth their fetch cost: every block runs slot 0
-    DevBuf dev_code, blk_slot, choice_stats;
+    bool cost_pending = false;   // choice_cost not yet read back (settle_learned)
+    DevBuf dev_code, blk_slot, choice_stats, choice_cost;
 };
+
+// Reads back the predicted costs of every learned key plan of `kps` (one
+// synchronisation for all) and drops the per-block plans of those whose
+// predicted saving is under the context's minimum.  Call once the key plans
+// sit where they will stay, before their match parameters are used.
+void settle_learned(Ctx* c, std::vector<KeyPlan>& kps);
 
 // The evaluation path of a plan kind (given order or the Section 4.2 plan;
 // the learned plan starts from the latter).
