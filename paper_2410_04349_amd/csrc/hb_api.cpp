@@ -547,6 +547,81 @@ static uint32_t group_rows(Ctx* c, Relation& rel, const std::vector<uint32_t>& a
     return ng;
 }
 
+// Consecutive blocks of at most kPackRows rows (in position order, lone rows
+// between them included) are packed into windows of at most kTile
+// positions, one tile each: a wave batch then serves several small blocks,
+// each pair masked to its own block, where it served one.  Returns false
+// (nothing changed) when no window would hold two blocks; otherwise
+// replaces the partition's tile table by one over the units.
+static bool pack_small_blocks(Ctx* c, Partition& P) {
+    const uint32_t nb = P.n_blocks;
+    if (nb < 2) return false;
+    // the blocks under a tile wide hold one tile each: packing pays when
+    // they are a sizeable share of the tiles (it costs a read-back of the
+    // block table), e.g. not for the 10M two-key workload's partitions,
+    // where they are 3% of the tiles
+    if ((double)(nb - P.n_big) < 0.25 * (double)P.n_tiles) return false;
+    std::vector<uint32_t> st(nb), sz(nb);
+    HB_HIP(hipMemcpyAsync(st.data(), P.blk_start.get(), sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream));
+    HB_HIP(hipMemcpyAsync(sz.data(), P.blk_size.get(), sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    std::vector<uint32_t> us, usz, ub;
+    std::vector<uint64_t> ubd;
+    uint32_t packed = 0;
+    for (uint32_t i = 0; i < nb;) {
+        uint32_t j = i + 1;
+        if (sz[i] <= kPackRows)
+            while (j < nb && sz[j] <= kPackRows && st[j] + sz[j] - st[i] <= (uint32_t)kTile) ++j;
+        if (j - i >= 2) {
+            const uint32_t span = st[j - 1] + sz[j - 1] - st[i];
+            // every position ends its block but a block's rows before its last
+            uint64_t bounds = span >= 64 ? ~0ull : (1ull << span) - 1ull;
+            for (uint32_t k = i; k < j; ++k) {
+                const uint32_t o = st[k] - st[i];
+                const uint64_t inner = ((1ull << (sz[k] - 1)) - 1ull) << o;   // sz[k] <= kPackRows < 64
+                bounds &= ~inner;
+            }
+            us.push_back(st[i]);
+            usz.push_back(span | kPackedUnit);
+            ub.push_back(~0u);
+            ubd.push_back(bounds);
+            ++packed;
+        } else {
+            us.push_back(st[i]);
+            usz.push_back(sz[i]);
+            ub.push_back(i);
+            ubd.push_back(0ull);
+            j = i + 1;
+        }
+        i = j;
+    }
+    if (packed == 0) return false;
+    const uint32_t nu = (uint32_t)us.size();
+    std::vector<uint64_t> prefix(nu + 1, 0);
+    for (uint32_t u = 0; u < nu; ++u) {
+        const uint64_t T = (usz[u] & kPackedUnit) ? 1 : ((uint64_t)(usz[u] & ~kPackedUnit) + kTile - 1) / kTile;
+        prefix[u + 1] = prefix[u] + ((usz[u] & kPackedUnit) ? 1 : T * (T + 1) / 2);
+    }
+    P.unit_start.alloc(c, sizeof(uint32_t) * nu);
+    P.unit_size.alloc(c, sizeof(uint32_t) * nu);
+    P.unit_blk.alloc(c, sizeof(uint32_t) * nu);
+    P.unit_bounds.alloc(c, sizeof(uint64_t) * nu);
+    P.tile_prefix.alloc(c, sizeof(uint64_t) * (nu + 1));
+    HB_HIP(hipMemcpyAsync(P.unit_start.get(), us.data(), sizeof(uint32_t) * nu, hipMemcpyHostToDevice, c->stream));
+    HB_HIP(hipMemcpyAsync(P.unit_size.get(), usz.data(), sizeof(uint32_t) * nu, hipMemcpyHostToDevice, c->stream));
+    HB_HIP(hipMemcpyAsync(P.unit_blk.get(), ub.data(), sizeof(uint32_t) * nu, hipMemcpyHostToDevice, c->stream));
+    HB_HIP(hipMemcpyAsync(P.unit_bounds.get(), ubd.data(), sizeof(uint64_t) * nu, hipMemcpyHostToDevice, c->stream));
+    HB_HIP(hipMemcpyAsync(P.tile_prefix.get(), prefix.data(), sizeof(uint64_t) * (nu + 1), hipMemcpyHostToDevice,
+                          c->stream));
+    P.n_units = nu;
+    P.n_packed = packed;
+    P.n_tiles = prefix[nu];
+    P.tile_blk.alloc(c, sizeof(uint32_t) * P.n_tiles);
+    HB_HIP(launch_tile_blocks(P.tile_prefix.as<uint64_t>(), nu, P.n_tiles, P.tile_blk.as<uint32_t>(), c->stream));
+    c->sync();   // the host vectors are the copies' sources
+    return true;
+}
+
 static Partition& key_partition(Ctx* c, Relation& rel, uint32_t attr) {
     auto it = rel.parts.find(attr);
     if (it != rel.parts.end()) return it->second;
@@ -606,9 +681,11 @@ static Partition& key_partition(Ctx* c, Relation& rel, uint32_t attr) {
         P.pairs = h[1];
         P.n_big = hb2[0] + hb2[1];
         if (P.n_tiles && P.n_tiles <= kMaxTiles) {   // more tiles cannot be matched in one launch
-            P.tile_blk.alloc(c, sizeof(uint32_t) * P.n_tiles);
-            HB_HIP(launch_tile_blocks(P.tile_prefix.as<uint64_t>(), P.n_blocks, P.n_tiles, P.tile_blk.as<uint32_t>(),
-                                      c->stream));
+            if (!pack_small_blocks(c, P)) {
+                P.tile_blk.alloc(c, sizeof(uint32_t) * P.n_tiles);
+                HB_HIP(launch_tile_blocks(P.tile_prefix.as<uint64_t>(), P.n_blocks, P.n_tiles,
+                                          P.tile_blk.as<uint32_t>(), c->stream));
+            }
         }
     }
     auto res = rel.parts.emplace(attr, std::move(P));
@@ -1062,6 +1139,10 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
     m.blk_size = P.blk_size.as<uint32_t>();
     m.tile_prefix = P.tile_prefix.as<uint64_t>();
     m.tile_blk = P.tile_blk.as<uint32_t>();
+    m.unit_start = P.n_units ? P.unit_start.as<uint32_t>() : nullptr;
+    m.unit_size = P.n_units ? P.unit_size.as<uint32_t>() : nullptr;
+    m.unit_blk = P.n_units ? P.unit_blk.as<uint32_t>() : nullptr;
+    m.unit_bounds = P.n_units ? P.unit_bounds.as<uint64_t>() : nullptr;
     m.n_blocks = P.n_blocks;
     m.n_tiles = P.n_tiles;
     if (m.n_tiles > kMaxTiles) fail(HB_ERR_LIMIT, "more than 2^30 - 8 tiles in one key partition");

@@ -95,9 +95,12 @@ struct Partition {
     uint32_t attr = 0, n_valid = 0, n_blocks = 0;
     uint64_t n_tiles = 0, pairs = 0;
     DevBuf perm, blk_start, blk_size, tile_prefix;
-    DevBuf tile_blk;      // block of each tile
+    DevBuf tile_blk;      // unit of each tile
     DevBuf big;           // blocks of >= kTile tuples (the ones with per-block plans)
     uint32_t n_big = 0;
+    // windows of small blocks (MatchParams::unit_*); empty: units are blocks
+    DevBuf unit_start, unit_size, unit_blk, unit_bounds;
+    uint32_t n_units = 0, n_packed = 0;
 };
 
 struct Relation {

@@ -16,6 +16,8 @@ constexpr int kRows = 16;        // i-rows per wave batch (four batches per 64-r
 // context's setting (hb_set_sparse_rows), or 0 for the default of the batch
 // size.
 constexpr int kMaxSparseRows = 32;
+constexpr uint32_t kPackRows = 32;   // blocks of at most this many rows are packed into shared windows
+constexpr uint32_t kPackedUnit = 1u << 31;   // unit_size flag of a packed window
 __host__ __device__ constexpr uint32_t sparse_rows(uint32_t setting, uint32_t rows) {
     return setting ? setting : rows >= 64 ? 16u : rows >= 32 ? 8u : 4u;
 }
@@ -131,8 +133,18 @@ struct MatchParams {
     // partition of the key: blocks of >= 2 rows
     const uint32_t* blk_start;
     const uint32_t* blk_size;
-    const uint64_t* tile_prefix;   // n_blocks + 1 entries
-    const uint32_t* tile_blk;      // block of each tile (n_tiles entries)
+    // the match's work units: blocks, or windows of consecutive small
+    // blocks packed into one tile.  With unit_start null the units are the
+    // blocks; otherwise unit u spans unit_size[u] positions from
+    // unit_start[u] (bit 31 of the size: a packed window), unit_blk[u] is
+    // its block (~0u for a window) and bit k of unit_bounds[u] marks
+    // position k of a window as the last of its block (or a lone row)
+    const uint32_t* unit_start;
+    const uint32_t* unit_size;
+    const uint32_t* unit_blk;
+    const uint64_t* unit_bounds;
+    const uint64_t* tile_prefix;   // units + 1 entries
+    const uint32_t* tile_blk;      // unit of each tile (n_tiles entries)
     uint32_t n_blocks;
     uint32_t ordered;   // 1: the rule set tells t from s (both valuations of a pair, ordered output)
     uint64_t n_tiles;

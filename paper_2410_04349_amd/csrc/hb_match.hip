@@ -324,7 +324,21 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
     const int wave = batch;
     uint32_t b, ti, tj;
     decode_tile(P, t, &b, &ti, &tj);
-    const uint32_t bstart = gmem(P.blk_start)[b], bsize = gmem(P.blk_size)[b];
+    // the tile's unit: a block, or a window of small blocks (one tile)
+    uint32_t bstart, bsize;
+    uint64_t bounds = 0;   // window: bit k set where position k ends its block
+    bool packed = false;
+    if (P.unit_start) {
+        const uint32_t u = b, us = gmem(P.unit_size)[u];
+        bstart = gmem(P.unit_start)[u];
+        packed = (us & kPackedUnit) != 0;
+        bsize = us & ~kPackedUnit;
+        b = gmem(P.unit_blk)[u];   // the block (per-block plans), ~0u for a window
+        if (packed) bounds = gmem(P.unit_bounds)[u];
+    } else {
+        bstart = gmem(P.blk_start)[b];
+        bsize = gmem(P.blk_size)[b];
+    }
     const uint32_t i0 = ti * kTile, j0 = tj * kTile;
     const uint32_t ni = min((uint32_t)kTile, bsize - i0), nj = min((uint32_t)kTile, bsize - j0);
     const bool diag = ti == tj;
@@ -362,19 +376,33 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
         uint8_t* peq = wbase + P.lds_wave_peq;
         const HB_GLOBAL Instr* __restrict__ pl = plan;
         uint32_t plen = P.plan_len;
-        if (P.blk_slot) pl = plan + (size_t)gmem(P.blk_slot)[b] * plen;
+        if (P.blk_slot && !packed) pl = plan + (size_t)gmem(P.blk_slot)[b] * plen;
 
         // bit r of a lane's masks = the pair (row r, this lane's j): lanes
         // below nj, and on a diagonal tile only j > i (lanes above r0 + r)
         const uint64_t lanes_j = nj >= 64 ? ~0ull : (1ull << nj) - 1ull;
         Mask pairs;
-        {
+        if (!packed) {
             RowPush<kR> acc;
 #pragma unroll
             for (int r = kR - 1; r >= 0; --r) {
                 const uint32_t above = r0 + (uint32_t)r + 1u;
                 const uint64_t upper = !diag ? ~0ull : above >= 64 ? 0ull : ~0ull << above;
                 acc.push(r, r < nr ? lanes_j & upper : 0ull);
+            }
+            pairs = acc.get();
+        } else {
+            // a window (one diagonal tile): row k pairs with the lanes after
+            // it up to its block's last position, the next set bit of bounds
+            RowPush<kR> acc;
+#pragma unroll
+            for (int r = kR - 1; r >= 0; --r) {
+                const uint32_t k = r0 + (uint32_t)r;
+                const uint64_t rest = k < 64 ? bounds >> k : 0ull;
+                const uint32_t end = rest ? k + 1u + (uint32_t)__builtin_ctzll(rest) : 0u;   // block end, exclusive
+                const uint64_t upper = k + 1 >= 64 ? 0ull : ~0ull << (k + 1);
+                const uint64_t below = end >= 64 ? ~0ull : (1ull << end) - 1ull;
+                acc.push(r, r < nr ? lanes_j & upper & below : 0ull);
             }
             pairs = acc.get();
         }
