@@ -283,6 +283,17 @@ hb_status hb_set_rows_per_wave(hb_ctx* ctx, uint32_t rows);
  * Values above 32: HB_ERR_INVALID_ARG. */
 hb_status hb_set_sparse_rows(hb_ctx* ctx, uint32_t max_rows);
 
+/* Work decomposition of the key partitions hb_partition builds after this
+ * call: with `on`, consecutive blocks of at most 32 rows are packed into
+ * windows of at most 64 positions, one 64 x 64 tile each, every pair masked
+ * to its own block (instead of one tile per block), where such blocks are
+ * at least a quarter of the partition's tiles.  The windows are built on
+ * the host from the block table (one read-back per partition).  Off by
+ * default: on the 5M long-title workload, whose blocks all hold at most 18
+ * rows, it cut the match kernel by 3% but the window build cost more than
+ * that.  The result is the same either way. */
+hb_status hb_set_pack_small_blocks(hb_ctx* ctx, int on);
+
 /* HB_PLAN_LEARNED keeps a key partition's per-block plans only when the
  * cost model predicts they save at least `min_saving` of the partition's
  * cost under the heuristic plan (default 0.25: distinct plans miss the

@@ -44,7 +44,7 @@ _PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC, "learned": HB_P
 EXPORTED = [
     "hb_create", "hb_destroy", "hb_last_error", "hb_version", "hb_load_relation", "hb_load_relation_async",
     "hb_release_relation",
-    "hb_compile_rules", "hb_partition", "hb_match", "hb_match_noalloc", "hb_set_rows_per_wave", "hb_set_sparse_rows", "hb_set_learned_min_saving", "hb_ruleset_estimates", "hb_ruleset_buckets",
+    "hb_compile_rules", "hb_partition", "hb_match", "hb_match_noalloc", "hb_set_rows_per_wave", "hb_set_sparse_rows", "hb_set_pack_small_blocks", "hb_set_learned_min_saving", "hb_ruleset_estimates", "hb_ruleset_buckets",
     "hb_epg_path", "hb_plan_path", "hb_profile_enable", "hb_profile_query", "hb_profile_bytes", "hb_profile_reset", "hb_last_match_stats",
     "hb_match_work", "hb_costmodel_init", "hb_costmodel_set_params", "hb_costmodel_get_params",
     "hb_costmodel_train", "hb_costmodel_predict", "hb_costmodel_trace", "hb_costmodel_adam_step",
@@ -136,6 +136,7 @@ def _load_lib():
         "hb_match_noalloc": (I32, [P, U32, U32, I32, P, U64, ctypes.POINTER(U64)]),
         "hb_set_rows_per_wave": (I32, [P, U32]),
         "hb_set_sparse_rows": (I32, [P, U32]),
+        "hb_set_pack_small_blocks": (I32, [P, ctypes.c_int]),
         "hb_set_learned_min_saving": (I32, [P, ctypes.c_float]),
         "hb_ruleset_estimates": (I32, [P, U32, P, P, U32, ctypes.POINTER(U32)]),
         "hb_ruleset_buckets": (I32, [P, U32, U32, P, ctypes.POINTER(U64)]),
@@ -362,6 +363,10 @@ def hb_match_noalloc(ctx: Context, rel_id: int, ruleset_id: int, plan, out, capa
 
 def hb_set_rows_per_wave(ctx: Context, rows: int) -> None:
     ctx.check(_lib.hb_set_rows_per_wave(ctx.h, rows))
+
+
+def hb_set_pack_small_blocks(ctx: Context, on: bool) -> None:
+    ctx.check(_lib.hb_set_pack_small_blocks(ctx.h, int(on)))
 
 
 def hb_set_sparse_rows(ctx: Context, max_rows: int) -> None:

@@ -555,11 +555,9 @@ static uint32_t group_rows(Ctx* c, Relation& rel, const std::vector<uint32_t>& a
 // replaces the partition's tile table by one over the units.
 static bool pack_small_blocks(Ctx* c, Partition& P) {
     const uint32_t nb = P.n_blocks;
-    if (nb < 2) return false;
-    // the blocks under a tile wide hold one tile each: packing pays when
-    // they are a sizeable share of the tiles (it costs a read-back of the
-    // block table), e.g. not for the 10M two-key workload's partitions,
-    // where they are 3% of the tiles
+    if (!c->pack_small_blocks || nb < 2) return false;
+    // the blocks under a tile wide hold one tile each: packing can pay only
+    // when they are a sizeable share of the tiles
     if ((double)(nb - P.n_big) < 0.25 * (double)P.n_tiles) return false;
     std::vector<uint32_t> st(nb), sz(nb);
     HB_HIP(hipMemcpyAsync(st.data(), P.blk_start.get(), sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream));
@@ -1774,6 +1772,10 @@ hb_status hb_set_learned_min_saving(hb_ctx* ctx, float min_saving) {
         c->learned_min_saving = min_saving;
         for (auto& it : c->rulesets) it.second->has_result = false;
     });
+}
+
+hb_status hb_set_pack_small_blocks(hb_ctx* ctx, int on) {
+    return guard(ctx, [&](Ctx* c) { c->pack_small_blocks = on != 0; });
 }
 
 hb_status hb_set_sparse_rows(hb_ctx* ctx, uint32_t max_rows) {

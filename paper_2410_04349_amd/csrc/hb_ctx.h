@@ -184,6 +184,7 @@ struct Ctx {
     uint32_t rows_per_wave = 64;   // i-rows per wave batch of hb_match's launches (16, 32 or 64)
     uint32_t sparse_rows = 0;      // the per-lane form's threshold (0: the default of the batch size)
     float learned_min_saving = 0.25f;   // predicted saving a key partition's per-block plans must reach
+    bool pack_small_blocks = false;     // hb_set_pack_small_blocks
     CostModel model;
     std::map<uint32_t, std::shared_ptr<Batch>> batches;
     // the last autotuned batch launch form, reused by batches created

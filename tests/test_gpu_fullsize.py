@@ -41,6 +41,7 @@ def hb():
 def ctx(hb):
     c = hb.hb_create(0, allocator="torch")
     hb.hb_set_learned_min_saving(c, 0.0)   # every per-block plan kept: their parity
+    hb.hb_set_pack_small_blocks(c, True)   # the long-title blocks packed into shared tiles
     assert np.isfinite(train_model(hb, c))
     yield c
     c.close()

@@ -1,4 +1,5 @@
-"""GPU parity of the launch shapes of hb_set_rows_per_wave (16 i-rows per
+"""GPU parity of the launch shapes of hb_set_rows_per_wave (with small
+blocks packed into shared tiles, hb_set_pack_small_blocks) (16 i-rows per
 wave batch, four batches per 64 x 64 tile; 32, two batches; 64, one batch
 with 64-bit row masks, the default, which the rest of the suite runs): bit-exact against the oracle on block
 sizes around the batch and tile edges, random small relations, patterns
@@ -28,6 +29,7 @@ def ctx(hb, request):
     c = hb.hb_create(0, allocator="torch")
     hb.hb_set_rows_per_wave(c, request.param)
     hb.hb_set_learned_min_saving(c, 0.0)   # every per-block plan kept: their parity
+    hb.hb_set_pack_small_blocks(c, True)   # small blocks packed into shared tiles: their parity
     c.rows = request.param
     yield c
     c.close()
