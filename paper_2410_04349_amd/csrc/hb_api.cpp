@@ -1039,14 +1039,21 @@ static bool prepare_key(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyPlan& 
         gp.int_valid[x] = col.valid.size() ? col.valid.as<uint8_t>() : nullptr;
         gp.int_vals[x] = col.values.as<int64_t>();
     }
-    uint32_t ed_words = 1;
     for (size_t x = 0; x < R.str_attr.size(); ++x) {
         m.str_attr[x] = R.str_attr[x];
         const Column& col = rel.cols[R.str_attr[x]];
         gp.str_valid[x] = col.valid.size() ? col.valid.as<uint8_t>() : nullptr;
         gp.str_off[x] = col.off.as<uint64_t>();
         gp.csig[x] = char_signature(c, rel, R.str_attr[x]);
-        ed_words = std::max<uint32_t>(ed_words, (rel.cols[R.str_attr[x]].max_len + 63) / 64);
+    }
+    // the pattern-match table covers the longest value an edit distance
+    // takes as its pattern (string equality compares bytes, so a long
+    // compared-only attribute does not widen it)
+    uint32_t ed_words = 1;
+    for (const PredSpec& sp : R.specs) {
+        if (sp.op != OP_ED && sp.op != OP_XED) continue;
+        ed_words = std::max<uint32_t>(ed_words, (rel.cols[R.str_attr[sp.res]].max_len + 63) / 64);
+        if (sp.op == OP_XED) ed_words = std::max<uint32_t>(ed_words, (rel.cols[R.str_attr[sp.aux]].max_len + 63) / 64);
     }
     uint32_t gram_cols = 0;   // f64 columns of the q-gram signatures
     for (size_t x = 0; x < R.gram_key.size(); ++x) {

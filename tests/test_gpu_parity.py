@@ -352,3 +352,25 @@ def test_work_counters_consistent(hb, ctx):
     # the cached result is untouched by the instrumented pass
     assert np.array_equal(hb.hb_match(ctx, rid, rs, "heuristic"), got)
     hb.hb_release_relation(ctx, rid)
+
+
+def test_long_equality_beside_short_edit_distance(hb, ctx):
+    """String equality on values of 300-600 bytes next to an edit distance
+    on a short attribute: the pattern-match table is sized by the edit
+    distance's attribute only (a compared-only attribute does not widen it,
+    nor push the partition past the LDS limit); bit-exact against the
+    oracle."""
+    show("long equality beside a short edit distance")
+    r = np.random.default_rng(31)
+    n = 3000
+    keys = r.integers(0, 60, size=n)
+    short = [bytes(r.integers(97, 100, size=int(r.integers(3, 7))).astype(np.uint8)) for _ in range(n)]
+    pool = [bytes(r.integers(97, 123, size=int(r.integers(300, 600))).astype(np.uint8)) for _ in range(40)]
+    long_ = [pool[int(v)] for v in r.integers(0, len(pool), size=n)]
+    rel = Relation([int_column("k", keys.tolist(), CATEGORICAL), string_column("s", short),
+                    string_column("l", long_)], n)
+    rules = [[Pred(EQ, 0), Pred(ED, 1, k=2), Pred(EQ, 2)]]
+    want = oracle.blocking(rel, rules, threads=8)
+    for plan in ("heuristic", "given"):
+        got, _ = run(hb, ctx, rel, rules, plan)
+        assert np.array_equal(got, want), plan
