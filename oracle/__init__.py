@@ -25,7 +25,8 @@ _SRC = os.path.join(_HERE, "hboracle.cpp")
 _LIB = os.path.join(_HERE, "libhboracle.so")
 
 _TYPES = {"string": 0, "categorical": 1, "int64": 2}
-_OPS = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3, "eq_const": 4, "eq_cross": 5, "ed_cross": 6}
+_OPS = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3, "eq_const": 4, "eq_cross": 5, "ed_cross": 6,
+        "jaccard_cross": 7}
 
 
 class _Col(ctypes.Structure):

@@ -14,8 +14,9 @@
  * over the pairs of a partition (Section 2, "Blocking").  With only
  * predicates of the forms t.A = s.A and t.A ~ s.A (a symmetric measure) the
  * two valuations of a pair agree, and each pair is listed once, as i < j.
- * A rule set with a predicate t.A = c or s.A = c, or t.A = s.B over two
- * different attributes, is "ordered": its valuations of (t_i, t_j) and
+ * A rule set with a predicate t.A = c or s.A = c, or t.A = s.B or
+ * t.A ~ s.B over two different attributes, is "ordered": its valuations of
+ * (t_i, t_j) and
  * (t_j, t_i) may differ, and Ca lists every ordered pair (i, j), i != j,
  * whose valuation has a witness.
  * evaluated naively: every rule, every predicate, in input order (the
@@ -30,7 +31,11 @@
  *     a categorical or int64 attribute); t.A = s.B iff both values are
  *     present and equal (Section 2, "Semantics": tuple relational calculus);
  *     t.A ~ s.B with edit distance iff both strings are present and the
- *     Levenshtein distance from t's A to s's B is at most k;
+ *     Levenshtein distance from t's A to s's B is at most k; t.A ~ s.B with
+ *     q-gram Jaccard iff both strings are present and the Jaccard
+ *     similarity of t's A's gram set and s's B's (the same q) is at least
+ *     num / den (Section 2, "Predicates": a similarity predicate compares
+ *     two attributes of the schema, not necessarily the same one);
  *   - a missing value fails every predicate, including missing = missing
  *     (Table 1 marks missing values; Example 3 and the Section 4 remark on
  *     (t1, t5) treat a missing value as failing equality and similarity);
@@ -63,7 +68,8 @@
 extern "C" {
 
 enum { ORA_STRING = 0, ORA_CATEGORICAL = 1, ORA_INT64 = 2 };
-enum { ORA_EQ = 0, ORA_ED = 1, ORA_JACCARD = 2, ORA_ABSDIFF = 3, ORA_CONST = 4, ORA_CROSS = 5, ORA_ED_CROSS = 6 };
+enum { ORA_EQ = 0, ORA_ED = 1, ORA_JACCARD = 2, ORA_ABSDIFF = 3, ORA_CONST = 4, ORA_CROSS = 5, ORA_ED_CROSS = 6,
+       ORA_JACCARD_CROSS = 7 };
 
 struct ora_col {
     int32_t type;
@@ -81,7 +87,7 @@ struct ora_pred {
     uint32_t num;
     uint32_t den;
     int64_t d;
-    uint32_t attr_b;  /* ORA_CROSS, ORA_ED_CROSS: the attribute B of t.A = s.B, t.A ~ s.B */
+    uint32_t attr_b;  /* ORA_CROSS, ORA_ED_CROSS, ORA_JACCARD_CROSS: the attribute B of t.A = s.B, t.A ~ s.B */
     int32_t side;     /* ORA_CONST: 0 for t.A = c, 1 for s.A = c */
     int64_t c;        /* ORA_CONST: the constant */
 };
@@ -145,16 +151,22 @@ bool jaccard_ge(uint64_t I, uint64_t U, uint32_t num, uint32_t den) {
  * function of the tuple alone, so it is built once per tuple. */
 struct GramCache {
     std::map<std::pair<uint32_t, uint32_t>, std::vector<std::set<std::string>>> sets;
+    void add(const ora_col* cols, uint64_t n, uint32_t attr, uint32_t q) {
+        auto key = std::make_pair(attr, q);
+        if (sets.count(key)) return;
+        const ora_col& c = cols[attr];
+        std::vector<std::set<std::string>> v(n);
+        for (uint64_t i = 0; i < n; ++i)
+            if (is_valid(c, i)) v[i] = qgrams(str_at(c, i), q);
+        sets.emplace(key, std::move(v));
+    }
     void build(const ora_col* cols, uint64_t n, const ora_pred* preds, size_t np) {
         for (size_t p = 0; p < np; ++p) {
-            if (preds[p].op != ORA_JACCARD) continue;
-            auto key = std::make_pair(preds[p].attr, preds[p].q);
-            if (sets.count(key)) continue;
-            const ora_col& c = cols[preds[p].attr];
-            std::vector<std::set<std::string>> v(n);
-            for (uint64_t i = 0; i < n; ++i)
-                if (is_valid(c, i)) v[i] = qgrams(str_at(c, i), preds[p].q);
-            sets.emplace(key, std::move(v));
+            if (preds[p].op == ORA_JACCARD) add(cols, n, preds[p].attr, preds[p].q);
+            if (preds[p].op == ORA_JACCARD_CROSS) {
+                add(cols, n, preds[p].attr, preds[p].q);
+                add(cols, n, preds[p].attr_b, preds[p].q);
+            }
         }
     }
 };
@@ -173,6 +185,18 @@ bool sat(const ora_col* cols, const ora_pred& p, uint64_t i, uint64_t j, const G
     if (p.op == ORA_ED_CROSS) {
         const ora_col& b = cols[p.attr_b];
         return is_valid(c, i) && is_valid(b, j) && levenshtein(str_at(c, i), str_at(b, j)) <= p.k;
+    }
+    if (p.op == ORA_JACCARD_CROSS) {   /* J(G_q(t.A), G_q(s.B)) >= num / den */
+        const ora_col& b = cols[p.attr_b];
+        if (!is_valid(c, i) || !is_valid(b, j)) return false;
+        uint64_t I, U;
+        if (gc) {
+            inter_union(gc->sets.at(std::make_pair(p.attr, p.q))[i], gc->sets.at(std::make_pair(p.attr_b, p.q))[j],
+                        &I, &U);
+        } else {
+            inter_union(qgrams(str_at(c, i), p.q), qgrams(str_at(b, j), p.q), &I, &U);
+        }
+        return jaccard_ge(I, U, p.num, p.den);
     }
     if (!is_valid(c, i) || !is_valid(c, j)) return false;
     switch (p.op) {
@@ -209,7 +233,9 @@ struct RuleSet {
 bool ordered_rules(const RuleSet& rs) {
     for (const auto& rule : rs.rules)
         for (const auto& p : rule)
-            if (p.op == ORA_CONST || ((p.op == ORA_CROSS || p.op == ORA_ED_CROSS) && p.attr != p.attr_b)) return true;
+            if (p.op == ORA_CONST ||
+                ((p.op == ORA_CROSS || p.op == ORA_ED_CROSS || p.op == ORA_JACCARD_CROSS) && p.attr != p.attr_b))
+                return true;
     return false;
 }
 

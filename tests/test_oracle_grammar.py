@@ -1,6 +1,6 @@
 """Pins of the oracle's predicates t.A = c, s.A = c, t.A = s.B and t.A ~ s.B
-under edit distance (Section 2, "Predicates" and "Semantics") and of its
-ordered listing of Ca (CPU only).
+under edit distance and under q-gram Jaccard (Section 2, "Predicates" and
+"Semantics") and of its ordered listing of Ca (CPU only).
 
 A valuation binds t to the pair's first row and s to its second; a rule set
 with a predicate that tells t from s lists every ordered pair whose valuation
@@ -12,8 +12,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gen import (CATEGORICAL, ED, ED_CROSS, EQ, EQ_CONST, EQ_CROSS, INT64, Pred, Relation, int_column,
-                 string_column)
+from gen import (CATEGORICAL, ED, ED_CROSS, EQ, EQ_CONST, EQ_CROSS, INT64, JACCARD, JACCARD_CROSS, Pred,
+                 Relation, int_column, string_column)
 
 
 def P(i, j):
@@ -87,6 +87,27 @@ def test_hand_worked_cross_edit_distance():
     assert np.array_equal(got3, pairs((0, 1), (1, 0), (2, 0), (2, 1)))
 
 
+def test_hand_worked_cross_jaccard():
+    #  row  k  x      y
+    #   0   1  abcd   bcde
+    #   1   1  bcd    abcd
+    #   2   1  xy     -
+    # 2-gram sets: x0 {ab,bc,cd}  x1 {bc,cd}  x2 {xy};  y0 {bc,cd,de}  y1 {ab,bc,cd}
+    # J(t.x, s.y):
+    #   (0,1) x0/y1 = 3/3 = 1      (1,0) x1/y0 = 2/3      (2,0) x2/y0 = 0/4
+    #   (2,1) x2/y1 = 0/4          (0,2), (1,2): y2 missing
+    rel = Relation([int_column("k", [1, 1, 1], CATEGORICAL), string_column("x", [b"abcd", b"bcd", b"xy"]),
+                    string_column("y", [b"bcde", b"abcd", None])], 3)
+    got_half = oracle.blocking(rel, [[KEY, Pred(JACCARD_CROSS, 1, attr_b=2, q=2, num=1, den=2)]])
+    assert np.array_equal(got_half, pairs((0, 1), (1, 0)))
+    got_two_thirds = oracle.blocking(rel, [[KEY, Pred(JACCARD_CROSS, 1, attr_b=2, q=2, num=2, den=3)]])
+    assert np.array_equal(got_two_thirds, pairs((0, 1), (1, 0)))
+    got_high = oracle.blocking(rel, [[KEY, Pred(JACCARD_CROSS, 1, attr_b=2, q=2, num=7, den=10)]])
+    assert np.array_equal(got_high, pairs((0, 1)))
+    got_zero = oracle.blocking(rel, [[KEY, Pred(JACCARD_CROSS, 1, attr_b=2, q=2, num=0, den=1)]])
+    assert np.array_equal(got_zero, pairs((0, 1), (1, 0), (2, 0), (2, 1)))
+
+
 def test_ordered_flag():
     assert not oracle.ordered([[KEY, Pred(EQ, 1)]])
     assert not oracle.ordered([[KEY, Pred(EQ_CROSS, 1, attr_b=1)]])
@@ -94,6 +115,8 @@ def test_ordered_flag():
     assert oracle.ordered([[KEY], [KEY, Pred(EQ_CONST, 1, side=1, c=0)]])
     assert oracle.ordered([[KEY, Pred(ED_CROSS, 1, attr_b=2, k=1)]])
     assert not oracle.ordered([[KEY, Pred(ED_CROSS, 1, attr_b=1, k=1)]])
+    assert oracle.ordered([[KEY, Pred(JACCARD_CROSS, 1, attr_b=2, q=2, num=1, den=2)]])
+    assert not oracle.ordered([[KEY, Pred(JACCARD_CROSS, 1, attr_b=1, q=2, num=1, den=2)]])
 
 
 def random_relation(seed, n=160, n_keys=6, dom=4, p_missing=0.1):
@@ -118,13 +141,13 @@ def random_relation(seed, n=160, n_keys=6, dom=4, p_missing=0.1):
 def random_rules(seed):
     """1-3 rules over the key, each with 1-3 of: a constant on t or s, a
     cross-attribute equality, a plain equality, an edit distance, an edit
-    distance across the two string attributes."""
+    distance or a q-gram Jaccard across the two string attributes."""
     r = np.random.default_rng(seed)
     rules = []
     for _ in range(int(r.integers(1, 4))):
         rule = [KEY]
         for _ in range(int(r.integers(1, 4))):
-            kind = int(r.integers(0, 5))
+            kind = int(r.integers(0, 6))
             if kind == 0:
                 rule.append(Pred(EQ_CONST, int(r.integers(1, 4)), side=int(r.integers(0, 2)), c=int(r.integers(0, 4))))
             elif kind == 1:
@@ -134,9 +157,13 @@ def random_rules(seed):
                 rule.append(Pred(EQ, int(r.integers(1, 4))))
             elif kind == 3:
                 rule.append(Pred(ED, 4, k=int(r.integers(0, 3))))
-            else:
+            elif kind == 4:
                 a = int(r.integers(4, 6))
                 rule.append(Pred(ED_CROSS, a, attr_b=9 - a, k=int(r.integers(0, 3))))
+            else:
+                a = int(r.integers(4, 6))
+                num, den = ((1, 3), (1, 2), (2, 3))[int(r.integers(0, 3))]
+                rule.append(Pred(JACCARD_CROSS, a, attr_b=9 - a, q=int(r.integers(1, 3)), num=num, den=den))
         rules.append(rule)
     return rules
 
@@ -149,6 +176,8 @@ def transpose_pred(p):
         return Pred(EQ_CROSS, p.attr_b, attr_b=p.attr)
     if p.op == ED_CROSS:   # the distance is symmetric in its two strings
         return Pred(ED_CROSS, p.attr_b, attr_b=p.attr, k=p.k)
+    if p.op == JACCARD_CROSS:   # so is the Jaccard similarity of two sets
+        return Pred(JACCARD_CROSS, p.attr_b, attr_b=p.attr, q=p.q, num=p.num, den=p.den)
     return p
 
 
@@ -177,6 +206,10 @@ def test_cross_on_one_attribute_is_equality(seed):
         for k in (0, 2):
             got = oracle.blocking(rel, [[KEY, Pred(ED_CROSS, a, attr_b=a, k=k)]])
             assert np.array_equal(got, oracle.blocking(rel, [[KEY, Pred(ED, a, k=k)]]))
+        for q, num, den in ((1, 1, 2), (2, 2, 3), (2, 0, 1)):
+            got = oracle.blocking(rel, [[KEY, Pred(JACCARD_CROSS, a, attr_b=a, q=q, num=num, den=den)]])
+            want = oracle.blocking(rel, [[KEY, Pred(JACCARD, a, q=q, num=num, den=den)]])
+            assert np.array_equal(got, want)
 
 
 @pytest.mark.parametrize("seed", range(6))
