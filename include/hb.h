@@ -130,13 +130,17 @@ hb_status hb_release_relation(hb_ctx* ctx, uint32_t rel_id);
  *   HB_EQ_CROSS    t.A = s.B: t's value of A and s's value of B (attr_b) are
  *                  both present and equal     (CATEGORICAL, INT64 for both);
  *   HB_ED_CROSS_LE t.A ~ s.B: Levenshtein distance over bytes from t's A to
- *                  s's B (attr_b) <= k            (STRING for both).
+ *                  s's B (attr_b) <= k            (STRING for both);
+ *   HB_JACCARD_CROSS_GE  t.A ~ s.B: the HB_JACCARD_GE test between t's
+ *                  q-gram set of A and s's of B (attr_b; one q)
+ *                                                 (STRING for both).
  * A missing value fails every predicate.  A rule set with an HB_EQ_CONST,
- * or an HB_EQ_CROSS or HB_ED_CROSS_LE over two different attributes, is
- * *ordered*: its two
+ * or an HB_EQ_CROSS, HB_ED_CROSS_LE or HB_JACCARD_CROSS_GE over two
+ * different attributes, is *ordered*: its two
  * valuations of a pair may differ, and hb_match lists ordered pairs (see
  * there).  HB_EQ_CROSS with attr_b = attr is an equality (unordered), but
- * never a blocking key; HB_ED_CROSS_LE with attr_b = attr is HB_ED_LE.
+ * never a blocking key; HB_ED_CROSS_LE with attr_b = attr is HB_ED_LE, and
+ * HB_JACCARD_CROSS_GE with attr_b = attr is HB_JACCARD_GE.
  * A rule (an MD X -> t.eid = s.eid, Section 2, "Rules") is a conjunction;
  * a rule set is their disjunction.  Every rule must contain an HB_EQ on a
  * CATEGORICAL or INT64 attribute: its first one (in the given order) is the
@@ -149,18 +153,19 @@ typedef enum {
     HB_ABSDIFF_LE = 3,
     HB_EQ_CONST = 4,
     HB_EQ_CROSS = 5,
-    HB_ED_CROSS_LE = 6
+    HB_ED_CROSS_LE = 6,
+    HB_JACCARD_CROSS_GE = 7
 } hb_op;
 
 typedef struct {
     int32_t op;     /* hb_op */
     uint32_t attr;  /* column index */
     int64_t k;      /* HB_ED_LE, HB_ED_CROSS_LE: 0..HB_MAX_ED_K */
-    uint32_t q;     /* HB_JACCARD_GE: 1..HB_MAX_Q */
-    uint32_t num;   /* HB_JACCARD_GE: threshold num/den, 0 <= num <= den */
-    uint32_t den;   /* HB_JACCARD_GE: den > 0, <= HB_MAX_JACCARD_DEN in lowest terms */
+    uint32_t q;     /* HB_JACCARD_GE, HB_JACCARD_CROSS_GE: 1..HB_MAX_Q */
+    uint32_t num;   /* HB_JACCARD_GE, HB_JACCARD_CROSS_GE: threshold num/den, 0 <= num <= den */
+    uint32_t den;   /* HB_JACCARD_GE, HB_JACCARD_CROSS_GE: den > 0, <= HB_MAX_JACCARD_DEN in lowest terms */
     int64_t d;      /* HB_ABSDIFF_LE: d >= 0 */
-    uint32_t attr_b;  /* HB_EQ_CROSS, HB_ED_CROSS_LE: column index of B */
+    uint32_t attr_b;  /* HB_EQ_CROSS, HB_ED_CROSS_LE, HB_JACCARD_CROSS_GE: column index of B */
     int32_t side;     /* HB_EQ_CONST: 0 = t.A = c, 1 = s.A = c */
     int64_t c;        /* HB_EQ_CONST: the constant */
 } hb_pred;

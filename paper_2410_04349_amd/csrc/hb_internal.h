@@ -85,7 +85,10 @@ enum Op : uint8_t {
     // is in `aux` once, and the rules up to the OP_ENDGUARD at `cp` start
     // from the pairs that pass it; OP_ENDGUARD returns to every pair
     OP_GUARD = 12,
-    OP_ENDGUARD = 13
+    OP_ENDGUARD = 13,
+    // q-gram Jaccard(t.A, s.B) >= num / den (ordered rule sets): res = A,
+    // aux = B (gram resources of one q), param = (num << 32) | den
+    OP_XJAC = 14
 };
 
 // One step of the sequential execution path.  `slot` identifies the step
@@ -98,7 +101,7 @@ struct Instr {
     uint8_t op;
     uint8_t slot;
     uint8_t res;
-    uint8_t aux;    // OP_CONST: side; OP_XEQ, OP_XED: resource of B
+    uint8_t aux;    // OP_CONST: side; OP_XEQ, OP_XED, OP_XJAC: resource of B
     uint16_t cp;
     uint16_t pad1;
     uint64_t param;

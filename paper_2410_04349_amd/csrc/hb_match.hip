@@ -538,6 +538,48 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                                 }
                             }
                         }
+                    } else if (op == OP_XJAC) {
+                        // Jaccard(G_q(t.A), G_q(s.B)) >= num / den, A = res, B = aux
+                        // (gram resources of one q): forward merges the row's
+                        // A list, staged in LDS, with the lane's B list,
+                        // backward the row's B with the lane's A, row by row
+                        // where some lane needs it
+                        const uint32_t num = (uint32_t)(param >> 32), den = (uint32_t)(param & 0xFFFFFFFFu);
+                        kf = 0;
+                        kb = 0;
+                        for (int r = 0; r < nr; ++r) {
+                            const uint64_t pi = pi0 + r;
+                            const uint32_t row_i = f32[pi];
+                            const uint32_t vmask_i = f32[n + pi];
+#pragma unroll 1
+                            for (int dir = 0; dir < 2; ++dir) {
+                                const uint32_t ga = dir == 0 ? res : aux;   // row side
+                                const uint32_t gb = dir == 0 ? aux : res;   // lane side
+                                const bool need = (((dir == 0 ? fwd : bwd) >> r) & 1) &&
+                                                  ((vmask_i >> (24 + ga)) & 1) && ((vmask_j >> (24 + gb)) & 1);
+                                if (!__any(need)) continue;
+                                const GramDev& g_a = P.gram[ga];
+                                const GramDev& g_b = P.gram[gb];
+                                const uint32_t ia = f32[(gram32 + ga) * n + pi];
+                                const uint32_t ca = ia & 0x7FFFFFFFu;
+                                uint32_t* ig = (uint32_t*)(wbase + P.lds_wave_igram[ga]);
+                                const uint32_t* src = g_a.codes + g_a.off[row_i];
+                                for (uint32_t x = lane; x < ca; x += 64) ig[x] = src[x];
+                                wave_sync();
+                                if (need) {
+                                    const uint32_t jb = J32(gram32 + gb);
+                                    const uint32_t cb = jb & 0x7FFFFFFFu;
+                                    const uint32_t I = intersect(ig, ca, (ia >> 31) != 0, g_b.codes + g_b.off[row_j], cb,
+                                                                 (jb >> 31) != 0);
+                                    const uint64_t U = (uint64_t)ca + cb - I;
+                                    if (U == 0 || (uint64_t)I * den >= (uint64_t)num * U) {
+                                        if (dir == 0) kf |= (Mask)1 << r;
+                                        else kb |= (Mask)1 << r;
+                                    }
+                                }
+                                wave_sync();   // the staging area is refilled for the next list
+                            }
+                        }
                     } else {   // OP_XEQ: t.A = s.B, A = res, B = aux
                         const int64_t ja = (int64_t)J64(res), jb = (int64_t)J64(aux);
                         RowPush<kR> fa, ga;

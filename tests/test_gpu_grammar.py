@@ -1,5 +1,5 @@
 """GPU parity of the predicates t.A = c, s.A = c, t.A = s.B and t.A ~ s.B
-(edit distance): libhb's ordered listing of Ca, through the C ABI, is
+(edit distance and q-gram Jaccard): libhb's ordered listing of Ca, through the C ABI, is
 bit-exact against the oracle's, for every non-learned plan, across tiles and
 their diagonals, with two keys, and with edit-distance patterns past 64
 bytes.  Calls the ordered path does not take are refused."""
@@ -7,8 +7,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gen import (CATEGORICAL, ED, ED_CROSS, EQ, EQ_CONST, EQ_CROSS, INT64, Pred, Relation, int_column,
-                 string_column)
+from gen import (CATEGORICAL, ED, ED_CROSS, EQ, EQ_CONST, EQ_CROSS, INT64, JACCARD, JACCARD_CROSS, Pred,
+                 Relation, int_column, string_column)
 from test_oracle_grammar import KEY, hand_relation, random_relation, random_rules
 
 pytestmark = pytest.mark.gpu
@@ -92,6 +92,32 @@ def test_cross_edit_distance_short_strings(hb, ctx):
         assert len(check(hb, ctx, rel, rules)) > 0
 
 
+def test_cross_jaccard(hb, ctx):
+    """Both valuations of t.A ~ s.B under q-gram Jaccard: short strings with
+    empty and missing values (random_relation), then two word-like string
+    attributes of 5-40 bytes drawn from one alphabet so that many pairs are
+    close, q = 1..3, beside a constant and a plain Jaccard."""
+    show("grammar: cross Jaccard")
+    rel = random_relation(78, n=1200, n_keys=5)
+    for rules in ([[KEY, Pred(JACCARD_CROSS, 4, attr_b=5, q=1, num=1, den=2)]],
+                  [[KEY, Pred(JACCARD_CROSS, 5, attr_b=4, q=2, num=1, den=3), Pred(EQ_CONST, 1, side=0, c=2)],
+                   [KEY, Pred(JACCARD, 4, q=1, num=2, den=3)]]):
+        assert len(check(hb, ctx, rel, rules)) > 0
+    r = np.random.default_rng(79)
+    n = 3000
+    words = [bytes(r.integers(97, 103, size=int(r.integers(3, 8))).astype(np.uint8)) for _ in range(60)]
+
+    def phrase():
+        return b" ".join(words[int(w)] for w in r.integers(0, len(words), size=int(r.integers(1, 6))))[:40]
+    a = [phrase() for _ in range(n)]
+    b = [x if r.random() < 0.3 else phrase() for x in a]
+    rel2 = Relation([int_column("k", [int(v) for v in r.integers(0, 40, size=n)], CATEGORICAL),
+                     string_column("a", a), string_column("b", b)], n)
+    for q, num, den in ((2, 1, 2), (3, 7, 10), (1, 4, 5)):
+        rules = [[Pred(EQ, 0), Pred(JACCARD_CROSS, 1, attr_b=2, q=q, num=num, den=den)]]
+        assert len(check(hb, ctx, rel2, rules, plans=["heuristic", "given"])) > 0
+
+
 def test_two_keys(hb, ctx):
     # a pair sharing both keys is evaluated in the first key's partition only
     show("grammar: two keys")
@@ -161,6 +187,8 @@ def test_refused_calls(hb, ctx):
                          ([KEY, Pred(EQ_CONST, 1, side=2, c=1)], hb.HB_ERR_INVALID_ARG),
                          ([KEY, Pred(ED_CROSS, 1, attr_b=3, k=1)], hb.HB_ERR_TYPE),     # A is an int
                          ([KEY, Pred(ED_CROSS, 3, attr_b=3, k=300)], hb.HB_ERR_INVALID_ARG),
+                         ([KEY, Pred(JACCARD_CROSS, 1, attr_b=3, q=2, num=1, den=2)], hb.HB_ERR_TYPE),
+                         ([KEY, Pred(JACCARD_CROSS, 3, attr_b=3, q=9, num=1, den=2)], hb.HB_ERR_INVALID_ARG),
                          ([Pred(EQ_CROSS, 0, attr_b=0)], hb.HB_ERR_UNBLOCKABLE)):   # never a key
         with pytest.raises(hb.HbError) as e:
             hb.hb_compile_rules(ctx, rid2, [rule])
