@@ -32,6 +32,7 @@ EQ, ED, JACCARD, ABSDIFF = "eq", "ed", "jaccard", "absdiff"
 EQ_CONST, EQ_CROSS = "eq_const", "eq_cross"   # t.A = c (side 0) / s.A = c (side 1); t.A = s.B
 ED_CROSS = "ed_cross"                           # edit distance from t.A to s.B <= k
 JACCARD_CROSS = "jaccard_cross"                 # q-gram Jaccard of t.A and s.B >= num / den
+CONTAIN = "contain"                             # share of t.A's q-grams found in s.B's >= num / den (asymmetric)
 
 
 @dataclass
@@ -145,7 +146,7 @@ class Pred:
     num: int = 0        # Jaccard threshold num/den
     den: int = 1
     d: int = 0          # ABSDIFF threshold |a-b| <= d
-    attr_b: int = 0     # EQ_CROSS, ED_CROSS, JACCARD_CROSS: the attribute B of t.A = s.B, t.A ~ s.B
+    attr_b: int = 0     # EQ_CROSS, ED_CROSS, JACCARD_CROSS, CONTAIN: the attribute B of t.A = s.B, t.A ~ s.B
     side: int = 0       # EQ_CONST: 0 for t.A = c, 1 for s.A = c
     c: int = 0          # EQ_CONST: the constant
 

@@ -26,7 +26,7 @@ _LIB = os.path.join(_HERE, "libhboracle.so")
 
 _TYPES = {"string": 0, "categorical": 1, "int64": 2}
 _OPS = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3, "eq_const": 4, "eq_cross": 5, "ed_cross": 6,
-        "jaccard_cross": 7}
+        "jaccard_cross": 7, "contain": 8}
 
 
 class _Col(ctypes.Structure):

@@ -36,6 +36,11 @@
  *     similarity of t's A's gram set and s's B's (the same q) is at least
  *     num / den (Section 2, "Predicates": a similarity predicate compares
  *     two attributes of the schema, not necessarily the same one);
+ *   - q-gram containment t.A <= s.B, the asymmetric measure of the grammar
+ *     (Section 2 allows any similarity, symmetric or asymmetric): both
+ *     strings present and |G_q(t.A) & G_q(s.B)| * den >= num * |G_q(t.A)|
+ *     (an empty t set is contained in anything); a rule set with it is
+ *     ordered even when A = B;
  *   - a missing value fails every predicate, including missing = missing
  *     (Table 1 marks missing values; Example 3 and the Section 4 remark on
  *     (t1, t5) treat a missing value as failing equality and similarity);
@@ -69,7 +74,7 @@ extern "C" {
 
 enum { ORA_STRING = 0, ORA_CATEGORICAL = 1, ORA_INT64 = 2 };
 enum { ORA_EQ = 0, ORA_ED = 1, ORA_JACCARD = 2, ORA_ABSDIFF = 3, ORA_CONST = 4, ORA_CROSS = 5, ORA_ED_CROSS = 6,
-       ORA_JACCARD_CROSS = 7 };
+       ORA_JACCARD_CROSS = 7, ORA_CONTAIN = 8 };
 
 struct ora_col {
     int32_t type;
@@ -87,7 +92,8 @@ struct ora_pred {
     uint32_t num;
     uint32_t den;
     int64_t d;
-    uint32_t attr_b;  /* ORA_CROSS, ORA_ED_CROSS, ORA_JACCARD_CROSS: the attribute B of t.A = s.B, t.A ~ s.B */
+    uint32_t attr_b;  /* ORA_CROSS, ORA_ED_CROSS, ORA_JACCARD_CROSS, ORA_CONTAIN: the attribute B of t.A = s.B,
+                         t.A ~ s.B */
     int32_t side;     /* ORA_CONST: 0 for t.A = c, 1 for s.A = c */
     int64_t c;        /* ORA_CONST: the constant */
 };
@@ -163,7 +169,7 @@ struct GramCache {
     void build(const ora_col* cols, uint64_t n, const ora_pred* preds, size_t np) {
         for (size_t p = 0; p < np; ++p) {
             if (preds[p].op == ORA_JACCARD) add(cols, n, preds[p].attr, preds[p].q);
-            if (preds[p].op == ORA_JACCARD_CROSS) {
+            if (preds[p].op == ORA_JACCARD_CROSS || preds[p].op == ORA_CONTAIN) {
                 add(cols, n, preds[p].attr, preds[p].q);
                 add(cols, n, preds[p].attr_b, preds[p].q);
             }
@@ -197,6 +203,23 @@ bool sat(const ora_col* cols, const ora_pred& p, uint64_t i, uint64_t j, const G
             inter_union(qgrams(str_at(c, i), p.q), qgrams(str_at(b, j), p.q), &I, &U);
         }
         return jaccard_ge(I, U, p.num, p.den);
+    }
+    if (p.op == ORA_CONTAIN) {   /* |G_q(t.A) & G_q(s.B)| / |G_q(t.A)| >= num / den */
+        const ora_col& b = cols[p.attr_b];
+        if (!is_valid(c, i) || !is_valid(b, j)) return false;
+        uint64_t I, U;
+        uint64_t nt;
+        if (gc) {
+            const auto& ga = gc->sets.at(std::make_pair(p.attr, p.q))[i];
+            inter_union(ga, gc->sets.at(std::make_pair(p.attr_b, p.q))[j], &I, &U);
+            nt = ga.size();
+        } else {
+            const std::set<std::string> ga = qgrams(str_at(c, i), p.q);
+            inter_union(ga, qgrams(str_at(b, j), p.q), &I, &U);
+            nt = ga.size();
+        }
+        (void)U;
+        return (unsigned __int128)I * p.den >= (unsigned __int128)p.num * nt;
     }
     if (!is_valid(c, i) || !is_valid(c, j)) return false;
     switch (p.op) {
@@ -233,7 +256,7 @@ struct RuleSet {
 bool ordered_rules(const RuleSet& rs) {
     for (const auto& rule : rs.rules)
         for (const auto& p : rule)
-            if (p.op == ORA_CONST ||
+            if (p.op == ORA_CONST || p.op == ORA_CONTAIN ||
                 ((p.op == ORA_CROSS || p.op == ORA_ED_CROSS || p.op == ORA_JACCARD_CROSS) && p.attr != p.attr_b))
                 return true;
     return false;

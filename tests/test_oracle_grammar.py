@@ -12,8 +12,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gen import (CATEGORICAL, ED, ED_CROSS, EQ, EQ_CONST, EQ_CROSS, INT64, JACCARD, JACCARD_CROSS, Pred,
-                 Relation, int_column, string_column)
+from gen import (CATEGORICAL, CONTAIN, ED, ED_CROSS, EQ, EQ_CONST, EQ_CROSS, INT64, JACCARD, JACCARD_CROSS,
+                 Pred, Relation, int_column, string_column)
 
 
 def P(i, j):
@@ -108,6 +108,40 @@ def test_hand_worked_cross_jaccard():
     assert np.array_equal(got_zero, pairs((0, 1), (1, 0), (2, 0), (2, 1)))
 
 
+def test_hand_worked_containment():
+    #  row  k  x     y
+    #   0   1  ab    abc
+    #   1   1  abc   ab
+    #   2   1  ""    bcz
+    # 2-gram sets: x0 {ab}  x1 {ab,bc}  x2 {};  y0 {ab,bc}  y1 {ab}  y2 {bc,cz}
+    # share of t.x's grams in s.y's:
+    #   (0,1) 1/1  (0,2) 0/1  (1,0) 2/2  (1,2) 1/2  (2,0) 0/0  (2,1) 0/0 (an
+    #   empty set is contained in anything)
+    rel = Relation([int_column("k", [1, 1, 1], CATEGORICAL), string_column("x", [b"ab", b"abc", b""]),
+                    string_column("y", [b"abc", b"ab", b"bcz"])], 3)
+    full = oracle.blocking(rel, [[KEY, Pred(CONTAIN, 1, attr_b=2, q=2, num=1, den=1)]])
+    assert np.array_equal(full, pairs((0, 1), (1, 0), (2, 0), (2, 1)))
+    half = oracle.blocking(rel, [[KEY, Pred(CONTAIN, 1, attr_b=2, q=2, num=1, den=2)]])
+    assert np.array_equal(half, pairs((0, 1), (1, 0), (1, 2), (2, 0), (2, 1)))
+    # on one attribute the measure stays asymmetric: x0 in x1 is 1, x1 in x0 is 1/2
+    same = oracle.blocking(rel, [[KEY, Pred(CONTAIN, 1, attr_b=1, q=2, num=1, den=1)]])
+    assert np.array_equal(same, pairs((0, 1), (2, 0), (2, 1)))
+    same_half = oracle.blocking(rel, [[KEY, Pred(CONTAIN, 1, attr_b=1, q=2, num=1, den=2)]])
+    assert np.array_equal(same_half, pairs((0, 1), (1, 0), (2, 0), (2, 1)))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_jaccard_implies_containment(seed):
+    # |A & B| / |A| >= |A & B| / |A | B|: every pair whose Jaccard reaches the
+    # threshold is contained to it, in both orders
+    rel = random_relation(400 + seed)
+    for q, num, den in ((1, 1, 2), (2, 1, 3), (2, 2, 3)):
+        jac = oracle.blocking(rel, [[KEY, Pred(JACCARD, 4, q=q, num=num, den=den)]])
+        both = set(jac.tolist()) | set(transpose_pairs(jac).tolist())
+        cont = set(oracle.blocking(rel, [[KEY, Pred(CONTAIN, 4, attr_b=4, q=q, num=num, den=den)]]).tolist())
+        assert both <= cont
+
+
 def test_ordered_flag():
     assert not oracle.ordered([[KEY, Pred(EQ, 1)]])
     assert not oracle.ordered([[KEY, Pred(EQ_CROSS, 1, attr_b=1)]])
@@ -117,6 +151,7 @@ def test_ordered_flag():
     assert not oracle.ordered([[KEY, Pred(ED_CROSS, 1, attr_b=1, k=1)]])
     assert oracle.ordered([[KEY, Pred(JACCARD_CROSS, 1, attr_b=2, q=2, num=1, den=2)]])
     assert not oracle.ordered([[KEY, Pred(JACCARD_CROSS, 1, attr_b=1, q=2, num=1, den=2)]])
+    assert oracle.ordered([[KEY, Pred(CONTAIN, 1, attr_b=1, q=2, num=1, den=2)]])   # asymmetric
 
 
 def random_relation(seed, n=160, n_keys=6, dom=4, p_missing=0.1):
