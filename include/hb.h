@@ -133,10 +133,16 @@ hb_status hb_release_relation(hb_ctx* ctx, uint32_t rel_id);
  *                  s's B (attr_b) <= k            (STRING for both);
  *   HB_JACCARD_CROSS_GE  t.A ~ s.B: the HB_JACCARD_GE test between t's
  *                  q-gram set of A and s's of B (attr_b; one q)
+ *                                                 (STRING for both);
+ *   HB_CONTAIN_GE  t.A ~ s.B, an asymmetric measure (Section 2 allows any
+ *                  similarity, symmetric or asymmetric): the share of t's
+ *                  q-grams of A found among s's of B (attr_b, which may
+ *                  equal attr), |G_q(t.A) & G_q(s.B)| * den >= num *
+ *                  |G_q(t.A)|; an empty t set is contained in anything
  *                                                 (STRING for both).
- * A missing value fails every predicate.  A rule set with an HB_EQ_CONST,
- * or an HB_EQ_CROSS, HB_ED_CROSS_LE or HB_JACCARD_CROSS_GE over two
- * different attributes, is *ordered*: its two
+ * A missing value fails every predicate.  A rule set with an HB_EQ_CONST or
+ * an HB_CONTAIN_GE, or an HB_EQ_CROSS, HB_ED_CROSS_LE or
+ * HB_JACCARD_CROSS_GE over two different attributes, is *ordered*: its two
  * valuations of a pair may differ, and hb_match lists ordered pairs (see
  * there).  HB_EQ_CROSS with attr_b = attr is an equality (unordered), but
  * never a blocking key; HB_ED_CROSS_LE with attr_b = attr is HB_ED_LE, and
@@ -154,18 +160,19 @@ typedef enum {
     HB_EQ_CONST = 4,
     HB_EQ_CROSS = 5,
     HB_ED_CROSS_LE = 6,
-    HB_JACCARD_CROSS_GE = 7
+    HB_JACCARD_CROSS_GE = 7,
+    HB_CONTAIN_GE = 8
 } hb_op;
 
 typedef struct {
     int32_t op;     /* hb_op */
     uint32_t attr;  /* column index */
     int64_t k;      /* HB_ED_LE, HB_ED_CROSS_LE: 0..HB_MAX_ED_K */
-    uint32_t q;     /* HB_JACCARD_GE, HB_JACCARD_CROSS_GE: 1..HB_MAX_Q */
-    uint32_t num;   /* HB_JACCARD_GE, HB_JACCARD_CROSS_GE: threshold num/den, 0 <= num <= den */
-    uint32_t den;   /* HB_JACCARD_GE, HB_JACCARD_CROSS_GE: den > 0, <= HB_MAX_JACCARD_DEN in lowest terms */
+    uint32_t q;     /* HB_JACCARD_GE, HB_JACCARD_CROSS_GE, HB_CONTAIN_GE: 1..HB_MAX_Q */
+    uint32_t num;   /* the same three: threshold num/den, 0 <= num <= den */
+    uint32_t den;   /* the same three: den > 0, <= HB_MAX_JACCARD_DEN in lowest terms */
     int64_t d;      /* HB_ABSDIFF_LE: d >= 0 */
-    uint32_t attr_b;  /* HB_EQ_CROSS, HB_ED_CROSS_LE, HB_JACCARD_CROSS_GE: column index of B */
+    uint32_t attr_b;  /* HB_EQ_CROSS, HB_ED_CROSS_LE, HB_JACCARD_CROSS_GE, HB_CONTAIN_GE: column index of B */
     int32_t side;     /* HB_EQ_CONST: 0 = t.A = c, 1 = s.A = c */
     int64_t c;        /* HB_EQ_CONST: the constant */
 } hb_pred;

@@ -36,7 +36,7 @@ HB_PLAN_LEARNED = 2
 
 _COLTYPE = {"string": 0, "categorical": 1, "int64": 2}
 _OP = {"eq": 0, "ed": 1, "jaccard": 2, "absdiff": 3, "eq_const": 4, "eq_cross": 5, "ed_cross": 6,
-       "jaccard_cross": 7}
+       "jaccard_cross": 7, "contain": 8}
 HB_PLAN_CHEAPEST, HB_PLAN_SELECTIVE, HB_PLAN_RANDOM_PREDS, HB_PLAN_RANDOM_RULES = 3, 4, 5, 6
 _PLAN = {"given": HB_PLAN_GIVEN, "heuristic": HB_PLAN_HEURISTIC, "learned": HB_PLAN_LEARNED,
          "cheapest": HB_PLAN_CHEAPEST, "selective": HB_PLAN_SELECTIVE,

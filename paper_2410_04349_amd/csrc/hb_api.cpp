@@ -280,7 +280,8 @@ static bool same_pred(const hb_pred& a, const hb_pred& b) {
     case HB_EQ_CONST: return a.side == b.side && a.c == b.c;
     case HB_EQ_CROSS: return a.attr_b == b.attr_b;
     case HB_ED_CROSS_LE: return a.attr_b == b.attr_b && a.k == b.k;
-    case HB_JACCARD_CROSS_GE: return a.attr_b == b.attr_b && a.q == b.q && a.num == b.num && a.den == b.den;
+    case HB_JACCARD_CROSS_GE:
+    case HB_CONTAIN_GE: return a.attr_b == b.attr_b && a.q == b.q && a.num == b.num && a.den == b.den;
     default: return true;
     }
 }
@@ -299,7 +300,8 @@ static double pred_cost(const Relation& rel, const hb_pred& p) {
         const double M = std::max(L, rel.cols[p.attr_b].mean_len);
         return 2.0 * (4.0 + 17.0 * M * std::max(1.0, std::ceil(M / 64.0)));
     }
-    case HB_JACCARD_CROSS_GE: {     // one list merge per valuation
+    case HB_JACCARD_CROSS_GE:
+    case HB_CONTAIN_GE: {           // one list merge per valuation
         const double M = std::max(L, rel.cols[p.attr_b].mean_len);
         return 2.0 * (4.0 + 6.0 * std::max(1.0, M - (double)p.q + 1.0));
     }
@@ -392,6 +394,22 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
                 if (p.attr_b == p.attr) p.op = HB_JACCARD_GE;   // the plain Jaccard
                 else rs->ordered = true;
                 break;
+            case HB_CONTAIN_GE:
+                if (p.attr_b >= rel.n_cols) fail(HB_ERR_INVALID_ARG, where + ": attribute B out of range");
+                if (t != HB_COL_STRING || rel.cols[p.attr_b].type != HB_COL_STRING)
+                    fail(HB_ERR_TYPE, where + ": q-gram containment needs string attributes");
+                if (p.q < 1 || p.q > HB_MAX_Q) fail(HB_ERR_INVALID_ARG, where + ": q must be in [1, 4]");
+                if (p.den == 0 || p.num > p.den) fail(HB_ERR_INVALID_ARG, where + ": need 0 <= num <= den, den > 0");
+                {
+                    uint32_t a = p.num, b = p.den;
+                    while (b) { const uint32_t t2 = a % b; a = b; b = t2; }
+                    if (a > 1) { p.num /= a; p.den /= a; }
+                }
+                if (p.den > HB_MAX_JACCARD_DEN) fail(HB_ERR_LIMIT, where + ": threshold denominator above 2^18");
+                if (rel.cols[p.attr].max_len > HB_MAX_GRAM_LEN || rel.cols[p.attr_b].max_len > HB_MAX_GRAM_LEN)
+                    fail(HB_ERR_LIMIT, where + ": strings longer than 4096 bytes");
+                rs->ordered = true;   // asymmetric, also on one attribute
+                break;
             default:
                 fail(HB_ERR_INVALID_ARG, where + ": unknown operator");
             }
@@ -401,11 +419,13 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
             if (id == rs->distinct.size()) {
                 if (rs->distinct.size() >= HB_MAX_DISTINCT_PREDS) fail(HB_ERR_LIMIT, "more than 64 distinct predicates");
                 hb_pred np = p;
-                const bool jac = np.op == HB_JACCARD_GE || np.op == HB_JACCARD_CROSS_GE;
+                const bool jac = np.op == HB_JACCARD_GE || np.op == HB_JACCARD_CROSS_GE || np.op == HB_CONTAIN_GE;
                 if (np.op != HB_ED_LE && np.op != HB_ED_CROSS_LE) np.k = 0;
                 if (!jac) { np.q = 0; np.num = 0; np.den = 1; }
                 if (np.op != HB_ABSDIFF_LE) np.d = 0;
-                if (np.op != HB_EQ_CROSS && np.op != HB_ED_CROSS_LE && np.op != HB_JACCARD_CROSS_GE) np.attr_b = 0;
+                if (np.op != HB_EQ_CROSS && np.op != HB_ED_CROSS_LE && np.op != HB_JACCARD_CROSS_GE &&
+                    np.op != HB_CONTAIN_GE)
+                    np.attr_b = 0;
                 if (np.op != HB_EQ_CONST) { np.side = 0; np.c = 0; }
                 rs->distinct.push_back(np);
             }
@@ -433,18 +453,19 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
         same[p] = p;
         for (size_t y = 0; y < p; ++y) {
             const hb_pred& py = rs->distinct[y];
-            const bool qdep = pr.op == HB_JACCARD_GE || pr.op == HB_JACCARD_CROSS_GE;
+            const bool qdep = pr.op == HB_JACCARD_GE || pr.op == HB_JACCARD_CROSS_GE || pr.op == HB_CONTAIN_GE;
             if (py.attr == pr.attr && py.op == pr.op && (!qdep || py.q == pr.q) &&
                 (pr.op != HB_ABSDIFF_LE || py.d == pr.d)) { same[p] = y; break; }
         }
-        if (pr.op == HB_JACCARD_GE || pr.op == HB_JACCARD_CROSS_GE) gram_index(c, rel, pr.attr, pr.q);
-        if (pr.op == HB_JACCARD_CROSS_GE) gram_index(c, rel, pr.attr_b, pr.q);
+        const bool grams = pr.op == HB_JACCARD_GE || pr.op == HB_JACCARD_CROSS_GE || pr.op == HB_CONTAIN_GE;
+        if (grams) gram_index(c, rel, pr.attr, pr.q);
+        if (pr.op == HB_JACCARD_CROSS_GE || pr.op == HB_CONTAIN_GE) gram_index(c, rel, pr.attr_b, pr.q);
         if (same[p] != p) continue;
         // t.A = c and t.A = s.B take the equality hash of A, t.A ~ s.B the
         // edit-distance or q-gram hash of A: their sp is that of the
         // predicate on A alone (it orders predicates only)
         const int op = pr.op == HB_ED_LE || pr.op == HB_ED_CROSS_LE ? 1
-                     : pr.op == HB_JACCARD_GE || pr.op == HB_JACCARD_CROSS_GE ? 2 : pr.op == HB_ABSDIFF_LE ? 3 : 0;
+                     : grams ? 2 : pr.op == HB_ABSDIFF_LE ? 3 : 0;
         const Column& lc = rel.cols[pr.attr];
         const double lsh_bytes = lc.type == HB_COL_STRING ? 8.0 * ((double)rel.n_rows + 1.0) + arena_bytes(lc)
                                                          : 8.0 * (double)rel.n_rows;
@@ -852,7 +873,8 @@ static KeyRes key_resources(const Relation& rel, const RuleSet& rs, size_t ka) {
             sp.param = ((uint64_t)d.num << 32) | d.den;
             break;
         }
-        case HB_JACCARD_CROSS_GE: {   // attr_b != attr (compile turns A = B into HB_JACCARD_GE)
+        case HB_JACCARD_CROSS_GE:     // attr_b != attr (compile turns A = B into HB_JACCARD_GE)
+        case HB_CONTAIN_GE: {         // attr_b may equal attr (one gram resource then)
             auto gres = [&](uint32_t attr) -> uint8_t {
                 auto gk = std::make_pair(attr, d.q);
                 auto it = std::find(R.gram_key.begin(), R.gram_key.end(), gk);
@@ -860,7 +882,7 @@ static KeyRes key_resources(const Relation& rel, const RuleSet& rs, size_t ka) {
                 R.gram_key.push_back(gk);
                 return (uint8_t)(R.gram_key.size() - 1);
             };
-            sp.op = OP_XJAC;
+            sp.op = d.op == HB_CONTAIN_GE ? OP_XCONT : OP_XJAC;
             sp.res = gres(d.attr);
             sp.aux = gres(d.attr_b);
             sp.param = ((uint64_t)d.num << 32) | d.den;
@@ -917,6 +939,7 @@ static std::vector<Instr> emit_code(const Relation& rel, const RuleSet& rs, cons
             case OP_XEQ:
             case OP_XED:
             case OP_XJAC:
+            case OP_XCONT:
                 in.op = sp->op;
                 r.first.push_back(in);
                 break;

@@ -88,7 +88,10 @@ enum Op : uint8_t {
     OP_ENDGUARD = 13,
     // q-gram Jaccard(t.A, s.B) >= num / den (ordered rule sets): res = A,
     // aux = B (gram resources of one q), param = (num << 32) | den
-    OP_XJAC = 14
+    OP_XJAC = 14,
+    // q-gram containment of t.A in s.B >= num / den (asymmetric; ordered
+    // rule sets; A may be B): operands as OP_XJAC
+    OP_XCONT = 15
 };
 
 // One step of the sequential execution path.  `slot` identifies the step
@@ -101,7 +104,7 @@ struct Instr {
     uint8_t op;
     uint8_t slot;
     uint8_t res;
-    uint8_t aux;    // OP_CONST: side; OP_XEQ, OP_XED, OP_XJAC: resource of B
+    uint8_t aux;    // OP_CONST: side; OP_XEQ, OP_XED, OP_XJAC, OP_XCONT: resource of B
     uint16_t cp;
     uint16_t pad1;
     uint64_t param;

@@ -538,12 +538,15 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                                 }
                             }
                         }
-                    } else if (op == OP_XJAC) {
-                        // Jaccard(G_q(t.A), G_q(s.B)) >= num / den, A = res, B = aux
-                        // (gram resources of one q): forward merges the row's
-                        // A list, staged in LDS, with the lane's B list,
-                        // backward the row's B with the lane's A, row by row
-                        // where some lane needs it
+                    } else if (op == OP_XJAC || op == OP_XCONT) {
+                        // Jaccard(G_q(t.A), G_q(s.B)) >= num / den, or the
+                        // containment of G_q(t.A) in G_q(s.B) (asymmetric: the
+                        // intersection over t's set), A = res, B = aux (gram
+                        // resources of one q): forward merges the row's A list,
+                        // staged in LDS, with the lane's B list, backward the
+                        // row's B with the lane's A, row by row where some lane
+                        // needs it
+                        const bool cont = op == OP_XCONT;
                         const uint32_t num = (uint32_t)(param >> 32), den = (uint32_t)(param & 0xFFFFFFFFu);
                         kf = 0;
                         kb = 0;
@@ -571,7 +574,9 @@ __device__ __forceinline__ void match_tile(const MatchParams& P, const HB_GLOBAL
                                     const uint32_t cb = jb & 0x7FFFFFFFu;
                                     const uint32_t I = intersect(ig, ca, (ia >> 31) != 0, g_b.codes + g_b.off[row_j], cb,
                                                                  (jb >> 31) != 0);
-                                    const uint64_t U = (uint64_t)ca + cb - I;
+                                    // the denominator: the union, or t's set (the row's
+                                    // A forward, the lane's A backward)
+                                    const uint64_t U = cont ? (dir == 0 ? ca : cb) : (uint64_t)ca + cb - I;
                                     if (U == 0 || (uint64_t)I * den >= (uint64_t)num * U) {
                                         if (dir == 0) kf |= (Mask)1 << r;
                                         else kb |= (Mask)1 << r;

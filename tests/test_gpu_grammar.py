@@ -7,8 +7,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gen import (CATEGORICAL, ED, ED_CROSS, EQ, EQ_CONST, EQ_CROSS, INT64, JACCARD, JACCARD_CROSS, Pred,
-                 Relation, int_column, string_column)
+from gen import (CATEGORICAL, CONTAIN, ED, ED_CROSS, EQ, EQ_CONST, EQ_CROSS, INT64, JACCARD, JACCARD_CROSS,
+                 Pred, Relation, int_column, string_column)
 from test_oracle_grammar import KEY, hand_relation, random_relation, random_rules
 
 pytestmark = pytest.mark.gpu
@@ -116,6 +116,17 @@ def test_cross_jaccard(hb, ctx):
     for q, num, den in ((2, 1, 2), (3, 7, 10), (1, 4, 5)):
         rules = [[Pred(EQ, 0), Pred(JACCARD_CROSS, 1, attr_b=2, q=q, num=num, den=den)]]
         assert len(check(hb, ctx, rel2, rules, plans=["heuristic", "given"])) > 0
+    # the asymmetric measure: containment of t's grams in s's, across the
+    # two attributes and within one (ordered either way), alone and beside
+    # a symmetric Jaccard rule
+    for rules in ([[Pred(EQ, 0), Pred(CONTAIN, 1, attr_b=2, q=2, num=4, den=5)]],
+                  [[Pred(EQ, 0), Pred(CONTAIN, 1, attr_b=1, q=3, num=1, den=1)]],
+                  [[Pred(EQ, 0), Pred(CONTAIN, 2, attr_b=1, q=1, num=9, den=10)],
+                   [Pred(EQ, 0), Pred(JACCARD, 1, q=2, num=1, den=2)]]):
+        assert len(check(hb, ctx, rel2, rules, plans=["heuristic", "given"])) > 0
+    for rules in ([[KEY, Pred(CONTAIN, 4, attr_b=5, q=1, num=2, den=3)]],
+                  [[KEY, Pred(CONTAIN, 5, attr_b=5, q=2, num=1, den=2), Pred(EQ_CONST, 1, side=1, c=1)]]):
+        assert len(check(hb, ctx, rel, rules)) > 0
 
 
 def test_two_keys(hb, ctx):
@@ -189,6 +200,8 @@ def test_refused_calls(hb, ctx):
                          ([KEY, Pred(ED_CROSS, 3, attr_b=3, k=300)], hb.HB_ERR_INVALID_ARG),
                          ([KEY, Pred(JACCARD_CROSS, 1, attr_b=3, q=2, num=1, den=2)], hb.HB_ERR_TYPE),
                          ([KEY, Pred(JACCARD_CROSS, 3, attr_b=3, q=9, num=1, den=2)], hb.HB_ERR_INVALID_ARG),
+                         ([KEY, Pred(CONTAIN, 1, attr_b=3, q=2, num=1, den=2)], hb.HB_ERR_TYPE),
+                         ([KEY, Pred(CONTAIN, 3, attr_b=3, q=2, num=3, den=2)], hb.HB_ERR_INVALID_ARG),
                          ([Pred(EQ_CROSS, 0, attr_b=0)], hb.HB_ERR_UNBLOCKABLE)):   # never a key
         with pytest.raises(hb.HbError) as e:
             hb.hb_compile_rules(ctx, rid2, [rule])
