@@ -11,6 +11,9 @@ import this package.  It shares no code with the GPU library
   * `epg.py` -- the execution-plan generator arithmetic of Section 4.2
     (cost-effectiveness ordering, execution tree, witness probability, edge
     scores, DFS order) and the LSH selectivity estimate.
+  * `pairnet.py` -- the per-pair cost network's inputs and estimate of
+    Section 4.2 ("Evaluation cost", "Estimated cost"): sampled pairs of
+    D x D, their features, and norm(sum of the network's estimates).
 """
 from __future__ import annotations
 
