@@ -331,7 +331,7 @@ def run_batched(args):
 
 
 PROFILE_NAMES = ("match", "partition_sort", "gram_slots", "gram_build", "char_sig", "lsh", "gather",
-                 "output_sort", "learned_plan", "block_features", "predict", "plan_choice")
+                 "output_sort", "learned_plan", "block_features", "predict", "plan_choice", "pair_cost")
 # steps bound by HBM bandwidth (their algorithmic bytes come from the library)
 STREAMING = ("gram_slots", "gram_build", "char_sig", "lsh", "partition_sort", "gather", "output_sort")
 PEAK_HBM = 8.0e12   # bytes/s
@@ -395,6 +395,45 @@ def train_cost_model(hb, ctx, workloads, np):
             "logs": "person_small (2k tuples) and plain_1m (1M tuples), 4 sample waves per block"}
     log(f"[bench] cost model trained on {len(x)} log rows in {info['train_s']:.1f}s, loss {loss:.4g}")
     return info
+
+
+def train_pair_model(hb, ctx, np, cols, n_rows, rules):
+    """The per-pair network (the paper's estimated cost, Section 4.2): logs
+    of 4096 sampled pairs of the workload's own relation (a sample apart
+    from the one the estimate reads), then training on the GPU."""
+    t = time.perf_counter()
+    rid = hb.hb_load_relation(ctx, cols, n_rows, on_device=True)
+    rs = hb.hb_compile_rules(ctx, rid, rules)
+    lg = hb.hb_pair_log_collect(ctx, rid, rs, 4096, 101)
+    hb.hb_release_relation(ctx, rid)
+    x, tl = lg["features"], lg["labels"]
+    perm = np.random.default_rng(0).permutation(len(x))
+    hb.hb_costmodel_select(ctx, "pair")
+    try:
+        hb.hb_costmodel_init(ctx, 5)
+        loss = hb.hb_costmodel_train(ctx, x[perm], tl[perm], epochs=20, batch=256, lr=2e-3)
+    finally:
+        hb.hb_costmodel_select(ctx, "block")
+    info = {"train_rows": int(len(x)), "epochs": 20, "final_loss": loss, "train_s": time.perf_counter() - t,
+            "logs": "4096 sampled pairs of the workload's relation per predicate (seed 101)",
+            "estimate": f"{PAIR_NET_SAMPLES} sampled pairs per predicate (seed {PAIR_NET_SEED})"}
+    log(f"[bench] per-pair network trained on {len(x)} log rows in {info['train_s']:.1f}s, loss {loss:.4g}")
+    return info
+
+
+PAIR_NET_SAMPLES, PAIR_NET_SEED = 4096, 7
+
+
+def ordered_rules(rules):
+    """Whether a rule set tells t from s (the per-pair network takes
+    predicates comparing one attribute of both tuples only)."""
+    for rule in rules:
+        for p in rule:
+            if p.op in ("eq_const", "contain"):
+                return True
+            if p.op in ("eq_cross", "ed_cross", "jaccard_cross") and p.attr_b != p.attr:
+                return True
+    return False
 
 
 def main():
@@ -476,7 +515,14 @@ def main():
         t0 = time.perf_counter()
         rid = hb.hb_load_relation(ctx, cols, rel.n_rows, on_device=True)
         t1 = time.perf_counter()
-        rs = hb.hb_compile_rules(ctx, rid, rules if rules_ is None else rules_)
+        if plan.endswith("_pair_net"):
+            # predicate costs from the per-pair network's estimate
+            plan = plan[: -len("_pair_net")]
+            hb.hb_set_cost_estimate(ctx, "pair_net", PAIR_NET_SAMPLES, PAIR_NET_SEED)
+        try:
+            rs = hb.hb_compile_rules(ctx, rid, rules if rules_ is None else rules_)
+        finally:
+            hb.hb_set_cost_estimate(ctx, "static")
         t2 = time.perf_counter()
         n_cand = hb.hb_partition(ctx, rid, rs)
         t3 = time.perf_counter()
@@ -654,9 +700,13 @@ def main():
         log(f"[bench] end to end from pinned host memory in {n_ch} key chunks: {overlap}")
 
     strategies = None
+    pair_net = None
     if args.strategies:
         strategies = {}
         snames = ("given", "heuristic", "cheapest", "selective", "random_preds", "random_rules")
+        if not ordered_rules(rules):
+            pair_net = train_pair_model(hb, ctx, np, cols, rel.n_rows, rules)
+            snames += ("heuristic_pair_net",)
         outs_s = {sn: torch.empty_like(out) for sn in snames}
         legs_s = timed_legs(list(snames), outs_s)
         for sn in snames:
@@ -668,6 +718,22 @@ def main():
                               "bit_exact": same}
         strategies[args.plan + " (timed above)"] = {"ms_per_step": ms_step,
                                                     "match_kernel_ms_per_step": L["match_ms_step"]}
+        if pair_net is not None:
+            # the two cost inputs side by side, and the predicate orders they give
+            rid = hb.hb_load_relation(ctx, cols, rel.n_rows, on_device=True)
+            sp, c_static = hb.hb_ruleset_estimates(ctx, hb.hb_compile_rules(ctx, rid, rules))
+            hb.hb_set_cost_estimate(ctx, "pair_net", PAIR_NET_SAMPLES, PAIR_NET_SEED)
+            try:
+                _, c_net = hb.hb_ruleset_estimates(ctx, hb.hb_compile_rules(ctx, rid, rules))
+            finally:
+                hb.hb_set_cost_estimate(ctx, "static")
+            hb.hb_release_relation(ctx, rid)
+            rank = lambda c: [int(v) for v in np.argsort(-(1.0 - sp) / c, kind="stable")]
+            pair_net.update({"cost_static": [round(float(v), 6) for v in c_static],
+                             "cost_pair_net": [round(float(v), 6) for v in c_net],
+                             "order_static": rank(c_static), "order_pair_net": rank(c_net)})
+            log(f"[bench] predicate costs, static: {pair_net['cost_static']}")
+            log(f"[bench] predicate costs, per-pair network: {pair_net['cost_pair_net']}")
         log(f"[bench] strategies: {strategies}")
 
     grammar = None
@@ -739,6 +805,7 @@ def main():
         "cost_model": learned,
         "quality": qual,
         "strategies": strategies,
+        "pair_net": pair_net,
         "grammar": grammar,
         "pcie_inclusive": pcie,
         "h2d_overlap": overlap,

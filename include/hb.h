@@ -314,6 +314,30 @@ hb_status hb_set_pack_small_blocks(hb_ctx* ctx, int on);
  * outside [0, 1): HB_ERR_INVALID_ARG. */
 hb_status hb_set_learned_min_saving(hb_ctx* ctx, float min_saving);
 
+/* Where hb_compile_rules takes each distinct predicate's cost (the
+ * denominator of the cost-effectiveness order, Section 4.2, "Predicate
+ * ordering"):
+ *   HB_COST_STATIC (default): per-operator formulas of the attribute's mean
+ *     length;
+ *   HB_COST_PAIR_NET: the paper's estimated cost (Section 4.2, "Estimated
+ *     cost"): the per-pair model (HB_MODEL_PAIR) estimates the time of
+ *     checking the predicate on each of `samples` sampled pairs of D x D
+ *     (the sample of hb_pair_log_collect with `seed`, the same pairs for
+ *     every predicate); a predicate's cost is the sum of its estimates,
+ *     2^(16 * clamp(y, 0, 4)) - 1 cycles per pair for the model's second
+ *     output y (NaN counts as 0), divided by the largest predicate's sum
+ *     (each kept at or above 2^-20 of it; every cost 1 when all sums are
+ *     zero or the relation has fewer than two tuples).  Compile then needs a
+ *     trained per-pair model (HB_ERR_STATE), predicates that compare one
+ *     attribute of both tuples (HB_ERR_INVALID_ARG otherwise) and at most 64
+ *     distinct predicates (HB_ERR_LIMIT); it reads the sums back with one
+ *     synchronisation.
+ * Costs order predicates only: every plan's result is unchanged.  Samples
+ * outside [1, 65536] or another source: HB_ERR_INVALID_ARG. */
+#define HB_COST_STATIC 0
+#define HB_COST_PAIR_NET 1
+hb_status hb_set_cost_estimate(hb_ctx* ctx, int source, uint32_t samples, uint64_t seed);
+
 /* ------------------------------------------------------------ introspection */
 
 /* Per distinct predicate of a rule set (in first-appearance order): its
@@ -346,7 +370,8 @@ hb_status hb_plan_path(uint32_t plan, uint32_t n_preds, const double* sp, const 
 /* Kernel timing: when enabled, HIP events bracket each kernel launch of the
  * named step on the context stream.  Names: "match", "partition_sort",
  * "gram_slots", "gram_build" (the q-gram codes and signatures), "char_sig",
- * "lsh", "gather", "output_sort", "log", "block_features", "plan_choice";
+ * "lsh", "gather", "output_sort", "log", "block_features", "plan_choice",
+ * "pair_cost" (the per-pair network's estimate inside hb_compile_rules);
  * and, as host wall
  * time including synchronisation, "learned_plan" (building one key
  * partition's per-block learned plans) and "predict" (cost-model inference
@@ -410,6 +435,15 @@ hb_status hb_match_work(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32
  * run in fp32.  The model belongs to the context. */
 #define HB_MLP_PARAMS 5378
 #define HB_MLP_FEATURES 16
+/* The context holds two models of this shape: the block model (the learned
+ * plan's, trained on hb_log_collect rows) and the per-pair model (the
+ * paper's network N of Section 4.2, trained on hb_pair_log_collect rows,
+ * which HB_COST_PAIR_NET reads).  The hb_costmodel_* calls below act on the
+ * selected one (the block model until this is called; HB_ERR_INVALID_ARG
+ * for another value).  The learned plan always reads the block model. */
+#define HB_MODEL_BLOCK 0
+#define HB_MODEL_PAIR 1
+hb_status hb_costmodel_select(hb_ctx* ctx, int which);
 /* He-uniform weights from a splitmix64 stream of `seed`, zero biases. */
 hb_status hb_costmodel_init(hb_ctx* ctx, uint64_t seed);
 /* Copy parameters in / out (host arrays of n = HB_MLP_PARAMS floats);
@@ -439,7 +473,9 @@ hb_status hb_costmodel_adam_step(hb_ctx* ctx, const float* grads, float lr);
  * offline on historical logs, Section 4.2, "Shallow NNs").  File layout,
  * little-endian: the 8 bytes "HBCMODEL"; uint32 version (1); uint32 inputs,
  * hidden width, outputs and parameter count (16, 64, 2, HB_MLP_PARAMS);
- * uint32 0; HB_MLP_PARAMS fp32 parameters in the order above; uint64 FNV-1a
+ * uint32 model (HB_MODEL_BLOCK or HB_MODEL_PAIR: the selected model when
+ * saved; loading needs the same selection); HB_MLP_PARAMS fp32 parameters in
+ * the order above; uint64 FNV-1a
  * 64 hash of those parameter bytes.  hb_costmodel_save needs a model
  * (HB_ERR_STATE) and writes `path` whole or not at all (a temporary file
  * renamed over it); hb_costmodel_load checks every field, the size and the
@@ -470,6 +506,33 @@ hb_status hb_costmodel_load(hb_ctx* ctx, const char* path);
 hb_status hb_log_collect(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, uint32_t samples, uint64_t seed,
                          float* features, float* labels, uint32_t* meta, uint64_t* counts, uint64_t cap_rows,
                          uint64_t* n_rows);
+
+/* Logging pass for the per-pair model (Section 4.2, "Evaluation cost":
+ * T_p(t1, t2) is the time of checking predicate p on the pair): for every
+ * distinct predicate (ascending id; each must compare one attribute of both
+ * tuples, HB_ERR_INVALID_ARG otherwise; at most 64, HB_ERR_LIMIT) and every
+ * sampled pair s of D x D,
+ * one row: i = h(seed + 2s) mod n, j = h(seed + 2s + 1) mod n, j replaced by
+ * (i + 1) mod n when equal to i (h = the splitmix64 output function;
+ * needs no hb_partition).  Row x * samples + s holds
+ *   features: 16 inputs -- one-hot kind (value equality, |a-b| <= d, string
+ *     equality, edit distance, Jaccard), t1.A and t2.A present, byte lengths
+ *     L1 / 64 and L2 / 64, then [L1 == L2] (string equality), pattern words
+ *     of L1 / 4 and k / 16 (edit distance: words 0 up to 32 bytes, else
+ *     ceil(L1 / 64)), or q-gram counts C1 / 64 and C2 / 64 (Jaccard), a flag
+ *     for a Jaccard value shorter than q, Jaccard's num / den (fp32),
+ *     min(L1, L2) / 64, |L1 - L2| / 64 and 1; a missing value has length
+ *     and count 0;
+ *   labels: 1 if the pair satisfies the predicate, else 0; and
+ *     log2(1 + clock cycles) / 16 of one wave checking that pair exactly
+ *     (every lane on the same pair).
+ * pairs [samples x 2] = (i, j).  Outputs are host arrays (any may be NULL).
+ * samples in [1, 65536] (HB_ERR_INVALID_ARG otherwise); a relation with
+ * fewer than two tuples gives no rows.  If cap_rows is too small the call
+ * returns HB_ERR_CAPACITY with *n_rows = rows needed. */
+hb_status hb_pair_log_collect(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, uint32_t samples, uint64_t seed,
+                              float* features, float* labels, uint32_t* pairs, uint64_t cap_rows,
+                              uint64_t* n_rows);
 
 /* Counters of the last hb_match: candidate pairs, pairs matched, launches
  * and tiles of the match kernel. */

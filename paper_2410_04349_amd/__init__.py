@@ -49,8 +49,8 @@ EXPORTED = [
     "hb_epg_path", "hb_plan_path", "hb_profile_enable", "hb_profile_query", "hb_profile_bytes", "hb_profile_reset", "hb_last_match_stats",
     "hb_match_work", "hb_costmodel_init", "hb_costmodel_set_params", "hb_costmodel_get_params",
     "hb_costmodel_train", "hb_costmodel_predict", "hb_costmodel_trace", "hb_costmodel_adam_step",
-    "hb_costmodel_save", "hb_costmodel_load",
-    "hb_log_collect", "hb_batch_create", "hb_batch_run", "hb_batch_result", "hb_batch_info_get",
+    "hb_costmodel_save", "hb_costmodel_load", "hb_costmodel_select", "hb_set_cost_estimate",
+    "hb_log_collect", "hb_pair_log_collect", "hb_batch_create", "hb_batch_run", "hb_batch_result", "hb_batch_info_get",
     "hb_batch_destroy",
 ]
 
@@ -59,6 +59,10 @@ HB_BATCH_AUTOTUNE = 2
 HB_BATCH_FORM = {"streams": 0x100, "multi": 0x200, "persistent": 0x300}
 
 HB_MLP_PARAMS = 5378
+HB_MODEL_BLOCK, HB_MODEL_PAIR = 0, 1
+_MODEL = {"block": HB_MODEL_BLOCK, "pair": HB_MODEL_PAIR}
+HB_COST_STATIC, HB_COST_PAIR_NET = 0, 1
+_COST = {"static": HB_COST_STATIC, "pair_net": HB_COST_PAIR_NET}
 
 OP_KINDS = ["eq_value", "absdiff", "eq_string_filter", "ed_filter", "jaccard_filter", "eq_string",
             "edit_distance", "jaccard"]
@@ -160,6 +164,9 @@ def _load_lib():
         "hb_costmodel_save": (I32, [P, ctypes.c_char_p]),
         "hb_costmodel_load": (I32, [P, ctypes.c_char_p]),
         "hb_log_collect": (I32, [P, U32, U32, U32, U64, P, P, P, P, U64, ctypes.POINTER(U64)]),
+        "hb_pair_log_collect": (I32, [P, U32, U32, U32, U64, P, P, P, U64, ctypes.POINTER(U64)]),
+        "hb_costmodel_select": (I32, [P, I32]),
+        "hb_set_cost_estimate": (I32, [P, I32, U32, U64]),
         "hb_batch_create": (I32, [P, ctypes.POINTER(HbJob), U32, I32, U32, ctypes.POINTER(U32)]),
         "hb_batch_run": (I32, [P, U32, ctypes.POINTER(U64)]),
         "hb_batch_result": (I32, [P, U32, U32, P, ctypes.c_int, U64, ctypes.POINTER(U64)]),
@@ -533,6 +540,36 @@ def hb_costmodel_save(ctx: Context, path: str) -> None:
 
 def hb_costmodel_load(ctx: Context, path: str) -> None:
     ctx.check(_lib.hb_costmodel_load(ctx.h, os.fsencode(path)))
+
+
+def hb_costmodel_select(ctx: Context, which) -> None:
+    """"block" (the learned plan's model) or "pair" (the per-pair network of
+    the estimated cost): the model the hb_costmodel_* calls act on."""
+    ctx.check(_lib.hb_costmodel_select(ctx.h, _MODEL[which] if isinstance(which, str) else int(which)))
+
+
+def hb_set_cost_estimate(ctx: Context, source, samples: int = 1024, seed: int = 0x48425041) -> None:
+    """"static" or "pair_net": where hb_compile_rules takes predicate costs."""
+    ctx.check(_lib.hb_set_cost_estimate(ctx.h, _COST[source] if isinstance(source, str) else int(source),
+                                        samples, seed))
+
+
+def hb_pair_log_collect(ctx: Context, rel_id: int, ruleset_id: int, samples: int, seed: int) -> dict:
+    """Per-pair logging pass (see include/hb.h): features [n x 16], labels
+    [n x 2] (satisfied, log2(1 + cycles) / 16), rows predicate-major, and
+    pairs [samples x 2] (i, j)."""
+    n = ctypes.c_uint64()
+    st = _lib.hb_pair_log_collect(ctx.h, rel_id, ruleset_id, samples, seed, None, None, None, 0, ctypes.byref(n))
+    if st not in (HB_OK, HB_ERR_CAPACITY):
+        ctx.check(st)
+    rows = n.value
+    f = np.zeros((max(rows, 1), 16), dtype=np.float32)
+    lab = np.zeros((max(rows, 1), 2), dtype=np.float32)
+    pairs = np.zeros((max(samples, 1), 2), dtype=np.uint32)
+    ctx.check(_lib.hb_pair_log_collect(ctx.h, rel_id, ruleset_id, samples, seed, ctypes.c_void_p(f.ctypes.data),
+                                       ctypes.c_void_p(lab.ctypes.data), ctypes.c_void_p(pairs.ctypes.data), rows,
+                                       ctypes.byref(n)))
+    return {"features": f[:rows], "labels": lab[:rows], "pairs": pairs[:samples] if rows else pairs[:0]}
 
 
 def hb_log_collect(ctx: Context, rel_id: int, ruleset_id: int, samples: int, seed: int) -> dict:

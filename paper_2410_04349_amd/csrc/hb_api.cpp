@@ -311,6 +311,129 @@ static double pred_cost(const Relation& rel, const hb_pred& p) {
 
 static const uint64_t* char_signature(Ctx* c, Relation& rel, uint32_t attr);
 
+// ------------------------------------------------------------ per-pair cost network
+
+static uint32_t align_up(uint32_t v, uint32_t a) { return (v + a - 1) / a * a; }
+
+constexpr uint32_t kMaxPairSamples = 65536;
+
+// The per-pair network's view of the rule set's distinct predicates
+// (Section 4.2, "Evaluation cost"): each compares one attribute of both
+// tuples; the q-gram indexes are the relation's (built by compile).
+static PairParams pair_params(Ctx* c, Relation& rel, const RuleSet& rs, uint32_t samples, uint64_t seed) {
+    PairParams P{};
+    if (rs.distinct.size() > (size_t)kMaxSpecs) fail(HB_ERR_LIMIT, "more than 64 distinct predicates");
+    std::vector<std::pair<uint32_t, uint32_t>> grams;
+    uint32_t lds = kPairLdsGrams + 16;
+    for (size_t x = 0; x < rs.distinct.size(); ++x) {
+        const hb_pred& d = rs.distinct[x];
+        PairSpec& sp = P.spec[x];
+        sp.attr = d.attr;
+        const bool str = rel.cols[d.attr].type == HB_COL_STRING;
+        if (d.op == HB_EQ || (d.op == HB_EQ_CROSS && d.attr_b == d.attr)) {
+            sp.kind = str ? PK_STRING_EQ : PK_VALUE_EQ;
+        } else if (d.op == HB_ABSDIFF_LE) {
+            sp.kind = PK_ABSDIFF;
+            sp.d = d.d;
+        } else if (d.op == HB_ED_LE) {
+            sp.kind = PK_EDIT;
+            sp.k = (uint32_t)d.k;
+        } else if (d.op == HB_JACCARD_GE) {
+            sp.kind = PK_JACCARD;
+            sp.q = d.q;
+            sp.num = d.num;
+            sp.den = d.den;
+            auto key = std::make_pair(d.attr, d.q);
+            auto it = std::find(grams.begin(), grams.end(), key);
+            if (it == grams.end()) {
+                if (grams.size() == (size_t)kMaxGramRes) fail(HB_ERR_LIMIT, "more than 8 q-gram attributes");
+                grams.push_back(key);
+                it = grams.end() - 1;
+            }
+            sp.gram = (uint8_t)(it - grams.begin());
+            P.gram[sp.gram] = gram_index(c, rel, d.attr, d.q).dev();
+            lds = std::max<uint32_t>(lds, kPairLdsGrams + (uint32_t)align_up(std::max<uint32_t>(
+                                                               P.gram[sp.gram].max_cnt, 1) * 4, 16));
+        } else {
+            fail(HB_ERR_INVALID_ARG, "the per-pair cost network takes predicates that compare one attribute of "
+                                     "both tuples (t.A = s.A, t.A ~ s.A) only");
+        }
+    }
+    if (lds > c->lds_limit) fail(HB_ERR_LIMIT, "the per-pair logging pass exceeds the device's LDS");
+    P.cols = rel.d_cols.as<ColDev>();
+    P.n_spec = (uint32_t)rs.distinct.size();
+    P.samples = rel.n_rows >= 2 ? samples : 0;   // one tuple: no pairs
+    P.n_rows = rel.n_rows;
+    P.seed = seed;
+    P.lds_bytes = lds;
+    return P;
+}
+
+// Estimated costs (Section 4.2, "Estimated cost"): per predicate, the sum
+// of the per-pair network's estimates over the sampled pairs of D x D,
+// normalised by the largest sum into (0, 1] (each kept at or above 2^-20 of
+// it; every cost 1 when all sums are zero or there are no pairs).  One
+// synchronisation: compile reads the sums back.
+static void pair_net_costs(Ctx* c, Relation& rel, RuleSet& rs) {
+    if (!c->pair_model.ready)
+        fail(HB_ERR_STATE, "the per-pair cost estimate needs a per-pair model (hb_costmodel_select, then train)");
+    PairParams P = pair_params(c, rel, rs, c->cost_samples, c->cost_seed);
+    const size_t np = rs.distinct.size();
+    const size_t rows = (size_t)P.n_spec * P.samples;
+    std::vector<double> sums(np, 0.0);
+    if (rows) {
+        DevBuf feat(c, sizeof(float) * kFeatures * rows), y(c, sizeof(float) * 2 * rows), dsum(c, sizeof(double) * np);
+        P.features = feat.as<float>();
+        P.y = y.as<float>();
+        P.sums = dsum.as<double>();
+        c->timed("pair_cost", [&] { return launch_pair_features(P, c->stream); });
+        c->timed("pair_cost", [&] {
+            return launch_mlp_forward(c->pair_model.params.as<float>(), P.features, rows, P.y, c->stream);
+        });
+        c->timed("pair_cost", [&] { return launch_pair_sum(P, c->stream); });
+        HB_HIP(hipMemcpyAsync(sums.data(), P.sums, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+    }
+    double top = 0.0;
+    for (double v : sums) top = std::max(top, v);
+    for (size_t p = 0; p < np; ++p) rs.cost[p] = top > 0.0 ? std::max(sums[p], top * 0x1p-20) / top : 1.0;
+}
+
+static void pair_log_collect(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint32_t samples, uint64_t seed,
+                             float* features, float* labels, uint32_t* pairs, uint64_t cap, uint64_t* n_rows) {
+    Relation& rel = get_rel(c, rel_id);
+    RuleSet& rs = get_rs(c, rs_id, rel_id);
+    if (!n_rows) fail(HB_ERR_INVALID_ARG, "NULL n_rows");
+    if (samples == 0 || samples > kMaxPairSamples) fail(HB_ERR_INVALID_ARG, "samples must be in [1, 65536]");
+    PairParams P = pair_params(c, rel, rs, samples, seed);
+    const size_t rows = (size_t)P.n_spec * P.samples;
+    *n_rows = rows;
+    if (cap < rows) fail(HB_ERR_CAPACITY, "row capacity " + std::to_string(cap) + " < " + std::to_string(rows));
+    if (rows == 0) return;
+    DevBuf feat(c, sizeof(float) * kFeatures * rows), sat(c, rows), cyc(c, sizeof(unsigned long long) * rows);
+    DevBuf pr(c, sizeof(uint32_t) * 2 * (size_t)P.samples);
+    P.features = feat.as<float>();
+    P.sat = sat.as<uint8_t>();
+    P.cycles = cyc.as<unsigned long long>();
+    P.pairs = pr.as<uint32_t>();
+    c->timed("log", [&] { return launch_pair_log(P, c->stream); });
+    std::vector<uint8_t> hs(rows);
+    std::vector<unsigned long long> hc(rows);
+    if (features)
+        HB_HIP(hipMemcpyAsync(features, P.features, sizeof(float) * kFeatures * rows, hipMemcpyDeviceToHost, c->stream));
+    if (pairs)
+        HB_HIP(hipMemcpyAsync(pairs, P.pairs, sizeof(uint32_t) * 2 * (size_t)P.samples, hipMemcpyDeviceToHost,
+                              c->stream));
+    HB_HIP(hipMemcpyAsync(hs.data(), P.sat, rows, hipMemcpyDeviceToHost, c->stream));
+    HB_HIP(hipMemcpyAsync(hc.data(), P.cycles, sizeof(unsigned long long) * rows, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    if (labels)
+        for (size_t r = 0; r < rows; ++r) {
+            labels[2 * r] = (float)hs[r];
+            labels[2 * r + 1] = (float)(std::log2(1.0 + (double)hc[r]) / 16.0);
+        }
+}
+
 static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_rule* rules, uint32_t* ruleset_id) {
     Relation& rel = get_rel(c, rel_id);
     if (!rules || !ruleset_id) fail(HB_ERR_INVALID_ARG, "NULL argument");
@@ -502,6 +625,7 @@ static void compile_rules(Ctx* c, uint32_t rel_id, uint32_t n_rules, const hb_ru
         cmax = std::max(cmax, rs->cost[p]);
     }
     for (size_t p = 0; p < np; ++p) rs->cost[p] /= cmax;
+    if (c->cost_source == HB_COST_PAIR_NET) pair_net_costs(c, rel, *rs);
     // the character signatures every string step reads, built here with the
     // q-gram indexes so that matching only reads per-relation indexes
     for (const hb_pred& d : rs->distinct) {
@@ -776,7 +900,6 @@ static void partition(Ctx* c, uint32_t rel_id, uint32_t rs_id, uint64_t* n_cand)
 // ------------------------------------------------------------ match
 
 
-static uint32_t align_up(uint32_t v, uint32_t a) { return (v + a - 1) / a * a; }
 
 static const uint64_t* char_signature(Ctx* c, Relation& rel, uint32_t attr) {
     auto it = rel.char_sig.find(attr);
@@ -1305,7 +1428,7 @@ static void learned_key_plan(Ctx* c, Relation& rel, RuleSet& rs, size_t ka, KeyP
     LearnParams L;
     block_features(c, kp, R, feat, L, part.big.as<uint32_t>(), nl);
     DevBuf y(c, sizeof(float) * 2 * (size_t)nl * ns);
-    c->host_timed("predict", [&] { costmodel_predict(c, feat.as<float>(), (uint64_t)nl * ns, 1, y.as<float>(), 1); });
+    c->host_timed("predict", [&] { model_forward(c, c->model, feat.as<float>(), (uint64_t)nl * ns, y.as<float>()); });
 
     C.y = y.as<float>();
     C.blocks = part.big.as<uint32_t>();
@@ -1841,6 +1964,32 @@ hb_status hb_set_learned_min_saving(hb_ctx* ctx, float min_saving) {
         if (!(min_saving >= 0.f && min_saving < 1.f)) hb::fail(HB_ERR_INVALID_ARG, "the minimum saving must be in [0, 1)");
         c->learned_min_saving = min_saving;
         for (auto& it : c->rulesets) it.second->has_result = false;
+    });
+}
+
+hb_status hb_costmodel_select(hb_ctx* ctx, int which) {
+    return guard(ctx, [&](Ctx* c) {
+        if (which != HB_MODEL_BLOCK && which != HB_MODEL_PAIR)
+            hb::fail(HB_ERR_INVALID_ARG, "model must be HB_MODEL_BLOCK or HB_MODEL_PAIR");
+        c->model_sel = which;
+    });
+}
+
+hb_status hb_set_cost_estimate(hb_ctx* ctx, int source, uint32_t samples, uint64_t seed) {
+    return guard(ctx, [&](Ctx* c) {
+        if (source != HB_COST_STATIC && source != HB_COST_PAIR_NET)
+            hb::fail(HB_ERR_INVALID_ARG, "source must be HB_COST_STATIC or HB_COST_PAIR_NET");
+        if (samples == 0 || samples > hb::kMaxPairSamples) hb::fail(HB_ERR_INVALID_ARG, "samples must be in [1, 65536]");
+        c->cost_source = source;
+        c->cost_samples = samples;
+        c->cost_seed = seed;
+    });
+}
+
+hb_status hb_pair_log_collect(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, uint32_t samples, uint64_t seed,
+                              float* features, float* labels, uint32_t* pairs, uint64_t cap_rows, uint64_t* n_rows) {
+    return guard(ctx, [&](Ctx* c) {
+        hb::pair_log_collect(c, rel_id, ruleset_id, samples, seed, features, labels, pairs, cap_rows, n_rows);
     });
 }
 

@@ -185,7 +185,14 @@ struct Ctx {
     uint32_t sparse_rows = 0;      // the per-lane form's threshold (0: the default of the batch size)
     float learned_min_saving = 0.25f;   // predicted saving a key partition's per-block plans must reach
     bool pack_small_blocks = false;     // hb_set_pack_small_blocks
-    CostModel model;
+    CostModel model;        // per (block, predicate): the learned plan's model
+    CostModel pair_model;   // per (predicate, pair): the estimated cost's network
+    int model_sel = 0;      // HB_MODEL_BLOCK / HB_MODEL_PAIR: what hb_costmodel_* act on
+    // hb_set_cost_estimate: the rule set's predicate costs from the static
+    // per-operator formulas (0) or from the pair network over sampled pairs
+    int cost_source = 0;
+    uint32_t cost_samples = 1024;
+    uint64_t cost_seed = 0x48425041ull;
     std::map<uint32_t, std::shared_ptr<Batch>> batches;
     // the last autotuned batch launch form, reused by batches created
     // without autotuning
@@ -345,7 +352,10 @@ inline std::vector<int> shifts_for_bits(int bits, int base) {
 // the reason in *err, when the runtime cannot give it.
 uint8_t* scratch_address(int device, std::string* err);
 
-// cost model (hb_learn.cpp)
+// cost models (hb_learn.cpp): the hb_costmodel_* calls act on the
+// selected model; model_forward runs a given one on device rows
+CostModel& selected_model(Ctx* c);
+void model_forward(Ctx* c, const CostModel& m, const float* x, uint64_t n, float* y);
 void costmodel_init(Ctx* c, uint64_t seed);
 void costmodel_set(Ctx* c, const float* p, uint32_t n);
 void costmodel_get(Ctx* c, float* p, uint32_t n);

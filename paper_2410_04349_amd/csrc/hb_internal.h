@@ -333,6 +333,45 @@ struct LearnParams {
 hipError_t launch_block_features(const LearnParams& p, hipStream_t s);
 hipError_t launch_log_samples(const LearnParams& p, hipStream_t s);
 
+// ------------------------------------------------------------ per-pair cost network
+// The estimated cost of Section 4.2 ("Evaluation cost", "Estimated cost"):
+// sampled pairs of D x D (not of blocks), each described to the per-pair
+// network by 16 features of the predicate and the two A-values, read
+// straight from the relation's columns.  Pair s of a seed:
+// i = mix64(seed + 2s) mod n, j = mix64(seed + 2s + 1) mod n, j = (i + 1)
+// mod n when equal to i.  Rows are predicate-major: row x * samples + s.
+enum PairKind : uint8_t { PK_VALUE_EQ = 0, PK_ABSDIFF = 1, PK_STRING_EQ = 2, PK_EDIT = 3, PK_JACCARD = 4 };
+struct PairSpec {
+    uint8_t kind;       // PairKind
+    uint8_t gram;       // PK_JACCARD: index into PairParams::gram
+    uint16_t pad;
+    uint32_t attr;      // the compared attribute
+    uint32_t q;         // PK_JACCARD
+    uint32_t k;         // PK_EDIT: distance bound
+    int64_t d;          // PK_ABSDIFF
+    uint32_t num, den;  // PK_JACCARD: threshold num / den
+};
+constexpr uint32_t kPairLdsPeq = 0;                                   // 256 x 4 64-bit words
+constexpr uint32_t kPairLdsMyers = 256 * kMaxEdWords * 8;             // long-pattern state
+constexpr uint32_t kPairLdsGrams = kPairLdsMyers + 2 * kMaxEdWords * 64 * 8;   // row i's q-gram list
+struct PairParams {
+    const ColDev* cols;             // the relation's columns (device)
+    GramDev gram[kMaxGramRes];
+    PairSpec spec[kMaxSpecs];
+    uint32_t n_spec, samples, n_rows;
+    uint32_t lds_bytes;             // logging: kPairLdsGrams + the longest q-gram list
+    uint64_t seed;
+    float* features;                // [n_spec x samples x 16]
+    float* y;                       // estimate: the network's outputs [n_spec x samples x 2]
+    double* sums;                   // estimate: [n_spec] summed cycles
+    uint8_t* sat;                   // logging: [n_spec x samples] the check's result
+    unsigned long long* cycles;     // logging: [n_spec x samples] clock cycles of the check
+    uint32_t* pairs;                // logging: [samples x 2] (i, j), or nullptr
+};
+hipError_t launch_pair_log(const PairParams& p, hipStream_t s);
+hipError_t launch_pair_features(const PairParams& p, hipStream_t s);
+hipError_t launch_pair_sum(const PairParams& p, hipStream_t s);
+
 // Per-block plan choice from the cost model's outputs.  Rules keep the
 // heuristic path's order; per block and rule the kernel picks the first-stage
 // order and the verification order.  Equal choices share a plan slot of an

@@ -1,9 +1,12 @@
-// The learned cost model of libhb: a 16 -> 64 -> 64 -> 2 MLP (ReLU) over
-// per-(block, predicate) features predicting (pass rate, cost), trained on
-// the GPU by this library's kernels (matrix-core GEMM with bf16 operands and
-// fp32 accumulation, Adam).  It replaces the paper's shallow network that
-// estimates predicate costs from logs (Section 4.2, "Shallow NNs",
-// "Estimated cost"; Adam and ReLU as in the paper's defaults, Section 6).
+// The learned cost models of libhb: 16 -> 64 -> 64 -> 2 MLPs (ReLU), trained
+// on the GPU by this library's kernels (matrix-core GEMM with bf16 operands
+// and fp32 accumulation, Adam).  Two of the same shape: the block model over
+// per-(block, predicate) features predicting (pass rate, cost), which the
+// learned plan reads, and the paper's per-pair network over features of a
+// predicate and two tuples' values predicting (satisfied, time of the
+// check), whose summed estimates give the predicates' costs (Section 4.2,
+// "Shallow NNs", "Estimated cost"; Adam and ReLU as in the paper's
+// defaults, Section 6).
 #include <cmath>
 #include <cstdio>
 
@@ -16,6 +19,8 @@ constexpr int kIn = 16, kHid = 64, kOut = 2;
 constexpr int kW1 = 0, kB1 = kW1 + kIn * kHid, kW2 = kB1 + kHid, kB2 = kW2 + kHid * kHid;
 constexpr int kW3 = kB2 + kHid, kB3 = kW3 + kHid * kOut, kParams = kB3 + kOut;
 static_assert(kParams == HB_MLP_PARAMS, "parameter count");
+
+CostModel& selected_model(Ctx* c) { return c->model_sel == HB_MODEL_PAIR ? c->pair_model : c->model; }
 
 namespace {
 
@@ -86,7 +91,7 @@ void backward(Ctx* c, const float* W, const float* x, const float* t, int n, Act
 }
 
 void adam(Ctx* c, const float* grad, float lr) {
-    CostModel& m = c->model;
+    CostModel& m = selected_model(c);
     m.adam_t += 1;
     const double b1 = 0.9, b2 = 0.999;
     const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)m.adam_t)));
@@ -96,7 +101,7 @@ void adam(Ctx* c, const float* grad, float lr) {
 }
 
 void ensure_model(Ctx* c) {
-    CostModel& m = c->model;
+    CostModel& m = selected_model(c);
     if (m.params.get()) return;
     m.params.alloc(c, sizeof(float) * kParams);
     m.m.alloc(c, sizeof(float) * kParams);
@@ -107,9 +112,10 @@ void ensure_model(Ctx* c) {
 }
 
 void reset_adam(Ctx* c) {
-    zero(c, c->model.m.get(), sizeof(float) * kParams);
-    zero(c, c->model.v.get(), sizeof(float) * kParams);
-    c->model.adam_t = 0;
+    CostModel& m = selected_model(c);
+    zero(c, m.m.get(), sizeof(float) * kParams);
+    zero(c, m.v.get(), sizeof(float) * kParams);
+    m.adam_t = 0;
 }
 
 uint64_t splitmix(uint64_t& s) {
@@ -143,25 +149,25 @@ void costmodel_init(Ctx* c, uint64_t seed) {
     fill(kW1, kIn, kIn * kHid);
     fill(kW2, kHid, kHid * kHid);
     fill(kW3, kHid, kHid * kOut);
-    HB_HIP(hipMemcpyAsync(c->model.params.get(), w.data(), sizeof(float) * kParams, hipMemcpyHostToDevice, c->stream));
+    HB_HIP(hipMemcpyAsync(selected_model(c).params.get(), w.data(), sizeof(float) * kParams, hipMemcpyHostToDevice, c->stream));
     reset_adam(c);
-    c->model.ready = true;
+    selected_model(c).ready = true;
     c->sync();
 }
 
 void costmodel_set(Ctx* c, const float* p, uint32_t n) {
     if (!p || n != (uint32_t)kParams) fail(HB_ERR_INVALID_ARG, "expected HB_MLP_PARAMS floats");
     ensure_model(c);
-    HB_HIP(hipMemcpyAsync(c->model.params.get(), p, sizeof(float) * kParams, hipMemcpyHostToDevice, c->stream));
+    HB_HIP(hipMemcpyAsync(selected_model(c).params.get(), p, sizeof(float) * kParams, hipMemcpyHostToDevice, c->stream));
     reset_adam(c);
-    c->model.ready = true;
+    selected_model(c).ready = true;
     c->sync();
 }
 
 void costmodel_get(Ctx* c, float* p, uint32_t n) {
     if (!p || n != (uint32_t)kParams) fail(HB_ERR_INVALID_ARG, "expected HB_MLP_PARAMS floats");
-    if (!c->model.ready) fail(HB_ERR_STATE, "no cost model (hb_costmodel_init / set / train first)");
-    HB_HIP(hipMemcpyAsync(p, c->model.params.get(), sizeof(float) * kParams, hipMemcpyDeviceToHost, c->stream));
+    if (!selected_model(c).ready) fail(HB_ERR_STATE, "no cost model (hb_costmodel_init / set / train first)");
+    HB_HIP(hipMemcpyAsync(p, selected_model(c).params.get(), sizeof(float) * kParams, hipMemcpyDeviceToHost, c->stream));
     c->sync();
 }
 
@@ -169,7 +175,7 @@ void costmodel_train(Ctx* c, const float* x, const float* t, uint64_t n, int on_
                      uint32_t batch, float lr, float* final_loss) {
     if (!x || !t || n == 0 || batch == 0) fail(HB_ERR_INVALID_ARG, "empty training set");
     if (n > (1ull << 30)) fail(HB_ERR_LIMIT, "more than 2^30 training rows");
-    if (!c->model.ready) costmodel_init(c, 0x48420007ull);
+    if (!selected_model(c).ready) costmodel_init(c, 0x48420007ull);
     DevBuf hx, ht;
     const float* dx = rows_on_device(c, x, n * kIn, on_device, hx);
     const float* dt = rows_on_device(c, t, n * kOut, on_device, ht);
@@ -183,8 +189,8 @@ void costmodel_train(Ctx* c, const float* x, const float* t, uint64_t n, int on_
             const int nb = (int)std::min<uint64_t>(b, n - r0);
             const float* xb = dx + r0 * kIn;
             const float* tb = dt + r0 * kOut;
-            forward(c, c->model.params.as<float>(), xb, nb, a);
-            backward(c, c->model.params.as<float>(), xb, tb, nb, a);
+            forward(c, selected_model(c).params.as<float>(), xb, nb, a);
+            backward(c, selected_model(c).params.as<float>(), xb, tb, nb, a);
             adam(c, a.grad.as<float>(), lr);
             if (e + 1 == epochs) sse += read1(c, a.sse.as<float>());
         }
@@ -194,8 +200,12 @@ void costmodel_train(Ctx* c, const float* x, const float* t, uint64_t n, int on_
     if (final_loss) *final_loss = (float)last;
 }
 
+void model_forward(Ctx* c, const CostModel& m, const float* x, uint64_t n, float* y) {
+    HB_HIP(launch_mlp_forward(m.params.as<float>(), x, n, y, c->stream));
+}
+
 void costmodel_predict(Ctx* c, const float* x, uint64_t n, int on_device, float* y, int y_on_device) {
-    if (!c->model.ready) fail(HB_ERR_STATE, "no cost model");
+    if (!selected_model(c).ready) fail(HB_ERR_STATE, "no cost model");
     if (!x || !y) fail(HB_ERR_INVALID_ARG, "NULL buffer");
     DevBuf hx, hy;
     const float* dx = rows_on_device(c, x, n * kIn, on_device, hx);
@@ -204,7 +214,7 @@ void costmodel_predict(Ctx* c, const float* x, uint64_t n, int on_device, float*
         hy.alloc(c, sizeof(float) * kOut * std::max<uint64_t>(n, 1));
         dy = hy.as<float>();
     }
-    HB_HIP(launch_mlp_forward(c->model.params.as<float>(), dx, n, dy, c->stream));
+    HB_HIP(launch_mlp_forward(selected_model(c).params.as<float>(), dx, n, dy, c->stream));
     if (!y_on_device) {
         HB_HIP(hipMemcpyAsync(y, dy, sizeof(float) * kOut * n, hipMemcpyDeviceToHost, c->stream));
         c->sync();
@@ -212,7 +222,7 @@ void costmodel_predict(Ctx* c, const float* x, uint64_t n, int on_device, float*
 }
 
 void costmodel_trace(Ctx* c, const float* x, const float* t, uint32_t n, float* out, uint64_t out_len) {
-    if (!c->model.ready) fail(HB_ERR_STATE, "no cost model");
+    if (!selected_model(c).ready) fail(HB_ERR_STATE, "no cost model");
     const uint64_t need = (uint64_t)n * (kHid * 6 + kOut * 2) + kParams;
     if (!x || !t || !out || n == 0 || out_len < need) fail(HB_ERR_INVALID_ARG, "trace buffer too small");
     DevBuf hx, ht;
@@ -220,8 +230,8 @@ void costmodel_trace(Ctx* c, const float* x, const float* t, uint32_t n, float* 
     const float* dt = rows_on_device(c, t, (size_t)n * kOut, 0, ht);
     Acts a;
     a.ensure(c, (int)n);
-    forward(c, c->model.params.as<float>(), dx, (int)n, a);
-    backward(c, c->model.params.as<float>(), dx, dt, (int)n, a);
+    forward(c, selected_model(c).params.as<float>(), dx, (int)n, a);
+    backward(c, selected_model(c).params.as<float>(), dx, dt, (int)n, a);
     float* o = out;
     const DevBuf* parts[] = {&a.z1, &a.h1, &a.z2, &a.h2, &a.y, &a.dy, &a.dz2, &a.dz1};
     const size_t sizes[] = {(size_t)n * kHid, (size_t)n * kHid, (size_t)n * kHid, (size_t)n * kHid,
@@ -236,8 +246,8 @@ void costmodel_trace(Ctx* c, const float* x, const float* t, uint32_t n, float* 
 
 // Model file (little-endian): the 8 bytes "HBCMODEL", u32 version (1),
 // u32 inputs, hidden width, outputs and parameter count (16, 64, 2, 5378),
-// u32 0, the fp32 parameters in hb.h's order, and the FNV-1a 64 hash of the
-// parameter bytes.
+// u32 model kind (0 block, 1 per pair), the fp32 parameters in hb.h's order,
+// and the FNV-1a 64 hash of the parameter bytes.
 namespace {
 constexpr char kMagic[8] = {'H', 'B', 'C', 'M', 'O', 'D', 'E', 'L'};
 constexpr uint32_t kFileVersion = 1;
@@ -263,7 +273,8 @@ void costmodel_save(Ctx* c, const char* path) {
     if (!path || !*path) fail(HB_ERR_INVALID_ARG, "NULL or empty path");
     std::vector<float> w(kParams);
     costmodel_get(c, w.data(), kParams);
-    const uint32_t head[6] = {kFileVersion, (uint32_t)kIn, (uint32_t)kHid, (uint32_t)kOut, (uint32_t)kParams, 0u};
+    const uint32_t head[6] = {kFileVersion, (uint32_t)kIn, (uint32_t)kHid, (uint32_t)kOut, (uint32_t)kParams,
+                              (uint32_t)c->model_sel};
     const uint64_t sum = fnv1a64((const uint8_t*)w.data(), sizeof(float) * kParams);
     // write a temporary file beside the target, then rename it over the target
     const std::string tmp = std::string(path) + ".tmp";
@@ -300,8 +311,11 @@ void costmodel_load(Ctx* c, const char* path) {
     if (std::fread(head, sizeof(uint32_t), 6, fc.f) != 6 || head[0] != kFileVersion)
         fail(HB_ERR_INVALID_ARG, std::string(path) + ": unknown cost-model file version");
     if (head[1] != (uint32_t)kIn || head[2] != (uint32_t)kHid || head[3] != (uint32_t)kOut ||
-        head[4] != (uint32_t)kParams || head[5] != 0u)
+        head[4] != (uint32_t)kParams || head[5] > 1u)
         fail(HB_ERR_INVALID_ARG, std::string(path) + ": the model's shape is not 16 -> 64 -> 64 -> 2");
+    if (head[5] != (uint32_t)c->model_sel)
+        fail(HB_ERR_INVALID_ARG, std::string(path) + (head[5] ? ": holds a per-pair model, the block model is selected"
+                                                              : ": holds a block model, the per-pair model is selected"));
     if (std::fread(w.data(), sizeof(float), kParams, fc.f) != (size_t)kParams ||
         std::fread(&sum, sizeof(sum), 1, fc.f) != 1)
         fail(HB_ERR_INVALID_ARG, std::string(path) + ": truncated cost-model file");
@@ -313,7 +327,7 @@ void costmodel_load(Ctx* c, const char* path) {
 }
 
 void costmodel_adam(Ctx* c, const float* grad_host, float lr) {
-    if (!c->model.ready) fail(HB_ERR_STATE, "no cost model");
+    if (!selected_model(c).ready) fail(HB_ERR_STATE, "no cost model");
     DevBuf g;
     const float* dg = rows_on_device(c, grad_host, kParams, 0, g);
     adam(c, dg, lr);

@@ -1412,6 +1412,162 @@ __global__ __launch_bounds__(64) void k_log_samples(const LearnParams L) {
     }
 }
 
+// ------------------------------------------------------------ per-pair cost network
+
+__device__ inline bool col_valid(const ColDev& c, uint32_t r) {
+    return c.valid == nullptr || ((c.valid[r >> 3] >> (r & 7)) & 1);
+}
+
+// Sampled pair s of D x D (n >= 2 rows).
+__device__ inline void sample_pair(uint64_t seed, uint32_t s, uint32_t n, uint32_t& i, uint32_t& j) {
+    i = (uint32_t)(mix64(seed + 2ull * s) % n);
+    j = (uint32_t)(mix64(seed + 2ull * s + 1) % n);
+    if (j == i) j = (i + 1) % n;
+}
+
+// The per-pair network's 16 inputs for predicate sp on rows (i, j):
+// one-hot kind (0-4), presence of both values (5, 6), byte lengths / 64
+// (7, 8), a kind-specific pair (9, 10: equal lengths for string equality;
+// pattern words / 4 and k / 16 for edit distance; q-gram counts / 64 for
+// Jaccard), Jaccard's short-string flag (11) and threshold (12), the
+// shorter length and the length difference / 64 (13, 14), and 1 (15).
+// Every value is an integer times a power of two, or one rounded fraction.
+__device__ inline void pair_features(const PairParams& P, const PairSpec& sp, uint32_t i, uint32_t j, float* f) {
+#pragma unroll
+    for (int k = 5; k < kFeatures; ++k) f[k] = 0.f;
+    const ColDev& c = P.cols[sp.attr];
+    const bool ok1 = col_valid(c, i), ok2 = col_valid(c, j);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) f[k] = sp.kind == k ? 1.f : 0.f;
+    f[5] = ok1 ? 1.f : 0.f;
+    f[6] = ok2 ? 1.f : 0.f;
+    f[15] = 1.f;
+    if (sp.kind == PK_VALUE_EQ || sp.kind == PK_ABSDIFF) return;
+    const uint32_t l1 = ok1 ? (uint32_t)(c.off[i + 1] - c.off[i]) : 0u;
+    const uint32_t l2 = ok2 ? (uint32_t)(c.off[j + 1] - c.off[j]) : 0u;
+    const float s64 = 1.f / 64.f;
+    f[7] = (float)l1 * s64;
+    f[8] = (float)l2 * s64;
+    f[13] = (float)min(l1, l2) * s64;
+    f[14] = (float)(l1 > l2 ? l1 - l2 : l2 - l1) * s64;
+    if (sp.kind == PK_STRING_EQ) {
+        f[9] = (ok1 && ok2 && l1 == l2) ? 1.f : 0.f;
+    } else if (sp.kind == PK_EDIT) {
+        f[9] = (float)(l1 <= 32 ? 0u : (l1 + 63) / 64) * 0.25f;
+        f[10] = (float)sp.k * (1.f / 16.f);
+    } else {
+        const GramDev& g = P.gram[sp.gram];
+        f[9] = (float)(ok1 ? g.cnt[i] : 0u) * s64;
+        f[10] = (float)(ok2 ? g.cnt[j] : 0u) * s64;
+        f[11] = ((l1 > 0 && l1 < sp.q) || (l2 > 0 && l2 < sp.q)) ? 1.f : 0.f;
+        f[12] = (float)((double)sp.num / (double)sp.den);
+    }
+}
+
+// Logging pass of the per-pair network: workgroup (s, x), one wave,
+// evaluates predicate x on sampled pair s with every lane on that same pair,
+// so the wave's clock cycles around the exact check are the time of
+// checking one pair (edit distance: the pattern table and Myers' scan;
+// Jaccard: staging row i's q-gram list and the merge).
+__global__ __launch_bounds__(64) void k_pair_log(const PairParams P) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int lane = threadIdx.x;
+    const uint32_t s = blockIdx.x, x = blockIdx.y;
+    const PairSpec sp = P.spec[x];
+    uint32_t i, j;
+    sample_pair(P.seed, s, P.n_rows, i, j);
+    const size_t row = (size_t)x * P.samples + s;
+    if (lane == 0) {
+        float f[kFeatures];
+        pair_features(P, sp, i, j, f);
+        float4* dst = (float4*)(P.features + row * kFeatures);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dst[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+        if (P.pairs && x == 0) {
+            P.pairs[2 * (size_t)s] = i;
+            P.pairs[2 * (size_t)s + 1] = j;
+        }
+    }
+    const ColDev& c = P.cols[sp.attr];
+    const bool ok = col_valid(c, i) && col_valid(c, j);   // uniform: one pair per wave
+    const uint64_t t0 = __builtin_readcyclecounter();
+    bool r = false;
+    if (ok) {
+        if (sp.kind == PK_VALUE_EQ) {
+            r = c.values[i] == c.values[j];
+        } else if (sp.kind == PK_ABSDIFF) {
+            r = absdiff_le(c.values[i], c.values[j], sp.d);
+        } else if (sp.kind == PK_STRING_EQ) {
+            const uint32_t l1 = (uint32_t)(c.off[i + 1] - c.off[i]), l2 = (uint32_t)(c.off[j + 1] - c.off[j]);
+            if (l1 == l2) {
+                const uint8_t* a = c.bytes + c.off[i];
+                const uint8_t* b = c.bytes + c.off[j];
+                r = true;
+                for (uint32_t q = 0; r && q < l1; ++q) r = a[q] == b[q];
+            }
+        } else if (sp.kind == PK_EDIT) {
+            const int m = (int)(c.off[i + 1] - c.off[i]), nn = (int)(c.off[j + 1] - c.off[j]);
+            const int words = m <= 32 ? 0 : (m + 63) / 64;   // <= kMaxEdWords: compile bounds the length
+            build_peq(lds + kPairLdsPeq, words, c.bytes + c.off[i], m, lane);
+            const int dist = myers_dispatch(lds + kPairLdsPeq, words, m, c.bytes + c.off[j], nn,
+                                            (uint64_t*)(lds + kPairLdsMyers), lane);
+            r = dist <= (int)sp.k;
+        } else {
+            const GramDev& g = P.gram[sp.gram];
+            const uint32_t ca = g.cnt[i], cb = g.cnt[j];   // ca <= max_cnt: the LDS holds it
+            uint32_t* ig = (uint32_t*)(lds + kPairLdsGrams);
+            const uint32_t* src = g.codes + g.off[i];
+            for (uint32_t q = lane; q < ca; q += 64) ig[q] = src[q];
+            wave_sync();
+            const uint32_t I = intersect(ig, ca, (g.flags[i] & 1) != 0, g.codes + g.off[j], cb, (g.flags[j] & 1) != 0);
+            const uint64_t U = (uint64_t)ca + cb - I;
+            r = U == 0 || (uint64_t)I * sp.den >= (uint64_t)sp.num * U;
+        }
+    }
+    const uint64_t passed = __ballot(r);
+    const uint64_t t1 = __builtin_readcyclecounter();
+    if (lane == 0) {
+        P.sat[row] = passed ? 1u : 0u;
+        P.cycles[row] = (unsigned long long)(t1 - t0);
+    }
+}
+
+// Features of every (predicate, sampled pair) row, one thread per row.
+__global__ __launch_bounds__(256) void k_pair_features(const PairParams P) {
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (uint64_t)P.n_spec * P.samples) return;
+    const uint32_t x = (uint32_t)(t / P.samples), s = (uint32_t)(t % P.samples);
+    uint32_t i, j;
+    sample_pair(P.seed, s, P.n_rows, i, j);
+    float f[kFeatures];
+    pair_features(P, P.spec[x], i, j, f);
+    float4* dst = (float4*)(P.features + t * kFeatures);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+}
+
+// Summed estimate of predicate x (workgroup x): the network's second
+// output y is log2(1 + cycles) / 16, so a row estimates
+// 2^(16 * clamp(y, 0, 4)) - 1 cycles (NaN counts as 0).  Fixed-order fp64
+// sums, so equal inputs give equal costs.
+__global__ __launch_bounds__(256) void k_pair_sum(const PairParams P) {
+    __shared__ double part[256];
+    const uint32_t x = blockIdx.x;
+    double acc = 0.0;
+    for (uint32_t s = threadIdx.x; s < P.samples; s += 256) {
+        const double y = (double)P.y[((size_t)x * P.samples + s) * 2 + 1];
+        const double t = fmin(fmax(y, 0.0), 4.0);
+        acc += exp2(16.0 * t) - 1.0;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) P.sums[x] = part[0];
+}
+
 // ------------------------------------------------------------ plan choice
 
 // The shape of a block's wave batches: rows per batch, lanes, and the
@@ -1839,6 +1995,30 @@ hipError_t launch_log_samples(const LearnParams& p, hipStream_t s) {
     }
     dim3 grid(p.mp.n_blocks, p.samples);
     k_log_samples<<<grid, 64, lds, s>>>(p);
+    return hipGetLastError();
+}
+
+}  // namespace hb
+
+namespace hb {
+
+hipError_t launch_pair_log(const PairParams& p, hipStream_t s) {
+    if (p.n_spec == 0 || p.samples == 0) return hipSuccess;
+    dim3 grid(p.samples, p.n_spec);
+    k_pair_log<<<grid, 64, p.lds_bytes, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_features(const PairParams& p, hipStream_t s) {
+    const uint64_t rows = (uint64_t)p.n_spec * p.samples;
+    if (rows == 0) return hipSuccess;
+    k_pair_features<<<(unsigned)((rows + 255) / 256), 256, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_sum(const PairParams& p, hipStream_t s) {
+    if (p.n_spec == 0 || p.samples == 0) return hipSuccess;
+    k_pair_sum<<<p.n_spec, 256, 0, s>>>(p);
     return hipGetLastError();
 }
 
