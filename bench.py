@@ -443,8 +443,10 @@ def main():
                     help="also time steps whose input comes from pinned host memory and whose result goes "
                          "back to the host (the PCIe-inclusive rate; never the reported value)")
     ap.add_argument("--strategies", action="store_true",
-                    help="also time the comparison orders (given, cheapest, selective, random_preds, "
-                         "random_rules) on the same workload; outputs must equal the timed plan's")
+                    help="time the comparison orders (given, cheapest, selective, random_preds, random_rules, "
+                         "and the heuristic on the per-pair network's costs) on the same workload; outputs "
+                         "must equal the timed plan's (the default unless --no-compare or --no-strategies)")
+    ap.add_argument("--no-strategies", action="store_true", help="skip the comparison orders")
     ap.add_argument("--grammar", action="store_true",
                     help="also time plain_1m under a rule set with t.i1 = 7 (ordered output) and check it "
                          "against the symmetric result")
@@ -701,7 +703,7 @@ def main():
 
     strategies = None
     pair_net = None
-    if args.strategies:
+    if args.strategies or not (args.no_compare or args.no_strategies):
         strategies = {}
         snames = ("given", "heuristic", "cheapest", "selective", "random_preds", "random_rules")
         if not ordered_rules(rules):

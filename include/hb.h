@@ -525,7 +525,9 @@ hb_status hb_log_collect(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, uint
  *     and count 0;
  *   labels: 1 if the pair satisfies the predicate, else 0; and
  *     log2(1 + clock cycles) / 16 of one wave checking that pair exactly
- *     (every lane on the same pair).
+ *     (every lane on the same pair; the check runs twice and the second,
+ *     with the pair's values in the caches, is timed, less the cycles of an
+ *     empty interval between two clock reads, floored at 0).
  * pairs [samples x 2] = (i, j).  Outputs are host arrays (any may be NULL).
  * samples in [1, 65536] (HB_ERR_INVALID_ARG otherwise); a relation with
  * fewer than two tuples gives no rows.  If cap_rows is too small the call
