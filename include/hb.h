@@ -424,15 +424,18 @@ typedef struct {
 hb_status hb_match_work(hb_ctx* ctx, uint32_t rel_id, uint32_t ruleset_id, int32_t plan, hb_work_stats* out);
 
 /* ------------------------------------------------------------ cost model
- * The learned cost model: an MLP 16 -> 64 -> 64 -> 2 (ReLU after both
- * hidden layers, linear output) predicting (pass rate, cost) of a predicate
- * on a block from 16 block features; it stands in for the paper's shallow
- * network trained on logs (Section 4.2, "Shallow NNs", "Estimated cost").
+ * The learned cost models: MLPs 16 -> 64 -> 64 -> 2 (ReLU after both
+ * hidden layers, linear output).  The block model predicts (pass rate,
+ * cost) of a predicate on a block from 16 block features, the per-block form
+ * of the paper's shallow network trained on logs (Section 4.2, "Shallow
+ * NNs", "Estimated cost"); the per-pair model (HB_MODEL_PAIR below) is that
+ * network's per-pair form, predicting (satisfied, time of the check) of a
+ * predicate on one pair.
  * Parameters: HB_MLP_PARAMS fp32 values, row-major, in the order W1 [16x64],
  * b1 [64], W2 [64x64], b2 [64], W3 [64x2], b3 [2], used as y = x W + b.
  * GEMMs round both operands to bf16 (nearest, ties to even) and accumulate
  * in fp32; bias, ReLU, the loss and Adam (beta1 0.9, beta2 0.999, eps 1e-8)
- * run in fp32.  The model belongs to the context. */
+ * run in fp32.  The models belong to the context. */
 #define HB_MLP_PARAMS 5378
 #define HB_MLP_FEATURES 16
 /* The context holds two models of this shape: the block model (the learned
